@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Benchmark of the SCLaP multilevel partitioner on one MI355X.
+
+One step = one full multilevel partition (clustering + contraction per level,
+initial partition of the coarsest graph, projection + refinement per level)
+of a seeded synthetic graph that is already resident in HBM.  Prints one JSON
+line with whole-job edge-visits/s, the roofline of the dominant kernel
+(HIP events on the library's stream, algorithmic bytes per launch) and the
+CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat24|rmat20|ba14]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+WORKLOADS = {
+    # R-MAT scale 24, edge factor 16, (a,b,c,d) = (.57,.19,.19,.05), unit weights, k = 64
+    "rmat24": dict(gen="rmat", scale=24, edge_factor=16, k=64, eps=0.03, seed=1, opts={}),
+    # R-MAT scale 20, edge factor 16, k = 16
+    "rmat20": dict(gen="rmat", scale=20, edge_factor=16, k=16, eps=0.03, seed=1, opts={}),
+    # Barabasi-Albert n = 2^14, m = 8, k = 2, one level then refine
+    "ba14": dict(gen="ba", n=1 << 14, m=8, k=2, eps=0.03, seed=1, opts={"max_levels": 1}),
+}
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def make_graph(w):
+    import numpy as np
+    import synth
+    if w["gen"] == "rmat":
+        g = synth.rmat(w["scale"], w["edge_factor"], seed=w["seed"])
+        name = "rmat%d_ef%d_k%d" % (w["scale"], w["edge_factor"], w["k"])
+    else:
+        g = synth.ba(w["n"], w["m"], seed=w["seed"])
+        name = "ba_n%d_m%d_k%d" % (w["n"], w["m"], w["k"])
+    # explicit unit weights: int32 CSR with int32 node and edge weights
+    g["adjwgt"] = np.ones(len(g["adjncy"]), dtype=np.int32)
+    g["vwgt"] = np.ones(g["n"], dtype=np.int32)
+    return g, name
+
+
+def cpu_baseline(g, w):
+    """The oracle, as it stands, on a bounded sample: the first sub-round
+    (colour 0 of 4) of the first clustering round on the full level-0 graph."""
+    import numpy as np
+    import oracle
+    n = g["n"]
+    U = oracle.cluster_bound(g, w["k"], 18)
+    label = np.arange(n, dtype=np.int32)
+    wt = g["vwgt"].astype(np.int64)
+    t = time.perf_counter()
+    moves, visits, ncand = oracle.subround(g, oracle.CLUSTER, 0, 0, 0, 4, w["seed"], U, label, wt)
+    dt = time.perf_counter() - t
+    return {"value": visits / dt, "unit": "edge-visits/s", "cores": 1, "kind": "oracle",
+            "sample": "oracle sub-round 0 of 4 of clustering round 0 on the full level-0 graph "
+                      "(%d edge visits, %.1f s, single thread)" % (visits, dt)}
+
+
+def copy_calibration(nbytes):
+    """A plain device copy of known size, for scaling HBM counters."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log("copy calibration: %d bytes read, %d bytes written" % (a.numel() * 4, b.numel() * 4))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", type=int, default=0, help="bytes for a plain copy kernel (counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build partitions on one GPU; --gpus %d is not supported "
+              "(multi-GPU sharding is described in DESIGN.md, not built)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1404_4797_amd as sc
+
+    w = WORKLOADS[args.workload]
+    t = time.time()
+    g, name = make_graph(w)
+    n, S = g["n"], int(g["xadj"][-1])
+    log("workload %s: n=%d S=%d generated in %.1fs" % (name, n, S, time.time() - t))
+    torch.cuda.set_device(0)
+    d = sc.to_device(g, "cuda")
+    part = torch.empty(n, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    opts = sc.default_options(**w["opts"])
+    torch.cuda.synchronize()
+    if args.copy_calib:
+        copy_calibration(args.copy_calib)
+
+    for i in range(args.warmup):
+        r = sc.partition_dev(d, w["k"], w["eps"], w["seed"], part=part, stream=stream, opts=opts)
+        log("warmup %d: cut=%d levels=%d" % (i, r["cut"], r["stats"]["levels"]))
+    torch.cuda.synchronize()
+    sc.profile_begin()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for i in range(args.steps):
+        r = sc.partition_dev(d, w["k"], w["eps"], w["seed"], part=part, stream=stream, opts=opts)
+        results.append(r)
+        log("step %d: cut=%d" % (i, r["cut"]))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kstats = sc.profile_end()
+    ms_per_step = (t1 - t0) * 1000.0 / max(args.steps, 1)
+    r = results[-1]
+    st = r["stats"]
+    assert all(x["cut"] == r["cut"] for x in results), "steps disagree"
+    visits = st["visits"]
+    value = visits / (ms_per_step / 1000.0)
+
+    # dominant kernel with an algorithmic byte model
+    modeled = {k: v for k, v in kstats.items() if v["bytes"] > 0 and v["launches"] > 0}
+    dom = max(modeled, key=lambda k: modeled[k]["ms"]) if modeled else None
+    roofline = None
+    if dom:
+        ks = kstats[dom]
+        avg_ms = ks["ms"] / ks["launches"]
+        gbs = ks["bytes"] / (ks["ms"] / 1000.0) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                    "avg_launch_ms": round(avg_ms, 5), "bytes_per_launch": ks["bytes"] / ks["launches"],
+                    "launches": ks["launches"] // max(args.steps, 1)}
+    total_k_ms = sum(v["ms"] for v in kstats.values())
+    kernels = {k: {"ms_per_step": round(v["ms"] / max(args.steps, 1), 3),
+                   "share": round(v["ms"] / total_k_ms, 4) if total_k_ms else 0,
+                   "launches_per_step": v["launches"] // max(args.steps, 1),
+                   "GBps": round(v["bytes"] / (v["ms"] / 1000.0) / 1e9, 1) if v["bytes"] and v["ms"] else None}
+               for k, v in sorted(kstats.items(), key=lambda kv: -kv[1]["ms"])}
+    lp_gb = sum(v["bytes"] for k, v in kstats.items() if k.startswith("lp_eval")) / max(args.steps, 1) / 1e9
+
+    out = {
+        "metric": "SCLaP edge-visits/s & partition time; batched vs plain graphs/s, same cut",
+        "value": value, "unit": "edge-visits/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": name, "n": n, "S": S, "k": w["k"], "eps": w["eps"], "seed": w["seed"],
+                   "coarsen_rounds": opts.coarsen_rounds, "refine_rounds": opts.refine_rounds,
+                   "subrounds": opts.subrounds, "max_levels": opts.max_levels},
+        "partition_ms": ms_per_step, "edge_visits_per_step": visits, "cut": r["cut"],
+        "max_block_weight": int(np.max(r["block_weights"])), "status": r["status"],
+        "levels": st["levels"], "level_n": st["level_n"], "cluster_rounds": st["cluster_rounds"],
+        "refine_rounds": st["refine_rounds"],
+        "phase_ms": {"coarsen": st["ms_coarsen"], "initial": st["ms_initial"], "refine": st["ms_refine"],
+                     "lp": st["ms_lp"]},
+        "lp_eval_GB_per_step": round(lp_gb, 3),
+        "roofline": roofline, "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample) ...")
+        out["cpu_baseline"] = cpu_baseline(g, w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

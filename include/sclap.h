@@ -1,0 +1,231 @@
+/*
+ * sclap.h: C ABI of the MI355X (gfx950) library for size-constrained label
+ * propagation (SCLaP), cluster contraction and multilevel graph
+ * partitioning, after Meyerhenke, Sanders and Schulz, "Parallel Graph
+ * Partitioning for Complex Networks" (2014).
+ *
+ * Problem (Section 2.1, Basic concepts): an undirected graph
+ * G = (V = {0..n-1}, E, c, w) with node weights c >= 0 and edge weights w >= 1
+ * is split into k blocks V_0..V_{k-1} with c(V_b) <= Lmax, where
+ * Lmax = (1+eps) * ceil(c(V)/k), minimising the cut, the total weight of the
+ * edges whose ends lie in different blocks.
+ *
+ * Graph layout (all entry points): symmetric CSR.
+ *   xadj   int64[n+1]  row offsets, xadj[0] = 0, non-decreasing
+ *   adjncy int32[S]    neighbour ids (S = xadj[n]); no self-loops; each
+ *                      undirected edge appears in both rows with equal weight
+ *   vwgt   int32[n]    node weights c(v) >= 0, or NULL for all 1
+ *   adjwgt int32[S]    edge weights w >= 1, or NULL for all 1
+ * c(V) and the undirected edge-weight total must each be <= 2^31-1.
+ *
+ * Memory: entry points without a suffix take host pointers and copy to and
+ * from the current HIP device.  Entry points ending in _dev take device
+ * pointers for the graph and every per-node array, plus the hipStream_t
+ * (passed as void*, NULL = the default stream) on which all work is
+ * enqueued; scalar outputs and the k block weights are host pointers.  The
+ * caller owns every buffer it passes and must size outputs to n (per-node)
+ * and k (per-block).  The library keeps no pointer after a call returns,
+ * except for graphs returned in sclap_graph_owned (free them with
+ * sclap_graph_free).  A _dev call returns after its results are complete.
+ *
+ * Determinism: every output is a pure function of (graph, k, eps, seed and
+ * the semantic options).  The tuning knobs in sclap_options (degree-bucket
+ * thresholds, table sizes) never change a result.
+ *
+ * Status codes: SCLAP_OK (0); SCLAP_WARN_IMBALANCED (1): result returned but
+ * some block exceeds Lmax; negative values are errors, after which outputs are
+ * unspecified; sclap_last_error() then describes the error.
+ */
+#ifndef SCLAP_H
+#define SCLAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SCLAP_OK 0
+#define SCLAP_WARN_IMBALANCED 1
+#define SCLAP_ERR_INVALID (-1)       /* bad argument or malformed graph */
+#define SCLAP_ERR_NOT_SYMMETRIC (-2) /* some edge (u,v,w) lacks its twin (v,u,w) */
+#define SCLAP_ERR_OVERFLOW (-3)      /* c(V) or the edge-weight total exceeds 2^31-1 */
+#define SCLAP_ERR_NO_MEMORY (-4)     /* device allocation failed */
+#define SCLAP_ERR_HIP (-5)           /* a HIP runtime call failed */
+#define SCLAP_ERR_BUSY (-6)          /* server queue full */
+
+typedef struct {
+    int32_t n;
+    const int64_t* xadj;
+    const int32_t* adjncy;
+    const int32_t* vwgt;   /* NULL => all 1 */
+    const int32_t* adjwgt; /* NULL => all 1 */
+} sclap_graph;
+
+/* A graph allocated by the library (host memory, or device memory when
+ * on_device is 1); release with sclap_graph_free. */
+typedef struct {
+    int32_t n;
+    int64_t S;
+    int64_t* xadj;
+    int32_t* adjncy;
+    int32_t* vwgt;
+    int32_t* adjwgt;
+    int32_t on_device;
+} sclap_graph_owned;
+
+typedef struct {
+    /* semantic options (change results) */
+    int32_t coarsen_rounds;  /* label propagation rounds per clustering (default 10) */
+    int32_t refine_rounds;   /* label propagation rounds per refinement (default 10) */
+    int32_t subrounds;       /* hash-coloured sub-rounds per round, 1..16 (default 4) */
+    int32_t cluster_divisor; /* W = floor(c(V) / (cluster_divisor * k)) (default 18) */
+    int32_t coarsest_nodes;  /* stop coarsening at <= this many nodes (default 10000) */
+    int32_t max_levels;      /* at most this many contractions, 0..64 (default 64) */
+    int32_t validate;        /* 1: check the input graph first (default 1) */
+    /* Replaces the hash colour of every node (values in [0, subrounds)) in
+     * sclap_cluster, sclap_refine and their _dev variants only; host or device
+     * memory to match the entry point; NULL = hash colours. */
+    const int32_t* color_override;
+    /* tuning knobs (never change results; 0 = library default) */
+    int32_t lane_max_degree;  /* rows up to this degree: one lane per node */
+    int32_t wave_max_degree;  /* up to this: one wave64 per node, LDS table */
+    int32_t block_max_degree; /* up to this: one workgroup per node, LDS table; above: hub path */
+    int32_t reserved[5];
+} sclap_options;
+
+#define SCLAP_MAX_LEVELS 64
+
+/* Per-call statistics (optional output). */
+typedef struct {
+    int32_t levels;                          /* contractions kept (L) */
+    int64_t visits;                          /* adjacency slots scanned by node evaluation */
+    int32_t level_n[SCLAP_MAX_LEVELS + 1];   /* nodes per level */
+    int64_t level_S[SCLAP_MAX_LEVELS + 1];   /* adjacency slots per level */
+    int32_t cluster_rounds[SCLAP_MAX_LEVELS + 1]; /* rounds executed per clustering */
+    int32_t refine_rounds[SCLAP_MAX_LEVELS + 1];  /* rounds executed per refinement */
+    double ms_coarsen;   /* wall time of clustering + contraction */
+    double ms_initial;   /* coarsest-graph transfer + initial partition */
+    double ms_refine;    /* projection + refinement */
+    double ms_lp;        /* label propagation rounds only (cluster + refine) */
+} sclap_stats;
+
+/* Fills *opt with the defaults above.  Returns 0. */
+int sclap_default_options(sclap_options* opt);
+
+/* Message for the last non-zero status on this thread ("" if none). */
+const char* sclap_last_error(void);
+
+/*
+ * Input staging and validation (Section 2.1 problem statement): offsets
+ * non-decreasing from 0, ids in range, no self-loops, w >= 1, c >= 0, both
+ * totals <= 2^31-1, symmetric with equal weights.  The device variant tests
+ * symmetry with an order-independent 64-bit hash of (u, v, w) over all slots
+ * (a false pass has probability about 2^-64); the host variant checks it
+ * exactly.  Returns 0, SCLAP_ERR_INVALID, SCLAP_ERR_NOT_SYMMETRIC or
+ * SCLAP_ERR_OVERFLOW.
+ */
+int sclap_validate(const sclap_graph* g);
+int sclap_validate_dev(const sclap_graph* g, void* stream);
+
+/*
+ * Size-constrained label propagation clustering (Section 3.1, Label
+ * Propagation with Size Constraints): every node starts in its own cluster;
+ * `rounds` rounds of hash-coloured sub-rounds move each node to the eligible
+ * neighbouring cluster of strongest connection, where eligible means the
+ * cluster stays within U; a round without moves ends the run early (the
+ * result is the same as running all rounds).  `level` and `seed` key the
+ * colour and tie-break hashes.  Outputs labels[n] (cluster ids in [0, n)) and
+ * *rounds_run (may be NULL).
+ */
+int sclap_cluster(const sclap_graph* g, int64_t U, int32_t rounds, uint64_t seed, int32_t level,
+                  const sclap_options* opt, int32_t* labels, int32_t* rounds_run);
+int sclap_cluster_dev(const sclap_graph* g, int64_t U, int32_t rounds, uint64_t seed, int32_t level,
+                      const sclap_options* opt, int32_t* labels, int32_t* rounds_run, void* stream);
+
+/*
+ * Cluster contraction (Section 3.1 contraction definition; Section 4.3
+ * relabelling): labels[n] in [0, n) -> C[n] with C(v) = rank of label(v)
+ * among the used labels, and the coarse graph (node weight = sum of members,
+ * edge weight = total weight between two clusters, rows sorted by neighbour
+ * id).  The coarse graph is allocated by the library: host memory for
+ * sclap_contract, device memory for sclap_contract_dev.
+ */
+int sclap_contract(const sclap_graph* g, const int32_t* labels, int32_t* C, sclap_graph_owned* coarse);
+int sclap_contract_dev(const sclap_graph* g, const int32_t* labels, int32_t* C, sclap_graph_owned* coarse,
+                       void* stream);
+void sclap_graph_free(sclap_graph_owned* g);
+
+/* Uncoarsening (Section 3.1; Section 4.3): part[v] = coarse_part[C[v]] for
+ * v < n; C values must lie in [0, n_coarse) (checked). */
+int sclap_project(int32_t n, int32_t n_coarse, const int32_t* C, const int32_t* coarse_part, int32_t* part);
+int sclap_project_dev(int32_t n, int32_t n_coarse, const int32_t* C, const int32_t* coarse_part, int32_t* part,
+                      void* stream);
+
+/*
+ * SCLaP as local search (Section 3.1, last paragraph; Section 4.5): improves
+ * part[n] (in/out, blocks in [0, k)) for `rounds` rounds with block bound
+ * Lmax; a node of an overloaded block moves to the best eligible
+ * neighbouring block even at a loss.
+ */
+int sclap_refine(const sclap_graph* g, int32_t k, int64_t Lmax, int32_t rounds, uint64_t seed, int32_t level,
+                 const sclap_options* opt, int32_t* part, int32_t* rounds_run);
+int sclap_refine_dev(const sclap_graph* g, int32_t k, int64_t Lmax, int32_t rounds, uint64_t seed,
+                     int32_t level, const sclap_options* opt, int32_t* part, int32_t* rounds_run, void* stream);
+
+/* Objective and balance (Section 2.1): *cut = total weight of edges between
+ * blocks, block_w[k] = c(V_b). */
+int sclap_cut(const sclap_graph* g, const int32_t* part, int32_t k, int64_t* cut, int64_t* block_w);
+int sclap_cut_dev(const sclap_graph* g, const int32_t* part, int32_t k, int64_t* cut, int64_t* block_w,
+                  void* stream);
+
+/*
+ * Host initial partition of a (coarsest) graph, the plain routine used in
+ * place of the paper's evolutionary algorithm (Section 4.5): greedy
+ * breadth-first growing of blocks 0..k-2 up to T = ceil(c(V)/k) each, then
+ * the remaining nodes in id order to the lightest block.  Host memory.
+ */
+int sclap_initial_partition(const sclap_graph* g, int32_t k, int32_t* part);
+
+/* Lmax = T + floor(T * round(eps * 10^6) / 10^6), T = ceil(cV / k). */
+int64_t sclap_lmax(int64_t cV, int32_t k, double eps);
+
+/*
+ * Multilevel partitioning (Section 4.5): cluster + contract while the graph
+ * has more than coarsest_nodes nodes (a level is kept only if it shrinks;
+ * coarsening continues only after a shrink of at least 5%), initial partition
+ * of the coarsest graph, then projection and refinement on every level.
+ * Outputs part[n], *cut, block_w[k]; stats may be NULL.  Returns 0 or
+ * SCLAP_WARN_IMBALANCED or an error.
+ */
+int sclap_partition(const sclap_graph* g, int32_t k, double eps, uint64_t seed, const sclap_options* opt,
+                    int32_t* part, int64_t* cut, int64_t* block_w, sclap_stats* stats);
+int sclap_partition_dev(const sclap_graph* g, int32_t k, double eps, uint64_t seed, const sclap_options* opt,
+                        int32_t* part, int64_t* cut, int64_t* block_w, sclap_stats* stats, void* stream);
+
+/*
+ * Instrumentation.  sclap_profile_begin() starts timing every kernel launch
+ * that later calls on this thread issue, with HIP events recorded on the
+ * launching stream around each launch; sclap_profile_end() stops, writes up to
+ * `capacity` per-kernel totals to out (launch count, summed event time, and
+ * the algorithmic bytes the launches must move: for node evaluation, per
+ * evaluated node its list entry, row offsets, label and weight, and per
+ * adjacency slot the neighbour id, edge weight and neighbour label), sets
+ * *count and clears the totals.  Timing adds event records but does not
+ * change any result.
+ */
+typedef struct {
+    char name[48];
+    int64_t launches;
+    double ms;
+    double bytes;
+} sclap_kernel_stat;
+
+int sclap_profile_begin(void);
+int sclap_profile_end(sclap_kernel_stat* out, int32_t capacity, int32_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCLAP_H */

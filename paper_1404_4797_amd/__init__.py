@@ -1,0 +1,411 @@
+"""Python binding of libsclap.so (include/sclap.h): argument marshalling only.
+
+Every step of the computation runs in the gfx950 kernels of the library; this
+module only passes pointers and sizes through ctypes.  Host variants take
+numpy arrays; ``*_dev`` variants take torch tensors on the GPU and enqueue on
+the current torch stream (or the stream passed in).  A missing library raises
+``ImportError``/``OSError``: there is no fallback path.
+
+Graphs are dicts ``{"n", "xadj" int64[n+1], "adjncy" int32[S], "adjwgt"
+int32[S] or None, "vwgt" int32[n] or None}`` of numpy arrays (host) or torch
+tensors (device, see :func:`to_device`).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsclap.so")
+_lib = None
+
+OK, WARN_IMBALANCED = 0, 1
+ERR_INVALID, ERR_NOT_SYMMETRIC, ERR_OVERFLOW, ERR_NO_MEMORY, ERR_HIP, ERR_BUSY = -1, -2, -3, -4, -5, -6
+MAX_LEVELS = 64
+
+#: every entry point declared in include/sclap.h
+EXPORTS = [
+    "sclap_default_options", "sclap_last_error", "sclap_lmax",
+    "sclap_validate", "sclap_validate_dev",
+    "sclap_cluster", "sclap_cluster_dev",
+    "sclap_contract", "sclap_contract_dev", "sclap_graph_free",
+    "sclap_project", "sclap_project_dev",
+    "sclap_refine", "sclap_refine_dev",
+    "sclap_cut", "sclap_cut_dev",
+    "sclap_initial_partition",
+    "sclap_partition", "sclap_partition_dev",
+    "sclap_profile_begin", "sclap_profile_end",
+]
+
+
+class SclapError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("sclap status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("xadj", ctypes.c_void_p), ("adjncy", ctypes.c_void_p),
+                ("vwgt", ctypes.c_void_p), ("adjwgt", ctypes.c_void_p)]
+
+
+class GraphOwned(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("S", ctypes.c_int64), ("xadj", ctypes.c_void_p),
+                ("adjncy", ctypes.c_void_p), ("vwgt", ctypes.c_void_p), ("adjwgt", ctypes.c_void_p),
+                ("on_device", ctypes.c_int32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("coarsen_rounds", ctypes.c_int32), ("refine_rounds", ctypes.c_int32),
+                ("subrounds", ctypes.c_int32), ("cluster_divisor", ctypes.c_int32),
+                ("coarsest_nodes", ctypes.c_int32), ("max_levels", ctypes.c_int32),
+                ("validate", ctypes.c_int32), ("color_override", ctypes.c_void_p),
+                ("lane_max_degree", ctypes.c_int32), ("wave_max_degree", ctypes.c_int32),
+                ("block_max_degree", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("visits", ctypes.c_int64),
+                ("level_n", ctypes.c_int32 * (MAX_LEVELS + 1)), ("level_S", ctypes.c_int64 * (MAX_LEVELS + 1)),
+                ("cluster_rounds", ctypes.c_int32 * (MAX_LEVELS + 1)),
+                ("refine_rounds", ctypes.c_int32 * (MAX_LEVELS + 1)),
+                ("ms_coarsen", ctypes.c_double), ("ms_initial", ctypes.c_double),
+                ("ms_refine", ctypes.c_double), ("ms_lp", ctypes.c_double)]
+
+    def to_dict(self):
+        L = self.levels
+        return {"levels": L, "visits": self.visits, "level_n": list(self.level_n[:L + 1]),
+                "level_S": list(self.level_S[:L + 1]), "cluster_rounds": list(self.cluster_rounds[:L]),
+                "refine_rounds": list(self.refine_rounds[:L + 1]), "ms_coarsen": self.ms_coarsen,
+                "ms_initial": self.ms_initial, "ms_refine": self.ms_refine, "ms_lp": self.ms_lp}
+
+
+def load():
+    """Loads libsclap.so (built by ``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libsclap.so not built: run __graft_entry__.build() (%s)" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    G = ctypes.POINTER(Graph)
+    O = ctypes.POINTER(Options)
+    GO = ctypes.POINTER(GraphOwned)
+    ST = ctypes.POINTER(Stats)
+    sig = {
+        "sclap_default_options": (ctypes.c_int, [O]),
+        "sclap_last_error": (ctypes.c_char_p, []),
+        "sclap_lmax": (i64, [i64, i32, dbl]),
+        "sclap_validate": (ctypes.c_int, [G]),
+        "sclap_validate_dev": (ctypes.c_int, [G, vp]),
+        "sclap_cluster": (ctypes.c_int, [G, i64, i32, u64, i32, O, vp, vp]),
+        "sclap_cluster_dev": (ctypes.c_int, [G, i64, i32, u64, i32, O, vp, vp, vp]),
+        "sclap_contract": (ctypes.c_int, [G, vp, vp, GO]),
+        "sclap_contract_dev": (ctypes.c_int, [G, vp, vp, GO, vp]),
+        "sclap_graph_free": (None, [GO]),
+        "sclap_project": (ctypes.c_int, [i32, i32, vp, vp, vp]),
+        "sclap_project_dev": (ctypes.c_int, [i32, i32, vp, vp, vp, vp]),
+        "sclap_refine": (ctypes.c_int, [G, i32, i64, i32, u64, i32, O, vp, vp]),
+        "sclap_refine_dev": (ctypes.c_int, [G, i32, i64, i32, u64, i32, O, vp, vp, vp]),
+        "sclap_cut": (ctypes.c_int, [G, vp, i32, vp, vp]),
+        "sclap_cut_dev": (ctypes.c_int, [G, vp, i32, vp, vp, vp]),
+        "sclap_initial_partition": (ctypes.c_int, [G, i32, vp]),
+        "sclap_partition": (ctypes.c_int, [G, i32, dbl, u64, O, vp, vp, vp, ST]),
+        "sclap_partition_dev": (ctypes.c_int, [G, i32, dbl, u64, O, vp, vp, vp, ST, vp]),
+        "sclap_profile_begin": (ctypes.c_int, []),
+        "sclap_profile_end": (ctypes.c_int, [ctypes.POINTER(KernelStat), i32, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def last_error():
+    return load().sclap_last_error().decode()
+
+
+def _check(st, allow_warn=False):
+    if st < 0 or (st > 0 and not allow_warn):
+        raise SclapError(st, last_error())
+    return st
+
+
+def default_options(**kw):
+    o = Options()
+    load().sclap_default_options(ctypes.byref(o))
+    for key, val in kw.items():
+        setattr(o, key, val)
+    return o
+
+
+def lmax(cV, k, eps):
+    return int(load().sclap_lmax(cV, k, eps))
+
+
+# ----------------------------------------------------------------- host side
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class _HostGraph:
+    def __init__(self, g):
+        self.xadj = np.ascontiguousarray(g["xadj"], dtype=np.int64)
+        self.adjncy = np.ascontiguousarray(g["adjncy"], dtype=np.int32)
+        self.vwgt = None if g.get("vwgt") is None else np.ascontiguousarray(g["vwgt"], dtype=np.int32)
+        self.adjwgt = None if g.get("adjwgt") is None else np.ascontiguousarray(g["adjwgt"], dtype=np.int32)
+        self.n = int(g["n"])
+        self.s = Graph(self.n, _np_ptr(self.xadj), _np_ptr(self.adjncy), _np_ptr(self.vwgt), _np_ptr(self.adjwgt))
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+
+def _opts(opts, color_override=None, keep=None):
+    o = opts if isinstance(opts, Options) else default_options(**(opts or {}))
+    if color_override is not None:
+        o.color_override = color_override
+    return o
+
+
+def validate(g):
+    return int(load().sclap_validate(_HostGraph(g).ref))
+
+
+def cluster(g, U, rounds=10, seed=1, level=0, color_override=None, **opts):
+    hg = _HostGraph(g)
+    co = None if color_override is None else np.ascontiguousarray(color_override, dtype=np.int32)
+    o = _opts(opts, _np_ptr(co))
+    labels = np.empty(hg.n, dtype=np.int32)
+    rr = ctypes.c_int32(0)
+    _check(load().sclap_cluster(hg.ref, U, rounds, seed, level, ctypes.byref(o), labels.ctypes.data,
+                                ctypes.addressof(rr)))
+    return labels, rr.value
+
+
+def refine(g, k, Lmax, part, rounds=10, seed=1, level=0, color_override=None, **opts):
+    hg = _HostGraph(g)
+    co = None if color_override is None else np.ascontiguousarray(color_override, dtype=np.int32)
+    o = _opts(opts, _np_ptr(co))
+    p = np.array(part, dtype=np.int32, copy=True)
+    rr = ctypes.c_int32(0)
+    _check(load().sclap_refine(hg.ref, k, Lmax, rounds, seed, level, ctypes.byref(o), p.ctypes.data,
+                               ctypes.addressof(rr)))
+    return p, rr.value
+
+
+def contract(g, labels):
+    hg = _HostGraph(g)
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    C = np.empty(hg.n, dtype=np.int32)
+    out = GraphOwned()
+    L = load()
+    _check(L.sclap_contract(hg.ref, lab.ctypes.data, C.ctypes.data, ctypes.byref(out)))
+    try:
+        n, S = out.n, out.S
+        def arr(ptr, count, ct, dt):
+            if count == 0:
+                return np.zeros(0, dtype=dt)
+            return np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(ct)), shape=(count,)).copy()
+        cg = {"n": n, "xadj": arr(out.xadj, n + 1, ctypes.c_int64, np.int64),
+              "adjncy": arr(out.adjncy, S, ctypes.c_int32, np.int32),
+              "adjwgt": arr(out.adjwgt, S, ctypes.c_int32, np.int32),
+              "vwgt": arr(out.vwgt, n, ctypes.c_int32, np.int32)}
+    finally:
+        L.sclap_graph_free(ctypes.byref(out))
+    return C, cg
+
+
+def project(C, coarse_part):
+    C = np.ascontiguousarray(C, dtype=np.int32)
+    cp = np.ascontiguousarray(coarse_part, dtype=np.int32)
+    out = np.empty(len(C), dtype=np.int32)
+    _check(load().sclap_project(len(C), len(cp), C.ctypes.data, cp.ctypes.data, out.ctypes.data))
+    return out
+
+
+def cut(g, part, k):
+    hg = _HostGraph(g)
+    p = np.ascontiguousarray(part, dtype=np.int32)
+    c = ctypes.c_int64(0)
+    bw = np.zeros(k, dtype=np.int64)
+    _check(load().sclap_cut(hg.ref, p.ctypes.data, k, ctypes.addressof(c), bw.ctypes.data))
+    return c.value, bw
+
+
+def initial_partition(g, k):
+    hg = _HostGraph(g)
+    part = np.empty(hg.n, dtype=np.int32)
+    _check(load().sclap_initial_partition(hg.ref, k, part.ctypes.data))
+    return part
+
+
+def partition(g, k, eps=0.03, seed=1, **opts):
+    """Multilevel partition of a host graph; returns dict(part, cut,
+    block_weights, status, stats)."""
+    hg = _HostGraph(g)
+    o = _opts(opts)
+    part = np.empty(hg.n, dtype=np.int32)
+    c = ctypes.c_int64(0)
+    bw = np.zeros(k, dtype=np.int64)
+    st = Stats()
+    status = _check(load().sclap_partition(hg.ref, k, eps, seed, ctypes.byref(o), part.ctypes.data,
+                                           ctypes.addressof(c), bw.ctypes.data, ctypes.byref(st)),
+                    allow_warn=True)
+    return {"part": part, "cut": c.value, "block_weights": bw, "status": status, "stats": st.to_dict()}
+
+
+# --------------------------------------------------------------- device side
+
+def to_device(g, device="cuda"):
+    """Copies a host graph dict to torch tensors on the GPU."""
+    import torch
+    d = {"n": int(g["n"]), "xadj": torch.as_tensor(np.ascontiguousarray(g["xadj"], dtype=np.int64)).to(device),
+         "adjncy": torch.as_tensor(np.ascontiguousarray(g["adjncy"], dtype=np.int32)).to(device)}
+    for key in ("adjwgt", "vwgt"):
+        d[key] = None if g.get(key) is None else torch.as_tensor(
+            np.ascontiguousarray(g[key], dtype=np.int32)).to(device)
+    return d
+
+
+def _t_ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class _DevGraph:
+    def __init__(self, d):
+        for key in ("xadj", "adjncy", "adjwgt", "vwgt"):
+            t = d.get(key)
+            if t is not None:
+                assert t.is_cuda and t.is_contiguous(), key
+        assert d["xadj"].dtype.itemsize == 8 and d["adjncy"].dtype.itemsize == 4
+        self.d = d
+        self.n = int(d["n"])
+        self.s = Graph(self.n, _t_ptr(d["xadj"]), _t_ptr(d["adjncy"]), _t_ptr(d.get("vwgt")),
+                       _t_ptr(d.get("adjwgt")))
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+
+def validate_dev(d, stream=None):
+    return int(load().sclap_validate_dev(_DevGraph(d).ref, _stream(stream)))
+
+
+def cluster_dev(d, U, rounds=10, seed=1, level=0, labels=None, color_override=None, stream=None, **opts):
+    import torch
+    dg = _DevGraph(d)
+    if labels is None:
+        labels = torch.empty(dg.n, dtype=torch.int32, device=d["xadj"].device)
+    o = _opts(opts, _t_ptr(color_override))
+    rr = ctypes.c_int32(0)
+    _check(load().sclap_cluster_dev(dg.ref, U, rounds, seed, level, ctypes.byref(o), _t_ptr(labels),
+                                    ctypes.addressof(rr), _stream(stream)))
+    return labels, rr.value
+
+
+def refine_dev(d, k, Lmax, part, rounds=10, seed=1, level=0, color_override=None, stream=None, **opts):
+    """Refines ``part`` (int32 tensor on the GPU) in place."""
+    dg = _DevGraph(d)
+    o = _opts(opts, _t_ptr(color_override))
+    rr = ctypes.c_int32(0)
+    _check(load().sclap_refine_dev(dg.ref, k, Lmax, rounds, seed, level, ctypes.byref(o), _t_ptr(part),
+                                   ctypes.addressof(rr), _stream(stream)))
+    return part, rr.value
+
+
+def contract_dev(d, labels, stream=None):
+    """Returns (C tensor, coarse graph dict of tensors copied from the library's buffers)."""
+    import torch
+    dg = _DevGraph(d)
+    dev = d["xadj"].device
+    C = torch.empty(dg.n, dtype=torch.int32, device=dev)
+    out = GraphOwned()
+    L = load()
+    _check(L.sclap_contract_dev(dg.ref, _t_ptr(labels), _t_ptr(C), ctypes.byref(out), _stream(stream)))
+    try:
+        n, S = out.n, out.S
+        cg = {"n": n, "xadj": torch.empty(n + 1, dtype=torch.int64, device=dev),
+              "adjncy": torch.empty(S, dtype=torch.int32, device=dev),
+              "adjwgt": torch.empty(S, dtype=torch.int32, device=dev),
+              "vwgt": torch.empty(n, dtype=torch.int32, device=dev)}
+        import torch.cuda as tc
+        hip = ctypes.CDLL("libamdhip64.so")
+        hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        tc.synchronize()
+        for key, ptr, nb in (("xadj", out.xadj, (n + 1) * 8), ("adjncy", out.adjncy, S * 4),
+                             ("adjwgt", out.adjwgt, S * 4), ("vwgt", out.vwgt, n * 4)):
+            if nb > 0 and ptr:
+                rc = hip.hipMemcpy(cg[key].data_ptr(), ptr, nb, 3)  # device to device
+                if rc != 0:
+                    raise SclapError(ERR_HIP, "hipMemcpy failed (%d)" % rc)
+    finally:
+        L.sclap_graph_free(ctypes.byref(out))
+    return C, cg
+
+
+def project_dev(C, coarse_part, part=None, stream=None):
+    import torch
+    if part is None:
+        part = torch.empty_like(C)
+    _check(load().sclap_project_dev(C.numel(), coarse_part.numel(), _t_ptr(C), _t_ptr(coarse_part), _t_ptr(part),
+                                    _stream(stream)))
+    return part
+
+
+def cut_dev(d, part, k, stream=None):
+    dg = _DevGraph(d)
+    c = ctypes.c_int64(0)
+    bw = np.zeros(k, dtype=np.int64)
+    _check(load().sclap_cut_dev(dg.ref, _t_ptr(part), k, ctypes.addressof(c), bw.ctypes.data, _stream(stream)))
+    return c.value, bw
+
+
+def partition_dev(d, k, eps=0.03, seed=1, part=None, stream=None, opts=None, **kw):
+    """Multilevel partition of a device graph; ``part`` (int32 tensor) receives
+    the blocks.  Returns dict(part, cut, block_weights, status, stats)."""
+    import torch
+    dg = _DevGraph(d)
+    if part is None:
+        part = torch.empty(dg.n, dtype=torch.int32, device=d["xadj"].device)
+    o = opts if isinstance(opts, Options) else default_options(**kw)
+    c = ctypes.c_int64(0)
+    bw = np.zeros(k, dtype=np.int64)
+    st = Stats()
+    status = _check(load().sclap_partition_dev(dg.ref, k, eps, seed, ctypes.byref(o), _t_ptr(part),
+                                               ctypes.addressof(c), bw.ctypes.data, ctypes.byref(st),
+                                               _stream(stream)), allow_warn=True)
+    return {"part": part, "cut": c.value, "block_weights": bw, "status": status, "stats": st.to_dict()}
+
+
+def profile_begin():
+    """Starts per-kernel HIP-event timing of the library's launches on this thread."""
+    _check(load().sclap_profile_begin())
+
+
+def profile_end():
+    """Stops timing; returns {kernel name: dict(launches, ms, bytes)}."""
+    cap = 64
+    arr = (KernelStat * cap)()
+    cnt = ctypes.c_int32(0)
+    _check(load().sclap_profile_end(arr, cap, ctypes.addressof(cnt)))
+    return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].ms, "bytes": arr[i].bytes}
+            for i in range(min(cnt.value, cap))}

@@ -1,0 +1,781 @@
+// C ABI (include/sclap.h): argument checks, the multilevel driver and the
+// host initial partitioner around the gfx950 kernels.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <queue>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "graph_ops.hpp"
+#include "profile.hpp"
+#include "sclap.h"
+
+namespace sclap {
+
+thread_local std::string t_err;
+
+void fail(int status, const std::string& msg) { throw Error(status, msg); }
+
+void hip_check(hipError_t e, const char* what, const char* file, int line) {
+    if (e == hipSuccess) return;
+    (void)hipGetLastError();
+    const int st = e == hipErrorOutOfMemory ? SCLAP_ERR_NO_MEMORY : SCLAP_ERR_HIP;
+    throw Error(st, std::string(what) + ": " + hipGetErrorString(e) + " (" + file + ":" + std::to_string(line) + ")");
+}
+
+// ------------------------------------------------------------ memory pool
+
+namespace {
+std::mutex g_pool_mu;
+bool g_pool_ready[256] = {};
+
+void ensure_pool() {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev >= 0 && dev < 256 && g_pool_ready[dev]) return;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (dev >= 0 && dev < 256 && g_pool_ready[dev]) return;
+    hipMemPool_t pool;
+    HIPCHK(hipDeviceGetDefaultMemPool(&pool, dev));
+    uint64_t keep = ~0ULL;  // keep freed blocks cached in the pool
+    HIPCHK(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+    if (dev >= 0 && dev < 256) g_pool_ready[dev] = true;
+}
+}  // namespace
+
+void* dev_alloc(size_t bytes, hipStream_t s) {
+    ensure_pool();
+    void* p = nullptr;
+    const hipError_t e = hipMallocAsync(&p, bytes, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(e == hipErrorOutOfMemory ? SCLAP_ERR_NO_MEMORY : SCLAP_ERR_HIP,
+             "device allocation of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+    }
+    return p;
+}
+
+void dev_free(void* p, hipStream_t s) { (void)hipFreeAsync(p, s); }
+
+// ----------------------------------------------------------------- options
+
+namespace {
+
+struct Opts {
+    int32_t coarsen_rounds = 10;
+    int32_t refine_rounds = 10;
+    int32_t nsub = 4;
+    int32_t divisor = 18;
+    int32_t coarsest = 10000;
+    int32_t max_levels = SCLAP_MAX_LEVELS;
+    int32_t validate = 1;
+    const int32_t* color_override = nullptr;
+    LPTuning tune;
+};
+
+Opts resolve(const sclap_options* o) {
+    Opts r;
+    if (!o) return r;
+    r.coarsen_rounds = o->coarsen_rounds;
+    r.refine_rounds = o->refine_rounds;
+    r.nsub = o->subrounds;
+    r.divisor = o->cluster_divisor;
+    r.coarsest = o->coarsest_nodes;
+    r.max_levels = o->max_levels;
+    r.validate = o->validate;
+    r.color_override = o->color_override;
+    if (o->lane_max_degree > 0) r.tune.lane_max = o->lane_max_degree;
+    if (o->wave_max_degree > 0) r.tune.wave_max = o->wave_max_degree;
+    if (o->block_max_degree > 0) r.tune.block_max = o->block_max_degree;
+    if (r.coarsen_rounds < 0 || r.refine_rounds < 0) fail(SCLAP_ERR_INVALID, "round counts must be >= 0");
+    if (r.nsub < 1 || r.nsub > 16) fail(SCLAP_ERR_INVALID, "subrounds must be in 1..16");
+    if (r.divisor < 1) fail(SCLAP_ERR_INVALID, "cluster_divisor must be >= 1");
+    if (r.coarsest < 0) fail(SCLAP_ERR_INVALID, "coarsest_nodes must be >= 0");
+    if (r.max_levels < 0 || r.max_levels > SCLAP_MAX_LEVELS) fail(SCLAP_ERR_INVALID, "max_levels must be in 0..64");
+    return r;
+}
+
+hipStream_t as_stream(void* p) { return reinterpret_cast<hipStream_t>(p); }
+
+// Device view of a caller graph with device pointers; reads S = xadj[n].
+DevGraph dev_view(const sclap_graph* g, hipStream_t s) {
+    if (!g) fail(SCLAP_ERR_INVALID, "graph is NULL");
+    if (g->n < 0) fail(SCLAP_ERR_INVALID, "n < 0");
+    DevGraph d;
+    d.n = g->n;
+    d.xadj = g->xadj;
+    d.adj = g->adjncy;
+    d.ew = g->adjwgt;
+    d.vw = g->vwgt;
+    if (g->n > 0) {
+        if (!g->xadj) fail(SCLAP_ERR_INVALID, "xadj is NULL");
+        HIPCHK(hipMemcpyAsync(&d.S, g->xadj + g->n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (d.S < 0) fail(SCLAP_ERR_INVALID, "xadj[n] < 0");
+        if (d.S > 0 && !g->adjncy) fail(SCLAP_ERR_INVALID, "adjncy is NULL");
+    }
+    return d;
+}
+
+void check_graph(const DevGraph& g, bool validate, int64_t* cV, int64_t* cmax, hipStream_t s) {
+    if (validate) {
+        const int st = validate_graph(g, cV, cmax, s);
+        if (st == SCLAP_ERR_INVALID) fail(st, "invalid graph (offsets, ids, self-loops or weights)");
+        if (st == SCLAP_ERR_NOT_SYMMETRIC) fail(st, "graph is not symmetric");
+        if (st == SCLAP_ERR_OVERFLOW) fail(st, "node or edge weight total exceeds 2^31-1");
+        if (st != 0) fail(st, "graph validation failed");
+    } else {
+        node_weight_stats(g, cV, cmax, s);
+    }
+}
+
+template <typename F>
+int guarded(F&& f) {
+    try {
+        t_err.clear();
+        return f();
+    } catch (const Error& e) {
+        t_err = e.what();
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        t_err = "host allocation failed";
+        return SCLAP_ERR_NO_MEMORY;
+    } catch (const std::exception& e) {
+        t_err = e.what();
+        return SCLAP_ERR_HIP;
+    }
+}
+
+int64_t lmax_of(int64_t cV, int32_t k, double eps) {
+    const int64_t T = (cV + k - 1) / k;
+    const int64_t ppm = std::llround(eps * 1e6);
+    return T + (T * ppm) / 1000000;
+}
+
+void check_k_eps(int32_t k, double eps) {
+    if (k < 1) fail(SCLAP_ERR_INVALID, "k must be >= 1");
+    if (!(eps >= 0.0) || eps > 1000.0) fail(SCLAP_ERR_INVALID, "eps must be in [0, 1000]");
+}
+
+// ------------------------------------------------- host initial partition
+
+// Smallest index >= from whose value is <= cap, over a segment tree of mins.
+struct MinTree {
+    int64_t size = 1;
+    std::vector<int64_t> t;
+    explicit MinTree(const std::vector<int64_t>& a) {
+        while (size < static_cast<int64_t>(a.size())) size <<= 1;
+        t.assign(2 * static_cast<size_t>(size), INT64_MAX);
+        for (size_t i = 0; i < a.size(); ++i) t[size + i] = a[i];
+        for (int32_t i = size - 1; i > 0; --i) t[i] = std::min(t[2 * i], t[2 * i + 1]);
+    }
+    void erase(int64_t i) {
+        int64_t p = i + size;
+        t[p] = INT64_MAX;
+        for (p >>= 1; p > 0; p >>= 1) t[p] = std::min(t[2 * p], t[2 * p + 1]);
+    }
+    int32_t first_le(int64_t from, int64_t cap) const { return static_cast<int32_t>(descend(1, 0, size, from, cap)); }
+    int64_t descend(int64_t node, int64_t lo, int64_t hi, int64_t from, int64_t cap) const {
+        if (hi <= from || t[node] > cap) return -1;
+        if (hi - lo == 1) return lo;
+        const int64_t mid = (lo + hi) / 2;
+        const int64_t r = descend(2 * node, lo, mid, from, cap);
+        return r >= 0 ? r : descend(2 * node + 1, mid, hi, from, cap);
+    }
+};
+
+// Grows blocks 0..k-2 by breadth-first search up to T each (seeds: smallest
+// unassigned node of positive degree that fits; neighbours in ascending id
+// order), then deals every remaining node, in id order, to the currently
+// lightest block (lowest id on ties).
+void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, const int32_t* vw, int32_t k,
+                            int64_t T, int32_t* part) {
+    std::fill(part, part + n, -1);
+    std::vector<int64_t> wb(static_cast<size_t>(k), 0);
+    std::vector<int64_t> seedw(static_cast<size_t>(n));
+    for (int32_t v = 0; v < n; ++v) seedw[v] = (xadj[v + 1] > xadj[v]) ? (vw ? vw[v] : 1) : INT64_MAX;
+    MinTree seeds(seedw);
+    std::vector<int32_t> nb;
+    std::deque<int32_t> q;
+    auto take = [&](int32_t v, int32_t b) {
+        part[v] = b;
+        wb[b] += vw ? vw[v] : 1;
+        if (seedw[v] != INT64_MAX) seeds.erase(v);
+    };
+    for (int32_t b = 0; b + 1 < k; ++b) {
+        int32_t from = 0;
+        while (true) {
+            const int32_t sd = seeds.first_le(from, T - wb[b]);
+            if (sd < 0) break;
+            take(sd, b);
+            q.push_back(sd);
+            while (!q.empty()) {
+                const int32_t u = q.front();
+                q.pop_front();
+                nb.assign(adj + xadj[u], adj + xadj[u + 1]);
+                if (!std::is_sorted(nb.begin(), nb.end())) std::sort(nb.begin(), nb.end());
+                for (int32_t x : nb) {
+                    if (part[x] >= 0) continue;
+                    if (wb[b] + (vw ? vw[x] : 1) > T) continue;
+                    take(x, b);
+                    q.push_back(x);
+                }
+            }
+            from = sd + 1;
+        }
+    }
+    using Item = std::pair<int64_t, int32_t>;  // (weight, block): lightest, then lowest id
+    std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+    for (int32_t b = 0; b < k; ++b) heap.push({wb[b], b});
+    for (int32_t v = 0; v < n; ++v) {
+        if (part[v] >= 0) continue;
+        Item it = heap.top();
+        heap.pop();
+        part[v] = it.second;
+        it.first += vw ? vw[v] : 1;
+        heap.push(it);
+    }
+}
+
+// ------------------------------------------------------------ multilevel
+
+struct Level {
+    OwnedDevGraph own;
+    DevGraph g;
+    DBuf<int32_t> C;  // map to the next coarser level
+};
+
+using Clock = std::chrono::steady_clock;
+double ms_since(Clock::time_point t) { return std::chrono::duration<double, std::milli>(Clock::now() - t).count(); }
+
+int partition_impl(const DevGraph& g0, int32_t k, double eps, uint64_t seed, const Opts& o, int32_t* part_out,
+                   int64_t* cut, int64_t* bw, sclap_stats* stats, hipStream_t s) {
+    check_k_eps(k, eps);
+    if (!part_out && g0.n > 0) fail(SCLAP_ERR_INVALID, "part is NULL");
+    if (!cut || !bw) fail(SCLAP_ERR_INVALID, "cut / block_w is NULL");
+    int64_t cV = 0, cmax0 = 0;
+    check_graph(g0, o.validate != 0, &cV, &cmax0, s);
+    sclap_stats local;
+    sclap_stats* st = stats ? stats : &local;
+    std::memset(st, 0, sizeof(*st));
+    const int64_t Lmax = lmax_of(cV, k, eps);
+    const int64_t W = cV / (static_cast<int64_t>(o.divisor) * k);
+
+    std::vector<Level> L(1);
+    L[0].g = g0;
+    st->level_n[0] = g0.n;
+    st->level_S[0] = g0.S;
+    auto t_coarsen = Clock::now();
+    double lp_ms = 0;
+    int32_t lev = 0;
+    while (L[lev].g.n > o.coarsest && lev < o.max_levels) {
+        const DevGraph G = L[lev].g;
+        const int32_t n = G.n;
+        int64_t cvl = 0, cmax = cmax0;
+        if (lev > 0) node_weight_stats(G, &cvl, &cmax, s);
+        const int64_t U = std::max(cmax, W);
+        DBuf<int32_t> labels(n, s), w(n, s);
+        iota_u32(reinterpret_cast<uint32_t*>(labels.get()), n, s);
+        label_weights(G, labels.get(), w.get(), n, s);
+        auto t_lp = Clock::now();
+        const LPResult r = run_lp(G, kCluster, lev, seed, o.nsub, o.coarsen_rounds, U, labels.get(), w.get(), n,
+                                  nullptr, o.tune, s);
+        lp_ms += ms_since(t_lp);
+        st->visits += r.visits;
+        st->cluster_rounds[lev] = r.rounds_run;
+        w.release();
+        DBuf<int32_t> C(n, s);
+        Level nx;
+        contract(G, labels.get(), C.get(), nx.own, s);
+        if (nx.own.n >= n) break;  // no shrink: keep the current level as the coarsest
+        L[lev].C = std::move(C);
+        nx.g = nx.own.view();
+        L.push_back(std::move(nx));
+        ++lev;
+        st->level_n[lev] = L[lev].g.n;
+        st->level_S[lev] = L[lev].g.S;
+        if (20LL * L[lev].g.n > 19LL * n) break;  // stalled
+    }
+    st->levels = lev;
+    HIPCHK(hipStreamSynchronize(s));
+    st->ms_coarsen = ms_since(t_coarsen);
+
+    // initial partition of the coarsest graph on the host
+    auto t_init = Clock::now();
+    const DevGraph Gc = L[lev].g;
+    const int32_t nc = Gc.n;
+    std::vector<int64_t> hx(static_cast<size_t>(nc) + 1);
+    std::vector<int32_t> ha(static_cast<size_t>(std::max<int64_t>(Gc.S, 1))), hv, hp(static_cast<size_t>(nc));
+    if (nc > 0) {
+        HIPCHK(hipMemcpyAsync(hx.data(), Gc.xadj, (nc + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        if (Gc.S > 0)
+            HIPCHK(hipMemcpyAsync(ha.data(), Gc.adj, Gc.S * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        if (Gc.vw) {
+            hv.resize(nc);
+            HIPCHK(hipMemcpyAsync(hv.data(), Gc.vw, nc * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        }
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    const int64_t T = (cV + k - 1) / k;
+    host_initial_partition(nc, hx.data(), ha.data(), Gc.vw ? hv.data() : nullptr, k, T, hp.data());
+    DBuf<int32_t> cur;
+    int32_t* curp = part_out;
+    if (lev > 0) {
+        cur.alloc(nc, s);
+        curp = cur.get();
+    }
+    if (nc > 0) HIPCHK(hipMemcpyAsync(curp, hp.data(), nc * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    st->ms_initial = ms_since(t_init);
+
+    auto t_ref = Clock::now();
+    DBuf<int32_t> w(k, s);
+    for (int32_t l = lev; l >= 0; --l) {
+        const DevGraph G = L[l].g;
+        if (l < lev) {
+            DBuf<int32_t> fine;
+            int32_t* finep = part_out;
+            if (l > 0) {
+                fine.alloc(G.n, s);
+                finep = fine.get();
+            }
+            project(G.n, L[l].C.get(), curp, finep, s);
+            cur = std::move(fine);
+            curp = finep;
+            L[l + 1].own = OwnedDevGraph();  // the coarser graph is no longer needed
+            L[l].C.release();
+        }
+        label_weights(G, curp, w.get(), k, s);
+        auto t_lp = Clock::now();
+        const LPResult r = run_lp(G, kRefine, l, seed, o.nsub, o.refine_rounds, Lmax, curp, w.get(), k, nullptr,
+                                  o.tune, s);
+        lp_ms += ms_since(t_lp);
+        st->visits += r.visits;
+        st->refine_rounds[l] = r.rounds_run;
+    }
+    cut_and_weights(g0, part_out, k, cut, bw, s);
+    st->ms_refine = ms_since(t_ref);
+    st->ms_lp = lp_ms;
+    for (int32_t b = 0; b < k; ++b)
+        if (bw[b] > Lmax) return SCLAP_WARN_IMBALANCED;
+    return SCLAP_OK;
+}
+
+// ------------------------------------------------ host <-> device staging
+
+struct Staged {
+    OwnedDevGraph own;
+    DevGraph g;
+};
+
+Staged upload(const sclap_graph* h, hipStream_t s) {
+    if (!h) fail(SCLAP_ERR_INVALID, "graph is NULL");
+    if (h->n < 0) fail(SCLAP_ERR_INVALID, "n < 0");
+    Staged st;
+    const int32_t n = h->n;
+    st.own.n = n;
+    if (n > 0 && !h->xadj) fail(SCLAP_ERR_INVALID, "xadj is NULL");
+    const int64_t S = n > 0 ? h->xadj[n] : 0;
+    if (S < 0) fail(SCLAP_ERR_INVALID, "xadj[n] < 0");
+    if (S > 0 && !h->adjncy) fail(SCLAP_ERR_INVALID, "adjncy is NULL");
+    st.own.S = S;
+    st.own.xadj.alloc(static_cast<size_t>(n) + 1, s);
+    if (n > 0) HIPCHK(hipMemcpyAsync(st.own.xadj.get(), h->xadj, (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    else fill_i64(st.own.xadj.get(), 0, 1, s);
+    if (S > 0) {
+        st.own.adj.alloc(S, s);
+        HIPCHK(hipMemcpyAsync(st.own.adj.get(), h->adjncy, S * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        if (h->adjwgt) {
+            st.own.ew.alloc(S, s);
+            HIPCHK(hipMemcpyAsync(st.own.ew.get(), h->adjwgt, S * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        }
+    }
+    if (n > 0 && h->vwgt) {
+        st.own.vw.alloc(n, s);
+        HIPCHK(hipMemcpyAsync(st.own.vw.get(), h->vwgt, n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    }
+    st.g = st.own.view();
+    return st;
+}
+
+template <typename T>
+DBuf<T> upload_array(const T* h, int64_t count, hipStream_t s) {
+    DBuf<T> d(std::max<int64_t>(count, 1), s);
+    if (count > 0) HIPCHK(hipMemcpyAsync(d.get(), h, count * sizeof(T), hipMemcpyHostToDevice, s));
+    return d;
+}
+
+template <typename T>
+void download(T* h, const T* d, int64_t count, hipStream_t s) {
+    if (count > 0) HIPCHK(hipMemcpyAsync(h, d, count * sizeof(T), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------ single operations
+
+int cluster_impl(const DevGraph& g, int64_t U, int32_t rounds, uint64_t seed, int32_t level, const Opts& o,
+                 const int32_t* color_dev, int32_t* labels, int32_t* rounds_run, hipStream_t s) {
+    if (rounds < 0) fail(SCLAP_ERR_INVALID, "rounds < 0");
+    if (U < 0) fail(SCLAP_ERR_INVALID, "U < 0");
+    if (g.n > 0 && !labels) fail(SCLAP_ERR_INVALID, "labels is NULL");
+    int64_t cV = 0, cmax = 0;
+    check_graph(g, o.validate != 0, &cV, &cmax, s);
+    if (color_dev && !all_in_range(color_dev, g.n, 0, o.nsub, s))
+        fail(SCLAP_ERR_INVALID, "color_override value outside [0, subrounds)");
+    DBuf<int32_t> w(std::max(g.n, 1), s);
+    iota_u32(reinterpret_cast<uint32_t*>(labels), g.n, s);
+    label_weights(g, labels, w.get(), g.n, s);
+    const LPResult r = run_lp(g, kCluster, level, seed, o.nsub, rounds, U, labels, w.get(), g.n, color_dev, o.tune, s);
+    HIPCHK(hipStreamSynchronize(s));
+    if (rounds_run) *rounds_run = r.rounds_run;
+    return SCLAP_OK;
+}
+
+int refine_impl(const DevGraph& g, int32_t k, int64_t Lmax, int32_t rounds, uint64_t seed, int32_t level,
+                const Opts& o, const int32_t* color_dev, int32_t* part, int32_t* rounds_run, hipStream_t s) {
+    if (k < 1) fail(SCLAP_ERR_INVALID, "k must be >= 1");
+    if (rounds < 0) fail(SCLAP_ERR_INVALID, "rounds < 0");
+    if (g.n > 0 && !part) fail(SCLAP_ERR_INVALID, "part is NULL");
+    int64_t cV = 0, cmax = 0;
+    check_graph(g, o.validate != 0, &cV, &cmax, s);
+    if (!all_in_range(part, g.n, 0, k, s)) fail(SCLAP_ERR_INVALID, "part value outside [0, k)");
+    if (color_dev && !all_in_range(color_dev, g.n, 0, o.nsub, s))
+        fail(SCLAP_ERR_INVALID, "color_override value outside [0, subrounds)");
+    DBuf<int32_t> w(k, s);
+    label_weights(g, part, w.get(), k, s);
+    const LPResult r = run_lp(g, kRefine, level, seed, o.nsub, rounds, Lmax, part, w.get(), k, color_dev, o.tune, s);
+    HIPCHK(hipStreamSynchronize(s));
+    if (rounds_run) *rounds_run = r.rounds_run;
+    return SCLAP_OK;
+}
+
+}  // namespace
+}  // namespace sclap
+
+using namespace sclap;
+
+// =================================================================== C ABI
+
+extern "C" {
+
+int sclap_default_options(sclap_options* opt) {
+    if (!opt) return SCLAP_ERR_INVALID;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->coarsen_rounds = 10;
+    opt->refine_rounds = 10;
+    opt->subrounds = 4;
+    opt->cluster_divisor = 18;
+    opt->coarsest_nodes = 10000;
+    opt->max_levels = SCLAP_MAX_LEVELS;
+    opt->validate = 1;
+    return SCLAP_OK;
+}
+
+const char* sclap_last_error(void) { return t_err.c_str(); }
+
+int64_t sclap_lmax(int64_t cV, int32_t k, double eps) {
+    if (k < 1) return -1;
+    return lmax_of(cV, k, eps);
+}
+
+int sclap_validate_dev(const sclap_graph* g, void* stream) {
+    return guarded([&] {
+        hipStream_t s = as_stream(stream);
+        const DevGraph d = dev_view(g, s);
+        int64_t cV, cmax;
+        const int st = validate_graph(d, &cV, &cmax, s);
+        if (st != 0) t_err = "graph validation failed";
+        return st;
+    });
+}
+
+int sclap_validate(const sclap_graph* g) {
+    return guarded([&]() -> int {
+        if (!g || g->n < 0) fail(SCLAP_ERR_INVALID, "bad graph");
+        const int32_t n = g->n;
+        if (n == 0) return SCLAP_OK;
+        if (!g->xadj || g->xadj[0] != 0) fail(SCLAP_ERR_INVALID, "xadj must start at 0");
+        for (int32_t v = 0; v < n; ++v)
+            if (g->xadj[v + 1] < g->xadj[v]) fail(SCLAP_ERR_INVALID, "xadj not monotone");
+        const int64_t S = g->xadj[n];
+        if (S > 0 && !g->adjncy) fail(SCLAP_ERR_INVALID, "adjncy is NULL");
+        int64_t cV = 0, ws = 0;
+        std::vector<std::pair<uint64_t, int32_t>> fwd(S), bwd(S);
+        for (int32_t v = 0; v < n; ++v) {
+            const int32_t c = g->vwgt ? g->vwgt[v] : 1;
+            if (c < 0) fail(SCLAP_ERR_INVALID, "negative node weight");
+            cV += c;
+            for (int64_t i = g->xadj[v]; i < g->xadj[v + 1]; ++i) {
+                const int32_t u = g->adjncy[i];
+                const int32_t w = g->adjwgt ? g->adjwgt[i] : 1;
+                if (u < 0 || u >= n || u == v) fail(SCLAP_ERR_INVALID, "neighbour id out of range or self-loop");
+                if (w < 1) fail(SCLAP_ERR_INVALID, "edge weight < 1");
+                ws += w;
+                fwd[i] = {(static_cast<uint64_t>(v) << 32) | static_cast<uint32_t>(u), w};
+                bwd[i] = {(static_cast<uint64_t>(u) << 32) | static_cast<uint32_t>(v), w};
+            }
+        }
+        if (cV > 2147483647LL || ws / 2 > 2147483647LL) fail(SCLAP_ERR_OVERFLOW, "weight total exceeds 2^31-1");
+        std::sort(fwd.begin(), fwd.end());
+        std::sort(bwd.begin(), bwd.end());
+        if (fwd != bwd) fail(SCLAP_ERR_NOT_SYMMETRIC, "graph is not symmetric");
+        return SCLAP_OK;
+    });
+}
+
+int sclap_cluster_dev(const sclap_graph* g, int64_t U, int32_t rounds, uint64_t seed, int32_t level,
+                      const sclap_options* opt, int32_t* labels, int32_t* rounds_run, void* stream) {
+    return guarded([&] {
+        hipStream_t s = as_stream(stream);
+        const Opts o = resolve(opt);
+        const DevGraph d = dev_view(g, s);
+        return cluster_impl(d, U, rounds, seed, level, o, o.color_override, labels, rounds_run, s);
+    });
+}
+
+int sclap_cluster(const sclap_graph* g, int64_t U, int32_t rounds, uint64_t seed, int32_t level,
+                  const sclap_options* opt, int32_t* labels, int32_t* rounds_run) {
+    return guarded([&] {
+        hipStream_t s = nullptr;
+        const Opts o = resolve(opt);
+        Staged st = upload(g, s);
+        DBuf<int32_t> col;
+        if (o.color_override) col = upload_array(o.color_override, g->n, s);
+        DBuf<int32_t> lab(std::max(g->n, 1), s);
+        const int r = cluster_impl(st.g, U, rounds, seed, level, o, o.color_override ? col.get() : nullptr,
+                                   lab.get(), rounds_run, s);
+        download(labels, lab.get(), g->n, s);
+        return r;
+    });
+}
+
+int sclap_refine_dev(const sclap_graph* g, int32_t k, int64_t Lmax, int32_t rounds, uint64_t seed, int32_t level,
+                     const sclap_options* opt, int32_t* part, int32_t* rounds_run, void* stream) {
+    return guarded([&] {
+        hipStream_t s = as_stream(stream);
+        const Opts o = resolve(opt);
+        const DevGraph d = dev_view(g, s);
+        return refine_impl(d, k, Lmax, rounds, seed, level, o, o.color_override, part, rounds_run, s);
+    });
+}
+
+int sclap_refine(const sclap_graph* g, int32_t k, int64_t Lmax, int32_t rounds, uint64_t seed, int32_t level,
+                 const sclap_options* opt, int32_t* part, int32_t* rounds_run) {
+    return guarded([&] {
+        hipStream_t s = nullptr;
+        const Opts o = resolve(opt);
+        Staged st = upload(g, s);
+        if (g->n > 0 && !part) fail(SCLAP_ERR_INVALID, "part is NULL");
+        DBuf<int32_t> col;
+        if (o.color_override) col = upload_array(o.color_override, g->n, s);
+        DBuf<int32_t> p = upload_array(part, g->n, s);
+        const int r = refine_impl(st.g, k, Lmax, rounds, seed, level, o, o.color_override ? col.get() : nullptr,
+                                  p.get(), rounds_run, s);
+        download(part, p.get(), g->n, s);
+        return r;
+    });
+}
+
+int sclap_contract_dev(const sclap_graph* g, const int32_t* labels, int32_t* C, sclap_graph_owned* coarse,
+                       void* stream) {
+    return guarded([&] {
+        hipStream_t s = as_stream(stream);
+        if (!coarse) fail(SCLAP_ERR_INVALID, "coarse is NULL");
+        const DevGraph d = dev_view(g, s);
+        if (d.n > 0 && (!labels || !C)) fail(SCLAP_ERR_INVALID, "labels / C is NULL");
+        if (!all_in_range(labels, d.n, 0, std::max(d.n, 1), s)) fail(SCLAP_ERR_INVALID, "label outside [0, n)");
+        OwnedDevGraph cg;
+        contract(d, labels, C, cg, s);
+        HIPCHK(hipStreamSynchronize(s));
+        coarse->n = cg.n;
+        coarse->S = cg.S;
+        coarse->xadj = cg.xadj.p;
+        coarse->adjncy = cg.adj.p;
+        coarse->adjwgt = cg.ew.p;
+        coarse->vwgt = cg.vw.p;
+        coarse->on_device = 1;
+        cg.xadj.p = nullptr;
+        cg.adj.p = nullptr;
+        cg.ew.p = nullptr;
+        cg.vw.p = nullptr;
+        return SCLAP_OK;
+    });
+}
+
+int sclap_contract(const sclap_graph* g, const int32_t* labels, int32_t* C, sclap_graph_owned* coarse) {
+    return guarded([&] {
+        hipStream_t s = nullptr;
+        if (!coarse) fail(SCLAP_ERR_INVALID, "coarse is NULL");
+        Staged st = upload(g, s);
+        const int32_t n = st.g.n;
+        if (n > 0 && (!labels || !C)) fail(SCLAP_ERR_INVALID, "labels / C is NULL");
+        DBuf<int32_t> lab = upload_array(labels, n, s);
+        if (!all_in_range(lab.get(), n, 0, std::max(n, 1), s)) fail(SCLAP_ERR_INVALID, "label outside [0, n)");
+        DBuf<int32_t> dC(std::max(n, 1), s);
+        OwnedDevGraph cg;
+        contract(st.g, lab.get(), dC.get(), cg, s);
+        download(C, dC.get(), n, s);
+        sclap_graph_owned out{};
+        out.n = cg.n;
+        out.S = cg.S;
+        out.on_device = 0;
+        out.xadj = static_cast<int64_t*>(std::malloc((cg.n + 1) * sizeof(int64_t)));
+        out.adjncy = static_cast<int32_t*>(std::malloc(std::max<int64_t>(cg.S, 1) * sizeof(int32_t)));
+        out.adjwgt = static_cast<int32_t*>(std::malloc(std::max<int64_t>(cg.S, 1) * sizeof(int32_t)));
+        out.vwgt = static_cast<int32_t*>(std::malloc(std::max(cg.n, 1) * sizeof(int32_t)));
+        if (!out.xadj || !out.adjncy || !out.adjwgt || !out.vwgt) {
+            std::free(out.xadj); std::free(out.adjncy); std::free(out.adjwgt); std::free(out.vwgt);
+            throw std::bad_alloc();
+        }
+        download(out.xadj, cg.xadj.get(), cg.n + 1, s);
+        download(out.adjncy, cg.adj.get(), cg.S, s);
+        download(out.adjwgt, cg.ew.get(), cg.S, s);
+        download(out.vwgt, cg.vw.get(), cg.n, s);
+        *coarse = out;
+        return SCLAP_OK;
+    });
+}
+
+void sclap_graph_free(sclap_graph_owned* g) {
+    if (!g) return;
+    if (g->on_device) {
+        if (g->xadj) (void)hipFreeAsync(g->xadj, nullptr);
+        if (g->adjncy) (void)hipFreeAsync(g->adjncy, nullptr);
+        if (g->adjwgt) (void)hipFreeAsync(g->adjwgt, nullptr);
+        if (g->vwgt) (void)hipFreeAsync(g->vwgt, nullptr);
+        (void)hipStreamSynchronize(nullptr);
+    } else {
+        std::free(g->xadj);
+        std::free(g->adjncy);
+        std::free(g->adjwgt);
+        std::free(g->vwgt);
+    }
+    std::memset(g, 0, sizeof(*g));
+}
+
+int sclap_project_dev(int32_t n, int32_t n_coarse, const int32_t* C, const int32_t* coarse_part, int32_t* part,
+                      void* stream) {
+    return guarded([&] {
+        hipStream_t s = as_stream(stream);
+        if (n < 0 || n_coarse < 0) fail(SCLAP_ERR_INVALID, "negative size");
+        if (n == 0) return SCLAP_OK;
+        if (!C || !coarse_part || !part) fail(SCLAP_ERR_INVALID, "NULL array");
+        if (!all_in_range(C, n, 0, n_coarse, s)) fail(SCLAP_ERR_INVALID, "C value outside [0, n_coarse)");
+        project(n, C, coarse_part, part, s);
+        HIPCHK(hipStreamSynchronize(s));
+        return SCLAP_OK;
+    });
+}
+
+int sclap_project(int32_t n, int32_t n_coarse, const int32_t* C, const int32_t* coarse_part, int32_t* part) {
+    return guarded([&] {
+        hipStream_t s = nullptr;
+        if (n < 0 || n_coarse < 0) fail(SCLAP_ERR_INVALID, "negative size");
+        if (n == 0) return SCLAP_OK;
+        if (!C || !coarse_part || !part) fail(SCLAP_ERR_INVALID, "NULL array");
+        DBuf<int32_t> dC = upload_array(C, n, s);
+        DBuf<int32_t> dcp = upload_array(coarse_part, n_coarse, s);
+        DBuf<int32_t> dp(n, s);
+        if (!all_in_range(dC.get(), n, 0, n_coarse, s)) fail(SCLAP_ERR_INVALID, "C value outside [0, n_coarse)");
+        project(n, dC.get(), dcp.get(), dp.get(), s);
+        download(part, dp.get(), n, s);
+        return SCLAP_OK;
+    });
+}
+
+int sclap_cut_dev(const sclap_graph* g, const int32_t* part, int32_t k, int64_t* cut, int64_t* block_w,
+                  void* stream) {
+    return guarded([&] {
+        hipStream_t s = as_stream(stream);
+        if (k < 1 || !cut || !block_w) fail(SCLAP_ERR_INVALID, "bad k or NULL output");
+        const DevGraph d = dev_view(g, s);
+        if (d.n > 0 && !part) fail(SCLAP_ERR_INVALID, "part is NULL");
+        if (!all_in_range(part, d.n, 0, k, s)) fail(SCLAP_ERR_INVALID, "part value outside [0, k)");
+        cut_and_weights(d, part, k, cut, block_w, s);
+        return SCLAP_OK;
+    });
+}
+
+int sclap_cut(const sclap_graph* g, const int32_t* part, int32_t k, int64_t* cut, int64_t* block_w) {
+    return guarded([&] {
+        hipStream_t s = nullptr;
+        if (k < 1 || !cut || !block_w) fail(SCLAP_ERR_INVALID, "bad k or NULL output");
+        Staged st = upload(g, s);
+        if (st.g.n > 0 && !part) fail(SCLAP_ERR_INVALID, "part is NULL");
+        DBuf<int32_t> p = upload_array(part, st.g.n, s);
+        if (!all_in_range(p.get(), st.g.n, 0, k, s)) fail(SCLAP_ERR_INVALID, "part value outside [0, k)");
+        cut_and_weights(st.g, p.get(), k, cut, block_w, s);
+        return SCLAP_OK;
+    });
+}
+
+int sclap_initial_partition(const sclap_graph* g, int32_t k, int32_t* part) {
+    return guarded([&] {
+        if (!g || g->n < 0 || k < 1) fail(SCLAP_ERR_INVALID, "bad arguments");
+        if (g->n == 0) return SCLAP_OK;
+        if (!g->xadj || !part || (g->xadj[g->n] > 0 && !g->adjncy)) fail(SCLAP_ERR_INVALID, "NULL array");
+        int64_t cV = 0;
+        for (int32_t v = 0; v < g->n; ++v) cV += g->vwgt ? g->vwgt[v] : 1;
+        host_initial_partition(g->n, g->xadj, g->adjncy, g->vwgt, k, (cV + k - 1) / k, part);
+        return SCLAP_OK;
+    });
+}
+
+int sclap_partition_dev(const sclap_graph* g, int32_t k, double eps, uint64_t seed, const sclap_options* opt,
+                        int32_t* part, int64_t* cut, int64_t* block_w, sclap_stats* stats, void* stream) {
+    return guarded([&] {
+        hipStream_t s = as_stream(stream);
+        const Opts o = resolve(opt);
+        const DevGraph d = dev_view(g, s);
+        return partition_impl(d, k, eps, seed, o, part, cut, block_w, stats, s);
+    });
+}
+
+int sclap_partition(const sclap_graph* g, int32_t k, double eps, uint64_t seed, const sclap_options* opt,
+                    int32_t* part, int64_t* cut, int64_t* block_w, sclap_stats* stats) {
+    return guarded([&] {
+        hipStream_t s = nullptr;
+        const Opts o = resolve(opt);
+        check_k_eps(k, eps);
+        Staged st = upload(g, s);
+        if (st.g.n > 0 && !part) fail(SCLAP_ERR_INVALID, "part is NULL");
+        DBuf<int32_t> p(std::max(st.g.n, 1), s);
+        const int r = partition_impl(st.g, k, eps, seed, o, p.get(), cut, block_w, stats, s);
+        download(part, p.get(), st.g.n, s);
+        return r;
+    });
+}
+
+int sclap_profile_begin(void) {
+    return guarded([&] {
+        profiler().reset();
+        profiler().on = true;
+        return SCLAP_OK;
+    });
+}
+
+int sclap_profile_end(sclap_kernel_stat* out, int32_t capacity, int32_t* count) {
+    return guarded([&] {
+        Profiler& p = profiler();
+        p.collect();
+        const int32_t m = static_cast<int32_t>(p.stats.size());
+        for (int32_t i = 0; i < m && i < capacity && out; ++i) {
+            std::memset(&out[i], 0, sizeof(out[i]));
+            std::strncpy(out[i].name, p.stats[i].name.c_str(), sizeof(out[i].name) - 1);
+            out[i].launches = p.stats[i].launches;
+            out[i].ms = p.stats[i].ms;
+            out[i].bytes = p.stats[i].bytes;
+        }
+        if (count) *count = m;
+        p.stats.clear();
+        p.on = false;
+        return SCLAP_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,455 @@
+// Contraction, projection, cut / block weights and validation on gfx950.
+//
+// Slot-parallel kernels walk the adjacency array in tiles of kTile
+// consecutive slots.  Each workgroup recovers the source node of every slot
+// of its tile in LDS (row starts scattered into the tile, then a max-scan), so
+// rows of any length are split evenly over the grid without a per-slot search.
+#include <climits>
+
+#include "graph_ops.hpp"
+
+namespace sclap {
+
+namespace {
+
+constexpr int kTileThreads = 256;
+constexpr int kTilePer = 8;
+constexpr int kTile = kTileThreads * kTilePer;
+
+__device__ int32_t upper_node(const int64_t* __restrict__ xadj, int32_t n, int64_t slot) {
+    // largest u in [0, n) with xadj[u] <= slot
+    int32_t lo = 0, hi = n;  // invariant: xadj[lo] <= slot, answer in [lo, hi)
+    while (hi - lo > 1) {
+        const int32_t mid = lo + (hi - lo) / 2;
+        if (xadj[mid] <= slot) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Fills owner[0 .. i1-i0) with the source node of each slot of [i0, i1).
+__device__ void tile_owners(const int64_t* __restrict__ xadj, int32_t n, int64_t i0, int64_t i1, int32_t* owner) {
+    __shared__ int32_t s_u[2];
+    __shared__ int32_t s_carry[kTileThreads / kWave];
+    const int tid = threadIdx.x;
+    for (int j = tid; j < kTile; j += kTileThreads) owner[j] = -1;
+    if (tid == 0) s_u[0] = upper_node(xadj, n, i0);
+    if (tid == 1) s_u[1] = upper_node(xadj, n, i1 - 1);
+    __syncthreads();
+    const int32_t u0 = s_u[0], u1 = s_u[1];
+    if (tid == 0) atomicMax(&owner[0], u0);
+    for (int64_t u = static_cast<int64_t>(u0) + 1 + tid; u <= u1; u += kTileThreads) {
+        const int64_t st = xadj[u];
+        if (st >= i0 && st < i1) atomicMax(&owner[st - i0], static_cast<int32_t>(u));
+    }
+    __syncthreads();
+    // inclusive max-scan over the tile: 8 consecutive entries per thread
+    int32_t loc[kTilePer];
+    int32_t m = -1;
+#pragma unroll
+    for (int j = 0; j < kTilePer; ++j) {
+        loc[j] = owner[tid * kTilePer + j];
+        m = loc[j] > m ? loc[j] : m;
+    }
+    int32_t incl = m;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int32_t t = __shfl_up(incl, o, 64);
+        if (lane_id() >= o) incl = t > incl ? t : incl;
+    }
+    if (lane_id() == kWave - 1) s_carry[tid / kWave] = incl;
+    __syncthreads();
+    int32_t run = __shfl_up(incl, 1, 64);
+    if (lane_id() == 0) run = -1;
+    for (int w = 0; w < tid / kWave; ++w) run = s_carry[w] > run ? s_carry[w] : run;
+#pragma unroll
+    for (int j = 0; j < kTilePer; ++j) {
+        run = loc[j] > run ? loc[j] : run;
+        owner[tid * kTilePer + j] = run;
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------ contraction
+
+__global__ void mark_used_kernel(int32_t n, const int32_t* __restrict__ labels, int32_t* __restrict__ used) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v < n) used[labels[v]] = 1;
+}
+
+__global__ void map_kernel(int32_t n, const int32_t* __restrict__ labels, const int32_t* __restrict__ q,
+                           const int32_t* __restrict__ vw, int32_t* __restrict__ C, int32_t* __restrict__ cvw) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= n) return;
+    const int32_t cv = q[labels[v]];
+    C[v] = cv;
+    const int32_t c = vw ? vw[v] : 1;
+    if (c) atomicAdd(&cvw[cv], c);
+}
+
+// Emits (C(u) << bn | C(v), w) for every slot u->v between different clusters.
+__global__ void __launch_bounds__(kTileThreads) emit_kernel(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj,
+                                                            const int32_t* __restrict__ ew, int32_t n, int64_t S,
+                                                            const int32_t* __restrict__ C, int bn,
+                                                            uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                            unsigned long long* __restrict__ count) {
+    __shared__ int32_t owner[kTile];
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kTile;
+    const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
+    tile_owners(xadj, n, i0, i1, owner);
+    for (int r = 0; r < kTilePer; ++r) {
+        const int64_t i = i0 + r * kTileThreads + threadIdx.x;
+        bool e = false;
+        uint64_t key = 0;
+        uint32_t val = 0;
+        if (i < i1) {
+            const int32_t cu = C[owner[i - i0]];
+            const int32_t cx = C[adj[i]];
+            if (cu != cx) {
+                e = true;
+                key = (static_cast<uint64_t>(cu) << bn) | static_cast<uint64_t>(cx);
+                val = ew ? static_cast<uint32_t>(ew[i]) : 1u;
+            }
+        }
+        const uint64_t m = __ballot(e);
+        if (m == 0) continue;
+        const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+        unsigned long long base = 0;
+        if (lane_id() == leader) base = atomicAdd(count, static_cast<unsigned long long>(__popcll(m)));
+        base = __shfl(base, leader, 64);
+        if (e) {
+            const unsigned long long idx = base + static_cast<unsigned long long>(__popcll(m & lanemask_lt()));
+            keys[idx] = key;
+            vals[idx] = val;
+        }
+    }
+}
+
+__global__ void heads_kernel(const uint64_t* __restrict__ keys, int64_t m, int32_t* __restrict__ head) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i < m) head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+}
+
+__global__ void reduce_write_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t m,
+                                    const int32_t* __restrict__ head, const int64_t* __restrict__ pos, int bn,
+                                    int32_t* __restrict__ cadj, int32_t* __restrict__ cadjw,
+                                    int32_t* __restrict__ rowcnt) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= m) return;
+    const int64_t p = pos[i] + head[i] - 1;  // index of this key's coarse slot
+    const uint64_t k = keys[i];
+    if (head[i]) {
+        cadj[p] = static_cast<int32_t>(k & ((1ULL << bn) - 1));
+        atomicAdd(&rowcnt[k >> bn], 1);
+    }
+    atomicAdd(&cadjw[p], static_cast<int32_t>(vals[i]));
+}
+
+__global__ void set_last_kernel(int64_t* __restrict__ xadj, int32_t n, const int64_t* __restrict__ total) {
+    xadj[n] = *total;
+}
+
+__global__ void project_kernel(int32_t n, const int32_t* __restrict__ C, const int32_t* __restrict__ cp,
+                               int32_t* __restrict__ part) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v < n) part[v] = cp[C[v]];
+}
+
+// ---------------------------------------------------------- cut and weights
+
+__global__ void __launch_bounds__(kTileThreads) cut_kernel(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj,
+                                                           const int32_t* __restrict__ ew, int32_t n, int64_t S,
+                                                           const int32_t* __restrict__ part,
+                                                           unsigned long long* __restrict__ cut) {
+    __shared__ int32_t owner[kTile];
+    __shared__ unsigned long long s_sum[kTileThreads / kWave];
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kTile;
+    const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
+    tile_owners(xadj, n, i0, i1, owner);
+    unsigned long long acc = 0;
+    for (int r = 0; r < kTilePer; ++r) {
+        const int64_t i = i0 + r * kTileThreads + threadIdx.x;
+        if (i < i1 && part[owner[i - i0]] != part[adj[i]]) acc += ew ? static_cast<unsigned long long>(ew[i]) : 1ULL;
+    }
+    acc = wave_sum(acc);
+    if (lane_id() == 0) s_sum[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kTileThreads / kWave; ++w) t += s_sum[w];
+        if (t) atomicAdd(cut, t);
+    }
+}
+
+__global__ void __launch_bounds__(256) block_weight_kernel(int32_t n, const int32_t* __restrict__ part,
+                                                           const int32_t* __restrict__ vw, int32_t k,
+                                                           unsigned long long* __restrict__ bw) {
+    __shared__ unsigned long long loc[1024];
+    const bool use_lds = k <= 1024;
+    if (use_lds)
+        for (int j = threadIdx.x; j < k; j += 256) loc[j] = 0;
+    __syncthreads();
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v < n) {
+        const unsigned long long c = vw ? static_cast<unsigned long long>(vw[v]) : 1ULL;
+        if (c) {
+            if (use_lds) atomicAdd(&loc[part[v]], c);
+            else atomicAdd(&bw[part[v]], c);
+        }
+    }
+    __syncthreads();
+    if (use_lds)
+        for (int j = threadIdx.x; j < k; j += 256)
+            if (loc[j]) atomicAdd(&bw[j], loc[j]);
+}
+
+// ------------------------------------------------------------- validation
+
+struct VStats {
+    unsigned long long cV;
+    unsigned long long wsum;
+    unsigned long long hfwd;
+    unsigned long long hbwd;
+    int32_t cmax;
+    uint32_t bad;  // bit 0: structure / range, bit 1: negative node weight, bit 2: edge weight < 1
+    uint32_t pad[2];
+};
+
+__device__ __forceinline__ unsigned long long edge_hash(uint32_t u, uint32_t v, uint32_t w) {
+    return mix64(mix64((static_cast<uint64_t>(u) << 32) | v) ^ w);
+}
+
+__global__ void validate_nodes_kernel(int32_t n, const int64_t* __restrict__ xadj, const int32_t* __restrict__ vw,
+                                      VStats* st) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    unsigned long long c = 0;
+    int32_t cm = 0;
+    uint32_t bad = 0;
+    if (v < n) {
+        if (xadj[v + 1] < xadj[v]) bad |= 1u;
+        const int32_t cv = vw ? vw[v] : 1;
+        if (cv < 0) {
+            bad |= 2u;
+        } else {
+            c = static_cast<unsigned long long>(cv);
+            cm = cv;
+        }
+    }
+    c = wave_sum(c);
+    cm = wave_max(cm);
+    if (lane_id() == 0) {
+        if (c) atomicAdd(&st->cV, c);
+        atomicMax(&st->cmax, cm);
+    }
+    if (bad) atomicOr(&st->bad, bad);
+}
+
+__global__ void __launch_bounds__(kTileThreads) validate_slots_kernel(const int64_t* __restrict__ xadj,
+                                                                      const int32_t* __restrict__ adj,
+                                                                      const int32_t* __restrict__ ew, int32_t n,
+                                                                      int64_t S, VStats* st) {
+    __shared__ int32_t owner[kTile];
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kTile;
+    const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
+    tile_owners(xadj, n, i0, i1, owner);
+    unsigned long long ws = 0, hf = 0, hb = 0;
+    uint32_t bad = 0;
+    for (int r = 0; r < kTilePer; ++r) {
+        const int64_t i = i0 + r * kTileThreads + threadIdx.x;
+        if (i >= i1) continue;
+        const int32_t u = owner[i - i0];
+        const int32_t x = adj[i];
+        const int32_t w = ew ? ew[i] : 1;
+        if (x < 0 || x >= n || x == u) bad |= 1u;
+        if (w < 1) bad |= 4u;
+        ws += static_cast<unsigned long long>(w > 0 ? w : 0);
+        hf += edge_hash(static_cast<uint32_t>(u), static_cast<uint32_t>(x), static_cast<uint32_t>(w));
+        hb += edge_hash(static_cast<uint32_t>(x), static_cast<uint32_t>(u), static_cast<uint32_t>(w));
+    }
+    ws = wave_sum(ws);
+    hf = wave_sum(hf);
+    hb = wave_sum(hb);
+    if (lane_id() == 0) {
+        if (ws) atomicAdd(&st->wsum, ws);
+        atomicAdd(&st->hfwd, hf);
+        atomicAdd(&st->hbwd, hb);
+    }
+    if (bad) atomicOr(&st->bad, bad);
+}
+
+__global__ void range_kernel(const int32_t* __restrict__ a, int64_t count, int32_t lo, int32_t hi,
+                             uint32_t* __restrict__ bad) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i < count && (a[i] < lo || a[i] >= hi)) atomicOr(bad, 1u);
+}
+
+}  // namespace
+
+void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGraph& coarse, hipStream_t s) {
+    const int32_t n = g.n;
+    if (n == 0) {
+        coarse.n = 0;
+        coarse.S = 0;
+        coarse.xadj.alloc(1, s);
+        fill_i64(coarse.xadj.get(), 0, 1, s);
+        return;
+    }
+    DBuf<int32_t> q(n, s);
+    DBuf<int32_t> total(1, s);
+    fill_i32(q.get(), 0, n, s);
+    mark_used_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, labels, q.get());
+    LAUNCHCHK();
+    exclusive_scan_i32(q.get(), q.get(), n, total.get(), s);
+    int32_t nc = 0;
+    HIPCHK(hipMemcpyAsync(&nc, total.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    coarse.n = nc;
+    coarse.vw.alloc(nc, s);
+    fill_i32(coarse.vw.get(), 0, nc, s);
+    map_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, labels, q.get(), g.vw, C, coarse.vw.get());
+    LAUNCHCHK();
+    q.release();
+
+    // inter-cluster slots, sorted by (C(u), C(v)), equal keys summed
+    const int bn = std::max(1, bits_for(static_cast<uint64_t>(nc - 1)));
+    DBuf<uint64_t> keys(std::max<int64_t>(g.S, 1), s);
+    DBuf<uint32_t> vals(std::max<int64_t>(g.S, 1), s);
+    DBuf<unsigned long long> cnt(1, s);
+    HIPCHK(hipMemsetAsync(cnt.get(), 0, sizeof(unsigned long long), s));
+    if (g.S > 0) {
+        emit_kernel<<<grid_for(g.S, kTile), kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, n, g.S, C, bn, keys.get(),
+                                                                  vals.get(), cnt.get());
+        LAUNCHCHK();
+    }
+    unsigned long long m64 = 0;
+    HIPCHK(hipMemcpyAsync(&m64, cnt.get(), sizeof(m64), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const int64_t m = static_cast<int64_t>(m64);
+    coarse.xadj.alloc(static_cast<size_t>(nc) + 1, s);
+    DBuf<int32_t> rowcnt(std::max(nc, 1), s);
+    fill_i32(rowcnt.get(), 0, nc, s);
+    if (m == 0) {
+        coarse.S = 0;
+        coarse.adj.alloc(1, s);
+        coarse.ew.alloc(1, s);
+        fill_i64(coarse.xadj.get(), 0, static_cast<int64_t>(nc) + 1, s);
+        return;
+    }
+    {
+        DBuf<uint64_t> ktmp(m, s);
+        DBuf<uint32_t> vtmp(m, s);
+        RadixScratch rs;
+        radix_sort_pairs(keys.get(), vals.get(), ktmp.get(), vtmp.get(), m, 0, 2 * bn, rs, s);
+    }
+    DBuf<int32_t> head(m, s);
+    DBuf<int64_t> pos(m, s), stot(1, s);
+    heads_kernel<<<grid_for(m, 256), 256, 0, s>>>(keys.get(), m, head.get());
+    LAUNCHCHK();
+    exclusive_scan_i32_to_i64(head.get(), pos.get(), m, stot.get(), s);
+    int64_t Sc = 0;
+    HIPCHK(hipMemcpyAsync(&Sc, stot.get(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    coarse.S = Sc;
+    coarse.adj.alloc(Sc, s);
+    coarse.ew.alloc(Sc, s);
+    fill_i32(coarse.ew.get(), 0, Sc, s);
+    reduce_write_kernel<<<grid_for(m, 256), 256, 0, s>>>(keys.get(), vals.get(), m, head.get(), pos.get(), bn,
+                                                         coarse.adj.get(), coarse.ew.get(), rowcnt.get());
+    LAUNCHCHK();
+    exclusive_scan_i32_to_i64(rowcnt.get(), coarse.xadj.get(), nc, stot.get(), s);
+    set_last_kernel<<<1, 1, 0, s>>>(coarse.xadj.get(), nc, stot.get());
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+void project(int32_t n, const int32_t* C, const int32_t* coarse_part, int32_t* part, hipStream_t s) {
+    if (n <= 0) return;
+    project_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, C, coarse_part, part);
+    LAUNCHCHK();
+}
+
+void cut_and_weights(const DevGraph& g, const int32_t* part, int32_t k, int64_t* cut, int64_t* bw, hipStream_t s) {
+    DBuf<unsigned long long> acc(1 + static_cast<size_t>(k), s);
+    HIPCHK(hipMemsetAsync(acc.get(), 0, (1 + static_cast<size_t>(k)) * sizeof(unsigned long long), s));
+    if (g.S > 0) {
+        cut_kernel<<<grid_for(g.S, kTile), kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, g.n, g.S, part, acc.get());
+        LAUNCHCHK();
+    }
+    if (g.n > 0) {
+        block_weight_kernel<<<grid_for(g.n, 256), 256, 0, s>>>(g.n, part, g.vw, k, acc.get() + 1);
+        LAUNCHCHK();
+    }
+    std::vector<unsigned long long> h(1 + static_cast<size_t>(k));
+    HIPCHK(hipMemcpyAsync(h.data(), acc.get(), h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *cut = static_cast<int64_t>(h[0] / 2);
+    for (int32_t b = 0; b < k; ++b) bw[b] = static_cast<int64_t>(h[1 + b]);
+}
+
+int validate_graph(const DevGraph& g, int64_t* cV, int64_t* cmax, hipStream_t s) {
+    const int32_t n = g.n;
+    if (n < 0) return -1;
+    if (n == 0) {
+        *cV = 0;
+        *cmax = 0;
+        return 0;
+    }
+    if (!g.xadj) return -1;
+    int64_t ends[2];
+    HIPCHK(hipMemcpyAsync(&ends[0], g.xadj, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&ends[1], g.xadj + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (ends[0] != 0 || ends[1] != g.S || g.S < 0) return -1;
+    if (g.S > 0 && !g.adj) return -1;
+    DBuf<VStats> st(1, s);
+    HIPCHK(hipMemsetAsync(st.get(), 0, sizeof(VStats), s));
+    validate_nodes_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, g.xadj, g.vw, st.get());
+    LAUNCHCHK();
+    VStats h;
+    HIPCHK(hipMemcpyAsync(&h, st.get(), sizeof(VStats), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (h.bad) return -1;  // offsets not monotone or negative node weight
+    if (g.S > 0) {
+        validate_slots_kernel<<<grid_for(g.S, kTile), kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, n, g.S, st.get());
+        LAUNCHCHK();
+        HIPCHK(hipMemcpyAsync(&h, st.get(), sizeof(VStats), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    if (h.bad) return -1;
+    if (h.cV > 2147483647ULL || h.wsum / 2 > 2147483647ULL) return -3;
+    if (h.hfwd != h.hbwd) return -2;
+    *cV = static_cast<int64_t>(h.cV);
+    *cmax = h.cmax;
+    return 0;
+}
+
+void node_weight_stats(const DevGraph& g, int64_t* cV, int64_t* cmax, hipStream_t s) {
+    if (g.n == 0) {
+        *cV = 0;
+        *cmax = 0;
+        return;
+    }
+    DBuf<VStats> st(1, s);
+    HIPCHK(hipMemsetAsync(st.get(), 0, sizeof(VStats), s));
+    validate_nodes_kernel<<<grid_for(g.n, 256), 256, 0, s>>>(g.n, g.xadj, g.vw, st.get());
+    LAUNCHCHK();
+    VStats h;
+    HIPCHK(hipMemcpyAsync(&h, st.get(), sizeof(VStats), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *cV = static_cast<int64_t>(h.cV);
+    *cmax = h.cmax;
+}
+
+bool all_in_range(const int32_t* a, int64_t count, int32_t lo, int32_t hi, hipStream_t s) {
+    if (count <= 0) return true;
+    DBuf<uint32_t> bad(1, s);
+    fill_u32(bad.get(), 0, 1, s);
+    range_kernel<<<grid_for(count, 256), 256, 0, s>>>(a, count, lo, hi, bad.get());
+    LAUNCHCHK();
+    uint32_t h = 0;
+    HIPCHK(hipMemcpyAsync(&h, bad.get(), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return h == 0;
+}
+
+}  // namespace sclap

@@ -1,0 +1,939 @@
+// Size-constrained label propagation (SCLaP) kernels for gfx950.
+//
+// Follows Section 3.1 (Label Propagation with Size Constraints) of
+// Meyerhenke, Sanders, Schulz (2014): a visited node moves to the eligible
+// neighbouring label (cluster or block) of strongest connection, eligible
+// meaning the label stays within the bound after the move; during refinement
+// a node of an overloaded block moves to the best eligible block regardless
+// of its own.  The paper's asynchronous visiting is realised as hash-coloured
+// sub-rounds: every node of colour s is evaluated against the state at the
+// start of sub-round s, then each target admits its candidates in
+// (gain desc, node asc) order while it stays within the bound, then the moves
+// are applied.  All arithmetic is integer, so the result does not depend on
+// thread order.
+//
+// Node evaluation is bucketed by degree:
+//   lane   one lane per node, neighbour labels kept in registers (deg <= 16)
+//   wave   one wave64 per node, open-addressing table in LDS (deg <= 256)
+//   block  one 512-thread workgroup per node, 128 KB LDS table (deg <= 8192)
+//   hub    several workgroups per node, open-addressing table in HBM
+// The per-node connection table maps a neighbour label to the summed weight
+// of the edges to it (Section 4.1 uses hashing with linear probing for this).
+#include <climits>
+
+#include "lp.hpp"
+#include "profile.hpp"
+
+namespace sclap {
+
+namespace {
+
+constexpr int kNB = 5;  // buckets: lane4, lane16, wave, block, hub
+constexpr int kLaneSmall = 4;
+constexpr int kLaneMax = 16;
+constexpr int kWaveTable = 512;
+constexpr int kWaveMaxDeg = kWaveTable / 2;
+constexpr int kBlockThreads = 512;
+constexpr int kBlockTable = 16384;
+constexpr int kBlockMaxDeg = kBlockTable / 2;
+constexpr int kHubChunk = 4096;   // adjacency slots per insert workgroup
+constexpr int kHubTChunk = 4096;  // table entries per scan workgroup
+
+struct Counters {
+    uint32_t ncand;
+    uint32_t nslow;
+    int32_t gmin;
+    int32_t gmax;
+    uint32_t bad_color;
+    uint32_t pad[3];
+};
+
+struct EvalArgs {
+    const int64_t* xadj;
+    const int32_t* adj;
+    const int32_t* ew;
+    const int32_t* vw;
+    const int32_t* label;
+    const int32_t* w;
+    int64_t bound;
+    uint64_t tp;  // H(seed, 2, level, phase, round)
+    int32_t refine;
+    const int32_t* nodes;
+    int32_t count;
+    int32_t* cv;  // candidate node
+    int32_t* ct;  // candidate target label
+    int32_t* cg;  // candidate gain
+    int32_t* tsum;  // per-label total weight of candidates targeting it
+    Counters* ctr;
+};
+
+// ------------------------------------------------------- selection helpers
+
+// Best eligible label seen so far under the total order
+// (conn desc, tie(x) asc, x asc); tie(x) = mix(tp ^ x) is computed lazily,
+// only when two labels have equal connection.
+struct Best {
+    int32_t conn;
+    int32_t x;
+    uint64_t tie;
+    bool tv;
+};
+
+__device__ __forceinline__ void best_init(Best& b) {
+    b.conn = -1;
+    b.x = -1;
+    b.tie = 0;
+    b.tv = false;
+}
+
+__device__ __forceinline__ uint64_t tie_of(uint64_t tp, int32_t x) {
+    return mix64(tp ^ static_cast<uint64_t>(static_cast<uint32_t>(x)));
+}
+
+__device__ __forceinline__ void best_consider(Best& b, int32_t x, int32_t conn, uint64_t tp) {
+    if (b.x < 0 || conn > b.conn) {
+        b.conn = conn;
+        b.x = x;
+        b.tv = false;
+        return;
+    }
+    if (conn < b.conn) return;
+    const uint64_t tx = tie_of(tp, x);
+    if (!b.tv) {
+        b.tie = tie_of(tp, b.x);
+        b.tv = true;
+    }
+    if (tx < b.tie || (tx == b.tie && x < b.x)) {
+        b.x = x;
+        b.tie = tx;
+    }
+}
+
+__device__ __forceinline__ uint64_t best_tie(const Best& b, uint64_t tp) { return b.tv ? b.tie : tie_of(tp, b.x); }
+
+// Wave-wide argmax; every lane gets the winning (x, conn) or x = -1.
+__device__ __forceinline__ void wave_argmax(const Best& b, uint64_t tp, int32_t& out_x, int32_t& out_conn) {
+    const int32_t bc = b.x >= 0 ? b.conn : -1;
+    const int32_t maxc = wave_max(bc);
+    if (maxc < 0) {
+        out_x = -1;
+        out_conn = -1;
+        return;
+    }
+    const bool top = b.x >= 0 && bc == maxc;
+    const uint64_t tk = top ? best_tie(b, tp) : ~0ULL;
+    const uint64_t mt = wave_min_u64(tk);
+    const int32_t xx = (top && tk == mt) ? b.x : INT_MAX;
+    out_x = wave_min(xx);
+    out_conn = maxc;
+}
+
+__device__ __forceinline__ bool eligible(const EvalArgs& A, int32_t x, int32_t c) {
+    return static_cast<int64_t>(A.w[x]) + c <= A.bound;
+}
+
+__device__ __forceinline__ void emit_one(const EvalArgs& A, int32_t v, int32_t t, int32_t gain, int32_t c) {
+    const uint32_t idx = atomicAdd(&A.ctr->ncand, 1u);
+    A.cv[idx] = v;
+    A.ct[idx] = t;
+    A.cg[idx] = gain;
+    if (c) atomicAdd(&A.tsum[t], c);
+}
+
+__device__ __forceinline__ uint32_t table_size_for(int32_t d, uint32_t lo, uint32_t hi) {
+    uint32_t t = lo;
+    while (t < 2u * static_cast<uint32_t>(d) && t < hi) t <<= 1;
+    return t;
+}
+
+// Linear-probing insert of (x, wt) into a table of 2^k entries (key -1 = empty).
+__device__ __forceinline__ void table_add(int32_t* keys, int32_t* vals, uint32_t mask, int32_t x, int32_t wt) {
+    uint32_t h = slot_hash(static_cast<uint32_t>(x)) & mask;
+    while (true) {
+        const int32_t prev = atomicCAS(&keys[h], -1, x);
+        if (prev == -1 || prev == x) {
+            atomicAdd(&vals[h], wt);
+            return;
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+// ------------------------------------------------------------ lane bucket
+
+template <int MAXD>
+__global__ void __launch_bounds__(256) eval_lane_kernel(EvalArgs A) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    bool emit = false;
+    int32_t v = 0, t = 0, gain = 0, c = 0;
+    if (i < A.count) {
+        v = A.nodes[i];
+        const int64_t b = A.xadj[v];
+        const int d = static_cast<int>(A.xadj[v + 1] - b);
+        const int32_t a = A.label[v];
+        c = A.vw ? A.vw[v] : 1;
+        int32_t lab[MAXD], wt[MAXD];
+#pragma unroll
+        for (int j = 0; j < MAXD; ++j) {
+            if (j < d) {
+                lab[j] = A.label[A.adj[b + j]];
+                wt[j] = A.ew ? A.ew[b + j] : 1;
+            } else {
+                lab[j] = -1;
+                wt[j] = 0;
+            }
+        }
+        int32_t own = 0;
+#pragma unroll
+        for (int j = 0; j < MAXD; ++j) own += (lab[j] == a) ? wt[j] : 0;
+        const bool over = A.refine && A.w[a] > A.bound;
+        Best best;
+        best_init(best);
+#pragma unroll
+        for (int j = 0; j < MAXD; ++j) {
+            const int32_t x = lab[j];
+            bool skip = (x < 0) || (x == a);
+#pragma unroll
+            for (int j2 = 0; j2 < j; ++j2) skip |= (lab[j2] == x);
+            if (skip) continue;
+            int32_t conn = 0;
+#pragma unroll
+            for (int j2 = j; j2 < MAXD; ++j2) conn += (lab[j2] == x) ? wt[j2] : 0;
+            if (!over && conn <= own) continue;  // cannot give a positive gain
+            if (best.x >= 0 && conn < best.conn) continue;
+            if (!eligible(A, x, c)) continue;
+            best_consider(best, x, conn, A.tp);
+        }
+        if (best.x >= 0) {
+            gain = best.conn - own;
+            emit = over || gain > 0;
+            t = best.x;
+        }
+    }
+    const uint64_t m = __ballot(emit);
+    if (m == 0) return;
+    const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+    uint32_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(&A.ctr->ncand, static_cast<uint32_t>(__popcll(m)));
+    base = __shfl(base, leader, 64);
+    if (emit) {
+        const uint32_t idx = base + static_cast<uint32_t>(__popcll(m & lanemask_lt()));
+        A.cv[idx] = v;
+        A.ct[idx] = t;
+        A.cg[idx] = gain;
+        if (c) atomicAdd(&A.tsum[t], c);
+    }
+}
+
+// ------------------------------------------------------------ wave bucket
+
+__global__ void __launch_bounds__(256) eval_wave_kernel(EvalArgs A) {
+    __shared__ int32_t tkeys[4][kWaveTable];
+    __shared__ int32_t tvals[4][kWaveTable];
+    const int wid = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int node_i = blockIdx.x * 4 + wid;
+    if (node_i >= A.count) return;
+    int32_t* keys = tkeys[wid];
+    int32_t* vals = tvals[wid];
+    const int32_t v = A.nodes[node_i];
+    const int64_t b = A.xadj[v];
+    const int32_t d = static_cast<int32_t>(A.xadj[v + 1] - b);
+    const int32_t a = A.label[v];
+    const int32_t c = A.vw ? A.vw[v] : 1;
+    const uint32_t tsz = table_size_for(d, 64, kWaveTable);
+    const uint32_t mask = tsz - 1;
+    for (uint32_t j = lane; j < tsz; j += 64) {
+        keys[j] = -1;
+        vals[j] = 0;
+    }
+    wave_sync();
+    for (int32_t j = lane; j < d; j += 64) {
+        const int32_t x = A.label[A.adj[b + j]];
+        const int32_t wt = A.ew ? A.ew[b + j] : 1;
+        table_add(keys, vals, mask, x, wt);
+    }
+    wave_sync();
+    int32_t ownp = 0;
+    for (uint32_t j = lane; j < tsz; j += 64)
+        if (keys[j] == a) ownp = vals[j];
+    const int32_t own = wave_max(ownp);
+    const bool over = A.refine && A.w[a] > A.bound;
+    Best best;
+    best_init(best);
+    for (uint32_t j = lane; j < tsz; j += 64) {
+        const int32_t x = keys[j];
+        if (x < 0 || x == a) continue;
+        const int32_t conn = vals[j];
+        if (!over && conn <= own) continue;
+        if (best.x >= 0 && conn < best.conn) continue;
+        if (!eligible(A, x, c)) continue;
+        best_consider(best, x, conn, A.tp);
+    }
+    int32_t bx, bconn;
+    wave_argmax(best, A.tp, bx, bconn);
+    if (bx < 0) return;
+    const int32_t gain = bconn - own;
+    if (lane == 0 && (over || gain > 0)) emit_one(A, v, bx, gain, c);
+}
+
+// ----------------------------------------------------------- block bucket
+
+// Combines one candidate per wave (written to LDS by each wave's lane 0).
+__device__ __forceinline__ void combine_into(int32_t& bc, uint64_t& bt, int32_t& bx, int32_t c2, uint64_t t2,
+                                             int32_t x2) {
+    if (x2 < 0) return;
+    if (bx < 0 || c2 > bc || (c2 == bc && (t2 < bt || (t2 == bt && x2 < bx)))) {
+        bc = c2;
+        bt = t2;
+        bx = x2;
+    }
+}
+
+__global__ void __launch_bounds__(kBlockThreads) eval_block_kernel(EvalArgs A) {
+    __shared__ int32_t keys[kBlockTable];
+    __shared__ int32_t vals[kBlockTable];
+    __shared__ int32_t s_own;
+    __shared__ int32_t s_conn[kBlockThreads / 64];
+    __shared__ int32_t s_x[kBlockThreads / 64];
+    __shared__ uint64_t s_tie[kBlockThreads / 64];
+    const int tid = threadIdx.x;
+    const int wid = tid >> 6;
+    const int lane = lane_id();
+    const int32_t v = A.nodes[blockIdx.x];
+    const int64_t b = A.xadj[v];
+    const int32_t d = static_cast<int32_t>(A.xadj[v + 1] - b);
+    const int32_t a = A.label[v];
+    const int32_t c = A.vw ? A.vw[v] : 1;
+    const uint32_t tsz = table_size_for(d, 512, kBlockTable);
+    const uint32_t mask = tsz - 1;
+    for (uint32_t j = tid; j < tsz; j += kBlockThreads) {
+        keys[j] = -1;
+        vals[j] = 0;
+    }
+    if (tid == 0) s_own = 0;
+    __syncthreads();
+    for (int32_t j = tid; j < d; j += kBlockThreads) {
+        const int32_t x = A.label[A.adj[b + j]];
+        const int32_t wt = A.ew ? A.ew[b + j] : 1;
+        table_add(keys, vals, mask, x, wt);
+    }
+    __syncthreads();
+    for (uint32_t j = tid; j < tsz; j += kBlockThreads)
+        if (keys[j] == a) s_own = vals[j];
+    __syncthreads();
+    const int32_t own = s_own;
+    const bool over = A.refine && A.w[a] > A.bound;
+    Best best;
+    best_init(best);
+    for (uint32_t j = tid; j < tsz; j += kBlockThreads) {
+        const int32_t x = keys[j];
+        if (x < 0 || x == a) continue;
+        const int32_t conn = vals[j];
+        if (!over && conn <= own) continue;
+        if (best.x >= 0 && conn < best.conn) continue;
+        if (!eligible(A, x, c)) continue;
+        best_consider(best, x, conn, A.tp);
+    }
+    int32_t bx, bconn;
+    wave_argmax(best, A.tp, bx, bconn);
+    if (lane == 0) {
+        s_conn[wid] = bconn;
+        s_x[wid] = bx;
+        s_tie[wid] = bx >= 0 ? tie_of(A.tp, bx) : ~0ULL;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int32_t fc = -1, fx = -1;
+        uint64_t ft = ~0ULL;
+        for (int w = 0; w < kBlockThreads / 64; ++w) combine_into(fc, ft, fx, s_conn[w], s_tie[w], s_x[w]);
+        if (fx >= 0) {
+            const int32_t gain = fc - own;
+            if (over || gain > 0) emit_one(A, v, fx, gain, c);
+        }
+    }
+}
+
+// ------------------------------------------------------------- hub bucket
+
+struct HubArgs {
+    const int32_t* hub_nodes;    // [H]
+    const int64_t* hub_toff;     // [H] table offset
+    const uint32_t* hub_tmask;   // [H] table size - 1
+    const int32_t* hub_tfirst;   // [H+1] first scan chunk of each hub
+    const int32_t* chunk_hub;    // [nchunks]
+    const int64_t* chunk_begin;  // [nchunks] first slot
+    const int32_t* tchunk_hub;   // [ntchunks]
+    const int64_t* tchunk_begin; // [ntchunks] first table entry (absolute)
+    int32_t* gkeys;
+    int32_t* gvals;
+    int32_t* hub_own;   // [H]
+    int32_t* p_conn;    // [ntchunks]
+    uint64_t* p_tie;
+    int32_t* p_x;
+};
+
+__global__ void __launch_bounds__(256) hub_insert_kernel(EvalArgs A, HubArgs H) {
+    const int32_t h = H.chunk_hub[blockIdx.x];
+    const int32_t v = H.hub_nodes[h];
+    const int64_t begin = H.chunk_begin[blockIdx.x];
+    const int64_t row_end = A.xadj[v + 1];
+    const int64_t end = begin + kHubChunk < row_end ? begin + kHubChunk : row_end;
+    int32_t* keys = H.gkeys + H.hub_toff[h];
+    int32_t* vals = H.gvals + H.hub_toff[h];
+    const uint32_t mask = H.hub_tmask[h];
+    for (int64_t i = begin + threadIdx.x; i < end; i += 256) {
+        const int32_t x = A.label[A.adj[i]];
+        const int32_t wt = A.ew ? A.ew[i] : 1;
+        table_add(keys, vals, mask, x, wt);
+    }
+}
+
+__global__ void __launch_bounds__(256) hub_scan_kernel(EvalArgs A, HubArgs H) {
+    __shared__ int32_t s_conn[4];
+    __shared__ int32_t s_x[4];
+    __shared__ uint64_t s_tie[4];
+    const int32_t h = H.tchunk_hub[blockIdx.x];
+    const int32_t v = H.hub_nodes[h];
+    const int32_t a = A.label[v];
+    const int32_t c = A.vw ? A.vw[v] : 1;
+    const int64_t begin = H.tchunk_begin[blockIdx.x];
+    const int64_t tend = H.hub_toff[h] + static_cast<int64_t>(H.hub_tmask[h]) + 1;
+    const int64_t end = begin + kHubTChunk < tend ? begin + kHubTChunk : tend;
+    Best best;
+    best_init(best);
+    for (int64_t j = begin + threadIdx.x; j < end; j += 256) {
+        const int32_t x = H.gkeys[j];
+        if (x < 0) continue;
+        const int32_t conn = H.gvals[j];
+        if (x == a) {
+            H.hub_own[h] = conn;  // the own label occupies exactly one entry
+            continue;
+        }
+        if (best.x >= 0 && conn < best.conn) continue;
+        if (!eligible(A, x, c)) continue;
+        best_consider(best, x, conn, A.tp);
+    }
+    int32_t bx, bconn;
+    wave_argmax(best, A.tp, bx, bconn);
+    const int wid = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        s_conn[wid] = bconn;
+        s_x[wid] = bx;
+        s_tie[wid] = bx >= 0 ? tie_of(A.tp, bx) : ~0ULL;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t fc = -1, fx = -1;
+        uint64_t ft = ~0ULL;
+        for (int w = 0; w < 4; ++w) combine_into(fc, ft, fx, s_conn[w], s_tie[w], s_x[w]);
+        H.p_conn[blockIdx.x] = fc;
+        H.p_tie[blockIdx.x] = ft;
+        H.p_x[blockIdx.x] = fx;
+    }
+}
+
+__global__ void __launch_bounds__(64) hub_finish_kernel(EvalArgs A, HubArgs H) {
+    const int32_t h = blockIdx.x;
+    const int32_t v = H.hub_nodes[h];
+    const int32_t a = A.label[v];
+    const int32_t c = A.vw ? A.vw[v] : 1;
+    int32_t fc = -1, fx = -1;
+    uint64_t ft = ~0ULL;
+    for (int32_t j = H.hub_tfirst[h] + lane_id(); j < H.hub_tfirst[h + 1]; j += 64)
+        combine_into(fc, ft, fx, H.p_conn[j], H.p_tie[j], H.p_x[j]);
+    const int32_t maxc = wave_max(fx >= 0 ? fc : -1);
+    if (maxc < 0) return;
+    const bool top = fx >= 0 && fc == maxc;
+    const uint64_t mt = wave_min_u64(top ? ft : ~0ULL);
+    const int32_t bx = wave_min((top && ft == mt) ? fx : INT_MAX);
+    const int32_t own = H.hub_own[h];
+    const bool over = A.refine && A.w[a] > A.bound;
+    const int32_t gain = maxc - own;
+    if (lane_id() == 0 && (over || gain > 0)) emit_one(A, v, bx, gain, c);
+}
+
+// ----------------------------------------------------------- admission
+
+__global__ void __launch_bounds__(256) admit_fast_kernel(const int32_t* __restrict__ ct, const int32_t* __restrict__ cg,
+                                                         const int32_t* __restrict__ w, const int32_t* __restrict__ tsum,
+                                                         int64_t bound, Counters* ctr, uint8_t* __restrict__ ok,
+                                                         uint32_t* __restrict__ slow_idx) {
+    const uint32_t n = ctr->ncand;
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const int32_t t = ct[i];
+        if (static_cast<int64_t>(w[t]) + tsum[t] <= bound) {
+            ok[i] = 1;  // everything aimed at t fits
+        } else {
+            ok[i] = 0;
+            const uint32_t j = atomicAdd(&ctr->nslow, 1u);
+            slow_idx[j] = i;
+            atomicMin(&ctr->gmin, cg[i]);
+            atomicMax(&ctr->gmax, cg[i]);
+        }
+    }
+}
+
+// key = [t][gmax - gain][v] packed into the low bits; value = candidate index.
+__global__ void slow_keys_kernel(const uint32_t* __restrict__ slow_idx, uint32_t m, const int32_t* __restrict__ cv,
+                                 const int32_t* __restrict__ ct, const int32_t* __restrict__ cg, int32_t gmax,
+                                 int bits_v, int shift_t, int with_t, uint64_t* __restrict__ keys,
+                                 uint32_t* __restrict__ vals) {
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= m) return;
+    const uint32_t i = slow_idx[j];
+    uint64_t k = (static_cast<uint64_t>(static_cast<int64_t>(gmax) - cg[i]) << bits_v) |
+                 static_cast<uint64_t>(static_cast<uint32_t>(cv[i]));
+    if (with_t) k |= static_cast<uint64_t>(static_cast<uint32_t>(ct[i])) << shift_t;
+    keys[j] = k;
+    vals[j] = i;
+}
+
+__global__ void slow_keys_t_kernel(const uint32_t* __restrict__ vals, uint32_t m, const int32_t* __restrict__ ct,
+                                   uint64_t* __restrict__ keys) {
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= m) return;
+    keys[j] = static_cast<uint64_t>(static_cast<uint32_t>(ct[vals[j]]));
+}
+
+__global__ void slow_gather_kernel(const uint32_t* __restrict__ vals, uint32_t m, const int32_t* __restrict__ cv,
+                                   const int32_t* __restrict__ ct, const int32_t* __restrict__ vw,
+                                   int64_t* __restrict__ csum, int32_t* __restrict__ head) {
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= m) return;
+    const uint32_t i = vals[j];
+    csum[j] = vw ? vw[cv[i]] : 1;
+    head[j] = (j == 0 || ct[vals[j - 1]] != ct[i]) ? static_cast<int32_t>(j) : 0;
+}
+
+__global__ void slow_admit_kernel(const uint32_t* __restrict__ vals, uint32_t m, const int32_t* __restrict__ ct,
+                                  const int32_t* __restrict__ w, const int64_t* __restrict__ psum,
+                                  const int32_t* __restrict__ segstart, int64_t bound, uint8_t* __restrict__ ok) {
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= m) return;
+    const uint32_t i = vals[j];
+    const int32_t s0 = segstart[j];
+    const int64_t pre = psum[j] - (s0 > 0 ? psum[s0 - 1] : 0);
+    ok[i] = (static_cast<int64_t>(w[ct[i]]) + pre <= bound) ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(256) apply_kernel(const int32_t* __restrict__ cv, const int32_t* __restrict__ ct,
+                                                    const uint8_t* __restrict__ ok, uint32_t ncand,
+                                                    const int32_t* __restrict__ vw, int32_t* __restrict__ label,
+                                                    int32_t* __restrict__ w, int32_t* __restrict__ tsum) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= ncand) return;
+    const int32_t t = ct[i];
+    tsum[t] = 0;
+    if (!ok[i]) return;
+    const int32_t v = cv[i];
+    const int32_t a = label[v];
+    const int32_t c = vw ? vw[v] : 1;
+    label[v] = t;
+    if (c) {
+        atomicAdd(&w[t], c);
+        atomicSub(&w[a], c);
+    }
+}
+
+__global__ void reset_counters_kernel(Counters* ctr) {
+    ctr->ncand = 0;
+    ctr->nslow = 0;
+    ctr->gmin = INT_MAX;
+    ctr->gmax = INT_MIN;
+}
+
+// --------------------------------------------------------------- schedule
+
+// Category of a node: colour * kNB + degree bucket; degree-0 nodes never move
+// and go to the extra category ncat.
+__global__ void __launch_bounds__(256) classify_kernel(int32_t n, const int64_t* __restrict__ xadj,
+                                                       const int32_t* __restrict__ color_override, uint64_t hc,
+                                                       int32_t nsub, int32_t th0, int32_t th1, int32_t th2,
+                                                       int32_t th3, uint64_t* __restrict__ keys,
+                                                       uint32_t* __restrict__ vals, uint32_t* __restrict__ cat_count,
+                                                       unsigned long long* __restrict__ cat_slots, Counters* ctr) {
+    __shared__ uint32_t hist[16 * kNB + 1];
+    __shared__ unsigned long long shist[16 * kNB + 1];
+    const int ncat = nsub * kNB;
+    for (int j = threadIdx.x; j <= ncat; j += 256) {
+        hist[j] = 0;
+        shist[j] = 0;
+    }
+    __syncthreads();
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v < n) {
+        const int64_t d = xadj[v + 1] - xadj[v];
+        int32_t col;
+        if (color_override) {
+            col = color_override[v];
+            if (col < 0 || col >= nsub) {
+                atomicOr(&ctr->bad_color, 1u);
+                col = 0;
+            }
+        } else {
+            col = static_cast<int32_t>(mix64(hc ^ static_cast<uint64_t>(static_cast<uint32_t>(v))) %
+                                       static_cast<uint64_t>(nsub));
+        }
+        int32_t bucket = d <= th0 ? 0 : d <= th1 ? 1 : d <= th2 ? 2 : d <= th3 ? 3 : 4;
+        const int32_t cat = d == 0 ? ncat : col * kNB + bucket;
+        keys[v] = static_cast<uint64_t>(cat);
+        vals[v] = static_cast<uint32_t>(v);
+        atomicAdd(&hist[cat], 1u);
+        if (d) atomicAdd(&shist[cat], static_cast<unsigned long long>(d));
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j <= ncat; j += 256) {
+        if (hist[j]) atomicAdd(&cat_count[j], hist[j]);
+        if (shist[j]) atomicAdd(&cat_slots[j], shist[j]);
+    }
+}
+
+// rows[2i] = first slot of nodes[i], rows[2i+1] = its degree
+__global__ void gather_rows_kernel(const int32_t* __restrict__ nodes, int32_t count, const int64_t* __restrict__ xadj,
+                                   int64_t* __restrict__ rows) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < count) {
+        rows[2 * i] = xadj[nodes[i]];
+        rows[2 * i + 1] = xadj[nodes[i] + 1] - xadj[nodes[i]];
+    }
+}
+
+__global__ void __launch_bounds__(256) label_weights_kernel(int32_t n, const int32_t* __restrict__ label,
+                                                            const int32_t* __restrict__ vw, int32_t* __restrict__ w) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= n) return;
+    const int32_t c = vw ? vw[v] : 1;
+    if (c) atomicAdd(&w[label[v]], c);
+}
+
+// Per-colour hub metadata built on the host after the schedule is known.
+struct HubPlan {
+    int32_t count = 0;
+    int32_t nchunks = 0;
+    int32_t ntchunks = 0;
+    int64_t table_entries = 0;
+    // device arrays (offsets into one buffer)
+    DBuf<int32_t> i32;  // hub_nodes[H] | hub_tfirst[H+1] | chunk_hub[nc] | tchunk_hub[ntc]
+    DBuf<int64_t> i64;  // hub_toff[H] | chunk_begin[nc] | tchunk_begin[ntc]
+    DBuf<uint32_t> u32; // hub_tmask[H]
+};
+
+thread_local Counters* t_host_ctr = nullptr;
+
+Counters* host_counters() {
+    if (!t_host_ctr) HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&t_host_ctr), sizeof(Counters), hipHostMallocDefault));
+    return t_host_ctr;
+}
+
+}  // namespace
+
+void label_weights(const DevGraph& g, const int32_t* label, int32_t* w, int32_t nw, hipStream_t s) {
+    fill_i32(w, 0, nw, s);
+    if (g.n > 0) {
+        label_weights_kernel<<<grid_for(g.n, 256), 256, 0, s>>>(g.n, label, g.vw, w);
+        LAUNCHCHK();
+    }
+}
+
+LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, int32_t nsub, int32_t rounds,
+                int64_t bound, int32_t* label, int32_t* w, int32_t nw, const int32_t* color_override,
+                const LPTuning& tune, hipStream_t s) {
+    LPResult res;
+    const int32_t n = g.n;
+    if (n == 0 || rounds <= 0) return res;
+    if (nsub < 1 || nsub > 16) fail(-1, "subrounds must be in 1..16");
+
+    // --- schedule: nodes grouped by (colour, degree bucket), ascending ids
+    const int32_t ncat = nsub * kNB;
+    const int32_t th1 = std::max(1, std::min(tune.lane_max, kLaneMax));
+    const int32_t th0 = std::min(kLaneSmall, th1);
+    const int32_t th2 = std::max(th1, std::min(tune.wave_max, kWaveMaxDeg));
+    const int32_t th3 = std::max(th2, std::min(tune.block_max, kBlockMaxDeg));
+    DBuf<uint64_t> ckeys(n, s), ckeys_tmp(n, s);
+    DBuf<uint32_t> order(n, s), order_tmp(n, s);
+    DBuf<uint32_t> cat_count(ncat + 1, s);
+    DBuf<unsigned long long> cat_slots(ncat + 1, s);
+    DBuf<Counters> ctr(1, s);
+    fill_u32(cat_count.get(), 0, ncat + 1, s);
+    HIPCHK(hipMemsetAsync(cat_slots.get(), 0, (ncat + 1) * sizeof(unsigned long long), s));
+    HIPCHK(hipMemsetAsync(ctr.get(), 0, sizeof(Counters), s));
+    const uint64_t hc = hash_prefix({seed, 1, static_cast<uint64_t>(static_cast<uint32_t>(level)),
+                                     static_cast<uint64_t>(static_cast<uint32_t>(phase))});
+    {
+        ProfScope ps("lp_schedule", 0, s);
+        classify_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, g.xadj, color_override, hc, nsub, th0, th1, th2, th3,
+                                                         ckeys.get(), order.get(), cat_count.get(), cat_slots.get(),
+                                                         ctr.get());
+        LAUNCHCHK();
+    }
+    RadixScratch rs;
+    radix_sort_pairs(ckeys.get(), order.get(), ckeys_tmp.get(), order_tmp.get(), n, 0, bits_for(ncat), rs, s);
+    ckeys.release();
+    ckeys_tmp.release();
+    order_tmp.release();
+    std::vector<uint32_t> cnt(ncat + 1);
+    std::vector<unsigned long long> cslots(ncat + 1);
+    HIPCHK(hipMemcpyAsync(cnt.data(), cat_count.get(), (ncat + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(cslots.data(), cat_slots.get(), (ncat + 1) * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, s));
+    Counters* hctr = host_counters();
+    HIPCHK(hipMemcpyAsync(hctr, ctr.get(), sizeof(Counters), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hctr->bad_color) fail(-1, "color_override value outside [0, subrounds)");
+    std::vector<int64_t> off(ncat + 2, 0);
+    for (int32_t j = 0; j <= ncat; ++j) off[j + 1] = off[j] + cnt[j];
+    const int32_t* nodes = reinterpret_cast<const int32_t*>(order.get());
+
+    // --- hub plans per colour
+    std::vector<HubPlan> plans(nsub);
+    int64_t max_table = 0;
+    int32_t max_tch = 0, max_hubs = 0;
+    for (int32_t sc = 0; sc < nsub; ++sc) {
+        const int32_t cat = sc * kNB + 4;
+        const int32_t H = static_cast<int32_t>(cnt[cat]);
+        HubPlan& P = plans[sc];
+        P.count = H;
+        if (H == 0) continue;
+        std::vector<int32_t> hn(H);
+        std::vector<int64_t> rows(2 * static_cast<size_t>(H)), hd(H), xs(H);
+        HIPCHK(hipMemcpyAsync(hn.data(), nodes + off[cat], H * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        {
+            DBuf<int64_t> drows(2 * static_cast<size_t>(H), s);
+            gather_rows_kernel<<<grid_for(H, 256), 256, 0, s>>>(nodes + off[cat], H, g.xadj, drows.get());
+            LAUNCHCHK();
+            HIPCHK(hipMemcpyAsync(rows.data(), drows.get(), 2 * H * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        for (int32_t h = 0; h < H; ++h) {
+            xs[h] = rows[2 * h];
+            hd[h] = rows[2 * h + 1];
+        }
+        std::vector<int64_t> toff(H);
+        std::vector<uint32_t> tmask(H);
+        std::vector<int32_t> tfirst(H + 1), chub, thub;
+        std::vector<int64_t> cbeg, tbeg;
+        int64_t tot = 0;
+        int32_t ntc = 0;
+        for (int32_t h = 0; h < H; ++h) {
+            uint64_t tsz = 1;
+            while (tsz < 2 * static_cast<uint64_t>(hd[h])) tsz <<= 1;
+            toff[h] = tot;
+            tmask[h] = static_cast<uint32_t>(tsz - 1);
+            for (int64_t sl = 0; sl < hd[h]; sl += kHubChunk) {
+                chub.push_back(h);
+                cbeg.push_back(xs[h] + sl);
+            }
+            tfirst[h] = ntc;
+            for (int64_t e = 0; e < static_cast<int64_t>(tsz); e += kHubTChunk) {
+                thub.push_back(h);
+                tbeg.push_back(tot + e);
+                ++ntc;
+            }
+            tot += static_cast<int64_t>(tsz);
+        }
+        tfirst[H] = ntc;
+        P.nchunks = static_cast<int32_t>(chub.size());
+        P.ntchunks = ntc;
+        P.table_entries = tot;
+        std::vector<int32_t> i32;
+        i32.insert(i32.end(), hn.begin(), hn.end());
+        i32.insert(i32.end(), tfirst.begin(), tfirst.end());
+        i32.insert(i32.end(), chub.begin(), chub.end());
+        i32.insert(i32.end(), thub.begin(), thub.end());
+        std::vector<int64_t> i64;
+        i64.insert(i64.end(), toff.begin(), toff.end());
+        i64.insert(i64.end(), cbeg.begin(), cbeg.end());
+        i64.insert(i64.end(), tbeg.begin(), tbeg.end());
+        P.i32.alloc(i32.size(), s);
+        P.i64.alloc(i64.size(), s);
+        P.u32.alloc(tmask.size(), s);
+        HIPCHK(hipMemcpyAsync(P.i32.get(), i32.data(), i32.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(P.i64.get(), i64.data(), i64.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(P.u32.get(), tmask.data(), tmask.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));  // host vectors go out of scope
+        max_table = std::max(max_table, tot);
+        max_tch = std::max(max_tch, ntc);
+        max_hubs = std::max(max_hubs, H);
+    }
+    DBuf<int32_t> gkeys, gvals, hub_own, p_conn, p_x;
+    DBuf<uint64_t> p_tie;
+    if (max_table > 0) {
+        gkeys.alloc(max_table, s);
+        gvals.alloc(max_table, s);
+        hub_own.alloc(max_hubs, s);
+        p_conn.alloc(max_tch, s);
+        p_x.alloc(max_tch, s);
+        p_tie.alloc(max_tch, s);
+    }
+
+    // --- candidate buffers: at most the nodes of one colour
+    int64_t max_color = 0;
+    for (int32_t sc = 0; sc < nsub; ++sc) max_color = std::max(max_color, off[(sc + 1) * kNB] - off[sc * kNB]);
+    const int64_t cap = std::max<int64_t>(max_color, 1);
+    DBuf<int32_t> cv(cap, s), ct(cap, s), cg(cap, s), tsum(nw, s);
+    DBuf<uint8_t> ok(cap, s);
+    DBuf<uint32_t> slow_idx(cap, s);
+    fill_i32(tsum.get(), 0, nw, s);
+
+    EvalArgs A;
+    A.xadj = g.xadj;
+    A.adj = g.adj;
+    A.ew = g.ew;
+    A.vw = g.vw;
+    A.label = label;
+    A.w = w;
+    A.bound = bound;
+    A.refine = phase == kRefine ? 1 : 0;
+    A.cv = cv.get();
+    A.ct = ct.get();
+    A.cg = cg.get();
+    A.tsum = tsum.get();
+    A.ctr = ctr.get();
+
+    // Algorithmic bytes of one evaluation launch: per node its list entry,
+    // row offsets, own label and weight (and w(own) when refining); per slot
+    // the neighbour id, edge weight and neighbour label.
+    const double node_bytes = 4.0 + 16.0 + 4.0 + (g.vw ? 4.0 : 0.0) + (phase == kRefine ? 4.0 : 0.0);
+    const double slot_bytes = 8.0 + (g.ew ? 4.0 : 0.0);
+    auto eval_bytes = [&](int64_t nodes_in, unsigned long long slots_in) {
+        return node_bytes * static_cast<double>(nodes_in) + slot_bytes * static_cast<double>(slots_in);
+    };
+    reset_counters_kernel<<<1, 1, 0, s>>>(ctr.get());
+    LAUNCHCHK();
+    DBuf<uint64_t> sk, sk_tmp;
+    DBuf<uint32_t> sv_tmp;
+    DBuf<int64_t> psum;
+    DBuf<int32_t> heads;
+    const int bits_v = bits_for(static_cast<uint64_t>(n - 1));
+    const int bits_t = bits_for(static_cast<uint64_t>(nw > 0 ? nw - 1 : 0));
+
+    for (int32_t r = 0; r < rounds; ++r) {
+        A.tp = hash_prefix({seed, 2, static_cast<uint64_t>(static_cast<uint32_t>(level)),
+                            static_cast<uint64_t>(static_cast<uint32_t>(phase)),
+                            static_cast<uint64_t>(static_cast<uint32_t>(r))});
+        int64_t round_cands = 0;
+        for (int32_t sc = 0; sc < nsub; ++sc) {
+            const int32_t c0 = sc * kNB;
+            // evaluation
+            for (int32_t bk = 0; bk < 4; ++bk) {
+                const int64_t count = off[c0 + bk + 1] - off[c0 + bk];
+                if (count == 0) continue;
+                A.nodes = nodes + off[c0 + bk];
+                A.count = static_cast<int32_t>(count);
+                static const char* const kNames[4] = {"lp_eval_lane4", "lp_eval_lane16", "lp_eval_wave",
+                                                      "lp_eval_block"};
+                ProfScope ps(kNames[bk], eval_bytes(count, cslots[c0 + bk]), s);
+                if (bk == 0) {
+                    eval_lane_kernel<kLaneSmall><<<grid_for(count, 256), 256, 0, s>>>(A);
+                } else if (bk == 1) {
+                    eval_lane_kernel<kLaneMax><<<grid_for(count, 256), 256, 0, s>>>(A);
+                } else if (bk == 2) {
+                    eval_wave_kernel<<<grid_for(count, 4), 256, 0, s>>>(A);
+                } else {
+                    eval_block_kernel<<<static_cast<unsigned>(count), kBlockThreads, 0, s>>>(A);
+                }
+                LAUNCHCHK();
+            }
+            const HubPlan& P = plans[sc];
+            if (P.count > 0) {
+                HubArgs H;
+                H.hub_nodes = P.i32.get();
+                H.hub_tfirst = P.i32.get() + P.count;
+                H.chunk_hub = P.i32.get() + 2 * P.count + 1;
+                H.tchunk_hub = P.i32.get() + 2 * P.count + 1 + P.nchunks;
+                H.hub_toff = P.i64.get();
+                H.chunk_begin = P.i64.get() + P.count;
+                H.tchunk_begin = P.i64.get() + P.count + P.nchunks;
+                H.hub_tmask = P.u32.get();
+                H.gkeys = gkeys.get();
+                H.gvals = gvals.get();
+                H.hub_own = hub_own.get();
+                H.p_conn = p_conn.get();
+                H.p_tie = p_tie.get();
+                H.p_x = p_x.get();
+                fill_i32(gkeys.get(), -1, P.table_entries, s);
+                fill_i32(gvals.get(), 0, P.table_entries, s);
+                fill_i32(hub_own.get(), 0, P.count, s);
+                A.nodes = H.hub_nodes;
+                A.count = P.count;
+                {
+                    ProfScope ps("lp_eval_hub_insert", eval_bytes(P.count, cslots[c0 + 4]), s);
+                    hub_insert_kernel<<<P.nchunks, 256, 0, s>>>(A, H);
+                    LAUNCHCHK();
+                }
+                {
+                    ProfScope ps("lp_eval_hub_scan", 8.0 * static_cast<double>(P.table_entries), s);
+                    hub_scan_kernel<<<P.ntchunks, 256, 0, s>>>(A, H);
+                    LAUNCHCHK();
+                }
+                hub_finish_kernel<<<P.count, 64, 0, s>>>(A, H);
+                LAUNCHCHK();
+            }
+            // admission, fast path: targets whose candidates all fit
+            const int64_t ccount = off[c0 + kNB] - off[c0];
+            {
+                ProfScope ps("lp_admit", 0, s);
+                admit_fast_kernel<<<grid_for(std::max<int64_t>(ccount, 1), 256), 256, 0, s>>>(
+                    ct.get(), cg.get(), w, tsum.get(), bound, ctr.get(), ok.get(), slow_idx.get());
+                LAUNCHCHK();
+            }
+            HIPCHK(hipMemcpyAsync(hctr, ctr.get(), sizeof(Counters), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (profiler().on) profiler().collect();
+            const uint32_t ncand = hctr->ncand;
+            const uint32_t m = hctr->nslow;
+            if (m > 0) {
+                // slow path: sort candidates of overflowing targets by
+                // (target, gain desc, node asc) and admit the prefix that fits
+                const int bits_g = bits_for(static_cast<uint64_t>(static_cast<int64_t>(hctr->gmax) - hctr->gmin));
+                const int low_bits = bits_g + bits_v;
+                const bool single = low_bits + bits_t <= 64;
+                sk.reserve(m, s);
+                sk_tmp.reserve(m, s);
+                sv_tmp.reserve(m, s);
+                psum.reserve(m, s);
+                heads.reserve(m, s);
+                uint32_t* sv = slow_idx.get();  // reused as values (sorted in place)
+                slow_keys_kernel<<<grid_for(m, 256), 256, 0, s>>>(slow_idx.get(), m, cv.get(), ct.get(), cg.get(),
+                                                                  hctr->gmax, bits_v, low_bits, single ? 1 : 0,
+                                                                  sk.get(), sv);
+                LAUNCHCHK();
+                if (single) {
+                    radix_sort_pairs(sk.get(), sv, sk_tmp.get(), sv_tmp.get(), m, 0, low_bits + bits_t, rs, s);
+                } else {
+                    radix_sort_pairs(sk.get(), sv, sk_tmp.get(), sv_tmp.get(), m, 0, low_bits, rs, s);
+                    slow_keys_t_kernel<<<grid_for(m, 256), 256, 0, s>>>(sv, m, ct.get(), sk.get());
+                    LAUNCHCHK();
+                    radix_sort_pairs(sk.get(), sv, sk_tmp.get(), sv_tmp.get(), m, 0, bits_t, rs, s);
+                }
+                slow_gather_kernel<<<grid_for(m, 256), 256, 0, s>>>(sv, m, cv.get(), ct.get(), g.vw, psum.get(),
+                                                                    heads.get());
+                LAUNCHCHK();
+                inclusive_scan_i64(psum.get(), psum.get(), m, s);
+                inclusive_max_i32(heads.get(), heads.get(), m, s);
+                slow_admit_kernel<<<grid_for(m, 256), 256, 0, s>>>(sv, m, ct.get(), w, psum.get(), heads.get(), bound,
+                                                                   ok.get());
+                LAUNCHCHK();
+            }
+            if (ncand > 0) {
+                ProfScope ps("lp_apply", 0, s);
+                apply_kernel<<<grid_for(ncand, 256), 256, 0, s>>>(cv.get(), ct.get(), ok.get(), ncand, g.vw, label, w,
+                                                                  tsum.get());
+                LAUNCHCHK();
+            }
+            reset_counters_kernel<<<1, 1, 0, s>>>(ctr.get());
+            LAUNCHCHK();
+            round_cands += ncand;  // the first candidate of every target is always admitted
+        }
+        res.rounds_run = r + 1;
+        res.moves += round_cands;
+        if (round_cands == 0) break;
+    }
+    res.visits = static_cast<int64_t>(res.rounds_run) * g.S;
+    HIPCHK(hipStreamSynchronize(s));
+    if (profiler().on) profiler().collect();
+    return res;
+}
+
+}  // namespace sclap

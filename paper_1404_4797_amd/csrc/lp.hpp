@@ -1,0 +1,42 @@
+// Size-constrained label propagation (SCLaP) on gfx950: one level, one phase.
+#pragma once
+
+#include "common.hpp"
+#include "primitives.hpp"
+
+namespace sclap {
+
+enum Phase : int32_t { kCluster = 0, kRefine = 1 };
+
+struct DevGraph {
+    int32_t n = 0;
+    int64_t S = 0;
+    const int64_t* xadj = nullptr;
+    const int32_t* adj = nullptr;
+    const int32_t* ew = nullptr;  // null => unit edge weights
+    const int32_t* vw = nullptr;  // null => unit node weights
+};
+
+struct LPTuning {
+    int32_t lane_max = 16;    // <= 16
+    int32_t wave_max = 256;   // <= 256
+    int32_t block_max = 8192; // <= 8192
+};
+
+struct LPResult {
+    int32_t rounds_run = 0;
+    int64_t visits = 0;
+    int64_t moves = 0;
+};
+
+// Runs SCLaP rounds for one (level, phase) in place on `label` (n entries,
+// values in [0, nw)) and `w` (nw entries, w[x] = total node weight of label
+// x).  `color_override` is a device array or null.
+LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, int32_t nsub, int32_t rounds,
+                int64_t bound, int32_t* label, int32_t* w, int32_t nw, const int32_t* color_override,
+                const LPTuning& tune, hipStream_t s);
+
+// w[x] = sum of c(v) over label(v) = x, for x in [0, nw).
+void label_weights(const DevGraph& g, const int32_t* label, int32_t* w, int32_t nw, hipStream_t s);
+
+}  // namespace sclap

@@ -1,0 +1,63 @@
+"""Writes oracle_digests.json: digests of the CPU oracle's multilevel output
+on the seeded benchmark workloads, for GPU parity tests at sizes where the
+oracle takes too long to run inside a test.
+
+Calls only the oracle and the input generators:
+    python tests/golden/make_oracle_digests.py
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+WORKLOADS = {
+    # Barabasi-Albert n=2^14, m=8, unit weights; one level then refine; k=2
+    "ba14_m8_k2_onelevel": dict(gen=("ba", dict(n=1 << 14, m=8, seed=1)), k=2, eps=0.03, seed=1,
+                                opts=dict(max_levels=1)),
+    # R-MAT scale 20, edge factor 16, (0.57, 0.19, 0.19, 0.05); full multilevel; k=16
+    "rmat20_ef16_k16": dict(gen=("rmat", dict(scale=20, edge_factor=16, seed=1)), k=16, eps=0.03, seed=1,
+                            opts=dict()),
+}
+
+
+def make_graph(spec):
+    kind, kw = spec
+    return synth.ba(**kw) if kind == "ba" else synth.rmat(**kw)
+
+
+def digest(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def main():
+    out = {"note": "Digests of the oracle's output; regenerate with this script.", "workloads": {}}
+    for name, w in WORKLOADS.items():
+        g = make_graph(w["gen"])
+        t = time.time()
+        r = oracle.partition(g, w["k"], w["eps"], w["seed"], **w["opts"])
+        print("%s: %.1fs cut=%d levels=%d" % (name, time.time() - t, r["cut"], r["levels"]), flush=True)
+        out["workloads"][name] = {
+            "graph": {"kind": w["gen"][0], **w["gen"][1]}, "k": w["k"], "eps": w["eps"], "seed": w["seed"],
+            "opts": w["opts"], "n": int(g["n"]), "S": int(g["xadj"][-1]),
+            "input_sha256": digest(g["adjncy"]),
+            "part_sha256": digest(r["part"].astype(np.int32)), "cut": r["cut"],
+            "block_weights": r["block_weights"].tolist(), "status": r["status"], "levels": r["levels"],
+            "level_n": r["level_n"], "level_S": [int(x) for x in r["level_S"]], "visits": r["visits"],
+            "cluster_rounds": r["cluster_rounds"], "refine_rounds": r["refine_rounds"],
+        }
+    with open(os.path.join(HERE, "oracle_digests.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

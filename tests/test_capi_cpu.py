@@ -1,0 +1,122 @@
+"""C-ABI checks that need no GPU.
+
+* libsclap.so loads and exports every function include/sclap.h declares;
+* the option defaults, the Lmax helper and the struct layouts match the
+  header;
+* the host-only routines of the library (exact validation, the initial
+  partitioner) agree with the oracle's separately written ones.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    import paper_1404_4797_amd as sc
+    if not os.path.exists(sc.LIB_PATH):
+        from paper_1404_4797_amd import build
+        build.build()
+    return sc, sc.load()
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "sclap.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sclap_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_expected_calls():
+    import paper_1404_4797_amd as sc
+    assert _declared() == sorted(sc.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    sc, L = _lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_default_options():
+    sc, _ = _lib()
+    o = sc.default_options()
+    assert (o.coarsen_rounds, o.refine_rounds, o.subrounds, o.cluster_divisor, o.coarsest_nodes,
+            o.max_levels, o.validate) == (10, 10, 4, 18, 10000, 64, 1)
+    assert o.color_override is None
+
+
+def test_struct_layouts_match_c(tmp_path):
+    # gcc computes every field offset and struct size from the header itself
+    sc, _ = _lib()
+    import subprocess
+    structs = {"sclap_graph": sc.Graph, "sclap_graph_owned": sc.GraphOwned, "sclap_options": sc.Options,
+               "sclap_stats": sc.Stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sclap.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    got = dict((" ".join(l.split()[:2]), int(l.split()[2])) for l in out if l.strip())
+    for cname, py in structs.items():
+        assert got[cname + " size"] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[cname + " " + f] == getattr(py, f).offset, (cname, f)
+
+
+@pytest.mark.parametrize("cV,k,eps", [(16384, 2, 0.03), (1 << 24, 64, 0.03), (4, 2, 0.0), (999983, 5, 0.013)])
+def test_lmax_matches_oracle(cV, k, eps):
+    sc, _ = _lib()
+    assert sc.lmax(cV, k, eps) == oracle.lmax(cV, k, eps)
+
+
+def test_host_validation_matches_oracle():
+    sc, _ = _lib()
+    good = synth.rgg(300, seed=2, weighted=True)
+    assert sc.validate(good) == 0 == oracle.validate(good)
+    bad = dict(good)
+    bad["adjwgt"] = good["adjwgt"].copy()
+    bad["adjwgt"][5] += 1
+    assert sc.validate(bad) == oracle.validate(bad) == -2
+    loop = {"n": 2, "xadj": np.array([0, 1, 2]), "adjncy": np.array([0, 1], dtype=np.int32)}
+    assert sc.validate(loop) == oracle.validate(loop) == -1
+
+
+@pytest.mark.parametrize("make", [
+    lambda: synth.rmat(11, 8, seed=4, weighted=True),
+    lambda: synth.ba(3000, 3, seed=5, weighted=True),
+    lambda: synth.rgg(4000, seed=6, weighted=True),
+])
+@pytest.mark.parametrize("k", [1, 2, 7, 64])
+def test_initial_partition_cross_coded(make, k):
+    sc, _ = _lib()
+    g = make()
+    rng = np.random.default_rng(k)
+    g["vwgt"] = rng.integers(0, 5, size=g["n"]).astype(np.int32)
+    T = -(-int(g["vwgt"].sum()) // k)
+    a = sc.initial_partition(g, k)
+    b = oracle.initial_partition(g, k, T)
+    assert np.array_equal(a, b)
+
+
+def test_initial_partition_unsorted_rows():
+    sc, _ = _lib()
+    g = synth.rmat(10, 8, seed=9)
+    rng = np.random.default_rng(0)
+    for v in range(g["n"]):
+        b, e = int(g["xadj"][v]), int(g["xadj"][v + 1])
+        g["adjncy"][b:e] = g["adjncy"][b:e][rng.permutation(e - b)]
+    T = -(-g["n"] // 4)
+    assert np.array_equal(sc.initial_partition(g, 4), oracle.initial_partition(g, 4, T))

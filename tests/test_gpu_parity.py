@@ -1,0 +1,298 @@
+"""GPU parity: every output of the HIP path, called through the C ABI, equals
+the CPU oracle's bit for bit (all arithmetic is integer).
+
+Covers clustering, refinement, contraction, projection, cut / block weights
+and the full multilevel partition, on seeded graphs that span several tiles
+and every degree bucket (lane, wave, workgroup, hub), plus the degenerate
+cases (empty graph, isolated nodes, k = 1, k > n, zero node weights, eps = 0),
+validation status codes, tuning-knob invariance and run-to-run determinism.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sc():
+    import paper_1404_4797_amd as m
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    m.load()
+    return m
+
+
+def dev(sc, g):
+    return sc.to_device(g, "cuda")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def with_node_weights(g, seed, zero_frac=0.1):
+    rng = np.random.default_rng(seed)
+    w = rng.integers(1, 6, size=g["n"]).astype(np.int32)
+    w[rng.random(g["n"]) < zero_frac] = 0
+    h = dict(g)
+    h["vwgt"] = w
+    return h
+
+
+def star(n_leaves, weights=None):
+    edges = [(0, i) for i in range(1, n_leaves + 1)]
+    return synth.from_edges(n_leaves + 1, edges, weights)
+
+
+GRAPHS = {
+    "ba_4k": lambda: synth.ba(4000, 4, seed=11, weighted=True),
+    "rgg_6k": lambda: synth.rgg(6000, seed=12, weighted=True),
+    "rmat_13": lambda: synth.rmat(13, 16, seed=13, weighted=True),
+    "rmat_12_nodew": lambda: with_node_weights(synth.rmat(12, 8, seed=14, weighted=True), 1),
+    "star_9000": lambda: star(9000),
+}
+
+# small thresholds push rows into the wave, workgroup and hub paths
+KNOBS = [dict(), dict(lane_max_degree=2, wave_max_degree=8, block_max_degree=24),
+         dict(lane_max_degree=16, wave_max_degree=256, block_max_degree=300)]
+
+
+# ------------------------------------------------------------ hand-worked
+
+def test_handworked_on_gpu(sc, golden_dir):
+    with open(os.path.join(golden_dir, "handworked.json")) as f:
+        ex = json.load(f)
+    for name in ("A_admission_by_gain", "B_admission_by_node_id"):
+        e = ex[name]
+        g = synth.from_edges(e["n"], [tuple(x) for x in e["edges"]], e["weights"])
+        col = torch.tensor(e["colors"], dtype=torch.int32, device="cuda")
+        lab, rr = sc.cluster_dev(dev(sc, g), e["U"], rounds=e["rounds"], seed=e["seed"], color_override=col,
+                                 subrounds=e["nsub"])
+        assert lab.cpu().tolist() == e["expected_labels"] and rr == e["expected_rounds_run"], name
+    e = ex["F_longest_prefix"]
+    g = synth.from_edges(e["n"], [tuple(x) for x in e["edges"]], e["weights"], vwgt=e["vwgt"])
+    col = torch.tensor(e["colors"], dtype=torch.int32, device="cuda")
+    lab, rr = sc.cluster_dev(dev(sc, g), e["U"], rounds=1, seed=1, color_override=col, subrounds=2)
+    assert lab.cpu().tolist() == e["expected_labels_after_1_round"]
+    lab, rr = sc.cluster_dev(dev(sc, g), e["U"], rounds=10, seed=1, color_override=col, subrounds=2)
+    assert lab.cpu().tolist() == e["expected_labels"] and rr == e["expected_rounds_run"]
+    e = ex["C_overloaded_rule"]
+    g = synth.from_edges(e["n"], [tuple(x) for x in e["edges"]], e["weights"])
+    part = torch.tensor(e["initial_part"], dtype=torch.int32, device="cuda")
+    col = torch.tensor(e["colors"], dtype=torch.int32, device="cuda")
+    sc.refine_dev(dev(sc, g), e["k"], e["Lmax"], part, rounds=e["rounds"], seed=1, color_override=col, subrounds=1)
+    assert part.cpu().tolist() == e["expected_part"]
+    e = ex["D_contraction_ranks"]
+    g = synth.from_edges(e["n"], [tuple(x) for x in e["edges"]], e["weights"])
+    C, cg = sc.contract_dev(dev(sc, g), torch.tensor(e["labels"], dtype=torch.int32, device="cuda"))
+    assert C.cpu().tolist() == e["expected_C"]
+    for key, val in e["expected_coarse"].items():
+        got = cg[key] if key == "n" else cg[key].cpu().tolist()
+        assert got == val, key
+
+
+# ------------------------------------------------------------- clustering
+
+@pytest.mark.parametrize("gname", list(GRAPHS))
+@pytest.mark.parametrize("knobs", range(len(KNOBS)))
+def test_cluster_parity(sc, gname, knobs):
+    g = GRAPHS[gname]()
+    d = dev(sc, g)
+    cV = int(g["vwgt"].sum()) if g.get("vwgt") is not None else g["n"]
+    for U, seed, nsub in ((max(3, cV // 300), 1, 4), (max(10, cV // 50), 5, 1), (max(2, cV // 2000), 9, 7)):
+        cmax = int(g["vwgt"].max()) if g.get("vwgt") is not None else 1
+        U = max(U, cmax)
+        say("cluster", gname, KNOBS[knobs], "U=%d seed=%d nsub=%d" % (U, seed, nsub))
+        lab, rr = sc.cluster_dev(d, U, rounds=6, seed=seed, level=2, subrounds=nsub, **KNOBS[knobs])
+        ref, rr_ref, _ = oracle.cluster(g, U, rounds=6, seed=seed, level=2, nsub=nsub)
+        assert rr == rr_ref
+        assert np.array_equal(lab.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("gname", list(GRAPHS))
+@pytest.mark.parametrize("k", [2, 5, 64])
+def test_refine_parity(sc, gname, k):
+    g = GRAPHS[gname]()
+    d = dev(sc, g)
+    cV = int(g["vwgt"].sum()) if g.get("vwgt") is not None else g["n"]
+    rng = np.random.default_rng(k)
+    for eps in (0.0, 0.03):
+        Lmax = oracle.lmax(cV, k, eps)
+        p0 = rng.integers(0, k, size=g["n"]).astype(np.int32)
+        if k == 2:
+            p0[: g["n"] * 3 // 4] = 0  # start overloaded
+        say("refine", gname, "k=%d eps=%g" % (k, eps))
+        part = torch.tensor(p0, device="cuda")
+        _, rr = sc.refine_dev(d, k, Lmax, part, rounds=8, seed=3, level=1, block_max_degree=40)
+        ref, rr_ref, _ = oracle.refine(g, k, Lmax, p0, rounds=8, seed=3, level=1)
+        assert rr == rr_ref
+        assert np.array_equal(part.cpu().numpy(), ref)
+
+
+# ------------------------------------------------------------ contraction
+
+@pytest.mark.parametrize("gname", list(GRAPHS))
+def test_contract_project_cut_parity(sc, gname):
+    g = GRAPHS[gname]()
+    d = dev(sc, g)
+    n = g["n"]
+    rng = np.random.default_rng(5)
+    lab_lp, _, _ = oracle.cluster(g, max(4, n // 100), rounds=4, seed=2)
+    for labels in (lab_lp, rng.integers(0, max(1, n // 7), size=n).astype(np.int32), np.arange(n, dtype=np.int32)):
+        say("contract", gname, "labels used=%d" % len(np.unique(labels)))
+        C, cg = sc.contract_dev(d, torch.tensor(labels, device="cuda"))
+        C_ref, cg_ref = oracle.contract(g, labels)
+        assert np.array_equal(C.cpu().numpy(), C_ref)
+        assert cg["n"] == cg_ref["n"]
+        for key in ("xadj", "adjncy", "adjwgt", "vwgt"):
+            assert np.array_equal(cg[key].cpu().numpy(), cg_ref[key]), key
+        for k in (2, 9):
+            cp = rng.integers(0, k, size=cg_ref["n"]).astype(np.int32)
+            fp = sc.project_dev(C, torch.tensor(cp, device="cuda"))
+            assert np.array_equal(fp.cpu().numpy(), oracle.project(C_ref, cp))
+            cut, bw = sc.cut_dev(d, fp, k)
+            cut_ref, bw_ref = oracle.cut(g, oracle.project(C_ref, cp), k)
+            assert cut == cut_ref and np.array_equal(bw, bw_ref)
+
+
+# ------------------------------------------------------------- multilevel
+
+@pytest.mark.parametrize("gname", list(GRAPHS))
+@pytest.mark.parametrize("k", [2, 16])
+def test_partition_parity(sc, gname, k):
+    g = GRAPHS[gname]()
+    say("partition", gname, "k=%d" % k)
+    r = sc.partition_dev(dev(sc, g), k, 0.03, 4, coarsest_nodes=300)
+    ref = oracle.partition(g, k, 0.03, 4, coarsest_nodes=300)
+    assert r["stats"]["level_n"] == ref["level_n"]
+    assert r["stats"]["cluster_rounds"] == ref["cluster_rounds"]
+    assert r["stats"]["refine_rounds"] == ref["refine_rounds"]
+    assert r["stats"]["visits"] == ref["visits"]
+    assert np.array_equal(r["part"].cpu().numpy(), ref["part"])
+    assert r["cut"] == ref["cut"] and np.array_equal(r["block_weights"], ref["block_weights"])
+    assert r["status"] == ref["status"]
+
+
+def test_partition_host_entry_point(sc):
+    g = synth.rmat(12, 16, seed=21, weighted=True)
+    r = sc.partition(g, 8, 0.05, 2, coarsest_nodes=500)
+    ref = oracle.partition(g, 8, 0.05, 2, coarsest_nodes=500)
+    assert np.array_equal(r["part"], ref["part"]) and r["cut"] == ref["cut"]
+    C, cg = sc.contract(g, ref["part"])
+    C_ref, cg_ref = oracle.contract(g, ref["part"])
+    assert np.array_equal(C, C_ref) and np.array_equal(cg["adjwgt"], cg_ref["adjwgt"])
+    lab, rr = sc.cluster(g, 40, rounds=5, seed=3)
+    lab_ref, rr_ref, _ = oracle.cluster(g, 40, rounds=5, seed=3)
+    assert np.array_equal(lab, lab_ref) and rr == rr_ref
+
+
+def test_config1_ba_one_level(sc):
+    # Barabasi-Albert n = 2^14, m = 8, unit weights, k = 2, eps = 0.03, one
+    # level then refinement, 10 rounds each, 4 sub-rounds, seed 1.
+    g = synth.ba(1 << 14, 8, seed=1)
+    r = sc.partition_dev(dev(sc, g), 2, 0.03, 1, max_levels=1)
+    ref = oracle.partition(g, 2, 0.03, 1, max_levels=1)
+    assert np.array_equal(r["part"].cpu().numpy(), ref["part"])
+    assert r["cut"] == ref["cut"] and np.array_equal(r["block_weights"], ref["block_weights"])
+    assert r["stats"]["level_n"] == ref["level_n"]
+
+
+def test_config2_rmat20_digest(sc, golden_dir):
+    # R-MAT scale 20, full multilevel, k = 16: compared with the stored digest
+    # of the oracle's output (tests/golden/make_oracle_digests.py).
+    import hashlib
+    with open(os.path.join(golden_dir, "oracle_digests.json")) as f:
+        w = json.load(f)["workloads"]["rmat20_ef16_k16"]
+    g = synth.rmat(20, 16, seed=1)
+    assert hashlib.sha256(g["adjncy"].tobytes()).hexdigest() == w["input_sha256"]
+    r = sc.partition_dev(dev(sc, g), w["k"], w["eps"], w["seed"])
+    part = r["part"].cpu().numpy().astype(np.int32)
+    assert r["stats"]["level_n"] == w["level_n"]
+    assert r["cut"] == w["cut"] and r["block_weights"].tolist() == w["block_weights"]
+    assert hashlib.sha256(part.tobytes()).hexdigest() == w["part_sha256"]
+    assert r["stats"]["visits"] == w["visits"]
+
+
+# ---------------------------------------------------------- degenerate cases
+
+def test_degenerate_cases(sc):
+    # empty graph
+    e = {"n": 0, "xadj": np.zeros(1, dtype=np.int64), "adjncy": np.zeros(0, dtype=np.int32)}
+    r = sc.partition(e, 3, 0.03, 1)
+    assert r["cut"] == 0 and r["block_weights"].tolist() == [0, 0, 0]
+    # edgeless graph, more blocks than nodes, k = 1, single node
+    for n, k in ((37, 4), (5, 9), (50, 1), (1, 2)):
+        g = {"n": n, "xadj": np.zeros(n + 1, dtype=np.int64), "adjncy": np.zeros(0, dtype=np.int32)}
+        r = sc.partition_dev(dev(sc, g), k, 0.0, 1, coarsest_nodes=3)
+        ref = oracle.partition(g, k, 0.0, 1, coarsest_nodes=3)
+        assert np.array_equal(r["part"].cpu().numpy(), ref["part"]) and r["status"] == ref["status"]
+    # zero node weights everywhere
+    g = synth.rgg(500, seed=3)
+    g["vwgt"] = np.zeros(500, dtype=np.int32)
+    r = sc.partition_dev(dev(sc, g), 4, 0.03, 1, coarsest_nodes=20)
+    ref = oracle.partition(g, 4, 0.03, 1, coarsest_nodes=20)
+    assert np.array_equal(r["part"].cpu().numpy(), ref["part"]) and r["cut"] == ref["cut"]
+    # k > n on a connected graph
+    g = synth.ba(30, 2, seed=1)
+    r = sc.partition_dev(dev(sc, g), 64, 0.03, 1)
+    ref = oracle.partition(g, 64, 0.03, 1)
+    assert np.array_equal(r["part"].cpu().numpy(), ref["part"])
+
+
+def test_validation_codes_on_device(sc):
+    good = synth.rgg(400, seed=2, weighted=True)
+    assert sc.validate_dev(dev(sc, good)) == 0
+    asym = dict(good)
+    asym["adjwgt"] = good["adjwgt"].copy()
+    asym["adjwgt"][3] += 1
+    assert sc.validate_dev(dev(sc, asym)) == -2
+    loop = synth.from_edges(3, [(0, 1), (1, 2)])
+    loop["adjncy"] = loop["adjncy"].copy()
+    loop["adjncy"][0] = 0  # self-loop at node 0
+    assert sc.validate_dev(dev(sc, loop)) == -1
+    oob = synth.from_edges(3, [(0, 1), (1, 2)])
+    oob["adjncy"] = oob["adjncy"].copy()
+    oob["adjncy"][1] = 3  # id out of range
+    assert sc.validate_dev(dev(sc, oob)) == -1
+    big = dict(good)
+    big["vwgt"] = np.full(400, 2**24, dtype=np.int32)
+    assert sc.validate_dev(dev(sc, big)) == -3
+    with pytest.raises(sc.SclapError) as ei:
+        sc.partition_dev(dev(sc, asym), 2)
+    assert ei.value.status == -2
+    # out-of-range partition / labels are rejected before any kernel reads them
+    d = dev(sc, good)
+    with pytest.raises(sc.SclapError):
+        sc.refine_dev(d, 2, 300, torch.full((400,), 2, dtype=torch.int32, device="cuda"))
+    with pytest.raises(sc.SclapError):
+        sc.contract_dev(d, torch.full((400,), 400, dtype=torch.int32, device="cuda"))
+
+
+# ------------------------------------------------------------ metamorphic
+
+def test_repeat_runs_identical_and_row_order_free(sc):
+    g = synth.rmat(14, 16, seed=31, weighted=True)
+    d = dev(sc, g)
+    a = sc.partition_dev(d, 16, 0.03, 3, coarsest_nodes=400)
+    b = sc.partition_dev(d, 16, 0.03, 3, coarsest_nodes=400, lane_max_degree=4, wave_max_degree=32,
+                         block_max_degree=64)
+    assert torch.equal(a["part"], b["part"]) and a["cut"] == b["cut"]
+    h = dict(g)
+    rng = np.random.default_rng(1)
+    h["adjncy"] = g["adjncy"].copy()
+    h["adjwgt"] = g["adjwgt"].copy()
+    for v in range(g["n"]):
+        lo, hi = int(g["xadj"][v]), int(g["xadj"][v + 1])
+        p = rng.permutation(hi - lo) + lo
+        h["adjncy"][lo:hi] = g["adjncy"][p]
+        h["adjwgt"][lo:hi] = g["adjwgt"][p]
+    c = sc.partition_dev(dev(sc, h), 16, 0.03, 3, coarsest_nodes=400)
+    assert torch.equal(a["part"], c["part"])
