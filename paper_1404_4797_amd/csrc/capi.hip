@@ -189,56 +189,147 @@ struct MinTree {
     }
 };
 
+// Binary min-heap of packed (weight << 32 | block) keys: the lightest block,
+// lowest id on ties, is at the root.
+struct BlockHeap {
+    std::vector<uint64_t> h;
+    static uint64_t key(int64_t w, int32_t b) { return (static_cast<uint64_t>(w) << 32) | static_cast<uint32_t>(b); }
+    explicit BlockHeap(const std::vector<int64_t>& wb) {
+        for (size_t b = 0; b < wb.size(); ++b) h.push_back(key(wb[b], static_cast<int32_t>(b)));
+        std::make_heap(h.begin(), h.end(), std::greater<uint64_t>());
+    }
+    int32_t top() const { return static_cast<int32_t>(h[0] & 0xFFFFFFFFu); }
+    // adds c to the root's weight and restores the heap order
+    void add_to_top(int64_t c) {
+        if (c == 0) return;
+        const uint64_t x = h[0] + (static_cast<uint64_t>(c) << 32);
+        size_t i = 0;
+        const size_t n = h.size();
+        while (true) {
+            size_t l = 2 * i + 1;
+            if (l >= n) break;
+            if (l + 1 < n && h[l + 1] < h[l]) ++l;
+            if (h[l] >= x) break;
+            h[i] = h[l];
+            i = l;
+        }
+        h[i] = x;
+    }
+};
+
 // Grows blocks 0..k-2 by breadth-first search up to T each (seeds: smallest
 // unassigned node of positive degree that fits; neighbours in ascending id
 // order), then deals every remaining node, in id order, to the currently
-// lightest block (lowest id on ties).
+// lightest block (lowest id on ties).  Weights fit 31 bits (c(V) <= 2^31-1).
 void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, const int32_t* vw, int32_t k,
                             int64_t T, int32_t* part) {
     std::fill(part, part + n, -1);
     std::vector<int64_t> wb(static_cast<size_t>(k), 0);
-    std::vector<int64_t> seedw(static_cast<size_t>(n));
-    for (int32_t v = 0; v < n; ++v) seedw[v] = (xadj[v + 1] > xadj[v]) ? (vw ? vw[v] : 1) : INT64_MAX;
-    MinTree seeds(seedw);
+    // seed candidates: nodes of positive degree, in id order
+    std::vector<int32_t> seed_node;
+    std::vector<int64_t> seed_w;
+    std::vector<int32_t> seed_pos(static_cast<size_t>(n), -1);
+    for (int32_t v = 0; v < n; ++v)
+        if (xadj[v + 1] > xadj[v]) {
+            seed_pos[v] = static_cast<int32_t>(seed_node.size());
+            seed_node.push_back(v);
+            seed_w.push_back(vw ? vw[v] : 1);
+        }
+    MinTree seeds(seed_w);
     std::vector<int32_t> nb;
     std::deque<int32_t> q;
     auto take = [&](int32_t v, int32_t b) {
         part[v] = b;
         wb[b] += vw ? vw[v] : 1;
-        if (seedw[v] != INT64_MAX) seeds.erase(v);
+        if (seed_pos[v] >= 0) seeds.erase(seed_pos[v]);
     };
     for (int32_t b = 0; b + 1 < k; ++b) {
         int32_t from = 0;
         while (true) {
-            const int32_t sd = seeds.first_le(from, T - wb[b]);
-            if (sd < 0) break;
+            const int32_t si = seeds.first_le(from, T - wb[b]);
+            if (si < 0) break;
+            const int32_t sd = seed_node[si];
             take(sd, b);
             q.push_back(sd);
             while (!q.empty()) {
                 const int32_t u = q.front();
                 q.pop_front();
-                nb.assign(adj + xadj[u], adj + xadj[u + 1]);
-                if (!std::is_sorted(nb.begin(), nb.end())) std::sort(nb.begin(), nb.end());
-                for (int32_t x : nb) {
+                const int32_t* row = adj + xadj[u];
+                const int32_t* row_end = adj + xadj[u + 1];
+                if (!std::is_sorted(row, row_end)) {
+                    nb.assign(row, row_end);
+                    std::sort(nb.begin(), nb.end());
+                    row = nb.data();
+                    row_end = nb.data() + nb.size();
+                }
+                for (const int32_t* it = row; it != row_end; ++it) {
+                    const int32_t x = *it;
                     if (part[x] >= 0) continue;
                     if (wb[b] + (vw ? vw[x] : 1) > T) continue;
                     take(x, b);
                     q.push_back(x);
                 }
             }
-            from = sd + 1;
+            from = si + 1;
         }
     }
-    using Item = std::pair<int64_t, int32_t>;  // (weight, block): lightest, then lowest id
-    std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
-    for (int32_t b = 0; b < k; ++b) heap.push({wb[b], b});
-    for (int32_t v = 0; v < n; ++v) {
-        if (part[v] >= 0) continue;
-        Item it = heap.top();
-        heap.pop();
-        part[v] = it.second;
-        it.first += vw ? vw[v] : 1;
-        heap.push(it);
+    // Step 2: every remaining node, in id order, to the lightest block.
+    // Within a run of nodes of equal weight c > 0, the blocks whose weight
+    // lies within c of the lightest form a group that receives nodes
+    // cyclically in (weight, id) order, one per block per pass, until the next
+    // heavier block X is due; the number of nodes before that is the count of
+    // group values (w_g + j c, g) below (w_X, X).  X then joins and the group
+    // is recomputed.  The result equals dealing node by node.
+    std::vector<int32_t> rest;
+    rest.reserve(static_cast<size_t>(n));
+    for (int32_t v = 0; v < n; ++v)
+        if (part[v] < 0) rest.push_back(v);
+    auto cw = [&](int32_t v) -> int64_t { return vw ? vw[v] : 1; };
+    std::vector<int32_t> ord(static_cast<size_t>(k));
+    size_t i = 0;
+    while (i < rest.size()) {
+        const int64_t c = cw(rest[i]);
+        size_t j = i;
+        while (j < rest.size() && cw(rest[j]) == c) ++j;
+        if (c == 0 || k > 4096) {  // node by node
+            BlockHeap heap(wb);
+            for (; i < j; ++i) {
+                const int32_t b = heap.top();
+                part[rest[i]] = b;
+                wb[b] += c;
+                heap.add_to_top(c);
+            }
+            continue;
+        }
+        while (i < j) {
+            for (int32_t b = 0; b < k; ++b) ord[b] = b;
+            std::sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+                return wb[x] != wb[y] ? wb[x] < wb[y] : x < y;
+            });
+            const int64_t m0 = wb[ord[0]];
+            int32_t gsz = 1;
+            while (gsz < k && wb[ord[gsz]] < m0 + c) ++gsz;
+            size_t take = j - i;
+            if (gsz < k) {
+                const int32_t X = ord[gsz];
+                const int64_t wx = wb[X];
+                uint64_t before = 0;
+                for (int32_t t = 0; t < gsz; ++t) {
+                    const int32_t g = ord[t];
+                    const int64_t d = wx - wb[g];
+                    before += static_cast<uint64_t>((d + c - 1) / c + ((d % c == 0 && g < X) ? 1 : 0));
+                }
+                take = std::min<size_t>(take, static_cast<size_t>(before));
+            }
+            int32_t pos = 0;
+            for (size_t t = 0; t < take; ++t) {
+                const int32_t b = ord[pos];
+                part[rest[i + t]] = b;
+                wb[b] += c;
+                if (++pos == gsz) pos = 0;
+            }
+            i += take;
+        }
     }
 }
 

@@ -7,6 +7,7 @@
 #include <climits>
 
 #include "graph_ops.hpp"
+#include "profile.hpp"
 
 namespace sclap {
 
@@ -87,16 +88,45 @@ __global__ void map_kernel(int32_t n, const int32_t* __restrict__ labels, const 
     if (c) atomicAdd(&cvw[cv], c);
 }
 
-// Emits (C(u) << bn | C(v), w) for every slot u->v between different clusters.
-__global__ void __launch_bounds__(kTileThreads) emit_kernel(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj,
-                                                            const int32_t* __restrict__ ew, int32_t n, int64_t S,
-                                                            const int32_t* __restrict__ C, int bn,
-                                                            uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                            unsigned long long* __restrict__ count) {
+// Number of slots u->v with C(u) != C(v) in each tile.
+__global__ void __launch_bounds__(kTileThreads) count_cross_kernel(const int64_t* __restrict__ xadj,
+                                                                   const int32_t* __restrict__ adj, int32_t n,
+                                                                   int64_t S, const int32_t* __restrict__ C,
+                                                                   int32_t* __restrict__ tile_cnt) {
     __shared__ int32_t owner[kTile];
+    __shared__ int32_t s_sum[kTileThreads / kWave];
     const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kTile;
     const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
     tile_owners(xadj, n, i0, i1, owner);
+    int32_t cnt = 0;
+    for (int r = 0; r < kTilePer; ++r) {
+        const int64_t i = i0 + r * kTileThreads + threadIdx.x;
+        if (i < i1 && C[owner[i - i0]] != C[adj[i]]) ++cnt;
+    }
+    cnt = wave_sum(cnt);
+    if (lane_id() == 0) s_sum[threadIdx.x / kWave] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int w = 0; w < kTileThreads / kWave; ++w) t += s_sum[w];
+        tile_cnt[blockIdx.x] = t;
+    }
+}
+
+// Writes (C(u) << bn | C(v), w) for every slot u->v between different
+// clusters, in slot order, starting at the tile's scanned offset.
+__global__ void __launch_bounds__(kTileThreads) emit_kernel(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj,
+                                                            const int32_t* __restrict__ ew, int32_t n, int64_t S,
+                                                            const int32_t* __restrict__ C, int bn,
+                                                            const int64_t* __restrict__ tile_off,
+                                                            uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    __shared__ int32_t owner[kTile];
+    __shared__ int32_t s_cnt[kTileThreads / kWave];
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kTile;
+    const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
+    tile_owners(xadj, n, i0, i1, owner);
+    int64_t base = tile_off[blockIdx.x];
+    const int wid = threadIdx.x / kWave;
     for (int r = 0; r < kTilePer; ++r) {
         const int64_t i = i0 + r * kTileThreads + threadIdx.x;
         bool e = false;
@@ -112,42 +142,67 @@ __global__ void __launch_bounds__(kTileThreads) emit_kernel(const int64_t* __res
             }
         }
         const uint64_t m = __ballot(e);
-        if (m == 0) continue;
-        const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
-        unsigned long long base = 0;
-        if (lane_id() == leader) base = atomicAdd(count, static_cast<unsigned long long>(__popcll(m)));
-        base = __shfl(base, leader, 64);
+        if (lane_id() == 0) s_cnt[wid] = static_cast<int32_t>(__popcll(m));
+        __syncthreads();
+        int64_t pre = base;
+        int64_t tot = 0;
+        for (int w = 0; w < kTileThreads / kWave; ++w) {
+            if (w < wid) pre += s_cnt[w];
+            tot += s_cnt[w];
+        }
         if (e) {
-            const unsigned long long idx = base + static_cast<unsigned long long>(__popcll(m & lanemask_lt()));
+            const int64_t idx = pre + static_cast<int64_t>(__popcll(m & lanemask_lt()));
             keys[idx] = key;
             vals[idx] = val;
         }
+        base += tot;
+        __syncthreads();
     }
 }
 
-__global__ void heads_kernel(const uint64_t* __restrict__ keys, int64_t m, int32_t* __restrict__ head) {
+__global__ void heads_kernel(const uint64_t* __restrict__ keys, int64_t m, int32_t* __restrict__ head,
+                             int64_t* __restrict__ wsum, const uint32_t* __restrict__ vals) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (i < m) head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+    if (i < m) {
+        head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+        wsum[i] = vals[i];
+    }
 }
 
-__global__ void reduce_write_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t m,
-                                    const int32_t* __restrict__ head, const int64_t* __restrict__ pos, int bn,
-                                    int32_t* __restrict__ cadj, int32_t* __restrict__ cadjw,
-                                    int32_t* __restrict__ rowcnt) {
+// Heads of equal-key runs write the coarse neighbour and remember where the
+// run starts; heads that open a new coarse row also set the row offsets of
+// every coarse node from the previous row's source up to this one.
+__global__ void run_heads_kernel(const uint64_t* __restrict__ keys, int64_t m, const int32_t* __restrict__ head,
+                                 const int64_t* __restrict__ pos, int bn, int32_t nc, int64_t Sc,
+                                 int32_t* __restrict__ cadj, int64_t* __restrict__ run_start,
+                                 int64_t* __restrict__ cxadj) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
     if (i >= m) return;
-    const int64_t p = pos[i] + head[i] - 1;  // index of this key's coarse slot
     const uint64_t k = keys[i];
+    const int64_t src = static_cast<int64_t>(k >> bn);
     if (head[i]) {
-        cadj[p] = static_cast<int32_t>(k & ((1ULL << bn) - 1));
-        atomicAdd(&rowcnt[k >> bn], 1);
+        const int64_t j = pos[i];
+        cadj[j] = static_cast<int32_t>(k & ((1ULL << bn) - 1));
+        run_start[j] = i;
+        const int64_t prev = i == 0 ? -1 : static_cast<int64_t>(keys[i - 1] >> bn);
+        for (int64_t c = prev + 1; c <= src; ++c) cxadj[c] = j;
     }
-    atomicAdd(&cadjw[p], static_cast<int32_t>(vals[i]));
+    if (i == m - 1)
+        for (int64_t c = src + 1; c <= nc; ++c) cxadj[c] = Sc;
 }
 
-__global__ void set_last_kernel(int64_t* __restrict__ xadj, int32_t n, const int64_t* __restrict__ total) {
-    xadj[n] = *total;
+// Tails of runs: coarse edge weight = sum of the run (from the inclusive scan).
+__global__ void run_tails_kernel(const uint64_t* __restrict__ keys, int64_t m, const int32_t* __restrict__ head,
+                                 const int64_t* __restrict__ pos, const int64_t* __restrict__ psum,
+                                 const int64_t* __restrict__ run_start, int32_t* __restrict__ cadjw) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= m) return;
+    if (i + 1 < m && keys[i + 1] == keys[i]) return;
+    const int64_t j = pos[i] + head[i] - 1;
+    const int64_t st = run_start[j];
+    cadjw[j] = static_cast<int32_t>(psum[i] - (st > 0 ? psum[st - 1] : 0));
 }
+
 
 __global__ void project_kernel(int32_t n, const int32_t* __restrict__ C, const int32_t* __restrict__ cp,
                                int32_t* __restrict__ part) {
@@ -157,28 +212,36 @@ __global__ void project_kernel(int32_t n, const int32_t* __restrict__ C, const i
 
 // ---------------------------------------------------------- cut and weights
 
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v) {
+    __shared__ unsigned long long s[kTileThreads / kWave];
+    v = wave_sum(v);
+    if (lane_id() == 0) s[threadIdx.x / kWave] = v;
+    __syncthreads();
+    unsigned long long t = 0;
+    for (int w = 0; w < kTileThreads / kWave; ++w) t += s[w];
+    __syncthreads();
+    return t;
+}
+
+// Grid-stride over tiles; one atomic per workgroup.
 __global__ void __launch_bounds__(kTileThreads) cut_kernel(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj,
                                                            const int32_t* __restrict__ ew, int32_t n, int64_t S,
                                                            const int32_t* __restrict__ part,
                                                            unsigned long long* __restrict__ cut) {
     __shared__ int32_t owner[kTile];
-    __shared__ unsigned long long s_sum[kTileThreads / kWave];
-    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kTile;
-    const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
-    tile_owners(xadj, n, i0, i1, owner);
     unsigned long long acc = 0;
-    for (int r = 0; r < kTilePer; ++r) {
-        const int64_t i = i0 + r * kTileThreads + threadIdx.x;
-        if (i < i1 && part[owner[i - i0]] != part[adj[i]]) acc += ew ? static_cast<unsigned long long>(ew[i]) : 1ULL;
+    for (int64_t tile = blockIdx.x; tile * kTile < S; tile += gridDim.x) {
+        const int64_t i0 = tile * kTile;
+        const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
+        tile_owners(xadj, n, i0, i1, owner);
+        for (int r = 0; r < kTilePer; ++r) {
+            const int64_t i = i0 + r * kTileThreads + threadIdx.x;
+            if (i < i1 && part[owner[i - i0]] != part[adj[i]]) acc += ew ? static_cast<unsigned long long>(ew[i]) : 1ULL;
+        }
+        __syncthreads();
     }
-    acc = wave_sum(acc);
-    if (lane_id() == 0) s_sum[threadIdx.x / kWave] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int w = 0; w < kTileThreads / kWave; ++w) t += s_sum[w];
-        if (t) atomicAdd(cut, t);
-    }
+    acc = block_sum_u64(acc);
+    if (threadIdx.x == 0 && acc) atomicAdd(cut, acc);
 }
 
 __global__ void __launch_bounds__(256) block_weight_kernel(int32_t n, const int32_t* __restrict__ part,
@@ -189,8 +252,7 @@ __global__ void __launch_bounds__(256) block_weight_kernel(int32_t n, const int3
     if (use_lds)
         for (int j = threadIdx.x; j < k; j += 256) loc[j] = 0;
     __syncthreads();
-    const int32_t v = blockIdx.x * 256 + threadIdx.x;
-    if (v < n) {
+    for (int32_t v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) {
         const unsigned long long c = vw ? static_cast<unsigned long long>(vw[v]) : 1ULL;
         if (c) {
             if (use_lds) atomicAdd(&loc[part[v]], c);
@@ -219,25 +281,28 @@ __device__ __forceinline__ unsigned long long edge_hash(uint32_t u, uint32_t v, 
     return mix64(mix64((static_cast<uint64_t>(u) << 32) | v) ^ w);
 }
 
-__global__ void validate_nodes_kernel(int32_t n, const int64_t* __restrict__ xadj, const int32_t* __restrict__ vw,
-                                      VStats* st) {
-    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+__global__ void __launch_bounds__(kTileThreads) validate_nodes_kernel(int32_t n, const int64_t* __restrict__ xadj,
+                                                                      const int32_t* __restrict__ vw, VStats* st) {
+    __shared__ int32_t s_max[kTileThreads / kWave];
     unsigned long long c = 0;
     int32_t cm = 0;
     uint32_t bad = 0;
-    if (v < n) {
+    for (int32_t v = blockIdx.x * kTileThreads + threadIdx.x; v < n; v += gridDim.x * kTileThreads) {
         if (xadj[v + 1] < xadj[v]) bad |= 1u;
         const int32_t cv = vw ? vw[v] : 1;
         if (cv < 0) {
             bad |= 2u;
         } else {
-            c = static_cast<unsigned long long>(cv);
-            cm = cv;
+            c += static_cast<unsigned long long>(cv);
+            cm = cv > cm ? cv : cm;
         }
     }
-    c = wave_sum(c);
+    c = block_sum_u64(c);
     cm = wave_max(cm);
-    if (lane_id() == 0) {
+    if (lane_id() == 0) s_max[threadIdx.x / kWave] = cm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < kTileThreads / kWave; ++w) cm = s_max[w] > cm ? s_max[w] : cm;
         if (c) atomicAdd(&st->cV, c);
         atomicMax(&st->cmax, cm);
     }
@@ -249,27 +314,30 @@ __global__ void __launch_bounds__(kTileThreads) validate_slots_kernel(const int6
                                                                       const int32_t* __restrict__ ew, int32_t n,
                                                                       int64_t S, VStats* st) {
     __shared__ int32_t owner[kTile];
-    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kTile;
-    const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
-    tile_owners(xadj, n, i0, i1, owner);
     unsigned long long ws = 0, hf = 0, hb = 0;
     uint32_t bad = 0;
-    for (int r = 0; r < kTilePer; ++r) {
-        const int64_t i = i0 + r * kTileThreads + threadIdx.x;
-        if (i >= i1) continue;
-        const int32_t u = owner[i - i0];
-        const int32_t x = adj[i];
-        const int32_t w = ew ? ew[i] : 1;
-        if (x < 0 || x >= n || x == u) bad |= 1u;
-        if (w < 1) bad |= 4u;
-        ws += static_cast<unsigned long long>(w > 0 ? w : 0);
-        hf += edge_hash(static_cast<uint32_t>(u), static_cast<uint32_t>(x), static_cast<uint32_t>(w));
-        hb += edge_hash(static_cast<uint32_t>(x), static_cast<uint32_t>(u), static_cast<uint32_t>(w));
+    for (int64_t tile = blockIdx.x; tile * kTile < S; tile += gridDim.x) {
+        const int64_t i0 = tile * kTile;
+        const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
+        tile_owners(xadj, n, i0, i1, owner);
+        for (int r = 0; r < kTilePer; ++r) {
+            const int64_t i = i0 + r * kTileThreads + threadIdx.x;
+            if (i >= i1) continue;
+            const int32_t u = owner[i - i0];
+            const int32_t x = adj[i];
+            const int32_t w = ew ? ew[i] : 1;
+            if (x < 0 || x >= n || x == u) bad |= 1u;
+            if (w < 1) bad |= 4u;
+            ws += static_cast<unsigned long long>(w > 0 ? w : 0);
+            hf += edge_hash(static_cast<uint32_t>(u), static_cast<uint32_t>(x), static_cast<uint32_t>(w));
+            hb += edge_hash(static_cast<uint32_t>(x), static_cast<uint32_t>(u), static_cast<uint32_t>(w));
+        }
+        __syncthreads();
     }
-    ws = wave_sum(ws);
-    hf = wave_sum(hf);
-    hb = wave_sum(hb);
-    if (lane_id() == 0) {
+    ws = block_sum_u64(ws);
+    hf = block_sum_u64(hf);
+    hb = block_sum_u64(hb);
+    if (threadIdx.x == 0) {
         if (ws) atomicAdd(&st->wsum, ws);
         atomicAdd(&st->hfwd, hf);
         atomicAdd(&st->hbwd, hb);
@@ -281,6 +349,16 @@ __global__ void range_kernel(const int32_t* __restrict__ a, int64_t count, int32
                              uint32_t* __restrict__ bad) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
     if (i < count && (a[i] < lo || a[i] >= hi)) atomicOr(bad, 1u);
+}
+
+unsigned capped_tiles(int64_t S) {
+    const int64_t t = (S + kTile - 1) / kTile;
+    return static_cast<unsigned>(t < 1 ? 1 : (t > 2048 ? 2048 : t));
+}
+
+unsigned capped_nodes(int64_t n) {
+    const int64_t t = (n + kTileThreads - 1) / kTileThreads;
+    return static_cast<unsigned>(t < 1 ? 1 : (t > 2048 ? 2048 : t));
 }
 
 }  // namespace
@@ -312,52 +390,64 @@ void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGrap
 
     // inter-cluster slots, sorted by (C(u), C(v)), equal keys summed
     const int bn = std::max(1, bits_for(static_cast<uint64_t>(nc - 1)));
-    DBuf<uint64_t> keys(std::max<int64_t>(g.S, 1), s);
-    DBuf<uint32_t> vals(std::max<int64_t>(g.S, 1), s);
-    DBuf<unsigned long long> cnt(1, s);
-    HIPCHK(hipMemsetAsync(cnt.get(), 0, sizeof(unsigned long long), s));
-    if (g.S > 0) {
-        emit_kernel<<<grid_for(g.S, kTile), kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, n, g.S, C, bn, keys.get(),
-                                                                  vals.get(), cnt.get());
-        LAUNCHCHK();
-    }
-    unsigned long long m64 = 0;
-    HIPCHK(hipMemcpyAsync(&m64, cnt.get(), sizeof(m64), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    const int64_t m = static_cast<int64_t>(m64);
     coarse.xadj.alloc(static_cast<size_t>(nc) + 1, s);
-    DBuf<int32_t> rowcnt(std::max(nc, 1), s);
-    fill_i32(rowcnt.get(), 0, nc, s);
+    const int64_t ntiles = (g.S + kTile - 1) / kTile;
+    int64_t m = 0;
+    DBuf<int64_t> tile_off(std::max<int64_t>(ntiles, 1), s), mtot(1, s);
+    if (g.S > 0) {
+        ProfScope ps("contract_count", (8.0 + 4.0) * static_cast<double>(g.S) + 8.0 * n, s);
+        DBuf<int32_t> tile_cnt(ntiles, s);
+        count_cross_kernel<<<static_cast<unsigned>(ntiles), kTileThreads, 0, s>>>(g.xadj, g.adj, n, g.S, C,
+                                                                                  tile_cnt.get());
+        LAUNCHCHK();
+        exclusive_scan_i32_to_i64(tile_cnt.get(), tile_off.get(), ntiles, mtot.get(), s);
+        HIPCHK(hipMemcpyAsync(&m, mtot.get(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
     if (m == 0) {
         coarse.S = 0;
         coarse.adj.alloc(1, s);
         coarse.ew.alloc(1, s);
         fill_i64(coarse.xadj.get(), 0, static_cast<int64_t>(nc) + 1, s);
+        HIPCHK(hipStreamSynchronize(s));
         return;
     }
+    DBuf<uint64_t> keys(m, s);
+    DBuf<uint32_t> vals(m, s);
     {
+        ProfScope ps("contract_emit", (8.0 + (g.ew ? 4.0 : 0.0)) * static_cast<double>(g.S) + 8.0 * n + 12.0 * m, s);
+        emit_kernel<<<static_cast<unsigned>(ntiles), kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, n, g.S, C, bn,
+                                                                            tile_off.get(), keys.get(), vals.get());
+        LAUNCHCHK();
+    }
+    tile_off.release();
+    {
+        ProfScope ps("contract_sort", 0, s);
         DBuf<uint64_t> ktmp(m, s);
         DBuf<uint32_t> vtmp(m, s);
         RadixScratch rs;
         radix_sort_pairs(keys.get(), vals.get(), ktmp.get(), vtmp.get(), m, 0, 2 * bn, rs, s);
     }
+    ProfScope ps_runs("contract_runs", 0, s);
     DBuf<int32_t> head(m, s);
-    DBuf<int64_t> pos(m, s), stot(1, s);
-    heads_kernel<<<grid_for(m, 256), 256, 0, s>>>(keys.get(), m, head.get());
+    DBuf<int64_t> pos(m, s), psum(m, s), stot(1, s);
+    heads_kernel<<<grid_for(m, 256), 256, 0, s>>>(keys.get(), m, head.get(), psum.get(), vals.get());
     LAUNCHCHK();
+    vals.release();
     exclusive_scan_i32_to_i64(head.get(), pos.get(), m, stot.get(), s);
+    inclusive_scan_i64(psum.get(), psum.get(), m, s);
     int64_t Sc = 0;
     HIPCHK(hipMemcpyAsync(&Sc, stot.get(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     coarse.S = Sc;
     coarse.adj.alloc(Sc, s);
     coarse.ew.alloc(Sc, s);
-    fill_i32(coarse.ew.get(), 0, Sc, s);
-    reduce_write_kernel<<<grid_for(m, 256), 256, 0, s>>>(keys.get(), vals.get(), m, head.get(), pos.get(), bn,
-                                                         coarse.adj.get(), coarse.ew.get(), rowcnt.get());
+    DBuf<int64_t> run_start(Sc, s);
+    run_heads_kernel<<<grid_for(m, 256), 256, 0, s>>>(keys.get(), m, head.get(), pos.get(), bn, nc, Sc,
+                                                      coarse.adj.get(), run_start.get(), coarse.xadj.get());
     LAUNCHCHK();
-    exclusive_scan_i32_to_i64(rowcnt.get(), coarse.xadj.get(), nc, stot.get(), s);
-    set_last_kernel<<<1, 1, 0, s>>>(coarse.xadj.get(), nc, stot.get());
+    run_tails_kernel<<<grid_for(m, 256), 256, 0, s>>>(keys.get(), m, head.get(), pos.get(), psum.get(),
+                                                      run_start.get(), coarse.ew.get());
     LAUNCHCHK();
     HIPCHK(hipStreamSynchronize(s));
 }
@@ -372,11 +462,11 @@ void cut_and_weights(const DevGraph& g, const int32_t* part, int32_t k, int64_t*
     DBuf<unsigned long long> acc(1 + static_cast<size_t>(k), s);
     HIPCHK(hipMemsetAsync(acc.get(), 0, (1 + static_cast<size_t>(k)) * sizeof(unsigned long long), s));
     if (g.S > 0) {
-        cut_kernel<<<grid_for(g.S, kTile), kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, g.n, g.S, part, acc.get());
+        cut_kernel<<<capped_tiles(g.S), kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, g.n, g.S, part, acc.get());
         LAUNCHCHK();
     }
     if (g.n > 0) {
-        block_weight_kernel<<<grid_for(g.n, 256), 256, 0, s>>>(g.n, part, g.vw, k, acc.get() + 1);
+        block_weight_kernel<<<capped_nodes(g.n), 256, 0, s>>>(g.n, part, g.vw, k, acc.get() + 1);
         LAUNCHCHK();
     }
     std::vector<unsigned long long> h(1 + static_cast<size_t>(k));
@@ -403,14 +493,14 @@ int validate_graph(const DevGraph& g, int64_t* cV, int64_t* cmax, hipStream_t s)
     if (g.S > 0 && !g.adj) return -1;
     DBuf<VStats> st(1, s);
     HIPCHK(hipMemsetAsync(st.get(), 0, sizeof(VStats), s));
-    validate_nodes_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, g.xadj, g.vw, st.get());
+    validate_nodes_kernel<<<capped_nodes(n), kTileThreads, 0, s>>>(n, g.xadj, g.vw, st.get());
     LAUNCHCHK();
     VStats h;
     HIPCHK(hipMemcpyAsync(&h, st.get(), sizeof(VStats), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (h.bad) return -1;  // offsets not monotone or negative node weight
     if (g.S > 0) {
-        validate_slots_kernel<<<grid_for(g.S, kTile), kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, n, g.S, st.get());
+        validate_slots_kernel<<<capped_tiles(g.S), kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, n, g.S, st.get());
         LAUNCHCHK();
         HIPCHK(hipMemcpyAsync(&h, st.get(), sizeof(VStats), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -431,7 +521,7 @@ void node_weight_stats(const DevGraph& g, int64_t* cV, int64_t* cmax, hipStream_
     }
     DBuf<VStats> st(1, s);
     HIPCHK(hipMemsetAsync(st.get(), 0, sizeof(VStats), s));
-    validate_nodes_kernel<<<grid_for(g.n, 256), 256, 0, s>>>(g.n, g.xadj, g.vw, st.get());
+    validate_nodes_kernel<<<capped_nodes(g.n), kTileThreads, 0, s>>>(g.n, g.xadj, g.vw, st.get());
     LAUNCHCHK();
     VStats h;
     HIPCHK(hipMemcpyAsync(&h, st.get(), sizeof(VStats), hipMemcpyDeviceToHost, s));

@@ -15,10 +15,17 @@
 // Node evaluation is bucketed by degree:
 //   lane   one lane per node, neighbour labels kept in registers (deg <= 16)
 //   wave   one wave64 per node, open-addressing table in LDS (deg <= 256)
-//   block  one 512-thread workgroup per node, 128 KB LDS table (deg <= 8192)
-//   hub    several workgroups per node, open-addressing table in HBM
+//   block  one workgroup per node with an LDS table of 16, 64 or 128 KB
+//          (deg <= 1024, 4096, 8192)
+//   hub    the row is cut into 8192-slot chunks; each workgroup sums its
+//          chunk in an LDS table, then merges the distinct labels into an
+//          open-addressing table in HBM that a second pass scans
 // The per-node connection table maps a neighbour label to the summed weight
 // of the edges to it (Section 4.1 uses hashing with linear probing for this).
+//
+// Evaluation writes each node's result at the node's position in the
+// sub-round's schedule, so no counter is shared.  Per-label sums use
+// LDS-private histograms when the label space is small (refinement: k blocks).
 #include <climits>
 
 #include "lp.hpp"
@@ -28,7 +35,8 @@ namespace sclap {
 
 namespace {
 
-constexpr int kNB = 5;  // buckets: lane4, lane16, wave, block, hub
+constexpr int kNB = 7;  // buckets: lane4, lane16, wave, block (3 table sizes), hub
+constexpr int kHubBucket = kNB - 1;
 constexpr int kLaneSmall = 4;
 constexpr int kLaneMax = 16;
 constexpr int kWaveTable = 512;
@@ -36,8 +44,12 @@ constexpr int kWaveMaxDeg = kWaveTable / 2;
 constexpr int kBlockThreads = 512;
 constexpr int kBlockTable = 16384;
 constexpr int kBlockMaxDeg = kBlockTable / 2;
-constexpr int kHubChunk = 4096;   // adjacency slots per insert workgroup
-constexpr int kHubTChunk = 4096;  // table entries per scan workgroup
+constexpr int kBlock1Max = 1024;  // 256 threads, 16 KB table
+constexpr int kBlock2Max = 4096;  // 512 threads, 64 KB table
+constexpr int kHubChunk = kBlockMaxDeg;  // slots per hub workgroup (table load <= 1/2)
+constexpr int kHubTChunk = 4096;         // HBM table entries per scan workgroup
+constexpr int kSmallLabels = 4096;       // LDS-private histograms up to this many labels
+constexpr int kMaxBlocks = 1024;         // grid cap of the grid-stride candidate kernels
 
 struct Counters {
     uint32_t ncand;
@@ -58,13 +70,10 @@ struct EvalArgs {
     int64_t bound;
     uint64_t tp;  // H(seed, 2, level, phase, round)
     int32_t refine;
-    const int32_t* nodes;
+    const int32_t* nodes;  // schedule entries of this launch
     int32_t count;
-    int32_t* cv;  // candidate node
-    int32_t* ct;  // candidate target label
-    int32_t* cg;  // candidate gain
-    int32_t* tsum;  // per-label total weight of candidates targeting it
-    Counters* ctr;
+    int32_t* ct;  // per entry: target label or -1
+    int32_t* cg;  // per entry: gain
 };
 
 // ------------------------------------------------------- selection helpers
@@ -128,16 +137,33 @@ __device__ __forceinline__ void wave_argmax(const Best& b, uint64_t tp, int32_t&
     out_conn = maxc;
 }
 
+// Combines one candidate per wave (written to LDS by each wave's lane 0).
+__device__ __forceinline__ void combine_into(int32_t& bc, uint64_t& bt, int32_t& bx, int32_t c2, uint64_t t2,
+                                             int32_t x2) {
+    if (x2 < 0) return;
+    if (bx < 0 || c2 > bc || (c2 == bc && (t2 < bt || (t2 == bt && x2 < bx)))) {
+        bc = c2;
+        bt = t2;
+        bx = x2;
+    }
+}
+
 __device__ __forceinline__ bool eligible(const EvalArgs& A, int32_t x, int32_t c) {
     return static_cast<int64_t>(A.w[x]) + c <= A.bound;
 }
 
-__device__ __forceinline__ void emit_one(const EvalArgs& A, int32_t v, int32_t t, int32_t gain, int32_t c) {
-    const uint32_t idx = atomicAdd(&A.ctr->ncand, 1u);
-    A.cv[idx] = v;
-    A.ct[idx] = t;
-    A.cg[idx] = gain;
-    if (c) atomicAdd(&A.tsum[t], c);
+// Decision for a node given its best eligible label (x, conn) and the
+// connection to its own label: a move needs a positive gain, or an overloaded
+// own block during refinement.
+__device__ __forceinline__ void store_result(const EvalArgs& A, int32_t i, int32_t x, int32_t conn, int32_t own,
+                                             bool over) {
+    int32_t t = -1, gain = 0;
+    if (x >= 0) {
+        gain = conn - own;
+        if (over || gain > 0) t = x;
+    }
+    A.ct[i] = t;
+    A.cg[i] = gain;
 }
 
 __device__ __forceinline__ uint32_t table_size_for(int32_t d, uint32_t lo, uint32_t hi) {
@@ -146,7 +172,8 @@ __device__ __forceinline__ uint32_t table_size_for(int32_t d, uint32_t lo, uint3
     return t;
 }
 
-// Linear-probing insert of (x, wt) into a table of 2^k entries (key -1 = empty).
+// Linear-probing insert of (x, wt) into a table of 2^k entries (key -1 =
+// empty), in LDS or HBM.  The table always has a free entry for a new key.
 __device__ __forceinline__ void table_add(int32_t* keys, int32_t* vals, uint32_t mask, int32_t x, int32_t wt) {
     uint32_t h = slot_hash(static_cast<uint32_t>(x)) & mask;
     while (true) {
@@ -159,70 +186,74 @@ __device__ __forceinline__ void table_add(int32_t* keys, int32_t* vals, uint32_t
     }
 }
 
+// Adds the slots [b, b+d) of a row to a table; each thread keeps U gathers
+// in flight before inserting.
+template <int NT, int U>
+__device__ __forceinline__ void insert_slots(const EvalArgs& A, int64_t b, int32_t d, int32_t* keys, int32_t* vals,
+                                             uint32_t mask, int tid) {
+    for (int32_t j0 = tid; j0 < d; j0 += NT * U) {
+        int32_t x[U], wt[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t j = j0 + u * NT;
+            x[u] = j < d ? A.adj[b + j] : 0;
+            wt[u] = j < d ? (A.ew ? A.ew[b + j] : 1) : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t j = j0 + u * NT;
+            x[u] = j < d ? A.label[x[u]] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (x[u] >= 0) table_add(keys, vals, mask, x[u], wt[u]);
+    }
+}
+
 // ------------------------------------------------------------ lane bucket
 
 template <int MAXD>
 __global__ void __launch_bounds__(256) eval_lane_kernel(EvalArgs A) {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    bool emit = false;
-    int32_t v = 0, t = 0, gain = 0, c = 0;
-    if (i < A.count) {
-        v = A.nodes[i];
-        const int64_t b = A.xadj[v];
-        const int d = static_cast<int>(A.xadj[v + 1] - b);
-        const int32_t a = A.label[v];
-        c = A.vw ? A.vw[v] : 1;
-        int32_t lab[MAXD], wt[MAXD];
+    if (i >= A.count) return;
+    const int32_t v = A.nodes[i];
+    const int64_t b = A.xadj[v];
+    const int d = static_cast<int>(A.xadj[v + 1] - b);
+    const int32_t a = A.label[v];
+    const int32_t c = A.vw ? A.vw[v] : 1;
+    int32_t lab[MAXD], wt[MAXD];
 #pragma unroll
-        for (int j = 0; j < MAXD; ++j) {
-            if (j < d) {
-                lab[j] = A.label[A.adj[b + j]];
-                wt[j] = A.ew ? A.ew[b + j] : 1;
-            } else {
-                lab[j] = -1;
-                wt[j] = 0;
-            }
-        }
-        int32_t own = 0;
-#pragma unroll
-        for (int j = 0; j < MAXD; ++j) own += (lab[j] == a) ? wt[j] : 0;
-        const bool over = A.refine && A.w[a] > A.bound;
-        Best best;
-        best_init(best);
-#pragma unroll
-        for (int j = 0; j < MAXD; ++j) {
-            const int32_t x = lab[j];
-            bool skip = (x < 0) || (x == a);
-#pragma unroll
-            for (int j2 = 0; j2 < j; ++j2) skip |= (lab[j2] == x);
-            if (skip) continue;
-            int32_t conn = 0;
-#pragma unroll
-            for (int j2 = j; j2 < MAXD; ++j2) conn += (lab[j2] == x) ? wt[j2] : 0;
-            if (!over && conn <= own) continue;  // cannot give a positive gain
-            if (best.x >= 0 && conn < best.conn) continue;
-            if (!eligible(A, x, c)) continue;
-            best_consider(best, x, conn, A.tp);
-        }
-        if (best.x >= 0) {
-            gain = best.conn - own;
-            emit = over || gain > 0;
-            t = best.x;
+    for (int j = 0; j < MAXD; ++j) {
+        if (j < d) {
+            lab[j] = A.label[A.adj[b + j]];
+            wt[j] = A.ew ? A.ew[b + j] : 1;
+        } else {
+            lab[j] = -1;
+            wt[j] = 0;
         }
     }
-    const uint64_t m = __ballot(emit);
-    if (m == 0) return;
-    const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
-    uint32_t base = 0;
-    if (lane_id() == leader) base = atomicAdd(&A.ctr->ncand, static_cast<uint32_t>(__popcll(m)));
-    base = __shfl(base, leader, 64);
-    if (emit) {
-        const uint32_t idx = base + static_cast<uint32_t>(__popcll(m & lanemask_lt()));
-        A.cv[idx] = v;
-        A.ct[idx] = t;
-        A.cg[idx] = gain;
-        if (c) atomicAdd(&A.tsum[t], c);
+    int32_t own = 0;
+#pragma unroll
+    for (int j = 0; j < MAXD; ++j) own += (lab[j] == a) ? wt[j] : 0;
+    const bool over = A.refine && A.w[a] > A.bound;
+    Best best;
+    best_init(best);
+#pragma unroll
+    for (int j = 0; j < MAXD; ++j) {
+        const int32_t x = lab[j];
+        bool skip = (x < 0) || (x == a);
+#pragma unroll
+        for (int j2 = 0; j2 < j; ++j2) skip |= (lab[j2] == x);
+        if (skip) continue;
+        int32_t conn = 0;
+#pragma unroll
+        for (int j2 = j; j2 < MAXD; ++j2) conn += (lab[j2] == x) ? wt[j2] : 0;
+        if (!over && conn <= own) continue;  // cannot give a positive gain
+        if (best.x >= 0 && conn < best.conn) continue;
+        if (!eligible(A, x, c)) continue;
+        best_consider(best, x, conn, A.tp);
     }
+    store_result(A, i, best.x, best.conn, own, over);
 }
 
 // ------------------------------------------------------------ wave bucket
@@ -248,11 +279,7 @@ __global__ void __launch_bounds__(256) eval_wave_kernel(EvalArgs A) {
         vals[j] = 0;
     }
     wave_sync();
-    for (int32_t j = lane; j < d; j += 64) {
-        const int32_t x = A.label[A.adj[b + j]];
-        const int32_t wt = A.ew ? A.ew[b + j] : 1;
-        table_add(keys, vals, mask, x, wt);
-    }
+    insert_slots<64, 4>(A, b, d, keys, vals, mask, lane);
     wave_sync();
     int32_t ownp = 0;
     for (uint32_t j = lane; j < tsz; j += 64)
@@ -272,31 +299,19 @@ __global__ void __launch_bounds__(256) eval_wave_kernel(EvalArgs A) {
     }
     int32_t bx, bconn;
     wave_argmax(best, A.tp, bx, bconn);
-    if (bx < 0) return;
-    const int32_t gain = bconn - own;
-    if (lane == 0 && (over || gain > 0)) emit_one(A, v, bx, gain, c);
+    if (lane == 0) store_result(A, node_i, bx, bconn, own, over);
 }
 
 // ----------------------------------------------------------- block bucket
 
-// Combines one candidate per wave (written to LDS by each wave's lane 0).
-__device__ __forceinline__ void combine_into(int32_t& bc, uint64_t& bt, int32_t& bx, int32_t c2, uint64_t t2,
-                                             int32_t x2) {
-    if (x2 < 0) return;
-    if (bx < 0 || c2 > bc || (c2 == bc && (t2 < bt || (t2 == bt && x2 < bx)))) {
-        bc = c2;
-        bt = t2;
-        bx = x2;
-    }
-}
-
-__global__ void __launch_bounds__(kBlockThreads) eval_block_kernel(EvalArgs A) {
-    __shared__ int32_t keys[kBlockTable];
-    __shared__ int32_t vals[kBlockTable];
+template <int NT, int TABLE>
+__global__ void __launch_bounds__(NT) eval_block_kernel(EvalArgs A) {
+    __shared__ int32_t keys[TABLE];
+    __shared__ int32_t vals[TABLE];
     __shared__ int32_t s_own;
-    __shared__ int32_t s_conn[kBlockThreads / 64];
-    __shared__ int32_t s_x[kBlockThreads / 64];
-    __shared__ uint64_t s_tie[kBlockThreads / 64];
+    __shared__ int32_t s_conn[NT / 64];
+    __shared__ int32_t s_x[NT / 64];
+    __shared__ uint64_t s_tie[NT / 64];
     const int tid = threadIdx.x;
     const int wid = tid >> 6;
     const int lane = lane_id();
@@ -305,28 +320,24 @@ __global__ void __launch_bounds__(kBlockThreads) eval_block_kernel(EvalArgs A) {
     const int32_t d = static_cast<int32_t>(A.xadj[v + 1] - b);
     const int32_t a = A.label[v];
     const int32_t c = A.vw ? A.vw[v] : 1;
-    const uint32_t tsz = table_size_for(d, 512, kBlockTable);
+    const uint32_t tsz = table_size_for(d, 512, TABLE);
     const uint32_t mask = tsz - 1;
-    for (uint32_t j = tid; j < tsz; j += kBlockThreads) {
+    for (uint32_t j = tid; j < tsz; j += NT) {
         keys[j] = -1;
         vals[j] = 0;
     }
     if (tid == 0) s_own = 0;
     __syncthreads();
-    for (int32_t j = tid; j < d; j += kBlockThreads) {
-        const int32_t x = A.label[A.adj[b + j]];
-        const int32_t wt = A.ew ? A.ew[b + j] : 1;
-        table_add(keys, vals, mask, x, wt);
-    }
+    insert_slots<NT, 4>(A, b, d, keys, vals, mask, tid);
     __syncthreads();
-    for (uint32_t j = tid; j < tsz; j += kBlockThreads)
+    for (uint32_t j = tid; j < tsz; j += NT)
         if (keys[j] == a) s_own = vals[j];
     __syncthreads();
     const int32_t own = s_own;
     const bool over = A.refine && A.w[a] > A.bound;
     Best best;
     best_init(best);
-    for (uint32_t j = tid; j < tsz; j += kBlockThreads) {
+    for (uint32_t j = tid; j < tsz; j += NT) {
         const int32_t x = keys[j];
         if (x < 0 || x == a) continue;
         const int32_t conn = vals[j];
@@ -346,11 +357,8 @@ __global__ void __launch_bounds__(kBlockThreads) eval_block_kernel(EvalArgs A) {
     if (tid == 0) {
         int32_t fc = -1, fx = -1;
         uint64_t ft = ~0ULL;
-        for (int w = 0; w < kBlockThreads / 64; ++w) combine_into(fc, ft, fx, s_conn[w], s_tie[w], s_x[w]);
-        if (fx >= 0) {
-            const int32_t gain = fc - own;
-            if (over || gain > 0) emit_one(A, v, fx, gain, c);
-        }
+        for (int w = 0; w < NT / 64; ++w) combine_into(fc, ft, fx, s_conn[w], s_tie[w], s_x[w]);
+        store_result(A, blockIdx.x, fx, fc, own, over);
     }
 }
 
@@ -373,19 +381,32 @@ struct HubArgs {
     int32_t* p_x;
 };
 
-__global__ void __launch_bounds__(256) hub_insert_kernel(EvalArgs A, HubArgs H) {
+// Sums one chunk of a hub row in LDS, then adds its distinct labels to the
+// hub's table in HBM (one HBM update per distinct label per chunk).
+__global__ void __launch_bounds__(kBlockThreads) hub_insert_kernel(EvalArgs A, HubArgs H) {
+    __shared__ int32_t keys[kBlockTable];
+    __shared__ int32_t vals[kBlockTable];
+    const int tid = threadIdx.x;
     const int32_t h = H.chunk_hub[blockIdx.x];
     const int32_t v = H.hub_nodes[h];
     const int64_t begin = H.chunk_begin[blockIdx.x];
     const int64_t row_end = A.xadj[v + 1];
     const int64_t end = begin + kHubChunk < row_end ? begin + kHubChunk : row_end;
-    int32_t* keys = H.gkeys + H.hub_toff[h];
-    int32_t* vals = H.gvals + H.hub_toff[h];
-    const uint32_t mask = H.hub_tmask[h];
-    for (int64_t i = begin + threadIdx.x; i < end; i += 256) {
-        const int32_t x = A.label[A.adj[i]];
-        const int32_t wt = A.ew ? A.ew[i] : 1;
-        table_add(keys, vals, mask, x, wt);
+    const uint32_t tsz = table_size_for(static_cast<int32_t>(end - begin), 512, kBlockTable);
+    const uint32_t mask = tsz - 1;
+    for (uint32_t j = tid; j < tsz; j += kBlockThreads) {
+        keys[j] = -1;
+        vals[j] = 0;
+    }
+    __syncthreads();
+    insert_slots<kBlockThreads, 4>(A, begin, static_cast<int32_t>(end - begin), keys, vals, mask, tid);
+    __syncthreads();
+    int32_t* gk = H.gkeys + H.hub_toff[h];
+    int32_t* gv = H.gvals + H.hub_toff[h];
+    const uint32_t gmask = H.hub_tmask[h];
+    for (uint32_t j = tid; j < tsz; j += kBlockThreads) {
+        const int32_t x = keys[j];
+        if (x >= 0) table_add(gk, gv, gmask, x, vals[j]);
     }
 }
 
@@ -437,56 +458,153 @@ __global__ void __launch_bounds__(64) hub_finish_kernel(EvalArgs A, HubArgs H) {
     const int32_t h = blockIdx.x;
     const int32_t v = H.hub_nodes[h];
     const int32_t a = A.label[v];
-    const int32_t c = A.vw ? A.vw[v] : 1;
     int32_t fc = -1, fx = -1;
     uint64_t ft = ~0ULL;
     for (int32_t j = H.hub_tfirst[h] + lane_id(); j < H.hub_tfirst[h + 1]; j += 64)
         combine_into(fc, ft, fx, H.p_conn[j], H.p_tie[j], H.p_x[j]);
     const int32_t maxc = wave_max(fx >= 0 ? fc : -1);
-    if (maxc < 0) return;
-    const bool top = fx >= 0 && fc == maxc;
-    const uint64_t mt = wave_min_u64(top ? ft : ~0ULL);
-    const int32_t bx = wave_min((top && ft == mt) ? fx : INT_MAX);
-    const int32_t own = H.hub_own[h];
+    int32_t bx = -1;
+    if (maxc >= 0) {
+        const bool top = fx >= 0 && fc == maxc;
+        const uint64_t mt = wave_min_u64(top ? ft : ~0ULL);
+        bx = wave_min((top && ft == mt) ? fx : INT_MAX);
+    }
     const bool over = A.refine && A.w[a] > A.bound;
-    const int32_t gain = maxc - own;
-    if (lane_id() == 0 && (over || gain > 0)) emit_one(A, v, bx, gain, c);
+    if (lane_id() == 0) store_result(A, h, bx, maxc, H.hub_own[h], over);
 }
 
-// ----------------------------------------------------------- admission
+// ------------------------------------------------------- block utilities
 
-__global__ void __launch_bounds__(256) admit_fast_kernel(const int32_t* __restrict__ ct, const int32_t* __restrict__ cg,
-                                                         const int32_t* __restrict__ w, const int32_t* __restrict__ tsum,
-                                                         int64_t bound, Counters* ctr, uint8_t* __restrict__ ok,
-                                                         uint32_t* __restrict__ slow_idx) {
-    const uint32_t n = ctr->ncand;
-    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-        const int32_t t = ct[i];
-        if (static_cast<int64_t>(w[t]) + tsum[t] <= bound) {
-            ok[i] = 1;  // everything aimed at t fits
-        } else {
-            ok[i] = 0;
-            const uint32_t j = atomicAdd(&ctr->nslow, 1u);
-            slow_idx[j] = i;
-            atomicMin(&ctr->gmin, cg[i]);
-            atomicMax(&ctr->gmax, cg[i]);
+// One atomic per block: returns the position of this thread's item among all
+// flagged items of the grid (order within the grid unspecified).
+__device__ __forceinline__ uint32_t block_append(bool flag, uint32_t* counter) {
+    __shared__ uint32_t s_cnt[4];
+    __shared__ uint32_t s_base;
+    const int wid = threadIdx.x >> 6;
+    const uint64_t m = __ballot(flag);
+    if (lane_id() == 0) s_cnt[wid] = static_cast<uint32_t>(__popcll(m));
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < 4; ++w) {
+            const uint32_t c = s_cnt[w];
+            s_cnt[w] = run;
+            run += c;
         }
+        s_base = run ? atomicAdd(counter, run) : 0;
+    }
+    __syncthreads();
+    const uint32_t idx = s_base + s_cnt[wid] + static_cast<uint32_t>(__popcll(m & lanemask_lt()));
+    __syncthreads();
+    return idx;
+}
+
+__device__ __forceinline__ int32_t block_sum_i32(int32_t v) {
+    __shared__ int32_t s[4];
+    v = wave_sum(v);
+    if (lane_id() == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const int32_t t = s[0] + s[1] + s[2] + s[3];
+    __syncthreads();
+    return t;
+}
+
+// ------------------------------------------------- candidates and admission
+
+// tsum[t] += c(v) over the candidates of the sub-round; counts them.
+template <bool kSmall>
+__global__ void __launch_bounds__(256) cand_accum_kernel(const int32_t* __restrict__ ct,
+                                                         const int32_t* __restrict__ nodes, int32_t count,
+                                                         const int32_t* __restrict__ vw, int32_t* __restrict__ tsum,
+                                                         int32_t nw, Counters* ctr) {
+    __shared__ int32_t loc[kSmall ? kSmallLabels : 1];
+    if (kSmall) {
+        for (int j = threadIdx.x; j < nw; j += 256) loc[j] = 0;
+        __syncthreads();
+    }
+    int32_t found = 0;
+    for (int32_t p = blockIdx.x * 256 + threadIdx.x; p < count; p += gridDim.x * 256) {
+        const int32_t t = ct[p];
+        if (t < 0) continue;
+        ++found;
+        const int32_t c = vw ? vw[nodes[p]] : 1;
+        if (c) {
+            if (kSmall) atomicAdd(&loc[t], c);
+            else atomicAdd(&tsum[t], c);
+        }
+    }
+    if (kSmall) {
+        __syncthreads();
+        for (int j = threadIdx.x; j < nw; j += 256)
+            if (loc[j]) atomicAdd(&tsum[j], loc[j]);
+    }
+    const int32_t tot = block_sum_i32(found);
+    if (threadIdx.x == 0 && tot) atomicAdd(&ctr->ncand, static_cast<uint32_t>(tot));
+}
+
+// Fast path of admission: if everything aimed at t fits, admit it all;
+// otherwise the candidate goes to the slow list.
+__global__ void __launch_bounds__(256) admit_kernel(const int32_t* __restrict__ ct, const int32_t* __restrict__ cg,
+                                                    int32_t count, const int32_t* __restrict__ w,
+                                                    const int32_t* __restrict__ tsum, int64_t bound,
+                                                    uint8_t* __restrict__ ok, uint32_t* __restrict__ slow_idx,
+                                                    Counters* ctr) {
+    __shared__ int32_t s_min[4], s_max[4];
+    const int32_t stride = gridDim.x * 256;
+    const int32_t iters = (count + stride - 1) / stride;
+    int32_t gmin = INT_MAX, gmax = INT_MIN;
+    for (int32_t it = 0; it < iters; ++it) {
+        const int32_t p = it * stride + blockIdx.x * 256 + threadIdx.x;
+        bool slow = false;
+        if (p < count) {
+            const int32_t t = ct[p];
+            uint8_t o = 0;
+            if (t >= 0) {
+                if (static_cast<int64_t>(w[t]) + tsum[t] <= bound) {
+                    o = 1;
+                } else {
+                    slow = true;
+                    const int32_t gain = cg[p];
+                    gmin = gain < gmin ? gain : gmin;
+                    gmax = gain > gmax ? gain : gmax;
+                }
+            }
+            ok[p] = o;
+        }
+        const uint32_t j = block_append(slow, &ctr->nslow);
+        if (slow) slow_idx[j] = static_cast<uint32_t>(p);
+    }
+    gmin = wave_min(gmin);
+    gmax = wave_max(gmax);
+    if (lane_id() == 0) {
+        s_min[threadIdx.x >> 6] = gmin;
+        s_max[threadIdx.x >> 6] = gmax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t a = INT_MAX, b = INT_MIN;
+        for (int w2 = 0; w2 < 4; ++w2) {
+            a = s_min[w2] < a ? s_min[w2] : a;
+            b = s_max[w2] > b ? s_max[w2] : b;
+        }
+        if (a != INT_MAX) atomicMin(&ctr->gmin, a);
+        if (b != INT_MIN) atomicMax(&ctr->gmax, b);
     }
 }
 
-// key = [t][gmax - gain][v] packed into the low bits; value = candidate index.
-__global__ void slow_keys_kernel(const uint32_t* __restrict__ slow_idx, uint32_t m, const int32_t* __restrict__ cv,
+// key = [t][gmax - gain][v] packed into the low bits; value = schedule entry.
+__global__ void slow_keys_kernel(const uint32_t* __restrict__ slow_idx, uint32_t m, const int32_t* __restrict__ nodes,
                                  const int32_t* __restrict__ ct, const int32_t* __restrict__ cg, int32_t gmax,
                                  int bits_v, int shift_t, int with_t, uint64_t* __restrict__ keys,
                                  uint32_t* __restrict__ vals) {
     const uint32_t j = blockIdx.x * 256 + threadIdx.x;
     if (j >= m) return;
-    const uint32_t i = slow_idx[j];
-    uint64_t k = (static_cast<uint64_t>(static_cast<int64_t>(gmax) - cg[i]) << bits_v) |
-                 static_cast<uint64_t>(static_cast<uint32_t>(cv[i]));
-    if (with_t) k |= static_cast<uint64_t>(static_cast<uint32_t>(ct[i])) << shift_t;
+    const uint32_t p = slow_idx[j];
+    uint64_t k = (static_cast<uint64_t>(static_cast<int64_t>(gmax) - cg[p]) << bits_v) |
+                 static_cast<uint64_t>(static_cast<uint32_t>(nodes[p]));
+    if (with_t) k |= static_cast<uint64_t>(static_cast<uint32_t>(ct[p])) << shift_t;
     keys[j] = k;
-    vals[j] = i;
+    vals[j] = p;
 }
 
 __global__ void slow_keys_t_kernel(const uint32_t* __restrict__ vals, uint32_t m, const int32_t* __restrict__ ct,
@@ -496,43 +614,63 @@ __global__ void slow_keys_t_kernel(const uint32_t* __restrict__ vals, uint32_t m
     keys[j] = static_cast<uint64_t>(static_cast<uint32_t>(ct[vals[j]]));
 }
 
-__global__ void slow_gather_kernel(const uint32_t* __restrict__ vals, uint32_t m, const int32_t* __restrict__ cv,
+__global__ void slow_gather_kernel(const uint32_t* __restrict__ vals, uint32_t m, const int32_t* __restrict__ nodes,
                                    const int32_t* __restrict__ ct, const int32_t* __restrict__ vw,
                                    int64_t* __restrict__ csum, int32_t* __restrict__ head) {
     const uint32_t j = blockIdx.x * 256 + threadIdx.x;
     if (j >= m) return;
-    const uint32_t i = vals[j];
-    csum[j] = vw ? vw[cv[i]] : 1;
-    head[j] = (j == 0 || ct[vals[j - 1]] != ct[i]) ? static_cast<int32_t>(j) : 0;
+    const uint32_t p = vals[j];
+    csum[j] = vw ? vw[nodes[p]] : 1;
+    head[j] = (j == 0 || ct[vals[j - 1]] != ct[p]) ? static_cast<int32_t>(j) : 0;
 }
 
+// Sorted by (target, gain desc, node asc): admit while the running weight of
+// the target's candidates keeps it within the bound (node weights are >= 0,
+// so the admitted set is a prefix).
 __global__ void slow_admit_kernel(const uint32_t* __restrict__ vals, uint32_t m, const int32_t* __restrict__ ct,
                                   const int32_t* __restrict__ w, const int64_t* __restrict__ psum,
                                   const int32_t* __restrict__ segstart, int64_t bound, uint8_t* __restrict__ ok) {
     const uint32_t j = blockIdx.x * 256 + threadIdx.x;
     if (j >= m) return;
-    const uint32_t i = vals[j];
+    const uint32_t p = vals[j];
     const int32_t s0 = segstart[j];
     const int64_t pre = psum[j] - (s0 > 0 ? psum[s0 - 1] : 0);
-    ok[i] = (static_cast<int64_t>(w[ct[i]]) + pre <= bound) ? 1 : 0;
+    ok[p] = (static_cast<int64_t>(w[ct[p]]) + pre <= bound) ? 1 : 0;
 }
 
-__global__ void __launch_bounds__(256) apply_kernel(const int32_t* __restrict__ cv, const int32_t* __restrict__ ct,
-                                                    const uint8_t* __restrict__ ok, uint32_t ncand,
+template <bool kSmall>
+__global__ void __launch_bounds__(256) apply_kernel(const int32_t* __restrict__ ct, const uint8_t* __restrict__ ok,
+                                                    const int32_t* __restrict__ nodes, int32_t count,
                                                     const int32_t* __restrict__ vw, int32_t* __restrict__ label,
-                                                    int32_t* __restrict__ w, int32_t* __restrict__ tsum) {
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= ncand) return;
-    const int32_t t = ct[i];
-    tsum[t] = 0;
-    if (!ok[i]) return;
-    const int32_t v = cv[i];
-    const int32_t a = label[v];
-    const int32_t c = vw ? vw[v] : 1;
-    label[v] = t;
-    if (c) {
-        atomicAdd(&w[t], c);
-        atomicSub(&w[a], c);
+                                                    int32_t* __restrict__ w, int32_t* __restrict__ tsum, int32_t nw) {
+    __shared__ int32_t delta[kSmall ? kSmallLabels : 1];
+    if (kSmall) {
+        for (int j = threadIdx.x; j < nw; j += 256) delta[j] = 0;
+        __syncthreads();
+    }
+    for (int32_t p = blockIdx.x * 256 + threadIdx.x; p < count; p += gridDim.x * 256) {
+        const int32_t t = ct[p];
+        if (t < 0) continue;
+        if (!kSmall) tsum[t] = 0;
+        if (!ok[p]) continue;
+        const int32_t v = nodes[p];
+        const int32_t a = label[v];
+        const int32_t c = vw ? vw[v] : 1;
+        label[v] = t;
+        if (c) {
+            if (kSmall) {
+                atomicAdd(&delta[t], c);
+                atomicSub(&delta[a], c);
+            } else {
+                atomicAdd(&w[t], c);
+                atomicSub(&w[a], c);
+            }
+        }
+    }
+    if (kSmall) {
+        __syncthreads();
+        for (int j = threadIdx.x; j < nw; j += 256)
+            if (delta[j]) atomicAdd(&w[j], delta[j]);
     }
 }
 
@@ -550,7 +688,8 @@ __global__ void reset_counters_kernel(Counters* ctr) {
 __global__ void __launch_bounds__(256) classify_kernel(int32_t n, const int64_t* __restrict__ xadj,
                                                        const int32_t* __restrict__ color_override, uint64_t hc,
                                                        int32_t nsub, int32_t th0, int32_t th1, int32_t th2,
-                                                       int32_t th3, uint64_t* __restrict__ keys,
+                                                       int32_t th3, int32_t th4, int32_t th5,
+                                                       uint64_t* __restrict__ keys,
                                                        uint32_t* __restrict__ vals, uint32_t* __restrict__ cat_count,
                                                        unsigned long long* __restrict__ cat_slots, Counters* ctr) {
     __shared__ uint32_t hist[16 * kNB + 1];
@@ -575,7 +714,13 @@ __global__ void __launch_bounds__(256) classify_kernel(int32_t n, const int64_t*
             col = static_cast<int32_t>(mix64(hc ^ static_cast<uint64_t>(static_cast<uint32_t>(v))) %
                                        static_cast<uint64_t>(nsub));
         }
-        int32_t bucket = d <= th0 ? 0 : d <= th1 ? 1 : d <= th2 ? 2 : d <= th3 ? 3 : 4;
+        const int32_t bucket = d <= th0   ? 0
+                               : d <= th1 ? 1
+                               : d <= th2 ? 2
+                               : d <= th3 ? 3
+                               : d <= th4 ? 4
+                               : d <= th5 ? 5
+                                          : kHubBucket;
         const int32_t cat = d == 0 ? ncat : col * kNB + bucket;
         keys[v] = static_cast<uint64_t>(cat);
         vals[v] = static_cast<uint32_t>(v);
@@ -599,12 +744,26 @@ __global__ void gather_rows_kernel(const int32_t* __restrict__ nodes, int32_t co
     }
 }
 
+template <bool kSmall>
 __global__ void __launch_bounds__(256) label_weights_kernel(int32_t n, const int32_t* __restrict__ label,
-                                                            const int32_t* __restrict__ vw, int32_t* __restrict__ w) {
-    const int32_t v = blockIdx.x * 256 + threadIdx.x;
-    if (v >= n) return;
-    const int32_t c = vw ? vw[v] : 1;
-    if (c) atomicAdd(&w[label[v]], c);
+                                                            const int32_t* __restrict__ vw, int32_t* __restrict__ w,
+                                                            int32_t nw) {
+    __shared__ int32_t loc[kSmall ? kSmallLabels : 1];
+    if (kSmall) {
+        for (int j = threadIdx.x; j < nw; j += 256) loc[j] = 0;
+        __syncthreads();
+    }
+    for (int32_t v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) {
+        const int32_t c = vw ? vw[v] : 1;
+        if (!c) continue;
+        if (kSmall) atomicAdd(&loc[label[v]], c);
+        else atomicAdd(&w[label[v]], c);
+    }
+    if (kSmall) {
+        __syncthreads();
+        for (int j = threadIdx.x; j < nw; j += 256)
+            if (loc[j]) atomicAdd(&w[j], loc[j]);
+    }
 }
 
 // Per-colour hub metadata built on the host after the schedule is known.
@@ -613,7 +772,6 @@ struct HubPlan {
     int32_t nchunks = 0;
     int32_t ntchunks = 0;
     int64_t table_entries = 0;
-    // device arrays (offsets into one buffer)
     DBuf<int32_t> i32;  // hub_nodes[H] | hub_tfirst[H+1] | chunk_hub[nc] | tchunk_hub[ntc]
     DBuf<int64_t> i64;  // hub_toff[H] | chunk_begin[nc] | tchunk_begin[ntc]
     DBuf<uint32_t> u32; // hub_tmask[H]
@@ -626,12 +784,20 @@ Counters* host_counters() {
     return t_host_ctr;
 }
 
+unsigned capped_grid(int64_t items) {
+    const int64_t g = (items + 255) / 256;
+    return static_cast<unsigned>(g < 1 ? 1 : (g > kMaxBlocks ? kMaxBlocks : g));
+}
+
 }  // namespace
 
 void label_weights(const DevGraph& g, const int32_t* label, int32_t* w, int32_t nw, hipStream_t s) {
     fill_i32(w, 0, nw, s);
     if (g.n > 0) {
-        label_weights_kernel<<<grid_for(g.n, 256), 256, 0, s>>>(g.n, label, g.vw, w);
+        if (nw <= kSmallLabels)
+            label_weights_kernel<true><<<capped_grid(g.n), 256, 0, s>>>(g.n, label, g.vw, w, nw);
+        else
+            label_weights_kernel<false><<<grid_for(g.n, 256), 256, 0, s>>>(g.n, label, g.vw, w, nw);
         LAUNCHCHK();
     }
 }
@@ -643,13 +809,17 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     const int32_t n = g.n;
     if (n == 0 || rounds <= 0) return res;
     if (nsub < 1 || nsub > 16) fail(-1, "subrounds must be in 1..16");
+    const bool small = nw <= kSmallLabels;
 
     // --- schedule: nodes grouped by (colour, degree bucket), ascending ids
     const int32_t ncat = nsub * kNB;
     const int32_t th1 = std::max(1, std::min(tune.lane_max, kLaneMax));
     const int32_t th0 = std::min(kLaneSmall, th1);
     const int32_t th2 = std::max(th1, std::min(tune.wave_max, kWaveMaxDeg));
-    const int32_t th3 = std::max(th2, std::min(tune.block_max, kBlockMaxDeg));
+    const int32_t tb = std::max(th2, std::min(tune.block_max, kBlockMaxDeg));
+    const int32_t th3 = std::min(tb, std::max(th2, kBlock1Max));
+    const int32_t th4 = std::min(tb, std::max(th3, kBlock2Max));
+    const int32_t th5 = tb;
     DBuf<uint64_t> ckeys(n, s), ckeys_tmp(n, s);
     DBuf<uint32_t> order(n, s), order_tmp(n, s);
     DBuf<uint32_t> cat_count(ncat + 1, s);
@@ -662,7 +832,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                                      static_cast<uint64_t>(static_cast<uint32_t>(phase))});
     {
         ProfScope ps("lp_schedule", 0, s);
-        classify_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, g.xadj, color_override, hc, nsub, th0, th1, th2, th3,
+        classify_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, g.xadj, color_override, hc, nsub, th0, th1, th2, th3, th4, th5,
                                                          ckeys.get(), order.get(), cat_count.get(), cat_slots.get(),
                                                          ctr.get());
         LAUNCHCHK();
@@ -690,7 +860,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     int64_t max_table = 0;
     int32_t max_tch = 0, max_hubs = 0;
     for (int32_t sc = 0; sc < nsub; ++sc) {
-        const int32_t cat = sc * kNB + 4;
+        const int32_t cat = sc * kNB + kHubBucket;
         const int32_t H = static_cast<int32_t>(cnt[cat]);
         HubPlan& P = plans[sc];
         P.count = H;
@@ -767,11 +937,11 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
         p_tie.alloc(max_tch, s);
     }
 
-    // --- candidate buffers: at most the nodes of one colour
+    // --- per-entry candidate buffers: at most the nodes of one colour
     int64_t max_color = 0;
     for (int32_t sc = 0; sc < nsub; ++sc) max_color = std::max(max_color, off[(sc + 1) * kNB] - off[sc * kNB]);
     const int64_t cap = std::max<int64_t>(max_color, 1);
-    DBuf<int32_t> cv(cap, s), ct(cap, s), cg(cap, s), tsum(nw, s);
+    DBuf<int32_t> ct(cap, s), cg(cap, s), tsum(nw, s);
     DBuf<uint8_t> ok(cap, s);
     DBuf<uint32_t> slow_idx(cap, s);
     fill_i32(tsum.get(), 0, nw, s);
@@ -785,16 +955,12 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     A.w = w;
     A.bound = bound;
     A.refine = phase == kRefine ? 1 : 0;
-    A.cv = cv.get();
-    A.ct = ct.get();
-    A.cg = cg.get();
-    A.tsum = tsum.get();
-    A.ctr = ctr.get();
 
-    // Algorithmic bytes of one evaluation launch: per node its list entry,
-    // row offsets, own label and weight (and w(own) when refining); per slot
-    // the neighbour id, edge weight and neighbour label.
-    const double node_bytes = 4.0 + 16.0 + 4.0 + (g.vw ? 4.0 : 0.0) + (phase == kRefine ? 4.0 : 0.0);
+    // Algorithmic bytes of one evaluation launch: per node its schedule entry,
+    // row offsets, own label and weight (and w(own) when refining) and its
+    // result (target, gain); per slot the neighbour id, edge weight and
+    // neighbour label.
+    const double node_bytes = 4.0 + 16.0 + 4.0 + (g.vw ? 4.0 : 0.0) + (phase == kRefine ? 4.0 : 0.0) + 8.0;
     const double slot_bytes = 8.0 + (g.ew ? 4.0 : 0.0);
     auto eval_bytes = [&](int64_t nodes_in, unsigned long long slots_in) {
         return node_bytes * static_cast<double>(nodes_in) + slot_bytes * static_cast<double>(slots_in);
@@ -815,23 +981,34 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
         int64_t round_cands = 0;
         for (int32_t sc = 0; sc < nsub; ++sc) {
             const int32_t c0 = sc * kNB;
-            // evaluation
-            for (int32_t bk = 0; bk < 4; ++bk) {
+            const int64_t ccount = off[c0 + kNB] - off[c0];
+            if (ccount == 0) continue;
+            const int32_t* cnodes = nodes + off[c0];
+            // evaluation: one result per schedule entry of this colour
+            for (int32_t bk = 0; bk < kHubBucket; ++bk) {
                 const int64_t count = off[c0 + bk + 1] - off[c0 + bk];
                 if (count == 0) continue;
                 A.nodes = nodes + off[c0 + bk];
                 A.count = static_cast<int32_t>(count);
-                static const char* const kNames[4] = {"lp_eval_lane4", "lp_eval_lane16", "lp_eval_wave",
-                                                      "lp_eval_block"};
+                A.ct = ct.get() + (off[c0 + bk] - off[c0]);
+                A.cg = cg.get() + (off[c0 + bk] - off[c0]);
+                static const char* const kNames[kHubBucket] = {"lp_eval_lane4", "lp_eval_lane16", "lp_eval_wave",
+                                                               "lp_eval_block1k", "lp_eval_block4k",
+                                                               "lp_eval_block8k"};
                 ProfScope ps(kNames[bk], eval_bytes(count, cslots[c0 + bk]), s);
+                const unsigned nb = static_cast<unsigned>(count);
                 if (bk == 0) {
                     eval_lane_kernel<kLaneSmall><<<grid_for(count, 256), 256, 0, s>>>(A);
                 } else if (bk == 1) {
                     eval_lane_kernel<kLaneMax><<<grid_for(count, 256), 256, 0, s>>>(A);
                 } else if (bk == 2) {
                     eval_wave_kernel<<<grid_for(count, 4), 256, 0, s>>>(A);
+                } else if (bk == 3) {
+                    eval_block_kernel<256, 2 * kBlock1Max><<<nb, 256, 0, s>>>(A);
+                } else if (bk == 4) {
+                    eval_block_kernel<512, 2 * kBlock2Max><<<nb, 512, 0, s>>>(A);
                 } else {
-                    eval_block_kernel<<<static_cast<unsigned>(count), kBlockThreads, 0, s>>>(A);
+                    eval_block_kernel<1024, kBlockTable><<<nb, 1024, 0, s>>>(A);
                 }
                 LAUNCHCHK();
             }
@@ -857,9 +1034,11 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 fill_i32(hub_own.get(), 0, P.count, s);
                 A.nodes = H.hub_nodes;
                 A.count = P.count;
+                A.ct = ct.get() + (off[c0 + kHubBucket] - off[c0]);
+                A.cg = cg.get() + (off[c0 + kHubBucket] - off[c0]);
                 {
-                    ProfScope ps("lp_eval_hub_insert", eval_bytes(P.count, cslots[c0 + 4]), s);
-                    hub_insert_kernel<<<P.nchunks, 256, 0, s>>>(A, H);
+                    ProfScope ps("lp_eval_hub_insert", eval_bytes(P.count, cslots[c0 + kHubBucket]), s);
+                    hub_insert_kernel<<<P.nchunks, kBlockThreads, 0, s>>>(A, H);
                     LAUNCHCHK();
                 }
                 {
@@ -870,12 +1049,18 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 hub_finish_kernel<<<P.count, 64, 0, s>>>(A, H);
                 LAUNCHCHK();
             }
-            // admission, fast path: targets whose candidates all fit
-            const int64_t ccount = off[c0 + kNB] - off[c0];
+            // per-target candidate weight, then admission (fast path)
             {
                 ProfScope ps("lp_admit", 0, s);
-                admit_fast_kernel<<<grid_for(std::max<int64_t>(ccount, 1), 256), 256, 0, s>>>(
-                    ct.get(), cg.get(), w, tsum.get(), bound, ctr.get(), ok.get(), slow_idx.get());
+                if (small)
+                    cand_accum_kernel<true><<<capped_grid(ccount), 256, 0, s>>>(ct.get(), cnodes, ccount, g.vw,
+                                                                                tsum.get(), nw, ctr.get());
+                else
+                    cand_accum_kernel<false><<<capped_grid(ccount), 256, 0, s>>>(ct.get(), cnodes, ccount, g.vw,
+                                                                                 tsum.get(), nw, ctr.get());
+                LAUNCHCHK();
+                admit_kernel<<<capped_grid(ccount), 256, 0, s>>>(ct.get(), cg.get(), ccount, w, tsum.get(), bound,
+                                                                 ok.get(), slow_idx.get(), ctr.get());
                 LAUNCHCHK();
             }
             HIPCHK(hipMemcpyAsync(hctr, ctr.get(), sizeof(Counters), hipMemcpyDeviceToHost, s));
@@ -886,6 +1071,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
             if (m > 0) {
                 // slow path: sort candidates of overflowing targets by
                 // (target, gain desc, node asc) and admit the prefix that fits
+                ProfScope ps("lp_admit_sorted", 0, s);
                 const int bits_g = bits_for(static_cast<uint64_t>(static_cast<int64_t>(hctr->gmax) - hctr->gmin));
                 const int low_bits = bits_g + bits_v;
                 const bool single = low_bits + bits_t <= 64;
@@ -894,8 +1080,8 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 sv_tmp.reserve(m, s);
                 psum.reserve(m, s);
                 heads.reserve(m, s);
-                uint32_t* sv = slow_idx.get();  // reused as values (sorted in place)
-                slow_keys_kernel<<<grid_for(m, 256), 256, 0, s>>>(slow_idx.get(), m, cv.get(), ct.get(), cg.get(),
+                uint32_t* sv = slow_idx.get();  // values, sorted in place
+                slow_keys_kernel<<<grid_for(m, 256), 256, 0, s>>>(slow_idx.get(), m, cnodes, ct.get(), cg.get(),
                                                                   hctr->gmax, bits_v, low_bits, single ? 1 : 0,
                                                                   sk.get(), sv);
                 LAUNCHCHK();
@@ -907,7 +1093,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                     LAUNCHCHK();
                     radix_sort_pairs(sk.get(), sv, sk_tmp.get(), sv_tmp.get(), m, 0, bits_t, rs, s);
                 }
-                slow_gather_kernel<<<grid_for(m, 256), 256, 0, s>>>(sv, m, cv.get(), ct.get(), g.vw, psum.get(),
+                slow_gather_kernel<<<grid_for(m, 256), 256, 0, s>>>(sv, m, cnodes, ct.get(), g.vw, psum.get(),
                                                                     heads.get());
                 LAUNCHCHK();
                 inclusive_scan_i64(psum.get(), psum.get(), m, s);
@@ -918,9 +1104,16 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
             }
             if (ncand > 0) {
                 ProfScope ps("lp_apply", 0, s);
-                apply_kernel<<<grid_for(ncand, 256), 256, 0, s>>>(cv.get(), ct.get(), ok.get(), ncand, g.vw, label, w,
-                                                                  tsum.get());
-                LAUNCHCHK();
+                if (small) {
+                    apply_kernel<true><<<capped_grid(ccount), 256, 0, s>>>(ct.get(), ok.get(), cnodes, ccount, g.vw,
+                                                                           label, w, tsum.get(), nw);
+                    LAUNCHCHK();
+                    fill_i32(tsum.get(), 0, nw, s);
+                } else {
+                    apply_kernel<false><<<grid_for(ccount, 256), 256, 0, s>>>(ct.get(), ok.get(), cnodes, ccount,
+                                                                              g.vw, label, w, tsum.get(), nw);
+                    LAUNCHCHK();
+                }
             }
             reset_counters_kernel<<<1, 1, 0, s>>>(ctr.get());
             LAUNCHCHK();
