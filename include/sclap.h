@@ -92,7 +92,9 @@ typedef struct {
     int32_t lane_max_degree;  /* rows up to this degree: one lane per node */
     int32_t wave_max_degree;  /* up to this: one wave64 per node, LDS table */
     int32_t block_max_degree; /* up to this: one workgroup per node, LDS table; above: hub path */
-    int32_t reserved[5];
+    int32_t hub_part_limit;   /* hub label partitions summed in LDS up to this many entries */
+    int32_t hub_region_cap;   /* entries a hub partition keeps before spilling to its overflow list */
+    int32_t reserved[3];
 } sclap_options;
 
 #define SCLAP_MAX_LEVELS 64

@@ -92,6 +92,8 @@ Opts resolve(const sclap_options* o) {
     if (o->lane_max_degree > 0) r.tune.lane_max = o->lane_max_degree;
     if (o->wave_max_degree > 0) r.tune.wave_max = o->wave_max_degree;
     if (o->block_max_degree > 0) r.tune.block_max = o->block_max_degree;
+    if (o->hub_part_limit > 0) r.tune.hub_part_limit = o->hub_part_limit;
+    if (o->hub_region_cap > 0) r.tune.hub_region_cap = o->hub_region_cap;
     if (r.coarsen_rounds < 0 || r.refine_rounds < 0) fail(SCLAP_ERR_INVALID, "round counts must be >= 0");
     if (r.nsub < 1 || r.nsub > 16) fail(SCLAP_ERR_INVALID, "subrounds must be in 1..16");
     if (r.divisor < 1) fail(SCLAP_ERR_INVALID, "cluster_divisor must be >= 1");
@@ -180,6 +182,7 @@ struct MinTree {
         for (p >>= 1; p > 0; p >>= 1) t[p] = std::min(t[2 * p], t[2 * p + 1]);
     }
     int32_t first_le(int64_t from, int64_t cap) const { return static_cast<int32_t>(descend(1, 0, size, from, cap)); }
+    int64_t min() const { return t[1]; }
     int64_t descend(int64_t node, int64_t lo, int64_t hi, int64_t from, int64_t cap) const {
         if (hi <= from || t[node] > cap) return -1;
         if (hi - lo == 1) return lo;
@@ -222,8 +225,9 @@ struct BlockHeap {
 // order), then deals every remaining node, in id order, to the currently
 // lightest block (lowest id on ties).  Weights fit 31 bits (c(V) <= 2^31-1).
 void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, const int32_t* vw, int32_t k,
-                            int64_t T, int32_t* part) {
+                            int64_t T, int32_t* part, bool rows_sorted = false) {
     std::fill(part, part + n, -1);
+    std::vector<uint64_t> taken((static_cast<size_t>(n) + 63) / 64, 0);  // 1 bit per node, cache resident
     std::vector<int64_t> wb(static_cast<size_t>(k), 0);
     // seed candidates: nodes of positive degree, in id order
     std::vector<int32_t> seed_node;
@@ -240,6 +244,7 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
     std::deque<int32_t> q;
     auto take = [&](int32_t v, int32_t b) {
         part[v] = b;
+        taken[static_cast<size_t>(v) >> 6] |= 1ULL << (v & 63);
         wb[b] += vw ? vw[v] : 1;
         if (seed_pos[v] >= 0) seeds.erase(seed_pos[v]);
     };
@@ -252,11 +257,17 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
             take(sd, b);
             q.push_back(sd);
             while (!q.empty()) {
+                // every node a search can reach has positive degree, so once
+                // the lightest such unassigned node does not fit, stop
+                if (seeds.min() > T - wb[b]) {
+                    q.clear();
+                    break;
+                }
                 const int32_t u = q.front();
                 q.pop_front();
                 const int32_t* row = adj + xadj[u];
                 const int32_t* row_end = adj + xadj[u + 1];
-                if (!std::is_sorted(row, row_end)) {
+                if (!rows_sorted && !std::is_sorted(row, row_end)) {
                     nb.assign(row, row_end);
                     std::sort(nb.begin(), nb.end());
                     row = nb.data();
@@ -264,7 +275,7 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
                 }
                 for (const int32_t* it = row; it != row_end; ++it) {
                     const int32_t x = *it;
-                    if (part[x] >= 0) continue;
+                    if ((taken[static_cast<size_t>(x) >> 6] >> (x & 63)) & 1ULL) continue;
                     if (wb[b] + (vw ? vw[x] : 1) > T) continue;
                     take(x, b);
                     q.push_back(x);
@@ -413,7 +424,8 @@ int partition_impl(const DevGraph& g0, int32_t k, double eps, uint64_t seed, con
         HIPCHK(hipStreamSynchronize(s));
     }
     const int64_t T = (cV + k - 1) / k;
-    host_initial_partition(nc, hx.data(), ha.data(), Gc.vw ? hv.data() : nullptr, k, T, hp.data());
+    // rows of contracted levels are sorted by construction
+    host_initial_partition(nc, hx.data(), ha.data(), Gc.vw ? hv.data() : nullptr, k, T, hp.data(), lev > 0);
     DBuf<int32_t> cur;
     int32_t* curp = part_out;
     if (lev > 0) {

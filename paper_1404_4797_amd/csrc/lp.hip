@@ -18,8 +18,10 @@
 //   block  one workgroup per node with an LDS table of 16, 64 or 128 KB
 //          (deg <= 1024, 4096, 8192)
 //   hub    the row is cut into 8192-slot chunks; each workgroup sums its
-//          chunk in an LDS table, then merges the distinct labels into an
-//          open-addressing table in HBM that a second pass scans
+//          chunk in an LDS table and appends the chunk's distinct labels to
+//          the hub's entry list; one workgroup per hub then sums that list in
+//          LDS, or, when it is longer than 8192 entries, through an
+//          open-addressing table in HBM that a further pass scans
 // The per-node connection table maps a neighbour label to the summed weight
 // of the edges to it (Section 4.1 uses hashing with linear probing for this).
 //
@@ -27,6 +29,8 @@
 // sub-round's schedule, so no counter is shared.  Per-label sums use
 // LDS-private histograms when the label space is small (refinement: k blocks).
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
 
 #include "lp.hpp"
 #include "profile.hpp"
@@ -41,7 +45,6 @@ constexpr int kLaneSmall = 4;
 constexpr int kLaneMax = 16;
 constexpr int kWaveTable = 512;
 constexpr int kWaveMaxDeg = kWaveTable / 2;
-constexpr int kBlockThreads = 512;
 constexpr int kBlockTable = 16384;
 constexpr int kBlockMaxDeg = kBlockTable / 2;
 constexpr int kBlock1Max = 1024;  // 256 threads, 16 KB table
@@ -366,55 +369,249 @@ __global__ void __launch_bounds__(NT) eval_block_kernel(EvalArgs A) {
 
 struct HubArgs {
     const int32_t* hub_nodes;    // [H]
-    const int64_t* hub_toff;     // [H] table offset
-    const uint32_t* hub_tmask;   // [H] table size - 1
-    const int32_t* hub_tfirst;   // [H+1] first scan chunk of each hub
+    const int32_t* hub_plog;     // [H] log2 of the hub's partition count
+    const int32_t* hub_pbase;    // [H+1] first partition of each hub
+    const int32_t* hub_cap;      // [H] entries per partition region
+    const int32_t* hub_tfirst;   // [H+1] first HBM table chunk of each hub
     const int32_t* chunk_hub;    // [nchunks]
-    const int64_t* chunk_begin;  // [nchunks] first slot
+    const int32_t* part_hub;     // [nparts]
     const int32_t* tchunk_hub;   // [ntchunks]
+    const int64_t* hub_rbase;    // [H] first region entry of the hub
+    const int64_t* hub_obase;    // [H] first overflow entry of the hub
+    const int64_t* hub_toff;     // [H] HBM table offset
+    const int64_t* chunk_begin;  // [nchunks] first slot of the chunk
     const int64_t* tchunk_begin; // [ntchunks] first table entry (absolute)
-    int32_t* gkeys;
+    const uint32_t* hub_tmask;   // [H] HBM table size - 1
+    int32_t* rcount;   // [nparts] entries reserved per partition    } zeroed
+    int32_t* ocount;   // [H] overflow entries                      } per
+    int32_t* big;      // [H] hub needs the HBM table               } sub-
+    int32_t* hub_own;  // [H] connection to the own label           } round
+    int32_t* ekeys;    // partition regions (label, summed weight)
+    int32_t* evals;
+    int32_t* okeys;    // overflow of full regions
+    int32_t* ovals;
+    int32_t* gkeys;    // HBM tables
     int32_t* gvals;
-    int32_t* hub_own;   // [H]
-    int32_t* p_conn;    // [ntchunks]
-    uint64_t* p_tie;
-    int32_t* p_x;
+    int32_t* w_conn;   // winners per partition, then per table chunk
+    uint64_t* w_tie;
+    int32_t* w_x;
+    int32_t part_limit;  // partitions with more entries take the HBM table path
 };
 
-// Sums one chunk of a hub row in LDS, then adds its distinct labels to the
-// hub's table in HBM (one HBM update per distinct label per chunk).
-__global__ void __launch_bounds__(kBlockThreads) hub_insert_kernel(EvalArgs A, HubArgs H) {
+constexpr int kHubThreads = 1024;
+constexpr int kPartThreads = 256;
+constexpr int kPartTable = 8192;  // 64 KB LDS table of a partition workgroup
+constexpr int kMaxPartLog = 10;   // at most 1024 partitions per hub
+
+__device__ __forceinline__ uint32_t part_of(int32_t x, int32_t plog) {
+    return plog == 0 ? 0u : (slot_hash(static_cast<uint32_t>(x)) >> (32 - plog));
+}
+
+// Sums one chunk of a hub row in an LDS table, then scatters the chunk's
+// distinct (label, weight) entries into the hub's label partitions.
+__global__ void __launch_bounds__(kHubThreads) hub_chunk_kernel(EvalArgs A, HubArgs H) {
     __shared__ int32_t keys[kBlockTable];
     __shared__ int32_t vals[kBlockTable];
+    __shared__ uint32_t pcount[1 << kMaxPartLog];
+    __shared__ int32_t pbase[1 << kMaxPartLog];
+    constexpr int kPer = kBlockTable / kHubThreads;
     const int tid = threadIdx.x;
     const int32_t h = H.chunk_hub[blockIdx.x];
     const int32_t v = H.hub_nodes[h];
     const int64_t begin = H.chunk_begin[blockIdx.x];
     const int64_t row_end = A.xadj[v + 1];
     const int64_t end = begin + kHubChunk < row_end ? begin + kHubChunk : row_end;
-    const uint32_t tsz = table_size_for(static_cast<int32_t>(end - begin), 512, kBlockTable);
+    const uint32_t tsz = table_size_for(static_cast<int32_t>(end - begin), 1024, kBlockTable);
     const uint32_t mask = tsz - 1;
-    for (uint32_t j = tid; j < tsz; j += kBlockThreads) {
+    const int32_t plog = H.hub_plog[h];
+    const int32_t P = 1 << plog;
+    for (uint32_t j = tid; j < tsz; j += kHubThreads) {
+        keys[j] = -1;
+        vals[j] = 0;
+    }
+    for (int32_t j = tid; j < P; j += kHubThreads) pcount[j] = 0;
+    __syncthreads();
+    insert_slots<kHubThreads, 4>(A, begin, static_cast<int32_t>(end - begin), keys, vals, mask, tid);
+    __syncthreads();
+    for (int j = 0; j < kPer; ++j) {
+        const uint32_t e = static_cast<uint32_t>(tid) * kPer + j;
+        if (e < tsz && keys[e] >= 0) atomicAdd(&pcount[part_of(keys[e], plog)], 1u);
+    }
+    __syncthreads();
+    for (int32_t j = tid; j < P; j += kHubThreads) {
+        const uint32_t c = pcount[j];
+        pbase[j] = c ? atomicAdd(&H.rcount[H.hub_pbase[h] + j], static_cast<int32_t>(c)) : 0;
+        pcount[j] = 0;
+    }
+    __syncthreads();
+    const int32_t cap = H.hub_cap[h];
+    const int64_t rb = H.hub_rbase[h];
+    for (int j = 0; j < kPer; ++j) {
+        const uint32_t e = static_cast<uint32_t>(tid) * kPer + j;
+        if (e >= tsz || keys[e] < 0) continue;
+        const uint32_t p = part_of(keys[e], plog);
+        const int32_t idx = pbase[p] + static_cast<int32_t>(atomicAdd(&pcount[p], 1u));
+        if (idx < cap) {
+            const int64_t at = rb + static_cast<int64_t>(p) * cap + idx;
+            H.ekeys[at] = keys[e];
+            H.evals[at] = vals[e];
+        } else {  // region full: the rest of the partition goes to the hub's overflow list
+            const int64_t at = H.hub_obase[h] + atomicAdd(&H.ocount[h], 1);
+            H.okeys[at] = keys[e];
+            H.ovals[at] = vals[e];
+        }
+    }
+}
+
+__device__ __forceinline__ int32_t block_sum_part(int32_t v, int32_t* s_red) {
+    v = wave_sum(v);
+    if (lane_id() == 0) s_red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int32_t t = 0;
+    for (int w = 0; w < kPartThreads / 64; ++w) t += s_red[w];
+    __syncthreads();
+    return t;
+}
+
+// One workgroup per label partition of a hub: sums the partition's entries
+// in LDS and writes the partition's best eligible label.  A partition with
+// more than part_limit entries marks its hub for the HBM table path.
+__global__ void __launch_bounds__(kPartThreads) hub_part_kernel(EvalArgs A, HubArgs H) {
+    __shared__ int32_t keys[kPartTable];
+    __shared__ int32_t vals[kPartTable];
+    __shared__ int32_t s_red[kPartThreads / 64];
+    __shared__ int32_t s_conn[kPartThreads / 64];
+    __shared__ int32_t s_x[kPartThreads / 64];
+    __shared__ uint64_t s_tie[kPartThreads / 64];
+    const int tid = threadIdx.x;
+    const int32_t gp = blockIdx.x;
+    const int32_t h = H.part_hub[gp];
+    const int32_t p = gp - H.hub_pbase[h];
+    const int32_t plog = H.hub_plog[h];
+    const int32_t cap = H.hub_cap[h];
+    const int32_t in_region = H.rcount[gp] < cap ? H.rcount[gp] : cap;
+    const int32_t ov = H.ocount[h];
+    const int64_t ob = H.hub_obase[h];
+    int32_t mine = 0;
+    for (int32_t j = tid; j < ov; j += kPartThreads) mine += part_of(H.okeys[ob + j], plog) == static_cast<uint32_t>(p);
+    const int32_t total = in_region + (ov > 0 ? block_sum_part(mine, s_red) : 0);
+    if (total > H.part_limit) {
+        if (tid == 0) H.big[h] = 1;
+        return;
+    }
+    const uint32_t tsz = table_size_for(total, 256, kPartTable);
+    const uint32_t mask = tsz - 1;
+    for (uint32_t j = tid; j < tsz; j += kPartThreads) {
         keys[j] = -1;
         vals[j] = 0;
     }
     __syncthreads();
-    insert_slots<kBlockThreads, 4>(A, begin, static_cast<int32_t>(end - begin), keys, vals, mask, tid);
+    const int64_t r0 = H.hub_rbase[h] + static_cast<int64_t>(p) * cap;
+    for (int32_t j = tid; j < in_region; j += kPartThreads) table_add(keys, vals, mask, H.ekeys[r0 + j], H.evals[r0 + j]);
+    for (int32_t j = tid; j < ov; j += kPartThreads) {
+        const int32_t x = H.okeys[ob + j];
+        if (part_of(x, plog) == static_cast<uint32_t>(p)) table_add(keys, vals, mask, x, H.ovals[ob + j]);
+    }
     __syncthreads();
-    int32_t* gk = H.gkeys + H.hub_toff[h];
-    int32_t* gv = H.gvals + H.hub_toff[h];
-    const uint32_t gmask = H.hub_tmask[h];
-    for (uint32_t j = tid; j < tsz; j += kBlockThreads) {
+    const int32_t v = H.hub_nodes[h];
+    const int32_t a = A.label[v];
+    const int32_t c = A.vw ? A.vw[v] : 1;
+    Best best;
+    best_init(best);
+    for (uint32_t j = tid; j < tsz; j += kPartThreads) {
         const int32_t x = keys[j];
-        if (x >= 0) table_add(gk, gv, gmask, x, vals[j]);
+        if (x < 0) continue;
+        const int32_t conn = vals[j];
+        if (x == a) {
+            H.hub_own[h] = conn;  // only the partition of a holds a, in one entry
+            continue;
+        }
+        if (best.x >= 0 && conn < best.conn) continue;
+        if (!eligible(A, x, c)) continue;
+        best_consider(best, x, conn, A.tp);
+    }
+    int32_t bx, bconn;
+    wave_argmax(best, A.tp, bx, bconn);
+    const int wid = tid >> 6;
+    if (lane_id() == 0) {
+        s_conn[wid] = bconn;
+        s_x[wid] = bx;
+        s_tie[wid] = bx >= 0 ? tie_of(A.tp, bx) : ~0ULL;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int32_t fc = -1, fx = -1;
+        uint64_t ft = ~0ULL;
+        for (int w = 0; w < kPartThreads / 64; ++w) combine_into(fc, ft, fx, s_conn[w], s_tie[w], s_x[w]);
+        H.w_conn[gp] = fc;
+        H.w_tie[gp] = ft;
+        H.w_x[gp] = fx;
     }
 }
 
-__global__ void __launch_bounds__(256) hub_scan_kernel(EvalArgs A, HubArgs H) {
+// Decision of a hub from the winners in [first[h], first[h+1]).
+__device__ __forceinline__ void hub_decide(const EvalArgs& A, const HubArgs& H, int32_t h, const int32_t* first) {
+    const int32_t v = H.hub_nodes[h];
+    const int32_t a = A.label[v];
+    int32_t fc = -1, fx = -1;
+    uint64_t ft = ~0ULL;
+    for (int32_t j = first[h] + lane_id(); j < first[h + 1]; j += 64)
+        combine_into(fc, ft, fx, H.w_conn[j], H.w_tie[j], H.w_x[j]);
+    const int32_t maxc = wave_max(fx >= 0 ? fc : -1);
+    int32_t bx = -1;
+    if (maxc >= 0) {
+        const bool top = fx >= 0 && fc == maxc;
+        const uint64_t mt = wave_min_u64(top ? ft : ~0ULL);
+        bx = wave_min((top && ft == mt) ? fx : INT_MAX);
+    }
+    const bool over = A.refine && A.w[a] > A.bound;
+    if (lane_id() == 0) store_result(A, h, bx, maxc, H.hub_own[h], over);
+}
+
+__global__ void __launch_bounds__(64) hub_finish_kernel(EvalArgs A, HubArgs H) {
+    if (H.big[blockIdx.x]) return;
+    hub_decide(A, H, blockIdx.x, H.hub_pbase);
+}
+
+// HBM table path for marked hubs: clear the table ...
+__global__ void __launch_bounds__(256) hub_clear_kernel(HubArgs H) {
+    const int32_t h = H.tchunk_hub[blockIdx.x];
+    if (!H.big[h]) return;
+    const int64_t begin = H.tchunk_begin[blockIdx.x];
+    const int64_t tend = H.hub_toff[h] + static_cast<int64_t>(H.hub_tmask[h]) + 1;
+    const int64_t end = begin + kHubTChunk < tend ? begin + kHubTChunk : tend;
+    for (int64_t j = begin + threadIdx.x; j < end; j += 256) {
+        H.gkeys[j] = -1;
+        H.gvals[j] = 0;
+    }
+}
+
+// ... add every partition region (and, from partition 0, the overflow list) ...
+__global__ void __launch_bounds__(256) hub_table_insert_kernel(HubArgs H) {
+    const int32_t gp = blockIdx.x;
+    const int32_t h = H.part_hub[gp];
+    if (!H.big[h]) return;
+    const int32_t p = gp - H.hub_pbase[h];
+    const int32_t cap = H.hub_cap[h];
+    const int32_t in_region = H.rcount[gp] < cap ? H.rcount[gp] : cap;
+    int32_t* gk = H.gkeys + H.hub_toff[h];
+    int32_t* gv = H.gvals + H.hub_toff[h];
+    const uint32_t gmask = H.hub_tmask[h];
+    const int64_t r0 = H.hub_rbase[h] + static_cast<int64_t>(p) * cap;
+    for (int32_t j = threadIdx.x; j < in_region; j += 256) table_add(gk, gv, gmask, H.ekeys[r0 + j], H.evals[r0 + j]);
+    if (p == 0) {
+        const int64_t ob = H.hub_obase[h];
+        for (int32_t j = threadIdx.x; j < H.ocount[h]; j += 256) table_add(gk, gv, gmask, H.okeys[ob + j], H.ovals[ob + j]);
+    }
+}
+
+// ... pick the best entry of each table chunk ...
+__global__ void __launch_bounds__(256) hub_scan_kernel(EvalArgs A, HubArgs H, int32_t wbase) {
     __shared__ int32_t s_conn[4];
     __shared__ int32_t s_x[4];
     __shared__ uint64_t s_tie[4];
     const int32_t h = H.tchunk_hub[blockIdx.x];
+    if (!H.big[h]) return;
     const int32_t v = H.hub_nodes[h];
     const int32_t a = A.label[v];
     const int32_t c = A.vw ? A.vw[v] : 1;
@@ -428,7 +625,7 @@ __global__ void __launch_bounds__(256) hub_scan_kernel(EvalArgs A, HubArgs H) {
         if (x < 0) continue;
         const int32_t conn = H.gvals[j];
         if (x == a) {
-            H.hub_own[h] = conn;  // the own label occupies exactly one entry
+            H.hub_own[h] = conn;
             continue;
         }
         if (best.x >= 0 && conn < best.conn) continue;
@@ -448,29 +645,16 @@ __global__ void __launch_bounds__(256) hub_scan_kernel(EvalArgs A, HubArgs H) {
         int32_t fc = -1, fx = -1;
         uint64_t ft = ~0ULL;
         for (int w = 0; w < 4; ++w) combine_into(fc, ft, fx, s_conn[w], s_tie[w], s_x[w]);
-        H.p_conn[blockIdx.x] = fc;
-        H.p_tie[blockIdx.x] = ft;
-        H.p_x[blockIdx.x] = fx;
+        H.w_conn[wbase + blockIdx.x] = fc;
+        H.w_tie[wbase + blockIdx.x] = ft;
+        H.w_x[wbase + blockIdx.x] = fx;
     }
 }
 
-__global__ void __launch_bounds__(64) hub_finish_kernel(EvalArgs A, HubArgs H) {
-    const int32_t h = blockIdx.x;
-    const int32_t v = H.hub_nodes[h];
-    const int32_t a = A.label[v];
-    int32_t fc = -1, fx = -1;
-    uint64_t ft = ~0ULL;
-    for (int32_t j = H.hub_tfirst[h] + lane_id(); j < H.hub_tfirst[h + 1]; j += 64)
-        combine_into(fc, ft, fx, H.p_conn[j], H.p_tie[j], H.p_x[j]);
-    const int32_t maxc = wave_max(fx >= 0 ? fc : -1);
-    int32_t bx = -1;
-    if (maxc >= 0) {
-        const bool top = fx >= 0 && fc == maxc;
-        const uint64_t mt = wave_min_u64(top ? ft : ~0ULL);
-        bx = wave_min((top && ft == mt) ? fx : INT_MAX);
-    }
-    const bool over = A.refine && A.w[a] > A.bound;
-    if (lane_id() == 0) store_result(A, h, bx, maxc, H.hub_own[h], over);
+// ... and decide from the chunk winners (stored after the partition winners).
+__global__ void __launch_bounds__(64) hub_big_finish_kernel(EvalArgs A, HubArgs H, const int32_t* tfirst_shifted) {
+    if (!H.big[blockIdx.x]) return;
+    hub_decide(A, H, blockIdx.x, tfirst_shifted);
 }
 
 // ------------------------------------------------------- block utilities
@@ -770,11 +954,16 @@ __global__ void __launch_bounds__(256) label_weights_kernel(int32_t n, const int
 struct HubPlan {
     int32_t count = 0;
     int32_t nchunks = 0;
+    int32_t nparts = 0;
     int32_t ntchunks = 0;
+    int64_t region_entries = 0;
+    int64_t overflow_entries = 0;
     int64_t table_entries = 0;
-    DBuf<int32_t> i32;  // hub_nodes[H] | hub_tfirst[H+1] | chunk_hub[nc] | tchunk_hub[ntc]
-    DBuf<int64_t> i64;  // hub_toff[H] | chunk_begin[nc] | tchunk_begin[ntc]
-    DBuf<uint32_t> u32; // hub_tmask[H]
+    // hub_nodes | plog | pbase[H+1] | cap | tfirst_shifted[H+1] | chunk_hub | part_hub | tchunk_hub
+    DBuf<int32_t> i32;
+    // rbase | obase | toff | chunk_begin | tchunk_begin
+    DBuf<int64_t> i64;
+    DBuf<uint32_t> u32;  // tmask
 };
 
 thread_local Counters* t_host_ctr = nullptr;
@@ -810,6 +999,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     if (n == 0 || rounds <= 0) return res;
     if (nsub < 1 || nsub > 16) fail(-1, "subrounds must be in 1..16");
     const bool small = nw <= kSmallLabels;
+    static const bool trace = std::getenv("SCLAP_TRACE") != nullptr;  // per sub-round counts on stderr
 
     // --- schedule: nodes grouped by (colour, degree bucket), ascending ids
     const int32_t ncat = nsub * kNB;
@@ -857,8 +1047,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
 
     // --- hub plans per colour
     std::vector<HubPlan> plans(nsub);
-    int64_t max_table = 0;
-    int32_t max_tch = 0, max_hubs = 0;
+    int64_t max_region = 0, max_over = 0, max_table = 0, max_win = 0, max_hub_ints = 0;
     for (int32_t sc = 0; sc < nsub; ++sc) {
         const int32_t cat = sc * kNB + kHubBucket;
         const int32_t H = static_cast<int32_t>(cnt[cat]);
@@ -879,16 +1068,29 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
             xs[h] = rows[2 * h];
             hd[h] = rows[2 * h + 1];
         }
-        std::vector<int64_t> toff(H);
+        std::vector<int32_t> plog(H), pbase(H + 1), cap(H), tfirst(H + 1), chub, phub, thub;
+        std::vector<int64_t> rbase(H), obase(H), toff(H), cbeg, tbeg;
         std::vector<uint32_t> tmask(H);
-        std::vector<int32_t> tfirst(H + 1), chub, thub;
-        std::vector<int64_t> cbeg, tbeg;
-        int64_t tot = 0;
-        int32_t ntc = 0;
+        int64_t rtot = 0, otot = 0, ttot = 0;
+        int32_t np = 0, ntc = 0;
         for (int32_t h = 0; h < H; ++h) {
+            // about 2048 entries per label partition, at most 1024 partitions
+            int32_t lg = 0;
+            while (lg < kMaxPartLog && (static_cast<int64_t>(2048) << lg) < hd[h]) ++lg;
+            plog[h] = lg;
+            const int64_t per = (hd[h] + (1LL << lg) - 1) >> lg;
+            cap[h] = static_cast<int32_t>(std::min<int64_t>(2 * per + 64, hd[h]));
+            if (tune.hub_region_cap > 0) cap[h] = std::min(cap[h], tune.hub_region_cap);
+            pbase[h] = np;
+            for (int32_t p = 0; p < (1 << lg); ++p) phub.push_back(h);
+            np += 1 << lg;
+            rbase[h] = rtot;
+            rtot += static_cast<int64_t>(cap[h]) << lg;
+            obase[h] = otot;
+            otot += hd[h];
             uint64_t tsz = 1;
             while (tsz < 2 * static_cast<uint64_t>(hd[h])) tsz <<= 1;
-            toff[h] = tot;
+            toff[h] = ttot;
             tmask[h] = static_cast<uint32_t>(tsz - 1);
             for (int64_t sl = 0; sl < hd[h]; sl += kHubChunk) {
                 chub.push_back(h);
@@ -897,24 +1099,26 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
             tfirst[h] = ntc;
             for (int64_t e = 0; e < static_cast<int64_t>(tsz); e += kHubTChunk) {
                 thub.push_back(h);
-                tbeg.push_back(tot + e);
+                tbeg.push_back(ttot + e);
                 ++ntc;
             }
-            tot += static_cast<int64_t>(tsz);
+            ttot += static_cast<int64_t>(tsz);
         }
+        pbase[H] = np;
         tfirst[H] = ntc;
         P.nchunks = static_cast<int32_t>(chub.size());
+        P.nparts = np;
         P.ntchunks = ntc;
-        P.table_entries = tot;
+        P.region_entries = rtot;
+        P.overflow_entries = otot;
+        P.table_entries = ttot;
+        // table-chunk winners are stored after the partition winners
+        for (int32_t h = 0; h <= H; ++h) tfirst[h] += np;
         std::vector<int32_t> i32;
-        i32.insert(i32.end(), hn.begin(), hn.end());
-        i32.insert(i32.end(), tfirst.begin(), tfirst.end());
-        i32.insert(i32.end(), chub.begin(), chub.end());
-        i32.insert(i32.end(), thub.begin(), thub.end());
+        for (const auto* vec : {&hn, &plog, &pbase, &cap, &tfirst, &chub, &phub, &thub})
+            i32.insert(i32.end(), vec->begin(), vec->end());
         std::vector<int64_t> i64;
-        i64.insert(i64.end(), toff.begin(), toff.end());
-        i64.insert(i64.end(), cbeg.begin(), cbeg.end());
-        i64.insert(i64.end(), tbeg.begin(), tbeg.end());
+        for (const auto* vec : {&rbase, &obase, &toff, &cbeg, &tbeg}) i64.insert(i64.end(), vec->begin(), vec->end());
         P.i32.alloc(i32.size(), s);
         P.i64.alloc(i64.size(), s);
         P.u32.alloc(tmask.size(), s);
@@ -922,19 +1126,25 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
         HIPCHK(hipMemcpyAsync(P.i64.get(), i64.data(), i64.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(P.u32.get(), tmask.data(), tmask.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
         HIPCHK(hipStreamSynchronize(s));  // host vectors go out of scope
-        max_table = std::max(max_table, tot);
-        max_tch = std::max(max_tch, ntc);
-        max_hubs = std::max(max_hubs, H);
+        max_region = std::max(max_region, rtot);
+        max_over = std::max(max_over, otot);
+        max_table = std::max(max_table, ttot);
+        max_win = std::max(max_win, static_cast<int64_t>(np) + ntc);
+        max_hub_ints = std::max(max_hub_ints, static_cast<int64_t>(np) + 3 * static_cast<int64_t>(H));
     }
-    DBuf<int32_t> gkeys, gvals, hub_own, p_conn, p_x;
-    DBuf<uint64_t> p_tie;
-    if (max_table > 0) {
+    DBuf<int32_t> ekeys, evals, okeys, ovals, gkeys, gvals, hub_ints, w_conn, w_x;
+    DBuf<uint64_t> w_tie;
+    if (max_win > 0) {
+        ekeys.alloc(max_region, s);
+        evals.alloc(max_region, s);
+        okeys.alloc(max_over, s);
+        ovals.alloc(max_over, s);
         gkeys.alloc(max_table, s);
         gvals.alloc(max_table, s);
-        hub_own.alloc(max_hubs, s);
-        p_conn.alloc(max_tch, s);
-        p_x.alloc(max_tch, s);
-        p_tie.alloc(max_tch, s);
+        hub_ints.alloc(max_hub_ints, s);
+        w_conn.alloc(max_win, s);
+        w_x.alloc(max_win, s);
+        w_tie.alloc(max_win, s);
     }
 
     // --- per-entry candidate buffers: at most the nodes of one colour
@@ -1014,40 +1224,67 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
             }
             const HubPlan& P = plans[sc];
             if (P.count > 0) {
+                const int32_t Hn = P.count;
                 HubArgs H;
-                H.hub_nodes = P.i32.get();
-                H.hub_tfirst = P.i32.get() + P.count;
-                H.chunk_hub = P.i32.get() + 2 * P.count + 1;
-                H.tchunk_hub = P.i32.get() + 2 * P.count + 1 + P.nchunks;
-                H.hub_toff = P.i64.get();
-                H.chunk_begin = P.i64.get() + P.count;
-                H.tchunk_begin = P.i64.get() + P.count + P.nchunks;
+                const int32_t* i32 = P.i32.get();
+                H.hub_nodes = i32;
+                H.hub_plog = i32 + Hn;
+                H.hub_pbase = i32 + 2 * Hn;
+                H.hub_cap = i32 + 3 * Hn + 1;
+                const int32_t* tfirst_shifted = i32 + 4 * Hn + 1;
+                H.hub_tfirst = tfirst_shifted;
+                H.chunk_hub = i32 + 5 * Hn + 2;
+                H.part_hub = H.chunk_hub + P.nchunks;
+                H.tchunk_hub = H.part_hub + P.nparts;
+                const int64_t* i64 = P.i64.get();
+                H.hub_rbase = i64;
+                H.hub_obase = i64 + Hn;
+                H.hub_toff = i64 + 2 * Hn;
+                H.chunk_begin = i64 + 3 * Hn;
+                H.tchunk_begin = H.chunk_begin + P.nchunks;
                 H.hub_tmask = P.u32.get();
+                H.rcount = hub_ints.get();
+                H.ocount = H.rcount + P.nparts;
+                H.big = H.ocount + Hn;
+                H.hub_own = H.big + Hn;
+                H.ekeys = ekeys.get();
+                H.evals = evals.get();
+                H.okeys = okeys.get();
+                H.ovals = ovals.get();
                 H.gkeys = gkeys.get();
                 H.gvals = gvals.get();
-                H.hub_own = hub_own.get();
-                H.p_conn = p_conn.get();
-                H.p_tie = p_tie.get();
-                H.p_x = p_x.get();
-                fill_i32(gkeys.get(), -1, P.table_entries, s);
-                fill_i32(gvals.get(), 0, P.table_entries, s);
-                fill_i32(hub_own.get(), 0, P.count, s);
+                H.w_conn = w_conn.get();
+                H.w_tie = w_tie.get();
+                H.w_x = w_x.get();
+                H.part_limit = std::max(1, std::min(tune.hub_part_limit, kPartTable / 2));
+                fill_i32(H.rcount, 0, static_cast<int64_t>(P.nparts) + 3 * Hn, s);
                 A.nodes = H.hub_nodes;
-                A.count = P.count;
+                A.count = Hn;
                 A.ct = ct.get() + (off[c0 + kHubBucket] - off[c0]);
                 A.cg = cg.get() + (off[c0 + kHubBucket] - off[c0]);
                 {
-                    ProfScope ps("lp_eval_hub_insert", eval_bytes(P.count, cslots[c0 + kHubBucket]), s);
-                    hub_insert_kernel<<<P.nchunks, kBlockThreads, 0, s>>>(A, H);
+                    ProfScope ps("lp_eval_hub_chunk", eval_bytes(Hn, cslots[c0 + kHubBucket]), s);
+                    hub_chunk_kernel<<<P.nchunks, kHubThreads, 0, s>>>(A, H);
                     LAUNCHCHK();
                 }
                 {
-                    ProfScope ps("lp_eval_hub_scan", 8.0 * static_cast<double>(P.table_entries), s);
-                    hub_scan_kernel<<<P.ntchunks, 256, 0, s>>>(A, H);
+                    ProfScope ps("lp_eval_hub_part", 0, s);
+                    hub_part_kernel<<<P.nparts, kPartThreads, 0, s>>>(A, H);
+                    LAUNCHCHK();
+                    hub_finish_kernel<<<Hn, 64, 0, s>>>(A, H);
                     LAUNCHCHK();
                 }
-                hub_finish_kernel<<<P.count, 64, 0, s>>>(A, H);
-                LAUNCHCHK();
+                {
+                    ProfScope ps("lp_eval_hub_table", 0, s);
+                    hub_clear_kernel<<<P.ntchunks, 256, 0, s>>>(H);
+                    LAUNCHCHK();
+                    hub_table_insert_kernel<<<P.nparts, 256, 0, s>>>(H);
+                    LAUNCHCHK();
+                    hub_scan_kernel<<<P.ntchunks, 256, 0, s>>>(A, H, P.nparts);
+                    LAUNCHCHK();
+                    hub_big_finish_kernel<<<Hn, 64, 0, s>>>(A, H, tfirst_shifted);
+                    LAUNCHCHK();
+                }
             }
             // per-target candidate weight, then admission (fast path)
             {
@@ -1068,6 +1305,10 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
             if (profiler().on) profiler().collect();
             const uint32_t ncand = hctr->ncand;
             const uint32_t m = hctr->nslow;
+            if (trace)
+                fprintf(stderr, "[sclap] %s L%d r%d s%d n=%lld cand=%u slow=%u gain=[%d,%d] hubs=%d hub_slots=%llu\n",
+                        phase == kRefine ? "refine" : "cluster", level, r, sc, static_cast<long long>(ccount), ncand,
+                        m, m ? hctr->gmin : 0, m ? hctr->gmax : 0, plans[sc].count, cslots[c0 + kHubBucket]);
             if (m > 0) {
                 // slow path: sort candidates of overflowing targets by
                 // (target, gain desc, node asc) and admit the prefix that fits

@@ -21,6 +21,8 @@ struct LPTuning {
     int32_t lane_max = 16;    // <= 16
     int32_t wave_max = 256;   // <= 256
     int32_t block_max = 8192; // <= 8192
+    int32_t hub_part_limit = 4096;  // <= 4096; larger hub partitions use the HBM table
+    int32_t hub_region_cap = 0;     // 0: about twice a partition's expected share
 };
 
 struct LPResult {

@@ -62,7 +62,11 @@ GRAPHS = {
 
 # small thresholds push rows into the wave, workgroup and hub paths
 KNOBS = [dict(), dict(lane_max_degree=2, wave_max_degree=8, block_max_degree=24),
-         dict(lane_max_degree=16, wave_max_degree=256, block_max_degree=300)]
+         dict(lane_max_degree=16, wave_max_degree=256, block_max_degree=300),
+         # hub partitions summed through the HBM table / regions spilling to overflow
+         dict(lane_max_degree=2, wave_max_degree=8, block_max_degree=24, hub_part_limit=1),
+         dict(lane_max_degree=2, wave_max_degree=8, block_max_degree=40, hub_region_cap=3),
+         dict(block_max_degree=60, hub_part_limit=5, hub_region_cap=2)]
 
 
 # ------------------------------------------------------------ hand-worked
@@ -117,9 +121,13 @@ def test_cluster_parity(sc, gname, knobs):
         assert np.array_equal(lab.cpu().numpy(), ref)
 
 
+REFINE_KNOBS = [dict(block_max_degree=40), dict(block_max_degree=30, hub_part_limit=1, hub_region_cap=2)]
+
+
 @pytest.mark.parametrize("gname", list(GRAPHS))
 @pytest.mark.parametrize("k", [2, 5, 64])
-def test_refine_parity(sc, gname, k):
+@pytest.mark.parametrize("knobs", range(len(REFINE_KNOBS)))
+def test_refine_parity(sc, gname, k, knobs):
     g = GRAPHS[gname]()
     d = dev(sc, g)
     cV = int(g["vwgt"].sum()) if g.get("vwgt") is not None else g["n"]
@@ -129,9 +137,9 @@ def test_refine_parity(sc, gname, k):
         p0 = rng.integers(0, k, size=g["n"]).astype(np.int32)
         if k == 2:
             p0[: g["n"] * 3 // 4] = 0  # start overloaded
-        say("refine", gname, "k=%d eps=%g" % (k, eps))
+        say("refine", gname, "k=%d eps=%g" % (k, eps), REFINE_KNOBS[knobs])
         part = torch.tensor(p0, device="cuda")
-        _, rr = sc.refine_dev(d, k, Lmax, part, rounds=8, seed=3, level=1, block_max_degree=40)
+        _, rr = sc.refine_dev(d, k, Lmax, part, rounds=8, seed=3, level=1, **REFINE_KNOBS[knobs])
         ref, rr_ref, _ = oracle.refine(g, k, Lmax, p0, rounds=8, seed=3, level=1)
         assert rr == rr_ref
         assert np.array_equal(part.cpu().numpy(), ref)
