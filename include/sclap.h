@@ -94,7 +94,8 @@ typedef struct {
     int32_t block_max_degree; /* up to this: one workgroup per node, LDS table; above: hub path */
     int32_t hub_part_limit;   /* hub label partitions summed in LDS up to this many entries */
     int32_t hub_region_cap;   /* entries a hub partition keeps before spilling to its overflow list */
-    int32_t reserved[3];
+    int32_t select_small_max; /* overflowing targets with more candidates: multi-workgroup selection */
+    int32_t reserved[2];
 } sclap_options;
 
 #define SCLAP_MAX_LEVELS 64

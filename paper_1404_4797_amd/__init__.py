@@ -62,7 +62,8 @@ class Options(ctypes.Structure):
                 ("validate", ctypes.c_int32), ("color_override", ctypes.c_void_p),
                 ("lane_max_degree", ctypes.c_int32), ("wave_max_degree", ctypes.c_int32),
                 ("block_max_degree", ctypes.c_int32), ("hub_part_limit", ctypes.c_int32),
-                ("hub_region_cap", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("hub_region_cap", ctypes.c_int32), ("select_small_max", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class KernelStat(ctypes.Structure):

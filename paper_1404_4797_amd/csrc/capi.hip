@@ -94,6 +94,7 @@ Opts resolve(const sclap_options* o) {
     if (o->block_max_degree > 0) r.tune.block_max = o->block_max_degree;
     if (o->hub_part_limit > 0) r.tune.hub_part_limit = o->hub_part_limit;
     if (o->hub_region_cap > 0) r.tune.hub_region_cap = o->hub_region_cap;
+    if (o->select_small_max > 0) r.tune.select_small_max = o->select_small_max;
     if (r.coarsen_rounds < 0 || r.refine_rounds < 0) fail(SCLAP_ERR_INVALID, "round counts must be >= 0");
     if (r.nsub < 1 || r.nsub > 16) fail(SCLAP_ERR_INVALID, "subrounds must be in 1..16");
     if (r.divisor < 1) fail(SCLAP_ERR_INVALID, "cluster_divisor must be >= 1");

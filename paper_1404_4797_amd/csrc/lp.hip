@@ -53,14 +53,21 @@ constexpr int kHubChunk = kBlockMaxDeg;  // slots per hub workgroup (table load 
 constexpr int kHubTChunk = 4096;         // HBM table entries per scan workgroup
 constexpr int kSmallLabels = 4096;       // LDS-private histograms up to this many labels
 constexpr int kMaxBlocks = 1024;         // grid cap of the grid-stride candidate kernels
+constexpr int kSmallSeg = 4096;          // segments up to this length: one selecting workgroup
+constexpr int kSegChunk = 4096;          // entries per workgroup in the multi-workgroup selection
 
 struct Counters {
-    uint32_t ncand;
-    uint32_t nslow;
-    int32_t gmin;
+    uint32_t ncand;        // candidates of the sub-round
+    uint32_t nslow;        // candidates aimed at targets that cannot take them all
+    int32_t gmin;          // gain range of those candidates
     int32_t gmax;
     uint32_t bad_color;
-    uint32_t pad[3];
+    uint32_t nseg;         // targets that cannot take all their candidates
+    uint32_t slow_total;   // entries reserved in their segments
+    uint32_t round_cands;  // candidates of the round so far
+    uint32_t nlarge;       // segments longer than kSmallSeg
+    uint32_t nlchunks;     // kSegChunk-entry chunks of those segments
+    uint32_t pad[2];
 };
 
 struct EvalArgs {
@@ -695,35 +702,83 @@ __device__ __forceinline__ int32_t block_sum_i32(int32_t v) {
 
 // ------------------------------------------------- candidates and admission
 
-// tsum[t] += c(v) over the candidates of the sub-round; counts them.
+// Block-local LDS index of label t: t itself for small label spaces, else an
+// open-addressing slot (kAggTable entries, at most kAggChunk keys per chunk,
+// so the table is never more than half full).
+constexpr int kAggChunk = 2048;
+constexpr int kAggTable = 4096;
+
+template <bool kSmall>
+__device__ __forceinline__ int32_t agg_slot(int32_t* keys, int32_t t, bool insert) {
+    if (kSmall) return t;
+    uint32_t h = slot_hash(static_cast<uint32_t>(t)) & (kAggTable - 1);
+    while (true) {
+        const int32_t k = insert ? atomicCAS(&keys[h], -1, t) : keys[h];
+        if (k == t || (insert && k == -1)) return static_cast<int32_t>(h);
+        h = (h + 1) & (kAggTable - 1);
+    }
+}
+
+// tsum[t] += c(v) and cnt[t] += 1 over the candidates of the sub-round, summed
+// per block in LDS first so that a label many nodes aim at (a hub's cluster)
+// costs one global atomic per block and chunk, not one per candidate.
 template <bool kSmall>
 __global__ void __launch_bounds__(256) cand_accum_kernel(const int32_t* __restrict__ ct,
                                                          const int32_t* __restrict__ nodes, int32_t count,
                                                          const int32_t* __restrict__ vw, int32_t* __restrict__ tsum,
-                                                         int32_t nw, Counters* ctr) {
-    __shared__ int32_t loc[kSmall ? kSmallLabels : 1];
-    if (kSmall) {
-        for (int j = threadIdx.x; j < nw; j += 256) loc[j] = 0;
-        __syncthreads();
+                                                         int32_t* __restrict__ cnt, int32_t nw, Counters* ctr) {
+    constexpr int kSlots = kSmall ? kSmallLabels : kAggTable;
+    __shared__ int32_t keys[kSmall ? 1 : kAggTable];
+    __shared__ int32_t lsum[kSlots];
+    __shared__ int32_t lcnt[kSlots];
+    const int32_t nslots = kSmall ? nw : kAggTable;
+    for (int j = threadIdx.x; j < nslots; j += 256) {
+        if (!kSmall) keys[j] = -1;
+        lsum[j] = 0;
+        lcnt[j] = 0;
     }
+    __syncthreads();
     int32_t found = 0;
-    for (int32_t p = blockIdx.x * 256 + threadIdx.x; p < count; p += gridDim.x * 256) {
-        const int32_t t = ct[p];
-        if (t < 0) continue;
-        ++found;
-        const int32_t c = vw ? vw[nodes[p]] : 1;
-        if (c) {
-            if (kSmall) atomicAdd(&loc[t], c);
-            else atomicAdd(&tsum[t], c);
+    for (int64_t base = static_cast<int64_t>(blockIdx.x) * kAggChunk; base < count;
+         base += static_cast<int64_t>(gridDim.x) * kAggChunk) {
+        for (int r = 0; r < kAggChunk / 256; ++r) {
+            const int64_t p = base + r * 256 + threadIdx.x;
+            if (p >= count) continue;
+            const int32_t t = ct[p];
+            if (t < 0) continue;
+            ++found;
+            const int32_t c = vw ? vw[nodes[p]] : 1;
+            const int32_t i = agg_slot<kSmall>(keys, t, true);
+            if (c) atomicAdd(&lsum[i], c);
+            atomicAdd(&lcnt[i], 1);
+        }
+        if (!kSmall) {  // flush this chunk's labels
+            __syncthreads();
+            for (int j = threadIdx.x; j < kAggTable; j += 256) {
+                const int32_t t = keys[j];
+                if (t >= 0) {
+                    if (lsum[j]) atomicAdd(&tsum[t], lsum[j]);
+                    atomicAdd(&cnt[t], lcnt[j]);
+                    keys[j] = -1;
+                    lsum[j] = 0;
+                    lcnt[j] = 0;
+                }
+            }
+            __syncthreads();
         }
     }
     if (kSmall) {
         __syncthreads();
-        for (int j = threadIdx.x; j < nw; j += 256)
-            if (loc[j]) atomicAdd(&tsum[j], loc[j]);
+        for (int j = threadIdx.x; j < nw; j += 256) {
+            if (lsum[j]) atomicAdd(&tsum[j], lsum[j]);
+            if (lcnt[j]) atomicAdd(&cnt[j], lcnt[j]);
+        }
     }
     const int32_t tot = block_sum_i32(found);
-    if (threadIdx.x == 0 && tot) atomicAdd(&ctr->ncand, static_cast<uint32_t>(tot));
+    if (threadIdx.x == 0 && tot) {
+        atomicAdd(&ctr->ncand, static_cast<uint32_t>(tot));
+        atomicAdd(&ctr->round_cands, static_cast<uint32_t>(tot));
+    }
 }
 
 // Fast path of admission: if everything aimed at t fits, admit it all;
@@ -776,57 +831,311 @@ __global__ void __launch_bounds__(256) admit_kernel(const int32_t* __restrict__ 
     }
 }
 
-// key = [t][gmax - gain][v] packed into the low bits; value = schedule entry.
-__global__ void slow_keys_kernel(const uint32_t* __restrict__ slow_idx, uint32_t m, const int32_t* __restrict__ nodes,
-                                 const int32_t* __restrict__ ct, const int32_t* __restrict__ cg, int32_t gmax,
-                                 int bits_v, int shift_t, int with_t, uint64_t* __restrict__ keys,
-                                 uint32_t* __restrict__ vals) {
-    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= m) return;
-    const uint32_t p = slow_idx[j];
-    uint64_t k = (static_cast<uint64_t>(static_cast<int64_t>(gmax) - cg[p]) << bits_v) |
-                 static_cast<uint64_t>(static_cast<uint32_t>(nodes[p]));
-    if (with_t) k |= static_cast<uint64_t>(static_cast<uint32_t>(ct[p])) << shift_t;
-    keys[j] = k;
-    vals[j] = p;
+// A target that cannot take all its candidates gets a segment of cnt[t]
+// entries (small label spaces: one thread per label).
+__global__ void __launch_bounds__(256) claim_small_kernel(int32_t nw, const int32_t* __restrict__ w,
+                                                          const int32_t* __restrict__ tsum,
+                                                          const int32_t* __restrict__ cnt, int64_t bound,
+                                                          int32_t* __restrict__ seg_off, int32_t* __restrict__ seg_list,
+                                                          int32_t* __restrict__ large_list, int32_t small_max,
+                                                          Counters* ctr) {
+    const int32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= nw || cnt[t] == 0 || static_cast<int64_t>(w[t]) + tsum[t] <= bound) return;
+    seg_off[t] = static_cast<int32_t>(atomicAdd(&ctr->slow_total, static_cast<uint32_t>(cnt[t])));
+    seg_list[atomicAdd(&ctr->nseg, 1u)] = t;
+    if (cnt[t] > small_max) large_list[atomicAdd(&ctr->nlarge, 1u)] = t;
 }
 
-__global__ void slow_keys_t_kernel(const uint32_t* __restrict__ vals, uint32_t m, const int32_t* __restrict__ ct,
-                                   uint64_t* __restrict__ keys) {
-    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= m) return;
-    keys[j] = static_cast<uint64_t>(static_cast<uint32_t>(ct[vals[j]]));
+// Same for large label spaces: the first slow candidate of a target claims;
+// each block tries a label once per chunk.
+__global__ void __launch_bounds__(256) claim_big_kernel(const uint32_t* __restrict__ slow_idx,
+                                                        const int32_t* __restrict__ ct, const int32_t* __restrict__ cnt,
+                                                        int32_t* __restrict__ seg_off, int32_t* __restrict__ seg_list,
+                                                        int32_t* __restrict__ large_list, int32_t small_max,
+                                                        Counters* ctr) {
+    __shared__ int32_t keys[kAggTable];
+    for (int j = threadIdx.x; j < kAggTable; j += 256) keys[j] = -1;
+    __syncthreads();
+    const uint32_t m = ctr->nslow;
+    for (uint32_t base = blockIdx.x * kAggChunk; base < m; base += gridDim.x * kAggChunk) {
+        for (int r = 0; r < kAggChunk / 256; ++r) {
+            const uint32_t j = base + r * 256 + threadIdx.x;
+            if (j >= m) continue;
+            const int32_t t = ct[slow_idx[j]];
+            uint32_t h = slot_hash(static_cast<uint32_t>(t)) & (kAggTable - 1);
+            bool fresh = false;
+            while (true) {
+                const int32_t k = atomicCAS(&keys[h], -1, t);
+                if (k == -1) fresh = true;
+                if (k == -1 || k == t) break;
+                h = (h + 1) & (kAggTable - 1);
+            }
+            if (!fresh || seg_off[t] != -1 || atomicCAS(&seg_off[t], -1, -2) != -1) continue;
+            seg_off[t] = static_cast<int32_t>(atomicAdd(&ctr->slow_total, static_cast<uint32_t>(cnt[t])));
+            seg_list[atomicAdd(&ctr->nseg, 1u)] = t;
+            if (cnt[t] > small_max) large_list[atomicAdd(&ctr->nlarge, 1u)] = t;
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < kAggTable; j += 256) keys[j] = -1;
+        __syncthreads();
+    }
 }
 
-__global__ void slow_gather_kernel(const uint32_t* __restrict__ vals, uint32_t m, const int32_t* __restrict__ nodes,
-                                   const int32_t* __restrict__ ct, const int32_t* __restrict__ vw,
-                                   int64_t* __restrict__ csum, int32_t* __restrict__ head) {
-    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= m) return;
-    const uint32_t p = vals[j];
-    csum[j] = vw ? vw[nodes[p]] : 1;
-    head[j] = (j == 0 || ct[vals[j - 1]] != ct[p]) ? static_cast<int32_t>(j) : 0;
+// Writes every slow candidate into its target's segment as the key
+// [gmax - gain][node] (ascending key = gain desc, node asc), with its weight.
+// Space is reserved once per label per block chunk.
+template <bool kSmall>
+__global__ void __launch_bounds__(256) scatter_kernel(const uint32_t* __restrict__ slow_idx,
+                                                      const int32_t* __restrict__ nodes, const int32_t* __restrict__ ct,
+                                                      const int32_t* __restrict__ cg, const int32_t* __restrict__ vw,
+                                                      int bits_v, int32_t nw, const int32_t* __restrict__ seg_off,
+                                                      int32_t* __restrict__ seg_fill, uint64_t* __restrict__ skey,
+                                                      uint32_t* __restrict__ spos, int32_t* __restrict__ swt,
+                                                      const Counters* ctr) {
+    constexpr int kSlots = kSmall ? kSmallLabels : kAggTable;
+    __shared__ int32_t keys[kSmall ? 1 : kAggTable];
+    __shared__ int32_t lcnt[kSlots];
+    __shared__ int32_t lbase[kSlots];
+    const int32_t nslots = kSmall ? nw : kAggTable;
+    const uint32_t m = ctr->nslow;
+    const int32_t gmax = ctr->gmax;
+    for (int j = threadIdx.x; j < nslots; j += 256) {
+        if (!kSmall) keys[j] = -1;
+        lcnt[j] = 0;
+    }
+    __syncthreads();
+    for (uint32_t base = blockIdx.x * kAggChunk; base < m; base += gridDim.x * kAggChunk) {
+        for (int r = 0; r < kAggChunk / 256; ++r) {
+            const uint32_t j = base + r * 256 + threadIdx.x;
+            if (j < m) atomicAdd(&lcnt[agg_slot<kSmall>(keys, ct[slow_idx[j]], true)], 1);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < nslots; i += 256) {
+            const int32_t t = kSmall ? i : keys[i];
+            lbase[i] = (t >= 0 && lcnt[i]) ? atomicAdd(&seg_fill[t], lcnt[i]) : 0;
+            lcnt[i] = 0;
+        }
+        __syncthreads();
+        for (int r = 0; r < kAggChunk / 256; ++r) {
+            const uint32_t j = base + r * 256 + threadIdx.x;
+            if (j >= m) continue;
+            const uint32_t p = slow_idx[j];
+            const int32_t t = ct[p];
+            const int32_t v = nodes[p];
+            const int32_t i = agg_slot<kSmall>(keys, t, false);
+            const int32_t at = seg_off[t] + lbase[i] + atomicAdd(&lcnt[i], 1);
+            skey[at] = (static_cast<uint64_t>(static_cast<int64_t>(gmax) - cg[p]) << bits_v) |
+                       static_cast<uint64_t>(static_cast<uint32_t>(v));
+            spos[at] = p;
+            swt[at] = vw ? vw[v] : 1;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < nslots; i += 256) {
+            if (!kSmall) keys[i] = -1;
+            lcnt[i] = 0;
+        }
+        __syncthreads();
+    }
 }
 
-// Sorted by (target, gain desc, node asc): admit while the running weight of
-// the target's candidates keeps it within the bound (node weights are >= 0,
-// so the admitted set is a prefix).
-__global__ void slow_admit_kernel(const uint32_t* __restrict__ vals, uint32_t m, const int32_t* __restrict__ ct,
-                                  const int32_t* __restrict__ w, const int64_t* __restrict__ psum,
-                                  const int32_t* __restrict__ segstart, int64_t bound, uint8_t* __restrict__ ok) {
-    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= m) return;
-    const uint32_t p = vals[j];
-    const int32_t s0 = segstart[j];
-    const int64_t pre = psum[j] - (s0 > 0 ? psum[s0 - 1] : 0);
-    ok[p] = (static_cast<int64_t>(w[ct[p]]) + pre <= bound) ? 1 : 0;
+__device__ __forceinline__ int bits_of(uint64_t x) { return x ? 64 - __clzll(static_cast<long long>(x)) : 0; }
+
+// One workgroup per overflowing target (grid-stride over the segments):
+// finds the smallest key whose inclusive weight prefix, in key order, exceeds
+// the target's room bound - w(t), by a most-significant-digit-first radix
+// selection on weight histograms; every candidate with a smaller key is
+// admitted (node weights are >= 0, so that is exactly the admitted prefix).
+__global__ void __launch_bounds__(256) select_kernel(const int32_t* __restrict__ seg_list,
+                                                     int32_t* __restrict__ seg_off, int32_t* __restrict__ seg_fill,
+                                                     const int32_t* __restrict__ cnt, const int32_t* __restrict__ w,
+                                                     int64_t bound, int bits_v, const uint64_t* __restrict__ skey,
+                                                     const uint32_t* __restrict__ spos,
+                                                     const int32_t* __restrict__ swt, uint8_t* __restrict__ ok,
+                                                     int32_t small_max, const Counters* ctr) {
+    __shared__ unsigned long long hist[256];
+    __shared__ uint64_t s_prefix, s_mask;
+    __shared__ int64_t s_room;
+    const uint32_t nseg = ctr->nseg;
+    const int total_bits = bits_of(static_cast<uint64_t>(static_cast<int64_t>(ctr->gmax) - ctr->gmin)) + bits_v;
+    const int passes = total_bits > 0 ? (total_bits + 7) / 8 : 1;
+    for (uint32_t sid = blockIdx.x; sid < nseg; sid += gridDim.x) {
+        const int32_t t = seg_list[sid];
+        const int32_t base = seg_off[t];
+        const int32_t len = cnt[t];
+        if (len > small_max) continue;  // selected by the multi-workgroup kernels
+        if (threadIdx.x == 0) {
+            s_prefix = 0;
+            s_mask = 0;
+            s_room = bound - static_cast<int64_t>(w[t]);
+        }
+        __syncthreads();
+        for (int pass = passes - 1; pass >= 0; --pass) {
+            const int shift = 8 * pass;
+            hist[threadIdx.x] = 0;
+            __syncthreads();
+            const uint64_t prefix = s_prefix, pmask = s_mask;
+            for (int32_t i = threadIdx.x; i < len; i += 256) {
+                const uint64_t k = skey[base + i];
+                const int32_t c = swt[base + i];
+                if ((k & pmask) == prefix && c) atomicAdd(&hist[(k >> shift) & 255], static_cast<unsigned long long>(c));
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                // boundary digit: the first whose cumulative weight exceeds the room
+                int64_t run = 0, room = s_room;
+                int d = 0;
+                for (; d < 255; ++d) {
+                    if (run + static_cast<int64_t>(hist[d]) > room) break;
+                    run += static_cast<int64_t>(hist[d]);
+                }
+                s_room = room - run;
+                s_prefix = prefix | (static_cast<uint64_t>(d) << shift);
+                s_mask = pmask | (255ULL << shift);
+            }
+            __syncthreads();
+        }
+        const uint64_t boundary = s_prefix;  // smallest key that does not fit
+        for (int32_t i = threadIdx.x; i < len; i += 256) ok[spos[base + i]] = skey[base + i] < boundary ? 1 : 0;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            seg_off[t] = -1;
+            seg_fill[t] = 0;
+        }
+    }
+}
+
+// Multi-workgroup selection for segments longer than kSmallSeg: the same
+// most-significant-digit-first selection, with per-segment histograms in HBM.
+struct LargeSel {
+    int32_t* large_list;    // [nlarge] target of each large segment
+    int32_t* chunk_first;   // [nlarge+1] first chunk of each large segment
+    uint32_t* hist;         // [nlarge][256] weight per digit
+    uint64_t* prefix;       // [nlarge] digits fixed so far
+    int64_t* room;          // [nlarge] weight still admissible below the prefix
+    uint32_t* done;         // blocks finished with the current digit
+};
+
+__global__ void large_setup_kernel(LargeSel L, const int32_t* __restrict__ cnt, const int32_t* __restrict__ w,
+                                   int64_t bound, Counters* ctr) {
+    // one thread: chunk prefix over the large segments (their number is small)
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int32_t run = 0;
+    for (uint32_t l = 0; l < ctr->nlarge; ++l) {
+        const int32_t t = L.large_list[l];
+        L.chunk_first[l] = run;
+        run += (cnt[t] + kSegChunk - 1) / kSegChunk;
+        L.prefix[l] = 0;
+        L.room[l] = bound - static_cast<int64_t>(w[t]);
+    }
+    L.chunk_first[ctr->nlarge] = run;
+    ctr->nlchunks = static_cast<uint32_t>(run);
+}
+
+__device__ __forceinline__ int32_t large_of_chunk(const LargeSel& L, uint32_t nlarge, int32_t c) {
+    int32_t lo = 0, hi = static_cast<int32_t>(nlarge);  // chunk_first[lo] <= c < chunk_first[hi]
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) / 2;
+        if (L.chunk_first[mid] <= c) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// One digit of the multi-workgroup selection: every block adds its chunks'
+// weight histograms to the segment histograms in HBM; the last block to
+// finish picks each segment's boundary digit (no block waits for another).
+__global__ void __launch_bounds__(256) large_pass_kernel(LargeSel L, int pass, int bits_v,
+                                                         const int32_t* __restrict__ seg_off,
+                                                         const int32_t* __restrict__ cnt,
+                                                         const uint64_t* __restrict__ skey,
+                                                         const int32_t* __restrict__ swt, Counters* ctr) {
+    __shared__ uint32_t h[256];
+    __shared__ int s_last;
+    const int total_bits = bits_of(static_cast<uint64_t>(static_cast<int64_t>(ctr->gmax) - ctr->gmin)) + bits_v;
+    const int passes = total_bits > 0 ? (total_bits + 7) / 8 : 1;
+    const uint32_t nlarge = ctr->nlarge;
+    if (pass >= passes || nlarge == 0) return;  // uniform over the grid
+    const int shift = 8 * pass;
+    const uint64_t above = pass + 1 >= 8 ? 0ULL : ~0ULL << (shift + 8);  // digits already fixed
+    const int32_t nch = static_cast<int32_t>(ctr->nlchunks);
+    for (int32_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        const int32_t l = large_of_chunk(L, nlarge, c);
+        const int32_t t = L.large_list[l];
+        const int32_t base = seg_off[t];
+        const int32_t len = cnt[t];
+        const int32_t i0 = (c - L.chunk_first[l]) * kSegChunk;
+        const int32_t i1 = i0 + kSegChunk < len ? i0 + kSegChunk : len;
+        const uint64_t prefix = L.prefix[l];
+        h[threadIdx.x] = 0;
+        __syncthreads();
+        for (int32_t i = i0 + threadIdx.x; i < i1; i += 256) {
+            const uint64_t k = skey[base + i];
+            const int32_t wt = swt[base + i];
+            if ((k & above) == prefix && wt) atomicAdd(&h[(k >> shift) & 255], static_cast<uint32_t>(wt));
+        }
+        __syncthreads();
+        if (h[threadIdx.x]) atomicAdd(&L.hist[static_cast<size_t>(l) * 256 + threadIdx.x], h[threadIdx.x]);
+        __syncthreads();
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(L.done, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    for (uint32_t l = threadIdx.x; l < nlarge; l += 256) {
+        uint32_t* hl = L.hist + static_cast<size_t>(l) * 256;
+        int64_t run = 0;
+        const int64_t room = L.room[l];
+        int d = 0;
+        for (; d < 255; ++d) {
+            const uint32_t hd = atomicOr(&hl[d], 0u);
+            if (run + static_cast<int64_t>(hd) > room) break;
+            run += hd;
+        }
+        L.room[l] = room - run;
+        L.prefix[l] |= static_cast<uint64_t>(d) << shift;
+        for (int j = 0; j < 256; ++j) hl[j] = 0;
+    }
+    if (threadIdx.x == 0) *L.done = 0;
+}
+
+__global__ void __launch_bounds__(256) large_admit_kernel(LargeSel L, int32_t* __restrict__ seg_off,
+                                                          int32_t* __restrict__ seg_fill,
+                                                          const int32_t* __restrict__ cnt,
+                                                          const uint64_t* __restrict__ skey,
+                                                          const uint32_t* __restrict__ spos,
+                                                          uint8_t* __restrict__ ok, const Counters* ctr) {
+    const uint32_t nlarge = ctr->nlarge;
+    const int32_t nch = static_cast<int32_t>(ctr->nlchunks);
+    for (int32_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        const int32_t l = large_of_chunk(L, nlarge, c);
+        const int32_t t = L.large_list[l];
+        const int32_t base = seg_off[t];
+        const int32_t len = cnt[t];
+        const int32_t i0 = (c - L.chunk_first[l]) * kSegChunk;
+        const int32_t i1 = i0 + kSegChunk < len ? i0 + kSegChunk : len;
+        const uint64_t boundary = L.prefix[l];  // smallest key that does not fit
+        for (int32_t i = i0 + threadIdx.x; i < i1; i += 256) ok[spos[base + i]] = skey[base + i] < boundary ? 1 : 0;
+    }
+}
+
+__global__ void large_reset_kernel(LargeSel L, int32_t* __restrict__ seg_off, int32_t* __restrict__ seg_fill,
+                                   const Counters* ctr) {
+    const uint32_t nlarge = ctr->nlarge;
+    for (uint32_t l = blockIdx.x * 256 + threadIdx.x; l < nlarge; l += gridDim.x * 256) {
+        const int32_t t = L.large_list[l];
+        seg_off[t] = -1;
+        seg_fill[t] = 0;
+    }
 }
 
 template <bool kSmall>
 __global__ void __launch_bounds__(256) apply_kernel(const int32_t* __restrict__ ct, const uint8_t* __restrict__ ok,
                                                     const int32_t* __restrict__ nodes, int32_t count,
                                                     const int32_t* __restrict__ vw, int32_t* __restrict__ label,
-                                                    int32_t* __restrict__ w, int32_t* __restrict__ tsum, int32_t nw) {
+                                                    int32_t* __restrict__ w, int32_t* __restrict__ tsum,
+                                                    int32_t* __restrict__ cnt, int32_t nw) {
     __shared__ int32_t delta[kSmall ? kSmallLabels : 1];
     if (kSmall) {
         for (int j = threadIdx.x; j < nw; j += 256) delta[j] = 0;
@@ -835,7 +1144,10 @@ __global__ void __launch_bounds__(256) apply_kernel(const int32_t* __restrict__ 
     for (int32_t p = blockIdx.x * 256 + threadIdx.x; p < count; p += gridDim.x * 256) {
         const int32_t t = ct[p];
         if (t < 0) continue;
-        if (!kSmall) tsum[t] = 0;
+        if (!kSmall) {
+            tsum[t] = 0;
+            cnt[t] = 0;
+        }
         if (!ok[p]) continue;
         const int32_t v = nodes[p];
         const int32_t a = label[v];
@@ -858,11 +1170,16 @@ __global__ void __launch_bounds__(256) apply_kernel(const int32_t* __restrict__ 
     }
 }
 
-__global__ void reset_counters_kernel(Counters* ctr) {
+__global__ void reset_counters_kernel(Counters* ctr, int round_too) {
     ctr->ncand = 0;
     ctr->nslow = 0;
     ctr->gmin = INT_MAX;
     ctr->gmax = INT_MIN;
+    ctr->nseg = 0;
+    ctr->slow_total = 0;
+    ctr->nlarge = 0;
+    ctr->nlchunks = 0;
+    if (round_too) ctr->round_cands = 0;
 }
 
 // --------------------------------------------------------------- schedule
@@ -1151,10 +1468,28 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     int64_t max_color = 0;
     for (int32_t sc = 0; sc < nsub; ++sc) max_color = std::max(max_color, off[(sc + 1) * kNB] - off[sc * kNB]);
     const int64_t cap = std::max<int64_t>(max_color, 1);
-    DBuf<int32_t> ct(cap, s), cg(cap, s), tsum(nw, s);
+    DBuf<int32_t> ct(cap, s), cg(cap, s), tsum(nw, s), tcnt(nw, s), seg_off(nw, s), seg_fill(nw, s);
+    DBuf<int32_t> seg_list(std::min<int64_t>(cap, nw), s), swt(cap, s);
     DBuf<uint8_t> ok(cap, s);
-    DBuf<uint32_t> slow_idx(cap, s);
+    DBuf<uint32_t> slow_idx(cap, s), spos(cap, s);
+    DBuf<uint64_t> skey(cap, s);
+    // multi-workgroup selection state: at most cap / kSmallSeg large segments
+    const int32_t small_max = std::max(1, std::min(tune.select_small_max, kSmallSeg));
+    const int64_t max_large = cap / small_max + 1;
+    DBuf<int32_t> large_list(max_large, s), chunk_first(max_large + 1, s);
+    DBuf<uint32_t> lhist(max_large * 256, s);
+    DBuf<uint64_t> lprefix(max_large, s);
+    DBuf<int64_t> lroom(max_large, s);
+    DBuf<uint32_t> ldone(1, s);
+    fill_u32(lhist.get(), 0, max_large * 256, s);
+    fill_u32(ldone.get(), 0, 1, s);
+    LargeSel LS{large_list.get(), chunk_first.get(), lhist.get(), lprefix.get(), lroom.get(), ldone.get()};
+    // digits of the selection key: node id bits plus at most 32 bits of gain range
+    const int max_sel_passes = (bits_for(static_cast<uint64_t>(n - 1)) + 32 + 7) / 8;
     fill_i32(tsum.get(), 0, nw, s);
+    fill_i32(tcnt.get(), 0, nw, s);
+    fill_i32(seg_off.get(), -1, nw, s);
+    fill_i32(seg_fill.get(), 0, nw, s);
 
     EvalArgs A;
     A.xadj = g.xadj;
@@ -1175,20 +1510,14 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     auto eval_bytes = [&](int64_t nodes_in, unsigned long long slots_in) {
         return node_bytes * static_cast<double>(nodes_in) + slot_bytes * static_cast<double>(slots_in);
     };
-    reset_counters_kernel<<<1, 1, 0, s>>>(ctr.get());
+    reset_counters_kernel<<<1, 1, 0, s>>>(ctr.get(), 1);
     LAUNCHCHK();
-    DBuf<uint64_t> sk, sk_tmp;
-    DBuf<uint32_t> sv_tmp;
-    DBuf<int64_t> psum;
-    DBuf<int32_t> heads;
     const int bits_v = bits_for(static_cast<uint64_t>(n - 1));
-    const int bits_t = bits_for(static_cast<uint64_t>(nw > 0 ? nw - 1 : 0));
 
     for (int32_t r = 0; r < rounds; ++r) {
         A.tp = hash_prefix({seed, 2, static_cast<uint64_t>(static_cast<uint32_t>(level)),
                             static_cast<uint64_t>(static_cast<uint32_t>(phase)),
                             static_cast<uint64_t>(static_cast<uint32_t>(r))});
-        int64_t round_cands = 0;
         for (int32_t sc = 0; sc < nsub; ++sc) {
             const int32_t c0 = sc * kNB;
             const int64_t ccount = off[c0 + kNB] - off[c0];
@@ -1286,80 +1615,94 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                     LAUNCHCHK();
                 }
             }
-            // per-target candidate weight, then admission (fast path)
+            // per-target candidate weight and count, then admission: targets
+            // that can take all their candidates admit them; the others
+            // select the admitted prefix on the device
             {
                 ProfScope ps("lp_admit", 0, s);
+                const unsigned gc = capped_grid(ccount);
                 if (small)
-                    cand_accum_kernel<true><<<capped_grid(ccount), 256, 0, s>>>(ct.get(), cnodes, ccount, g.vw,
-                                                                                tsum.get(), nw, ctr.get());
+                    cand_accum_kernel<true><<<gc, 256, 0, s>>>(ct.get(), cnodes, ccount, g.vw, tsum.get(), tcnt.get(),
+                                                               nw, ctr.get());
                 else
-                    cand_accum_kernel<false><<<capped_grid(ccount), 256, 0, s>>>(ct.get(), cnodes, ccount, g.vw,
-                                                                                 tsum.get(), nw, ctr.get());
+                    cand_accum_kernel<false><<<gc, 256, 0, s>>>(ct.get(), cnodes, ccount, g.vw, tsum.get(),
+                                                                tcnt.get(), nw, ctr.get());
                 LAUNCHCHK();
-                admit_kernel<<<capped_grid(ccount), 256, 0, s>>>(ct.get(), cg.get(), ccount, w, tsum.get(), bound,
-                                                                 ok.get(), slow_idx.get(), ctr.get());
+                admit_kernel<<<gc, 256, 0, s>>>(ct.get(), cg.get(), ccount, w, tsum.get(), bound, ok.get(),
+                                                slow_idx.get(), ctr.get());
                 LAUNCHCHK();
             }
-            HIPCHK(hipMemcpyAsync(hctr, ctr.get(), sizeof(Counters), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            if (profiler().on) profiler().collect();
-            const uint32_t ncand = hctr->ncand;
-            const uint32_t m = hctr->nslow;
-            if (trace)
-                fprintf(stderr, "[sclap] %s L%d r%d s%d n=%lld cand=%u slow=%u gain=[%d,%d] hubs=%d hub_slots=%llu\n",
-                        phase == kRefine ? "refine" : "cluster", level, r, sc, static_cast<long long>(ccount), ncand,
-                        m, m ? hctr->gmin : 0, m ? hctr->gmax : 0, plans[sc].count, cslots[c0 + kHubBucket]);
-            if (m > 0) {
-                // slow path: sort candidates of overflowing targets by
-                // (target, gain desc, node asc) and admit the prefix that fits
-                ProfScope ps("lp_admit_sorted", 0, s);
-                const int bits_g = bits_for(static_cast<uint64_t>(static_cast<int64_t>(hctr->gmax) - hctr->gmin));
-                const int low_bits = bits_g + bits_v;
-                const bool single = low_bits + bits_t <= 64;
-                sk.reserve(m, s);
-                sk_tmp.reserve(m, s);
-                sv_tmp.reserve(m, s);
-                psum.reserve(m, s);
-                heads.reserve(m, s);
-                uint32_t* sv = slow_idx.get();  // values, sorted in place
-                slow_keys_kernel<<<grid_for(m, 256), 256, 0, s>>>(slow_idx.get(), m, cnodes, ct.get(), cg.get(),
-                                                                  hctr->gmax, bits_v, low_bits, single ? 1 : 0,
-                                                                  sk.get(), sv);
-                LAUNCHCHK();
-                if (single) {
-                    radix_sort_pairs(sk.get(), sv, sk_tmp.get(), sv_tmp.get(), m, 0, low_bits + bits_t, rs, s);
-                } else {
-                    radix_sort_pairs(sk.get(), sv, sk_tmp.get(), sv_tmp.get(), m, 0, low_bits, rs, s);
-                    slow_keys_t_kernel<<<grid_for(m, 256), 256, 0, s>>>(sv, m, ct.get(), sk.get());
+            {
+                ProfScope ps("lp_admit_select", 0, s);
+                const unsigned gc = capped_grid(ccount);
+                if (small) {
+                    claim_small_kernel<<<grid_for(nw, 256), 256, 0, s>>>(nw, w, tsum.get(), tcnt.get(), bound,
+                                                                         seg_off.get(), seg_list.get(),
+                                                                         large_list.get(), small_max, ctr.get());
                     LAUNCHCHK();
-                    radix_sort_pairs(sk.get(), sv, sk_tmp.get(), sv_tmp.get(), m, 0, bits_t, rs, s);
+                    scatter_kernel<true><<<gc, 256, 0, s>>>(slow_idx.get(), cnodes, ct.get(), cg.get(), g.vw, bits_v,
+                                                            nw, seg_off.get(), seg_fill.get(), skey.get(), spos.get(),
+                                                            swt.get(), ctr.get());
+                } else {
+                    claim_big_kernel<<<gc, 256, 0, s>>>(slow_idx.get(), ct.get(), tcnt.get(), seg_off.get(),
+                                                        seg_list.get(), large_list.get(), small_max, ctr.get());
+                    LAUNCHCHK();
+                    scatter_kernel<false><<<gc, 256, 0, s>>>(slow_idx.get(), cnodes, ct.get(), cg.get(), g.vw, bits_v,
+                                                             nw, seg_off.get(), seg_fill.get(), skey.get(), spos.get(),
+                                                             swt.get(), ctr.get());
                 }
-                slow_gather_kernel<<<grid_for(m, 256), 256, 0, s>>>(sv, m, cnodes, ct.get(), g.vw, psum.get(),
-                                                                    heads.get());
                 LAUNCHCHK();
-                inclusive_scan_i64(psum.get(), psum.get(), m, s);
-                inclusive_max_i32(heads.get(), heads.get(), m, s);
-                slow_admit_kernel<<<grid_for(m, 256), 256, 0, s>>>(sv, m, ct.get(), w, psum.get(), heads.get(), bound,
-                                                                   ok.get());
+                large_setup_kernel<<<1, 1, 0, s>>>(LS, tcnt.get(), w, bound, ctr.get());
+                LAUNCHCHK();
+                select_kernel<<<kMaxBlocks, 256, 0, s>>>(seg_list.get(), seg_off.get(), seg_fill.get(), tcnt.get(), w,
+                                                         bound, bits_v, skey.get(), spos.get(), swt.get(), ok.get(),
+                                                         small_max, ctr.get());
+                LAUNCHCHK();
+                for (int pass = max_sel_passes - 1; pass >= 0; --pass) {
+                    large_pass_kernel<<<kMaxBlocks, 256, 0, s>>>(LS, pass, bits_v, seg_off.get(), tcnt.get(),
+                                                                 skey.get(), swt.get(), ctr.get());
+                    LAUNCHCHK();
+                }
+                large_admit_kernel<<<kMaxBlocks, 256, 0, s>>>(LS, seg_off.get(), seg_fill.get(), tcnt.get(),
+                                                              skey.get(), spos.get(), ok.get(), ctr.get());
+                LAUNCHCHK();
+                large_reset_kernel<<<1, 256, 0, s>>>(LS, seg_off.get(), seg_fill.get(), ctr.get());
                 LAUNCHCHK();
             }
-            if (ncand > 0) {
+            if (trace) {
+                HIPCHK(hipMemcpyAsync(hctr, ctr.get(), sizeof(Counters), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                fprintf(stderr, "[sclap] %s L%d r%d s%d n=%lld cand=%u slow=%u targets=%u gain=[%d,%d] hubs=%d\n",
+                        phase == kRefine ? "refine" : "cluster", level, r, sc, static_cast<long long>(ccount),
+                        hctr->ncand, hctr->nslow, hctr->nseg, hctr->nslow ? hctr->gmin : 0,
+                        hctr->nslow ? hctr->gmax : 0, plans[sc].count);
+            }
+            {
                 ProfScope ps("lp_apply", 0, s);
                 if (small) {
                     apply_kernel<true><<<capped_grid(ccount), 256, 0, s>>>(ct.get(), ok.get(), cnodes, ccount, g.vw,
-                                                                           label, w, tsum.get(), nw);
+                                                                           label, w, tsum.get(), tcnt.get(), nw);
                     LAUNCHCHK();
                     fill_i32(tsum.get(), 0, nw, s);
+                    fill_i32(tcnt.get(), 0, nw, s);
                 } else {
                     apply_kernel<false><<<grid_for(ccount, 256), 256, 0, s>>>(ct.get(), ok.get(), cnodes, ccount,
-                                                                              g.vw, label, w, tsum.get(), nw);
+                                                                              g.vw, label, w, tsum.get(), tcnt.get(),
+                                                                              nw);
                     LAUNCHCHK();
                 }
             }
-            reset_counters_kernel<<<1, 1, 0, s>>>(ctr.get());
+            reset_counters_kernel<<<1, 1, 0, s>>>(ctr.get(), 0);
             LAUNCHCHK();
-            round_cands += ncand;  // the first candidate of every target is always admitted
         }
+        // one host synchronisation per round: a round without candidates
+        // moved nothing (the first candidate of every target is always admitted)
+        HIPCHK(hipMemcpyAsync(hctr, ctr.get(), sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (profiler().on) profiler().collect();
+        const uint32_t round_cands = hctr->round_cands;
+        reset_counters_kernel<<<1, 1, 0, s>>>(ctr.get(), 1);
+        LAUNCHCHK();
         res.rounds_run = r + 1;
         res.moves += round_cands;
         if (round_cands == 0) break;

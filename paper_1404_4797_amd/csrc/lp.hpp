@@ -23,6 +23,7 @@ struct LPTuning {
     int32_t block_max = 8192; // <= 8192
     int32_t hub_part_limit = 4096;  // <= 4096; larger hub partitions use the HBM table
     int32_t hub_region_cap = 0;     // 0: about twice a partition's expected share
+    int32_t select_small_max = 4096;  // larger overflow segments: multi-workgroup selection
 };
 
 struct LPResult {

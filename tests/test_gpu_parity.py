@@ -66,7 +66,7 @@ KNOBS = [dict(), dict(lane_max_degree=2, wave_max_degree=8, block_max_degree=24)
          # hub partitions summed through the HBM table / regions spilling to overflow
          dict(lane_max_degree=2, wave_max_degree=8, block_max_degree=24, hub_part_limit=1),
          dict(lane_max_degree=2, wave_max_degree=8, block_max_degree=40, hub_region_cap=3),
-         dict(block_max_degree=60, hub_part_limit=5, hub_region_cap=2)]
+         dict(block_max_degree=60, hub_part_limit=5, hub_region_cap=2, select_small_max=1)]
 
 
 # ------------------------------------------------------------ hand-worked
@@ -121,7 +121,9 @@ def test_cluster_parity(sc, gname, knobs):
         assert np.array_equal(lab.cpu().numpy(), ref)
 
 
-REFINE_KNOBS = [dict(block_max_degree=40), dict(block_max_degree=30, hub_part_limit=1, hub_region_cap=2)]
+REFINE_KNOBS = [dict(block_max_degree=40), dict(block_max_degree=30, hub_part_limit=1, hub_region_cap=2),
+                # every overflowing target through the multi-workgroup selection
+                dict(select_small_max=1), dict(select_small_max=7)]
 
 
 @pytest.mark.parametrize("gname", list(GRAPHS))
