@@ -67,6 +67,27 @@ def cpu_baseline(g, w):
                       "(%d edge visits, %.1f s, single thread)" % (visits, dt)}
 
 
+def recorded_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the rocprofv3 counter record in
+    profiles/, or None if there is none or the kernel source changed since."""
+    import glob
+    import hashlib
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md")):
+        for line in open(path):
+            if not line.startswith("machine-readable:"):
+                continue
+            kv = dict(tok.split("=", 1) for tok in line.split()[1:] if "=" in tok)
+            if kv.get("kernel") != kernel or kv.get("workload", workload) != workload:
+                continue
+            src = os.path.join(ROOT, kv["source"])
+            if not os.path.exists(src):
+                return None
+            if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get("sha256"):
+                return None
+            return float(kv["traffic_bytes_per_launch"])
+    return None
+
+
 def copy_calibration(nbytes):
     """A plain device copy of known size, for scaling HBM counters."""
     import torch
@@ -140,8 +161,10 @@ def main():
         ks = kstats[dom]
         avg_ms = ks["ms"] / ks["launches"]
         gbs = ks["bytes"] / (ks["ms"] / 1000.0) / 1e9
+        traffic = recorded_traffic(dom, name)
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "traffic_GBps": round(traffic / avg_ms / 1e6, 1) if traffic else None,
                     "avg_launch_ms": round(avg_ms, 5), "bytes_per_launch": ks["bytes"] / ks["launches"],
                     "launches": ks["launches"] // max(args.steps, 1)}
     total_k_ms = sum(v["ms"] for v in kstats.values())
