@@ -88,6 +88,57 @@ def recorded_traffic(kernel, workload):
     return None
 
 
+def batch_comparison(ngraphs, seed, log_lo, log_hi):
+    """Batched vs plain on the same device-resident mix: all graphs in one
+    batched call, then each graph by itself through the one-graph entry
+    point; per-graph parts and cuts must be identical."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1404_4797_amd as sc
+    t = time.time()
+    gs = synth.batch_mix(ngraphs, seed=seed, n_lo_log2=log_lo, n_hi_log2=log_hi)
+    ks = [g["k"] for g in gs]
+    eps = [g["eps"] for g in gs]
+    seeds = [g["seed"] for g in gs]
+    u, nb = sc.union(gs)
+    log("batch mix: %d graphs, n=%d S=%d generated in %.1fs" % (ngraphs, u["n"], int(u["xadj"][-1]),
+                                                               time.time() - t))
+    du = sc.to_device(u, "cuda")
+    dgs = [sc.to_device(g, "cuda") for g in gs]
+    part = torch.empty(max(u["n"], 1), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    r = sc.partition_batch_dev(du, nb, ks, eps, seeds, part=part, stream=stream)  # warmup
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = sc.partition_batch_dev(du, nb, ks, eps, seeds, part=part, stream=stream)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    log("batched: %.1f ms for %d graphs" % (t_batch * 1e3, ngraphs))
+    bpart = part.cpu().numpy()
+    same = True
+    t_plain = 0.0
+    visits_plain = 0
+    for i, dg in enumerate(dgs):
+        p = torch.empty(max(gs[i]["n"], 1), dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        q = sc.partition_dev(dg, ks[i], eps[i], seeds[i], part=p, stream=stream)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t0
+        visits_plain += q["stats"]["visits"]
+        if q["cut"] != int(r["cut"][i]) or not np.array_equal(p.cpu().numpy()[:gs[i]["n"]],
+                                                              bpart[nb[i]:nb[i + 1]]):
+            same = False
+    log("plain: %.1f ms for %d graphs, identical=%s" % (t_plain * 1e3, ngraphs, same))
+    return {"graphs": ngraphs, "n_log2_range": [log_lo, log_hi], "n": u["n"], "S": int(u["xadj"][-1]),
+            "batched_ms": round(t_batch * 1e3, 3), "plain_ms": round(t_plain * 1e3, 3),
+            "batched_graphs_per_s": ngraphs / t_batch, "plain_graphs_per_s": ngraphs / t_plain,
+            "speedup": t_plain / t_batch, "identical_parts_and_cuts": same,
+            "batched_edge_visits": r["stats"]["visits"], "plain_edge_visits": visits_plain,
+            "levels_max": r["stats"]["levels"]}
+
+
 def copy_calibration(nbytes):
     """A plain device copy of known size, for scaling HBM counters."""
     import torch
@@ -107,6 +158,8 @@ def main():
     ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0, help="bytes for a plain copy kernel (counter scaling)")
+    ap.add_argument("--batch-graphs", type=int, default=512, help="graphs in the batched-vs-plain comparison (0: skip)")
+    ap.add_argument("--batch-log2", type=int, nargs=2, default=[10, 18], help="log2 range of n in the batch")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build partitions on one GPU; --gpus %d is not supported "
@@ -192,6 +245,8 @@ def main():
         "lp_eval_GB_per_step": round(lp_gb, 3),
         "roofline": roofline, "kernels": kernels,
     }
+    if args.batch_graphs > 0:
+        out["batched"] = batch_comparison(args.batch_graphs, 0, args.batch_log2[0], args.batch_log2[1])
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample) ...")
         out["cpu_baseline"] = cpu_baseline(g, w)

@@ -208,6 +208,40 @@ int sclap_partition_dev(const sclap_graph* g, int32_t k, double eps, uint64_t se
                         int32_t* part, int64_t* cut, int64_t* block_w, sclap_stats* stats, void* stream);
 
 /*
+ * Batched multilevel partitioning (the Section 4.5 algorithm applied to many
+ * independent graphs at once).  The batch is one CSR holding `count` graphs:
+ * graph i owns nodes [node_base[i], node_base[i+1]) (node_base: host array
+ * of count+1 entries, node_base[0] = 0, node_base[count] = n) and every edge
+ * joins two nodes of the same graph (checked when validating).  Graph i is
+ * partitioned into k[i] blocks with eps[i] and seed[i]; its result is exactly
+ * what sclap_partition returns for that graph alone with the same options:
+ * every hash and order uses graph-local ids.  Each level runs every kernel
+ * once for all graphs still coarsening.
+ *   part[n]          graph-local block ids, per node of the batch
+ *   cut[count]       host; cut of each graph
+ *   block_w[sum k]   host; graph i's block weights start at k[0]+..+k[i-1]
+ * Each graph's c(V) must be <= 2^31-1; when validating, so must the totals of
+ * the whole batch.  Returns 0, SCLAP_WARN_IMBALANCED (some graph has a block
+ * above its Lmax) or an error.
+ */
+typedef struct {
+    int32_t levels;        /* most contractions kept by any graph */
+    int64_t visits;        /* adjacency slots scanned by node evaluation, whole batch */
+    double ms_coarsen;     /* clustering + contraction of all levels */
+    double ms_initial;     /* coarsest-graph transfers + host initial partitions */
+    double ms_refine;      /* projection + refinement */
+    double ms_lp;          /* label propagation rounds only */
+    int32_t* graph_levels; /* optional caller array [count]: contractions kept per graph, or NULL */
+} sclap_batch_stats;
+
+int sclap_partition_batch(const sclap_graph* g, int32_t count, const int32_t* node_base, const int32_t* k,
+                          const double* eps, const uint64_t* seed, const sclap_options* opt, int32_t* part,
+                          int64_t* cut, int64_t* block_w, sclap_batch_stats* stats);
+int sclap_partition_batch_dev(const sclap_graph* g, int32_t count, const int32_t* node_base, const int32_t* k,
+                              const double* eps, const uint64_t* seed, const sclap_options* opt, int32_t* part,
+                              int64_t* cut, int64_t* block_w, sclap_batch_stats* stats, void* stream);
+
+/*
  * Instrumentation.  sclap_profile_begin() starts timing every kernel launch
  * that later calls on this thread issue, with HIP events recorded on the
  * launching stream around each launch; sclap_profile_end() stops, writes up to

@@ -34,6 +34,7 @@ EXPORTS = [
     "sclap_cut", "sclap_cut_dev",
     "sclap_initial_partition",
     "sclap_partition", "sclap_partition_dev",
+    "sclap_partition_batch", "sclap_partition_batch_dev",
     "sclap_profile_begin", "sclap_profile_end",
 ]
 
@@ -87,6 +88,17 @@ class Stats(ctypes.Structure):
                 "ms_initial": self.ms_initial, "ms_refine": self.ms_refine, "ms_lp": self.ms_lp}
 
 
+class BatchStats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("visits", ctypes.c_int64),
+                ("ms_coarsen", ctypes.c_double), ("ms_initial", ctypes.c_double),
+                ("ms_refine", ctypes.c_double), ("ms_lp", ctypes.c_double),
+                ("graph_levels", ctypes.c_void_p)]
+
+    def to_dict(self):
+        return {"levels": self.levels, "visits": self.visits, "ms_coarsen": self.ms_coarsen,
+                "ms_initial": self.ms_initial, "ms_refine": self.ms_refine, "ms_lp": self.ms_lp}
+
+
 def load():
     """Loads libsclap.so (built by ``__graft_entry__.build()``)."""
     global _lib
@@ -100,6 +112,7 @@ def load():
     O = ctypes.POINTER(Options)
     GO = ctypes.POINTER(GraphOwned)
     ST = ctypes.POINTER(Stats)
+    BST = ctypes.POINTER(BatchStats)
     sig = {
         "sclap_default_options": (ctypes.c_int, [O]),
         "sclap_last_error": (ctypes.c_char_p, []),
@@ -120,6 +133,8 @@ def load():
         "sclap_initial_partition": (ctypes.c_int, [G, i32, vp]),
         "sclap_partition": (ctypes.c_int, [G, i32, dbl, u64, O, vp, vp, vp, ST]),
         "sclap_partition_dev": (ctypes.c_int, [G, i32, dbl, u64, O, vp, vp, vp, ST, vp]),
+        "sclap_partition_batch": (ctypes.c_int, [G, i32, vp, vp, vp, vp, O, vp, vp, vp, BST]),
+        "sclap_partition_batch_dev": (ctypes.c_int, [G, i32, vp, vp, vp, vp, O, vp, vp, vp, BST, vp]),
         "sclap_profile_begin": (ctypes.c_int, []),
         "sclap_profile_end": (ctypes.c_int, [ctypes.POINTER(KernelStat), i32, vp]),
     }
@@ -411,3 +426,104 @@ def profile_end():
     _check(load().sclap_profile_end(arr, cap, ctypes.addressof(cnt)))
     return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].ms, "bytes": arr[i].bytes}
             for i in range(min(cnt.value, cap))}
+
+
+# ------------------------------------------------------------------ batches
+
+def union(graphs):
+    """Concatenates host graph dicts into one CSR (graph i's ids shifted by
+    the nodes before it).  Returns (graph dict, node_base int32[count+1])."""
+    nb = np.zeros(len(graphs) + 1, dtype=np.int64)
+    for i, g in enumerate(graphs):
+        nb[i + 1] = nb[i] + int(g["n"])
+    if nb[-1] > np.iinfo(np.int32).max:
+        raise ValueError("batch has more than 2^31-1 nodes")
+    S = [int(g["xadj"][-1]) if int(g["n"]) > 0 else 0 for g in graphs]
+    sb = np.concatenate([[0], np.cumsum(S)]).astype(np.int64)
+    xadj = np.zeros(int(nb[-1]) + 1, dtype=np.int64)
+    for i, g in enumerate(graphs):
+        if int(g["n"]) > 0:
+            xadj[nb[i] + 1:nb[i + 1] + 1] = np.asarray(g["xadj"][1:], dtype=np.int64) + sb[i]
+    adj = np.concatenate([np.asarray(g["adjncy"][:S[i]], dtype=np.int64) + nb[i] for i, g in enumerate(graphs)]
+                         or [np.zeros(0, dtype=np.int64)]).astype(np.int32)
+    u = {"n": int(nb[-1]), "xadj": xadj, "adjncy": adj}
+    for key, size in (("adjwgt", S), ("vwgt", [int(g["n"]) for g in graphs])):
+        if all(g.get(key) is None for g in graphs):
+            u[key] = None
+        else:
+            u[key] = np.concatenate([np.ones(size[i], dtype=np.int32) if g.get(key) is None
+                                     else np.asarray(g[key][:size[i]], dtype=np.int32)
+                                     for i, g in enumerate(graphs)] or [np.zeros(0, dtype=np.int32)])
+    return u, nb.astype(np.int32)
+
+
+def _batch_args(count, k, eps, seed):
+    k = np.ascontiguousarray(k, dtype=np.int32)
+    eps = np.ascontiguousarray(eps, dtype=np.float64)
+    seed = np.ascontiguousarray(seed, dtype=np.uint64)
+    if not (len(k) == len(eps) == len(seed) == count):
+        raise ValueError("k, eps and seed need one entry per graph")
+    return k, eps, seed
+
+
+def _split_batch(part, node_base, k, cut, bw, status, st, levels):
+    kb = np.concatenate([[0], np.cumsum(k)])
+    out = []
+    for i in range(len(k)):
+        out.append({"part": part[node_base[i]:node_base[i + 1]], "cut": int(cut[i]),
+                    "block_weights": bw[kb[i]:kb[i + 1]], "levels": int(levels[i])})
+    return {"graphs": out, "status": status, "stats": st.to_dict()}
+
+
+def partition_batch(graphs, k, eps, seed, **opts):
+    """Partitions a list of host graphs together (one multilevel pass over
+    their union).  Returns dict(graphs=[dict(part, cut, block_weights,
+    levels)], status, stats); each graph's result equals partition() of that
+    graph alone."""
+    g, node_base = union(graphs)
+    return partition_batch_union(g, node_base, k, eps, seed, **opts)
+
+
+def partition_batch_union(g, node_base, k, eps, seed, **opts):
+    """partition_batch() on a host union already built (see union())."""
+    node_base = np.ascontiguousarray(node_base, dtype=np.int32)
+    count = len(node_base) - 1
+    k, eps, seed = _batch_args(count, k, eps, seed)
+    hg = _HostGraph(g)
+    o = _opts(opts)
+    part = np.empty(hg.n, dtype=np.int32)
+    cut = np.zeros(count, dtype=np.int64)
+    bw = np.zeros(int(k.sum()), dtype=np.int64)
+    levels = np.zeros(count, dtype=np.int32)
+    st = BatchStats()
+    st.graph_levels = levels.ctypes.data
+    status = _check(load().sclap_partition_batch(hg.ref, count, node_base.ctypes.data, k.ctypes.data,
+                                                 eps.ctypes.data, seed.ctypes.data, ctypes.byref(o),
+                                                 part.ctypes.data, cut.ctypes.data, bw.ctypes.data,
+                                                 ctypes.byref(st)), allow_warn=True)
+    return _split_batch(part, node_base, k, cut, bw, status, st, levels)
+
+
+def partition_batch_dev(d, node_base, k, eps, seed, part=None, stream=None, opts=None, **kw):
+    """Batched partition of a device-resident union (see union()); ``part``
+    receives graph-local blocks.  Returns dict(part, cut[count],
+    block_weights[sum k], levels[count], status, stats)."""
+    import torch
+    dg = _DevGraph(d)
+    node_base = np.ascontiguousarray(node_base, dtype=np.int32)
+    count = len(node_base) - 1
+    k, eps, seed = _batch_args(count, k, eps, seed)
+    if part is None:
+        part = torch.empty(dg.n, dtype=torch.int32, device=d["xadj"].device)
+    o = opts if isinstance(opts, Options) else default_options(**kw)
+    cut = np.zeros(count, dtype=np.int64)
+    bw = np.zeros(int(k.sum()), dtype=np.int64)
+    levels = np.zeros(count, dtype=np.int32)
+    st = BatchStats()
+    st.graph_levels = levels.ctypes.data
+    status = _check(load().sclap_partition_batch_dev(dg.ref, count, node_base.ctypes.data, k.ctypes.data,
+                                                     eps.ctypes.data, seed.ctypes.data, ctypes.byref(o),
+                                                     _t_ptr(part), cut.ctypes.data, bw.ctypes.data,
+                                                     ctypes.byref(st), _stream(stream)), allow_warn=True)
+    return {"part": part, "cut": cut, "block_weights": bw, "levels": levels, "status": status,
+            "stats": st.to_dict()}

@@ -1,7 +1,11 @@
 // C ABI (include/sclap.h): argument checks, the multilevel driver and the
 // host initial partitioner around the gfx950 kernels.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <climits>
+#include <exception>
+#include <thread>
 #include <cmath>
 #include <cstring>
 #include <deque>
@@ -470,6 +474,341 @@ int partition_impl(const DevGraph& g0, int32_t k, double eps, uint64_t seed, con
     return SCLAP_OK;
 }
 
+// ------------------------------------------------------------- batches
+//
+// Many graphs partitioned together: the graphs of a batch are one CSR with a
+// node range per graph and no edge between ranges.  Every level runs each
+// kernel once for all graphs; hashes, orders and bounds are per graph
+// (graph-local ids, own seed, U and Lmax), so every graph gets exactly the
+// result it gets alone.  A graph leaves the coarsening loop by its own stop
+// rule; later levels hold only the graphs still coarsening.
+
+struct BatchLevel {
+    OwnedDevGraph own;
+    DevGraph g;
+    std::vector<int32_t> ids;  // batch index of each member graph
+    std::vector<int32_t> nb;   // first node of each member, then n
+    std::vector<int64_t> sb;   // first slot of each member, then S
+    DBuf<int32_t> gid;         // [n] batch index of each node
+    DBuf<int32_t> C;           // [n] node of the next level, -1 where the graph ends here
+};
+
+template <typename T>
+void upload_vec(DBuf<T>& d, const std::vector<T>& h, hipStream_t s) {
+    if (h.empty()) return;
+    HIPCHK(hipMemcpyAsync(d.get(), h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+// Runs f(i) for i in [0, count) on up to `threads` host threads.
+template <typename F>
+void parallel_for(int32_t count, int32_t threads, F f) {
+    threads = std::max(1, std::min(threads, count));
+    if (threads == 1) {
+        for (int32_t i = 0; i < count; ++i) f(i);
+        return;
+    }
+    std::atomic<int32_t> next{0};
+    std::vector<std::exception_ptr> errs(threads);
+    std::vector<std::thread> pool;
+    for (int32_t t = 0; t < threads; ++t)
+        pool.emplace_back([&, t] {
+            try {
+                for (int32_t i = next++; i < count; i = next++) f(i);
+            } catch (...) {
+                errs[t] = std::current_exception();
+            }
+        });
+    for (auto& th : pool) th.join();
+    for (auto& e : errs)
+        if (e) std::rethrow_exception(e);
+}
+
+int partition_batch_impl(const DevGraph& g0, int32_t G, const int32_t* node_base, const int32_t* k,
+                         const double* eps, const uint64_t* seed, const Opts& o, int32_t* part_out, int64_t* cut,
+                         int64_t* bw, sclap_batch_stats* stats, hipStream_t s) {
+    if (G < 1) fail(SCLAP_ERR_INVALID, "count must be >= 1");
+    if (!node_base || !k || !eps || !seed) fail(SCLAP_ERR_INVALID, "node_base, k, eps or seed is NULL");
+    if (node_base[0] != 0 || node_base[G] != g0.n) fail(SCLAP_ERR_INVALID, "node_base must run from 0 to n");
+    std::vector<int32_t> kb(static_cast<size_t>(G) + 1, 0);
+    for (int32_t g = 0; g < G; ++g) {
+        if (node_base[g + 1] < node_base[g]) fail(SCLAP_ERR_INVALID, "node_base must be non-decreasing");
+        check_k_eps(k[g], eps[g]);
+        if (static_cast<int64_t>(kb[g]) + k[g] > (1 << 30)) fail(SCLAP_ERR_INVALID, "sum of k too large");
+        kb[g + 1] = kb[g] + k[g];
+    }
+    const int32_t K = kb[G];
+    if (!part_out && g0.n > 0) fail(SCLAP_ERR_INVALID, "part is NULL");
+    if (!cut || !bw) fail(SCLAP_ERR_INVALID, "cut / block_w is NULL");
+    sclap_batch_stats local;
+    sclap_batch_stats* st = stats ? stats : &local;
+    int32_t* graph_levels = st->graph_levels;
+    std::memset(st, 0, sizeof(*st));
+    st->graph_levels = graph_levels;
+    auto t_coarsen = Clock::now();
+    double lp_ms = 0;
+
+    std::vector<BatchLevel> L(1);
+    {
+        BatchLevel& B = L[0];
+        B.g = g0;
+        B.ids.resize(G);
+        for (int32_t g = 0; g < G; ++g) B.ids[g] = g;
+        B.nb.assign(node_base, node_base + G + 1);
+        B.sb = member_slot_bases(g0.xadj, B.nb, s);
+        B.gid.alloc(std::max(g0.n, 1), s);
+        member_ids(g0.n, B.nb, B.ids, B.gid.get(), s);
+    }
+    if (o.validate) {
+        int64_t cVu = 0, cmu = 0;
+        check_graph(g0, true, &cVu, &cmu, s);
+        if (!members_closed(g0, L[0].nb, L[0].sb, s)) fail(SCLAP_ERR_INVALID, "an edge joins two graphs of the batch");
+    }
+    std::vector<int64_t> cV(G), cmax0(G);
+    graph_node_stats(g0.n, L[0].gid.get(), g0.vw, G, cV.data(), cmax0.data(), s);
+    std::vector<int64_t> Lmax(G), W(G), T(G);
+    for (int32_t g = 0; g < G; ++g) {
+        if (cV[g] > 2147483647LL) fail(SCLAP_ERR_OVERFLOW, "node weight total of a graph exceeds 2^31-1");
+        Lmax[g] = lmax_of(cV[g], k[g], eps[g]);
+        W[g] = cV[g] / (static_cast<int64_t>(o.divisor) * k[g]);
+        T[g] = (cV[g] + k[g] - 1) / k[g];
+    }
+
+    // per-graph device parameters
+    DBuf<uint64_t> d_seed(G, s);
+    DBuf<int64_t> d_bound(G, s);
+    DBuf<int32_t> d_lbase(G, s), d_nbase(G, s), d_kb(G, s);
+    DBuf<uint8_t> d_active(G, s);
+    HIPCHK(hipMemcpyAsync(d_seed.get(), seed, G * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    upload_vec(d_kb, std::vector<int32_t>(kb.begin(), kb.begin() + G), s);
+
+    // ---- coarsening
+    std::vector<uint8_t> cont(G, 1);
+    int32_t lev = 0;
+    while (true) {
+        const int32_t M = static_cast<int32_t>(L[lev].ids.size());
+        std::vector<uint8_t> act(G, 0);
+        bool any = false;
+        for (int32_t m = 0; m < M; ++m) {
+            const int32_t g = L[lev].ids[m];
+            const int32_t nm = L[lev].nb[m + 1] - L[lev].nb[m];
+            if (cont[g] && nm > o.coarsest && lev < o.max_levels) {
+                act[g] = 1;
+                any = true;
+            }
+        }
+        if (!any) break;
+        BatchLevel& B = L[lev];
+        const int32_t n = B.g.n;
+        std::vector<int64_t> cvl(G), cm = cmax0;
+        if (lev > 0) graph_node_stats(n, B.gid.get(), B.g.vw, G, cvl.data(), cm.data(), s);
+        std::vector<int64_t> bound(G, 0);
+        std::vector<int32_t> base(G, 0);
+        for (int32_t m = 0; m < M; ++m) {
+            const int32_t g = B.ids[m];
+            bound[g] = std::max(cm[g], W[g]);
+            base[g] = B.nb[m];
+        }
+        upload_vec(d_bound, bound, s);
+        upload_vec(d_lbase, base, s);
+        upload_vec(d_nbase, base, s);
+        upload_vec(d_active, act, s);
+        DBuf<int32_t> labels(n, s), w(n, s);
+        iota_u32(reinterpret_cast<uint32_t*>(labels.get()), n, s);
+        label_weights(B.g, labels.get(), w.get(), n, s);
+        MultiGraph mg;
+        mg.G = G;
+        mg.gid = B.gid.get();
+        mg.lgid = B.gid.get();  // cluster labels are node ids
+        mg.nbase = d_nbase.get();
+        mg.lbase = d_lbase.get();
+        mg.bound = d_bound.get();
+        mg.seed = d_seed.get();
+        mg.active = d_active.get();
+        auto t_lp = Clock::now();
+        const LPResult r =
+            run_lp(B.g, kCluster, lev, 0, o.nsub, o.coarsen_rounds, 0, labels.get(), w.get(), n, nullptr, o.tune, s, &mg);
+        lp_ms += ms_since(t_lp);
+        st->visits += r.visits;
+        w.release();
+        // contraction of the whole level; member m's coarse nodes start at cb[m]
+        DBuf<int32_t> probe(M + 1, s), qb(M + 1, s), C(n, s);
+        upload_vec(probe, B.nb, s);
+        OwnedDevGraph coarse;
+        contract(B.g, labels.get(), C.get(), coarse, s, probe.get(), M + 1, qb.get());
+        std::vector<int32_t> cb(M + 1);
+        HIPCHK(hipMemcpyAsync(cb.data(), qb.get(), (M + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        labels.release();
+        std::vector<int32_t> keep;
+        for (int32_t m = 0; m < M; ++m) {
+            const int32_t g = B.ids[m];
+            if (!act[g]) {
+                cont[g] = 0;
+                continue;
+            }
+            const int64_t nm = B.nb[m + 1] - B.nb[m], nc = cb[m + 1] - cb[m];
+            if (nc >= nm) {  // no shrink: this level stays the graph's coarsest
+                cont[g] = 0;
+                continue;
+            }
+            keep.push_back(m);
+            if (20 * nc > 19 * nm) cont[g] = 0;  // stalled
+        }
+        if (keep.empty()) break;
+        BatchLevel N;
+        const std::vector<int64_t> csb = member_slot_bases(coarse.xadj.get(), cb, s);
+        N.nb.push_back(0);
+        N.sb.push_back(0);
+        std::vector<int32_t> onb;
+        std::vector<int64_t> osb;
+        for (int32_t m : keep) {
+            N.ids.push_back(B.ids[m]);
+            N.nb.push_back(N.nb.back() + (cb[m + 1] - cb[m]));
+            N.sb.push_back(N.sb.back() + (csb[m + 1] - csb[m]));
+            onb.push_back(cb[m]);
+            osb.push_back(csb[m]);
+        }
+        if (static_cast<int32_t>(keep.size()) == M) {
+            N.own = std::move(coarse);
+        } else {
+            compact_members(coarse.view(), onb, osb, N.nb, N.sb, N.own, s);
+            coarse = OwnedDevGraph();
+        }
+        N.g = N.own.view();
+        N.gid.alloc(std::max(N.g.n, 1), s);
+        member_ids(N.g.n, N.nb, N.ids, N.gid.get(), s);
+        std::vector<int32_t> delta(G, INT_MIN);
+        for (size_t j = 0; j < keep.size(); ++j) delta[N.ids[j]] = N.nb[j] - cb[keep[j]];
+        remap_members(n, B.gid.get(), delta, C.get(), s);
+        B.C = std::move(C);
+        L.push_back(std::move(N));  // B is not used after this
+        ++lev;
+    }
+    const int32_t top = lev;
+    std::vector<int32_t> last(G, 0), mpos(G, 0);
+    for (int32_t l = 0; l <= top; ++l)
+        for (size_t m = 0; m < L[l].ids.size(); ++m) last[L[l].ids[m]] = l;
+    st->levels = top;
+    if (st->graph_levels)
+        for (int32_t g = 0; g < G; ++g) st->graph_levels[g] = last[g];
+    HIPCHK(hipStreamSynchronize(s));
+    st->ms_coarsen = ms_since(t_coarsen);
+
+    // ---- initial partition of every graph's coarsest level, on the host
+    auto t_init = Clock::now();
+    struct Slice {
+        std::vector<int64_t> x;
+        std::vector<int32_t> a, v, part;
+    };
+    std::vector<Slice> ip(G);
+    for (int32_t l = 0; l <= top; ++l) {
+        const BatchLevel& B = L[l];
+        for (size_t m = 0; m < B.ids.size(); ++m) {
+            const int32_t g = B.ids[m];
+            mpos[g] = static_cast<int32_t>(m);
+            if (last[g] != l) continue;
+            const int32_t nm = B.nb[m + 1] - B.nb[m];
+            const int64_t Sm = B.sb[m + 1] - B.sb[m];
+            Slice& sl = ip[g];
+            sl.x.resize(static_cast<size_t>(nm) + 1);
+            sl.a.resize(static_cast<size_t>(std::max<int64_t>(Sm, 1)));
+            sl.part.resize(static_cast<size_t>(nm));
+            HIPCHK(hipMemcpyAsync(sl.x.data(), B.g.xadj + B.nb[m], (nm + 1) * sizeof(int64_t), hipMemcpyDeviceToHost,
+                                  s));
+            if (Sm > 0)
+                HIPCHK(hipMemcpyAsync(sl.a.data(), B.g.adj + B.sb[m], Sm * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            if (B.g.vw && nm > 0) {
+                sl.v.resize(nm);
+                HIPCHK(hipMemcpyAsync(sl.v.data(), B.g.vw + B.nb[m], nm * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            }
+        }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    const unsigned hw = std::thread::hardware_concurrency();
+    parallel_for(G, static_cast<int32_t>(std::min(16u, hw ? hw : 1u)), [&](int32_t g) {
+        Slice& sl = ip[g];
+        const BatchLevel& B = L[last[g]];
+        const int32_t m = mpos[g];
+        const int32_t nm = B.nb[m + 1] - B.nb[m];
+        const int64_t x0 = sl.x[0];
+        for (auto& x : sl.x) x -= x0;
+        for (int64_t j = 0; j < sl.x[nm]; ++j) sl.a[j] -= B.nb[m];
+        host_initial_partition(nm, sl.x.data(), sl.a.data(), sl.v.empty() ? nullptr : sl.v.data(), k[g], T[g],
+                               sl.part.data(), last[g] > 0);
+        for (auto& b : sl.part) b += kb[g];  // labels of the batch's block space
+        sl.x = {};
+        sl.a = {};
+        sl.v = {};
+    });
+    st->ms_initial = ms_since(t_init);
+
+    // ---- refinement from the top level down
+    auto t_ref = Clock::now();
+    std::vector<int32_t> lgid(std::max(K, 1));
+    for (int32_t g = 0; g < G; ++g)
+        for (int32_t b = kb[g]; b < kb[g + 1]; ++b) lgid[b] = g;
+    DBuf<int32_t> d_lgid(std::max(K, 1), s);
+    upload_vec(d_lgid, lgid, s);
+    upload_vec(d_bound, Lmax, s);
+    upload_vec(d_active, std::vector<uint8_t>(G, 1), s);
+    DBuf<int32_t> w(std::max(K, 1), s), cur;
+    for (int32_t l = top; l >= 0; --l) {
+        BatchLevel& B = L[l];
+        const int32_t n = B.g.n;
+        DBuf<int32_t> mine;
+        int32_t* part = part_out;
+        if (l > 0) {
+            mine.alloc(std::max(n, 1), s);
+            part = mine.get();
+        }
+        if (l < top) project_kept(n, B.C.get(), cur.get(), part, s);
+        for (size_t m = 0; m < B.ids.size(); ++m) {
+            const int32_t g = B.ids[m];
+            if (last[g] != l || ip[g].part.empty()) continue;
+            HIPCHK(hipMemcpyAsync(part + B.nb[m], ip[g].part.data(), ip[g].part.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, s));
+        }
+        std::vector<int32_t> base(G, 0);
+        for (size_t m = 0; m < B.ids.size(); ++m) base[B.ids[m]] = B.nb[m];
+        upload_vec(d_nbase, base, s);
+        label_weights(B.g, part, w.get(), K, s);
+        MultiGraph mg;
+        mg.G = G;
+        mg.gid = B.gid.get();
+        mg.lgid = d_lgid.get();
+        mg.nbase = d_nbase.get();
+        mg.lbase = d_kb.get();
+        mg.bound = d_bound.get();
+        mg.seed = d_seed.get();
+        mg.active = d_active.get();
+        auto t_lp = Clock::now();
+        const LPResult r =
+            run_lp(B.g, kRefine, l, 0, o.nsub, o.refine_rounds, 0, part, w.get(), K, nullptr, o.tune, s, &mg);
+        lp_ms += ms_since(t_lp);
+        st->visits += r.visits;
+        HIPCHK(hipStreamSynchronize(s));  // host slices uploaded above must stay alive until here
+        for (size_t m = 0; m < B.ids.size(); ++m)
+            if (last[B.ids[m]] == l) ip[B.ids[m]].part = {};
+        cur = std::move(mine);
+        if (l < top) L[l + 1] = BatchLevel();
+        B.C.release();
+    }
+    std::vector<int32_t> hw_(std::max(K, 1));
+    HIPCHK(hipMemcpyAsync(hw_.data(), w.get(), std::max(K, 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    graph_cuts(g0, part_out, L[0].gid.get(), G, cut, s);  // synchronises
+    shift_by_graph(g0.n, L[0].gid.get(), d_kb.get(), -1, part_out, s);
+    HIPCHK(hipStreamSynchronize(s));
+    int status = SCLAP_OK;
+    for (int32_t g = 0; g < G; ++g)
+        for (int32_t b = kb[g]; b < kb[g + 1]; ++b) {
+            bw[b] = hw_[b];
+            if (bw[b] > Lmax[g]) status = SCLAP_WARN_IMBALANCED;
+        }
+    st->ms_refine = ms_since(t_ref);
+    st->ms_lp = lp_ms;
+    return status;
+}
+
 // ------------------------------------------------ host <-> device staging
 
 struct Staged {
@@ -850,6 +1189,32 @@ int sclap_partition(const sclap_graph* g, int32_t k, double eps, uint64_t seed, 
         if (st.g.n > 0 && !part) fail(SCLAP_ERR_INVALID, "part is NULL");
         DBuf<int32_t> p(std::max(st.g.n, 1), s);
         const int r = partition_impl(st.g, k, eps, seed, o, p.get(), cut, block_w, stats, s);
+        download(part, p.get(), st.g.n, s);
+        return r;
+    });
+}
+
+int sclap_partition_batch_dev(const sclap_graph* g, int32_t count, const int32_t* node_base, const int32_t* k,
+                              const double* eps, const uint64_t* seed, const sclap_options* opt, int32_t* part,
+                              int64_t* cut, int64_t* block_w, sclap_batch_stats* stats, void* stream) {
+    return guarded([&] {
+        hipStream_t s = as_stream(stream);
+        const Opts o = resolve(opt);
+        const DevGraph d = dev_view(g, s);
+        return partition_batch_impl(d, count, node_base, k, eps, seed, o, part, cut, block_w, stats, s);
+    });
+}
+
+int sclap_partition_batch(const sclap_graph* g, int32_t count, const int32_t* node_base, const int32_t* k,
+                          const double* eps, const uint64_t* seed, const sclap_options* opt, int32_t* part,
+                          int64_t* cut, int64_t* block_w, sclap_batch_stats* stats) {
+    return guarded([&] {
+        hipStream_t s = nullptr;
+        const Opts o = resolve(opt);
+        Staged st = upload(g, s);
+        if (st.g.n > 0 && !part) fail(SCLAP_ERR_INVALID, "part is NULL");
+        DBuf<int32_t> p(std::max(st.g.n, 1), s);
+        const int r = partition_batch_impl(st.g, count, node_base, k, eps, seed, o, p.get(), cut, block_w, stats, s);
         download(part, p.get(), st.g.n, s);
         return r;
     });

@@ -204,6 +204,13 @@ __global__ void run_tails_kernel(const uint64_t* __restrict__ keys, int64_t m, c
 }
 
 
+// probe_out[i] = number of used labels below probe[i] (probe[i] in [0, n]).
+__global__ void probe_kernel(const int32_t* __restrict__ probe, int32_t nprobe, const int32_t* __restrict__ q,
+                             int32_t n, const int32_t* __restrict__ total, int32_t* __restrict__ out) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < nprobe) out[i] = probe[i] < n ? q[probe[i]] : *total;
+}
+
 __global__ void project_kernel(int32_t n, const int32_t* __restrict__ C, const int32_t* __restrict__ cp,
                                int32_t* __restrict__ part) {
     const int32_t v = blockIdx.x * 256 + threadIdx.x;
@@ -363,13 +370,15 @@ unsigned capped_nodes(int64_t n) {
 
 }  // namespace
 
-void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGraph& coarse, hipStream_t s) {
+void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGraph& coarse, hipStream_t s,
+              const int32_t* probe, int32_t nprobe, int32_t* probe_out) {
     const int32_t n = g.n;
     if (n == 0) {
         coarse.n = 0;
         coarse.S = 0;
         coarse.xadj.alloc(1, s);
         fill_i64(coarse.xadj.get(), 0, 1, s);
+        if (nprobe > 0) fill_i32(probe_out, 0, nprobe, s);
         return;
     }
     DBuf<int32_t> q(n, s);
@@ -378,6 +387,10 @@ void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGrap
     mark_used_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, labels, q.get());
     LAUNCHCHK();
     exclusive_scan_i32(q.get(), q.get(), n, total.get(), s);
+    if (nprobe > 0) {
+        probe_kernel<<<grid_for(nprobe, 256), 256, 0, s>>>(probe, nprobe, q.get(), n, total.get(), probe_out);
+        LAUNCHCHK();
+    }
     int32_t nc = 0;
     HIPCHK(hipMemcpyAsync(&nc, total.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -540,6 +553,290 @@ bool all_in_range(const int32_t* a, int64_t count, int32_t lo, int32_t hi, hipSt
     HIPCHK(hipMemcpyAsync(&h, bad.get(), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return h == 0;
+}
+
+// ---------------------------------------------- several graphs in one CSR
+//
+// Member m of a batch owns nodes [nb[m], nb[m+1]) and slots [sb[m], sb[m+1]);
+// no edge leaves a member.  Empty members are allowed.
+
+namespace {
+
+// Largest m in [0, M) with base[m] <= x (base non-decreasing, base[0] <= x).
+template <typename T>
+__device__ __forceinline__ int32_t member_of(const T* __restrict__ base, int32_t M, int64_t x) {
+    int32_t lo = 0, hi = M;
+    while (hi - lo > 1) {
+        const int32_t mid = lo + (hi - lo) / 2;
+        if (static_cast<int64_t>(base[mid]) <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void member_ids_kernel(int32_t n, int32_t M, const int32_t* __restrict__ nb,
+                                  const int32_t* __restrict__ ids, int32_t* __restrict__ gid) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v < n) gid[v] = ids[member_of(nb, M, v)];
+}
+
+__global__ void members_closed_kernel(int64_t S, int32_t M, const int64_t* __restrict__ sb,
+                                      const int32_t* __restrict__ nb, const int32_t* __restrict__ adj,
+                                      uint32_t* __restrict__ bad) {
+    uint32_t b = 0;
+    for (int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; j < S;
+         j += static_cast<int64_t>(gridDim.x) * 256) {
+        const int32_t m = member_of(sb, M, j);
+        const int32_t u = adj[j];
+        if (u < nb[m] || u >= nb[m + 1]) b = 1;
+    }
+    if (__any(b) && lane_id() == 0) atomicOr(bad, 1u);
+}
+
+// One atomic per wave when the wave's items belong to one graph (graphs are
+// contiguous), else one per item.
+__device__ __forceinline__ void add_by_graph(bool valid, int32_t g, unsigned long long val,
+                                             unsigned long long* __restrict__ out) {
+    const int32_t lo = wave_min(valid ? g : INT_MAX);
+    const int32_t hi = wave_max(valid ? g : -1);
+    if (lo == hi) {
+        const unsigned long long t = wave_sum(valid ? val : 0ULL);
+        if (lane_id() == 0 && t) atomicAdd(&out[lo], t);
+    } else if (valid && val) {
+        atomicAdd(&out[g], val);
+    }
+}
+
+__global__ void graph_node_stats_kernel(int32_t n, const int32_t* __restrict__ gid, const int32_t* __restrict__ vw,
+                                        unsigned long long* __restrict__ cV, unsigned long long* __restrict__ cmax) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    const bool valid = v < n;
+    const int32_t g = valid ? gid[v] : 0;
+    const int32_t c = valid ? (vw ? vw[v] : 1) : 0;
+    add_by_graph(valid, g, static_cast<unsigned long long>(c < 0 ? 0 : c), cV);
+    const int32_t lo = wave_min(valid ? g : INT_MAX);
+    const int32_t hi = wave_max(valid ? g : -1);
+    if (lo == hi) {
+        const int32_t m = wave_max(valid ? c : 0);
+        if (lane_id() == 0 && m > 0) atomicMax(&cmax[lo], static_cast<unsigned long long>(m));
+    } else if (valid && c > 0) {
+        atomicMax(&cmax[g], static_cast<unsigned long long>(c));
+    }
+}
+
+__global__ void __launch_bounds__(kTileThreads) graph_cut_kernel(const int64_t* __restrict__ xadj,
+                                                                 const int32_t* __restrict__ adj,
+                                                                 const int32_t* __restrict__ ew, int32_t n, int64_t S,
+                                                                 const int32_t* __restrict__ part,
+                                                                 const int32_t* __restrict__ gid,
+                                                                 unsigned long long* __restrict__ cut) {
+    __shared__ int32_t owner[kTile];
+    for (int64_t tile = blockIdx.x; tile * kTile < S; tile += gridDim.x) {
+        const int64_t i0 = tile * kTile;
+        const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
+        tile_owners(xadj, n, i0, i1, owner);
+        for (int r = 0; r < kTilePer; ++r) {
+            const int64_t i = i0 + r * kTileThreads + threadIdx.x;
+            const bool valid = i < i1;
+            int32_t g = 0;
+            unsigned long long val = 0;
+            if (valid) {
+                const int32_t u = owner[i - i0];
+                g = gid[u];
+                if (part[u] != part[adj[i]]) val = ew ? static_cast<unsigned long long>(ew[i]) : 1ULL;
+            }
+            add_by_graph(valid, g, val, cut);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void compact_nodes_kernel(int32_t n_new, int32_t Mk, const int32_t* __restrict__ nnb,
+                                     const int32_t* __restrict__ onb, const int64_t* __restrict__ osb,
+                                     const int64_t* __restrict__ nsb, const int64_t* __restrict__ oxadj,
+                                     const int32_t* __restrict__ ovw, int64_t S_new, int64_t* __restrict__ nxadj,
+                                     int32_t* __restrict__ nvw) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i == 0) nxadj[n_new] = S_new;
+    if (i >= n_new) return;
+    const int32_t m = member_of(nnb, Mk, i);
+    const int32_t o = onb[m] + (i - nnb[m]);
+    nxadj[i] = oxadj[o] - osb[m] + nsb[m];
+    nvw[i] = ovw[o];
+}
+
+__global__ void compact_slots_kernel(int64_t S_new, int32_t Mk, const int64_t* __restrict__ nsb,
+                                     const int64_t* __restrict__ osb, const int32_t* __restrict__ onb,
+                                     const int32_t* __restrict__ nnb, const int32_t* __restrict__ oadj,
+                                     const int32_t* __restrict__ oew, int32_t* __restrict__ nadj,
+                                     int32_t* __restrict__ new_) {
+    for (int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; j < S_new;
+         j += static_cast<int64_t>(gridDim.x) * 256) {
+        const int32_t m = member_of(nsb, Mk, j);
+        const int64_t o = osb[m] + (j - nsb[m]);
+        nadj[j] = oadj[o] - onb[m] + nnb[m];
+        new_[j] = oew[o];
+    }
+}
+
+__global__ void remap_members_kernel(int32_t n, const int32_t* __restrict__ gid, const int32_t* __restrict__ delta,
+                                     int32_t* __restrict__ C) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= n) return;
+    const int32_t d = delta[gid[v]];
+    C[v] = d == INT_MIN ? -1 : C[v] + d;
+}
+
+__global__ void project_kept_kernel(int32_t n, const int32_t* __restrict__ C, const int32_t* __restrict__ cp,
+                                    int32_t* __restrict__ part) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v < n && C[v] >= 0) part[v] = cp[C[v]];
+}
+
+__global__ void shift_by_graph_kernel(int32_t n, const int32_t* __restrict__ gid, const int32_t* __restrict__ add,
+                                      int32_t sign, int32_t* __restrict__ part) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v < n) part[v] += sign * add[gid[v]];
+}
+
+__global__ void gather_offsets_kernel(const int64_t* __restrict__ xadj, const int32_t* __restrict__ pos, int32_t M,
+                                      int64_t* __restrict__ out) {
+    const int32_t m = blockIdx.x * 256 + threadIdx.x;
+    if (m < M) out[m] = xadj[pos[m]];
+}
+
+unsigned capped_grid_s(int64_t items) {
+    const int64_t g = (items + 255) / 256;
+    return static_cast<unsigned>(g < 1 ? 1 : (g > 4096 ? 4096 : g));
+}
+
+}  // namespace
+
+void member_ids(int32_t n, const std::vector<int32_t>& nb, const std::vector<int32_t>& ids, int32_t* gid,
+                hipStream_t s) {
+    if (n == 0) return;
+    const int32_t M = static_cast<int32_t>(ids.size());
+    DBuf<int32_t> d(2 * static_cast<size_t>(M) + 1, s);
+    HIPCHK(hipMemcpyAsync(d.get(), nb.data(), (M + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d.get() + M + 1, ids.data(), M * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    member_ids_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, M, d.get(), d.get() + M + 1, gid);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(s));  // host vectors may go away
+}
+
+std::vector<int64_t> member_slot_bases(const int64_t* xadj, const std::vector<int32_t>& nb, hipStream_t s) {
+    const int32_t M1 = static_cast<int32_t>(nb.size());
+    std::vector<int64_t> sb(M1);
+    DBuf<int32_t> pos(M1, s);
+    DBuf<int64_t> out(M1, s);
+    HIPCHK(hipMemcpyAsync(pos.get(), nb.data(), M1 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    gather_offsets_kernel<<<grid_for(M1, 256), 256, 0, s>>>(xadj, pos.get(), M1, out.get());
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(sb.data(), out.get(), M1 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return sb;
+}
+
+bool members_closed(const DevGraph& g, const std::vector<int32_t>& nb, const std::vector<int64_t>& sb,
+                    hipStream_t s) {
+    if (g.S == 0) return true;
+    const int32_t M = static_cast<int32_t>(nb.size()) - 1;
+    DBuf<int32_t> dnb(M + 1, s);
+    DBuf<int64_t> dsb(M + 1, s);
+    DBuf<uint32_t> bad(1, s);
+    HIPCHK(hipMemcpyAsync(dnb.get(), nb.data(), (M + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dsb.get(), sb.data(), (M + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    fill_u32(bad.get(), 0, 1, s);
+    members_closed_kernel<<<capped_grid_s(g.S), 256, 0, s>>>(g.S, M, dsb.get(), dnb.get(), g.adj, bad.get());
+    LAUNCHCHK();
+    uint32_t h = 0;
+    HIPCHK(hipMemcpyAsync(&h, bad.get(), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return h == 0;
+}
+
+void graph_node_stats(int32_t n, const int32_t* gid, const int32_t* vw, int32_t G, int64_t* cV, int64_t* cmax,
+                      hipStream_t s) {
+    DBuf<unsigned long long> d(2 * static_cast<size_t>(std::max(G, 1)), s);
+    HIPCHK(hipMemsetAsync(d.get(), 0, 2 * std::max(G, 1) * sizeof(unsigned long long), s));
+    if (n > 0) {
+        graph_node_stats_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, gid, vw, d.get(), d.get() + G);
+        LAUNCHCHK();
+    }
+    std::vector<unsigned long long> h(2 * static_cast<size_t>(std::max(G, 1)));
+    HIPCHK(hipMemcpyAsync(h.data(), d.get(), h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int32_t g = 0; g < G; ++g) {
+        cV[g] = static_cast<int64_t>(h[g]);
+        cmax[g] = static_cast<int64_t>(h[G + g]);
+    }
+}
+
+void graph_cuts(const DevGraph& g, const int32_t* part, const int32_t* gid, int32_t G, int64_t* cut, hipStream_t s) {
+    DBuf<unsigned long long> d(std::max(G, 1), s);
+    HIPCHK(hipMemsetAsync(d.get(), 0, std::max(G, 1) * sizeof(unsigned long long), s));
+    if (g.S > 0) {
+        const int64_t ntiles = (g.S + kTile - 1) / kTile;
+        const unsigned grid = static_cast<unsigned>(ntiles < 2048 ? ntiles : 2048);
+        graph_cut_kernel<<<grid, kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, g.n, g.S, part, gid, d.get());
+        LAUNCHCHK();
+    }
+    std::vector<unsigned long long> h(std::max(G, 1));
+    HIPCHK(hipMemcpyAsync(h.data(), d.get(), h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int32_t i = 0; i < G; ++i) cut[i] = static_cast<int64_t>(h[i] / 2);
+}
+
+void compact_members(const DevGraph& src, const std::vector<int32_t>& onb, const std::vector<int64_t>& osb,
+                     const std::vector<int32_t>& nnb, const std::vector<int64_t>& nsb, OwnedDevGraph& dst,
+                     hipStream_t s) {
+    const int32_t Mk = static_cast<int32_t>(onb.size());
+    const int32_t n_new = nnb[Mk];
+    const int64_t S_new = nsb[Mk];
+    dst.n = n_new;
+    dst.S = S_new;
+    dst.xadj.alloc(static_cast<size_t>(n_new) + 1, s);
+    dst.vw.alloc(std::max(n_new, 1), s);
+    dst.adj.alloc(std::max<int64_t>(S_new, 1), s);
+    dst.ew.alloc(std::max<int64_t>(S_new, 1), s);
+    DBuf<int32_t> i32(3 * static_cast<size_t>(Mk) + 2, s);  // nnb[Mk+1] | onb[Mk] | nnb copy for slots
+    DBuf<int64_t> i64(3 * static_cast<size_t>(Mk) + 2, s);  // nsb[Mk+1] | osb[Mk] | nsb copy for nodes
+    HIPCHK(hipMemcpyAsync(i32.get(), nnb.data(), (Mk + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(i32.get() + Mk + 1, onb.data(), Mk * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(i64.get(), nsb.data(), (Mk + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(i64.get() + Mk + 1, osb.data(), Mk * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    compact_nodes_kernel<<<grid_for(std::max(n_new, 1), 256), 256, 0, s>>>(
+        n_new, Mk, i32.get(), i32.get() + Mk + 1, i64.get() + Mk + 1, i64.get(), src.xadj, src.vw, S_new,
+        dst.xadj.get(), dst.vw.get());
+    LAUNCHCHK();
+    if (S_new > 0) {
+        compact_slots_kernel<<<capped_grid_s(S_new), 256, 0, s>>>(S_new, Mk, i64.get(), i64.get() + Mk + 1,
+                                                                  i32.get() + Mk + 1, i32.get(), src.adj, src.ew,
+                                                                  dst.adj.get(), dst.ew.get());
+        LAUNCHCHK();
+    }
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+void remap_members(int32_t n, const int32_t* gid, const std::vector<int32_t>& delta, int32_t* C, hipStream_t s) {
+    if (n == 0) return;
+    DBuf<int32_t> d(std::max<size_t>(delta.size(), 1), s);
+    HIPCHK(hipMemcpyAsync(d.get(), delta.data(), delta.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    remap_members_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, gid, d.get(), C);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+void project_kept(int32_t n, const int32_t* C, const int32_t* coarse_part, int32_t* part, hipStream_t s) {
+    if (n == 0) return;
+    project_kept_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, C, coarse_part, part);
+    LAUNCHCHK();
+}
+
+void shift_by_graph(int32_t n, const int32_t* gid, const int32_t* add, int32_t sign, int32_t* part, hipStream_t s) {
+    if (n == 0) return;
+    shift_by_graph_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, gid, add, sign, part);
+    LAUNCHCHK();
 }
 
 }  // namespace sclap

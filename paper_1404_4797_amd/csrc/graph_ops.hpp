@@ -2,6 +2,8 @@
 // weights, validation, range checks.
 #pragma once
 
+#include <vector>
+
 #include "lp.hpp"
 
 namespace sclap {
@@ -29,7 +31,10 @@ struct OwnedDevGraph {
 // Contraction (Section 3.1; Section 4.3): labels in [0, n) -> C[n] and the
 // coarse graph with sorted rows.  Always materialises coarse edge and node
 // weights.
-void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGraph& coarse, hipStream_t s);
+// probe (device, nprobe entries in [0, n]) optionally reports the coarse id
+// base of label positions: probe_out[i] = number of used labels < probe[i].
+void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGraph& coarse, hipStream_t s,
+              const int32_t* probe = nullptr, int32_t nprobe = 0, int32_t* probe_out = nullptr);
 
 // part[v] = coarse_part[C[v]]
 void project(int32_t n, const int32_t* C, const int32_t* coarse_part, int32_t* part, hipStream_t s);
@@ -46,5 +51,33 @@ void node_weight_stats(const DevGraph& g, int64_t* cV, int64_t* cmax, hipStream_
 
 // True iff every value of a[0..count) lies in [lo, hi).
 bool all_in_range(const int32_t* a, int64_t count, int32_t lo, int32_t hi, hipStream_t s);
+
+// Several disjoint graphs in one CSR.  Member m owns nodes [nb[m], nb[m+1])
+// and slots [sb[m], sb[m+1]); ids[m] is its index in the caller's batch.
+
+// gid[v] = ids[m] for the member m holding v.
+void member_ids(int32_t n, const std::vector<int32_t>& nb, const std::vector<int32_t>& ids, int32_t* gid,
+                hipStream_t s);
+// sb[m] = xadj[nb[m]] for every entry of nb (host result).
+std::vector<int64_t> member_slot_bases(const int64_t* xadj, const std::vector<int32_t>& nb, hipStream_t s);
+// True iff every slot's neighbour lies in the slot owner's member.
+bool members_closed(const DevGraph& g, const std::vector<int32_t>& nb, const std::vector<int64_t>& sb,
+                    hipStream_t s);
+// Per graph c(V_g) and max c(v) over its nodes (host arrays of G entries).
+void graph_node_stats(int32_t n, const int32_t* gid, const int32_t* vw, int32_t G, int64_t* cV, int64_t* cmax,
+                      hipStream_t s);
+// Per graph cut of part (host array of G entries).
+void graph_cuts(const DevGraph& g, const int32_t* part, const int32_t* gid, int32_t G, int64_t* cut, hipStream_t s);
+// dst = the members of src with old bases (onb, osb), placed at (nnb, nsb);
+// neighbour ids move with their member.  src must carry node and edge weights.
+void compact_members(const DevGraph& src, const std::vector<int32_t>& onb, const std::vector<int64_t>& osb,
+                     const std::vector<int32_t>& nnb, const std::vector<int64_t>& nsb, OwnedDevGraph& dst,
+                     hipStream_t s);
+// C[v] += delta[gid[v]], or -1 where delta is INT_MIN (graph dropped).
+void remap_members(int32_t n, const int32_t* gid, const std::vector<int32_t>& delta, int32_t* C, hipStream_t s);
+// part[v] = coarse_part[C[v]] where C[v] >= 0.
+void project_kept(int32_t n, const int32_t* C, const int32_t* coarse_part, int32_t* part, hipStream_t s);
+// part[v] += sign * add[gid[v]] (add: device array indexed by graph).
+void shift_by_graph(int32_t n, const int32_t* gid, const int32_t* add, int32_t sign, int32_t* part, hipStream_t s);
 
 }  // namespace sclap

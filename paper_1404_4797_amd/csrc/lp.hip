@@ -80,6 +80,11 @@ struct EvalArgs {
     int64_t bound;
     uint64_t tp;  // H(seed, 2, level, phase, round)
     int32_t refine;
+    // several graphs in one launch; gid == null: one graph, the scalars above
+    const int32_t* gid;      // [n] graph of each node
+    const uint64_t* g_tp;    // [G] tie prefix of each graph for this round
+    const int64_t* g_bound;  // [G] bound of each graph's labels
+    const int32_t* g_lbase;  // [G] first label of each graph
     const int32_t* nodes;  // schedule entries of this launch
     int32_t count;
     int32_t* ct;  // per entry: target label or -1
@@ -87,6 +92,22 @@ struct EvalArgs {
 };
 
 // ------------------------------------------------------- selection helpers
+
+// Per-node constants: the tie prefix and bound of the node's graph and the
+// graph's first label (ties hash graph-local label ids).
+struct Ctx {
+    uint64_t tp;
+    int64_t bound;
+    int32_t lbase;
+};
+
+__device__ __forceinline__ Ctx ctx_of(const EvalArgs& A, int32_t v) {
+    if (A.gid) {
+        const int32_t g = A.gid[v];
+        return Ctx{A.g_tp[g], A.g_bound[g], A.g_lbase[g]};
+    }
+    return Ctx{A.tp, A.bound, 0};
+}
 
 // Best eligible label seen so far under the total order
 // (conn desc, tie(x) asc, x asc); tie(x) = mix(tp ^ x) is computed lazily,
@@ -105,11 +126,11 @@ __device__ __forceinline__ void best_init(Best& b) {
     b.tv = false;
 }
 
-__device__ __forceinline__ uint64_t tie_of(uint64_t tp, int32_t x) {
-    return mix64(tp ^ static_cast<uint64_t>(static_cast<uint32_t>(x)));
+__device__ __forceinline__ uint64_t tie_of(const Ctx& kx, int32_t x) {
+    return mix64(kx.tp ^ static_cast<uint64_t>(static_cast<uint32_t>(x - kx.lbase)));
 }
 
-__device__ __forceinline__ void best_consider(Best& b, int32_t x, int32_t conn, uint64_t tp) {
+__device__ __forceinline__ void best_consider(Best& b, int32_t x, int32_t conn, const Ctx& kx) {
     if (b.x < 0 || conn > b.conn) {
         b.conn = conn;
         b.x = x;
@@ -117,9 +138,9 @@ __device__ __forceinline__ void best_consider(Best& b, int32_t x, int32_t conn, 
         return;
     }
     if (conn < b.conn) return;
-    const uint64_t tx = tie_of(tp, x);
+    const uint64_t tx = tie_of(kx, x);
     if (!b.tv) {
-        b.tie = tie_of(tp, b.x);
+        b.tie = tie_of(kx, b.x);
         b.tv = true;
     }
     if (tx < b.tie || (tx == b.tie && x < b.x)) {
@@ -128,10 +149,10 @@ __device__ __forceinline__ void best_consider(Best& b, int32_t x, int32_t conn, 
     }
 }
 
-__device__ __forceinline__ uint64_t best_tie(const Best& b, uint64_t tp) { return b.tv ? b.tie : tie_of(tp, b.x); }
+__device__ __forceinline__ uint64_t best_tie(const Best& b, const Ctx& kx) { return b.tv ? b.tie : tie_of(kx, b.x); }
 
 // Wave-wide argmax; every lane gets the winning (x, conn) or x = -1.
-__device__ __forceinline__ void wave_argmax(const Best& b, uint64_t tp, int32_t& out_x, int32_t& out_conn) {
+__device__ __forceinline__ void wave_argmax(const Best& b, const Ctx& kx, int32_t& out_x, int32_t& out_conn) {
     const int32_t bc = b.x >= 0 ? b.conn : -1;
     const int32_t maxc = wave_max(bc);
     if (maxc < 0) {
@@ -140,7 +161,7 @@ __device__ __forceinline__ void wave_argmax(const Best& b, uint64_t tp, int32_t&
         return;
     }
     const bool top = b.x >= 0 && bc == maxc;
-    const uint64_t tk = top ? best_tie(b, tp) : ~0ULL;
+    const uint64_t tk = top ? best_tie(b, kx) : ~0ULL;
     const uint64_t mt = wave_min_u64(tk);
     const int32_t xx = (top && tk == mt) ? b.x : INT_MAX;
     out_x = wave_min(xx);
@@ -158,8 +179,8 @@ __device__ __forceinline__ void combine_into(int32_t& bc, uint64_t& bt, int32_t&
     }
 }
 
-__device__ __forceinline__ bool eligible(const EvalArgs& A, int32_t x, int32_t c) {
-    return static_cast<int64_t>(A.w[x]) + c <= A.bound;
+__device__ __forceinline__ bool eligible(const EvalArgs& A, int32_t x, int32_t c, const Ctx& kx) {
+    return static_cast<int64_t>(A.w[x]) + c <= kx.bound;
 }
 
 // Decision for a node given its best eligible label (x, conn) and the
@@ -227,6 +248,7 @@ __global__ void __launch_bounds__(256) eval_lane_kernel(EvalArgs A) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= A.count) return;
     const int32_t v = A.nodes[i];
+    const Ctx kx = ctx_of(A, v);
     const int64_t b = A.xadj[v];
     const int d = static_cast<int>(A.xadj[v + 1] - b);
     const int32_t a = A.label[v];
@@ -245,7 +267,7 @@ __global__ void __launch_bounds__(256) eval_lane_kernel(EvalArgs A) {
     int32_t own = 0;
 #pragma unroll
     for (int j = 0; j < MAXD; ++j) own += (lab[j] == a) ? wt[j] : 0;
-    const bool over = A.refine && A.w[a] > A.bound;
+    const bool over = A.refine && A.w[a] > kx.bound;
     Best best;
     best_init(best);
 #pragma unroll
@@ -260,8 +282,8 @@ __global__ void __launch_bounds__(256) eval_lane_kernel(EvalArgs A) {
         for (int j2 = j; j2 < MAXD; ++j2) conn += (lab[j2] == x) ? wt[j2] : 0;
         if (!over && conn <= own) continue;  // cannot give a positive gain
         if (best.x >= 0 && conn < best.conn) continue;
-        if (!eligible(A, x, c)) continue;
-        best_consider(best, x, conn, A.tp);
+        if (!eligible(A, x, c, kx)) continue;
+        best_consider(best, x, conn, kx);
     }
     store_result(A, i, best.x, best.conn, own, over);
 }
@@ -278,6 +300,7 @@ __global__ void __launch_bounds__(256) eval_wave_kernel(EvalArgs A) {
     int32_t* keys = tkeys[wid];
     int32_t* vals = tvals[wid];
     const int32_t v = A.nodes[node_i];
+    const Ctx kx = ctx_of(A, v);
     const int64_t b = A.xadj[v];
     const int32_t d = static_cast<int32_t>(A.xadj[v + 1] - b);
     const int32_t a = A.label[v];
@@ -295,7 +318,7 @@ __global__ void __launch_bounds__(256) eval_wave_kernel(EvalArgs A) {
     for (uint32_t j = lane; j < tsz; j += 64)
         if (keys[j] == a) ownp = vals[j];
     const int32_t own = wave_max(ownp);
-    const bool over = A.refine && A.w[a] > A.bound;
+    const bool over = A.refine && A.w[a] > kx.bound;
     Best best;
     best_init(best);
     for (uint32_t j = lane; j < tsz; j += 64) {
@@ -304,11 +327,11 @@ __global__ void __launch_bounds__(256) eval_wave_kernel(EvalArgs A) {
         const int32_t conn = vals[j];
         if (!over && conn <= own) continue;
         if (best.x >= 0 && conn < best.conn) continue;
-        if (!eligible(A, x, c)) continue;
-        best_consider(best, x, conn, A.tp);
+        if (!eligible(A, x, c, kx)) continue;
+        best_consider(best, x, conn, kx);
     }
     int32_t bx, bconn;
-    wave_argmax(best, A.tp, bx, bconn);
+    wave_argmax(best, kx, bx, bconn);
     if (lane == 0) store_result(A, node_i, bx, bconn, own, over);
 }
 
@@ -326,6 +349,7 @@ __global__ void __launch_bounds__(NT) eval_block_kernel(EvalArgs A) {
     const int wid = tid >> 6;
     const int lane = lane_id();
     const int32_t v = A.nodes[blockIdx.x];
+    const Ctx kx = ctx_of(A, v);
     const int64_t b = A.xadj[v];
     const int32_t d = static_cast<int32_t>(A.xadj[v + 1] - b);
     const int32_t a = A.label[v];
@@ -344,7 +368,7 @@ __global__ void __launch_bounds__(NT) eval_block_kernel(EvalArgs A) {
         if (keys[j] == a) s_own = vals[j];
     __syncthreads();
     const int32_t own = s_own;
-    const bool over = A.refine && A.w[a] > A.bound;
+    const bool over = A.refine && A.w[a] > kx.bound;
     Best best;
     best_init(best);
     for (uint32_t j = tid; j < tsz; j += NT) {
@@ -353,15 +377,15 @@ __global__ void __launch_bounds__(NT) eval_block_kernel(EvalArgs A) {
         const int32_t conn = vals[j];
         if (!over && conn <= own) continue;
         if (best.x >= 0 && conn < best.conn) continue;
-        if (!eligible(A, x, c)) continue;
-        best_consider(best, x, conn, A.tp);
+        if (!eligible(A, x, c, kx)) continue;
+        best_consider(best, x, conn, kx);
     }
     int32_t bx, bconn;
-    wave_argmax(best, A.tp, bx, bconn);
+    wave_argmax(best, kx, bx, bconn);
     if (lane == 0) {
         s_conn[wid] = bconn;
         s_x[wid] = bx;
-        s_tie[wid] = bx >= 0 ? tie_of(A.tp, bx) : ~0ULL;
+        s_tie[wid] = bx >= 0 ? tie_of(kx, bx) : ~0ULL;
     }
     __syncthreads();
     if (tid == 0) {
@@ -521,6 +545,7 @@ __global__ void __launch_bounds__(kPartThreads) hub_part_kernel(EvalArgs A, HubA
     }
     __syncthreads();
     const int32_t v = H.hub_nodes[h];
+    const Ctx kx = ctx_of(A, v);
     const int32_t a = A.label[v];
     const int32_t c = A.vw ? A.vw[v] : 1;
     Best best;
@@ -534,16 +559,16 @@ __global__ void __launch_bounds__(kPartThreads) hub_part_kernel(EvalArgs A, HubA
             continue;
         }
         if (best.x >= 0 && conn < best.conn) continue;
-        if (!eligible(A, x, c)) continue;
-        best_consider(best, x, conn, A.tp);
+        if (!eligible(A, x, c, kx)) continue;
+        best_consider(best, x, conn, kx);
     }
     int32_t bx, bconn;
-    wave_argmax(best, A.tp, bx, bconn);
+    wave_argmax(best, kx, bx, bconn);
     const int wid = tid >> 6;
     if (lane_id() == 0) {
         s_conn[wid] = bconn;
         s_x[wid] = bx;
-        s_tie[wid] = bx >= 0 ? tie_of(A.tp, bx) : ~0ULL;
+        s_tie[wid] = bx >= 0 ? tie_of(kx, bx) : ~0ULL;
     }
     __syncthreads();
     if (tid == 0) {
@@ -559,6 +584,7 @@ __global__ void __launch_bounds__(kPartThreads) hub_part_kernel(EvalArgs A, HubA
 // Decision of a hub from the winners in [first[h], first[h+1]).
 __device__ __forceinline__ void hub_decide(const EvalArgs& A, const HubArgs& H, int32_t h, const int32_t* first) {
     const int32_t v = H.hub_nodes[h];
+    const Ctx kx = ctx_of(A, v);
     const int32_t a = A.label[v];
     int32_t fc = -1, fx = -1;
     uint64_t ft = ~0ULL;
@@ -571,7 +597,7 @@ __device__ __forceinline__ void hub_decide(const EvalArgs& A, const HubArgs& H, 
         const uint64_t mt = wave_min_u64(top ? ft : ~0ULL);
         bx = wave_min((top && ft == mt) ? fx : INT_MAX);
     }
-    const bool over = A.refine && A.w[a] > A.bound;
+    const bool over = A.refine && A.w[a] > kx.bound;
     if (lane_id() == 0) store_result(A, h, bx, maxc, H.hub_own[h], over);
 }
 
@@ -620,6 +646,7 @@ __global__ void __launch_bounds__(256) hub_scan_kernel(EvalArgs A, HubArgs H, in
     const int32_t h = H.tchunk_hub[blockIdx.x];
     if (!H.big[h]) return;
     const int32_t v = H.hub_nodes[h];
+    const Ctx kx = ctx_of(A, v);
     const int32_t a = A.label[v];
     const int32_t c = A.vw ? A.vw[v] : 1;
     const int64_t begin = H.tchunk_begin[blockIdx.x];
@@ -636,16 +663,16 @@ __global__ void __launch_bounds__(256) hub_scan_kernel(EvalArgs A, HubArgs H, in
             continue;
         }
         if (best.x >= 0 && conn < best.conn) continue;
-        if (!eligible(A, x, c)) continue;
-        best_consider(best, x, conn, A.tp);
+        if (!eligible(A, x, c, kx)) continue;
+        best_consider(best, x, conn, kx);
     }
     int32_t bx, bconn;
-    wave_argmax(best, A.tp, bx, bconn);
+    wave_argmax(best, kx, bx, bconn);
     const int wid = threadIdx.x >> 6;
     if (lane_id() == 0) {
         s_conn[wid] = bconn;
         s_x[wid] = bx;
-        s_tie[wid] = bx >= 0 ? tie_of(A.tp, bx) : ~0ULL;
+        s_tie[wid] = bx >= 0 ? tie_of(kx, bx) : ~0ULL;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -701,6 +728,17 @@ __device__ __forceinline__ int32_t block_sum_i32(int32_t v) {
 }
 
 // ------------------------------------------------- candidates and admission
+
+// Bound of a target label: one scalar, or per graph through the label's graph.
+struct Bounds {
+    int64_t bound;
+    const int32_t* lgid;     // [nw] graph of each label, or null
+    const int64_t* g_bound;  // [G]
+};
+
+__device__ __forceinline__ int64_t bound_of(const Bounds& B, int32_t t) {
+    return B.lgid ? B.g_bound[B.lgid[t]] : B.bound;
+}
 
 // Block-local LDS index of label t: t itself for small label spaces, else an
 // open-addressing slot (kAggTable entries, at most kAggChunk keys per chunk,
@@ -785,7 +823,7 @@ __global__ void __launch_bounds__(256) cand_accum_kernel(const int32_t* __restri
 // otherwise the candidate goes to the slow list.
 __global__ void __launch_bounds__(256) admit_kernel(const int32_t* __restrict__ ct, const int32_t* __restrict__ cg,
                                                     int32_t count, const int32_t* __restrict__ w,
-                                                    const int32_t* __restrict__ tsum, int64_t bound,
+                                                    const int32_t* __restrict__ tsum, Bounds B,
                                                     uint8_t* __restrict__ ok, uint32_t* __restrict__ slow_idx,
                                                     Counters* ctr) {
     __shared__ int32_t s_min[4], s_max[4];
@@ -799,7 +837,7 @@ __global__ void __launch_bounds__(256) admit_kernel(const int32_t* __restrict__ 
             const int32_t t = ct[p];
             uint8_t o = 0;
             if (t >= 0) {
-                if (static_cast<int64_t>(w[t]) + tsum[t] <= bound) {
+                if (static_cast<int64_t>(w[t]) + tsum[t] <= bound_of(B, t)) {
                     o = 1;
                 } else {
                     slow = true;
@@ -835,12 +873,12 @@ __global__ void __launch_bounds__(256) admit_kernel(const int32_t* __restrict__ 
 // entries (small label spaces: one thread per label).
 __global__ void __launch_bounds__(256) claim_small_kernel(int32_t nw, const int32_t* __restrict__ w,
                                                           const int32_t* __restrict__ tsum,
-                                                          const int32_t* __restrict__ cnt, int64_t bound,
+                                                          const int32_t* __restrict__ cnt, Bounds B,
                                                           int32_t* __restrict__ seg_off, int32_t* __restrict__ seg_list,
                                                           int32_t* __restrict__ large_list, int32_t small_max,
                                                           Counters* ctr) {
     const int32_t t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= nw || cnt[t] == 0 || static_cast<int64_t>(w[t]) + tsum[t] <= bound) return;
+    if (t >= nw || cnt[t] == 0 || static_cast<int64_t>(w[t]) + tsum[t] <= bound_of(B, t)) return;
     seg_off[t] = static_cast<int32_t>(atomicAdd(&ctr->slow_total, static_cast<uint32_t>(cnt[t])));
     seg_list[atomicAdd(&ctr->nseg, 1u)] = t;
     if (cnt[t] > small_max) large_list[atomicAdd(&ctr->nlarge, 1u)] = t;
@@ -948,7 +986,7 @@ __device__ __forceinline__ int bits_of(uint64_t x) { return x ? 64 - __clzll(sta
 __global__ void __launch_bounds__(256) select_kernel(const int32_t* __restrict__ seg_list,
                                                      int32_t* __restrict__ seg_off, int32_t* __restrict__ seg_fill,
                                                      const int32_t* __restrict__ cnt, const int32_t* __restrict__ w,
-                                                     int64_t bound, int bits_v, const uint64_t* __restrict__ skey,
+                                                     Bounds B, int bits_v, const uint64_t* __restrict__ skey,
                                                      const uint32_t* __restrict__ spos,
                                                      const int32_t* __restrict__ swt, uint8_t* __restrict__ ok,
                                                      int32_t small_max, const Counters* ctr) {
@@ -966,7 +1004,7 @@ __global__ void __launch_bounds__(256) select_kernel(const int32_t* __restrict__
         if (threadIdx.x == 0) {
             s_prefix = 0;
             s_mask = 0;
-            s_room = bound - static_cast<int64_t>(w[t]);
+            s_room = bound_of(B, t) - static_cast<int64_t>(w[t]);
         }
         __syncthreads();
         for (int pass = passes - 1; pass >= 0; --pass) {
@@ -1012,11 +1050,11 @@ struct LargeSel {
     uint32_t* hist;         // [nlarge][256] weight per digit
     uint64_t* prefix;       // [nlarge] digits fixed so far
     int64_t* room;          // [nlarge] weight still admissible below the prefix
-    uint32_t* done;         // blocks finished with the current digit
+    uint32_t* done;         // [nlarge] chunks finished with the current digit
 };
 
 __global__ void large_setup_kernel(LargeSel L, const int32_t* __restrict__ cnt, const int32_t* __restrict__ w,
-                                   int64_t bound, Counters* ctr) {
+                                   Bounds B, Counters* ctr) {
     // one thread: chunk prefix over the large segments (their number is small)
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int32_t run = 0;
@@ -1025,7 +1063,7 @@ __global__ void large_setup_kernel(LargeSel L, const int32_t* __restrict__ cnt, 
         L.chunk_first[l] = run;
         run += (cnt[t] + kSegChunk - 1) / kSegChunk;
         L.prefix[l] = 0;
-        L.room[l] = bound - static_cast<int64_t>(w[t]);
+        L.room[l] = bound_of(B, t) - static_cast<int64_t>(w[t]);
     }
     L.chunk_first[ctr->nlarge] = run;
     ctr->nlchunks = static_cast<uint32_t>(run);
@@ -1041,16 +1079,19 @@ __device__ __forceinline__ int32_t large_of_chunk(const LargeSel& L, uint32_t nl
     return lo;
 }
 
-// One digit of the multi-workgroup selection: every block adds its chunks'
-// weight histograms to the segment histograms in HBM; the last block to
-// finish picks each segment's boundary digit (no block waits for another).
+// One digit of the multi-workgroup selection: every block adds its chunk's
+// weight histogram to the segment's histogram in HBM; the last block to
+// finish a segment picks that segment's boundary digit with a block-wide scan
+// (no block waits for another).
 __global__ void __launch_bounds__(256) large_pass_kernel(LargeSel L, int pass, int bits_v,
                                                          const int32_t* __restrict__ seg_off,
                                                          const int32_t* __restrict__ cnt,
                                                          const uint64_t* __restrict__ skey,
                                                          const int32_t* __restrict__ swt, Counters* ctr) {
     __shared__ uint32_t h[256];
-    __shared__ int s_last;
+    __shared__ int64_t sc[256];
+    __shared__ int s_last, s_d;
+    __shared__ int64_t s_run;
     const int total_bits = bits_of(static_cast<uint64_t>(static_cast<int64_t>(ctr->gmax) - ctr->gmin)) + bits_v;
     const int passes = total_bits > 0 ? (total_bits + 7) / 8 : 1;
     const uint32_t nlarge = ctr->nlarge;
@@ -1058,6 +1099,7 @@ __global__ void __launch_bounds__(256) large_pass_kernel(LargeSel L, int pass, i
     const int shift = 8 * pass;
     const uint64_t above = pass + 1 >= 8 ? 0ULL : ~0ULL << (shift + 8);  // digits already fixed
     const int32_t nch = static_cast<int32_t>(ctr->nlchunks);
+    const int j = threadIdx.x;
     for (int32_t c = blockIdx.x; c < nch; c += gridDim.x) {
         const int32_t l = large_of_chunk(L, nlarge, c);
         const int32_t t = L.large_list[l];
@@ -1066,38 +1108,57 @@ __global__ void __launch_bounds__(256) large_pass_kernel(LargeSel L, int pass, i
         const int32_t i0 = (c - L.chunk_first[l]) * kSegChunk;
         const int32_t i1 = i0 + kSegChunk < len ? i0 + kSegChunk : len;
         const uint64_t prefix = L.prefix[l];
-        h[threadIdx.x] = 0;
+        uint32_t* hl = L.hist + static_cast<size_t>(l) * 256;
+        h[j] = 0;
         __syncthreads();
-        for (int32_t i = i0 + threadIdx.x; i < i1; i += 256) {
+        for (int32_t i = i0 + j; i < i1; i += 256) {
             const uint64_t k = skey[base + i];
             const int32_t wt = swt[base + i];
             if ((k & above) == prefix && wt) atomicAdd(&h[(k >> shift) & 255], static_cast<uint32_t>(wt));
         }
         __syncthreads();
-        if (h[threadIdx.x]) atomicAdd(&L.hist[static_cast<size_t>(l) * 256 + threadIdx.x], h[threadIdx.x]);
+        if (h[j]) atomicAdd(&hl[j], h[j]);
+        __threadfence();
+        __syncthreads();
+        if (j == 0) {
+            const uint32_t nchunks = static_cast<uint32_t>(L.chunk_first[l + 1] - L.chunk_first[l]);
+            s_last = atomicAdd(&L.done[l], 1u) == nchunks - 1;
+        }
+        __syncthreads();
+        if (s_last) {  // block-uniform
+            __threadfence();
+            const uint32_t hj = __hip_atomic_load(&hl[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sc[j] = hj;
+            __syncthreads();
+            for (int o = 1; o < 256; o <<= 1) {  // inclusive scan
+                const int64_t add = j >= o ? sc[j - o] : 0;
+                __syncthreads();
+                sc[j] += add;
+                __syncthreads();
+            }
+            const int64_t room = L.room[l];
+            const int64_t incl = sc[j];
+            const int64_t excl = incl - hj;
+            if (j == 255) {
+                s_d = 255;
+                s_run = excl;
+            }
+            __syncthreads();
+            // the digit where the admissible weight runs out (monotone: one thread)
+            if (incl > room && excl <= room && j < 255) {
+                s_d = j;
+                s_run = excl;
+            }
+            hl[j] = 0;
+            __syncthreads();
+            if (j == 0) {
+                L.room[l] = room - s_run;
+                L.prefix[l] |= static_cast<uint64_t>(s_d) << shift;
+                L.done[l] = 0;
+            }
+        }
         __syncthreads();
     }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = atomicAdd(L.done, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    for (uint32_t l = threadIdx.x; l < nlarge; l += 256) {
-        uint32_t* hl = L.hist + static_cast<size_t>(l) * 256;
-        int64_t run = 0;
-        const int64_t room = L.room[l];
-        int d = 0;
-        for (; d < 255; ++d) {
-            const uint32_t hd = atomicOr(&hl[d], 0u);
-            if (run + static_cast<int64_t>(hd) > room) break;
-            run += hd;
-        }
-        L.room[l] = room - run;
-        L.prefix[l] |= static_cast<uint64_t>(d) << shift;
-        for (int j = 0; j < 256; ++j) hl[j] = 0;
-    }
-    if (threadIdx.x == 0) *L.done = 0;
 }
 
 __global__ void __launch_bounds__(256) large_admit_kernel(LargeSel L, int32_t* __restrict__ seg_off,
@@ -1188,6 +1249,9 @@ __global__ void reset_counters_kernel(Counters* ctr, int round_too) {
 // and go to the extra category ncat.
 __global__ void __launch_bounds__(256) classify_kernel(int32_t n, const int64_t* __restrict__ xadj,
                                                        const int32_t* __restrict__ color_override, uint64_t hc,
+                                                       const int32_t* __restrict__ gid, const uint64_t* __restrict__ g_hc,
+                                                       const int32_t* __restrict__ g_nbase,
+                                                       const uint8_t* __restrict__ g_active,
                                                        int32_t nsub, int32_t th0, int32_t th1, int32_t th2,
                                                        int32_t th3, int32_t th4, int32_t th5,
                                                        uint64_t* __restrict__ keys,
@@ -1204,6 +1268,15 @@ __global__ void __launch_bounds__(256) classify_kernel(int32_t n, const int64_t*
     const int32_t v = blockIdx.x * 256 + threadIdx.x;
     if (v < n) {
         const int64_t d = xadj[v + 1] - xadj[v];
+        uint64_t hcv = hc;
+        int32_t lv = v;  // graph-local id
+        bool act = true;
+        if (gid) {
+            const int32_t g = gid[v];
+            hcv = g_hc[g];
+            lv = v - g_nbase[g];
+            act = g_active[g] != 0;
+        }
         int32_t col;
         if (color_override) {
             col = color_override[v];
@@ -1212,7 +1285,7 @@ __global__ void __launch_bounds__(256) classify_kernel(int32_t n, const int64_t*
                 col = 0;
             }
         } else {
-            col = static_cast<int32_t>(mix64(hc ^ static_cast<uint64_t>(static_cast<uint32_t>(v))) %
+            col = static_cast<int32_t>(mix64(hcv ^ static_cast<uint64_t>(static_cast<uint32_t>(lv))) %
                                        static_cast<uint64_t>(nsub));
         }
         const int32_t bucket = d <= th0   ? 0
@@ -1222,7 +1295,7 @@ __global__ void __launch_bounds__(256) classify_kernel(int32_t n, const int64_t*
                                : d <= th4 ? 4
                                : d <= th5 ? 5
                                           : kHubBucket;
-        const int32_t cat = d == 0 ? ncat : col * kNB + bucket;
+        const int32_t cat = (d == 0 || !act) ? ncat : col * kNB + bucket;
         keys[v] = static_cast<uint64_t>(cat);
         vals[v] = static_cast<uint32_t>(v);
         atomicAdd(&hist[cat], 1u);
@@ -1243,6 +1316,19 @@ __global__ void gather_rows_kernel(const int32_t* __restrict__ nodes, int32_t co
         rows[2 * i] = xadj[nodes[i]];
         rows[2 * i + 1] = xadj[nodes[i] + 1] - xadj[nodes[i]];
     }
+}
+
+// Per-graph hash prefixes H(seed_g, tag, level, phase[, round]).
+__global__ void graph_prefix_kernel(int32_t G, const uint64_t* __restrict__ seed, uint64_t tag, uint64_t level,
+                                    uint64_t phase, int64_t round, uint64_t* __restrict__ out) {
+    const int32_t g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= G) return;
+    uint64_t h = mix64(seed[g]);
+    h = mix64(h ^ tag);
+    h = mix64(h ^ level);
+    h = mix64(h ^ phase);
+    if (round >= 0) h = mix64(h ^ static_cast<uint64_t>(round));
+    out[g] = h;
 }
 
 template <bool kSmall>
@@ -1310,7 +1396,7 @@ void label_weights(const DevGraph& g, const int32_t* label, int32_t* w, int32_t 
 
 LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, int32_t nsub, int32_t rounds,
                 int64_t bound, int32_t* label, int32_t* w, int32_t nw, const int32_t* color_override,
-                const LPTuning& tune, hipStream_t s) {
+                const LPTuning& tune, hipStream_t s, const MultiGraph* mg) {
     LPResult res;
     const int32_t n = g.n;
     if (n == 0 || rounds <= 0) return res;
@@ -1337,9 +1423,20 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     HIPCHK(hipMemsetAsync(ctr.get(), 0, sizeof(Counters), s));
     const uint64_t hc = hash_prefix({seed, 1, static_cast<uint64_t>(static_cast<uint32_t>(level)),
                                      static_cast<uint64_t>(static_cast<uint32_t>(phase))});
+    const uint64_t lvl64 = static_cast<uint64_t>(static_cast<uint32_t>(level));
+    const uint64_t ph64 = static_cast<uint64_t>(static_cast<uint32_t>(phase));
+    DBuf<uint64_t> g_hc, g_tp;
+    if (mg) {
+        g_hc.alloc(std::max(mg->G, 1), s);
+        g_tp.alloc(std::max(mg->G, 1), s);
+        graph_prefix_kernel<<<grid_for(mg->G, 256), 256, 0, s>>>(mg->G, mg->seed, 1, lvl64, ph64, -1, g_hc.get());
+        LAUNCHCHK();
+    }
     {
         ProfScope ps("lp_schedule", 0, s);
-        classify_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, g.xadj, color_override, hc, nsub, th0, th1, th2, th3, th4, th5,
+        classify_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, g.xadj, color_override, hc, mg ? mg->gid : nullptr,
+                                                         g_hc.get(), mg ? mg->nbase : nullptr,
+                                                         mg ? mg->active : nullptr, nsub, th0, th1, th2, th3, th4, th5,
                                                          ckeys.get(), order.get(), cat_count.get(), cat_slots.get(),
                                                          ctr.get());
         LAUNCHCHK();
@@ -1480,9 +1577,9 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     DBuf<uint32_t> lhist(max_large * 256, s);
     DBuf<uint64_t> lprefix(max_large, s);
     DBuf<int64_t> lroom(max_large, s);
-    DBuf<uint32_t> ldone(1, s);
+    DBuf<uint32_t> ldone(max_large, s);
     fill_u32(lhist.get(), 0, max_large * 256, s);
-    fill_u32(ldone.get(), 0, 1, s);
+    fill_u32(ldone.get(), 0, max_large, s);
     LargeSel LS{large_list.get(), chunk_first.get(), lhist.get(), lprefix.get(), lroom.get(), ldone.get()};
     // digits of the selection key: node id bits plus at most 32 bits of gain range
     const int max_sel_passes = (bits_for(static_cast<uint64_t>(n - 1)) + 32 + 7) / 8;
@@ -1500,6 +1597,11 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     A.w = w;
     A.bound = bound;
     A.refine = phase == kRefine ? 1 : 0;
+    A.gid = mg ? mg->gid : nullptr;
+    A.g_tp = g_tp.get();
+    A.g_bound = mg ? mg->bound : nullptr;
+    A.g_lbase = mg ? mg->lbase : nullptr;
+    const Bounds BB{bound, mg ? mg->lgid : nullptr, mg ? mg->bound : nullptr};
 
     // Algorithmic bytes of one evaluation launch: per node its schedule entry,
     // row offsets, own label and weight (and w(own) when refining) and its
@@ -1515,6 +1617,10 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     const int bits_v = bits_for(static_cast<uint64_t>(n - 1));
 
     for (int32_t r = 0; r < rounds; ++r) {
+        if (mg) {
+            graph_prefix_kernel<<<grid_for(mg->G, 256), 256, 0, s>>>(mg->G, mg->seed, 2, lvl64, ph64, r, g_tp.get());
+            LAUNCHCHK();
+        }
         A.tp = hash_prefix({seed, 2, static_cast<uint64_t>(static_cast<uint32_t>(level)),
                             static_cast<uint64_t>(static_cast<uint32_t>(phase)),
                             static_cast<uint64_t>(static_cast<uint32_t>(r))});
@@ -1628,7 +1734,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                     cand_accum_kernel<false><<<gc, 256, 0, s>>>(ct.get(), cnodes, ccount, g.vw, tsum.get(),
                                                                 tcnt.get(), nw, ctr.get());
                 LAUNCHCHK();
-                admit_kernel<<<gc, 256, 0, s>>>(ct.get(), cg.get(), ccount, w, tsum.get(), bound, ok.get(),
+                admit_kernel<<<gc, 256, 0, s>>>(ct.get(), cg.get(), ccount, w, tsum.get(), BB, ok.get(),
                                                 slow_idx.get(), ctr.get());
                 LAUNCHCHK();
             }
@@ -1636,7 +1742,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 ProfScope ps("lp_admit_select", 0, s);
                 const unsigned gc = capped_grid(ccount);
                 if (small) {
-                    claim_small_kernel<<<grid_for(nw, 256), 256, 0, s>>>(nw, w, tsum.get(), tcnt.get(), bound,
+                    claim_small_kernel<<<grid_for(nw, 256), 256, 0, s>>>(nw, w, tsum.get(), tcnt.get(), BB,
                                                                          seg_off.get(), seg_list.get(),
                                                                          large_list.get(), small_max, ctr.get());
                     LAUNCHCHK();
@@ -1652,10 +1758,10 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                                                              swt.get(), ctr.get());
                 }
                 LAUNCHCHK();
-                large_setup_kernel<<<1, 1, 0, s>>>(LS, tcnt.get(), w, bound, ctr.get());
+                large_setup_kernel<<<1, 1, 0, s>>>(LS, tcnt.get(), w, BB, ctr.get());
                 LAUNCHCHK();
                 select_kernel<<<kMaxBlocks, 256, 0, s>>>(seg_list.get(), seg_off.get(), seg_fill.get(), tcnt.get(), w,
-                                                         bound, bits_v, skey.get(), spos.get(), swt.get(), ok.get(),
+                                                         BB, bits_v, skey.get(), spos.get(), swt.get(), ok.get(),
                                                          small_max, ctr.get());
                 LAUNCHCHK();
                 for (int pass = max_sel_passes - 1; pass >= 0; --pass) {

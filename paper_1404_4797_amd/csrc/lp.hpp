@@ -26,6 +26,20 @@ struct LPTuning {
     int32_t select_small_max = 4096;  // larger overflow segments: multi-workgroup selection
 };
 
+// Several disjoint graphs in one CSR (node ranges per graph, no edge between
+// ranges).  Every hash and order uses graph-local ids and the graph's own
+// seed and bound, so each graph's result equals its result alone.
+struct MultiGraph {
+    int32_t G = 0;
+    const int32_t* gid = nullptr;     // [n] graph of each node
+    const int32_t* lgid = nullptr;    // [nw] graph of each label
+    const int32_t* nbase = nullptr;   // [G] first node of each graph
+    const int32_t* lbase = nullptr;   // [G] first label of each graph
+    const int64_t* bound = nullptr;   // [G] bound of each graph's labels
+    const uint64_t* seed = nullptr;   // [G]
+    const uint8_t* active = nullptr;  // [G] nodes of inactive graphs never move
+};
+
 struct LPResult {
     int32_t rounds_run = 0;
     int64_t visits = 0;
@@ -37,7 +51,7 @@ struct LPResult {
 // x).  `color_override` is a device array or null.
 LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, int32_t nsub, int32_t rounds,
                 int64_t bound, int32_t* label, int32_t* w, int32_t nw, const int32_t* color_override,
-                const LPTuning& tune, hipStream_t s);
+                const LPTuning& tune, hipStream_t s, const MultiGraph* mg = nullptr);
 
 // w[x] = sum of c(v) over label(v) = x, for x in [0, nw).
 void label_weights(const DevGraph& g, const int32_t* label, int32_t* w, int32_t nw, hipStream_t s);

@@ -57,7 +57,7 @@ def test_struct_layouts_match_c(tmp_path):
     sc, _ = _lib()
     import subprocess
     structs = {"sclap_graph": sc.Graph, "sclap_graph_owned": sc.GraphOwned, "sclap_options": sc.Options,
-               "sclap_stats": sc.Stats}
+               "sclap_stats": sc.Stats, "sclap_batch_stats": sc.BatchStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sclap.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
@@ -120,3 +120,20 @@ def test_initial_partition_unsorted_rows():
         g["adjncy"][b:e] = g["adjncy"][b:e][rng.permutation(e - b)]
     T = -(-g["n"] // 4)
     assert np.array_equal(sc.initial_partition(g, 4), oracle.initial_partition(g, 4, T))
+
+
+def test_union_builder():
+    # the host-side batch builder: graph i's ids shift by the nodes before it
+    sc, _ = _lib()
+    import synth
+    gs = [synth.ba(30, 2, seed=1, weighted=True), synth.from_edges(0, []), synth.rgg(40, seed=2)]
+    u, nb = sc.union(gs)
+    assert list(nb) == [0, 30, 30, 70]
+    for i, g in enumerate(gs):
+        lo, hi = nb[i], nb[i + 1]
+        x = u["xadj"][lo:hi + 1] - u["xadj"][lo]
+        assert np.array_equal(x, g["xadj"])
+        a = u["adjncy"][u["xadj"][lo]:u["xadj"][hi]] - lo
+        assert np.array_equal(a, g["adjncy"])
+        assert np.array_equal(u["adjwgt"][u["xadj"][lo]:u["xadj"][hi]],
+                              g["adjwgt"] if g.get("adjwgt") is not None else np.ones(len(a), np.int32))
