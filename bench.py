@@ -139,6 +139,68 @@ def batch_comparison(ngraphs, seed, log_lo, log_hi):
             "levels_max": r["stats"]["levels"]}
 
 
+def serve_benchmark(nreq, log_lo, log_hi, fracs, plain_sample):
+    """Poisson arrivals of partition requests (the batch mix's graph
+    distribution) at fixed rates, given as multiples of the plain path's
+    throughput on the same distribution; reports p50/p99 latency (arrival to
+    result) and graphs/s of the continuous-batching server."""
+    import threading
+    import numpy as np
+    import torch
+    import synth
+    import paper_1404_4797_amd as sc
+    t = time.time()
+    gs = synth.batch_mix(nreq, seed=7, n_lo_log2=log_lo, n_hi_log2=log_hi)
+    log("serve mix: %d requests, n=%d generated in %.1fs" % (nreq, sum(g["n"] for g in gs), time.time() - t))
+    # plain path (one graph per call, graph already on the device) on a sample
+    plain = {}
+    t_plain = 0.0
+    for i in range(min(plain_sample, nreq)):
+        d = sc.to_device(gs[i], "cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = sc.partition_dev(d, gs[i]["k"], gs[i]["eps"], gs[i]["seed"])
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t0
+        plain[i] = r["cut"]
+    plain_gps = len(plain) / t_plain
+    log("plain: %.1f graphs/s on %d requests" % (plain_gps, len(plain)))
+    rng = np.random.default_rng(7)
+    runs = []
+    same = True
+    with sc.Server(slots=3, max_batch=64) as sv:
+        sv.wait(sv.submit(gs[0], gs[0]["k"], gs[0]["eps"], gs[0]["seed"]))  # warm up the workers
+        for f in fracs:
+            qps = f * plain_gps
+            gaps = rng.exponential(1.0 / qps, size=nreq)
+            ids = [None] * nreq
+
+            def producer():
+                t_next = time.perf_counter()
+                for i, g in enumerate(gs):
+                    t_next += gaps[i]
+                    dt = t_next - time.perf_counter()
+                    if dt > 0:
+                        time.sleep(dt)
+                    ids[i] = sv.submit(g, g["k"], g["eps"], g["seed"])
+
+            th = threading.Thread(target=producer)
+            th.start()
+            th.join()
+            res = [sv.wait(i) for i in ids]
+            lat = np.array([r["done_ms"] - r["submit_ms"] for r in res])
+            span = (max(r["done_ms"] for r in res) - min(r["submit_ms"] for r in res)) / 1000.0
+            for i, c in plain.items():
+                same &= res[i]["cut"] == c
+            runs.append({"rate_vs_plain": f, "offered_qps": round(qps, 2), "graphs_per_s": round(nreq / span, 2),
+                         "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                         "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                         "mean_batch": round(float(np.mean([r["batch_size"] for r in res])), 2)})
+            log("serve at %.1fx plain (%.1f qps): %s" % (f, qps, runs[-1]))
+    return {"requests": nreq, "n_log2_range": [log_lo, log_hi], "plain_graphs_per_s": round(plain_gps, 2),
+            "plain_sample": len(plain), "identical_cuts_on_sample": bool(same), "runs": runs}
+
+
 def copy_calibration(nbytes):
     """A plain device copy of known size, for scaling HBM counters."""
     import torch
@@ -160,6 +222,10 @@ def main():
     ap.add_argument("--copy-calib", type=int, default=0, help="bytes for a plain copy kernel (counter scaling)")
     ap.add_argument("--batch-graphs", type=int, default=512, help="graphs in the batched-vs-plain comparison (0: skip)")
     ap.add_argument("--batch-log2", type=int, nargs=2, default=[10, 18], help="log2 range of n in the batch")
+    ap.add_argument("--serve-requests", type=int, default=120, help="requests per serving run (0: skip)")
+    ap.add_argument("--serve-log2", type=int, nargs=2, default=[10, 20], help="log2 range of n of the requests")
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[0.5, 0.8, 4.0],
+                    help="arrival rates as multiples of the plain path's graphs/s")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build partitions on one GPU; --gpus %d is not supported "
@@ -247,6 +313,9 @@ def main():
     }
     if args.batch_graphs > 0:
         out["batched"] = batch_comparison(args.batch_graphs, 0, args.batch_log2[0], args.batch_log2[1])
+    if args.serve_requests > 0:
+        out["serving"] = serve_benchmark(args.serve_requests, args.serve_log2[0], args.serve_log2[1],
+                                         args.serve_rates, plain_sample=24)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample) ...")
         out["cpu_baseline"] = cpu_baseline(g, w)

@@ -242,6 +242,48 @@ int sclap_partition_batch_dev(const sclap_graph* g, int32_t count, const int32_t
                               int64_t* cut, int64_t* block_w, sclap_batch_stats* stats, void* stream);
 
 /*
+ * Serving: continuous batching of partition requests on one GPU (the batched
+ * partitioner above behind a request queue).  sclap_server_submit copies the
+ * request's host graph into the server and queues it; `slots` worker threads,
+ * each with its own HIP stream, repeatedly take the longest queue prefix
+ * (at most max_batch graphs) whose device-memory footprint fits the free part
+ * of hbm_budget and partition it as one batch, so requests that arrive while
+ * others run are admitted as soon as a slot and memory are free, and their
+ * work overlaps on the device.  Footprint of a request: 64 B per node plus
+ * 64 B per adjacency slot plus 4 MiB; a request larger than the budget is
+ * refused (SCLAP_ERR_NO_MEMORY), a full queue returns SCLAP_ERR_BUSY.  Each
+ * result equals sclap_partition of that graph alone with the server's options.
+ *
+ * sclap_server_create: device index, hbm_budget in bytes (<= 0: 80% of the
+ * device memory free at creation), slots in 1..16, max_batch >= 1; returns
+ * NULL on error (see sclap_last_error).
+ * sclap_server_poll: waits up to timeout_ms (0: no wait, < 0: until done);
+ * *done = 0 while the request runs (nothing written), else writes part[n],
+ * *cut, block_w[k] (host; any may be NULL) and info (may be NULL), releases
+ * the request and returns its status (a request's errors are reported here).
+ * sclap_server_destroy waits for running batches and drops queued requests;
+ * no other call on the server may run concurrently with it.  The other calls
+ * are thread-safe.
+ */
+typedef struct sclap_server sclap_server;
+
+typedef struct {
+    double submit_ms;   /* times since the server's creation */
+    double start_ms;    /* batch taken up by a worker */
+    double done_ms;     /* results stored */
+    int32_t batch_size; /* graphs in the request's batch */
+    int32_t reserved;
+} sclap_request_info;
+
+sclap_server* sclap_server_create(int32_t device, int64_t hbm_budget, int32_t slots, int32_t max_batch,
+                                  const sclap_options* opt);
+int sclap_server_submit(sclap_server* sv, const sclap_graph* g, int32_t k, double eps, uint64_t seed,
+                        uint64_t* req);
+int sclap_server_poll(sclap_server* sv, uint64_t req, int32_t timeout_ms, int32_t* done, int32_t* part,
+                      int64_t* cut, int64_t* block_w, sclap_request_info* info);
+void sclap_server_destroy(sclap_server* sv);
+
+/*
  * Instrumentation.  sclap_profile_begin() starts timing every kernel launch
  * that later calls on this thread issue, with HIP events recorded on the
  * launching stream around each launch; sclap_profile_end() stops, writes up to

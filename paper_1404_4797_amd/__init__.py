@@ -35,6 +35,7 @@ EXPORTS = [
     "sclap_initial_partition",
     "sclap_partition", "sclap_partition_dev",
     "sclap_partition_batch", "sclap_partition_batch_dev",
+    "sclap_server_create", "sclap_server_submit", "sclap_server_poll", "sclap_server_destroy",
     "sclap_profile_begin", "sclap_profile_end",
 ]
 
@@ -99,6 +100,11 @@ class BatchStats(ctypes.Structure):
                 "ms_initial": self.ms_initial, "ms_refine": self.ms_refine, "ms_lp": self.ms_lp}
 
 
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("submit_ms", ctypes.c_double), ("start_ms", ctypes.c_double), ("done_ms", ctypes.c_double),
+                ("batch_size", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 def load():
     """Loads libsclap.so (built by ``__graft_entry__.build()``)."""
     global _lib
@@ -134,6 +140,10 @@ def load():
         "sclap_partition": (ctypes.c_int, [G, i32, dbl, u64, O, vp, vp, vp, ST]),
         "sclap_partition_dev": (ctypes.c_int, [G, i32, dbl, u64, O, vp, vp, vp, ST, vp]),
         "sclap_partition_batch": (ctypes.c_int, [G, i32, vp, vp, vp, vp, O, vp, vp, vp, BST]),
+        "sclap_server_create": (vp, [i32, i64, i32, i32, O]),
+        "sclap_server_submit": (ctypes.c_int, [vp, G, i32, dbl, u64, vp]),
+        "sclap_server_poll": (ctypes.c_int, [vp, u64, i32, vp, vp, vp, vp, ctypes.POINTER(RequestInfo)]),
+        "sclap_server_destroy": (None, [vp]),
         "sclap_partition_batch_dev": (ctypes.c_int, [G, i32, vp, vp, vp, vp, O, vp, vp, vp, BST, vp]),
         "sclap_profile_begin": (ctypes.c_int, []),
         "sclap_profile_end": (ctypes.c_int, [ctypes.POINTER(KernelStat), i32, vp]),
@@ -527,3 +537,70 @@ def partition_batch_dev(d, node_base, k, eps, seed, part=None, stream=None, opts
                                                      ctypes.byref(st), _stream(stream)), allow_warn=True)
     return {"part": part, "cut": cut, "block_weights": bw, "levels": levels, "status": status,
             "stats": st.to_dict()}
+
+
+# ------------------------------------------------------------------ serving
+
+class Server:
+    """Continuous-batching partition server on one GPU (see sclap.h).
+
+    submit() copies the graph and returns a request id; poll() returns None
+    while the request runs, else dict(part, cut, block_weights, status,
+    submit_ms, start_ms, done_ms, batch_size).  A failed request raises
+    SclapError from poll()."""
+
+    def __init__(self, device=0, hbm_budget=0, slots=2, max_batch=64, **opts):
+        L = load()
+        self._o = _opts(opts)
+        self._p = L.sclap_server_create(device, hbm_budget, slots, max_batch, ctypes.byref(self._o))
+        if not self._p:
+            raise SclapError(ERR_INVALID, last_error())
+        self._meta = {}
+
+    def submit(self, g, k, eps=0.03, seed=1):
+        hg = _HostGraph(g)
+        rid = ctypes.c_uint64(0)
+        _check(load().sclap_server_submit(self._p, hg.ref, k, eps, seed, ctypes.addressof(rid)))
+        self._meta[rid.value] = (hg.n, k)
+        return rid.value
+
+    def poll(self, rid, timeout_ms=0):
+        n, k = self._meta[rid]
+        done = ctypes.c_int32(0)
+        part = np.empty(max(n, 1), dtype=np.int32)
+        cut = ctypes.c_int64(0)
+        bw = np.zeros(k, dtype=np.int64)
+        info = RequestInfo()
+        try:
+            status = _check(load().sclap_server_poll(self._p, rid, timeout_ms, ctypes.addressof(done),
+                                                     part.ctypes.data, ctypes.addressof(cut), bw.ctypes.data,
+                                                     ctypes.byref(info)), allow_warn=True)
+        except SclapError:
+            self._meta.pop(rid, None)
+            raise
+        if not done.value:
+            return None
+        del self._meta[rid]
+        return {"part": part[:n], "cut": cut.value, "block_weights": bw, "status": status,
+                "submit_ms": info.submit_ms, "start_ms": info.start_ms, "done_ms": info.done_ms,
+                "batch_size": info.batch_size}
+
+    def wait(self, rid):
+        return self.poll(rid, timeout_ms=-1)
+
+    def close(self):
+        if self._p:
+            load().sclap_server_destroy(self._p)
+            self._p = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

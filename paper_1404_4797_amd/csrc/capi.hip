@@ -1,5 +1,5 @@
-// C ABI (include/sclap.h): argument checks, the multilevel driver and the
-// host initial partitioner around the gfx950 kernels.
+// C ABI (include/sclap.h): argument checks and host/device staging around the
+// gfx950 kernels and the multilevel drivers.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -15,9 +15,8 @@
 #include <utility>
 #include <vector>
 
-#include "graph_ops.hpp"
+#include "driver.hpp"
 #include "profile.hpp"
-#include "sclap.h"
 
 namespace sclap {
 
@@ -66,80 +65,9 @@ void* dev_alloc(size_t bytes, hipStream_t s) {
 
 void dev_free(void* p, hipStream_t s) { (void)hipFreeAsync(p, s); }
 
-// ----------------------------------------------------------------- options
-
 namespace {
 
-struct Opts {
-    int32_t coarsen_rounds = 10;
-    int32_t refine_rounds = 10;
-    int32_t nsub = 4;
-    int32_t divisor = 18;
-    int32_t coarsest = 10000;
-    int32_t max_levels = SCLAP_MAX_LEVELS;
-    int32_t validate = 1;
-    const int32_t* color_override = nullptr;
-    LPTuning tune;
-};
-
-Opts resolve(const sclap_options* o) {
-    Opts r;
-    if (!o) return r;
-    r.coarsen_rounds = o->coarsen_rounds;
-    r.refine_rounds = o->refine_rounds;
-    r.nsub = o->subrounds;
-    r.divisor = o->cluster_divisor;
-    r.coarsest = o->coarsest_nodes;
-    r.max_levels = o->max_levels;
-    r.validate = o->validate;
-    r.color_override = o->color_override;
-    if (o->lane_max_degree > 0) r.tune.lane_max = o->lane_max_degree;
-    if (o->wave_max_degree > 0) r.tune.wave_max = o->wave_max_degree;
-    if (o->block_max_degree > 0) r.tune.block_max = o->block_max_degree;
-    if (o->hub_part_limit > 0) r.tune.hub_part_limit = o->hub_part_limit;
-    if (o->hub_region_cap > 0) r.tune.hub_region_cap = o->hub_region_cap;
-    if (o->select_small_max > 0) r.tune.select_small_max = o->select_small_max;
-    if (r.coarsen_rounds < 0 || r.refine_rounds < 0) fail(SCLAP_ERR_INVALID, "round counts must be >= 0");
-    if (r.nsub < 1 || r.nsub > 16) fail(SCLAP_ERR_INVALID, "subrounds must be in 1..16");
-    if (r.divisor < 1) fail(SCLAP_ERR_INVALID, "cluster_divisor must be >= 1");
-    if (r.coarsest < 0) fail(SCLAP_ERR_INVALID, "coarsest_nodes must be >= 0");
-    if (r.max_levels < 0 || r.max_levels > SCLAP_MAX_LEVELS) fail(SCLAP_ERR_INVALID, "max_levels must be in 0..64");
-    return r;
-}
-
 hipStream_t as_stream(void* p) { return reinterpret_cast<hipStream_t>(p); }
-
-// Device view of a caller graph with device pointers; reads S = xadj[n].
-DevGraph dev_view(const sclap_graph* g, hipStream_t s) {
-    if (!g) fail(SCLAP_ERR_INVALID, "graph is NULL");
-    if (g->n < 0) fail(SCLAP_ERR_INVALID, "n < 0");
-    DevGraph d;
-    d.n = g->n;
-    d.xadj = g->xadj;
-    d.adj = g->adjncy;
-    d.ew = g->adjwgt;
-    d.vw = g->vwgt;
-    if (g->n > 0) {
-        if (!g->xadj) fail(SCLAP_ERR_INVALID, "xadj is NULL");
-        HIPCHK(hipMemcpyAsync(&d.S, g->xadj + g->n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (d.S < 0) fail(SCLAP_ERR_INVALID, "xadj[n] < 0");
-        if (d.S > 0 && !g->adjncy) fail(SCLAP_ERR_INVALID, "adjncy is NULL");
-    }
-    return d;
-}
-
-void check_graph(const DevGraph& g, bool validate, int64_t* cV, int64_t* cmax, hipStream_t s) {
-    if (validate) {
-        const int st = validate_graph(g, cV, cmax, s);
-        if (st == SCLAP_ERR_INVALID) fail(st, "invalid graph (offsets, ids, self-loops or weights)");
-        if (st == SCLAP_ERR_NOT_SYMMETRIC) fail(st, "graph is not symmetric");
-        if (st == SCLAP_ERR_OVERFLOW) fail(st, "node or edge weight total exceeds 2^31-1");
-        if (st != 0) fail(st, "graph validation failed");
-    } else {
-        node_weight_stats(g, cV, cmax, s);
-    }
-}
 
 template <typename F>
 int guarded(F&& f) {
@@ -156,657 +84,6 @@ int guarded(F&& f) {
         t_err = e.what();
         return SCLAP_ERR_HIP;
     }
-}
-
-int64_t lmax_of(int64_t cV, int32_t k, double eps) {
-    const int64_t T = (cV + k - 1) / k;
-    const int64_t ppm = std::llround(eps * 1e6);
-    return T + (T * ppm) / 1000000;
-}
-
-void check_k_eps(int32_t k, double eps) {
-    if (k < 1) fail(SCLAP_ERR_INVALID, "k must be >= 1");
-    if (!(eps >= 0.0) || eps > 1000.0) fail(SCLAP_ERR_INVALID, "eps must be in [0, 1000]");
-}
-
-// ------------------------------------------------- host initial partition
-
-// Smallest index >= from whose value is <= cap, over a segment tree of mins.
-struct MinTree {
-    int64_t size = 1;
-    std::vector<int64_t> t;
-    explicit MinTree(const std::vector<int64_t>& a) {
-        while (size < static_cast<int64_t>(a.size())) size <<= 1;
-        t.assign(2 * static_cast<size_t>(size), INT64_MAX);
-        for (size_t i = 0; i < a.size(); ++i) t[size + i] = a[i];
-        for (int32_t i = size - 1; i > 0; --i) t[i] = std::min(t[2 * i], t[2 * i + 1]);
-    }
-    void erase(int64_t i) {
-        int64_t p = i + size;
-        t[p] = INT64_MAX;
-        for (p >>= 1; p > 0; p >>= 1) t[p] = std::min(t[2 * p], t[2 * p + 1]);
-    }
-    int32_t first_le(int64_t from, int64_t cap) const { return static_cast<int32_t>(descend(1, 0, size, from, cap)); }
-    int64_t min() const { return t[1]; }
-    int64_t descend(int64_t node, int64_t lo, int64_t hi, int64_t from, int64_t cap) const {
-        if (hi <= from || t[node] > cap) return -1;
-        if (hi - lo == 1) return lo;
-        const int64_t mid = (lo + hi) / 2;
-        const int64_t r = descend(2 * node, lo, mid, from, cap);
-        return r >= 0 ? r : descend(2 * node + 1, mid, hi, from, cap);
-    }
-};
-
-// Binary min-heap of packed (weight << 32 | block) keys: the lightest block,
-// lowest id on ties, is at the root.
-struct BlockHeap {
-    std::vector<uint64_t> h;
-    static uint64_t key(int64_t w, int32_t b) { return (static_cast<uint64_t>(w) << 32) | static_cast<uint32_t>(b); }
-    explicit BlockHeap(const std::vector<int64_t>& wb) {
-        for (size_t b = 0; b < wb.size(); ++b) h.push_back(key(wb[b], static_cast<int32_t>(b)));
-        std::make_heap(h.begin(), h.end(), std::greater<uint64_t>());
-    }
-    int32_t top() const { return static_cast<int32_t>(h[0] & 0xFFFFFFFFu); }
-    // adds c to the root's weight and restores the heap order
-    void add_to_top(int64_t c) {
-        if (c == 0) return;
-        const uint64_t x = h[0] + (static_cast<uint64_t>(c) << 32);
-        size_t i = 0;
-        const size_t n = h.size();
-        while (true) {
-            size_t l = 2 * i + 1;
-            if (l >= n) break;
-            if (l + 1 < n && h[l + 1] < h[l]) ++l;
-            if (h[l] >= x) break;
-            h[i] = h[l];
-            i = l;
-        }
-        h[i] = x;
-    }
-};
-
-// Grows blocks 0..k-2 by breadth-first search up to T each (seeds: smallest
-// unassigned node of positive degree that fits; neighbours in ascending id
-// order), then deals every remaining node, in id order, to the currently
-// lightest block (lowest id on ties).  Weights fit 31 bits (c(V) <= 2^31-1).
-void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, const int32_t* vw, int32_t k,
-                            int64_t T, int32_t* part, bool rows_sorted = false) {
-    std::fill(part, part + n, -1);
-    std::vector<uint64_t> taken((static_cast<size_t>(n) + 63) / 64, 0);  // 1 bit per node, cache resident
-    std::vector<int64_t> wb(static_cast<size_t>(k), 0);
-    // seed candidates: nodes of positive degree, in id order
-    std::vector<int32_t> seed_node;
-    std::vector<int64_t> seed_w;
-    std::vector<int32_t> seed_pos(static_cast<size_t>(n), -1);
-    for (int32_t v = 0; v < n; ++v)
-        if (xadj[v + 1] > xadj[v]) {
-            seed_pos[v] = static_cast<int32_t>(seed_node.size());
-            seed_node.push_back(v);
-            seed_w.push_back(vw ? vw[v] : 1);
-        }
-    MinTree seeds(seed_w);
-    std::vector<int32_t> nb;
-    std::deque<int32_t> q;
-    auto take = [&](int32_t v, int32_t b) {
-        part[v] = b;
-        taken[static_cast<size_t>(v) >> 6] |= 1ULL << (v & 63);
-        wb[b] += vw ? vw[v] : 1;
-        if (seed_pos[v] >= 0) seeds.erase(seed_pos[v]);
-    };
-    for (int32_t b = 0; b + 1 < k; ++b) {
-        int32_t from = 0;
-        while (true) {
-            const int32_t si = seeds.first_le(from, T - wb[b]);
-            if (si < 0) break;
-            const int32_t sd = seed_node[si];
-            take(sd, b);
-            q.push_back(sd);
-            while (!q.empty()) {
-                // every node a search can reach has positive degree, so once
-                // the lightest such unassigned node does not fit, stop
-                if (seeds.min() > T - wb[b]) {
-                    q.clear();
-                    break;
-                }
-                const int32_t u = q.front();
-                q.pop_front();
-                const int32_t* row = adj + xadj[u];
-                const int32_t* row_end = adj + xadj[u + 1];
-                if (!rows_sorted && !std::is_sorted(row, row_end)) {
-                    nb.assign(row, row_end);
-                    std::sort(nb.begin(), nb.end());
-                    row = nb.data();
-                    row_end = nb.data() + nb.size();
-                }
-                for (const int32_t* it = row; it != row_end; ++it) {
-                    const int32_t x = *it;
-                    if ((taken[static_cast<size_t>(x) >> 6] >> (x & 63)) & 1ULL) continue;
-                    if (wb[b] + (vw ? vw[x] : 1) > T) continue;
-                    take(x, b);
-                    q.push_back(x);
-                }
-            }
-            from = si + 1;
-        }
-    }
-    // Step 2: every remaining node, in id order, to the lightest block.
-    // Within a run of nodes of equal weight c > 0, the blocks whose weight
-    // lies within c of the lightest form a group that receives nodes
-    // cyclically in (weight, id) order, one per block per pass, until the next
-    // heavier block X is due; the number of nodes before that is the count of
-    // group values (w_g + j c, g) below (w_X, X).  X then joins and the group
-    // is recomputed.  The result equals dealing node by node.
-    std::vector<int32_t> rest;
-    rest.reserve(static_cast<size_t>(n));
-    for (int32_t v = 0; v < n; ++v)
-        if (part[v] < 0) rest.push_back(v);
-    auto cw = [&](int32_t v) -> int64_t { return vw ? vw[v] : 1; };
-    std::vector<int32_t> ord(static_cast<size_t>(k));
-    size_t i = 0;
-    while (i < rest.size()) {
-        const int64_t c = cw(rest[i]);
-        size_t j = i;
-        while (j < rest.size() && cw(rest[j]) == c) ++j;
-        if (c == 0 || k > 4096) {  // node by node
-            BlockHeap heap(wb);
-            for (; i < j; ++i) {
-                const int32_t b = heap.top();
-                part[rest[i]] = b;
-                wb[b] += c;
-                heap.add_to_top(c);
-            }
-            continue;
-        }
-        while (i < j) {
-            for (int32_t b = 0; b < k; ++b) ord[b] = b;
-            std::sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
-                return wb[x] != wb[y] ? wb[x] < wb[y] : x < y;
-            });
-            const int64_t m0 = wb[ord[0]];
-            int32_t gsz = 1;
-            while (gsz < k && wb[ord[gsz]] < m0 + c) ++gsz;
-            size_t take = j - i;
-            if (gsz < k) {
-                const int32_t X = ord[gsz];
-                const int64_t wx = wb[X];
-                uint64_t before = 0;
-                for (int32_t t = 0; t < gsz; ++t) {
-                    const int32_t g = ord[t];
-                    const int64_t d = wx - wb[g];
-                    before += static_cast<uint64_t>((d + c - 1) / c + ((d % c == 0 && g < X) ? 1 : 0));
-                }
-                take = std::min<size_t>(take, static_cast<size_t>(before));
-            }
-            int32_t pos = 0;
-            for (size_t t = 0; t < take; ++t) {
-                const int32_t b = ord[pos];
-                part[rest[i + t]] = b;
-                wb[b] += c;
-                if (++pos == gsz) pos = 0;
-            }
-            i += take;
-        }
-    }
-}
-
-// ------------------------------------------------------------ multilevel
-
-struct Level {
-    OwnedDevGraph own;
-    DevGraph g;
-    DBuf<int32_t> C;  // map to the next coarser level
-};
-
-using Clock = std::chrono::steady_clock;
-double ms_since(Clock::time_point t) { return std::chrono::duration<double, std::milli>(Clock::now() - t).count(); }
-
-int partition_impl(const DevGraph& g0, int32_t k, double eps, uint64_t seed, const Opts& o, int32_t* part_out,
-                   int64_t* cut, int64_t* bw, sclap_stats* stats, hipStream_t s) {
-    check_k_eps(k, eps);
-    if (!part_out && g0.n > 0) fail(SCLAP_ERR_INVALID, "part is NULL");
-    if (!cut || !bw) fail(SCLAP_ERR_INVALID, "cut / block_w is NULL");
-    int64_t cV = 0, cmax0 = 0;
-    check_graph(g0, o.validate != 0, &cV, &cmax0, s);
-    sclap_stats local;
-    sclap_stats* st = stats ? stats : &local;
-    std::memset(st, 0, sizeof(*st));
-    const int64_t Lmax = lmax_of(cV, k, eps);
-    const int64_t W = cV / (static_cast<int64_t>(o.divisor) * k);
-
-    std::vector<Level> L(1);
-    L[0].g = g0;
-    st->level_n[0] = g0.n;
-    st->level_S[0] = g0.S;
-    auto t_coarsen = Clock::now();
-    double lp_ms = 0;
-    int32_t lev = 0;
-    while (L[lev].g.n > o.coarsest && lev < o.max_levels) {
-        const DevGraph G = L[lev].g;
-        const int32_t n = G.n;
-        int64_t cvl = 0, cmax = cmax0;
-        if (lev > 0) node_weight_stats(G, &cvl, &cmax, s);
-        const int64_t U = std::max(cmax, W);
-        DBuf<int32_t> labels(n, s), w(n, s);
-        iota_u32(reinterpret_cast<uint32_t*>(labels.get()), n, s);
-        label_weights(G, labels.get(), w.get(), n, s);
-        auto t_lp = Clock::now();
-        const LPResult r = run_lp(G, kCluster, lev, seed, o.nsub, o.coarsen_rounds, U, labels.get(), w.get(), n,
-                                  nullptr, o.tune, s);
-        lp_ms += ms_since(t_lp);
-        st->visits += r.visits;
-        st->cluster_rounds[lev] = r.rounds_run;
-        w.release();
-        DBuf<int32_t> C(n, s);
-        Level nx;
-        contract(G, labels.get(), C.get(), nx.own, s);
-        if (nx.own.n >= n) break;  // no shrink: keep the current level as the coarsest
-        L[lev].C = std::move(C);
-        nx.g = nx.own.view();
-        L.push_back(std::move(nx));
-        ++lev;
-        st->level_n[lev] = L[lev].g.n;
-        st->level_S[lev] = L[lev].g.S;
-        if (20LL * L[lev].g.n > 19LL * n) break;  // stalled
-    }
-    st->levels = lev;
-    HIPCHK(hipStreamSynchronize(s));
-    st->ms_coarsen = ms_since(t_coarsen);
-
-    // initial partition of the coarsest graph on the host
-    auto t_init = Clock::now();
-    const DevGraph Gc = L[lev].g;
-    const int32_t nc = Gc.n;
-    std::vector<int64_t> hx(static_cast<size_t>(nc) + 1);
-    std::vector<int32_t> ha(static_cast<size_t>(std::max<int64_t>(Gc.S, 1))), hv, hp(static_cast<size_t>(nc));
-    if (nc > 0) {
-        HIPCHK(hipMemcpyAsync(hx.data(), Gc.xadj, (nc + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        if (Gc.S > 0)
-            HIPCHK(hipMemcpyAsync(ha.data(), Gc.adj, Gc.S * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        if (Gc.vw) {
-            hv.resize(nc);
-            HIPCHK(hipMemcpyAsync(hv.data(), Gc.vw, nc * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        }
-        HIPCHK(hipStreamSynchronize(s));
-    }
-    const int64_t T = (cV + k - 1) / k;
-    // rows of contracted levels are sorted by construction
-    host_initial_partition(nc, hx.data(), ha.data(), Gc.vw ? hv.data() : nullptr, k, T, hp.data(), lev > 0);
-    DBuf<int32_t> cur;
-    int32_t* curp = part_out;
-    if (lev > 0) {
-        cur.alloc(nc, s);
-        curp = cur.get();
-    }
-    if (nc > 0) HIPCHK(hipMemcpyAsync(curp, hp.data(), nc * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
-    st->ms_initial = ms_since(t_init);
-
-    auto t_ref = Clock::now();
-    DBuf<int32_t> w(k, s);
-    for (int32_t l = lev; l >= 0; --l) {
-        const DevGraph G = L[l].g;
-        if (l < lev) {
-            DBuf<int32_t> fine;
-            int32_t* finep = part_out;
-            if (l > 0) {
-                fine.alloc(G.n, s);
-                finep = fine.get();
-            }
-            project(G.n, L[l].C.get(), curp, finep, s);
-            cur = std::move(fine);
-            curp = finep;
-            L[l + 1].own = OwnedDevGraph();  // the coarser graph is no longer needed
-            L[l].C.release();
-        }
-        label_weights(G, curp, w.get(), k, s);
-        auto t_lp = Clock::now();
-        const LPResult r = run_lp(G, kRefine, l, seed, o.nsub, o.refine_rounds, Lmax, curp, w.get(), k, nullptr,
-                                  o.tune, s);
-        lp_ms += ms_since(t_lp);
-        st->visits += r.visits;
-        st->refine_rounds[l] = r.rounds_run;
-    }
-    cut_and_weights(g0, part_out, k, cut, bw, s);
-    st->ms_refine = ms_since(t_ref);
-    st->ms_lp = lp_ms;
-    for (int32_t b = 0; b < k; ++b)
-        if (bw[b] > Lmax) return SCLAP_WARN_IMBALANCED;
-    return SCLAP_OK;
-}
-
-// ------------------------------------------------------------- batches
-//
-// Many graphs partitioned together: the graphs of a batch are one CSR with a
-// node range per graph and no edge between ranges.  Every level runs each
-// kernel once for all graphs; hashes, orders and bounds are per graph
-// (graph-local ids, own seed, U and Lmax), so every graph gets exactly the
-// result it gets alone.  A graph leaves the coarsening loop by its own stop
-// rule; later levels hold only the graphs still coarsening.
-
-struct BatchLevel {
-    OwnedDevGraph own;
-    DevGraph g;
-    std::vector<int32_t> ids;  // batch index of each member graph
-    std::vector<int32_t> nb;   // first node of each member, then n
-    std::vector<int64_t> sb;   // first slot of each member, then S
-    DBuf<int32_t> gid;         // [n] batch index of each node
-    DBuf<int32_t> C;           // [n] node of the next level, -1 where the graph ends here
-};
-
-template <typename T>
-void upload_vec(DBuf<T>& d, const std::vector<T>& h, hipStream_t s) {
-    if (h.empty()) return;
-    HIPCHK(hipMemcpyAsync(d.get(), h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
-}
-
-// Runs f(i) for i in [0, count) on up to `threads` host threads.
-template <typename F>
-void parallel_for(int32_t count, int32_t threads, F f) {
-    threads = std::max(1, std::min(threads, count));
-    if (threads == 1) {
-        for (int32_t i = 0; i < count; ++i) f(i);
-        return;
-    }
-    std::atomic<int32_t> next{0};
-    std::vector<std::exception_ptr> errs(threads);
-    std::vector<std::thread> pool;
-    for (int32_t t = 0; t < threads; ++t)
-        pool.emplace_back([&, t] {
-            try {
-                for (int32_t i = next++; i < count; i = next++) f(i);
-            } catch (...) {
-                errs[t] = std::current_exception();
-            }
-        });
-    for (auto& th : pool) th.join();
-    for (auto& e : errs)
-        if (e) std::rethrow_exception(e);
-}
-
-int partition_batch_impl(const DevGraph& g0, int32_t G, const int32_t* node_base, const int32_t* k,
-                         const double* eps, const uint64_t* seed, const Opts& o, int32_t* part_out, int64_t* cut,
-                         int64_t* bw, sclap_batch_stats* stats, hipStream_t s) {
-    if (G < 1) fail(SCLAP_ERR_INVALID, "count must be >= 1");
-    if (!node_base || !k || !eps || !seed) fail(SCLAP_ERR_INVALID, "node_base, k, eps or seed is NULL");
-    if (node_base[0] != 0 || node_base[G] != g0.n) fail(SCLAP_ERR_INVALID, "node_base must run from 0 to n");
-    std::vector<int32_t> kb(static_cast<size_t>(G) + 1, 0);
-    for (int32_t g = 0; g < G; ++g) {
-        if (node_base[g + 1] < node_base[g]) fail(SCLAP_ERR_INVALID, "node_base must be non-decreasing");
-        check_k_eps(k[g], eps[g]);
-        if (static_cast<int64_t>(kb[g]) + k[g] > (1 << 30)) fail(SCLAP_ERR_INVALID, "sum of k too large");
-        kb[g + 1] = kb[g] + k[g];
-    }
-    const int32_t K = kb[G];
-    if (!part_out && g0.n > 0) fail(SCLAP_ERR_INVALID, "part is NULL");
-    if (!cut || !bw) fail(SCLAP_ERR_INVALID, "cut / block_w is NULL");
-    sclap_batch_stats local;
-    sclap_batch_stats* st = stats ? stats : &local;
-    int32_t* graph_levels = st->graph_levels;
-    std::memset(st, 0, sizeof(*st));
-    st->graph_levels = graph_levels;
-    auto t_coarsen = Clock::now();
-    double lp_ms = 0;
-
-    std::vector<BatchLevel> L(1);
-    {
-        BatchLevel& B = L[0];
-        B.g = g0;
-        B.ids.resize(G);
-        for (int32_t g = 0; g < G; ++g) B.ids[g] = g;
-        B.nb.assign(node_base, node_base + G + 1);
-        B.sb = member_slot_bases(g0.xadj, B.nb, s);
-        B.gid.alloc(std::max(g0.n, 1), s);
-        member_ids(g0.n, B.nb, B.ids, B.gid.get(), s);
-    }
-    if (o.validate) {
-        int64_t cVu = 0, cmu = 0;
-        check_graph(g0, true, &cVu, &cmu, s);
-        if (!members_closed(g0, L[0].nb, L[0].sb, s)) fail(SCLAP_ERR_INVALID, "an edge joins two graphs of the batch");
-    }
-    std::vector<int64_t> cV(G), cmax0(G);
-    graph_node_stats(g0.n, L[0].gid.get(), g0.vw, G, cV.data(), cmax0.data(), s);
-    std::vector<int64_t> Lmax(G), W(G), T(G);
-    for (int32_t g = 0; g < G; ++g) {
-        if (cV[g] > 2147483647LL) fail(SCLAP_ERR_OVERFLOW, "node weight total of a graph exceeds 2^31-1");
-        Lmax[g] = lmax_of(cV[g], k[g], eps[g]);
-        W[g] = cV[g] / (static_cast<int64_t>(o.divisor) * k[g]);
-        T[g] = (cV[g] + k[g] - 1) / k[g];
-    }
-
-    // per-graph device parameters
-    DBuf<uint64_t> d_seed(G, s);
-    DBuf<int64_t> d_bound(G, s);
-    DBuf<int32_t> d_lbase(G, s), d_nbase(G, s), d_kb(G, s);
-    DBuf<uint8_t> d_active(G, s);
-    HIPCHK(hipMemcpyAsync(d_seed.get(), seed, G * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-    upload_vec(d_kb, std::vector<int32_t>(kb.begin(), kb.begin() + G), s);
-
-    // ---- coarsening
-    std::vector<uint8_t> cont(G, 1);
-    int32_t lev = 0;
-    while (true) {
-        const int32_t M = static_cast<int32_t>(L[lev].ids.size());
-        std::vector<uint8_t> act(G, 0);
-        bool any = false;
-        for (int32_t m = 0; m < M; ++m) {
-            const int32_t g = L[lev].ids[m];
-            const int32_t nm = L[lev].nb[m + 1] - L[lev].nb[m];
-            if (cont[g] && nm > o.coarsest && lev < o.max_levels) {
-                act[g] = 1;
-                any = true;
-            }
-        }
-        if (!any) break;
-        BatchLevel& B = L[lev];
-        const int32_t n = B.g.n;
-        std::vector<int64_t> cvl(G), cm = cmax0;
-        if (lev > 0) graph_node_stats(n, B.gid.get(), B.g.vw, G, cvl.data(), cm.data(), s);
-        std::vector<int64_t> bound(G, 0);
-        std::vector<int32_t> base(G, 0);
-        for (int32_t m = 0; m < M; ++m) {
-            const int32_t g = B.ids[m];
-            bound[g] = std::max(cm[g], W[g]);
-            base[g] = B.nb[m];
-        }
-        upload_vec(d_bound, bound, s);
-        upload_vec(d_lbase, base, s);
-        upload_vec(d_nbase, base, s);
-        upload_vec(d_active, act, s);
-        DBuf<int32_t> labels(n, s), w(n, s);
-        iota_u32(reinterpret_cast<uint32_t*>(labels.get()), n, s);
-        label_weights(B.g, labels.get(), w.get(), n, s);
-        MultiGraph mg;
-        mg.G = G;
-        mg.gid = B.gid.get();
-        mg.lgid = B.gid.get();  // cluster labels are node ids
-        mg.nbase = d_nbase.get();
-        mg.lbase = d_lbase.get();
-        mg.bound = d_bound.get();
-        mg.seed = d_seed.get();
-        mg.active = d_active.get();
-        auto t_lp = Clock::now();
-        const LPResult r =
-            run_lp(B.g, kCluster, lev, 0, o.nsub, o.coarsen_rounds, 0, labels.get(), w.get(), n, nullptr, o.tune, s, &mg);
-        lp_ms += ms_since(t_lp);
-        st->visits += r.visits;
-        w.release();
-        // contraction of the whole level; member m's coarse nodes start at cb[m]
-        DBuf<int32_t> probe(M + 1, s), qb(M + 1, s), C(n, s);
-        upload_vec(probe, B.nb, s);
-        OwnedDevGraph coarse;
-        contract(B.g, labels.get(), C.get(), coarse, s, probe.get(), M + 1, qb.get());
-        std::vector<int32_t> cb(M + 1);
-        HIPCHK(hipMemcpyAsync(cb.data(), qb.get(), (M + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        labels.release();
-        std::vector<int32_t> keep;
-        for (int32_t m = 0; m < M; ++m) {
-            const int32_t g = B.ids[m];
-            if (!act[g]) {
-                cont[g] = 0;
-                continue;
-            }
-            const int64_t nm = B.nb[m + 1] - B.nb[m], nc = cb[m + 1] - cb[m];
-            if (nc >= nm) {  // no shrink: this level stays the graph's coarsest
-                cont[g] = 0;
-                continue;
-            }
-            keep.push_back(m);
-            if (20 * nc > 19 * nm) cont[g] = 0;  // stalled
-        }
-        if (keep.empty()) break;
-        BatchLevel N;
-        const std::vector<int64_t> csb = member_slot_bases(coarse.xadj.get(), cb, s);
-        N.nb.push_back(0);
-        N.sb.push_back(0);
-        std::vector<int32_t> onb;
-        std::vector<int64_t> osb;
-        for (int32_t m : keep) {
-            N.ids.push_back(B.ids[m]);
-            N.nb.push_back(N.nb.back() + (cb[m + 1] - cb[m]));
-            N.sb.push_back(N.sb.back() + (csb[m + 1] - csb[m]));
-            onb.push_back(cb[m]);
-            osb.push_back(csb[m]);
-        }
-        if (static_cast<int32_t>(keep.size()) == M) {
-            N.own = std::move(coarse);
-        } else {
-            compact_members(coarse.view(), onb, osb, N.nb, N.sb, N.own, s);
-            coarse = OwnedDevGraph();
-        }
-        N.g = N.own.view();
-        N.gid.alloc(std::max(N.g.n, 1), s);
-        member_ids(N.g.n, N.nb, N.ids, N.gid.get(), s);
-        std::vector<int32_t> delta(G, INT_MIN);
-        for (size_t j = 0; j < keep.size(); ++j) delta[N.ids[j]] = N.nb[j] - cb[keep[j]];
-        remap_members(n, B.gid.get(), delta, C.get(), s);
-        B.C = std::move(C);
-        L.push_back(std::move(N));  // B is not used after this
-        ++lev;
-    }
-    const int32_t top = lev;
-    std::vector<int32_t> last(G, 0), mpos(G, 0);
-    for (int32_t l = 0; l <= top; ++l)
-        for (size_t m = 0; m < L[l].ids.size(); ++m) last[L[l].ids[m]] = l;
-    st->levels = top;
-    if (st->graph_levels)
-        for (int32_t g = 0; g < G; ++g) st->graph_levels[g] = last[g];
-    HIPCHK(hipStreamSynchronize(s));
-    st->ms_coarsen = ms_since(t_coarsen);
-
-    // ---- initial partition of every graph's coarsest level, on the host
-    auto t_init = Clock::now();
-    struct Slice {
-        std::vector<int64_t> x;
-        std::vector<int32_t> a, v, part;
-    };
-    std::vector<Slice> ip(G);
-    for (int32_t l = 0; l <= top; ++l) {
-        const BatchLevel& B = L[l];
-        for (size_t m = 0; m < B.ids.size(); ++m) {
-            const int32_t g = B.ids[m];
-            mpos[g] = static_cast<int32_t>(m);
-            if (last[g] != l) continue;
-            const int32_t nm = B.nb[m + 1] - B.nb[m];
-            const int64_t Sm = B.sb[m + 1] - B.sb[m];
-            Slice& sl = ip[g];
-            sl.x.resize(static_cast<size_t>(nm) + 1);
-            sl.a.resize(static_cast<size_t>(std::max<int64_t>(Sm, 1)));
-            sl.part.resize(static_cast<size_t>(nm));
-            HIPCHK(hipMemcpyAsync(sl.x.data(), B.g.xadj + B.nb[m], (nm + 1) * sizeof(int64_t), hipMemcpyDeviceToHost,
-                                  s));
-            if (Sm > 0)
-                HIPCHK(hipMemcpyAsync(sl.a.data(), B.g.adj + B.sb[m], Sm * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            if (B.g.vw && nm > 0) {
-                sl.v.resize(nm);
-                HIPCHK(hipMemcpyAsync(sl.v.data(), B.g.vw + B.nb[m], nm * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            }
-        }
-    }
-    HIPCHK(hipStreamSynchronize(s));
-    const unsigned hw = std::thread::hardware_concurrency();
-    parallel_for(G, static_cast<int32_t>(std::min(16u, hw ? hw : 1u)), [&](int32_t g) {
-        Slice& sl = ip[g];
-        const BatchLevel& B = L[last[g]];
-        const int32_t m = mpos[g];
-        const int32_t nm = B.nb[m + 1] - B.nb[m];
-        const int64_t x0 = sl.x[0];
-        for (auto& x : sl.x) x -= x0;
-        for (int64_t j = 0; j < sl.x[nm]; ++j) sl.a[j] -= B.nb[m];
-        host_initial_partition(nm, sl.x.data(), sl.a.data(), sl.v.empty() ? nullptr : sl.v.data(), k[g], T[g],
-                               sl.part.data(), last[g] > 0);
-        for (auto& b : sl.part) b += kb[g];  // labels of the batch's block space
-        sl.x = {};
-        sl.a = {};
-        sl.v = {};
-    });
-    st->ms_initial = ms_since(t_init);
-
-    // ---- refinement from the top level down
-    auto t_ref = Clock::now();
-    std::vector<int32_t> lgid(std::max(K, 1));
-    for (int32_t g = 0; g < G; ++g)
-        for (int32_t b = kb[g]; b < kb[g + 1]; ++b) lgid[b] = g;
-    DBuf<int32_t> d_lgid(std::max(K, 1), s);
-    upload_vec(d_lgid, lgid, s);
-    upload_vec(d_bound, Lmax, s);
-    upload_vec(d_active, std::vector<uint8_t>(G, 1), s);
-    DBuf<int32_t> w(std::max(K, 1), s), cur;
-    for (int32_t l = top; l >= 0; --l) {
-        BatchLevel& B = L[l];
-        const int32_t n = B.g.n;
-        DBuf<int32_t> mine;
-        int32_t* part = part_out;
-        if (l > 0) {
-            mine.alloc(std::max(n, 1), s);
-            part = mine.get();
-        }
-        if (l < top) project_kept(n, B.C.get(), cur.get(), part, s);
-        for (size_t m = 0; m < B.ids.size(); ++m) {
-            const int32_t g = B.ids[m];
-            if (last[g] != l || ip[g].part.empty()) continue;
-            HIPCHK(hipMemcpyAsync(part + B.nb[m], ip[g].part.data(), ip[g].part.size() * sizeof(int32_t),
-                                  hipMemcpyHostToDevice, s));
-        }
-        std::vector<int32_t> base(G, 0);
-        for (size_t m = 0; m < B.ids.size(); ++m) base[B.ids[m]] = B.nb[m];
-        upload_vec(d_nbase, base, s);
-        label_weights(B.g, part, w.get(), K, s);
-        MultiGraph mg;
-        mg.G = G;
-        mg.gid = B.gid.get();
-        mg.lgid = d_lgid.get();
-        mg.nbase = d_nbase.get();
-        mg.lbase = d_kb.get();
-        mg.bound = d_bound.get();
-        mg.seed = d_seed.get();
-        mg.active = d_active.get();
-        auto t_lp = Clock::now();
-        const LPResult r =
-            run_lp(B.g, kRefine, l, 0, o.nsub, o.refine_rounds, 0, part, w.get(), K, nullptr, o.tune, s, &mg);
-        lp_ms += ms_since(t_lp);
-        st->visits += r.visits;
-        HIPCHK(hipStreamSynchronize(s));  // host slices uploaded above must stay alive until here
-        for (size_t m = 0; m < B.ids.size(); ++m)
-            if (last[B.ids[m]] == l) ip[B.ids[m]].part = {};
-        cur = std::move(mine);
-        if (l < top) L[l + 1] = BatchLevel();
-        B.C.release();
-    }
-    std::vector<int32_t> hw_(std::max(K, 1));
-    HIPCHK(hipMemcpyAsync(hw_.data(), w.get(), std::max(K, 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    graph_cuts(g0, part_out, L[0].gid.get(), G, cut, s);  // synchronises
-    shift_by_graph(g0.n, L[0].gid.get(), d_kb.get(), -1, part_out, s);
-    HIPCHK(hipStreamSynchronize(s));
-    int status = SCLAP_OK;
-    for (int32_t g = 0; g < G; ++g)
-        for (int32_t b = kb[g]; b < kb[g + 1]; ++b) {
-            bw[b] = hw_[b];
-            if (bw[b] > Lmax[g]) status = SCLAP_WARN_IMBALANCED;
-        }
-    st->ms_refine = ms_since(t_ref);
-    st->ms_lp = lp_ms;
-    return status;
 }
 
 // ------------------------------------------------ host <-> device staging
@@ -1217,6 +494,37 @@ int sclap_partition_batch(const sclap_graph* g, int32_t count, const int32_t* no
         const int r = partition_batch_impl(st.g, count, node_base, k, eps, seed, o, p.get(), cut, block_w, stats, s);
         download(part, p.get(), st.g.n, s);
         return r;
+    });
+}
+
+sclap_server* sclap_server_create(int32_t device, int64_t hbm_budget, int32_t slots, int32_t max_batch,
+                                  const sclap_options* opt) {
+    sclap_server* sv = nullptr;
+    guarded([&] {
+        sv = server_create(device, hbm_budget, slots, max_batch, opt);
+        return SCLAP_OK;
+    });
+    return sv;
+}
+
+int sclap_server_submit(sclap_server* sv, const sclap_graph* g, int32_t k, double eps, uint64_t seed,
+                        uint64_t* req) {
+    return guarded([&] {
+        if (!req) fail(SCLAP_ERR_INVALID, "req is NULL");
+        *req = server_submit(sv, g, k, eps, seed);
+        return SCLAP_OK;
+    });
+}
+
+int sclap_server_poll(sclap_server* sv, uint64_t req, int32_t timeout_ms, int32_t* done, int32_t* part,
+                      int64_t* cut, int64_t* block_w, sclap_request_info* info) {
+    return guarded([&] { return server_poll(sv, req, timeout_ms, done, part, cut, block_w, info); });
+}
+
+void sclap_server_destroy(sclap_server* sv) {
+    guarded([&] {
+        server_destroy(sv);
+        return SCLAP_OK;
     });
 }
 
