@@ -95,7 +95,11 @@ typedef struct {
     int32_t hub_part_limit;   /* hub label partitions summed in LDS up to this many entries */
     int32_t hub_region_cap;   /* entries a hub partition keeps before spilling to its overflow list */
     int32_t select_small_max; /* overflowing targets with more candidates: multi-workgroup selection */
-    int32_t reserved[2];
+    int32_t skip_quiet;       /* 1: once few nodes move, skip nodes that emitted nothing, had no
+                                 neighbouring label stronger than their own and saw no neighbour move
+                                 since (their decision is unchanged); -1: evaluate every node;
+                                 0: on for batches, off for single graphs */
+    int32_t reserved;
 } sclap_options;
 
 #define SCLAP_MAX_LEVELS 64

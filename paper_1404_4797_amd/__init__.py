@@ -65,7 +65,7 @@ class Options(ctypes.Structure):
                 ("lane_max_degree", ctypes.c_int32), ("wave_max_degree", ctypes.c_int32),
                 ("block_max_degree", ctypes.c_int32), ("hub_part_limit", ctypes.c_int32),
                 ("hub_region_cap", ctypes.c_int32), ("select_small_max", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("skip_quiet", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):

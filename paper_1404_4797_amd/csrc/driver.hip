@@ -4,10 +4,14 @@
 #include <atomic>
 #include <climits>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
-#include <queue>
 #include <exception>
+#include <memory>
+#include <mutex>
+#include <queue>
 #include <thread>
 #include <utility>
 #include <vector>
@@ -36,6 +40,7 @@ Opts resolve(const sclap_options* o) {
     if (o->hub_part_limit > 0) r.tune.hub_part_limit = o->hub_part_limit;
     if (o->hub_region_cap > 0) r.tune.hub_region_cap = o->hub_region_cap;
     if (o->select_small_max > 0) r.tune.select_small_max = o->select_small_max;
+    r.tune.skip_quiet = o->skip_quiet < 0 ? -1 : (o->skip_quiet > 0 ? 1 : 0);
     if (r.coarsen_rounds < 0 || r.refine_rounds < 0) fail(SCLAP_ERR_INVALID, "round counts must be >= 0");
     if (r.nsub < 1 || r.nsub > 16) fail(SCLAP_ERR_INVALID, "subrounds must be in 1..16");
     if (r.divisor < 1) fail(SCLAP_ERR_INVALID, "cluster_divisor must be >= 1");
@@ -145,11 +150,12 @@ struct BlockHeap {
     }
 };
 
+}  // namespace
+
 // Grows blocks 0..k-2 by breadth-first search up to T each (seeds: smallest
 // unassigned node of positive degree that fits; neighbours in ascending id
 // order), then deals every remaining node, in id order, to the currently
 // lightest block (lowest id on ties).  Weights fit 31 bits (c(V) <= 2^31-1).
-}  // namespace
 
 void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, const int32_t* vw, int32_t k,
                             int64_t T, int32_t* part, bool rows_sorted) {
@@ -275,6 +281,65 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
 
 namespace {
 
+bool trace_on() {
+    static const bool on = std::getenv("SCLAP_TRACE") != nullptr;
+    return on;
+}
+
+// Page-locked host staging for the coarsest graph.  One buffer is kept for
+// the process and reused by whichever call holds it (pinning fresh memory on
+// every call costs more than the copy it speeds up); a call that finds it
+// busy uses ordinary uninitialised host memory instead.
+class HostStage {
+  public:
+    explicit HostStage(size_t bytes) : lk_(mu(), std::try_to_lock) {
+        if (lk_.owns_lock()) {
+            if (cap() < bytes) {
+                if (buf()) (void)hipHostFree(buf());
+                buf() = nullptr;
+                cap() = 0;
+                void* p = nullptr;
+                if (hipHostMalloc(&p, bytes, hipHostMallocDefault) == hipSuccess) {
+                    buf() = static_cast<char*>(p);
+                    cap() = bytes;
+                } else {
+                    (void)hipGetLastError();
+                }
+            }
+            if (buf()) {
+                data_ = buf();
+                return;
+            }
+            lk_.unlock();
+        }
+        own_.reset(new char[bytes]);
+        data_ = own_.get();
+    }
+    char* data() const { return data_; }
+    bool pinned() const { return lk_.owns_lock(); }
+
+  private:
+    static std::mutex& mu() {
+        static std::mutex m;
+        return m;
+    }
+    static char*& buf() {
+        static char* b = nullptr;
+        return b;
+    }
+    static size_t& cap() {
+        static size_t c = 0;
+        return c;
+    }
+    std::unique_lock<std::mutex> lk_;
+    std::unique_ptr<char[]> own_;
+    char* data_ = nullptr;
+};
+
+}  // namespace
+
+namespace {
+
 struct Level {
     OwnedDevGraph own;
     DevGraph g;
@@ -285,13 +350,26 @@ struct Level {
 
 double ms_since(Clock::time_point t) { return std::chrono::duration<double, std::milli>(Clock::now() - t).count(); }
 
-int partition_impl(const DevGraph& g0, int32_t k, double eps, uint64_t seed, const Opts& o, int32_t* part_out,
+namespace {
+
+// Weight arrays that hold only ones are dropped (read as implicit ones), so
+// the level-0 rounds do not stream them.
+void drop_unit_weights(DevGraph& g, hipStream_t s) {
+    if (g.ew && all_in_range(g.ew, g.S, 1, 2, s)) g.ew = nullptr;
+    if (g.vw && all_in_range(g.vw, g.n, 1, 2, s)) g.vw = nullptr;
+}
+
+}  // namespace
+
+int partition_impl(const DevGraph& g0_in, int32_t k, double eps, uint64_t seed, const Opts& o, int32_t* part_out,
                    int64_t* cut, int64_t* bw, sclap_stats* stats, hipStream_t s) {
+    DevGraph g0 = g0_in;
     check_k_eps(k, eps);
     if (!part_out && g0.n > 0) fail(SCLAP_ERR_INVALID, "part is NULL");
     if (!cut || !bw) fail(SCLAP_ERR_INVALID, "cut / block_w is NULL");
     int64_t cV = 0, cmax0 = 0;
     check_graph(g0, o.validate != 0, &cV, &cmax0, s);
+    drop_unit_weights(g0, s);
     sclap_stats local;
     sclap_stats* st = stats ? stats : &local;
     std::memset(st, 0, sizeof(*st));
@@ -341,29 +419,36 @@ int partition_impl(const DevGraph& g0, int32_t k, double eps, uint64_t seed, con
     auto t_init = Clock::now();
     const DevGraph Gc = L[lev].g;
     const int32_t nc = Gc.n;
-    std::vector<int64_t> hx(static_cast<size_t>(nc) + 1);
-    std::vector<int32_t> ha(static_cast<size_t>(std::max<int64_t>(Gc.S, 1))), hv, hp(static_cast<size_t>(nc));
+    const size_t bx = (static_cast<size_t>(nc) + 1) * sizeof(int64_t);
+    const size_t ba = static_cast<size_t>(std::max<int64_t>(Gc.S, 1)) * sizeof(int32_t);
+    const size_t bn = static_cast<size_t>(std::max(nc, 1)) * sizeof(int32_t);
+    HostStage stage(bx + ba + 2 * bn);
+    int64_t* hx = reinterpret_cast<int64_t*>(stage.data());
+    int32_t* ha = reinterpret_cast<int32_t*>(stage.data() + bx);
+    int32_t* hv = reinterpret_cast<int32_t*>(stage.data() + bx + ba);
+    int32_t* hp = reinterpret_cast<int32_t*>(stage.data() + bx + ba + bn);
     if (nc > 0) {
-        HIPCHK(hipMemcpyAsync(hx.data(), Gc.xadj, (nc + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        if (Gc.S > 0)
-            HIPCHK(hipMemcpyAsync(ha.data(), Gc.adj, Gc.S * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        if (Gc.vw) {
-            hv.resize(nc);
-            HIPCHK(hipMemcpyAsync(hv.data(), Gc.vw, nc * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        }
+        HIPCHK(hipMemcpyAsync(hx, Gc.xadj, bx, hipMemcpyDeviceToHost, s));
+        if (Gc.S > 0) HIPCHK(hipMemcpyAsync(ha, Gc.adj, Gc.S * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        if (Gc.vw) HIPCHK(hipMemcpyAsync(hv, Gc.vw, nc * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
     }
+    const double ms_d2h = ms_since(t_init);
     const int64_t T = (cV + k - 1) / k;
     // rows of contracted levels are sorted by construction
-    host_initial_partition(nc, hx.data(), ha.data(), Gc.vw ? hv.data() : nullptr, k, T, hp.data(), lev > 0);
+    host_initial_partition(nc, hx, ha, Gc.vw ? hv : nullptr, k, T, hp, lev > 0);
+    const double ms_ip = ms_since(t_init) - ms_d2h;
     DBuf<int32_t> cur;
     int32_t* curp = part_out;
     if (lev > 0) {
         cur.alloc(nc, s);
         curp = cur.get();
     }
-    if (nc > 0) HIPCHK(hipMemcpyAsync(curp, hp.data(), nc * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (nc > 0) HIPCHK(hipMemcpyAsync(curp, hp, nc * sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (trace_on())
+        fprintf(stderr, "[sclap] initial partition: n=%d S=%lld pinned=%d copy-in %.1f ms, partition %.1f ms\n", nc,
+                static_cast<long long>(Gc.S), stage.pinned() ? 1 : 0, ms_d2h, ms_ip);
     st->ms_initial = ms_since(t_init);
 
     auto t_ref = Clock::now();
@@ -452,9 +537,13 @@ void parallel_for(int32_t count, int32_t threads, F f) {
 
 }  // namespace
 
-int partition_batch_impl(const DevGraph& g0, int32_t G, const int32_t* node_base, const int32_t* k,
-                         const double* eps, const uint64_t* seed, const Opts& o, int32_t* part_out, int64_t* cut,
+int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_base, const int32_t* k,
+                         const double* eps, const uint64_t* seed, const Opts& o_in, int32_t* part_out, int64_t* cut,
                          int64_t* bw, sclap_batch_stats* stats, hipStream_t s) {
+    Opts o = o_in;
+    DevGraph g0 = g0_in;
+    // many small graphs converge early: skipping their quiet nodes pays off
+    if (o.tune.skip_quiet == 0) o.tune.skip_quiet = 1;
     if (G < 1) fail(SCLAP_ERR_INVALID, "count must be >= 1");
     if (!node_base || !k || !eps || !seed) fail(SCLAP_ERR_INVALID, "node_base, k, eps or seed is NULL");
     if (node_base[0] != 0 || node_base[G] != g0.n) fail(SCLAP_ERR_INVALID, "node_base must run from 0 to n");
@@ -492,6 +581,8 @@ int partition_batch_impl(const DevGraph& g0, int32_t G, const int32_t* node_base
         check_graph(g0, true, &cVu, &cmu, s);
         if (!members_closed(g0, L[0].nb, L[0].sb, s)) fail(SCLAP_ERR_INVALID, "an edge joins two graphs of the batch");
     }
+    drop_unit_weights(g0, s);
+    L[0].g = g0;
     std::vector<int64_t> cV(G), cmax0(G);
     graph_node_stats(g0.n, L[0].gid.get(), g0.vw, G, cV.data(), cmax0.data(), s);
     std::vector<int64_t> Lmax(G), W(G), T(G);

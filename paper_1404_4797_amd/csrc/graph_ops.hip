@@ -1,215 +1,15 @@
-// Contraction, projection, cut / block weights and validation on gfx950.
-//
-// Slot-parallel kernels walk the adjacency array in tiles of kTile
-// consecutive slots.  Each workgroup recovers the source node of every slot
-// of its tile in LDS (row starts scattered into the tile, then a max-scan), so
-// rows of any length are split evenly over the grid without a per-slot search.
+// Projection, cut / block weights, validation and the batch helpers on
+// gfx950 (contraction is in contract.hip).  Slot-parallel kernels use the
+// slot tiles of tiles.hpp.
 #include <climits>
 
 #include "graph_ops.hpp"
 #include "profile.hpp"
+#include "tiles.hpp"
 
 namespace sclap {
 
 namespace {
-
-constexpr int kTileThreads = 256;
-constexpr int kTilePer = 8;
-constexpr int kTile = kTileThreads * kTilePer;
-
-__device__ int32_t upper_node(const int64_t* __restrict__ xadj, int32_t n, int64_t slot) {
-    // largest u in [0, n) with xadj[u] <= slot
-    int32_t lo = 0, hi = n;  // invariant: xadj[lo] <= slot, answer in [lo, hi)
-    while (hi - lo > 1) {
-        const int32_t mid = lo + (hi - lo) / 2;
-        if (xadj[mid] <= slot) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// Fills owner[0 .. i1-i0) with the source node of each slot of [i0, i1).
-__device__ void tile_owners(const int64_t* __restrict__ xadj, int32_t n, int64_t i0, int64_t i1, int32_t* owner) {
-    __shared__ int32_t s_u[2];
-    __shared__ int32_t s_carry[kTileThreads / kWave];
-    const int tid = threadIdx.x;
-    for (int j = tid; j < kTile; j += kTileThreads) owner[j] = -1;
-    if (tid == 0) s_u[0] = upper_node(xadj, n, i0);
-    if (tid == 1) s_u[1] = upper_node(xadj, n, i1 - 1);
-    __syncthreads();
-    const int32_t u0 = s_u[0], u1 = s_u[1];
-    if (tid == 0) atomicMax(&owner[0], u0);
-    for (int64_t u = static_cast<int64_t>(u0) + 1 + tid; u <= u1; u += kTileThreads) {
-        const int64_t st = xadj[u];
-        if (st >= i0 && st < i1) atomicMax(&owner[st - i0], static_cast<int32_t>(u));
-    }
-    __syncthreads();
-    // inclusive max-scan over the tile: 8 consecutive entries per thread
-    int32_t loc[kTilePer];
-    int32_t m = -1;
-#pragma unroll
-    for (int j = 0; j < kTilePer; ++j) {
-        loc[j] = owner[tid * kTilePer + j];
-        m = loc[j] > m ? loc[j] : m;
-    }
-    int32_t incl = m;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const int32_t t = __shfl_up(incl, o, 64);
-        if (lane_id() >= o) incl = t > incl ? t : incl;
-    }
-    if (lane_id() == kWave - 1) s_carry[tid / kWave] = incl;
-    __syncthreads();
-    int32_t run = __shfl_up(incl, 1, 64);
-    if (lane_id() == 0) run = -1;
-    for (int w = 0; w < tid / kWave; ++w) run = s_carry[w] > run ? s_carry[w] : run;
-#pragma unroll
-    for (int j = 0; j < kTilePer; ++j) {
-        run = loc[j] > run ? loc[j] : run;
-        owner[tid * kTilePer + j] = run;
-    }
-    __syncthreads();
-}
-
-// ------------------------------------------------------------ contraction
-
-__global__ void mark_used_kernel(int32_t n, const int32_t* __restrict__ labels, int32_t* __restrict__ used) {
-    const int32_t v = blockIdx.x * 256 + threadIdx.x;
-    if (v < n) used[labels[v]] = 1;
-}
-
-__global__ void map_kernel(int32_t n, const int32_t* __restrict__ labels, const int32_t* __restrict__ q,
-                           const int32_t* __restrict__ vw, int32_t* __restrict__ C, int32_t* __restrict__ cvw) {
-    const int32_t v = blockIdx.x * 256 + threadIdx.x;
-    if (v >= n) return;
-    const int32_t cv = q[labels[v]];
-    C[v] = cv;
-    const int32_t c = vw ? vw[v] : 1;
-    if (c) atomicAdd(&cvw[cv], c);
-}
-
-// Number of slots u->v with C(u) != C(v) in each tile.
-__global__ void __launch_bounds__(kTileThreads) count_cross_kernel(const int64_t* __restrict__ xadj,
-                                                                   const int32_t* __restrict__ adj, int32_t n,
-                                                                   int64_t S, const int32_t* __restrict__ C,
-                                                                   int32_t* __restrict__ tile_cnt) {
-    __shared__ int32_t owner[kTile];
-    __shared__ int32_t s_sum[kTileThreads / kWave];
-    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kTile;
-    const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
-    tile_owners(xadj, n, i0, i1, owner);
-    int32_t cnt = 0;
-    for (int r = 0; r < kTilePer; ++r) {
-        const int64_t i = i0 + r * kTileThreads + threadIdx.x;
-        if (i < i1 && C[owner[i - i0]] != C[adj[i]]) ++cnt;
-    }
-    cnt = wave_sum(cnt);
-    if (lane_id() == 0) s_sum[threadIdx.x / kWave] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t t = 0;
-        for (int w = 0; w < kTileThreads / kWave; ++w) t += s_sum[w];
-        tile_cnt[blockIdx.x] = t;
-    }
-}
-
-// Writes (C(u) << bn | C(v), w) for every slot u->v between different
-// clusters, in slot order, starting at the tile's scanned offset.
-__global__ void __launch_bounds__(kTileThreads) emit_kernel(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj,
-                                                            const int32_t* __restrict__ ew, int32_t n, int64_t S,
-                                                            const int32_t* __restrict__ C, int bn,
-                                                            const int64_t* __restrict__ tile_off,
-                                                            uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-    __shared__ int32_t owner[kTile];
-    __shared__ int32_t s_cnt[kTileThreads / kWave];
-    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kTile;
-    const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
-    tile_owners(xadj, n, i0, i1, owner);
-    int64_t base = tile_off[blockIdx.x];
-    const int wid = threadIdx.x / kWave;
-    for (int r = 0; r < kTilePer; ++r) {
-        const int64_t i = i0 + r * kTileThreads + threadIdx.x;
-        bool e = false;
-        uint64_t key = 0;
-        uint32_t val = 0;
-        if (i < i1) {
-            const int32_t cu = C[owner[i - i0]];
-            const int32_t cx = C[adj[i]];
-            if (cu != cx) {
-                e = true;
-                key = (static_cast<uint64_t>(cu) << bn) | static_cast<uint64_t>(cx);
-                val = ew ? static_cast<uint32_t>(ew[i]) : 1u;
-            }
-        }
-        const uint64_t m = __ballot(e);
-        if (lane_id() == 0) s_cnt[wid] = static_cast<int32_t>(__popcll(m));
-        __syncthreads();
-        int64_t pre = base;
-        int64_t tot = 0;
-        for (int w = 0; w < kTileThreads / kWave; ++w) {
-            if (w < wid) pre += s_cnt[w];
-            tot += s_cnt[w];
-        }
-        if (e) {
-            const int64_t idx = pre + static_cast<int64_t>(__popcll(m & lanemask_lt()));
-            keys[idx] = key;
-            vals[idx] = val;
-        }
-        base += tot;
-        __syncthreads();
-    }
-}
-
-__global__ void heads_kernel(const uint64_t* __restrict__ keys, int64_t m, int32_t* __restrict__ head,
-                             int64_t* __restrict__ wsum, const uint32_t* __restrict__ vals) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (i < m) {
-        head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
-        wsum[i] = vals[i];
-    }
-}
-
-// Heads of equal-key runs write the coarse neighbour and remember where the
-// run starts; heads that open a new coarse row also set the row offsets of
-// every coarse node from the previous row's source up to this one.
-__global__ void run_heads_kernel(const uint64_t* __restrict__ keys, int64_t m, const int32_t* __restrict__ head,
-                                 const int64_t* __restrict__ pos, int bn, int32_t nc, int64_t Sc,
-                                 int32_t* __restrict__ cadj, int64_t* __restrict__ run_start,
-                                 int64_t* __restrict__ cxadj) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (i >= m) return;
-    const uint64_t k = keys[i];
-    const int64_t src = static_cast<int64_t>(k >> bn);
-    if (head[i]) {
-        const int64_t j = pos[i];
-        cadj[j] = static_cast<int32_t>(k & ((1ULL << bn) - 1));
-        run_start[j] = i;
-        const int64_t prev = i == 0 ? -1 : static_cast<int64_t>(keys[i - 1] >> bn);
-        for (int64_t c = prev + 1; c <= src; ++c) cxadj[c] = j;
-    }
-    if (i == m - 1)
-        for (int64_t c = src + 1; c <= nc; ++c) cxadj[c] = Sc;
-}
-
-// Tails of runs: coarse edge weight = sum of the run (from the inclusive scan).
-__global__ void run_tails_kernel(const uint64_t* __restrict__ keys, int64_t m, const int32_t* __restrict__ head,
-                                 const int64_t* __restrict__ pos, const int64_t* __restrict__ psum,
-                                 const int64_t* __restrict__ run_start, int32_t* __restrict__ cadjw) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (i >= m) return;
-    if (i + 1 < m && keys[i + 1] == keys[i]) return;
-    const int64_t j = pos[i] + head[i] - 1;
-    const int64_t st = run_start[j];
-    cadjw[j] = static_cast<int32_t>(psum[i] - (st > 0 ? psum[st - 1] : 0));
-}
-
-
-// probe_out[i] = number of used labels below probe[i] (probe[i] in [0, n]).
-__global__ void probe_kernel(const int32_t* __restrict__ probe, int32_t nprobe, const int32_t* __restrict__ q,
-                             int32_t n, const int32_t* __restrict__ total, int32_t* __restrict__ out) {
-    const int32_t i = blockIdx.x * 256 + threadIdx.x;
-    if (i < nprobe) out[i] = probe[i] < n ? q[probe[i]] : *total;
-}
 
 __global__ void project_kernel(int32_t n, const int32_t* __restrict__ C, const int32_t* __restrict__ cp,
                                int32_t* __restrict__ part) {
@@ -369,101 +169,6 @@ unsigned capped_nodes(int64_t n) {
 }
 
 }  // namespace
-
-void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGraph& coarse, hipStream_t s,
-              const int32_t* probe, int32_t nprobe, int32_t* probe_out) {
-    const int32_t n = g.n;
-    if (n == 0) {
-        coarse.n = 0;
-        coarse.S = 0;
-        coarse.xadj.alloc(1, s);
-        fill_i64(coarse.xadj.get(), 0, 1, s);
-        if (nprobe > 0) fill_i32(probe_out, 0, nprobe, s);
-        return;
-    }
-    DBuf<int32_t> q(n, s);
-    DBuf<int32_t> total(1, s);
-    fill_i32(q.get(), 0, n, s);
-    mark_used_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, labels, q.get());
-    LAUNCHCHK();
-    exclusive_scan_i32(q.get(), q.get(), n, total.get(), s);
-    if (nprobe > 0) {
-        probe_kernel<<<grid_for(nprobe, 256), 256, 0, s>>>(probe, nprobe, q.get(), n, total.get(), probe_out);
-        LAUNCHCHK();
-    }
-    int32_t nc = 0;
-    HIPCHK(hipMemcpyAsync(&nc, total.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    coarse.n = nc;
-    coarse.vw.alloc(nc, s);
-    fill_i32(coarse.vw.get(), 0, nc, s);
-    map_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, labels, q.get(), g.vw, C, coarse.vw.get());
-    LAUNCHCHK();
-    q.release();
-
-    // inter-cluster slots, sorted by (C(u), C(v)), equal keys summed
-    const int bn = std::max(1, bits_for(static_cast<uint64_t>(nc - 1)));
-    coarse.xadj.alloc(static_cast<size_t>(nc) + 1, s);
-    const int64_t ntiles = (g.S + kTile - 1) / kTile;
-    int64_t m = 0;
-    DBuf<int64_t> tile_off(std::max<int64_t>(ntiles, 1), s), mtot(1, s);
-    if (g.S > 0) {
-        ProfScope ps("contract_count", (8.0 + 4.0) * static_cast<double>(g.S) + 8.0 * n, s);
-        DBuf<int32_t> tile_cnt(ntiles, s);
-        count_cross_kernel<<<static_cast<unsigned>(ntiles), kTileThreads, 0, s>>>(g.xadj, g.adj, n, g.S, C,
-                                                                                  tile_cnt.get());
-        LAUNCHCHK();
-        exclusive_scan_i32_to_i64(tile_cnt.get(), tile_off.get(), ntiles, mtot.get(), s);
-        HIPCHK(hipMemcpyAsync(&m, mtot.get(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-    }
-    if (m == 0) {
-        coarse.S = 0;
-        coarse.adj.alloc(1, s);
-        coarse.ew.alloc(1, s);
-        fill_i64(coarse.xadj.get(), 0, static_cast<int64_t>(nc) + 1, s);
-        HIPCHK(hipStreamSynchronize(s));
-        return;
-    }
-    DBuf<uint64_t> keys(m, s);
-    DBuf<uint32_t> vals(m, s);
-    {
-        ProfScope ps("contract_emit", (8.0 + (g.ew ? 4.0 : 0.0)) * static_cast<double>(g.S) + 8.0 * n + 12.0 * m, s);
-        emit_kernel<<<static_cast<unsigned>(ntiles), kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, n, g.S, C, bn,
-                                                                            tile_off.get(), keys.get(), vals.get());
-        LAUNCHCHK();
-    }
-    tile_off.release();
-    {
-        ProfScope ps("contract_sort", 0, s);
-        DBuf<uint64_t> ktmp(m, s);
-        DBuf<uint32_t> vtmp(m, s);
-        RadixScratch rs;
-        radix_sort_pairs(keys.get(), vals.get(), ktmp.get(), vtmp.get(), m, 0, 2 * bn, rs, s);
-    }
-    ProfScope ps_runs("contract_runs", 0, s);
-    DBuf<int32_t> head(m, s);
-    DBuf<int64_t> pos(m, s), psum(m, s), stot(1, s);
-    heads_kernel<<<grid_for(m, 256), 256, 0, s>>>(keys.get(), m, head.get(), psum.get(), vals.get());
-    LAUNCHCHK();
-    vals.release();
-    exclusive_scan_i32_to_i64(head.get(), pos.get(), m, stot.get(), s);
-    inclusive_scan_i64(psum.get(), psum.get(), m, s);
-    int64_t Sc = 0;
-    HIPCHK(hipMemcpyAsync(&Sc, stot.get(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    coarse.S = Sc;
-    coarse.adj.alloc(Sc, s);
-    coarse.ew.alloc(Sc, s);
-    DBuf<int64_t> run_start(Sc, s);
-    run_heads_kernel<<<grid_for(m, 256), 256, 0, s>>>(keys.get(), m, head.get(), pos.get(), bn, nc, Sc,
-                                                      coarse.adj.get(), run_start.get(), coarse.xadj.get());
-    LAUNCHCHK();
-    run_tails_kernel<<<grid_for(m, 256), 256, 0, s>>>(keys.get(), m, head.get(), pos.get(), psum.get(),
-                                                      run_start.get(), coarse.ew.get());
-    LAUNCHCHK();
-    HIPCHK(hipStreamSynchronize(s));
-}
 
 void project(int32_t n, const int32_t* C, const int32_t* coarse_part, int32_t* part, hipStream_t s) {
     if (n <= 0) return;

@@ -76,6 +76,11 @@ struct EvalArgs {
     const int32_t* ew;
     const int32_t* vw;
     const int32_t* label;
+    // Narrow copies of label for the neighbour gathers when every label fits
+    // 8 or 16 bits (refinement: blocks): a cache line then holds 4 or 2
+    // times as many neighbours' labels.  Null when not kept.
+    const uint8_t* label8;
+    const uint16_t* label16;
     const int32_t* w;
     int64_t bound;
     uint64_t tp;  // H(seed, 2, level, phase, round)
@@ -85,6 +90,12 @@ struct EvalArgs {
     const uint64_t* g_tp;    // [G] tie prefix of each graph for this round
     const int64_t* g_bound;  // [G] bound of each graph's labels
     const int32_t* g_lbase;  // [G] first label of each graph
+    // Quiet nodes: evaluated with no neighbouring label connected more strongly
+    // than their own, not overloaded, and no neighbour has moved since.  Such a
+    // node emits nothing while it stays quiet and its block is not overloaded
+    // (its connections are unchanged), so it need not be evaluated again.
+    uint8_t* quiet;     // [n] flags, written by every evaluation (null: not tracked)
+    int32_t use_quiet;  // 1: skip quiet nodes
     const int32_t* nodes;  // schedule entries of this launch
     int32_t count;
     int32_t* ct;  // per entry: target label or -1
@@ -92,6 +103,12 @@ struct EvalArgs {
 };
 
 // ------------------------------------------------------- selection helpers
+
+__device__ __forceinline__ int32_t nbr_label(const EvalArgs& A, int32_t u) {
+    if (A.label8) return A.label8[u];
+    if (A.label16) return A.label16[u];
+    return A.label[u];
+}
 
 // Per-node constants: the tie prefix and bound of the node's graph and the
 // graph's first label (ties hash graph-local label ids).
@@ -197,6 +214,12 @@ __device__ __forceinline__ void store_result(const EvalArgs& A, int32_t i, int32
     A.cg[i] = gain;
 }
 
+// True if v is quiet and may skip evaluation (its block is not overloaded).
+__device__ __forceinline__ bool skip_quiet(const EvalArgs& A, int32_t v, const Ctx& kx) {
+    if (!A.use_quiet || !A.quiet[v]) return false;
+    return !A.refine || A.w[A.label[v]] <= kx.bound;
+}
+
 __device__ __forceinline__ uint32_t table_size_for(int32_t d, uint32_t lo, uint32_t hi) {
     uint32_t t = lo;
     while (t < 2u * static_cast<uint32_t>(d) && t < hi) t <<= 1;
@@ -233,7 +256,7 @@ __device__ __forceinline__ void insert_slots(const EvalArgs& A, int64_t b, int32
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int32_t j = j0 + u * NT;
-            x[u] = j < d ? A.label[x[u]] : -1;
+            x[u] = j < d ? nbr_label(A, x[u]) : -1;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -249,6 +272,10 @@ __global__ void __launch_bounds__(256) eval_lane_kernel(EvalArgs A) {
     if (i >= A.count) return;
     const int32_t v = A.nodes[i];
     const Ctx kx = ctx_of(A, v);
+    if (skip_quiet(A, v, kx)) {
+        store_result(A, i, -1, 0, 0, false);
+        return;
+    }
     const int64_t b = A.xadj[v];
     const int d = static_cast<int>(A.xadj[v + 1] - b);
     const int32_t a = A.label[v];
@@ -257,7 +284,7 @@ __global__ void __launch_bounds__(256) eval_lane_kernel(EvalArgs A) {
 #pragma unroll
     for (int j = 0; j < MAXD; ++j) {
         if (j < d) {
-            lab[j] = A.label[A.adj[b + j]];
+            lab[j] = nbr_label(A, A.adj[b + j]);
             wt[j] = A.ew ? A.ew[b + j] : 1;
         } else {
             lab[j] = -1;
@@ -270,6 +297,7 @@ __global__ void __launch_bounds__(256) eval_lane_kernel(EvalArgs A) {
     const bool over = A.refine && A.w[a] > kx.bound;
     Best best;
     best_init(best);
+    bool blocked = false;  // some other neighbouring label is connected more strongly
 #pragma unroll
     for (int j = 0; j < MAXD; ++j) {
         const int32_t x = lab[j];
@@ -280,12 +308,14 @@ __global__ void __launch_bounds__(256) eval_lane_kernel(EvalArgs A) {
         int32_t conn = 0;
 #pragma unroll
         for (int j2 = j; j2 < MAXD; ++j2) conn += (lab[j2] == x) ? wt[j2] : 0;
+        blocked |= conn > own;
         if (!over && conn <= own) continue;  // cannot give a positive gain
         if (best.x >= 0 && conn < best.conn) continue;
         if (!eligible(A, x, c, kx)) continue;
         best_consider(best, x, conn, kx);
     }
     store_result(A, i, best.x, best.conn, own, over);
+    if (A.quiet) A.quiet[v] = (!over && !blocked) ? 1 : 0;
 }
 
 // ------------------------------------------------------------ wave bucket
@@ -301,6 +331,10 @@ __global__ void __launch_bounds__(256) eval_wave_kernel(EvalArgs A) {
     int32_t* vals = tvals[wid];
     const int32_t v = A.nodes[node_i];
     const Ctx kx = ctx_of(A, v);
+    if (skip_quiet(A, v, kx)) {
+        if (lane == 0) store_result(A, node_i, -1, 0, 0, false);
+        return;
+    }
     const int64_t b = A.xadj[v];
     const int32_t d = static_cast<int32_t>(A.xadj[v + 1] - b);
     const int32_t a = A.label[v];
@@ -321,10 +355,12 @@ __global__ void __launch_bounds__(256) eval_wave_kernel(EvalArgs A) {
     const bool over = A.refine && A.w[a] > kx.bound;
     Best best;
     best_init(best);
+    bool blocked = false;  // some other neighbouring label is connected more strongly
     for (uint32_t j = lane; j < tsz; j += 64) {
         const int32_t x = keys[j];
         if (x < 0 || x == a) continue;
         const int32_t conn = vals[j];
+        blocked |= conn > own;
         if (!over && conn <= own) continue;
         if (best.x >= 0 && conn < best.conn) continue;
         if (!eligible(A, x, c, kx)) continue;
@@ -332,7 +368,11 @@ __global__ void __launch_bounds__(256) eval_wave_kernel(EvalArgs A) {
     }
     int32_t bx, bconn;
     wave_argmax(best, kx, bx, bconn);
-    if (lane == 0) store_result(A, node_i, bx, bconn, own, over);
+    const bool any_blocked = __any(blocked);
+    if (lane == 0) {
+        store_result(A, node_i, bx, bconn, own, over);
+        if (A.quiet) A.quiet[v] = (!over && !any_blocked) ? 1 : 0;
+    }
 }
 
 // ----------------------------------------------------------- block bucket
@@ -350,6 +390,10 @@ __global__ void __launch_bounds__(NT) eval_block_kernel(EvalArgs A) {
     const int lane = lane_id();
     const int32_t v = A.nodes[blockIdx.x];
     const Ctx kx = ctx_of(A, v);
+    if (skip_quiet(A, v, kx)) {  // uniform over the workgroup
+        if (tid == 0) store_result(A, blockIdx.x, -1, 0, 0, false);
+        return;
+    }
     const int64_t b = A.xadj[v];
     const int32_t d = static_cast<int32_t>(A.xadj[v + 1] - b);
     const int32_t a = A.label[v];
@@ -371,10 +415,12 @@ __global__ void __launch_bounds__(NT) eval_block_kernel(EvalArgs A) {
     const bool over = A.refine && A.w[a] > kx.bound;
     Best best;
     best_init(best);
+    bool blocked = false;
     for (uint32_t j = tid; j < tsz; j += NT) {
         const int32_t x = keys[j];
         if (x < 0 || x == a) continue;
         const int32_t conn = vals[j];
+        blocked |= conn > own;
         if (!over && conn <= own) continue;
         if (best.x >= 0 && conn < best.conn) continue;
         if (!eligible(A, x, c, kx)) continue;
@@ -387,12 +433,13 @@ __global__ void __launch_bounds__(NT) eval_block_kernel(EvalArgs A) {
         s_x[wid] = bx;
         s_tie[wid] = bx >= 0 ? tie_of(kx, bx) : ~0ULL;
     }
-    __syncthreads();
+    const int any_blocked = __syncthreads_or(blocked);
     if (tid == 0) {
         int32_t fc = -1, fx = -1;
         uint64_t ft = ~0ULL;
         for (int w = 0; w < NT / 64; ++w) combine_into(fc, ft, fx, s_conn[w], s_tie[w], s_x[w]);
         store_result(A, blockIdx.x, fx, fc, own, over);
+        if (A.quiet) A.quiet[v] = (!over && !any_blocked) ? 1 : 0;
     }
 }
 
@@ -1195,6 +1242,7 @@ template <bool kSmall>
 __global__ void __launch_bounds__(256) apply_kernel(const int32_t* __restrict__ ct, const uint8_t* __restrict__ ok,
                                                     const int32_t* __restrict__ nodes, int32_t count,
                                                     const int32_t* __restrict__ vw, int32_t* __restrict__ label,
+                                                    uint8_t* __restrict__ label8, uint16_t* __restrict__ label16,
                                                     int32_t* __restrict__ w, int32_t* __restrict__ tsum,
                                                     int32_t* __restrict__ cnt, int32_t nw) {
     __shared__ int32_t delta[kSmall ? kSmallLabels : 1];
@@ -1214,6 +1262,8 @@ __global__ void __launch_bounds__(256) apply_kernel(const int32_t* __restrict__ 
         const int32_t a = label[v];
         const int32_t c = vw ? vw[v] : 1;
         label[v] = t;
+        if (label8) label8[v] = static_cast<uint8_t>(t);
+        if (label16) label16[v] = static_cast<uint16_t>(t);
         if (c) {
             if (kSmall) {
                 atomicAdd(&delta[t], c);
@@ -1228,6 +1278,32 @@ __global__ void __launch_bounds__(256) apply_kernel(const int32_t* __restrict__ 
         __syncthreads();
         for (int j = threadIdx.x; j < nw; j += 256)
             if (delta[j]) atomicAdd(&w[j], delta[j]);
+    }
+}
+
+template <typename T>
+__global__ void narrow_kernel(const int32_t* __restrict__ label, int32_t n, T* __restrict__ out) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v < n) out[v] = static_cast<T>(label[v]);
+}
+
+// After a sub-round: every neighbour of a node that moved is no longer quiet.
+// One wave per 64 schedule positions; the wave walks each mover's row.
+__global__ void __launch_bounds__(256) unquiet_kernel(const int32_t* __restrict__ ct, const uint8_t* __restrict__ ok,
+                                                      const int32_t* __restrict__ nodes, int32_t count,
+                                                      const int64_t* __restrict__ xadj,
+                                                      const int32_t* __restrict__ adj, uint8_t* __restrict__ quiet) {
+    const int64_t base = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) & ~63LL;
+    const int lane = lane_id();
+    const int64_t p = base + lane;
+    const bool mover = p < count && ct[p] >= 0 && ok[p];
+    uint64_t m = __ballot(mover);
+    while (m) {
+        const int i = __ffsll(static_cast<long long>(m)) - 1;
+        m &= m - 1;
+        const int32_t u = nodes[base + i];
+        const int64_t e = xadj[u + 1];
+        for (int64_t j = xadj[u] + lane; j < e; j += 64) quiet[adj[j]] = 0;
     }
 }
 
@@ -1602,13 +1678,36 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     A.g_bound = mg ? mg->bound : nullptr;
     A.g_lbase = mg ? mg->lbase : nullptr;
     const Bounds BB{bound, mg ? mg->lgid : nullptr, mg ? mg->bound : nullptr};
+    DBuf<uint8_t> lab8;
+    DBuf<uint16_t> lab16;
+    if (nw <= 256) {
+        lab8.alloc(n, s);
+        narrow_kernel<uint8_t><<<grid_for(n, 256), 256, 0, s>>>(label, n, lab8.get());
+        LAUNCHCHK();
+    } else if (nw <= 65536) {
+        lab16.alloc(n, s);
+        narrow_kernel<uint16_t><<<grid_for(n, 256), 256, 0, s>>>(label, n, lab16.get());
+        LAUNCHCHK();
+    }
+    A.label8 = lab8.get();
+    A.label16 = lab16.get();
+    // quiet-node tracking starts once a round has few candidates (marking the
+    // neighbours of every mover is then cheap) and skipping one round later
+    DBuf<uint8_t> quiet;
+    // the default (0) leaves it off here; the batch driver turns it on
+    const bool track_quiet = tune.skip_quiet > 0;
+    if (track_quiet) {
+        quiet.alloc(n, s);
+        fill_u8(quiet.get(), 0, n, s);
+    }
+    int32_t mark_from = INT_MAX;
 
     // Algorithmic bytes of one evaluation launch: per node its schedule entry,
     // row offsets, own label and weight (and w(own) when refining) and its
     // result (target, gain); per slot the neighbour id, edge weight and
-    // neighbour label.
+    // neighbour label (1, 2 or 4 bytes).
     const double node_bytes = 4.0 + 16.0 + 4.0 + (g.vw ? 4.0 : 0.0) + (phase == kRefine ? 4.0 : 0.0) + 8.0;
-    const double slot_bytes = 8.0 + (g.ew ? 4.0 : 0.0);
+    const double slot_bytes = 4.0 + (nw <= 256 ? 1.0 : nw <= 65536 ? 2.0 : 4.0) + (g.ew ? 4.0 : 0.0);
     auto eval_bytes = [&](int64_t nodes_in, unsigned long long slots_in) {
         return node_bytes * static_cast<double>(nodes_in) + slot_bytes * static_cast<double>(slots_in);
     };
@@ -1621,6 +1720,8 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
             graph_prefix_kernel<<<grid_for(mg->G, 256), 256, 0, s>>>(mg->G, mg->seed, 2, lvl64, ph64, r, g_tp.get());
             LAUNCHCHK();
         }
+        A.quiet = r >= mark_from ? quiet.get() : nullptr;
+        A.use_quiet = r > mark_from ? 1 : 0;
         A.tp = hash_prefix({seed, 2, static_cast<uint64_t>(static_cast<uint32_t>(level)),
                             static_cast<uint64_t>(static_cast<uint32_t>(phase)),
                             static_cast<uint64_t>(static_cast<uint32_t>(r))});
@@ -1787,16 +1888,24 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 ProfScope ps("lp_apply", 0, s);
                 if (small) {
                     apply_kernel<true><<<capped_grid(ccount), 256, 0, s>>>(ct.get(), ok.get(), cnodes, ccount, g.vw,
-                                                                           label, w, tsum.get(), tcnt.get(), nw);
+                                                                           label, lab8.get(), lab16.get(), w,
+                                                                           tsum.get(), tcnt.get(), nw);
                     LAUNCHCHK();
                     fill_i32(tsum.get(), 0, nw, s);
                     fill_i32(tcnt.get(), 0, nw, s);
                 } else {
                     apply_kernel<false><<<grid_for(ccount, 256), 256, 0, s>>>(ct.get(), ok.get(), cnodes, ccount,
-                                                                              g.vw, label, w, tsum.get(), tcnt.get(),
-                                                                              nw);
+                                                                              g.vw, label, lab8.get(), lab16.get(), w,
+                                                                              tsum.get(), tcnt.get(), nw);
                     LAUNCHCHK();
                 }
+            }
+            if (A.quiet) {
+                ProfScope ps("lp_unquiet", 0, s);
+                unquiet_kernel<<<grid_for(ccount, 256), 256, 0, s>>>(ct.get(), ok.get(), cnodes,
+                                                                      static_cast<int32_t>(ccount), g.xadj, g.adj,
+                                                                      A.quiet);
+                LAUNCHCHK();
             }
             reset_counters_kernel<<<1, 1, 0, s>>>(ctr.get(), 0);
             LAUNCHCHK();
@@ -1812,6 +1921,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
         res.rounds_run = r + 1;
         res.moves += round_cands;
         if (round_cands == 0) break;
+        if (track_quiet && mark_from == INT_MAX && static_cast<int64_t>(round_cands) * 8 <= n) mark_from = r + 1;
     }
     res.visits = static_cast<int64_t>(res.rounds_run) * g.S;
     HIPCHK(hipStreamSynchronize(s));

@@ -34,6 +34,7 @@ static void fill_any(T* p, T value, int64_t count, hipStream_t s) {
 void fill_i32(int32_t* p, int32_t v, int64_t c, hipStream_t s) { fill_any(p, v, c, s); }
 void fill_i64(int64_t* p, int64_t v, int64_t c, hipStream_t s) { fill_any(p, v, c, s); }
 void fill_u32(uint32_t* p, uint32_t v, int64_t c, hipStream_t s) { fill_any(p, v, c, s); }
+void fill_u8(uint8_t* p, uint8_t v, int64_t c, hipStream_t s) { fill_any(p, v, c, s); }
 void iota_u32(uint32_t* p, int64_t c, hipStream_t s) {
     if (c <= 0) return;
     iota_kernel<<<fill_grid(c), 256, 0, s>>>(p, c);

@@ -9,6 +9,7 @@ namespace sclap {
 void fill_i32(int32_t* p, int32_t value, int64_t count, hipStream_t s);
 void fill_i64(int64_t* p, int64_t value, int64_t count, hipStream_t s);
 void fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
+void fill_u8(uint8_t* p, uint8_t value, int64_t count, hipStream_t s);
 void iota_u32(uint32_t* p, int64_t count, hipStream_t s);
 
 // Exclusive prefix sum of in[0..count) into out[0..count); when total is not

@@ -73,7 +73,8 @@ def check_against_oracle(r, gs, ks, eps, seeds, **opts):
 @pytest.mark.parametrize("opts", [dict(coarsest_nodes=200), dict(coarsest_nodes=50, max_levels=2),
                                   dict(max_levels=1), dict(coarsest_nodes=100000),
                                   dict(coarsest_nodes=200, lane_max_degree=2, wave_max_degree=8,
-                                       block_max_degree=24, select_small_max=1)])
+                                       block_max_degree=24, select_small_max=1),
+                                  dict(coarsest_nodes=200, skip_quiet=-1)])
 def test_batch_matches_oracle_per_graph(sc, opts):
     gs, ks, eps, seeds = mix_small()
     say("batch", opts)

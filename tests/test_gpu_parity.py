@@ -66,7 +66,9 @@ KNOBS = [dict(), dict(lane_max_degree=2, wave_max_degree=8, block_max_degree=24)
          # hub partitions summed through the HBM table / regions spilling to overflow
          dict(lane_max_degree=2, wave_max_degree=8, block_max_degree=24, hub_part_limit=1),
          dict(lane_max_degree=2, wave_max_degree=8, block_max_degree=40, hub_region_cap=3),
-         dict(block_max_degree=60, hub_part_limit=5, hub_region_cap=2, select_small_max=1)]
+         dict(block_max_degree=60, hub_part_limit=5, hub_region_cap=2, select_small_max=1),
+         # quiet nodes skipped once few nodes move
+         dict(skip_quiet=1)]
 
 
 # ------------------------------------------------------------ hand-worked
@@ -123,7 +125,7 @@ def test_cluster_parity(sc, gname, knobs):
 
 REFINE_KNOBS = [dict(block_max_degree=40), dict(block_max_degree=30, hub_part_limit=1, hub_region_cap=2),
                 # every overflowing target through the multi-workgroup selection
-                dict(select_small_max=1), dict(select_small_max=7)]
+                dict(select_small_max=1), dict(select_small_max=7), dict(skip_quiet=1)]
 
 
 @pytest.mark.parametrize("gname", list(GRAPHS))
@@ -156,7 +158,11 @@ def test_contract_project_cut_parity(sc, gname):
     n = g["n"]
     rng = np.random.default_rng(5)
     lab_lp, _, _ = oracle.cluster(g, max(4, n // 100), rounds=4, seed=2)
-    for labels in (lab_lp, rng.integers(0, max(1, n // 7), size=n).astype(np.int32), np.arange(n, dtype=np.int32)):
+    # clusterings, random groupings (short, medium and very long coarse rows with
+    # many parallel edges to merge) and the identity
+    for labels in (lab_lp, rng.integers(0, max(1, n // 7), size=n).astype(np.int32),
+                   rng.integers(0, 150, size=n).astype(np.int32), rng.integers(0, 3, size=n).astype(np.int32),
+                   np.arange(n, dtype=np.int32)):
         say("contract", gname, "labels used=%d" % len(np.unique(labels)))
         C, cg = sc.contract_dev(d, torch.tensor(labels, device="cuda"))
         C_ref, cg_ref = oracle.contract(g, labels)
