@@ -51,6 +51,16 @@ __global__ void probe_kernel(const int32_t* __restrict__ probe, int32_t nprobe, 
     if (i < nprobe) out[i] = probe[i] < n ? q[probe[i]] : *total;
 }
 
+__device__ __forceinline__ int32_t block_sum_i32_256(int32_t v) {
+    __shared__ int32_t sred[4];
+    v = wave_sum(v);
+    if (lane_id() == 0) sred[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const int32_t t = sred[0] + sred[1] + sred[2] + sred[3];
+    __syncthreads();
+    return t;
+}
+
 // Runs of equal keys over consecutive lanes: lead = first lane of this lane's
 // run, end = one past its last lane.
 __device__ __forceinline__ void wave_runs(int32_t key, int& lead, int& end) {
@@ -435,6 +445,176 @@ __global__ void long_tails_kernel(const int32_t* __restrict__ list, const int64_
     tw[rowoff[row] + (d - first)] = static_cast<int32_t>(psum[i] - (st > 0 ? psum[st - 1] : 0));
 }
 
+// Unsorted merge of rows of 65..4096 entries: one workgroup per row sums
+// equal neighbours in an LDS table and writes the distinct entries (in table
+// order) to the row's start.
+__global__ void __launch_bounds__(256) block_hash_rows_kernel(const int32_t* __restrict__ list,
+                                                              const int64_t* __restrict__ rowoff,
+                                                              const int32_t* __restrict__ rowcnt,
+                                                              int32_t* __restrict__ tk, int32_t* __restrict__ tw,
+                                                              int32_t* __restrict__ dcnt) {
+    constexpr int kT = 2 * kBlockRow;
+    __shared__ int32_t keys[kT];
+    __shared__ int32_t sums[kT];
+    __shared__ int32_t s_cnt[256];
+    const int tid = threadIdx.x;
+    const int32_t row = list[blockIdx.x];
+    const int64_t b = rowoff[row];
+    const int32_t len = rowcnt[row];
+    for (int j = tid; j < kT; j += 256) {
+        keys[j] = -1;
+        sums[j] = 0;
+    }
+    __syncthreads();
+    for (int j = tid; j < len; j += 256) {
+        const int32_t x = tk[b + j];
+        uint32_t h = slot_hash(static_cast<uint32_t>(x)) & (kT - 1);
+        while (true) {
+            const int32_t prev = atomicCAS(&keys[h], -1, x);
+            if (prev == -1 || prev == x) break;
+            h = (h + 1) & (kT - 1);
+        }
+        atomicAdd(&sums[h], tw[b + j]);  // partial sums never exceed the final coarse weight
+    }
+    __syncthreads();
+    constexpr int kPer = kT / 256;
+    int32_t mine = 0;
+    for (int j = 0; j < kPer; ++j) mine += keys[tid * kPer + j] >= 0;
+    s_cnt[tid] = mine;
+    __syncthreads();
+    if (tid == 0) {
+        int32_t run = 0;
+        for (int t = 0; t < 256; ++t) {
+            const int32_t x = s_cnt[t];
+            s_cnt[t] = run;
+            run += x;
+        }
+        dcnt[row] = run;
+    }
+    __syncthreads();
+    int32_t pos = s_cnt[tid];
+    for (int j = 0; j < kPer; ++j) {
+        const int e = tid * kPer + j;
+        if (keys[e] < 0) continue;
+        tk[b + pos] = keys[e];
+        tw[b + pos] = sums[e];
+        ++pos;
+    }
+}
+
+// Unsorted merge of long rows after the chunk merge: one open-addressing
+// table in HBM per row (at least twice its merged entries, a power of two),
+// filled with atomics, then compacted chunk by chunk.
+constexpr int kTabChunk = 4096;
+
+__global__ void long_table_sizes_kernel(uint32_t nl, const int64_t* __restrict__ loff, int64_t* __restrict__ tsz,
+                                        int64_t* __restrict__ tch) {
+    const uint32_t l = blockIdx.x * 256 + threadIdx.x;
+    if (l >= nl) return;
+    const int64_t want = 2 * (loff[l + 1] - loff[l]);
+    int64_t t = kTabChunk;
+    while (t < want) t <<= 1;
+    tsz[l] = t;
+    tch[l] = t / kTabChunk;
+}
+
+__global__ void long_table_insert_kernel(const int32_t* __restrict__ list, const int32_t* __restrict__ crow,
+                                         const int64_t* __restrict__ cfirst, int64_t nch,
+                                         const int64_t* __restrict__ coff, int64_t ml,
+                                         const int64_t* __restrict__ rowoff, const int32_t* __restrict__ tk,
+                                         const int32_t* __restrict__ tw, const int64_t* __restrict__ toff,
+                                         const int64_t* __restrict__ tsz, int32_t* __restrict__ gk,
+                                         int32_t* __restrict__ gv) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < ml;
+         i += static_cast<int64_t>(gridDim.x) * 256) {
+        int64_t lo = 0, hi = nch;  // coff[lo] <= i < coff[hi]
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) / 2;
+            if (coff[mid] <= i) lo = mid;
+            else hi = mid;
+        }
+        const int32_t l = crow[lo];
+        const int64_t src = rowoff[list[l]] + (lo - cfirst[l]) * kLongChunk + (i - coff[lo]);
+        const int32_t x = tk[src];
+        int32_t* keys = gk + toff[l];
+        const uint64_t mask = static_cast<uint64_t>(tsz[l]) - 1;
+        uint64_t h = slot_hash(static_cast<uint32_t>(x)) & mask;
+        while (true) {
+            const int32_t prev = atomicCAS(&keys[h], -1, x);
+            if (prev == -1 || prev == x) break;
+            h = (h + 1) & mask;
+        }
+        atomicAdd(&gv[toff[l] + h], tw[src]);
+    }
+}
+
+// table chunk q belongs to row tl[q]
+__global__ void long_table_chunks_kernel(uint32_t nl, const int64_t* __restrict__ tcfirst, int32_t* __restrict__ tl) {
+    const uint32_t l = blockIdx.x;
+    if (l >= nl) return;
+    for (int64_t q = tcfirst[l] + threadIdx.x; q < tcfirst[l + 1]; q += 256) tl[q] = static_cast<int32_t>(l);
+}
+
+__global__ void __launch_bounds__(256) long_table_count_kernel(const int32_t* __restrict__ tl,
+                                                               const int64_t* __restrict__ tcfirst,
+                                                               const int64_t* __restrict__ toff,
+                                                               const int32_t* __restrict__ gk,
+                                                               int32_t* __restrict__ qcnt) {
+    const int64_t q = blockIdx.x;
+    const int32_t l = tl[q];
+    const int64_t base = toff[l] + (q - tcfirst[l]) * kTabChunk;
+    int32_t c = 0;
+    for (int j = threadIdx.x; j < kTabChunk; j += 256) c += gk[base + j] >= 0;
+    c = block_sum_i32_256(c);
+    if (threadIdx.x == 0) qcnt[q] = c;
+}
+
+__global__ void __launch_bounds__(256) long_table_write_kernel(const int32_t* __restrict__ list,
+                                                               const int32_t* __restrict__ tl,
+                                                               const int64_t* __restrict__ tcfirst,
+                                                               const int64_t* __restrict__ toff,
+                                                               const int64_t* __restrict__ qoff,
+                                                               const int64_t* __restrict__ rowoff,
+                                                               const int32_t* __restrict__ gk,
+                                                               const int32_t* __restrict__ gv,
+                                                               int32_t* __restrict__ tk, int32_t* __restrict__ tw,
+                                                               int32_t* __restrict__ dcnt) {
+    __shared__ int32_t s_cnt[256];
+    const int64_t q = blockIdx.x;
+    const int32_t l = tl[q];
+    const int32_t row = list[l];
+    const int64_t base = toff[l] + (q - tcfirst[l]) * kTabChunk;
+    constexpr int kPer = kTabChunk / 256;
+    const int tid = threadIdx.x;
+    int32_t mine = 0;
+    for (int j = 0; j < kPer; ++j) mine += gk[base + tid * kPer + j] >= 0;
+    s_cnt[tid] = mine;
+    __syncthreads();
+    if (tid == 0) {
+        int32_t run = 0;
+        for (int t = 0; t < 256; ++t) {
+            const int32_t x = s_cnt[t];
+            s_cnt[t] = run;
+            run += x;
+        }
+    }
+    __syncthreads();
+    int64_t pos = rowoff[row] + (qoff[q] - qoff[tcfirst[l]]) + s_cnt[tid];
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t e = base + tid * kPer + j;
+        if (gk[e] < 0) continue;
+        tk[pos] = gk[e];
+        tw[pos] = gv[e];
+        ++pos;
+    }
+    if (q == tcfirst[l] && tid == 0) dcnt[row] = static_cast<int32_t>(qoff[tcfirst[l + 1]] - qoff[tcfirst[l]]);
+}
+
+__global__ void row_degrees_kernel(int32_t n, const int64_t* __restrict__ xadj, int32_t* __restrict__ deg) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v < n) deg[v] = static_cast<int32_t>(xadj[v + 1] - xadj[v]);
+}
+
 // Step 4: the merged prefix of every row to its place in the coarse CSR.
 __global__ void __launch_bounds__(kTileThreads) row_copy_kernel(const int64_t* __restrict__ rowoff, int32_t nc, int64_t m,
                                                                 const int32_t* __restrict__ dcnt,
@@ -460,8 +640,136 @@ __global__ void __launch_bounds__(kTileThreads) row_copy_kernel(const int64_t* _
 
 }  // namespace
 
+// Merges (and, if `sorted`, orders by neighbour id) every row r of the
+// entries tk/tw[rowoff[r] .. rowoff[r] + rowcnt[r]) in place; dcnt[r]
+// receives the number of distinct neighbours, written at the row's start.
+void merge_rows(int32_t nc, int64_t m, const int64_t* rowoff, const int32_t* rowcnt, int32_t* tk, int32_t* tw,
+                int32_t* dcnt, bool sorted, hipStream_t s) {
+    DBuf<int32_t> lists(3 * static_cast<size_t>(nc), s);
+    DBuf<uint32_t> counts(3, s);
+    uint32_t hc[3] = {0, 0, 0};
+    {
+        ProfScope ps("contract_rows", 16.0 * static_cast<double>(m), s);
+        fill_u32(counts.get(), 0, 3, s);
+        row_classify_kernel<<<grid_for(nc, 256), 256, 0, s>>>(nc, rowcnt, dcnt, lists.get(), nc,
+                                                               counts.get());
+        LAUNCHCHK();
+        HIPCHK(hipMemcpyAsync(hc, counts.get(), sizeof(hc), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (hc[0] > 0) {
+            wave_rows_kernel<<<grid_for(static_cast<int64_t>(hc[0]) * 64, 256), 256, 0, s>>>(
+                lists.get(), hc[0], rowoff, rowcnt, tk, tw, dcnt);
+            LAUNCHCHK();
+        }
+        if (hc[1] > 0) {
+            if (sorted)
+                block_rows_kernel<<<hc[1], 256, 0, s>>>(lists.get() + nc, rowoff, rowcnt, tk, tw, dcnt);
+            else
+                block_hash_rows_kernel<<<hc[1], 256, 0, s>>>(lists.get() + nc, rowoff, rowcnt, tk, tw, dcnt);
+            LAUNCHCHK();
+        }
+    }
+    if (hc[2] > 0) {
+        ProfScope ps("contract_long_rows", 0, s);
+        const uint32_t nl = hc[2];
+        const int32_t* llist = lists.get() + 2 * static_cast<size_t>(nc);
+        // chunks of the long rows, each merged in LDS first
+        DBuf<int32_t> lens(nl, s);
+        DBuf<int64_t> cfirst(static_cast<size_t>(nl) + 1, s), ctot(1, s);
+        long_lens_kernel<<<grid_for(nl, 256), 256, 0, s>>>(llist, nl, rowcnt, lens.get(), kLongChunk);
+        LAUNCHCHK();
+        exclusive_scan_i32_to_i64(lens.get(), cfirst.get(), nl, ctot.get(), s);
+        int64_t nch = 0;
+        HIPCHK(hipMemcpyAsync(&nch, ctot.get(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        fill_i64(cfirst.get() + nl, nch, 1, s);
+        DBuf<int32_t> crow(nch, s), ccnt(nch, s);
+        DBuf<int64_t> coff(static_cast<size_t>(nch) + 1, s), mtot2(1, s), loff(static_cast<size_t>(nl) + 1, s);
+        long_chunks_kernel<<<nl, 256, 0, s>>>(nl, cfirst.get(), crow.get());
+        LAUNCHCHK();
+        long_dedup_kernel<<<static_cast<unsigned>(nch), 256, 0, s>>>(llist, crow.get(), cfirst.get(), rowoff,
+                                                                     rowcnt, tk, tw, ccnt.get());
+        LAUNCHCHK();
+        exclusive_scan_i32_to_i64(ccnt.get(), coff.get(), nch, mtot2.get(), s);
+        int64_t ml = 0;
+        HIPCHK(hipMemcpyAsync(&ml, mtot2.get(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        fill_i64(coff.get() + nch, ml, 1, s);
+        long_offsets_kernel<<<grid_for(static_cast<int64_t>(nl) + 1, 256), 256, 0, s>>>(nl, cfirst.get(), coff.get(),
+                                                                                         loff.get());
+        LAUNCHCHK();
+        if (!sorted) {
+            DBuf<int64_t> tsz(nl, s), tch(nl, s), toff(static_cast<size_t>(nl) + 1, s),
+                tcfirst(static_cast<size_t>(nl) + 1, s);
+            long_table_sizes_kernel<<<grid_for(nl, 256), 256, 0, s>>>(nl, loff.get(), tsz.get(), tch.get());
+            LAUNCHCHK();
+            // offsets: [0, inclusive sums]
+            fill_i64(toff.get(), 0, 1, s);
+            fill_i64(tcfirst.get(), 0, 1, s);
+            inclusive_scan_i64(tsz.get(), toff.get() + 1, nl, s);
+            inclusive_scan_i64(tch.get(), tcfirst.get() + 1, nl, s);
+            int64_t hts[2] = {0, 0};
+            HIPCHK(hipMemcpyAsync(&hts[0], toff.get() + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(&hts[1], tcfirst.get() + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            const int64_t ttot = hts[0], nq = hts[1];
+            DBuf<int32_t> gk(ttot, s), gv(ttot, s), tl(nq, s), qcnt(nq, s);
+            DBuf<int64_t> qoff(static_cast<size_t>(nq) + 1, s), qt(1, s);
+            fill_i32(gk.get(), -1, ttot, s);
+            fill_i32(gv.get(), 0, ttot, s);
+            long_table_insert_kernel<<<static_cast<unsigned>(std::min<int64_t>((ml + 255) / 256, 8192)), 256, 0, s>>>(
+                llist, crow.get(), cfirst.get(), nch, coff.get(), ml, rowoff, tk, tw, toff.get(), tsz.get(), gk.get(),
+                gv.get());
+            LAUNCHCHK();
+            long_table_chunks_kernel<<<nl, 256, 0, s>>>(nl, tcfirst.get(), tl.get());
+            LAUNCHCHK();
+            long_table_count_kernel<<<static_cast<unsigned>(nq), 256, 0, s>>>(tl.get(), tcfirst.get(), toff.get(),
+                                                                            gk.get(), qcnt.get());
+            LAUNCHCHK();
+            exclusive_scan_i32_to_i64(qcnt.get(), qoff.get(), nq, qt.get(), s);
+            HIPCHK(hipMemcpyAsync(qoff.get() + nq, qt.get(), sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+            long_table_write_kernel<<<static_cast<unsigned>(nq), 256, 0, s>>>(llist, tl.get(), tcfirst.get(),
+                                                                            toff.get(), qoff.get(), rowoff, gk.get(),
+                                                                            gv.get(), tk, tw, dcnt);
+            LAUNCHCHK();
+            return;
+        }
+        const int bn = std::max(1, bits_for(static_cast<uint64_t>(nc - 1)));
+        DBuf<uint64_t> keys(ml, s), ktmp(ml, s);
+        DBuf<uint32_t> vals(ml, s), vtmp(ml, s);
+        long_keys_kernel<<<static_cast<unsigned>(std::min<int64_t>((ml + 255) / 256, 8192)), 256, 0, s>>>(
+            llist, crow.get(), cfirst.get(), nch, coff.get(), ml, rowoff, tk, tw, bn, keys.get(),
+            vals.get());
+        LAUNCHCHK();
+        {
+            ProfScope ps2("contract_long_sort", 0, s);
+            RadixScratch rs;
+            radix_sort_pairs(keys.get(), vals.get(), ktmp.get(), vtmp.get(), ml, 0,
+                             bn + std::max(1, bits_for(static_cast<uint64_t>(nl - 1))), rs, s);
+        }
+        DBuf<int32_t> head(ml, s);
+        DBuf<int64_t> pos(ml, s), psum(ml, s), dtot(1, s), run_start(ml, s);
+        ktmp.release();
+        vtmp.release();
+        long_heads_kernel<<<grid_for(ml, 256), 256, 0, s>>>(keys.get(), vals.get(), ml, head.get(), psum.get());
+        LAUNCHCHK();
+        exclusive_scan_i32_to_i64(head.get(), pos.get(), ml, dtot.get(), s);
+        inclusive_scan_i64(psum.get(), psum.get(), ml, s);
+        long_runs_kernel<<<grid_for(ml, 256), 256, 0, s>>>(llist, loff.get(), rowoff, keys.get(), ml,
+                                                           head.get(), pos.get(), bn, run_start.get(), tk,
+                                                           dcnt);
+        LAUNCHCHK();
+        long_tails_kernel<<<grid_for(ml, 256), 256, 0, s>>>(llist, loff.get(), rowoff, keys.get(), ml,
+                                                            head.get(), pos.get(), psum.get(), bn, run_start.get(),
+                                                            tw);
+        LAUNCHCHK();
+    }
+
+}
+
+
 void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGraph& coarse, hipStream_t s,
-              const int32_t* probe, int32_t nprobe, int32_t* probe_out) {
+              const int32_t* probe, int32_t nprobe, int32_t* probe_out, bool sorted) {
     const int32_t n = g.n;
     if (n == 0) {
         coarse.n = 0;
@@ -535,88 +843,9 @@ void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGrap
         LAUNCHCHK();
     }
 
-    // 3: sort and merge every row
-    DBuf<int32_t> dcnt(nc, s), lists(3 * static_cast<size_t>(nc), s);
-    DBuf<uint32_t> counts(3, s);
-    uint32_t hc[3] = {0, 0, 0};
-    {
-        ProfScope ps("contract_rows", 16.0 * static_cast<double>(m), s);
-        fill_u32(counts.get(), 0, 3, s);
-        row_classify_kernel<<<grid_for(nc, 256), 256, 0, s>>>(nc, rowcnt.get(), dcnt.get(), lists.get(), nc,
-                                                               counts.get());
-        LAUNCHCHK();
-        HIPCHK(hipMemcpyAsync(hc, counts.get(), sizeof(hc), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (hc[0] > 0) {
-            wave_rows_kernel<<<grid_for(static_cast<int64_t>(hc[0]) * 64, 256), 256, 0, s>>>(
-                lists.get(), hc[0], rowoff.get(), rowcnt.get(), tk.get(), tw.get(), dcnt.get());
-            LAUNCHCHK();
-        }
-        if (hc[1] > 0) {
-            block_rows_kernel<<<hc[1], 256, 0, s>>>(lists.get() + nc, rowoff.get(), rowcnt.get(), tk.get(), tw.get(),
-                                                     dcnt.get());
-            LAUNCHCHK();
-        }
-    }
-    if (hc[2] > 0) {
-        ProfScope ps("contract_long_rows", 0, s);
-        const uint32_t nl = hc[2];
-        const int32_t* llist = lists.get() + 2 * static_cast<size_t>(nc);
-        // chunks of the long rows, each merged in LDS first
-        DBuf<int32_t> lens(nl, s);
-        DBuf<int64_t> cfirst(static_cast<size_t>(nl) + 1, s), ctot(1, s);
-        long_lens_kernel<<<grid_for(nl, 256), 256, 0, s>>>(llist, nl, rowcnt.get(), lens.get(), kLongChunk);
-        LAUNCHCHK();
-        exclusive_scan_i32_to_i64(lens.get(), cfirst.get(), nl, ctot.get(), s);
-        int64_t nch = 0;
-        HIPCHK(hipMemcpyAsync(&nch, ctot.get(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        fill_i64(cfirst.get() + nl, nch, 1, s);
-        DBuf<int32_t> crow(nch, s), ccnt(nch, s);
-        DBuf<int64_t> coff(static_cast<size_t>(nch) + 1, s), mtot2(1, s), loff(static_cast<size_t>(nl) + 1, s);
-        long_chunks_kernel<<<nl, 256, 0, s>>>(nl, cfirst.get(), crow.get());
-        LAUNCHCHK();
-        long_dedup_kernel<<<static_cast<unsigned>(nch), 256, 0, s>>>(llist, crow.get(), cfirst.get(), rowoff.get(),
-                                                                     rowcnt.get(), tk.get(), tw.get(), ccnt.get());
-        LAUNCHCHK();
-        exclusive_scan_i32_to_i64(ccnt.get(), coff.get(), nch, mtot2.get(), s);
-        int64_t ml = 0;
-        HIPCHK(hipMemcpyAsync(&ml, mtot2.get(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        fill_i64(coff.get() + nch, ml, 1, s);
-        long_offsets_kernel<<<grid_for(static_cast<int64_t>(nl) + 1, 256), 256, 0, s>>>(nl, cfirst.get(), coff.get(),
-                                                                                         loff.get());
-        LAUNCHCHK();
-        const int bn = std::max(1, bits_for(static_cast<uint64_t>(nc - 1)));
-        DBuf<uint64_t> keys(ml, s), ktmp(ml, s);
-        DBuf<uint32_t> vals(ml, s), vtmp(ml, s);
-        long_keys_kernel<<<static_cast<unsigned>(std::min<int64_t>((ml + 255) / 256, 8192)), 256, 0, s>>>(
-            llist, crow.get(), cfirst.get(), nch, coff.get(), ml, rowoff.get(), tk.get(), tw.get(), bn, keys.get(),
-            vals.get());
-        LAUNCHCHK();
-        {
-            ProfScope ps2("contract_long_sort", 0, s);
-            RadixScratch rs;
-            radix_sort_pairs(keys.get(), vals.get(), ktmp.get(), vtmp.get(), ml, 0,
-                             bn + std::max(1, bits_for(static_cast<uint64_t>(nl - 1))), rs, s);
-        }
-        DBuf<int32_t> head(ml, s);
-        DBuf<int64_t> pos(ml, s), psum(ml, s), dtot(1, s), run_start(ml, s);
-        ktmp.release();
-        vtmp.release();
-        long_heads_kernel<<<grid_for(ml, 256), 256, 0, s>>>(keys.get(), vals.get(), ml, head.get(), psum.get());
-        LAUNCHCHK();
-        exclusive_scan_i32_to_i64(head.get(), pos.get(), ml, dtot.get(), s);
-        inclusive_scan_i64(psum.get(), psum.get(), ml, s);
-        long_runs_kernel<<<grid_for(ml, 256), 256, 0, s>>>(llist, loff.get(), rowoff.get(), keys.get(), ml,
-                                                           head.get(), pos.get(), bn, run_start.get(), tk.get(),
-                                                           dcnt.get());
-        LAUNCHCHK();
-        long_tails_kernel<<<grid_for(ml, 256), 256, 0, s>>>(llist, loff.get(), rowoff.get(), keys.get(), ml,
-                                                            head.get(), pos.get(), psum.get(), bn, run_start.get(),
-                                                            tw.get());
-        LAUNCHCHK();
-    }
+    // 3: merge (and order) every row
+    DBuf<int32_t> dcnt(nc, s);
+    merge_rows(nc, m, rowoff.get(), rowcnt.get(), tk.get(), tw.get(), dcnt.get(), sorted, s);
 
     // 4: coarse offsets and the merged rows
     ProfScope ps_copy("contract_copy", 16.0 * static_cast<double>(m), s);
@@ -634,6 +863,16 @@ void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGrap
                                                                            coarse.xadj.get(), tk.get(), tw.get(),
                                                                            coarse.adj.get(), coarse.ew.get());
     LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+void sort_rows(OwnedDevGraph& g, hipStream_t s) {
+    if (g.n == 0 || g.S == 0) return;
+    ProfScope ps("contract_sort_rows", 16.0 * static_cast<double>(g.S), s);
+    DBuf<int32_t> deg(g.n, s), dcnt(g.n, s);
+    row_degrees_kernel<<<grid_for(g.n, 256), 256, 0, s>>>(g.n, g.xadj.get(), deg.get());
+    LAUNCHCHK();
+    merge_rows(g.n, g.S, g.xadj.get(), deg.get(), g.adj.get(), g.ew.get(), dcnt.get(), true, s);
     HIPCHK(hipStreamSynchronize(s));
 }
 

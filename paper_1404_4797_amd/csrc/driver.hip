@@ -401,7 +401,7 @@ int partition_impl(const DevGraph& g0_in, int32_t k, double eps, uint64_t seed, 
         w.release();
         DBuf<int32_t> C(n, s);
         Level nx;
-        contract(G, labels.get(), C.get(), nx.own, s);
+        contract(G, labels.get(), C.get(), nx.own, s, nullptr, 0, nullptr, false);
         if (nx.own.n >= n) break;  // no shrink: keep the current level as the coarsest
         L[lev].C = std::move(C);
         nx.g = nx.own.view();
@@ -412,6 +412,9 @@ int partition_impl(const DevGraph& g0_in, int32_t k, double eps, uint64_t seed, 
         if (20LL * L[lev].g.n > 19LL * n) break;  // stalled
     }
     st->levels = lev;
+    // inner levels keep their rows unordered; the initial partition grows
+    // blocks along ascending neighbour ids, so order the coarsest graph's rows
+    if (lev > 0) sort_rows(L[lev].own, s);
     HIPCHK(hipStreamSynchronize(s));
     st->ms_coarsen = ms_since(t_coarsen);
 
@@ -654,7 +657,7 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
         DBuf<int32_t> probe(M + 1, s), qb(M + 1, s), C(n, s);
         upload_vec(probe, B.nb, s);
         OwnedDevGraph coarse;
-        contract(B.g, labels.get(), C.get(), coarse, s, probe.get(), M + 1, qb.get());
+        contract(B.g, labels.get(), C.get(), coarse, s, probe.get(), M + 1, qb.get(), false);
         std::vector<int32_t> cb(M + 1);
         HIPCHK(hipMemcpyAsync(cb.data(), qb.get(), (M + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -754,7 +757,7 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
         for (auto& x : sl.x) x -= x0;
         for (int64_t j = 0; j < sl.x[nm]; ++j) sl.a[j] -= B.nb[m];
         host_initial_partition(nm, sl.x.data(), sl.a.data(), sl.v.empty() ? nullptr : sl.v.data(), k[g], T[g],
-                               sl.part.data(), last[g] > 0);
+                               sl.part.data(), false);  // rows of inner levels are unordered
         for (auto& b : sl.part) b += kb[g];  // labels of the batch's block space
         sl.x = {};
         sl.a = {};

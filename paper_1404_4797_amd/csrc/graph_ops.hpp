@@ -33,8 +33,13 @@ struct OwnedDevGraph {
 // weights.
 // probe (device, nprobe entries in [0, n]) optionally reports the coarse id
 // base of label positions: probe_out[i] = number of used labels < probe[i].
+// sorted = false leaves each coarse row's distinct neighbours in an unspecified
+// order (label propagation and contraction do not depend on row order).
 void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGraph& coarse, hipStream_t s,
-              const int32_t* probe = nullptr, int32_t nprobe = 0, int32_t* probe_out = nullptr);
+              const int32_t* probe = nullptr, int32_t nprobe = 0, int32_t* probe_out = nullptr, bool sorted = true);
+
+// Orders every row of g by neighbour id (rows hold distinct neighbours).
+void sort_rows(OwnedDevGraph& g, hipStream_t s);
 
 // part[v] = coarse_part[C[v]]
 void project(int32_t n, const int32_t* C, const int32_t* coarse_part, int32_t* part, hipStream_t s);

@@ -39,10 +39,14 @@ namespace sclap {
 
 namespace {
 
-constexpr int kNB = 7;  // buckets: lane4, lane16, wave, block (3 table sizes), hub
+// buckets: lane4, lane16, group16 (16 lanes per node), group32, wave,
+// block (3 table sizes), hub
+constexpr int kNB = 9;
 constexpr int kHubBucket = kNB - 1;
 constexpr int kLaneSmall = 4;
 constexpr int kLaneMax = 16;
+constexpr int kG16Max = 32;  // 16 lanes and a 64-entry table per node
+constexpr int kG32Max = 64;  // 32 lanes and a 128-entry table per node
 constexpr int kWaveTable = 512;
 constexpr int kWaveMaxDeg = kWaveTable / 2;
 constexpr int kBlockTable = 16384;
@@ -185,6 +189,65 @@ __device__ __forceinline__ void wave_argmax(const Best& b, const Ctx& kx, int32_
     out_conn = maxc;
 }
 
+// Reductions over aligned groups of G lanes of a wave (G a power of two <= 64).
+template <int G>
+__device__ __forceinline__ int32_t group_max(int32_t v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+        const int32_t u = __shfl_xor(v, o, 64);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ int32_t group_min(int32_t v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+        const int32_t u = __shfl_xor(v, o, 64);
+        v = u < v ? u : v;
+    }
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ uint64_t group_min_u64(uint64_t v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+        const uint32_t lo = __shfl_xor(static_cast<uint32_t>(v), o, 64);
+        const uint32_t hi = __shfl_xor(static_cast<uint32_t>(v >> 32), o, 64);
+        const uint64_t u = (static_cast<uint64_t>(hi) << 32) | lo;
+        v = u < v ? u : v;
+    }
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ bool group_any(bool b) {
+    const uint64_t m = __ballot(b);
+    if (G == 64) return m != 0;
+    const int base = lane_id() & ~(G - 1);
+    return ((m >> base) & ((1ULL << G) - 1)) != 0;
+}
+
+// Group-wide argmax; every lane of the group gets the winning (x, conn).
+template <int G>
+__device__ __forceinline__ void group_argmax(const Best& b, const Ctx& kx, int32_t& out_x, int32_t& out_conn) {
+    const int32_t bc = b.x >= 0 ? b.conn : -1;
+    const int32_t maxc = group_max<G>(bc);
+    if (maxc < 0) {
+        out_x = -1;
+        out_conn = -1;
+        return;
+    }
+    const bool top = b.x >= 0 && bc == maxc;
+    const uint64_t tk = top ? best_tie(b, kx) : ~0ULL;
+    const uint64_t mt = group_min_u64<G>(tk);
+    const int32_t xx = (top && tk == mt) ? b.x : INT_MAX;
+    out_x = group_min<G>(xx);
+    out_conn = maxc;
+}
+
 // Combines one candidate per wave (written to LDS by each wave's lane 0).
 __device__ __forceinline__ void combine_into(int32_t& bc, uint64_t& bt, int32_t& bx, int32_t c2, uint64_t t2,
                                              int32_t x2) {
@@ -318,45 +381,49 @@ __global__ void __launch_bounds__(256) eval_lane_kernel(EvalArgs A) {
     if (A.quiet) A.quiet[v] = (!over && !blocked) ? 1 : 0;
 }
 
-// ------------------------------------------------------------ wave bucket
+// --------------------------------------------------- group and wave buckets
 
-__global__ void __launch_bounds__(256) eval_wave_kernel(EvalArgs A) {
-    __shared__ int32_t tkeys[4][kWaveTable];
-    __shared__ int32_t tvals[4][kWaveTable];
-    const int wid = threadIdx.x >> 6;
-    const int lane = lane_id();
-    const int node_i = blockIdx.x * 4 + wid;
-    if (node_i >= A.count) return;
-    int32_t* keys = tkeys[wid];
-    int32_t* vals = tvals[wid];
+// G lanes per node (G = 16, 32 or 64: 256 / G nodes per workgroup), each
+// group with an open-addressing table of T entries in LDS.
+template <int G, int T>
+__global__ void __launch_bounds__(256) eval_group_kernel(EvalArgs A) {
+    constexpr int NG = 256 / G;
+    __shared__ int32_t tkeys[NG][T];
+    __shared__ int32_t tvals[NG][T];
+    const int grp = threadIdx.x / G;
+    const int gl = threadIdx.x % G;
+    const int node_i = blockIdx.x * NG + grp;
+    if (node_i >= A.count) return;  // uniform per group
+    int32_t* keys = tkeys[grp];
+    int32_t* vals = tvals[grp];
     const int32_t v = A.nodes[node_i];
     const Ctx kx = ctx_of(A, v);
     if (skip_quiet(A, v, kx)) {
-        if (lane == 0) store_result(A, node_i, -1, 0, 0, false);
+        if (gl == 0) store_result(A, node_i, -1, 0, 0, false);
         return;
     }
     const int64_t b = A.xadj[v];
     const int32_t d = static_cast<int32_t>(A.xadj[v + 1] - b);
     const int32_t a = A.label[v];
     const int32_t c = A.vw ? A.vw[v] : 1;
-    const uint32_t tsz = table_size_for(d, 64, kWaveTable);
+    const uint32_t tsz = table_size_for(d, T < 64 ? T : 64, T);
     const uint32_t mask = tsz - 1;
-    for (uint32_t j = lane; j < tsz; j += 64) {
+    for (uint32_t j = gl; j < tsz; j += G) {
         keys[j] = -1;
         vals[j] = 0;
     }
     wave_sync();
-    insert_slots<64, 4>(A, b, d, keys, vals, mask, lane);
+    insert_slots<G, 4>(A, b, d, keys, vals, mask, gl);
     wave_sync();
     int32_t ownp = 0;
-    for (uint32_t j = lane; j < tsz; j += 64)
+    for (uint32_t j = gl; j < tsz; j += G)
         if (keys[j] == a) ownp = vals[j];
-    const int32_t own = wave_max(ownp);
+    const int32_t own = group_max<G>(ownp);
     const bool over = A.refine && A.w[a] > kx.bound;
     Best best;
     best_init(best);
     bool blocked = false;  // some other neighbouring label is connected more strongly
-    for (uint32_t j = lane; j < tsz; j += 64) {
+    for (uint32_t j = gl; j < tsz; j += G) {
         const int32_t x = keys[j];
         if (x < 0 || x == a) continue;
         const int32_t conn = vals[j];
@@ -367,9 +434,9 @@ __global__ void __launch_bounds__(256) eval_wave_kernel(EvalArgs A) {
         best_consider(best, x, conn, kx);
     }
     int32_t bx, bconn;
-    wave_argmax(best, kx, bx, bconn);
-    const bool any_blocked = __any(blocked);
-    if (lane == 0) {
+    group_argmax<G>(best, kx, bx, bconn);
+    const bool any_blocked = group_any<G>(blocked);
+    if (gl == 0) {
         store_result(A, node_i, bx, bconn, own, over);
         if (A.quiet) A.quiet[v] = (!over && !any_blocked) ? 1 : 0;
     }
@@ -1321,6 +1388,11 @@ __global__ void reset_counters_kernel(Counters* ctr, int round_too) {
 
 // --------------------------------------------------------------- schedule
 
+// Upper degree of each bucket but the hub bucket (non-decreasing).
+struct Thresholds {
+    int32_t t[kNB - 1];
+};
+
 // Category of a node: colour * kNB + degree bucket; degree-0 nodes never move
 // and go to the extra category ncat.
 __global__ void __launch_bounds__(256) classify_kernel(int32_t n, const int64_t* __restrict__ xadj,
@@ -1328,8 +1400,7 @@ __global__ void __launch_bounds__(256) classify_kernel(int32_t n, const int64_t*
                                                        const int32_t* __restrict__ gid, const uint64_t* __restrict__ g_hc,
                                                        const int32_t* __restrict__ g_nbase,
                                                        const uint8_t* __restrict__ g_active,
-                                                       int32_t nsub, int32_t th0, int32_t th1, int32_t th2,
-                                                       int32_t th3, int32_t th4, int32_t th5,
+                                                       int32_t nsub, Thresholds th,
                                                        uint64_t* __restrict__ keys,
                                                        uint32_t* __restrict__ vals, uint32_t* __restrict__ cat_count,
                                                        unsigned long long* __restrict__ cat_slots, Counters* ctr) {
@@ -1364,13 +1435,10 @@ __global__ void __launch_bounds__(256) classify_kernel(int32_t n, const int64_t*
             col = static_cast<int32_t>(mix64(hcv ^ static_cast<uint64_t>(static_cast<uint32_t>(lv))) %
                                        static_cast<uint64_t>(nsub));
         }
-        const int32_t bucket = d <= th0   ? 0
-                               : d <= th1 ? 1
-                               : d <= th2 ? 2
-                               : d <= th3 ? 3
-                               : d <= th4 ? 4
-                               : d <= th5 ? 5
-                                          : kHubBucket;
+        int32_t bucket = kHubBucket;
+#pragma unroll
+        for (int j = kHubBucket - 1; j >= 0; --j)
+            if (d <= th.t[j]) bucket = j;
         const int32_t cat = (d == 0 || !act) ? ncat : col * kNB + bucket;
         keys[v] = static_cast<uint64_t>(cat);
         vals[v] = static_cast<uint32_t>(v);
@@ -1482,13 +1550,20 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
 
     // --- schedule: nodes grouped by (colour, degree bucket), ascending ids
     const int32_t ncat = nsub * kNB;
-    const int32_t th1 = std::max(1, std::min(tune.lane_max, kLaneMax));
-    const int32_t th0 = std::min(kLaneSmall, th1);
-    const int32_t th2 = std::max(th1, std::min(tune.wave_max, kWaveMaxDeg));
-    const int32_t tb = std::max(th2, std::min(tune.block_max, kBlockMaxDeg));
-    const int32_t th3 = std::min(tb, std::max(th2, kBlock1Max));
-    const int32_t th4 = std::min(tb, std::max(th3, kBlock2Max));
-    const int32_t th5 = tb;
+    Thresholds th;
+    {
+        const int32_t lane = std::max(1, std::min(tune.lane_max, kLaneMax));
+        const int32_t wave = std::max(lane, std::min(tune.wave_max, kWaveMaxDeg));
+        const int32_t block = std::max(wave, std::min(tune.block_max, kBlockMaxDeg));
+        th.t[0] = std::min(kLaneSmall, lane);
+        th.t[1] = lane;
+        th.t[2] = std::max(lane, std::min(kG16Max, wave));
+        th.t[3] = std::max(th.t[2], std::min(kG32Max, wave));
+        th.t[4] = wave;
+        th.t[5] = std::min(block, std::max(wave, kBlock1Max));
+        th.t[6] = std::min(block, std::max(th.t[5], kBlock2Max));
+        th.t[7] = block;
+    }
     DBuf<uint64_t> ckeys(n, s), ckeys_tmp(n, s);
     DBuf<uint32_t> order(n, s), order_tmp(n, s);
     DBuf<uint32_t> cat_count(ncat + 1, s);
@@ -1512,7 +1587,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
         ProfScope ps("lp_schedule", 0, s);
         classify_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, g.xadj, color_override, hc, mg ? mg->gid : nullptr,
                                                          g_hc.get(), mg ? mg->nbase : nullptr,
-                                                         mg ? mg->active : nullptr, nsub, th0, th1, th2, th3, th4, th5,
+                                                         mg ? mg->active : nullptr, nsub, th,
                                                          ckeys.get(), order.get(), cat_count.get(), cat_slots.get(),
                                                          ctr.get());
         LAUNCHCHK();
@@ -1738,7 +1813,8 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 A.count = static_cast<int32_t>(count);
                 A.ct = ct.get() + (off[c0 + bk] - off[c0]);
                 A.cg = cg.get() + (off[c0 + bk] - off[c0]);
-                static const char* const kNames[kHubBucket] = {"lp_eval_lane4", "lp_eval_lane16", "lp_eval_wave",
+                static const char* const kNames[kHubBucket] = {"lp_eval_lane4", "lp_eval_lane16", "lp_eval_group16",
+                                                               "lp_eval_group32", "lp_eval_wave",
                                                                "lp_eval_block1k", "lp_eval_block4k",
                                                                "lp_eval_block8k"};
                 ProfScope ps(kNames[bk], eval_bytes(count, cslots[c0 + bk]), s);
@@ -1748,10 +1824,14 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 } else if (bk == 1) {
                     eval_lane_kernel<kLaneMax><<<grid_for(count, 256), 256, 0, s>>>(A);
                 } else if (bk == 2) {
-                    eval_wave_kernel<<<grid_for(count, 4), 256, 0, s>>>(A);
+                    eval_group_kernel<16, 2 * kG16Max><<<grid_for(count, 16), 256, 0, s>>>(A);
                 } else if (bk == 3) {
-                    eval_block_kernel<256, 2 * kBlock1Max><<<nb, 256, 0, s>>>(A);
+                    eval_group_kernel<32, 2 * kG32Max><<<grid_for(count, 8), 256, 0, s>>>(A);
                 } else if (bk == 4) {
+                    eval_group_kernel<64, kWaveTable><<<grid_for(count, 4), 256, 0, s>>>(A);
+                } else if (bk == 5) {
+                    eval_block_kernel<256, 2 * kBlock1Max><<<nb, 256, 0, s>>>(A);
+                } else if (bk == 6) {
                     eval_block_kernel<512, 2 * kBlock2Max><<<nb, 512, 0, s>>>(A);
                 } else {
                     eval_block_kernel<1024, kBlockTable><<<nb, 1024, 0, s>>>(A);
