@@ -292,7 +292,8 @@ def main():
                    "launches_per_step": v["launches"] // max(args.steps, 1),
                    "GBps": round(v["bytes"] / (v["ms"] / 1000.0) / 1e9, 1) if v["bytes"] and v["ms"] else None}
                for k, v in sorted(kstats.items(), key=lambda kv: -kv[1]["ms"])}
-    lp_gb = sum(v["bytes"] for k, v in kstats.items() if k.startswith("lp_eval")) / max(args.steps, 1) / 1e9
+    lp_gb = sum(v["bytes"] for k, v in kstats.items()
+                if k.startswith("lp_eval") or k.startswith("lp_refine")) / max(args.steps, 1) / 1e9
 
     out = {
         "metric": "SCLaP edge-visits/s & partition time; batched vs plain graphs/s, same cut",

@@ -368,24 +368,24 @@ __global__ void __launch_bounds__(256) long_dedup_kernel(const int32_t* __restri
     }
 }
 
-// Sort keys (long-row index << bn | C(v)) over the merged chunk entries.
-__global__ void long_keys_kernel(const int32_t* __restrict__ list, const int32_t* __restrict__ crow,
-                                 const int64_t* __restrict__ cfirst, int64_t nch, const int64_t* __restrict__ coff,
-                                 int64_t ml, const int64_t* __restrict__ rowoff, const int32_t* __restrict__ tk,
-                                 const int32_t* __restrict__ tw, int bn, uint64_t* __restrict__ keys,
-                                 uint32_t* __restrict__ vals) {
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < ml;
-         i += static_cast<int64_t>(gridDim.x) * 256) {
-        int64_t lo = 0, hi = nch;  // coff[lo] <= i < coff[hi]
-        while (hi - lo > 1) {
-            const int64_t mid = (lo + hi) / 2;
-            if (coff[mid] <= i) lo = mid;
-            else hi = mid;
-        }
-        const int32_t l = crow[lo];
-        const int64_t src = rowoff[list[l]] + (lo - cfirst[l]) * kLongChunk + (i - coff[lo]);
-        keys[i] = (static_cast<uint64_t>(l) << bn) | static_cast<uint32_t>(tk[src]);
-        vals[i] = static_cast<uint32_t>(tw[src]);
+// Sort keys (long-row index << bn | C(v)) over the merged chunk entries, one
+// chunk per workgroup.
+__global__ void __launch_bounds__(256) long_keys_kernel(const int32_t* __restrict__ list,
+                                                        const int32_t* __restrict__ crow,
+                                                        const int64_t* __restrict__ cfirst,
+                                                        const int32_t* __restrict__ ccnt,
+                                                        const int64_t* __restrict__ coff,
+                                                        const int64_t* __restrict__ rowoff,
+                                                        const int32_t* __restrict__ tk, const int32_t* __restrict__ tw,
+                                                        int bn, uint64_t* __restrict__ keys,
+                                                        uint32_t* __restrict__ vals) {
+    const int64_t c = blockIdx.x;
+    const int32_t l = crow[c];
+    const int64_t src = rowoff[list[l]] + (c - cfirst[l]) * kLongChunk;
+    const int64_t dst = coff[c];
+    for (int32_t j = threadIdx.x; j < ccnt[c]; j += 256) {
+        keys[dst + j] = (static_cast<uint64_t>(l) << bn) | static_cast<uint32_t>(tk[src + j]);
+        vals[dst + j] = static_cast<uint32_t>(tw[src + j]);
     }
 }
 
@@ -518,33 +518,31 @@ __global__ void long_table_sizes_kernel(uint32_t nl, const int64_t* __restrict__
     tch[l] = t / kTabChunk;
 }
 
-__global__ void long_table_insert_kernel(const int32_t* __restrict__ list, const int32_t* __restrict__ crow,
-                                         const int64_t* __restrict__ cfirst, int64_t nch,
-                                         const int64_t* __restrict__ coff, int64_t ml,
-                                         const int64_t* __restrict__ rowoff, const int32_t* __restrict__ tk,
-                                         const int32_t* __restrict__ tw, const int64_t* __restrict__ toff,
-                                         const int64_t* __restrict__ tsz, int32_t* __restrict__ gk,
-                                         int32_t* __restrict__ gv) {
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < ml;
-         i += static_cast<int64_t>(gridDim.x) * 256) {
-        int64_t lo = 0, hi = nch;  // coff[lo] <= i < coff[hi]
-        while (hi - lo > 1) {
-            const int64_t mid = (lo + hi) / 2;
-            if (coff[mid] <= i) lo = mid;
-            else hi = mid;
-        }
-        const int32_t l = crow[lo];
-        const int64_t src = rowoff[list[l]] + (lo - cfirst[l]) * kLongChunk + (i - coff[lo]);
-        const int32_t x = tk[src];
-        int32_t* keys = gk + toff[l];
-        const uint64_t mask = static_cast<uint64_t>(tsz[l]) - 1;
+__global__ void __launch_bounds__(256) long_table_insert_kernel(const int32_t* __restrict__ list,
+                                                                const int32_t* __restrict__ crow,
+                                                                const int64_t* __restrict__ cfirst,
+                                                                const int32_t* __restrict__ ccnt,
+                                                                const int64_t* __restrict__ rowoff,
+                                                                const int32_t* __restrict__ tk,
+                                                                const int32_t* __restrict__ tw,
+                                                                const int64_t* __restrict__ toff,
+                                                                const int64_t* __restrict__ tsz,
+                                                                int32_t* __restrict__ gk, int32_t* __restrict__ gv) {
+    const int64_t c = blockIdx.x;  // one merged chunk per workgroup
+    const int32_t l = crow[c];
+    const int64_t src = rowoff[list[l]] + (c - cfirst[l]) * kLongChunk;
+    int32_t* keys = gk + toff[l];
+    int32_t* vals = gv + toff[l];
+    const uint64_t mask = static_cast<uint64_t>(tsz[l]) - 1;
+    for (int32_t j = threadIdx.x; j < ccnt[c]; j += 256) {
+        const int32_t x = tk[src + j];
         uint64_t h = slot_hash(static_cast<uint32_t>(x)) & mask;
         while (true) {
             const int32_t prev = atomicCAS(&keys[h], -1, x);
             if (prev == -1 || prev == x) break;
             h = (h + 1) & mask;
         }
-        atomicAdd(&gv[toff[l] + h], tw[src]);
+        atomicAdd(&vals[h], tw[src + j]);
     }
 }
 
@@ -685,11 +683,14 @@ void merge_rows(int32_t nc, int64_t m, const int64_t* rowoff, const int32_t* row
         fill_i64(cfirst.get() + nl, nch, 1, s);
         DBuf<int32_t> crow(nch, s), ccnt(nch, s);
         DBuf<int64_t> coff(static_cast<size_t>(nch) + 1, s), mtot2(1, s), loff(static_cast<size_t>(nl) + 1, s);
-        long_chunks_kernel<<<nl, 256, 0, s>>>(nl, cfirst.get(), crow.get());
-        LAUNCHCHK();
-        long_dedup_kernel<<<static_cast<unsigned>(nch), 256, 0, s>>>(llist, crow.get(), cfirst.get(), rowoff,
-                                                                     rowcnt, tk, tw, ccnt.get());
-        LAUNCHCHK();
+        {
+            ProfScope ps_m("contract_long_merge", 0, s);
+            long_chunks_kernel<<<nl, 256, 0, s>>>(nl, cfirst.get(), crow.get());
+            LAUNCHCHK();
+            long_dedup_kernel<<<static_cast<unsigned>(nch), 256, 0, s>>>(llist, crow.get(), cfirst.get(), rowoff,
+                                                                         rowcnt, tk, tw, ccnt.get());
+            LAUNCHCHK();
+        }
         exclusive_scan_i32_to_i64(ccnt.get(), coff.get(), nch, mtot2.get(), s);
         int64_t ml = 0;
         HIPCHK(hipMemcpyAsync(&ml, mtot2.get(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -717,10 +718,13 @@ void merge_rows(int32_t nc, int64_t m, const int64_t* rowoff, const int32_t* row
             DBuf<int64_t> qoff(static_cast<size_t>(nq) + 1, s), qt(1, s);
             fill_i32(gk.get(), -1, ttot, s);
             fill_i32(gv.get(), 0, ttot, s);
-            long_table_insert_kernel<<<static_cast<unsigned>(std::min<int64_t>((ml + 255) / 256, 8192)), 256, 0, s>>>(
-                llist, crow.get(), cfirst.get(), nch, coff.get(), ml, rowoff, tk, tw, toff.get(), tsz.get(), gk.get(),
-                gv.get());
-            LAUNCHCHK();
+            {
+                ProfScope ps_i("contract_long_insert", 0, s);
+                long_table_insert_kernel<<<static_cast<unsigned>(nch), 256, 0, s>>>(
+                    llist, crow.get(), cfirst.get(), ccnt.get(), rowoff, tk, tw, toff.get(), tsz.get(), gk.get(),
+                    gv.get());
+                LAUNCHCHK();
+            }
             long_table_chunks_kernel<<<nl, 256, 0, s>>>(nl, tcfirst.get(), tl.get());
             LAUNCHCHK();
             long_table_count_kernel<<<static_cast<unsigned>(nq), 256, 0, s>>>(tl.get(), tcfirst.get(), toff.get(),
@@ -737,9 +741,9 @@ void merge_rows(int32_t nc, int64_t m, const int64_t* rowoff, const int32_t* row
         const int bn = std::max(1, bits_for(static_cast<uint64_t>(nc - 1)));
         DBuf<uint64_t> keys(ml, s), ktmp(ml, s);
         DBuf<uint32_t> vals(ml, s), vtmp(ml, s);
-        long_keys_kernel<<<static_cast<unsigned>(std::min<int64_t>((ml + 255) / 256, 8192)), 256, 0, s>>>(
-            llist, crow.get(), cfirst.get(), nch, coff.get(), ml, rowoff, tk, tw, bn, keys.get(),
-            vals.get());
+        long_keys_kernel<<<static_cast<unsigned>(nch), 256, 0, s>>>(llist, crow.get(), cfirst.get(), ccnt.get(),
+                                                                    coff.get(), rowoff, tk, tw, bn, keys.get(),
+                                                                    vals.get());
         LAUNCHCHK();
         {
             ProfScope ps2("contract_long_sort", 0, s);

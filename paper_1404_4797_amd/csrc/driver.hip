@@ -96,6 +96,30 @@ void check_k_eps(int32_t k, double eps) {
 
 namespace {
 
+// Runs f(i) for i in [0, count) on up to `threads` host threads.
+template <typename F>
+void parallel_for(int32_t count, int32_t threads, F f) {
+    threads = std::max(1, std::min(threads, count));
+    if (threads == 1) {
+        for (int32_t i = 0; i < count; ++i) f(i);
+        return;
+    }
+    std::atomic<int32_t> next{0};
+    std::vector<std::exception_ptr> errs(threads);
+    std::vector<std::thread> pool;
+    for (int32_t t = 0; t < threads; ++t)
+        pool.emplace_back([&, t] {
+            try {
+                for (int32_t i = next++; i < count; i = next++) f(i);
+            } catch (...) {
+                errs[t] = std::current_exception();
+            }
+        });
+    for (auto& th : pool) th.join();
+    for (auto& e : errs)
+        if (e) std::rethrow_exception(e);
+}
+
 // Smallest index >= from whose value is <= cap, over a segment tree of mins.
 struct MinTree {
     int64_t size = 1;
@@ -109,7 +133,11 @@ struct MinTree {
     void erase(int64_t i) {
         int64_t p = i + size;
         t[p] = INT64_MAX;
-        for (p >>= 1; p > 0; p >>= 1) t[p] = std::min(t[2 * p], t[2 * p + 1]);
+        for (p >>= 1; p > 0; p >>= 1) {
+            const int64_t m = std::min(t[2 * p], t[2 * p + 1]);
+            if (m == t[p]) break;  // ancestors keep their minima
+            t[p] = m;
+        }
     }
     int32_t first_le(int64_t from, int64_t cap) const { return static_cast<int32_t>(descend(1, 0, size, from, cap)); }
     int64_t min() const { return t[1]; }
@@ -159,27 +187,71 @@ struct BlockHeap {
 
 void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, const int32_t* vw, int32_t k,
                             int64_t T, int32_t* part, bool rows_sorted) {
-    std::fill(part, part + n, -1);
-    std::vector<uint64_t> taken((static_cast<size_t>(n) + 63) / 64, 0);  // 1 bit per node, cache resident
+    auto T0 = Clock::now();
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int32_t nthr = static_cast<int32_t>(std::min(16u, hw ? hw : 1u));
+    // id ranges of whole 64-node words, one task each
+    const size_t words = (static_cast<size_t>(n) + 63) / 64;
+    const int32_t ntask = n < (1 << 20) ? 1 : 4 * nthr;
+    auto task_words = [&](int32_t t, size_t& w0, size_t& w1) {
+        w0 = words * t / ntask;
+        w1 = words * (t + 1) / ntask;
+    };
+    std::vector<uint64_t> taken(words, 0);  // 1 bit per node, cache resident
     std::vector<int64_t> wb(static_cast<size_t>(k), 0);
-    // seed candidates: nodes of positive degree, in id order
-    std::vector<int32_t> seed_node;
-    std::vector<int64_t> seed_w;
-    std::vector<int32_t> seed_pos(static_cast<size_t>(n), -1);
-    for (int32_t v = 0; v < n; ++v)
-        if (xadj[v + 1] > xadj[v]) {
-            seed_pos[v] = static_cast<int32_t>(seed_node.size());
-            seed_node.push_back(v);
-            seed_w.push_back(vw ? vw[v] : 1);
+    // seed candidates: nodes of positive degree, in id order; a bitmap with
+    // per-word prefix counts gives a node's index among them in O(1)
+    std::vector<uint64_t> has_deg(words, 0);
+    std::vector<int32_t> rank_base(words + 1, 0);
+    std::vector<int32_t> task_cnt(static_cast<size_t>(ntask) + 1, 0);
+    parallel_for(ntask, nthr, [&](int32_t t) {
+        size_t w0, w1;
+        task_words(t, w0, w1);
+        int32_t cnt = 0;
+        for (size_t w = w0; w < w1; ++w) {
+            uint64_t bits = 0;
+            const int32_t v0 = static_cast<int32_t>(w * 64);
+            const int32_t v1 = std::min<int32_t>(n, v0 + 64);
+            for (int32_t v = v0; v < v1; ++v) {
+                part[v] = -1;
+                if (xadj[v + 1] > xadj[v]) bits |= 1ULL << (v - v0);
+            }
+            has_deg[w] = bits;
+            cnt += __builtin_popcountll(bits);
         }
+        task_cnt[t + 1] = cnt;
+    });
+    for (int32_t t = 0; t < ntask; ++t) task_cnt[t + 1] += task_cnt[t];
+    std::vector<int32_t> seed_node(static_cast<size_t>(task_cnt[ntask]));
+    std::vector<int64_t> seed_w(seed_node.size());
+    parallel_for(ntask, nthr, [&](int32_t t) {
+        size_t w0, w1;
+        task_words(t, w0, w1);
+        int32_t r = task_cnt[t];
+        for (size_t w = w0; w < w1; ++w) {
+            rank_base[w] = r;
+            for (uint64_t bits = has_deg[w]; bits; bits &= bits - 1) {
+                const int32_t v = static_cast<int32_t>(w * 64) + __builtin_ctzll(bits);
+                seed_node[r] = v;
+                seed_w[r] = vw ? vw[v] : 1;
+                ++r;
+            }
+        }
+    });
+    rank_base[words] = task_cnt[ntask];
+    auto seed_rank = [&](int32_t v) {
+        const size_t i = static_cast<size_t>(v) >> 6;
+        return rank_base[i] + __builtin_popcountll(has_deg[i] & ((1ULL << (v & 63)) - 1));
+    };
     MinTree seeds(seed_w);
+    const double t_seed = ms_since(T0);
     std::vector<int32_t> nb;
-    std::deque<int32_t> q;
+    std::vector<int32_t> fifo(static_cast<size_t>(seed_node.size()) + 1);  // every node is queued at most once
     auto take = [&](int32_t v, int32_t b) {
         part[v] = b;
         taken[static_cast<size_t>(v) >> 6] |= 1ULL << (v & 63);
         wb[b] += vw ? vw[v] : 1;
-        if (seed_pos[v] >= 0) seeds.erase(seed_pos[v]);
+        if ((has_deg[static_cast<size_t>(v) >> 6] >> (v & 63)) & 1ULL) seeds.erase(seed_rank(v));
     };
     for (int32_t b = 0; b + 1 < k; ++b) {
         int32_t from = 0;
@@ -188,16 +260,13 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
             if (si < 0) break;
             const int32_t sd = seed_node[si];
             take(sd, b);
-            q.push_back(sd);
-            while (!q.empty()) {
+            size_t head = 0, tail = 0;
+            fifo[tail++] = sd;
+            while (head < tail) {
                 // every node a search can reach has positive degree, so once
                 // the lightest such unassigned node does not fit, stop
-                if (seeds.min() > T - wb[b]) {
-                    q.clear();
-                    break;
-                }
-                const int32_t u = q.front();
-                q.pop_front();
+                if (seeds.min() > T - wb[b]) break;
+                const int32_t u = fifo[head++];
                 const int32_t* row = adj + xadj[u];
                 const int32_t* row_end = adj + xadj[u + 1];
                 if (!rows_sorted && !std::is_sorted(row, row_end)) {
@@ -211,30 +280,43 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
                     if ((taken[static_cast<size_t>(x) >> 6] >> (x & 63)) & 1ULL) continue;
                     if (wb[b] + (vw ? vw[x] : 1) > T) continue;
                     take(x, b);
-                    q.push_back(x);
+                    fifo[tail++] = x;
                 }
             }
             from = si + 1;
         }
     }
-    // Step 2: every remaining node, in id order, to the lightest block.
-    // Within a run of nodes of equal weight c > 0, the blocks whose weight
-    // lies within c of the lightest form a group that receives nodes
-    // cyclically in (weight, id) order, one per block per pass, until the next
-    // heavier block X is due; the number of nodes before that is the count of
-    // group values (w_g + j c, g) below (w_X, X).  X then joins and the group
-    // is recomputed.  The result equals dealing node by node.
-    std::vector<int32_t> rest;
-    rest.reserve(static_cast<size_t>(n));
-    for (int32_t v = 0; v < n; ++v)
-        if (part[v] < 0) rest.push_back(v);
+    const double t_bfs = ms_since(T0);
+    // unassigned nodes in id order (compacted per task, then concatenated)
+    std::fill(task_cnt.begin(), task_cnt.end(), 0);
+    parallel_for(ntask, nthr, [&](int32_t t) {
+        size_t w0, w1;
+        task_words(t, w0, w1);
+        int32_t cnt = 0;
+        const int32_t v1 = std::min<int32_t>(n, static_cast<int32_t>(w1 * 64));
+        for (int32_t v = static_cast<int32_t>(w0 * 64); v < v1; ++v) cnt += part[v] < 0;
+        task_cnt[t + 1] = cnt;
+    });
+    for (int32_t t = 0; t < ntask; ++t) task_cnt[t + 1] += task_cnt[t];
+    const size_t nrest = static_cast<size_t>(task_cnt[ntask]);
+    std::unique_ptr<int32_t[]> rest_buf(new int32_t[std::max<size_t>(nrest, 1)]);  // filled below
+    int32_t* const rest = rest_buf.get();
+    parallel_for(ntask, nthr, [&](int32_t t) {
+        size_t w0, w1;
+        task_words(t, w0, w1);
+        int32_t r = task_cnt[t];
+        const int32_t v1 = std::min<int32_t>(n, static_cast<int32_t>(w1 * 64));
+        for (int32_t v = static_cast<int32_t>(w0 * 64); v < v1; ++v)
+            if (part[v] < 0) rest[r++] = v;
+    });
+    const double t_rest = ms_since(T0);
     auto cw = [&](int32_t v) -> int64_t { return vw ? vw[v] : 1; };
     std::vector<int32_t> ord(static_cast<size_t>(k));
     size_t i = 0;
-    while (i < rest.size()) {
+    while (i < nrest) {
         const int64_t c = cw(rest[i]);
         size_t j = i;
-        while (j < rest.size() && cw(rest[j]) == c) ++j;
+        while (j < nrest && cw(rest[j]) == c) ++j;
         if (c == 0 || k > 4096) {  // node by node
             BlockHeap heap(wb);
             for (; i < j; ++i) {
@@ -265,16 +347,28 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
                 }
                 take = std::min<size_t>(take, static_cast<size_t>(before));
             }
-            int32_t pos = 0;
-            for (size_t t = 0; t < take; ++t) {
-                const int32_t b = ord[pos];
-                part[rest[i + t]] = b;
-                wb[b] += c;
-                if (++pos == gsz) pos = 0;
+            // node t of the run goes to ord[t mod gsz]
+            const int32_t* r0 = rest + i;
+            auto deal = [&](size_t t0, size_t t1) {
+                for (size_t t = t0; t < t1; ++t) part[r0[t]] = ord[t % gsz];
+            };
+            const size_t nt = take < (1u << 20) ? 1 : static_cast<size_t>(nthr);
+            if (nt <= 1) {
+                deal(0, take);
+            } else {
+                std::vector<std::thread> pool;
+                for (size_t q = 0; q < nt; ++q) pool.emplace_back(deal, take * q / nt, take * (q + 1) / nt);
+                for (auto& th : pool) th.join();
             }
+            for (int32_t g = 0; g < gsz; ++g)
+                wb[ord[g]] += c * static_cast<int64_t>(take / gsz + (static_cast<size_t>(g) < take % gsz ? 1 : 0));
             i += take;
         }
     }
+    static const bool trace = std::getenv("SCLAP_TRACE") != nullptr;
+    if (trace)
+        fprintf(stderr, "[sclap] host partition phases: seeds %.1f, growth %.1f, rest %.1f, total %.1f ms\n", t_seed,
+                t_bfs - t_seed, t_rest - t_bfs, ms_since(T0));
 }
 
 // ------------------------------------------------------------ multilevel
@@ -514,29 +608,6 @@ void upload_vec(DBuf<T>& d, const std::vector<T>& h, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(d.get(), h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
-// Runs f(i) for i in [0, count) on up to `threads` host threads.
-template <typename F>
-void parallel_for(int32_t count, int32_t threads, F f) {
-    threads = std::max(1, std::min(threads, count));
-    if (threads == 1) {
-        for (int32_t i = 0; i < count; ++i) f(i);
-        return;
-    }
-    std::atomic<int32_t> next{0};
-    std::vector<std::exception_ptr> errs(threads);
-    std::vector<std::thread> pool;
-    for (int32_t t = 0; t < threads; ++t)
-        pool.emplace_back([&, t] {
-            try {
-                for (int32_t i = next++; i < count; i = next++) f(i);
-            } catch (...) {
-                errs[t] = std::current_exception();
-            }
-        });
-    for (auto& th : pool) th.join();
-    for (auto& e : errs)
-        if (e) std::rethrow_exception(e);
-}
 
 }  // namespace
 

@@ -1813,11 +1813,12 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 A.count = static_cast<int32_t>(count);
                 A.ct = ct.get() + (off[c0 + bk] - off[c0]);
                 A.cg = cg.get() + (off[c0 + bk] - off[c0]);
-                static const char* const kNames[kHubBucket] = {"lp_eval_lane4", "lp_eval_lane16", "lp_eval_group16",
-                                                               "lp_eval_group32", "lp_eval_wave",
-                                                               "lp_eval_block1k", "lp_eval_block4k",
-                                                               "lp_eval_block8k"};
-                ProfScope ps(kNames[bk], eval_bytes(count, cslots[c0 + bk]), s);
+                static const char* const kNames[2][kHubBucket] = {
+                    {"lp_eval_lane4", "lp_eval_lane16", "lp_eval_group16", "lp_eval_group32", "lp_eval_wave",
+                     "lp_eval_block1k", "lp_eval_block4k", "lp_eval_block8k"},
+                    {"lp_refine_lane4", "lp_refine_lane16", "lp_refine_group16", "lp_refine_group32",
+                     "lp_refine_wave", "lp_refine_block1k", "lp_refine_block4k", "lp_refine_block8k"}};
+                ProfScope ps(kNames[A.refine][bk], eval_bytes(count, cslots[c0 + bk]), s);
                 const unsigned nb = static_cast<unsigned>(count);
                 if (bk == 0) {
                     eval_lane_kernel<kLaneSmall><<<grid_for(count, 256), 256, 0, s>>>(A);
@@ -1879,19 +1880,19 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 A.ct = ct.get() + (off[c0 + kHubBucket] - off[c0]);
                 A.cg = cg.get() + (off[c0 + kHubBucket] - off[c0]);
                 {
-                    ProfScope ps("lp_eval_hub_chunk", eval_bytes(Hn, cslots[c0 + kHubBucket]), s);
+                    ProfScope ps(A.refine ? "lp_refine_hub_chunk" : "lp_eval_hub_chunk", eval_bytes(Hn, cslots[c0 + kHubBucket]), s);
                     hub_chunk_kernel<<<P.nchunks, kHubThreads, 0, s>>>(A, H);
                     LAUNCHCHK();
                 }
                 {
-                    ProfScope ps("lp_eval_hub_part", 0, s);
+                    ProfScope ps(A.refine ? "lp_refine_hub_part" : "lp_eval_hub_part", 0, s);
                     hub_part_kernel<<<P.nparts, kPartThreads, 0, s>>>(A, H);
                     LAUNCHCHK();
                     hub_finish_kernel<<<Hn, 64, 0, s>>>(A, H);
                     LAUNCHCHK();
                 }
                 {
-                    ProfScope ps("lp_eval_hub_table", 0, s);
+                    ProfScope ps(A.refine ? "lp_refine_hub_table" : "lp_eval_hub_table", 0, s);
                     hub_clear_kernel<<<P.ntchunks, 256, 0, s>>>(H);
                     LAUNCHCHK();
                     hub_table_insert_kernel<<<P.nparts, 256, 0, s>>>(H);
@@ -1906,7 +1907,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
             // that can take all their candidates admit them; the others
             // select the admitted prefix on the device
             {
-                ProfScope ps("lp_admit", 0, s);
+                ProfScope ps(A.refine ? "lp_refine_admit" : "lp_admit", 0, s);
                 const unsigned gc = capped_grid(ccount);
                 if (small)
                     cand_accum_kernel<true><<<gc, 256, 0, s>>>(ct.get(), cnodes, ccount, g.vw, tsum.get(), tcnt.get(),
@@ -1920,7 +1921,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 LAUNCHCHK();
             }
             {
-                ProfScope ps("lp_admit_select", 0, s);
+                ProfScope ps(A.refine ? "lp_refine_admit_select" : "lp_admit_select", 0, s);
                 const unsigned gc = capped_grid(ccount);
                 if (small) {
                     claim_small_kernel<<<grid_for(nw, 256), 256, 0, s>>>(nw, w, tsum.get(), tcnt.get(), BB,
