@@ -870,6 +870,7 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
         mg.G = G;
         mg.gid = B.gid.get();
         mg.lgid = d_lgid.get();
+        mg.max_labels = *std::max_element(k, k + G);
         mg.nbase = d_nbase.get();
         mg.lbase = d_kb.get();
         mg.bound = d_bound.get();

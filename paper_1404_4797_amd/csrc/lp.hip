@@ -99,6 +99,7 @@ struct EvalArgs {
     // node emits nothing while it stays quiet and its block is not overloaded
     // (its connections are unchanged), so it need not be evaluated again.
     uint8_t* quiet;     // [n] flags, written by every evaluation (null: not tracked)
+    int32_t dense_k;    // > 0: every node's labels are lbase + [0, dense_k) (refinement blocks)
     int32_t use_quiet;  // 1: skip quiet nodes
     const int32_t* nodes;  // schedule entries of this launch
     int32_t count;
@@ -803,6 +804,192 @@ __global__ void __launch_bounds__(256) hub_scan_kernel(EvalArgs A, HubArgs H, in
 __global__ void __launch_bounds__(64) hub_big_finish_kernel(EvalArgs A, HubArgs H, const int32_t* tfirst_shifted) {
     if (!H.big[blockIdx.x]) return;
     hub_decide(A, H, blockIdx.x, tfirst_shifted);
+}
+
+// ------------------------------------------------ dense refinement buckets
+//
+// During refinement a node's labels are its graph's blocks, so connections
+// are summed in a dense array of dense_k entries (one LDS atomic add per
+// slot, no probing) instead of a hash table.
+
+constexpr int kDenseMax = 256;
+
+// Adds the slots [b, b+d) of a row to conn with LDS atomics (STRIDE lanes,
+// U batches of loads in flight).
+template <int STRIDE>
+__device__ __forceinline__ void dense_slots(const EvalArgs& A, const Ctx& kx, int64_t b, int32_t d, int32_t* conn,
+                                            int lane_in_set) {
+    constexpr int U = 4;
+    for (int32_t j0 = lane_in_set; j0 < d; j0 += STRIDE * U) {
+        int32_t x[U], wt[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t j = j0 + u * STRIDE;
+            x[u] = j < d ? A.adj[b + j] : -1;
+            wt[u] = j < d ? (A.ew ? A.ew[b + j] : 1) : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = x[u] >= 0 ? nbr_label(A, x[u]) - kx.lbase : -1;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (x[u] >= 0) atomicAdd(&conn[x[u]], wt[u]);
+    }
+}
+
+// Best eligible block of a node from its dense connections (lane j of the
+// set scans entries j, j + NT, ...).
+__device__ __forceinline__ void dense_best(const EvalArgs& A, const Ctx& kx, const int32_t* conn, int32_t a,
+                                           int32_t c, int32_t own, bool over, int first, int step, Best& best,
+                                           bool& blocked) {
+    const int32_t la = a - kx.lbase;
+    for (int32_t j = first; j < A.dense_k; j += step) {
+        const int32_t cn = conn[j];
+        if (cn == 0 || j == la) continue;  // not a neighbouring block, or the own one
+        blocked |= cn > own;
+        if (!over && cn <= own) continue;
+        if (best.x >= 0 && cn < best.conn) continue;
+        const int32_t x = j + kx.lbase;
+        if (!eligible(A, x, c, kx)) continue;
+        best_consider(best, x, cn, kx);
+    }
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) eval_dense_group_kernel(EvalArgs A) {
+    constexpr int NG = 256 / G;
+    __shared__ int32_t cs[NG][kDenseMax];
+    const int grp = threadIdx.x / G;
+    const int gl = threadIdx.x % G;
+    const int node_i = blockIdx.x * NG + grp;
+    if (node_i >= A.count) return;  // uniform per group
+    int32_t* conn = cs[grp];
+    const int32_t v = A.nodes[node_i];
+    const Ctx kx = ctx_of(A, v);
+    if (skip_quiet(A, v, kx)) {
+        if (gl == 0) store_result(A, node_i, -1, 0, 0, false);
+        return;
+    }
+    const int64_t b = A.xadj[v];
+    const int32_t d = static_cast<int32_t>(A.xadj[v + 1] - b);
+    const int32_t a = A.label[v];
+    const int32_t c = A.vw ? A.vw[v] : 1;
+    for (int32_t j = gl; j < A.dense_k; j += G) conn[j] = 0;
+    wave_sync();
+    dense_slots<G>(A, kx, b, d, conn, gl);
+    wave_sync();
+    const int32_t own = conn[a - kx.lbase];
+    const bool over = A.w[a] > kx.bound;
+    Best best;
+    best_init(best);
+    bool blocked = false;
+    dense_best(A, kx, conn, a, c, own, over, gl, G, best, blocked);
+    int32_t bx, bconn;
+    group_argmax<G>(best, kx, bx, bconn);
+    const bool any_blocked = group_any<G>(blocked);
+    if (gl == 0) {
+        store_result(A, node_i, bx, bconn, own, over);
+        if (A.quiet) A.quiet[v] = (!over && !any_blocked) ? 1 : 0;
+    }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT) eval_dense_block_kernel(EvalArgs A) {
+    __shared__ int32_t conn[kDenseMax];
+    __shared__ int32_t s_conn[NT / 64];
+    __shared__ int32_t s_x[NT / 64];
+    __shared__ uint64_t s_tie[NT / 64];
+    const int tid = threadIdx.x;
+    const int wid = tid >> 6;
+    const int32_t v = A.nodes[blockIdx.x];
+    const Ctx kx = ctx_of(A, v);
+    if (skip_quiet(A, v, kx)) {  // uniform over the workgroup
+        if (tid == 0) store_result(A, blockIdx.x, -1, 0, 0, false);
+        return;
+    }
+    const int64_t b = A.xadj[v];
+    const int32_t d = static_cast<int32_t>(A.xadj[v + 1] - b);
+    const int32_t a = A.label[v];
+    const int32_t c = A.vw ? A.vw[v] : 1;
+    for (int32_t j = tid; j < A.dense_k; j += NT) conn[j] = 0;
+    __syncthreads();
+    dense_slots<NT>(A, kx, b, d, conn, tid);
+    __syncthreads();
+    const int32_t own = conn[a - kx.lbase];
+    const bool over = A.w[a] > kx.bound;
+    Best best;
+    best_init(best);
+    bool blocked = false;
+    dense_best(A, kx, conn, a, c, own, over, tid, NT, best, blocked);
+    int32_t bx, bconn;
+    wave_argmax(best, kx, bx, bconn);
+    if (lane_id() == 0) {
+        s_conn[wid] = bconn;
+        s_x[wid] = bx;
+        s_tie[wid] = bx >= 0 ? tie_of(kx, bx) : ~0ULL;
+    }
+    const int any_blocked = __syncthreads_or(blocked);
+    if (tid == 0) {
+        int32_t fc = -1, fx = -1;
+        uint64_t ft = ~0ULL;
+        for (int w = 0; w < NT / 64; ++w) combine_into(fc, ft, fx, s_conn[w], s_tie[w], s_x[w]);
+        store_result(A, blockIdx.x, fx, fc, own, over);
+        if (A.quiet) A.quiet[v] = (!over && !any_blocked) ? 1 : 0;
+    }
+}
+
+// Hubs: every chunk of a hub's row adds its dense sums to the hub's row of
+// hub_sum (dense_k entries per hub) ...
+__global__ void __launch_bounds__(kHubThreads) hub_dense_chunk_kernel(EvalArgs A, HubArgs H,
+                                                                      int32_t* __restrict__ hub_sum) {
+    __shared__ int32_t conn[kDenseMax];
+    const int tid = threadIdx.x;
+    const int32_t h = H.chunk_hub[blockIdx.x];
+    const int32_t v = H.hub_nodes[h];
+    const Ctx kx = ctx_of(A, v);
+    const int64_t begin = H.chunk_begin[blockIdx.x];
+    const int64_t row_end = A.xadj[v + 1];
+    const int64_t end = begin + kHubChunk < row_end ? begin + kHubChunk : row_end;
+    for (int32_t j = tid; j < A.dense_k; j += kHubThreads) conn[j] = 0;
+    __syncthreads();
+    dense_slots<kHubThreads>(A, kx, begin, static_cast<int32_t>(end - begin), conn, tid);
+    __syncthreads();
+    for (int32_t j = tid; j < A.dense_k; j += kHubThreads)
+        if (conn[j]) atomicAdd(&hub_sum[static_cast<int64_t>(h) * A.dense_k + j], conn[j]);
+}
+
+// ... then one workgroup per hub decides and clears the hub's row.
+__global__ void __launch_bounds__(256) hub_dense_finish_kernel(EvalArgs A, HubArgs H, int32_t* __restrict__ hub_sum) {
+    __shared__ int32_t s_conn[4];
+    __shared__ int32_t s_x[4];
+    __shared__ uint64_t s_tie[4];
+    const int tid = threadIdx.x;
+    const int32_t h = blockIdx.x;
+    const int32_t v = H.hub_nodes[h];
+    const Ctx kx = ctx_of(A, v);
+    const int32_t a = A.label[v];
+    const int32_t c = A.vw ? A.vw[v] : 1;
+    int32_t* conn = hub_sum + static_cast<int64_t>(h) * A.dense_k;
+    const int32_t own = conn[a - kx.lbase];
+    const bool over = A.w[a] > kx.bound;
+    Best best;
+    best_init(best);
+    bool blocked = false;
+    dense_best(A, kx, conn, a, c, own, over, tid, 256, best, blocked);
+    int32_t bx, bconn;
+    wave_argmax(best, kx, bx, bconn);
+    if (lane_id() == 0) {
+        s_conn[tid >> 6] = bconn;
+        s_x[tid >> 6] = bx;
+        s_tie[tid >> 6] = bx >= 0 ? tie_of(kx, bx) : ~0ULL;
+    }
+    __syncthreads();
+    for (int32_t j = tid; j < A.dense_k; j += 256) conn[j] = 0;
+    if (tid == 0) {
+        int32_t fc = -1, fx = -1;
+        uint64_t ft = ~0ULL;
+        for (int w = 0; w < 4; ++w) combine_into(fc, ft, fx, s_conn[w], s_tie[w], s_x[w]);
+        store_result(A, h, fx, fc, own, over);
+    }
 }
 
 // ------------------------------------------------------- block utilities
@@ -1753,6 +1940,17 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     A.g_bound = mg ? mg->bound : nullptr;
     A.g_lbase = mg ? mg->lbase : nullptr;
     const Bounds BB{bound, mg ? mg->lgid : nullptr, mg ? mg->bound : nullptr};
+    // refinement labels are blocks: dense connection arrays when few enough
+    const int32_t dense_k = phase == kRefine ? (mg ? mg->max_labels : nw) : 0;
+    A.dense_k = dense_k > 0 && dense_k <= kDenseMax ? dense_k : 0;
+    const bool dense = A.dense_k > 0;
+    DBuf<int32_t> hub_sum;
+    if (dense) {
+        int64_t max_hubs = 1;
+        for (const HubPlan& P : plans) max_hubs = std::max<int64_t>(max_hubs, P.count);
+        hub_sum.alloc(max_hubs * A.dense_k, s);
+        fill_i32(hub_sum.get(), 0, max_hubs * A.dense_k, s);
+    }
     DBuf<uint8_t> lab8;
     DBuf<uint16_t> lab16;
     if (nw <= 256) {
@@ -1824,6 +2022,13 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                     eval_lane_kernel<kLaneSmall><<<grid_for(count, 256), 256, 0, s>>>(A);
                 } else if (bk == 1) {
                     eval_lane_kernel<kLaneMax><<<grid_for(count, 256), 256, 0, s>>>(A);
+                } else if (dense) {  // refinement blocks: dense connection arrays
+                    if (bk == 2) eval_dense_group_kernel<16><<<grid_for(count, 16), 256, 0, s>>>(A);
+                    else if (bk == 3) eval_dense_group_kernel<32><<<grid_for(count, 8), 256, 0, s>>>(A);
+                    else if (bk == 4) eval_dense_group_kernel<64><<<grid_for(count, 4), 256, 0, s>>>(A);
+                    else if (bk == 5) eval_dense_block_kernel<256><<<nb, 256, 0, s>>>(A);
+                    else if (bk == 6) eval_dense_block_kernel<512><<<nb, 512, 0, s>>>(A);
+                    else eval_dense_block_kernel<1024><<<nb, 1024, 0, s>>>(A);
                 } else if (bk == 2) {
                     eval_group_kernel<16, 2 * kG16Max><<<grid_for(count, 16), 256, 0, s>>>(A);
                 } else if (bk == 3) {
@@ -1879,6 +2084,13 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 A.count = Hn;
                 A.ct = ct.get() + (off[c0 + kHubBucket] - off[c0]);
                 A.cg = cg.get() + (off[c0 + kHubBucket] - off[c0]);
+                if (dense) {
+                    ProfScope ps("lp_refine_hub_dense", eval_bytes(Hn, cslots[c0 + kHubBucket]), s);
+                    hub_dense_chunk_kernel<<<P.nchunks, kHubThreads, 0, s>>>(A, H, hub_sum.get());
+                    LAUNCHCHK();
+                    hub_dense_finish_kernel<<<Hn, 256, 0, s>>>(A, H, hub_sum.get());
+                    LAUNCHCHK();
+                } else {
                 {
                     ProfScope ps(A.refine ? "lp_refine_hub_chunk" : "lp_eval_hub_chunk", eval_bytes(Hn, cslots[c0 + kHubBucket]), s);
                     hub_chunk_kernel<<<P.nchunks, kHubThreads, 0, s>>>(A, H);
@@ -1901,6 +2113,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                     LAUNCHCHK();
                     hub_big_finish_kernel<<<Hn, 64, 0, s>>>(A, H, tfirst_shifted);
                     LAUNCHCHK();
+                }
                 }
             }
             // per-target candidate weight and count, then admission: targets

@@ -39,6 +39,7 @@ struct MultiGraph {
     const int64_t* bound = nullptr;   // [G] bound of each graph's labels
     const uint64_t* seed = nullptr;   // [G]
     const uint8_t* active = nullptr;  // [G] nodes of inactive graphs never move
+    int32_t max_labels = 0;           // refinement: the most blocks of any graph (0: unknown)
 };
 
 struct LPResult {

@@ -129,7 +129,7 @@ REFINE_KNOBS = [dict(block_max_degree=40), dict(block_max_degree=30, hub_part_li
 
 
 @pytest.mark.parametrize("gname", list(GRAPHS))
-@pytest.mark.parametrize("k", [2, 5, 64])
+@pytest.mark.parametrize("k", [2, 5, 64, 300])
 @pytest.mark.parametrize("knobs", range(len(REFINE_KNOBS)))
 def test_refine_parity(sc, gname, k, knobs):
     g = GRAPHS[gname]()
