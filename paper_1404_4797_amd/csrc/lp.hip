@@ -1700,6 +1700,50 @@ struct HubPlan {
     DBuf<uint32_t> u32;  // tmask
 };
 
+// Side streams for the independent evaluation launches of a sub-round
+// (default priority, created once per thread).  fork() makes them wait for
+// the work already on the caller's stream, join() makes the caller's stream
+// wait for them.
+class EvalStreams {
+  public:
+    static constexpr int kN = 3;
+    EvalStreams() {
+        for (int i = 0; i < kN; ++i) {
+            HIPCHK(hipStreamCreateWithFlags(&st_[i], hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&done_[i], hipEventDisableTiming));
+        }
+        HIPCHK(hipEventCreateWithFlags(&start_, hipEventDisableTiming));
+    }
+    EvalStreams(const EvalStreams&) = delete;
+    EvalStreams& operator=(const EvalStreams&) = delete;
+    void fork(hipStream_t s) {
+        HIPCHK(hipEventRecord(start_, s));
+        for (int i = 0; i < kN; ++i) HIPCHK(hipStreamWaitEvent(st_[i], start_, 0));
+    }
+    void join(hipStream_t s) {
+        for (int i = 0; i < kN; ++i) {
+            HIPCHK(hipEventRecord(done_[i], st_[i]));
+            HIPCHK(hipStreamWaitEvent(s, done_[i], 0));
+        }
+    }
+    hipStream_t hub() const { return st_[0]; }
+    // heavy buckets (large rows) apart from each other and from the hubs
+    hipStream_t bucket(int bk) const {
+        static const int kMap[kNB - 1] = {1, 1, 2, 2, 2, 1, 2, 1};
+        return st_[kMap[bk]];
+    }
+
+  private:
+    hipStream_t st_[kN];
+    hipEvent_t done_[kN];
+    hipEvent_t start_;
+};
+
+EvalStreams& eval_streams() {
+    thread_local EvalStreams e;
+    return e;
+}
+
 thread_local Counters* t_host_ctr = nullptr;
 
 Counters* host_counters() {
@@ -1987,6 +2031,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     reset_counters_kernel<<<1, 1, 0, s>>>(ctr.get(), 1);
     LAUNCHCHK();
     const int bits_v = bits_for(static_cast<uint64_t>(n - 1));
+    EvalStreams& evs = eval_streams();
 
     for (int32_t r = 0; r < rounds; ++r) {
         if (mg) {
@@ -2003,8 +2048,15 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
             const int64_t ccount = off[c0 + kNB] - off[c0];
             if (ccount == 0) continue;
             const int32_t* cnodes = nodes + off[c0];
-            // evaluation: one result per schedule entry of this colour
+            // evaluation: one result per schedule entry of this colour; the
+            // buckets are independent and run side by side on the evaluation
+            // streams (hubs on the first), joined before admission
+            unsigned long long colour_slots = 0;
+            for (int32_t bk = 0; bk < kNB; ++bk) colour_slots += cslots[c0 + bk];
+            const bool side = colour_slots >= (1ULL << 22);  // small colours stay on one stream
+            if (side) evs.fork(s);
             for (int32_t bk = 0; bk < kHubBucket; ++bk) {
+                const hipStream_t bs = side ? evs.bucket(bk) : s;
                 const int64_t count = off[c0 + bk + 1] - off[c0 + bk];
                 if (count == 0) continue;
                 A.nodes = nodes + off[c0 + bk];
@@ -2016,35 +2068,36 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                      "lp_eval_block1k", "lp_eval_block4k", "lp_eval_block8k"},
                     {"lp_refine_lane4", "lp_refine_lane16", "lp_refine_group16", "lp_refine_group32",
                      "lp_refine_wave", "lp_refine_block1k", "lp_refine_block4k", "lp_refine_block8k"}};
-                ProfScope ps(kNames[A.refine][bk], eval_bytes(count, cslots[c0 + bk]), s);
+                ProfScope ps(kNames[A.refine][bk], eval_bytes(count, cslots[c0 + bk]), bs);
                 const unsigned nb = static_cast<unsigned>(count);
                 if (bk == 0) {
-                    eval_lane_kernel<kLaneSmall><<<grid_for(count, 256), 256, 0, s>>>(A);
+                    eval_lane_kernel<kLaneSmall><<<grid_for(count, 256), 256, 0, bs>>>(A);
                 } else if (bk == 1) {
-                    eval_lane_kernel<kLaneMax><<<grid_for(count, 256), 256, 0, s>>>(A);
+                    eval_lane_kernel<kLaneMax><<<grid_for(count, 256), 256, 0, bs>>>(A);
                 } else if (dense) {  // refinement blocks: dense connection arrays
-                    if (bk == 2) eval_dense_group_kernel<16><<<grid_for(count, 16), 256, 0, s>>>(A);
-                    else if (bk == 3) eval_dense_group_kernel<32><<<grid_for(count, 8), 256, 0, s>>>(A);
-                    else if (bk == 4) eval_dense_group_kernel<64><<<grid_for(count, 4), 256, 0, s>>>(A);
-                    else if (bk == 5) eval_dense_block_kernel<256><<<nb, 256, 0, s>>>(A);
-                    else if (bk == 6) eval_dense_block_kernel<512><<<nb, 512, 0, s>>>(A);
-                    else eval_dense_block_kernel<1024><<<nb, 1024, 0, s>>>(A);
+                    if (bk == 2) eval_dense_group_kernel<16><<<grid_for(count, 16), 256, 0, bs>>>(A);
+                    else if (bk == 3) eval_dense_group_kernel<32><<<grid_for(count, 8), 256, 0, bs>>>(A);
+                    else if (bk == 4) eval_dense_group_kernel<64><<<grid_for(count, 4), 256, 0, bs>>>(A);
+                    else if (bk == 5) eval_dense_block_kernel<256><<<nb, 256, 0, bs>>>(A);
+                    else if (bk == 6) eval_dense_block_kernel<512><<<nb, 512, 0, bs>>>(A);
+                    else eval_dense_block_kernel<1024><<<nb, 1024, 0, bs>>>(A);
                 } else if (bk == 2) {
-                    eval_group_kernel<16, 2 * kG16Max><<<grid_for(count, 16), 256, 0, s>>>(A);
+                    eval_group_kernel<16, 2 * kG16Max><<<grid_for(count, 16), 256, 0, bs>>>(A);
                 } else if (bk == 3) {
-                    eval_group_kernel<32, 2 * kG32Max><<<grid_for(count, 8), 256, 0, s>>>(A);
+                    eval_group_kernel<32, 2 * kG32Max><<<grid_for(count, 8), 256, 0, bs>>>(A);
                 } else if (bk == 4) {
-                    eval_group_kernel<64, kWaveTable><<<grid_for(count, 4), 256, 0, s>>>(A);
+                    eval_group_kernel<64, kWaveTable><<<grid_for(count, 4), 256, 0, bs>>>(A);
                 } else if (bk == 5) {
-                    eval_block_kernel<256, 2 * kBlock1Max><<<nb, 256, 0, s>>>(A);
+                    eval_block_kernel<256, 2 * kBlock1Max><<<nb, 256, 0, bs>>>(A);
                 } else if (bk == 6) {
-                    eval_block_kernel<512, 2 * kBlock2Max><<<nb, 512, 0, s>>>(A);
+                    eval_block_kernel<512, 2 * kBlock2Max><<<nb, 512, 0, bs>>>(A);
                 } else {
-                    eval_block_kernel<1024, kBlockTable><<<nb, 1024, 0, s>>>(A);
+                    eval_block_kernel<1024, kBlockTable><<<nb, 1024, 0, bs>>>(A);
                 }
                 LAUNCHCHK();
             }
             const HubPlan& P = plans[sc];
+            const hipStream_t hs = side ? evs.hub() : s;
             if (P.count > 0) {
                 const int32_t Hn = P.count;
                 HubArgs H;
@@ -2079,43 +2132,45 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 H.w_tie = w_tie.get();
                 H.w_x = w_x.get();
                 H.part_limit = std::max(1, std::min(tune.hub_part_limit, kPartTable / 2));
-                fill_i32(H.rcount, 0, static_cast<int64_t>(P.nparts) + 3 * Hn, s);
+                fill_i32(H.rcount, 0, static_cast<int64_t>(P.nparts) + 3 * Hn, hs);
                 A.nodes = H.hub_nodes;
                 A.count = Hn;
                 A.ct = ct.get() + (off[c0 + kHubBucket] - off[c0]);
                 A.cg = cg.get() + (off[c0 + kHubBucket] - off[c0]);
                 if (dense) {
-                    ProfScope ps("lp_refine_hub_dense", eval_bytes(Hn, cslots[c0 + kHubBucket]), s);
-                    hub_dense_chunk_kernel<<<P.nchunks, kHubThreads, 0, s>>>(A, H, hub_sum.get());
+                    ProfScope ps("lp_refine_hub_dense", eval_bytes(Hn, cslots[c0 + kHubBucket]), hs);
+                    hub_dense_chunk_kernel<<<P.nchunks, kHubThreads, 0, hs>>>(A, H, hub_sum.get());
                     LAUNCHCHK();
-                    hub_dense_finish_kernel<<<Hn, 256, 0, s>>>(A, H, hub_sum.get());
+                    hub_dense_finish_kernel<<<Hn, 256, 0, hs>>>(A, H, hub_sum.get());
                     LAUNCHCHK();
                 } else {
                 {
-                    ProfScope ps(A.refine ? "lp_refine_hub_chunk" : "lp_eval_hub_chunk", eval_bytes(Hn, cslots[c0 + kHubBucket]), s);
-                    hub_chunk_kernel<<<P.nchunks, kHubThreads, 0, s>>>(A, H);
+                    ProfScope ps(A.refine ? "lp_refine_hub_chunk" : "lp_eval_hub_chunk", eval_bytes(Hn, cslots[c0 + kHubBucket]), hs);
+                    hub_chunk_kernel<<<P.nchunks, kHubThreads, 0, hs>>>(A, H);
                     LAUNCHCHK();
                 }
                 {
-                    ProfScope ps(A.refine ? "lp_refine_hub_part" : "lp_eval_hub_part", 0, s);
-                    hub_part_kernel<<<P.nparts, kPartThreads, 0, s>>>(A, H);
+                    ProfScope ps(A.refine ? "lp_refine_hub_part" : "lp_eval_hub_part", 0, hs);
+                    hub_part_kernel<<<P.nparts, kPartThreads, 0, hs>>>(A, H);
                     LAUNCHCHK();
-                    hub_finish_kernel<<<Hn, 64, 0, s>>>(A, H);
+                    hub_finish_kernel<<<Hn, 64, 0, hs>>>(A, H);
                     LAUNCHCHK();
                 }
                 {
-                    ProfScope ps(A.refine ? "lp_refine_hub_table" : "lp_eval_hub_table", 0, s);
-                    hub_clear_kernel<<<P.ntchunks, 256, 0, s>>>(H);
+                    ProfScope ps(A.refine ? "lp_refine_hub_table" : "lp_eval_hub_table", 0, hs);
+                    hub_clear_kernel<<<P.ntchunks, 256, 0, hs>>>(H);
                     LAUNCHCHK();
-                    hub_table_insert_kernel<<<P.nparts, 256, 0, s>>>(H);
+                    hub_table_insert_kernel<<<P.nparts, 256, 0, hs>>>(H);
                     LAUNCHCHK();
-                    hub_scan_kernel<<<P.ntchunks, 256, 0, s>>>(A, H, P.nparts);
+                    hub_scan_kernel<<<P.ntchunks, 256, 0, hs>>>(A, H, P.nparts);
                     LAUNCHCHK();
-                    hub_big_finish_kernel<<<Hn, 64, 0, s>>>(A, H, tfirst_shifted);
+                    hub_big_finish_kernel<<<Hn, 64, 0, hs>>>(A, H, tfirst_shifted);
                     LAUNCHCHK();
                 }
                 }
             }
+            if (side) evs.join(s);
+
             // per-target candidate weight and count, then admission: targets
             // that can take all their candidates admit them; the others
             // select the admitted prefix on the device
