@@ -113,10 +113,24 @@ def batch_comparison(ngraphs, seed, log_lo, log_hi):
     t0 = time.perf_counter()
     r = sc.partition_batch_dev(du, nb, ks, eps, seeds, part=part, stream=stream)
     torch.cuda.synchronize()
+    t_default = time.perf_counter() - t0
+    ref_part = part.clone()
+    # degree-bucket thresholds tuned on one clustering round of the union
+    t0 = time.perf_counter()
+    o = sc.autotune_dev(du, int(np.median(ks)), stream=stream)
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t0
+    tuned = [o.lane_max_degree, o.wave_max_degree, o.block_max_degree]
+    r = sc.partition_batch_dev(du, nb, ks, eps, seeds, part=part, stream=stream, opts=o)  # warmup
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = sc.partition_batch_dev(du, nb, ks, eps, seeds, part=part, stream=stream, opts=o)
+    torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
-    log("batched: %.1f ms for %d graphs" % (t_batch * 1e3, ngraphs))
+    same = bool(torch.equal(part, ref_part))
+    log("batched: %.1f ms default thresholds, %.1f ms tuned %s (tuning %.1f ms), identical=%s"
+        % (t_default * 1e3, t_batch * 1e3, tuned, t_tune * 1e3, same))
     bpart = part.cpu().numpy()
-    same = True
     t_plain = 0.0
     visits_plain = 0
     for i, dg in enumerate(dgs):
@@ -132,7 +146,8 @@ def batch_comparison(ngraphs, seed, log_lo, log_hi):
             same = False
     log("plain: %.1f ms for %d graphs, identical=%s" % (t_plain * 1e3, ngraphs, same))
     return {"graphs": ngraphs, "n_log2_range": [log_lo, log_hi], "n": u["n"], "S": int(u["xadj"][-1]),
-            "batched_ms": round(t_batch * 1e3, 3), "plain_ms": round(t_plain * 1e3, 3),
+            "batched_ms": round(t_batch * 1e3, 3), "batched_default_thresholds_ms": round(t_default * 1e3, 3),
+            "tuned_thresholds": tuned, "tuning_ms": round(t_tune * 1e3, 3), "plain_ms": round(t_plain * 1e3, 3),
             "batched_graphs_per_s": ngraphs / t_batch, "plain_graphs_per_s": ngraphs / t_plain,
             "speedup": t_plain / t_batch, "identical_parts_and_cuts": same,
             "batched_edge_visits": r["stats"]["visits"], "plain_edge_visits": visits_plain,

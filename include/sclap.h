@@ -288,6 +288,17 @@ int sclap_server_poll(sclap_server* sv, uint64_t req, int32_t timeout_ms, int32_
 void sclap_server_destroy(sclap_server* sv);
 
 /*
+ * Tuning (result-free): times one clustering round (level 0, seed 1, cluster
+ * bound from k as in sclap_partition) of the device graph g under each of a
+ * few candidate sets of degree-bucket thresholds, which fix the LDS table
+ * size each row gets, and writes the fastest set into opt's tuning fields
+ * (lane_max_degree, wave_max_degree, block_max_degree).  g may be a batch
+ * union; k is then a representative block count.  Semantic fields of opt are
+ * read, not changed; results of later calls do not depend on the choice.
+ */
+int sclap_autotune_dev(const sclap_graph* g, int32_t k, sclap_options* opt, void* stream);
+
+/*
  * Instrumentation.  sclap_profile_begin() starts timing every kernel launch
  * that later calls on this thread issue, with HIP events recorded on the
  * launching stream around each launch; sclap_profile_end() stops, writes up to

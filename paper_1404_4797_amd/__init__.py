@@ -36,6 +36,7 @@ EXPORTS = [
     "sclap_partition", "sclap_partition_dev",
     "sclap_partition_batch", "sclap_partition_batch_dev",
     "sclap_server_create", "sclap_server_submit", "sclap_server_poll", "sclap_server_destroy",
+    "sclap_autotune_dev",
     "sclap_profile_begin", "sclap_profile_end",
 ]
 
@@ -144,6 +145,7 @@ def load():
         "sclap_server_submit": (ctypes.c_int, [vp, G, i32, dbl, u64, vp]),
         "sclap_server_poll": (ctypes.c_int, [vp, u64, i32, vp, vp, vp, vp, ctypes.POINTER(RequestInfo)]),
         "sclap_server_destroy": (None, [vp]),
+        "sclap_autotune_dev": (ctypes.c_int, [G, i32, O, vp]),
         "sclap_partition_batch_dev": (ctypes.c_int, [G, i32, vp, vp, vp, vp, O, vp, vp, vp, BST, vp]),
         "sclap_profile_begin": (ctypes.c_int, []),
         "sclap_profile_end": (ctypes.c_int, [ctypes.POINTER(KernelStat), i32, vp]),
@@ -537,6 +539,15 @@ def partition_batch_dev(d, node_base, k, eps, seed, part=None, stream=None, opts
                                                      ctypes.byref(st), _stream(stream)), allow_warn=True)
     return {"part": part, "cut": cut, "block_weights": bw, "levels": levels, "status": status,
             "stats": st.to_dict()}
+
+
+def autotune_dev(d, k, stream=None, opts=None, **kw):
+    """Returns Options whose degree-bucket thresholds ran one clustering round
+    of the device graph ``d`` fastest (results never depend on them)."""
+    dg = _DevGraph(d)
+    o = opts if isinstance(opts, Options) else default_options(**kw)
+    _check(load().sclap_autotune_dev(dg.ref, k, ctypes.byref(o), _stream(stream)))
+    return o
 
 
 # ------------------------------------------------------------------ serving

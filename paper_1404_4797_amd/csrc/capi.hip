@@ -528,6 +528,20 @@ void sclap_server_destroy(sclap_server* sv) {
     });
 }
 
+int sclap_autotune_dev(const sclap_graph* g, int32_t k, sclap_options* opt, void* stream) {
+    return guarded([&] {
+        if (!opt) fail(SCLAP_ERR_INVALID, "opt is NULL");
+        hipStream_t s = as_stream(stream);
+        const Opts o = resolve(opt);
+        const DevGraph d = dev_view(g, s);
+        const LPTuning t = autotune(d, k, o, s);
+        opt->lane_max_degree = t.lane_max;
+        opt->wave_max_degree = t.wave_max;
+        opt->block_max_degree = t.block_max;
+        return SCLAP_OK;
+    });
+}
+
 int sclap_profile_begin(void) {
     return guarded([&] {
         profiler().reset();

@@ -581,6 +581,48 @@ int partition_impl(const DevGraph& g0_in, int32_t k, double eps, uint64_t seed, 
     return SCLAP_OK;
 }
 
+// ------------------------------------------------------------- tuning
+
+LPTuning autotune(const DevGraph& g_in, int32_t k, const Opts& o, hipStream_t s) {
+    check_k_eps(k, 0.0);
+    DevGraph g = g_in;
+    int64_t cV = 0, cmax = 0;
+    check_graph(g, false, &cV, &cmax, s);
+    drop_unit_weights(g, s);
+    const int64_t U = std::max(cmax, cV / (static_cast<int64_t>(o.divisor) * k));
+    // (lane, wave, block) upper degrees; the first is the library default
+    static const int32_t kCand[][3] = {{16, 256, 8192}, {16, 128, 8192}, {8, 256, 8192},
+                                       {16, 256, 4096}, {16, 64, 2048},  {4, 128, 8192}};
+    LPTuning best = o.tune;
+    double best_ms = 1e300;
+    if (g.n == 0) return best;
+    DBuf<int32_t> labels(g.n, s), w(g.n, s);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (const auto& c : kCand) {
+        LPTuning t = o.tune;
+        t.lane_max = c[0];
+        t.wave_max = c[1];
+        t.block_max = c[2];
+        iota_u32(reinterpret_cast<uint32_t*>(labels.get()), g.n, s);
+        label_weights(g, labels.get(), w.get(), g.n, s);
+        HIPCHK(hipEventRecord(e0, s));
+        run_lp(g, kCluster, 0, 1, o.nsub, 1, U, labels.get(), w.get(), g.n, nullptr, t, s);
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return best;
+}
+
 // ------------------------------------------------------------- batches
 //
 // Many graphs partitioned together: the graphs of a batch are one CSR with a

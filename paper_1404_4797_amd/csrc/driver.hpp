@@ -52,6 +52,9 @@ int partition_batch_impl(const DevGraph& g0, int32_t G, const int32_t* node_base
 using Clock = std::chrono::steady_clock;
 double ms_since(Clock::time_point t);
 
+// Fastest candidate degree-bucket thresholds for one clustering round of g.
+LPTuning autotune(const DevGraph& g, int32_t k, const Opts& o, hipStream_t s);
+
 // Serving loop (server.hip); errors throw Error.
 sclap_server* server_create(int32_t device, int64_t hbm_budget, int32_t slots, int32_t max_batch,
                             const sclap_options* opt);

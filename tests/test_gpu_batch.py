@@ -125,3 +125,17 @@ def test_batch_rejects_edges_between_graphs(sc):
     assert e.value.status == -1
     with pytest.raises(sc.SclapError):  # node bases must cover n
         sc.partition_batch_union(u, [0, 5, 9], [2, 2], [0.03, 0.03], [1, 2])
+
+
+def test_autotuned_thresholds_leave_results_unchanged(sc):
+    gs, ks, eps, seeds = mix_small()
+    u, nb = sc.union(gs)
+    d = sc.to_device(u, "cuda")
+    o = sc.autotune_dev(d, int(np.median(ks)), coarsest_nodes=200)
+    cand = {(16, 256, 8192), (16, 128, 8192), (8, 256, 8192), (16, 256, 4096), (16, 64, 2048), (4, 128, 8192)}
+    assert (o.lane_max_degree, o.wave_max_degree, o.block_max_degree) in cand
+    assert o.coarsest_nodes == 200
+    tuned = sc.partition_batch_dev(d, nb, ks, eps, seeds, opts=o)
+    plain = sc.partition_batch_dev(d, nb, ks, eps, seeds, coarsest_nodes=200)
+    assert torch.equal(tuned["part"], plain["part"])
+    assert np.array_equal(tuned["cut"], plain["cut"]) and np.array_equal(tuned["block_weights"], plain["block_weights"])
