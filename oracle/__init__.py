@@ -46,7 +46,8 @@ class _Eval(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("coarsen_rounds", ctypes.c_int32), ("refine_rounds", ctypes.c_int32),
                 ("subrounds", ctypes.c_int32), ("cluster_divisor", ctypes.c_int32),
-                ("coarsest_nodes", ctypes.c_int32), ("max_levels", ctypes.c_int32)]
+                ("coarsest_nodes", ctypes.c_int32), ("max_levels", ctypes.c_int32),
+                ("vcycles", ctypes.c_int32)]
 
 
 _MAXL = 64
@@ -77,6 +78,10 @@ def _load():
             "orc_eval_node": (i32, [G, i32, i32, i32, u64, i64, vp, vp, i32, ctypes.POINTER(_Eval)]),
             "orc_subround": (i64, [G, i32, i32, i32, i32, i32, u64, i64, vp, vp, vp, vp, vp]),
             "orc_cluster": (i32, [G, i64, i32, i32, u64, i32, vp, vp, vp, vp]),
+            "orc_eval_node_within": (i32, [G, vp, i32, i32, i32, u64, i64, vp, vp, i32, ctypes.POINTER(_Eval)]),
+            "orc_subround_within": (i64, [G, vp, i32, i32, i32, i32, i32, u64, i64, vp, vp, vp, vp, vp]),
+            "orc_cluster_within": (i32, [G, vp, i64, i32, i32, u64, i32, vp, vp, vp, vp]),
+            "orc_cycle_seed": (u64, [u64, i32]),
             "orc_refine": (i32, [G, i32, i64, i32, i32, u64, i32, vp, vp, vp, vp]),
             "orc_contract": (i32, [G, vp, vp, vp, vp, vp, vp, vp, vp]),
             "orc_project": (None, [i32, vp, vp, vp]),
@@ -145,19 +150,29 @@ def validate(g):
     return int(_load().orc_validate(gv.ref))
 
 
-def eval_node(g, phase, level, rnd, seed, bound, label, w, v):
+def _block(block):
+    return None if block is None else np.ascontiguousarray(block, dtype=np.int32)
+
+
+def cycle_seed(seed, cycle):
+    return int(_load().orc_cycle_seed(seed, cycle))
+
+
+def eval_node(g, phase, level, rnd, seed, bound, label, w, v, block=None):
     gv = _GraphView(g)
     label = np.ascontiguousarray(label, dtype=np.int32)
     w = np.ascontiguousarray(w, dtype=np.int64)
+    blk = _block(block)
     e = _Eval()
-    _load().orc_eval_node(gv.ref, phase, level, rnd, seed, bound, label.ctypes.data, w.ctypes.data, v,
-                          ctypes.byref(e))
+    _load().orc_eval_node_within(gv.ref, _ptr(blk), phase, level, rnd, seed, bound, label.ctypes.data,
+                                 w.ctypes.data, v, ctypes.byref(e))
     return {"emit": e.emit, "target": e.target, "gain": e.gain, "conn_target": e.conn_target,
             "conn_own": e.conn_own, "over": e.over}
 
 
-def subround(g, phase, level, rnd, sub, nsub, seed, bound, label, w, color_override=None):
-    """One sub-round in place on ``label`` (int32) and ``w`` (int64).
+def subround(g, phase, level, rnd, sub, nsub, seed, bound, label, w, color_override=None, block=None):
+    """One sub-round in place on ``label`` (int32) and ``w`` (int64); with
+    ``block``, only same-block neighbours count.
 
     Returns (moves, visits, candidates)."""
     gv = _GraphView(g)
@@ -165,20 +180,24 @@ def subround(g, phase, level, rnd, sub, nsub, seed, bound, label, w, color_overr
     co = None if color_override is None else np.ascontiguousarray(color_override, dtype=np.int32)
     visits = np.zeros(1, dtype=np.int64)
     ncand = np.zeros(1, dtype=np.int64)
-    moves = _load().orc_subround(gv.ref, phase, level, rnd, sub, nsub, seed, bound, _ptr(co),
-                                 label.ctypes.data, w.ctypes.data, visits.ctypes.data, ncand.ctypes.data)
+    blk = _block(block)
+    moves = _load().orc_subround_within(gv.ref, _ptr(blk), phase, level, rnd, sub, nsub, seed, bound, _ptr(co),
+                                        label.ctypes.data, w.ctypes.data, visits.ctypes.data,
+                                        ncand.ctypes.data)
     return int(moves), int(visits[0]), int(ncand[0])
 
 
-def cluster(g, U, rounds=10, seed=1, level=0, nsub=4, color_override=None):
-    """Returns (labels, rounds_run, visits)."""
+def cluster(g, U, rounds=10, seed=1, level=0, nsub=4, color_override=None, block=None):
+    """Returns (labels, rounds_run, visits).  With ``block`` (int32[n]) every
+    cluster stays inside one block (clustering for iterated V-cycles)."""
     gv = _GraphView(g)
     labels = np.empty(gv.n, dtype=np.int32)
     rr = np.zeros(1, dtype=np.int32)
     visits = np.zeros(1, dtype=np.int64)
     co = None if color_override is None else np.ascontiguousarray(color_override, dtype=np.int32)
-    st = _load().orc_cluster(gv.ref, U, rounds, nsub, seed, level, _ptr(co), labels.ctypes.data,
-                             rr.ctypes.data, visits.ctypes.data)
+    blk = _block(block)
+    st = _load().orc_cluster_within(gv.ref, _ptr(blk), U, rounds, nsub, seed, level, _ptr(co), labels.ctypes.data,
+                                    rr.ctypes.data, visits.ctypes.data)
     if st != 0:
         raise ValueError("orc_cluster status %d" % st)
     return labels, int(rr[0]), int(visits[0])

@@ -160,19 +160,30 @@ static int cmp_lw(const void* x, const void* y) {
  *   moves to the best eligible block regardless of its own block (the
  *   local-search rule); otherwise it moves only for a strictly positive gain.
  */
-int32_t orc_eval_node(const orc_graph* g, int32_t phase, int32_t level, int32_t round, uint64_t seed,
-                      int64_t bound, const int32_t* label, const int64_t* w, int32_t v, orc_eval* out) {
+/*
+ * With a block array (clustering inside the blocks of an input partition,
+ * Section 4.5, Iterated Multilevel Schemes), only neighbours in v's own block
+ * are looked at: a cluster then never spans two blocks, so these are exactly
+ * the clusters of v's block.
+ */
+static int in_block(const int32_t* block, int32_t v, int32_t u) { return !block || block[u] == block[v]; }
+
+int32_t orc_eval_node_within(const orc_graph* g, const int32_t* block, int32_t phase, int32_t level,
+                             int32_t round, uint64_t seed, int64_t bound, const int32_t* label, const int64_t* w,
+                             int32_t v, orc_eval* out) {
     memset(out, 0, sizeof(*out));
     out->target = -1;
     int32_t a = label[v];
     int64_t cv = node_w(g, v);
-    int64_t b = g->xadj[v], e = g->xadj[v + 1], d = e - b;
+    int64_t b = g->xadj[v], e = g->xadj[v + 1], d = 0;
     out->over = (phase == ORC_REFINE && w[a] > bound) ? 1 : 0;
-    if (d == 0) return 0;
-    lw_pair* P = (lw_pair*)malloc((size_t)d * sizeof(lw_pair));
-    for (int64_t i = 0; i < d; ++i) {
-        P[i].label = label[g->adjncy[b + i]];
-        P[i].w = edge_w(g, b + i);
+    if (e == b) return 0;
+    lw_pair* P = (lw_pair*)malloc((size_t)(e - b) * sizeof(lw_pair));
+    for (int64_t i = b; i < e; ++i) {
+        if (!in_block(block, v, g->adjncy[i])) continue;
+        P[d].label = label[g->adjncy[i]];
+        P[d].w = edge_w(g, i);
+        ++d;
     }
     qsort(P, (size_t)d, sizeof(lw_pair), cmp_lw);
     int32_t best = -1;
@@ -203,6 +214,11 @@ int32_t orc_eval_node(const orc_graph* g, int32_t phase, int32_t level, int32_t 
     return 0;
 }
 
+int32_t orc_eval_node(const orc_graph* g, int32_t phase, int32_t level, int32_t round, uint64_t seed,
+                      int64_t bound, const int32_t* label, const int64_t* w, int32_t v, orc_eval* out) {
+    return orc_eval_node_within(g, NULL, phase, level, round, seed, bound, label, w, v, out);
+}
+
 /* ------------------------------------------------------------- sub-round */
 
 typedef struct { int32_t t; int64_t gain; int32_t v; int32_t from; int64_t c; } cand;
@@ -223,18 +239,20 @@ static int cmp_cand(const void* x, const void* y) {
  * sub-round are not credited).  Every block that started within the bound
  * therefore stays within it, which is the size constraint of Section 3.1.
  */
-int64_t orc_subround(const orc_graph* g, int32_t phase, int32_t level, int32_t round, int32_t sub,
-                     int32_t nsub, uint64_t seed, int64_t bound, const int32_t* color_override,
-                     int32_t* label, int64_t* w, int64_t* visits, int64_t* ncand) {
+int64_t orc_subround_within(const orc_graph* g, const int32_t* block, int32_t phase, int32_t level,
+                            int32_t round, int32_t sub, int32_t nsub, uint64_t seed, int64_t bound,
+                            const int32_t* color_override, int32_t* label, int64_t* w, int64_t* visits,
+                            int64_t* ncand) {
     int32_t n = g->n;
     cand* C = (cand*)malloc((size_t)(n > 0 ? n : 1) * sizeof(cand));
     int64_t nc = 0;
     for (int32_t v = 0; v < n; ++v) {
         int32_t col = color_override ? color_override[v] : orc_color(seed, level, phase, v, nsub);
         if (col != sub) continue;
-        if (visits) *visits += g->xadj[v + 1] - g->xadj[v];
+        if (visits)
+            for (int64_t i = g->xadj[v]; i < g->xadj[v + 1]; ++i) *visits += in_block(block, v, g->adjncy[i]);
         orc_eval ev;
-        orc_eval_node(g, phase, level, round, seed, bound, label, w, v, &ev);
+        orc_eval_node_within(g, block, phase, level, round, seed, bound, label, w, v, &ev);
         if (!ev.emit) continue;
         C[nc].t = ev.target;
         C[nc].gain = ev.gain;
@@ -272,16 +290,24 @@ int64_t orc_subround(const orc_graph* g, int32_t phase, int32_t level, int32_t r
     return moves;
 }
 
+int64_t orc_subround(const orc_graph* g, int32_t phase, int32_t level, int32_t round, int32_t sub,
+                     int32_t nsub, uint64_t seed, int64_t bound, const int32_t* color_override,
+                     int32_t* label, int64_t* w, int64_t* visits, int64_t* ncand) {
+    return orc_subround_within(g, NULL, phase, level, round, sub, nsub, seed, bound, color_override, label, w,
+                               visits, ncand);
+}
+
 /* Runs rounds of sub-rounds until `rounds` are done or a round moves nothing
  * (Section 3.1: at most l iterations, or until converged). */
-static int32_t run_rounds(const orc_graph* g, int32_t phase, int32_t level, int32_t rounds, int32_t nsub,
-                          uint64_t seed, int64_t bound, const int32_t* color_override, int32_t* label,
+static int32_t run_rounds(const orc_graph* g, const int32_t* block, int32_t phase, int32_t level, int32_t rounds,
+                          int32_t nsub, uint64_t seed, int64_t bound, const int32_t* color_override, int32_t* label,
                           int64_t* w, int32_t* rounds_run, int64_t* visits) {
     int32_t rr = 0;
     for (int32_t r = 0; r < rounds; ++r) {
         int64_t moves = 0;
         for (int32_t s = 0; s < nsub; ++s)
-            moves += orc_subround(g, phase, level, r, s, nsub, seed, bound, color_override, label, w, visits, NULL);
+            moves += orc_subround_within(g, block, phase, level, r, s, nsub, seed, bound, color_override, label, w,
+                                         visits, NULL);
         rr = r + 1;
         if (moves == 0) break;
     }
@@ -290,10 +316,13 @@ static int32_t run_rounds(const orc_graph* g, int32_t phase, int32_t level, int3
 }
 
 /* Size-constrained clustering: every node starts in its own cluster (label =
- * node id), cluster weights w(x) = c(x) (Section 3.1). */
-int32_t orc_cluster(const orc_graph* g, int64_t U, int32_t rounds, int32_t nsub, uint64_t seed,
-                    int32_t level, const int32_t* color_override, int32_t* labels, int32_t* rounds_run,
-                    int64_t* visits) {
+ * node id), cluster weights w(x) = c(x) (Section 3.1).  With a block array,
+ * a node only joins clusters of its own block (Section 4.5, Iterated
+ * Multilevel Schemes): singletons lie in one block each, and only same-block
+ * neighbours are looked at, so every cluster stays inside one block. */
+int32_t orc_cluster_within(const orc_graph* g, const int32_t* block, int64_t U, int32_t rounds, int32_t nsub,
+                           uint64_t seed, int32_t level, const int32_t* color_override, int32_t* labels,
+                           int32_t* rounds_run, int64_t* visits) {
     if (!g || g->n < 0 || rounds < 0 || nsub < 1) return -1;
     int32_t n = g->n;
     int64_t* w = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
@@ -301,9 +330,15 @@ int32_t orc_cluster(const orc_graph* g, int64_t U, int32_t rounds, int32_t nsub,
         labels[v] = v;
         w[v] = node_w(g, v);
     }
-    run_rounds(g, ORC_CLUSTER, level, rounds, nsub, seed, U, color_override, labels, w, rounds_run, visits);
+    run_rounds(g, block, ORC_CLUSTER, level, rounds, nsub, seed, U, color_override, labels, w, rounds_run, visits);
     free(w);
     return 0;
+}
+
+int32_t orc_cluster(const orc_graph* g, int64_t U, int32_t rounds, int32_t nsub, uint64_t seed,
+                    int32_t level, const int32_t* color_override, int32_t* labels, int32_t* rounds_run,
+                    int64_t* visits) {
+    return orc_cluster_within(g, NULL, U, rounds, nsub, seed, level, color_override, labels, rounds_run, visits);
 }
 
 /* SCLaP as local search on a k-way partition with bound Lmax (Section 3.1,
@@ -317,7 +352,7 @@ int32_t orc_refine(const orc_graph* g, int32_t k, int64_t Lmax, int32_t rounds, 
         if (part[v] < 0 || part[v] >= k) { free(w); return -1; }
         w[part[v]] += node_w(g, v);
     }
-    run_rounds(g, ORC_REFINE, level, rounds, nsub, seed, Lmax, color_override, part, w, rounds_run, visits);
+    run_rounds(g, NULL, ORC_REFINE, level, rounds, nsub, seed, Lmax, color_override, part, w, rounds_run, visits);
     free(w);
     return 0;
 }
@@ -475,6 +510,7 @@ void orc_default_options(orc_options* o) {
     o->cluster_divisor = 18;
     o->coarsest_nodes = 10000;
     o->max_levels = ORC_MAX_LEVELS;
+    o->vcycles = 1;
 }
 
 typedef struct {
@@ -483,8 +519,17 @@ typedef struct {
     int32_t* adj;
     int32_t* adjw;
     int32_t* vw;
-    int32_t* C; /* map to the next coarser level */
+    int32_t* C;   /* map to the next coarser level */
+    int32_t* blk; /* block of each node in the carried partition (later cycles) */
 } level_t;
+
+/* Seed of multilevel cycle c: the caller's seed for the first, a hash of
+ * (seed, 4, c) for later ones, so each cycle draws fresh colours and ties. */
+uint64_t orc_cycle_seed(uint64_t seed, int32_t cycle) {
+    if (cycle == 0) return seed;
+    uint64_t words[3] = {seed, 4, (uint64_t)(uint32_t)cycle};
+    return orc_hash(words, 3);
+}
 
 /*
  * Multilevel partitioning (Section 4.5): cluster with SCLaP under U and
@@ -493,6 +538,13 @@ typedef struct {
  * by at least 5%; partition the coarsest graph; then at every level from the
  * coarsest to the finest project the partition and refine it with SCLaP under
  * Lmax.
+ *
+ * Iterated V-cycles (Section 4.5, Iterated Multilevel Schemes): every cycle
+ * after the first clusters inside the blocks of the previous cycle's result,
+ * so no cut edge is contracted, each coarse node inherits the block of its
+ * members, and the inherited partition of the coarsest graph (same cut and
+ * block weights as the input partition) replaces the initial partitioner.
+ * The result of the last cycle is returned.
  */
 int32_t orc_partition(const orc_graph* g, int32_t k, double eps, uint64_t seed, const orc_options* opt_in,
                       int32_t* part, int64_t* cut, int64_t* bw, orc_stats* stats) {
@@ -501,7 +553,7 @@ int32_t orc_partition(const orc_graph* g, int32_t k, double eps, uint64_t seed, 
     else orc_default_options(&opt);
     if (!g || k < 1 || !(eps >= 0.0) || eps > 1000.0) return -1;
     if (opt.subrounds < 1 || opt.cluster_divisor < 1 || opt.max_levels < 0 || opt.max_levels > ORC_MAX_LEVELS ||
-        opt.coarsen_rounds < 0 || opt.refine_rounds < 0)
+        opt.coarsen_rounds < 0 || opt.refine_rounds < 0 || opt.vcycles < 1)
         return -1;
     int32_t st = orc_validate(g);
     if (st != 0) return st;
@@ -512,83 +564,101 @@ int32_t orc_partition(const orc_graph* g, int32_t k, double eps, uint64_t seed, 
     int64_t cV = total_node_weight(g);
     int64_t Lmax = orc_lmax(cV, k, eps);
     int64_t W = cV / ((int64_t)opt.cluster_divisor * k);
-
-    level_t L[ORC_MAX_LEVELS + 1];
-    memset(L, 0, sizeof(L));
-    /* level 0 views the input; materialise weights for uniform access */
-    L[0].n = n0;
-    L[0].xadj = (int64_t*)g->xadj;
-    L[0].adj = (int32_t*)g->adjncy;
     int64_t S0 = n0 > 0 ? g->xadj[n0] : 0;
-    L[0].adjw = (int32_t*)malloc((size_t)(S0 > 0 ? S0 : 1) * sizeof(int32_t));
-    L[0].vw = (int32_t*)malloc((size_t)(n0 > 0 ? n0 : 1) * sizeof(int32_t));
-    for (int64_t i = 0; i < S0; ++i) L[0].adjw[i] = (int32_t)edge_w(g, i);
-    for (int32_t v = 0; v < n0; ++v) L[0].vw[v] = (int32_t)node_w(g, v);
-    S->level_n[0] = n0;
-    S->level_S[0] = S0;
+    int32_t* prev = NULL; /* result of the previous cycle */
 
-    int32_t lev = 0;
-    while (L[lev].n > opt.coarsest_nodes && lev < opt.max_levels) {
-        orc_graph G = {L[lev].n, L[lev].xadj, L[lev].adj, L[lev].vw, L[lev].adjw};
-        int32_t n = G.n;
-        int64_t cmax = 0;
-        for (int32_t v = 0; v < n; ++v)
-            if (G.vwgt[v] > cmax) cmax = G.vwgt[v];
-        int64_t U = cmax > W ? cmax : W;
-        int32_t* labels = (int32_t*)malloc((size_t)n * sizeof(int32_t));
-        int32_t rr = 0;
-        orc_cluster(&G, U, opt.coarsen_rounds, opt.subrounds, seed, lev, NULL, labels, &rr, &S->visits);
-        S->cluster_rounds[lev] = rr;
-        int64_t Sl = G.xadj[n];
-        level_t nx;
-        nx.C = NULL;
-        int32_t* Cmap = (int32_t*)malloc((size_t)n * sizeof(int32_t));
-        nx.xadj = (int64_t*)malloc((size_t)(n + 1) * sizeof(int64_t));
-        nx.adj = (int32_t*)malloc((size_t)(Sl > 0 ? Sl : 1) * sizeof(int32_t));
-        nx.adjw = (int32_t*)malloc((size_t)(Sl > 0 ? Sl : 1) * sizeof(int32_t));
-        nx.vw = (int32_t*)malloc((size_t)n * sizeof(int32_t));
-        int64_t Sc = 0;
-        orc_contract(&G, labels, Cmap, &nx.n, nx.xadj, nx.adj, nx.adjw, nx.vw, &Sc);
-        free(labels);
-        if (nx.n >= n) { /* no shrink: discard the new level */
-            free(Cmap); free(nx.xadj); free(nx.adj); free(nx.adjw); free(nx.vw);
-            break;
-        }
-        L[lev].C = Cmap;
-        L[lev + 1] = nx;
-        ++lev;
-        S->level_n[lev] = nx.n;
-        S->level_S[lev] = Sc;
-        if (20LL * nx.n > 19LL * n) break; /* stalled: shrank by less than 5% */
-    }
-    S->levels = lev;
+    for (int32_t cyc = 0; cyc < opt.vcycles; ++cyc) {
+        uint64_t sd = orc_cycle_seed(seed, cyc);
+        int64_t visits = S->visits;
+        memset(S, 0, sizeof(*S));
+        S->visits = visits;
+        level_t L[ORC_MAX_LEVELS + 1];
+        memset(L, 0, sizeof(L));
+        /* level 0 views the input; materialise weights for uniform access */
+        L[0].n = n0;
+        L[0].xadj = (int64_t*)g->xadj;
+        L[0].adj = (int32_t*)g->adjncy;
+        L[0].adjw = (int32_t*)malloc((size_t)(S0 > 0 ? S0 : 1) * sizeof(int32_t));
+        L[0].vw = (int32_t*)malloc((size_t)(n0 > 0 ? n0 : 1) * sizeof(int32_t));
+        L[0].blk = prev;
+        for (int64_t i = 0; i < S0; ++i) L[0].adjw[i] = (int32_t)edge_w(g, i);
+        for (int32_t v = 0; v < n0; ++v) L[0].vw[v] = (int32_t)node_w(g, v);
+        S->level_n[0] = n0;
+        S->level_S[0] = S0;
 
-    /* initial partition of the coarsest graph */
-    int64_t T = (cV + k - 1) / k;
-    int32_t* cur = (int32_t*)malloc((size_t)(L[lev].n > 0 ? L[lev].n : 1) * sizeof(int32_t));
-    {
-        orc_graph G = {L[lev].n, L[lev].xadj, L[lev].adj, L[lev].vw, L[lev].adjw};
-        orc_initial_partition(&G, k, T, cur);
-    }
-    for (int32_t l = lev; l >= 0; --l) {
-        if (l < lev) {
-            int32_t* fine = (int32_t*)malloc((size_t)(L[l].n > 0 ? L[l].n : 1) * sizeof(int32_t));
-            orc_project(L[l].n, L[l].C, cur, fine);
-            free(cur);
-            cur = fine;
+        int32_t lev = 0;
+        while (L[lev].n > opt.coarsest_nodes && lev < opt.max_levels) {
+            orc_graph G = {L[lev].n, L[lev].xadj, L[lev].adj, L[lev].vw, L[lev].adjw};
+            int32_t n = G.n;
+            int64_t cmax = 0;
+            for (int32_t v = 0; v < n; ++v)
+                if (G.vwgt[v] > cmax) cmax = G.vwgt[v];
+            int64_t U = cmax > W ? cmax : W;
+            int32_t* labels = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+            int32_t rr = 0;
+            orc_cluster_within(&G, L[lev].blk, U, opt.coarsen_rounds, opt.subrounds, sd, lev, NULL, labels, &rr,
+                               &S->visits);
+            S->cluster_rounds[lev] = rr;
+            int64_t Sl = G.xadj[n];
+            level_t nx;
+            memset(&nx, 0, sizeof(nx));
+            int32_t* Cmap = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+            nx.xadj = (int64_t*)malloc((size_t)(n + 1) * sizeof(int64_t));
+            nx.adj = (int32_t*)malloc((size_t)(Sl > 0 ? Sl : 1) * sizeof(int32_t));
+            nx.adjw = (int32_t*)malloc((size_t)(Sl > 0 ? Sl : 1) * sizeof(int32_t));
+            nx.vw = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+            int64_t Sc = 0;
+            orc_contract(&G, labels, Cmap, &nx.n, nx.xadj, nx.adj, nx.adjw, nx.vw, &Sc);
+            free(labels);
+            if (nx.n >= n) { /* no shrink: discard the new level */
+                free(Cmap); free(nx.xadj); free(nx.adj); free(nx.adjw); free(nx.vw);
+                break;
+            }
+            if (L[lev].blk) { /* a coarse node lies in the block of its members */
+                nx.blk = (int32_t*)malloc((size_t)(nx.n > 0 ? nx.n : 1) * sizeof(int32_t));
+                for (int32_t v = 0; v < n; ++v) nx.blk[Cmap[v]] = L[lev].blk[v];
+            }
+            L[lev].C = Cmap;
+            L[lev + 1] = nx;
+            ++lev;
+            S->level_n[lev] = nx.n;
+            S->level_S[lev] = Sc;
+            if (20LL * nx.n > 19LL * n) break; /* stalled: shrank by less than 5% */
         }
-        orc_graph G = {L[l].n, L[l].xadj, L[l].adj, L[l].vw, L[l].adjw};
-        int32_t rr = 0;
-        orc_refine(&G, k, Lmax, opt.refine_rounds, opt.subrounds, seed, l, NULL, cur, &rr, &S->visits);
-        S->refine_rounds[l] = rr;
+        S->levels = lev;
+
+        /* partition of the coarsest graph: the initial partitioner in the
+         * first cycle, the inherited blocks in later ones */
+        int64_t T = (cV + k - 1) / k;
+        int32_t* cur = (int32_t*)malloc((size_t)(L[lev].n > 0 ? L[lev].n : 1) * sizeof(int32_t));
+        if (L[lev].blk) {
+            memcpy(cur, L[lev].blk, (size_t)L[lev].n * sizeof(int32_t));
+        } else {
+            orc_graph G = {L[lev].n, L[lev].xadj, L[lev].adj, L[lev].vw, L[lev].adjw};
+            orc_initial_partition(&G, k, T, cur);
+        }
+        for (int32_t l = lev; l >= 0; --l) {
+            if (l < lev) {
+                int32_t* fine = (int32_t*)malloc((size_t)(L[l].n > 0 ? L[l].n : 1) * sizeof(int32_t));
+                orc_project(L[l].n, L[l].C, cur, fine);
+                free(cur);
+                cur = fine;
+            }
+            orc_graph G = {L[l].n, L[l].xadj, L[l].adj, L[l].vw, L[l].adjw};
+            int32_t rr = 0;
+            orc_refine(&G, k, Lmax, opt.refine_rounds, opt.subrounds, sd, l, NULL, cur, &rr, &S->visits);
+            S->refine_rounds[l] = rr;
+        }
+        for (int32_t l = 0; l <= lev; ++l) {
+            if (l > 0) { free(L[l].xadj); free(L[l].adj); free(L[l].blk); }
+            free(L[l].adjw); free(L[l].vw); free(L[l].C);
+        }
+        free(prev);
+        prev = cur;
     }
-    memcpy(part, cur, (size_t)n0 * sizeof(int32_t));
-    free(cur);
+    memcpy(part, prev, (size_t)n0 * sizeof(int32_t));
+    free(prev);
     orc_cut(g, part, k, cut, bw);
-    for (int32_t l = 0; l <= lev; ++l) {
-        if (l > 0) { free(L[l].xadj); free(L[l].adj); }
-        free(L[l].adjw); free(L[l].vw); free(L[l].C);
-    }
     for (int32_t b = 0; b < k; ++b)
         if (bw[b] > Lmax) return 1;
     return 0;

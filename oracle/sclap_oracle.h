@@ -63,16 +63,31 @@ typedef struct {
 
 int32_t orc_eval_node(const orc_graph* g, int32_t phase, int32_t level, int32_t round, uint64_t seed,
                       int64_t bound, const int32_t* label, const int64_t* w, int32_t v, orc_eval* out);
+/* The same with block[n] != NULL: only neighbours u with block[u] == block[v]
+ * count (clustering inside the blocks of a partition, Section 4.5). */
+int32_t orc_eval_node_within(const orc_graph* g, const int32_t* block, int32_t phase, int32_t level,
+                             int32_t round, uint64_t seed, int64_t bound, const int32_t* label, const int64_t* w,
+                             int32_t v, orc_eval* out);
 
 /* One sub-round: evaluate colour `sub`, admit, apply.  Returns #moves.
  * Optional outputs: visits (+= degrees of evaluated nodes), ncand (+= #candidates). */
 int64_t orc_subround(const orc_graph* g, int32_t phase, int32_t level, int32_t round, int32_t sub,
                      int32_t nsub, uint64_t seed, int64_t bound, const int32_t* color_override,
                      int32_t* label, int64_t* w, int64_t* visits, int64_t* ncand);
+int64_t orc_subround_within(const orc_graph* g, const int32_t* block, int32_t phase, int32_t level,
+                            int32_t round, int32_t sub, int32_t nsub, uint64_t seed, int64_t bound,
+                            const int32_t* color_override, int32_t* label, int64_t* w, int64_t* visits,
+                            int64_t* ncand);
 
 int32_t orc_cluster(const orc_graph* g, int64_t U, int32_t rounds, int32_t nsub, uint64_t seed,
                     int32_t level, const int32_t* color_override, int32_t* labels, int32_t* rounds_run,
                     int64_t* visits);
+
+/* Clustering inside the blocks of block[n] (Section 4.5, Iterated Multilevel
+ * Schemes); visits counts only the same-block slots looked at. */
+int32_t orc_cluster_within(const orc_graph* g, const int32_t* block, int64_t U, int32_t rounds, int32_t nsub,
+                           uint64_t seed, int32_t level, const int32_t* color_override, int32_t* labels,
+                           int32_t* rounds_run, int64_t* visits);
 
 int32_t orc_refine(const orc_graph* g, int32_t k, int64_t Lmax, int32_t rounds, int32_t nsub, uint64_t seed,
                    int32_t level, const int32_t* color_override, int32_t* part, int32_t* rounds_run,
@@ -96,7 +111,10 @@ typedef struct {
     int32_t cluster_divisor; /* 18 */
     int32_t coarsest_nodes;  /* 10000 */
     int32_t max_levels;      /* 64 */
+    int32_t vcycles;         /* 1: multilevel cycles, each after the first inside the previous blocks */
 } orc_options;
+
+uint64_t orc_cycle_seed(uint64_t seed, int32_t cycle);
 
 #define ORC_MAX_LEVELS 64
 typedef struct {

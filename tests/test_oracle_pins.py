@@ -192,3 +192,25 @@ def test_tie_break_prefers_smallest_priority(seed, rnd):
     ev = oracle.eval_node(g, oracle.CLUSTER, 2, rnd, seed, 100, label, w, 0)
     expect = min(range(1, n), key=lambda x: (_h([seed, 2, 2, 0, rnd, x]), x))
     assert ev["target"] == expect and ev["emit"] == 1 and ev["gain"] == 1
+
+
+def test_handworked_clustering_inside_blocks(golden_dir):
+    ex = _load(golden_dir, "handworked.json")["G_cluster_within_blocks"]
+    g = _graph(ex)
+    col = np.array(ex["colors"], dtype=np.int32)
+    blk = np.array(ex["block"], dtype=np.int32)
+    lab, rr, visits = oracle.cluster(g, ex["U"], rounds=ex["rounds"], seed=ex["seed"], nsub=ex["nsub"],
+                                     color_override=col, block=blk)
+    assert lab.tolist() == ex["expected_labels"]
+    assert rr == ex["expected_rounds_run"] and visits == ex["expected_visits"]
+    free, _, fv = oracle.cluster(g, ex["U"], rounds=ex["rounds"], seed=ex["seed"], nsub=ex["nsub"],
+                                 color_override=col)
+    assert free.tolist() == ex["expected_labels_unrestricted"] and fv == ex["expected_visits_unrestricted"]
+    C, cg = oracle.contract(g, lab)
+    assert C.tolist() == ex["expected_C"]
+    for key, val in ex["expected_coarse"].items():
+        got = cg[key] if key == "n" else cg[key].tolist()
+        assert got == val, key
+    coarse_blk = np.zeros(cg["n"], dtype=np.int32)
+    coarse_blk[C] = blk
+    assert oracle.cut(cg, coarse_blk, 2)[0] == oracle.cut(g, blk, 2)[0] == ex["expected_coarse_cut"]

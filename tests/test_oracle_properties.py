@@ -21,7 +21,12 @@ the oracle's own arithmetic:
 * brute force: for n <= 16 the optimal balanced bipartition cut is a lower
   bound for the multilevel result, which must be balanced;
 * storage-order independence: permuting the neighbours inside rows changes
-  nothing.
+  nothing;
+* clustering inside the blocks of a partition (Section 4.5, iterated
+  V-cycles): every cluster lies in one block, contracting keeps the cut and
+  the block weights, one block reduces to plain clustering and singleton
+  blocks to the identity; a later V-cycle equals its composition from the
+  single operations.
 """
 import itertools
 
@@ -419,3 +424,117 @@ def test_stall_rule_on_mostly_isolated_graph(seed):
     for a, b in zip(ln[:-2], ln[1:-1]):
         assert 20 * b <= 19 * a
     assert ln[-1] > 10  # stopped by the stall rule, not by size
+
+
+# ------------------------------------------ clustering inside blocks, V-cycles
+# (Section 4.5, Iterated Multilevel Schemes)
+
+def py_block_conns(r, lab, blk, v):
+    c = {}
+    for u, w in r:
+        if blk[u] == blk[v]:
+            c[lab[u]] = c.get(lab[u], 0) + w
+    return c
+
+
+@pytest.mark.parametrize("name,make", GRAPHS)
+@pytest.mark.parametrize("nblk", [2, 5])
+def test_cluster_inside_blocks_invariants(name, make, nblk):
+    g = make()
+    n = g["n"]
+    c = vw(g)
+    blk = np.random.default_rng(nblk).integers(0, nblk, size=n).astype(np.int32)
+    U = max(8, int(c.max()))
+    lab, rr, visits = oracle.cluster(g, U, rounds=30, seed=3, block=blk)
+    # every cluster inside one block
+    owner = {}
+    for v in range(n):
+        assert owner.setdefault(int(lab[v]), int(blk[v])) == blk[v]
+    w = py_weights(g, lab, n)
+    assert w.max() <= U or U < c.max()
+    if rr < 30:  # converged: no node has a stronger eligible cluster of its block
+        for v, r in enumerate(rows(g)):
+            conn = py_block_conns(r, lab, blk, v)
+            own = conn.get(int(lab[v]), 0)
+            assert not any(conn[x] > own and w[x] + c[v] <= U for x in conn if x != lab[v])
+    # each round looks at the same-block slots of every node
+    same = sum(1 for v, r in enumerate(rows(g)) for u, _ in r if blk[u] == blk[v])
+    assert visits == rr * same
+    # contracting keeps every cut edge: the inherited coarse partition has
+    # the cut and the block weights of the input partition
+    C, cg = oracle.contract(g, lab)
+    cb = np.zeros(cg["n"], dtype=np.int32)
+    cb[C] = blk
+    assert np.array_equal(cb[C], blk)
+    assert py_cut(cg, cb) == py_cut(g, blk)
+    assert np.array_equal(py_weights(cg, cb, nblk), py_weights(g, blk, nblk))
+
+
+@pytest.mark.parametrize("name,make", GRAPHS)
+def test_cluster_inside_one_block_is_plain_clustering(name, make):
+    g = make()
+    U = max(10, int(vw(g).max()))
+    a = oracle.cluster(g, U, rounds=10, seed=2, block=np.zeros(g["n"], dtype=np.int32))
+    b = oracle.cluster(g, U, rounds=10, seed=2)
+    assert np.array_equal(a[0], b[0]) and a[1:] == b[1:]
+
+
+@pytest.mark.parametrize("name,make", GRAPHS)
+def test_cluster_inside_singleton_blocks_is_identity(name, make):
+    g = make()
+    lab, rr, visits = oracle.cluster(g, 10 ** 6, rounds=10, seed=2, block=np.arange(g["n"], dtype=np.int32))
+    assert np.array_equal(lab, np.arange(g["n"])) and rr == 1 and visits == 0
+
+
+def test_one_vcycle_is_the_plain_multilevel_run():
+    g = synth.rgg(2000, seed=3, weighted=True)
+    a = oracle.partition(g, 8, 0.03, 4, coarsest_nodes=150)
+    b = oracle.partition(g, 8, 0.03, 4, coarsest_nodes=150, vcycles=1)
+    assert np.array_equal(a["part"], b["part"]) and a["visits"] == b["visits"]
+    assert oracle.cycle_seed(4, 0) == 4 and oracle.cycle_seed(4, 1) != oracle.cycle_seed(4, 2)
+
+
+def py_vcycle(g, k, eps, seed, prev, cycle, coarsest):
+    """One later V-cycle composed from the oracle's single operations."""
+    sd = oracle.cycle_seed(seed, cycle)
+    cV = int(vw(g).sum())
+    Lmax = oracle.lmax(cV, k, eps)
+    W = cV // (18 * k)
+    levels, Cs = [(g, prev)], []
+    while levels[-1][0]["n"] > coarsest:
+        G, blk = levels[-1]
+        U = max(int(vw(G).max()), W)
+        lab, _, _ = oracle.cluster(G, U, rounds=10, seed=sd, level=len(Cs), block=blk)
+        C, cg = oracle.contract(G, lab)
+        if cg["n"] >= G["n"]:
+            break
+        cb = np.zeros(cg["n"], dtype=np.int32)
+        cb[C] = blk
+        assert py_cut(cg, cb) == py_cut(g, prev)  # no cut edge was contracted
+        Cs.append(C)
+        levels.append((cg, cb))
+        if 20 * cg["n"] > 19 * G["n"]:
+            break
+    part = levels[-1][1].copy()
+    for lev in range(len(levels) - 1, -1, -1):
+        if lev < len(levels) - 1:
+            part = oracle.project(Cs[lev], part)
+        part, _, _ = oracle.refine(levels[lev][0], k, Lmax, part, rounds=10, seed=sd, level=lev)
+    return part
+
+
+@pytest.mark.parametrize("make,k", [(lambda: synth.ba(3000, 4, seed=2), 4),
+                                    (lambda: synth.rgg(2500, seed=6, weighted=True), 16),
+                                    (lambda: synth.rmat(12, 8, seed=3), 8)])
+def test_vcycles_compose_from_single_operations(make, k):
+    g = make()
+    r1 = oracle.partition(g, k, 0.03, 7, coarsest_nodes=200)
+    r2 = oracle.partition(g, k, 0.03, 7, coarsest_nodes=200, vcycles=2)
+    r3 = oracle.partition(g, k, 0.03, 7, coarsest_nodes=200, vcycles=3)
+    p2 = py_vcycle(g, k, 0.03, 7, r1["part"], 1, 200)
+    assert np.array_equal(p2, r2["part"])
+    assert np.array_equal(py_vcycle(g, k, 0.03, 7, p2, 2, 200), r3["part"])
+    for r in (r2, r3):
+        assert r["cut"] == py_cut(g, r["part"])
+        assert np.array_equal(r["block_weights"], py_weights(g, r["part"], k))
+        assert r["status"] == (1 if r["block_weights"].max() > oracle.lmax(int(vw(g).sum()), k, 0.03) else 0)
