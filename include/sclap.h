@@ -99,7 +99,12 @@ typedef struct {
                                  neighbouring label stronger than their own and saw no neighbour move
                                  since (their decision is unchanged); -1: evaluate every node;
                                  0: on for batches, off for single graphs */
-    int32_t reserved;
+    int32_t vcycles;          /* multilevel cycles (Section 4.5, iterated V-cycles; 0 counts as 1,
+                                 at most 64): every cycle after the first clusters only inside the
+                                 blocks of the previous result, so no cut edge is contracted, and
+                                 starts refinement from that result on its coarsest graph; cycle c
+                                 uses the seed H(seed, 4, c) for c >= 1.  The last result is
+                                 returned.  Default 1. */
 } sclap_options;
 
 #define SCLAP_MAX_LEVELS 64
@@ -150,6 +155,20 @@ int sclap_cluster(const sclap_graph* g, int64_t U, int32_t rounds, uint64_t seed
                   const sclap_options* opt, int32_t* labels, int32_t* rounds_run);
 int sclap_cluster_dev(const sclap_graph* g, int64_t U, int32_t rounds, uint64_t seed, int32_t level,
                       const sclap_options* opt, int32_t* labels, int32_t* rounds_run, void* stream);
+
+/*
+ * Clustering inside the blocks of a partition (Section 4.5, Iterated
+ * Multilevel Schemes): as sclap_cluster, but a node only looks at the
+ * neighbours u with block[u] == block[v], so it only joins clusters of its own
+ * block and every cluster lies inside one block (contracting it keeps every
+ * cut edge of the partition).  block[n]: any int32 values, same memory as the
+ * other arrays of the call (host / device), read only.
+ */
+int sclap_cluster_within(const sclap_graph* g, const int32_t* block, int64_t U, int32_t rounds, uint64_t seed,
+                         int32_t level, const sclap_options* opt, int32_t* labels, int32_t* rounds_run);
+int sclap_cluster_within_dev(const sclap_graph* g, const int32_t* block, int64_t U, int32_t rounds,
+                             uint64_t seed, int32_t level, const sclap_options* opt, int32_t* labels,
+                             int32_t* rounds_run, void* stream);
 
 /*
  * Cluster contraction (Section 3.1 contraction definition; Section 4.3

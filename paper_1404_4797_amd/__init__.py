@@ -27,7 +27,7 @@ MAX_LEVELS = 64
 EXPORTS = [
     "sclap_default_options", "sclap_last_error", "sclap_lmax",
     "sclap_validate", "sclap_validate_dev",
-    "sclap_cluster", "sclap_cluster_dev",
+    "sclap_cluster", "sclap_cluster_dev", "sclap_cluster_within", "sclap_cluster_within_dev",
     "sclap_contract", "sclap_contract_dev", "sclap_graph_free",
     "sclap_project", "sclap_project_dev",
     "sclap_refine", "sclap_refine_dev",
@@ -66,7 +66,7 @@ class Options(ctypes.Structure):
                 ("lane_max_degree", ctypes.c_int32), ("wave_max_degree", ctypes.c_int32),
                 ("block_max_degree", ctypes.c_int32), ("hub_part_limit", ctypes.c_int32),
                 ("hub_region_cap", ctypes.c_int32), ("select_small_max", ctypes.c_int32),
-                ("skip_quiet", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("skip_quiet", ctypes.c_int32), ("vcycles", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):
@@ -128,6 +128,8 @@ def load():
         "sclap_validate_dev": (ctypes.c_int, [G, vp]),
         "sclap_cluster": (ctypes.c_int, [G, i64, i32, u64, i32, O, vp, vp]),
         "sclap_cluster_dev": (ctypes.c_int, [G, i64, i32, u64, i32, O, vp, vp, vp]),
+        "sclap_cluster_within": (ctypes.c_int, [G, vp, i64, i32, u64, i32, O, vp, vp]),
+        "sclap_cluster_within_dev": (ctypes.c_int, [G, vp, i64, i32, u64, i32, O, vp, vp, vp]),
         "sclap_contract": (ctypes.c_int, [G, vp, vp, GO]),
         "sclap_contract_dev": (ctypes.c_int, [G, vp, vp, GO, vp]),
         "sclap_graph_free": (None, [GO]),
@@ -211,14 +213,21 @@ def validate(g):
     return int(load().sclap_validate(_HostGraph(g).ref))
 
 
-def cluster(g, U, rounds=10, seed=1, level=0, color_override=None, **opts):
+def cluster(g, U, rounds=10, seed=1, level=0, color_override=None, block=None, **opts):
+    """Size-constrained clustering; with ``block`` (int32[n]) only inside the
+    blocks of that partition.  Returns (labels, rounds_run)."""
     hg = _HostGraph(g)
     co = None if color_override is None else np.ascontiguousarray(color_override, dtype=np.int32)
     o = _opts(opts, _np_ptr(co))
     labels = np.empty(hg.n, dtype=np.int32)
     rr = ctypes.c_int32(0)
-    _check(load().sclap_cluster(hg.ref, U, rounds, seed, level, ctypes.byref(o), labels.ctypes.data,
-                                ctypes.addressof(rr)))
+    if block is None:
+        _check(load().sclap_cluster(hg.ref, U, rounds, seed, level, ctypes.byref(o), labels.ctypes.data,
+                                    ctypes.addressof(rr)))
+    else:
+        blk = np.ascontiguousarray(block, dtype=np.int32)
+        _check(load().sclap_cluster_within(hg.ref, blk.ctypes.data, U, rounds, seed, level, ctypes.byref(o),
+                                           labels.ctypes.data, ctypes.addressof(rr)))
     return labels, rr.value
 
 
@@ -339,15 +348,21 @@ def validate_dev(d, stream=None):
     return int(load().sclap_validate_dev(_DevGraph(d).ref, _stream(stream)))
 
 
-def cluster_dev(d, U, rounds=10, seed=1, level=0, labels=None, color_override=None, stream=None, **opts):
+def cluster_dev(d, U, rounds=10, seed=1, level=0, labels=None, color_override=None, stream=None, block=None,
+                **opts):
+    """cluster() on a device graph; ``block`` is an int32 tensor on the GPU."""
     import torch
     dg = _DevGraph(d)
     if labels is None:
         labels = torch.empty(dg.n, dtype=torch.int32, device=d["xadj"].device)
     o = _opts(opts, _t_ptr(color_override))
     rr = ctypes.c_int32(0)
-    _check(load().sclap_cluster_dev(dg.ref, U, rounds, seed, level, ctypes.byref(o), _t_ptr(labels),
-                                    ctypes.addressof(rr), _stream(stream)))
+    if block is None:
+        _check(load().sclap_cluster_dev(dg.ref, U, rounds, seed, level, ctypes.byref(o), _t_ptr(labels),
+                                        ctypes.addressof(rr), _stream(stream)))
+    else:
+        _check(load().sclap_cluster_within_dev(dg.ref, _t_ptr(block), U, rounds, seed, level, ctypes.byref(o),
+                                               _t_ptr(labels), ctypes.addressof(rr), _stream(stream)))
     return labels, rr.value
 
 

@@ -139,7 +139,8 @@ void download(T* h, const T* d, int64_t count, hipStream_t s) {
 // ------------------------------------------------------ single operations
 
 int cluster_impl(const DevGraph& g, int64_t U, int32_t rounds, uint64_t seed, int32_t level, const Opts& o,
-                 const int32_t* color_dev, int32_t* labels, int32_t* rounds_run, hipStream_t s) {
+                 const int32_t* color_dev, int32_t* labels, int32_t* rounds_run, hipStream_t s,
+                 const int32_t* block = nullptr) {
     if (rounds < 0) fail(SCLAP_ERR_INVALID, "rounds < 0");
     if (U < 0) fail(SCLAP_ERR_INVALID, "U < 0");
     if (g.n > 0 && !labels) fail(SCLAP_ERR_INVALID, "labels is NULL");
@@ -150,7 +151,14 @@ int cluster_impl(const DevGraph& g, int64_t U, int32_t rounds, uint64_t seed, in
     DBuf<int32_t> w(std::max(g.n, 1), s);
     iota_u32(reinterpret_cast<uint32_t*>(labels), g.n, s);
     label_weights(g, labels, w.get(), g.n, s);
-    const LPResult r = run_lp(g, kCluster, level, seed, o.nsub, rounds, U, labels, w.get(), g.n, color_dev, o.tune, s);
+    OwnedDevGraph inside;
+    DevGraph gc = g;
+    if (block) {
+        within_blocks(g, block, inside, s);
+        gc = inside.view();
+        gc.vw = g.vw;
+    }
+    const LPResult r = run_lp(gc, kCluster, level, seed, o.nsub, rounds, U, labels, w.get(), g.n, color_dev, o.tune, s);
     HIPCHK(hipStreamSynchronize(s));
     if (rounds_run) *rounds_run = r.rounds_run;
     return SCLAP_OK;
@@ -193,6 +201,7 @@ int sclap_default_options(sclap_options* opt) {
     opt->coarsest_nodes = 10000;
     opt->max_levels = SCLAP_MAX_LEVELS;
     opt->validate = 1;
+    opt->vcycles = 1;
     return SCLAP_OK;
 }
 
@@ -269,6 +278,35 @@ int sclap_cluster(const sclap_graph* g, int64_t U, int32_t rounds, uint64_t seed
         DBuf<int32_t> lab(std::max(g->n, 1), s);
         const int r = cluster_impl(st.g, U, rounds, seed, level, o, o.color_override ? col.get() : nullptr,
                                    lab.get(), rounds_run, s);
+        download(labels, lab.get(), g->n, s);
+        return r;
+    });
+}
+
+int sclap_cluster_within_dev(const sclap_graph* g, const int32_t* block, int64_t U, int32_t rounds,
+                             uint64_t seed, int32_t level, const sclap_options* opt, int32_t* labels,
+                             int32_t* rounds_run, void* stream) {
+    return guarded([&] {
+        hipStream_t s = as_stream(stream);
+        const Opts o = resolve(opt);
+        const DevGraph d = dev_view(g, s);
+        if (d.n > 0 && !block) fail(SCLAP_ERR_INVALID, "block is NULL");
+        return cluster_impl(d, U, rounds, seed, level, o, o.color_override, labels, rounds_run, s, block);
+    });
+}
+
+int sclap_cluster_within(const sclap_graph* g, const int32_t* block, int64_t U, int32_t rounds, uint64_t seed,
+                         int32_t level, const sclap_options* opt, int32_t* labels, int32_t* rounds_run) {
+    return guarded([&] {
+        hipStream_t s = nullptr;
+        const Opts o = resolve(opt);
+        Staged st = upload(g, s);
+        if (g->n > 0 && !block) fail(SCLAP_ERR_INVALID, "block is NULL");
+        DBuf<int32_t> col, blk = upload_array(block, g->n, s);
+        if (o.color_override) col = upload_array(o.color_override, g->n, s);
+        DBuf<int32_t> lab(std::max(g->n, 1), s);
+        const int r = cluster_impl(st.g, U, rounds, seed, level, o, o.color_override ? col.get() : nullptr,
+                                   lab.get(), rounds_run, s, blk.get());
         download(labels, lab.get(), g->n, s);
         return r;
     });

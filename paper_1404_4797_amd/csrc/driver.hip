@@ -41,6 +41,8 @@ Opts resolve(const sclap_options* o) {
     if (o->hub_region_cap > 0) r.tune.hub_region_cap = o->hub_region_cap;
     if (o->select_small_max > 0) r.tune.select_small_max = o->select_small_max;
     r.tune.skip_quiet = o->skip_quiet < 0 ? -1 : (o->skip_quiet > 0 ? 1 : 0);
+    r.vcycles = o->vcycles == 0 ? 1 : o->vcycles;
+    if (r.vcycles < 1 || r.vcycles > 64) fail(SCLAP_ERR_INVALID, "vcycles must be in 1..64");
     if (r.coarsen_rounds < 0 || r.refine_rounds < 0) fail(SCLAP_ERR_INVALID, "round counts must be >= 0");
     if (r.nsub < 1 || r.nsub > 16) fail(SCLAP_ERR_INVALID, "subrounds must be in 1..16");
     if (r.divisor < 1) fail(SCLAP_ERR_INVALID, "cluster_divisor must be >= 1");
@@ -455,27 +457,31 @@ void drop_unit_weights(DevGraph& g, hipStream_t s) {
 
 }  // namespace
 
-int partition_impl(const DevGraph& g0_in, int32_t k, double eps, uint64_t seed, const Opts& o, int32_t* part_out,
-                   int64_t* cut, int64_t* bw, sclap_stats* stats, hipStream_t s) {
-    DevGraph g0 = g0_in;
-    check_k_eps(k, eps);
-    if (!part_out && g0.n > 0) fail(SCLAP_ERR_INVALID, "part is NULL");
-    if (!cut || !bw) fail(SCLAP_ERR_INVALID, "cut / block_w is NULL");
-    int64_t cV = 0, cmax0 = 0;
-    check_graph(g0, o.validate != 0, &cV, &cmax0, s);
-    drop_unit_weights(g0, s);
-    sclap_stats local;
-    sclap_stats* st = stats ? stats : &local;
-    std::memset(st, 0, sizeof(*st));
-    const int64_t Lmax = lmax_of(cV, k, eps);
-    const int64_t W = cV / (static_cast<int64_t>(o.divisor) * k);
+namespace {
 
+// One multilevel cycle (Section 4.5).  blk0 (device) is null in the first
+// cycle; in later ones it holds the previous cycle's partition: clustering
+// then stays inside its blocks (on the subgraph of intra-block slots), every
+// coarse node inherits the block of its members, and the inherited partition
+// of the coarsest graph replaces the initial partitioner (it has the cut and
+// the block weights of blk0, since no cut edge was contracted).  blk0 may
+// alias part_out.  Per-level statistics describe this cycle; visits and
+// times add up.
+void multilevel_cycle(const DevGraph& g0, int32_t k, int64_t cV, int64_t cmax0, int64_t Lmax, uint64_t seed,
+                      const Opts& o, const int32_t* blk0, int32_t* part_out, sclap_stats* st, double& lp_ms,
+                      hipStream_t s) {
+    const int64_t W = cV / (static_cast<int64_t>(o.divisor) * k);
+    std::memset(st->level_n, 0, sizeof(st->level_n));
+    std::memset(st->level_S, 0, sizeof(st->level_S));
+    std::memset(st->cluster_rounds, 0, sizeof(st->cluster_rounds));
+    std::memset(st->refine_rounds, 0, sizeof(st->refine_rounds));
     std::vector<Level> L(1);
+    std::vector<DBuf<int32_t>> blk(1);  // inherited blocks of levels >= 1
+    auto blk_of = [&](int32_t l) -> const int32_t* { return l == 0 ? blk0 : blk[l].get(); };
     L[0].g = g0;
     st->level_n[0] = g0.n;
     st->level_S[0] = g0.S;
     auto t_coarsen = Clock::now();
-    double lp_ms = 0;
     int32_t lev = 0;
     while (L[lev].g.n > o.coarsest && lev < o.max_levels) {
         const DevGraph G = L[lev].g;
@@ -486,10 +492,18 @@ int partition_impl(const DevGraph& g0_in, int32_t k, double eps, uint64_t seed, 
         DBuf<int32_t> labels(n, s), w(n, s);
         iota_u32(reinterpret_cast<uint32_t*>(labels.get()), n, s);
         label_weights(G, labels.get(), w.get(), n, s);
+        OwnedDevGraph inside;
+        DevGraph Gc = G;  // the graph clustering looks at
+        if (blk0) {
+            within_blocks(G, blk_of(lev), inside, s);
+            Gc = inside.view();
+            Gc.vw = G.vw;
+        }
         auto t_lp = Clock::now();
-        const LPResult r = run_lp(G, kCluster, lev, seed, o.nsub, o.coarsen_rounds, U, labels.get(), w.get(), n,
+        const LPResult r = run_lp(Gc, kCluster, lev, seed, o.nsub, o.coarsen_rounds, U, labels.get(), w.get(), n,
                                   nullptr, o.tune, s);
         lp_ms += ms_since(t_lp);
+        inside = OwnedDevGraph();
         st->visits += r.visits;
         st->cluster_rounds[lev] = r.rounds_run;
         w.release();
@@ -497,9 +511,15 @@ int partition_impl(const DevGraph& g0_in, int32_t k, double eps, uint64_t seed, 
         Level nx;
         contract(G, labels.get(), C.get(), nx.own, s, nullptr, 0, nullptr, false);
         if (nx.own.n >= n) break;  // no shrink: keep the current level as the coarsest
+        DBuf<int32_t> cb;
+        if (blk0) {
+            cb.alloc(std::max(nx.own.n, 1), s);
+            inherit_blocks(n, C.get(), blk_of(lev), cb.get(), s);
+        }
         L[lev].C = std::move(C);
         nx.g = nx.own.view();
         L.push_back(std::move(nx));
+        blk.push_back(std::move(cb));
         ++lev;
         st->level_n[lev] = L[lev].g.n;
         st->level_S[lev] = L[lev].g.S;
@@ -508,45 +528,52 @@ int partition_impl(const DevGraph& g0_in, int32_t k, double eps, uint64_t seed, 
     st->levels = lev;
     // inner levels keep their rows unordered; the initial partition grows
     // blocks along ascending neighbour ids, so order the coarsest graph's rows
-    if (lev > 0) sort_rows(L[lev].own, s);
+    if (lev > 0 && !blk0) sort_rows(L[lev].own, s);
     HIPCHK(hipStreamSynchronize(s));
-    st->ms_coarsen = ms_since(t_coarsen);
+    st->ms_coarsen += ms_since(t_coarsen);
 
-    // initial partition of the coarsest graph on the host
     auto t_init = Clock::now();
     const DevGraph Gc = L[lev].g;
     const int32_t nc = Gc.n;
-    const size_t bx = (static_cast<size_t>(nc) + 1) * sizeof(int64_t);
-    const size_t ba = static_cast<size_t>(std::max<int64_t>(Gc.S, 1)) * sizeof(int32_t);
-    const size_t bn = static_cast<size_t>(std::max(nc, 1)) * sizeof(int32_t);
-    HostStage stage(bx + ba + 2 * bn);
-    int64_t* hx = reinterpret_cast<int64_t*>(stage.data());
-    int32_t* ha = reinterpret_cast<int32_t*>(stage.data() + bx);
-    int32_t* hv = reinterpret_cast<int32_t*>(stage.data() + bx + ba);
-    int32_t* hp = reinterpret_cast<int32_t*>(stage.data() + bx + ba + bn);
-    if (nc > 0) {
-        HIPCHK(hipMemcpyAsync(hx, Gc.xadj, bx, hipMemcpyDeviceToHost, s));
-        if (Gc.S > 0) HIPCHK(hipMemcpyAsync(ha, Gc.adj, Gc.S * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        if (Gc.vw) HIPCHK(hipMemcpyAsync(hv, Gc.vw, nc * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-    }
-    const double ms_d2h = ms_since(t_init);
-    const int64_t T = (cV + k - 1) / k;
-    // rows of contracted levels are sorted by construction
-    host_initial_partition(nc, hx, ha, Gc.vw ? hv : nullptr, k, T, hp, lev > 0);
-    const double ms_ip = ms_since(t_init) - ms_d2h;
     DBuf<int32_t> cur;
     int32_t* curp = part_out;
     if (lev > 0) {
         cur.alloc(nc, s);
         curp = cur.get();
     }
-    if (nc > 0) HIPCHK(hipMemcpyAsync(curp, hp, nc * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (blk0) {
+        // the inherited partition of the coarsest graph
+        if (nc > 0 && curp != blk_of(lev))
+            HIPCHK(hipMemcpyAsync(curp, blk_of(lev), nc * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    } else {
+        // initial partition of the coarsest graph on the host
+        const size_t bx = (static_cast<size_t>(nc) + 1) * sizeof(int64_t);
+        const size_t ba = static_cast<size_t>(std::max<int64_t>(Gc.S, 1)) * sizeof(int32_t);
+        const size_t bn = static_cast<size_t>(std::max(nc, 1)) * sizeof(int32_t);
+        HostStage stage(bx + ba + 2 * bn);
+        int64_t* hx = reinterpret_cast<int64_t*>(stage.data());
+        int32_t* ha = reinterpret_cast<int32_t*>(stage.data() + bx);
+        int32_t* hv = reinterpret_cast<int32_t*>(stage.data() + bx + ba);
+        int32_t* hp = reinterpret_cast<int32_t*>(stage.data() + bx + ba + bn);
+        if (nc > 0) {
+            HIPCHK(hipMemcpyAsync(hx, Gc.xadj, bx, hipMemcpyDeviceToHost, s));
+            if (Gc.S > 0) HIPCHK(hipMemcpyAsync(ha, Gc.adj, Gc.S * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            if (Gc.vw) HIPCHK(hipMemcpyAsync(hv, Gc.vw, nc * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        const double ms_d2h = ms_since(t_init);
+        const int64_t T = (cV + k - 1) / k;
+        // rows of contracted levels are sorted by construction
+        host_initial_partition(nc, hx, ha, Gc.vw ? hv : nullptr, k, T, hp, lev > 0);
+        const double ms_ip = ms_since(t_init) - ms_d2h;
+        if (nc > 0) HIPCHK(hipMemcpyAsync(curp, hp, nc * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));  // the staging buffer is released below
+        if (trace_on())
+            fprintf(stderr, "[sclap] initial partition: n=%d S=%lld pinned=%d copy-in %.1f ms, partition %.1f ms\n",
+                    nc, static_cast<long long>(Gc.S), stage.pinned() ? 1 : 0, ms_d2h, ms_ip);
+    }
     HIPCHK(hipStreamSynchronize(s));
-    if (trace_on())
-        fprintf(stderr, "[sclap] initial partition: n=%d S=%lld pinned=%d copy-in %.1f ms, partition %.1f ms\n", nc,
-                static_cast<long long>(Gc.S), stage.pinned() ? 1 : 0, ms_d2h, ms_ip);
-    st->ms_initial = ms_since(t_init);
+    st->ms_initial += ms_since(t_init);
 
     auto t_ref = Clock::now();
     DBuf<int32_t> w(k, s);
@@ -563,6 +590,7 @@ int partition_impl(const DevGraph& g0_in, int32_t k, double eps, uint64_t seed, 
             cur = std::move(fine);
             curp = finep;
             L[l + 1].own = OwnedDevGraph();  // the coarser graph is no longer needed
+            blk[l + 1].release();
             L[l].C.release();
         }
         label_weights(G, curp, w.get(), k, s);
@@ -573,8 +601,37 @@ int partition_impl(const DevGraph& g0_in, int32_t k, double eps, uint64_t seed, 
         st->visits += r.visits;
         st->refine_rounds[l] = r.rounds_run;
     }
+    HIPCHK(hipStreamSynchronize(s));
+    st->ms_refine += ms_since(t_ref);
+}
+
+}  // namespace
+
+uint64_t cycle_seed(uint64_t seed, int32_t cycle) {
+    if (cycle == 0) return seed;
+    return hash_prefix({seed, 4, static_cast<uint64_t>(static_cast<uint32_t>(cycle))});
+}
+
+int partition_impl(const DevGraph& g0_in, int32_t k, double eps, uint64_t seed, const Opts& o, int32_t* part_out,
+                   int64_t* cut, int64_t* bw, sclap_stats* stats, hipStream_t s) {
+    DevGraph g0 = g0_in;
+    check_k_eps(k, eps);
+    if (!part_out && g0.n > 0) fail(SCLAP_ERR_INVALID, "part is NULL");
+    if (!cut || !bw) fail(SCLAP_ERR_INVALID, "cut / block_w is NULL");
+    int64_t cV = 0, cmax0 = 0;
+    check_graph(g0, o.validate != 0, &cV, &cmax0, s);
+    drop_unit_weights(g0, s);
+    sclap_stats local;
+    sclap_stats* st = stats ? stats : &local;
+    std::memset(st, 0, sizeof(*st));
+    const int64_t Lmax = lmax_of(cV, k, eps);
+    double lp_ms = 0;
+    for (int32_t c = 0; c < o.vcycles; ++c)
+        multilevel_cycle(g0, k, cV, cmax0, Lmax, cycle_seed(seed, c), o, c == 0 ? nullptr : part_out, part_out, st,
+                         lp_ms, s);
+    auto t_cut = Clock::now();
     cut_and_weights(g0, part_out, k, cut, bw, s);
-    st->ms_refine = ms_since(t_ref);
+    st->ms_refine += ms_since(t_cut);
     st->ms_lp = lp_ms;
     for (int32_t b = 0; b < k; ++b)
         if (bw[b] > Lmax) return SCLAP_WARN_IMBALANCED;
@@ -714,222 +771,260 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
     DBuf<int64_t> d_bound(G, s);
     DBuf<int32_t> d_lbase(G, s), d_nbase(G, s), d_kb(G, s);
     DBuf<uint8_t> d_active(G, s);
-    HIPCHK(hipMemcpyAsync(d_seed.get(), seed, G * sizeof(uint64_t), hipMemcpyHostToDevice, s));
     upload_vec(d_kb, std::vector<int32_t>(kb.begin(), kb.begin() + G), s);
-
-    // ---- coarsening
-    std::vector<uint8_t> cont(G, 1);
-    int32_t lev = 0;
-    while (true) {
-        const int32_t M = static_cast<int32_t>(L[lev].ids.size());
-        std::vector<uint8_t> act(G, 0);
-        bool any = false;
-        for (int32_t m = 0; m < M; ++m) {
-            const int32_t g = L[lev].ids[m];
-            const int32_t nm = L[lev].nb[m + 1] - L[lev].nb[m];
-            if (cont[g] && nm > o.coarsest && lev < o.max_levels) {
-                act[g] = 1;
-                any = true;
-            }
-        }
-        if (!any) break;
-        BatchLevel& B = L[lev];
-        const int32_t n = B.g.n;
-        std::vector<int64_t> cvl(G), cm = cmax0;
-        if (lev > 0) graph_node_stats(n, B.gid.get(), B.g.vw, G, cvl.data(), cm.data(), s);
-        std::vector<int64_t> bound(G, 0);
-        std::vector<int32_t> base(G, 0);
-        for (int32_t m = 0; m < M; ++m) {
-            const int32_t g = B.ids[m];
-            bound[g] = std::max(cm[g], W[g]);
-            base[g] = B.nb[m];
-        }
-        upload_vec(d_bound, bound, s);
-        upload_vec(d_lbase, base, s);
-        upload_vec(d_nbase, base, s);
-        upload_vec(d_active, act, s);
-        DBuf<int32_t> labels(n, s), w(n, s);
-        iota_u32(reinterpret_cast<uint32_t*>(labels.get()), n, s);
-        label_weights(B.g, labels.get(), w.get(), n, s);
-        MultiGraph mg;
-        mg.G = G;
-        mg.gid = B.gid.get();
-        mg.lgid = B.gid.get();  // cluster labels are node ids
-        mg.nbase = d_nbase.get();
-        mg.lbase = d_lbase.get();
-        mg.bound = d_bound.get();
-        mg.seed = d_seed.get();
-        mg.active = d_active.get();
-        auto t_lp = Clock::now();
-        const LPResult r =
-            run_lp(B.g, kCluster, lev, 0, o.nsub, o.coarsen_rounds, 0, labels.get(), w.get(), n, nullptr, o.tune, s, &mg);
-        lp_ms += ms_since(t_lp);
-        st->visits += r.visits;
-        w.release();
-        // contraction of the whole level; member m's coarse nodes start at cb[m]
-        DBuf<int32_t> probe(M + 1, s), qb(M + 1, s), C(n, s);
-        upload_vec(probe, B.nb, s);
-        OwnedDevGraph coarse;
-        contract(B.g, labels.get(), C.get(), coarse, s, probe.get(), M + 1, qb.get(), false);
-        std::vector<int32_t> cb(M + 1);
-        HIPCHK(hipMemcpyAsync(cb.data(), qb.get(), (M + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        labels.release();
-        std::vector<int32_t> keep;
-        for (int32_t m = 0; m < M; ++m) {
-            const int32_t g = B.ids[m];
-            if (!act[g]) {
-                cont[g] = 0;
-                continue;
-            }
-            const int64_t nm = B.nb[m + 1] - B.nb[m], nc = cb[m + 1] - cb[m];
-            if (nc >= nm) {  // no shrink: this level stays the graph's coarsest
-                cont[g] = 0;
-                continue;
-            }
-            keep.push_back(m);
-            if (20 * nc > 19 * nm) cont[g] = 0;  // stalled
-        }
-        if (keep.empty()) break;
-        BatchLevel N;
-        const std::vector<int64_t> csb = member_slot_bases(coarse.xadj.get(), cb, s);
-        N.nb.push_back(0);
-        N.sb.push_back(0);
-        std::vector<int32_t> onb;
-        std::vector<int64_t> osb;
-        for (int32_t m : keep) {
-            N.ids.push_back(B.ids[m]);
-            N.nb.push_back(N.nb.back() + (cb[m + 1] - cb[m]));
-            N.sb.push_back(N.sb.back() + (csb[m + 1] - csb[m]));
-            onb.push_back(cb[m]);
-            osb.push_back(csb[m]);
-        }
-        if (static_cast<int32_t>(keep.size()) == M) {
-            N.own = std::move(coarse);
-        } else {
-            compact_members(coarse.view(), onb, osb, N.nb, N.sb, N.own, s);
-            coarse = OwnedDevGraph();
-        }
-        N.g = N.own.view();
-        N.gid.alloc(std::max(N.g.n, 1), s);
-        member_ids(N.g.n, N.nb, N.ids, N.gid.get(), s);
-        std::vector<int32_t> delta(G, INT_MIN);
-        for (size_t j = 0; j < keep.size(); ++j) delta[N.ids[j]] = N.nb[j] - cb[keep[j]];
-        remap_members(n, B.gid.get(), delta, C.get(), s);
-        B.C = std::move(C);
-        L.push_back(std::move(N));  // B is not used after this
-        ++lev;
-    }
-    const int32_t top = lev;
-    std::vector<int32_t> last(G, 0), mpos(G, 0);
-    for (int32_t l = 0; l <= top; ++l)
-        for (size_t m = 0; m < L[l].ids.size(); ++m) last[L[l].ids[m]] = l;
-    st->levels = top;
-    if (st->graph_levels)
-        for (int32_t g = 0; g < G; ++g) st->graph_levels[g] = last[g];
-    HIPCHK(hipStreamSynchronize(s));
-    st->ms_coarsen = ms_since(t_coarsen);
-
-    // ---- initial partition of every graph's coarsest level, on the host
-    auto t_init = Clock::now();
-    struct Slice {
-        std::vector<int64_t> x;
-        std::vector<int32_t> a, v, part;
-    };
-    std::vector<Slice> ip(G);
-    for (int32_t l = 0; l <= top; ++l) {
-        const BatchLevel& B = L[l];
-        for (size_t m = 0; m < B.ids.size(); ++m) {
-            const int32_t g = B.ids[m];
-            mpos[g] = static_cast<int32_t>(m);
-            if (last[g] != l) continue;
-            const int32_t nm = B.nb[m + 1] - B.nb[m];
-            const int64_t Sm = B.sb[m + 1] - B.sb[m];
-            Slice& sl = ip[g];
-            sl.x.resize(static_cast<size_t>(nm) + 1);
-            sl.a.resize(static_cast<size_t>(std::max<int64_t>(Sm, 1)));
-            sl.part.resize(static_cast<size_t>(nm));
-            HIPCHK(hipMemcpyAsync(sl.x.data(), B.g.xadj + B.nb[m], (nm + 1) * sizeof(int64_t), hipMemcpyDeviceToHost,
-                                  s));
-            if (Sm > 0)
-                HIPCHK(hipMemcpyAsync(sl.a.data(), B.g.adj + B.sb[m], Sm * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            if (B.g.vw && nm > 0) {
-                sl.v.resize(nm);
-                HIPCHK(hipMemcpyAsync(sl.v.data(), B.g.vw + B.nb[m], nm * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            }
-        }
-    }
-    HIPCHK(hipStreamSynchronize(s));
-    const unsigned hw = std::thread::hardware_concurrency();
-    parallel_for(G, static_cast<int32_t>(std::min(16u, hw ? hw : 1u)), [&](int32_t g) {
-        Slice& sl = ip[g];
-        const BatchLevel& B = L[last[g]];
-        const int32_t m = mpos[g];
-        const int32_t nm = B.nb[m + 1] - B.nb[m];
-        const int64_t x0 = sl.x[0];
-        for (auto& x : sl.x) x -= x0;
-        for (int64_t j = 0; j < sl.x[nm]; ++j) sl.a[j] -= B.nb[m];
-        host_initial_partition(nm, sl.x.data(), sl.a.data(), sl.v.empty() ? nullptr : sl.v.data(), k[g], T[g],
-                               sl.part.data(), false);  // rows of inner levels are unordered
-        for (auto& b : sl.part) b += kb[g];  // labels of the batch's block space
-        sl.x = {};
-        sl.a = {};
-        sl.v = {};
-    });
-    st->ms_initial = ms_since(t_init);
-
-    // ---- refinement from the top level down
-    auto t_ref = Clock::now();
     std::vector<int32_t> lgid(std::max(K, 1));
     for (int32_t g = 0; g < G; ++g)
         for (int32_t b = kb[g]; b < kb[g + 1]; ++b) lgid[b] = g;
     DBuf<int32_t> d_lgid(std::max(K, 1), s);
     upload_vec(d_lgid, lgid, s);
-    upload_vec(d_bound, Lmax, s);
-    upload_vec(d_active, std::vector<uint8_t>(G, 1), s);
-    DBuf<int32_t> w(std::max(K, 1), s), cur;
-    for (int32_t l = top; l >= 0; --l) {
-        BatchLevel& B = L[l];
-        const int32_t n = B.g.n;
-        DBuf<int32_t> mine;
-        int32_t* part = part_out;
-        if (l > 0) {
-            mine.alloc(std::max(n, 1), s);
-            part = mine.get();
+    DBuf<int32_t> w(std::max(K, 1), s);
+
+    // Multilevel cycles (Section 4.5): from the second on, part_out holds the
+    // previous cycle's partition in the batch's block space; clustering stays
+    // inside its blocks and the inherited coarsest partitions replace the
+    // initial partitioner, as in multilevel_cycle.
+    for (int32_t cyc = 0; cyc < o.vcycles; ++cyc) {
+        const int32_t* carry = cyc == 0 ? nullptr : part_out;
+        std::vector<uint64_t> cseed(G);
+        for (int32_t g = 0; g < G; ++g) cseed[g] = cycle_seed(seed[g], cyc);
+        upload_vec(d_seed, cseed, s);
+        L.resize(1);
+        std::vector<DBuf<int32_t>> bblk(1);  // inherited blocks of levels >= 1
+        auto blk_of = [&](int32_t l) -> const int32_t* { return l == 0 ? carry : bblk[l].get(); };
+        t_coarsen = Clock::now();
+
+        // ---- coarsening
+        std::vector<uint8_t> cont(G, 1);
+        int32_t lev = 0;
+        while (true) {
+            const int32_t M = static_cast<int32_t>(L[lev].ids.size());
+            std::vector<uint8_t> act(G, 0);
+            bool any = false;
+            for (int32_t m = 0; m < M; ++m) {
+                const int32_t g = L[lev].ids[m];
+                const int32_t nm = L[lev].nb[m + 1] - L[lev].nb[m];
+                if (cont[g] && nm > o.coarsest && lev < o.max_levels) {
+                    act[g] = 1;
+                    any = true;
+                }
+            }
+            if (!any) break;
+            BatchLevel& B = L[lev];
+            const int32_t n = B.g.n;
+            std::vector<int64_t> cvl(G), cm = cmax0;
+            if (lev > 0) graph_node_stats(n, B.gid.get(), B.g.vw, G, cvl.data(), cm.data(), s);
+            std::vector<int64_t> bound(G, 0);
+            std::vector<int32_t> base(G, 0);
+            for (int32_t m = 0; m < M; ++m) {
+                const int32_t g = B.ids[m];
+                bound[g] = std::max(cm[g], W[g]);
+                base[g] = B.nb[m];
+            }
+            upload_vec(d_bound, bound, s);
+            upload_vec(d_lbase, base, s);
+            upload_vec(d_nbase, base, s);
+            upload_vec(d_active, act, s);
+            DBuf<int32_t> labels(n, s), wl(n, s);
+            iota_u32(reinterpret_cast<uint32_t*>(labels.get()), n, s);
+            label_weights(B.g, labels.get(), wl.get(), n, s);
+            MultiGraph mg;
+            mg.G = G;
+            mg.gid = B.gid.get();
+            mg.lgid = B.gid.get();  // cluster labels are node ids
+            mg.nbase = d_nbase.get();
+            mg.lbase = d_lbase.get();
+            mg.bound = d_bound.get();
+            mg.seed = d_seed.get();
+            mg.active = d_active.get();
+            OwnedDevGraph inside;
+            DevGraph Gc = B.g;  // the graph clustering looks at
+            if (carry) {
+                within_blocks(B.g, blk_of(lev), inside, s);
+                Gc = inside.view();
+                Gc.vw = B.g.vw;
+            }
+            auto t_lp = Clock::now();
+            const LPResult r =
+                run_lp(Gc, kCluster, lev, 0, o.nsub, o.coarsen_rounds, 0, labels.get(), wl.get(), n, nullptr, o.tune, s, &mg);
+            lp_ms += ms_since(t_lp);
+            inside = OwnedDevGraph();
+            st->visits += r.visits;
+            wl.release();
+            // contraction of the whole level; member m's coarse nodes start at cb[m]
+            DBuf<int32_t> probe(M + 1, s), qb(M + 1, s), C(n, s);
+            upload_vec(probe, B.nb, s);
+            OwnedDevGraph coarse;
+            contract(B.g, labels.get(), C.get(), coarse, s, probe.get(), M + 1, qb.get(), false);
+            std::vector<int32_t> cb(M + 1);
+            HIPCHK(hipMemcpyAsync(cb.data(), qb.get(), (M + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            labels.release();
+            std::vector<int32_t> keep;
+            for (int32_t m = 0; m < M; ++m) {
+                const int32_t g = B.ids[m];
+                if (!act[g]) {
+                    cont[g] = 0;
+                    continue;
+                }
+                const int64_t nm = B.nb[m + 1] - B.nb[m], nc = cb[m + 1] - cb[m];
+                if (nc >= nm) {  // no shrink: this level stays the graph's coarsest
+                    cont[g] = 0;
+                    continue;
+                }
+                keep.push_back(m);
+                if (20 * nc > 19 * nm) cont[g] = 0;  // stalled
+            }
+            if (keep.empty()) break;
+            BatchLevel N;
+            const std::vector<int64_t> csb = member_slot_bases(coarse.xadj.get(), cb, s);
+            N.nb.push_back(0);
+            N.sb.push_back(0);
+            std::vector<int32_t> onb;
+            std::vector<int64_t> osb;
+            for (int32_t m : keep) {
+                N.ids.push_back(B.ids[m]);
+                N.nb.push_back(N.nb.back() + (cb[m + 1] - cb[m]));
+                N.sb.push_back(N.sb.back() + (csb[m + 1] - csb[m]));
+                onb.push_back(cb[m]);
+                osb.push_back(csb[m]);
+            }
+            if (static_cast<int32_t>(keep.size()) == M) {
+                N.own = std::move(coarse);
+            } else {
+                compact_members(coarse.view(), onb, osb, N.nb, N.sb, N.own, s);
+                coarse = OwnedDevGraph();
+            }
+            N.g = N.own.view();
+            N.gid.alloc(std::max(N.g.n, 1), s);
+            member_ids(N.g.n, N.nb, N.ids, N.gid.get(), s);
+            std::vector<int32_t> delta(G, INT_MIN);
+            for (size_t j = 0; j < keep.size(); ++j) delta[N.ids[j]] = N.nb[j] - cb[keep[j]];
+            remap_members(n, B.gid.get(), delta, C.get(), s);
+            DBuf<int32_t> cbl;
+            if (carry) {
+                cbl.alloc(std::max(N.g.n, 1), s);
+                inherit_blocks(n, C.get(), blk_of(lev), cbl.get(), s);
+            }
+            B.C = std::move(C);
+            L.push_back(std::move(N));  // B is not used after this
+            bblk.push_back(std::move(cbl));
+            ++lev;
         }
-        if (l < top) project_kept(n, B.C.get(), cur.get(), part, s);
-        for (size_t m = 0; m < B.ids.size(); ++m) {
-            const int32_t g = B.ids[m];
-            if (last[g] != l || ip[g].part.empty()) continue;
-            HIPCHK(hipMemcpyAsync(part + B.nb[m], ip[g].part.data(), ip[g].part.size() * sizeof(int32_t),
-                                  hipMemcpyHostToDevice, s));
+        const int32_t top = lev;
+        std::vector<int32_t> last(G, 0), mpos(G, 0);
+        for (int32_t l = 0; l <= top; ++l)
+            for (size_t m = 0; m < L[l].ids.size(); ++m) last[L[l].ids[m]] = l;
+        st->levels = top;
+        if (st->graph_levels)
+            for (int32_t g = 0; g < G; ++g) st->graph_levels[g] = last[g];
+        HIPCHK(hipStreamSynchronize(s));
+        st->ms_coarsen += ms_since(t_coarsen);
+
+        // ---- initial partition of every graph's coarsest level, on the host
+        // (first cycle; later ones inherit it)
+        auto t_init = Clock::now();
+        struct Slice {
+            std::vector<int64_t> x;
+            std::vector<int32_t> a, v, part;
+        };
+        std::vector<Slice> ip(G);
+        for (int32_t l = 0; l <= top; ++l) {
+            const BatchLevel& B = L[l];
+            for (size_t m = 0; m < B.ids.size(); ++m) {
+                const int32_t g = B.ids[m];
+                mpos[g] = static_cast<int32_t>(m);
+                if (last[g] != l || carry) continue;
+                const int32_t nm = B.nb[m + 1] - B.nb[m];
+                const int64_t Sm = B.sb[m + 1] - B.sb[m];
+                Slice& sl = ip[g];
+                sl.x.resize(static_cast<size_t>(nm) + 1);
+                sl.a.resize(static_cast<size_t>(std::max<int64_t>(Sm, 1)));
+                sl.part.resize(static_cast<size_t>(nm));
+                HIPCHK(hipMemcpyAsync(sl.x.data(), B.g.xadj + B.nb[m], (nm + 1) * sizeof(int64_t), hipMemcpyDeviceToHost,
+                                      s));
+                if (Sm > 0)
+                    HIPCHK(hipMemcpyAsync(sl.a.data(), B.g.adj + B.sb[m], Sm * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                if (B.g.vw && nm > 0) {
+                    sl.v.resize(nm);
+                    HIPCHK(hipMemcpyAsync(sl.v.data(), B.g.vw + B.nb[m], nm * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                }
+            }
         }
-        std::vector<int32_t> base(G, 0);
-        for (size_t m = 0; m < B.ids.size(); ++m) base[B.ids[m]] = B.nb[m];
-        upload_vec(d_nbase, base, s);
-        label_weights(B.g, part, w.get(), K, s);
-        MultiGraph mg;
-        mg.G = G;
-        mg.gid = B.gid.get();
-        mg.lgid = d_lgid.get();
-        mg.max_labels = *std::max_element(k, k + G);
-        mg.nbase = d_nbase.get();
-        mg.lbase = d_kb.get();
-        mg.bound = d_bound.get();
-        mg.seed = d_seed.get();
-        mg.active = d_active.get();
-        auto t_lp = Clock::now();
-        const LPResult r =
-            run_lp(B.g, kRefine, l, 0, o.nsub, o.refine_rounds, 0, part, w.get(), K, nullptr, o.tune, s, &mg);
-        lp_ms += ms_since(t_lp);
-        st->visits += r.visits;
-        HIPCHK(hipStreamSynchronize(s));  // host slices uploaded above must stay alive until here
-        for (size_t m = 0; m < B.ids.size(); ++m)
-            if (last[B.ids[m]] == l) ip[B.ids[m]].part = {};
-        cur = std::move(mine);
-        if (l < top) L[l + 1] = BatchLevel();
-        B.C.release();
-    }
+        HIPCHK(hipStreamSynchronize(s));
+        const unsigned hw = std::thread::hardware_concurrency();
+        if (!carry) parallel_for(G, static_cast<int32_t>(std::min(16u, hw ? hw : 1u)), [&](int32_t g) {
+            Slice& sl = ip[g];
+            const BatchLevel& B = L[last[g]];
+            const int32_t m = mpos[g];
+            const int32_t nm = B.nb[m + 1] - B.nb[m];
+            const int64_t x0 = sl.x[0];
+            for (auto& x : sl.x) x -= x0;
+            for (int64_t j = 0; j < sl.x[nm]; ++j) sl.a[j] -= B.nb[m];
+            host_initial_partition(nm, sl.x.data(), sl.a.data(), sl.v.empty() ? nullptr : sl.v.data(), k[g], T[g],
+                                   sl.part.data(), false);  // rows of inner levels are unordered
+            for (auto& b : sl.part) b += kb[g];  // labels of the batch's block space
+            sl.x = {};
+            sl.a = {};
+            sl.v = {};
+        });
+        st->ms_initial += ms_since(t_init);
+
+        // ---- refinement from the top level down
+        auto t_ref = Clock::now();
+        upload_vec(d_bound, Lmax, s);
+        upload_vec(d_active, std::vector<uint8_t>(G, 1), s);
+        DBuf<int32_t> cur;
+        for (int32_t l = top; l >= 0; --l) {
+            BatchLevel& B = L[l];
+            const int32_t n = B.g.n;
+            DBuf<int32_t> mine;
+            int32_t* part = part_out;
+            if (l > 0) {
+                mine.alloc(std::max(n, 1), s);
+                part = mine.get();
+            }
+            if (carry && part != blk_of(l) && n > 0)  // graphs ending here keep their inherited blocks
+                HIPCHK(hipMemcpyAsync(part, blk_of(l), n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+            if (l < top) project_kept(n, B.C.get(), cur.get(), part, s);
+            for (size_t m = 0; m < B.ids.size(); ++m) {
+                const int32_t g = B.ids[m];
+                if (last[g] != l || ip[g].part.empty()) continue;
+                HIPCHK(hipMemcpyAsync(part + B.nb[m], ip[g].part.data(), ip[g].part.size() * sizeof(int32_t),
+                                      hipMemcpyHostToDevice, s));
+            }
+            std::vector<int32_t> base(G, 0);
+            for (size_t m = 0; m < B.ids.size(); ++m) base[B.ids[m]] = B.nb[m];
+            upload_vec(d_nbase, base, s);
+            label_weights(B.g, part, w.get(), K, s);
+            MultiGraph mg;
+            mg.G = G;
+            mg.gid = B.gid.get();
+            mg.lgid = d_lgid.get();
+            mg.max_labels = *std::max_element(k, k + G);
+            mg.nbase = d_nbase.get();
+            mg.lbase = d_kb.get();
+            mg.bound = d_bound.get();
+            mg.seed = d_seed.get();
+            mg.active = d_active.get();
+            auto t_lp = Clock::now();
+            const LPResult r =
+                run_lp(B.g, kRefine, l, 0, o.nsub, o.refine_rounds, 0, part, w.get(), K, nullptr, o.tune, s, &mg);
+            lp_ms += ms_since(t_lp);
+            st->visits += r.visits;
+            HIPCHK(hipStreamSynchronize(s));  // host slices uploaded above must stay alive until here
+            for (size_t m = 0; m < B.ids.size(); ++m)
+                if (last[B.ids[m]] == l) ip[B.ids[m]].part = {};
+            cur = std::move(mine);
+            if (l < top) {
+                L[l + 1] = BatchLevel();
+                bblk[l + 1].release();
+            }
+            B.C.release();
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        st->ms_refine += ms_since(t_ref);
+    }  // cycles
+    auto t_fin = Clock::now();
     std::vector<int32_t> hw_(std::max(K, 1));
     HIPCHK(hipMemcpyAsync(hw_.data(), w.get(), std::max(K, 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     graph_cuts(g0, part_out, L[0].gid.get(), G, cut, s);  // synchronises
@@ -941,7 +1036,7 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
             bw[b] = hw_[b];
             if (bw[b] > Lmax[g]) status = SCLAP_WARN_IMBALANCED;
         }
-    st->ms_refine = ms_since(t_ref);
+    st->ms_refine += ms_since(t_fin);
     st->ms_lp = lp_ms;
     return status;
 }

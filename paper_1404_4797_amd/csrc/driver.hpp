@@ -19,8 +19,13 @@ struct Opts {
     int32_t max_levels = SCLAP_MAX_LEVELS;
     int32_t validate = 1;
     const int32_t* color_override = nullptr;
+    int32_t vcycles = 1;
     LPTuning tune;
 };
+
+// Seed of multilevel cycle c (Section 4.5, iterated V-cycles): the caller's
+// seed for the first, H(seed, 4, c) for later ones.
+uint64_t cycle_seed(uint64_t seed, int32_t cycle);
 
 // Defaults for NULL; checks ranges (throws Error).
 Opts resolve(const sclap_options* o);
@@ -40,7 +45,8 @@ void check_k_eps(int32_t k, double eps);
 void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, const int32_t* vw, int32_t k,
                             int64_t T, int32_t* part, bool rows_sorted = false);
 
-// One graph: outputs part (device, n), cut and bw[k] (host).
+// One graph: outputs part (device, n), cut and bw[k] (host); o.vcycles
+// multilevel cycles.
 int partition_impl(const DevGraph& g0, int32_t k, double eps, uint64_t seed, const Opts& o, int32_t* part_out,
                    int64_t* cut, int64_t* bw, sclap_stats* stats, hipStream_t s);
 

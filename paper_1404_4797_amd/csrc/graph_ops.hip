@@ -532,6 +532,159 @@ void remap_members(int32_t n, const int32_t* gid, const std::vector<int32_t>& de
     HIPCHK(hipStreamSynchronize(s));
 }
 
+// ------------------------------------------------------- inside blocks
+//
+// Clustering inside the blocks of a partition (Section 4.5, iterated
+// V-cycles) runs on the subgraph of the slots u->v with blk[u] == blk[v]:
+// every cluster then stays inside one block.  Kept slots keep their order.
+// Pass 1 counts the kept slots of each slot tile, pass 2 scans inside the
+// tile, scatters, and writes the new offset of every row starting in it.
+
+namespace {
+
+__global__ void __launch_bounds__(kTileThreads) within_count_kernel(const int64_t* __restrict__ xadj,
+                                                                    const int32_t* __restrict__ adj, int32_t n,
+                                                                    int64_t S, const int32_t* __restrict__ blk,
+                                                                    int32_t* __restrict__ tcnt) {
+    __shared__ int32_t owner[kTile];
+    __shared__ int32_t s_w[kTileThreads / kWave];
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kTile;
+    const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
+    tile_owners(xadj, n, i0, i1, owner);
+    int32_t c = 0;
+    for (int r = 0; r < kTilePer; ++r) {
+        const int64_t i = i0 + r * kTileThreads + threadIdx.x;
+        if (i < i1) c += blk[owner[i - i0]] == blk[adj[i]];
+    }
+    c = wave_sum(c);
+    if (lane_id() == 0) s_w[threadIdx.x / kWave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int w = 0; w < kTileThreads / kWave; ++w) t += s_w[w];
+        tcnt[blockIdx.x] = t;
+    }
+}
+
+// first u in [0, n] with xadj[u] >= slot
+__device__ int32_t first_row_from(const int64_t* __restrict__ xadj, int32_t n, int64_t slot) {
+    int32_t lo = 0, hi = n;  // answer in [lo, hi]; xadj[n] = S > slot
+    while (lo < hi) {
+        const int32_t mid = lo + (hi - lo) / 2;
+        if (xadj[mid] >= slot) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kTileThreads) within_scatter_kernel(
+    const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj, const int32_t* __restrict__ ew, int32_t n,
+    int64_t S, const int32_t* __restrict__ blk, const int64_t* __restrict__ tbase, int64_t* __restrict__ oxadj,
+    int32_t* __restrict__ oadj, int32_t* __restrict__ oew) {
+    __shared__ int32_t owner[kTile];
+    __shared__ int32_t pre[kTile];
+    __shared__ int32_t s_w[kTileThreads / kWave];
+    __shared__ int32_t s_u0;
+    const int tid = threadIdx.x;
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kTile;
+    const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
+    if (tid == 0) s_u0 = first_row_from(xadj, n, i0);
+    tile_owners(xadj, n, i0, i1, owner);  // synchronises
+    // kTilePer consecutive slots per thread
+    uint32_t keep = 0;
+    int32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < kTilePer; ++j) {
+        const int idx = tid * kTilePer + j;
+        const int64_t i = i0 + idx;
+        if (i < i1 && blk[owner[idx]] == blk[adj[i]]) {
+            keep |= 1u << j;
+            ++c;
+        }
+    }
+    // exclusive prefix of c over the workgroup
+    int32_t incl = c;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int32_t t = __shfl_up(incl, o, 64);
+        if (lane_id() >= o) incl += t;
+    }
+    if (lane_id() == kWave - 1) s_w[tid / kWave] = incl;
+    __syncthreads();
+    int32_t run = incl - c;
+    for (int w = 0; w < tid / kWave; ++w) run += s_w[w];
+    const int64_t base = tbase[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < kTilePer; ++j) {
+        const int idx = tid * kTilePer + j;
+        pre[idx] = run;
+        if (keep >> j & 1u) {
+            const int64_t i = i0 + idx;
+            oadj[base + run] = adj[i];
+            if (oew) oew[base + run] = ew[i];
+            ++run;
+        }
+    }
+    __syncthreads();
+    for (int64_t u = static_cast<int64_t>(s_u0) + tid; u < n && xadj[u] < i1; u += kTileThreads)
+        oxadj[u] = base + pre[xadj[u] - i0];
+}
+
+__global__ void inherit_blocks_kernel(int32_t n, const int32_t* __restrict__ C, const int32_t* __restrict__ blk,
+                                      int32_t* __restrict__ cblk) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v < n && C[v] >= 0) cblk[C[v]] = blk[v];
+}
+
+// rows starting at S (empty tail rows, and the end offset)
+__global__ void within_tail_kernel(const int64_t* __restrict__ xadj, int32_t n, int64_t S,
+                                   const int64_t* __restrict__ total, int64_t* __restrict__ oxadj) {
+    const int64_t u = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (u <= n && xadj[u] >= S) oxadj[u] = *total;
+}
+
+}  // namespace
+
+void within_blocks(const DevGraph& g, const int32_t* blk, OwnedDevGraph& out, hipStream_t s) {
+    ProfScope ps("within_blocks", 24.0 * static_cast<double>(g.S), s);
+    out.n = g.n;
+    out.xadj.alloc(static_cast<size_t>(g.n) + 1, s);
+    DBuf<int64_t> total(1, s);
+    int64_t St = 0;
+    const int64_t tiles = (g.S + kTile - 1) / kTile;
+    DBuf<int64_t> tbase;
+    if (g.S > 0) {
+        DBuf<int32_t> tcnt(tiles, s);
+        tbase.alloc(tiles, s);
+        within_count_kernel<<<static_cast<unsigned>(tiles), kTileThreads, 0, s>>>(g.xadj, g.adj, g.n, g.S, blk,
+                                                                                  tcnt.get());
+        LAUNCHCHK();
+        exclusive_scan_i32_to_i64(tcnt.get(), tbase.get(), tiles, total.get(), s);
+        HIPCHK(hipMemcpyAsync(&St, total.get(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    } else {
+        fill_i64(total.get(), 0, 1, s);
+    }
+    out.S = St;
+    out.adj.alloc(std::max<int64_t>(St, 1), s);
+    if (g.ew) out.ew.alloc(std::max<int64_t>(St, 1), s);
+    if (g.S > 0) {
+        within_scatter_kernel<<<static_cast<unsigned>(tiles), kTileThreads, 0, s>>>(
+            g.xadj, g.adj, g.ew, g.n, g.S, blk, tbase.get(), out.xadj.get(), out.adj.get(),
+            g.ew ? out.ew.get() : nullptr);
+        LAUNCHCHK();
+    }
+    within_tail_kernel<<<grid_for(static_cast<int64_t>(g.n) + 1, 256), 256, 0, s>>>(g.xadj, g.n, g.S, total.get(),
+                                                                                    out.xadj.get());
+    LAUNCHCHK();
+}
+
+void inherit_blocks(int32_t n, const int32_t* C, const int32_t* blk, int32_t* cblk, hipStream_t s) {
+    if (n == 0) return;
+    inherit_blocks_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, C, blk, cblk);
+    LAUNCHCHK();
+}
+
 void project_kept(int32_t n, const int32_t* C, const int32_t* coarse_part, int32_t* part, hipStream_t s) {
     if (n == 0) return;
     project_kept_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, C, coarse_part, part);

@@ -81,6 +81,15 @@ void compact_members(const DevGraph& src, const std::vector<int32_t>& onb, const
 // C[v] += delta[gid[v]], or -1 where delta is INT_MIN (graph dropped).
 void remap_members(int32_t n, const int32_t* gid, const std::vector<int32_t>& delta, int32_t* C, hipStream_t s);
 // part[v] = coarse_part[C[v]] where C[v] >= 0.
+// The subgraph of the slots u->v with blk[u] == blk[v], slot order kept
+// (clustering inside the blocks of a partition, Section 4.5).  out.vw is left
+// empty: the caller pairs out's view with g.vw.
+void within_blocks(const DevGraph& g, const int32_t* blk, OwnedDevGraph& out, hipStream_t s);
+
+// cblk[C[v]] = blk[v] for every v with C[v] >= 0 (a coarse node lies in the
+// block of its members).
+void inherit_blocks(int32_t n, const int32_t* C, const int32_t* blk, int32_t* cblk, hipStream_t s);
+
 void project_kept(int32_t n, const int32_t* C, const int32_t* coarse_part, int32_t* part, hipStream_t s);
 // part[v] += sign * add[gid[v]] (add: device array indexed by graph).
 void shift_by_graph(int32_t n, const int32_t* gid, const int32_t* add, int32_t sign, int32_t* part, hipStream_t s);

@@ -3,7 +3,8 @@ on the seeded benchmark workloads, for GPU parity tests at sizes where the
 oracle takes too long to run inside a test.
 
 Calls only the oracle and the input generators:
-    python tests/golden/make_oracle_digests.py
+    python tests/golden/make_oracle_digests.py          # workloads not yet stored
+    python tests/golden/make_oracle_digests.py --all    # every workload
 """
 import hashlib
 import json
@@ -27,6 +28,9 @@ WORKLOADS = {
     # R-MAT scale 20, edge factor 16, (0.57, 0.19, 0.19, 0.05); full multilevel; k=16
     "rmat20_ef16_k16": dict(gen=("rmat", dict(scale=20, edge_factor=16, seed=1)), k=16, eps=0.03, seed=1,
                             opts=dict()),
+    # the same with two multilevel cycles (Section 4.5, iterated V-cycles)
+    "rmat20_ef16_k16_vcycles2": dict(gen=("rmat", dict(scale=20, edge_factor=16, seed=1)), k=16, eps=0.03,
+                                     seed=1, opts=dict(vcycles=2)),
 }
 
 
@@ -40,8 +44,14 @@ def digest(a):
 
 
 def main():
+    path = os.path.join(HERE, "oracle_digests.json")
     out = {"note": "Digests of the oracle's output; regenerate with this script.", "workloads": {}}
+    if "--all" not in sys.argv and os.path.exists(path):
+        with open(path) as f:
+            out = json.load(f)
     for name, w in WORKLOADS.items():
+        if name in out["workloads"]:
+            continue
         g = make_graph(w["gen"])
         t = time.time()
         r = oracle.partition(g, w["k"], w["eps"], w["seed"], **w["opts"])
@@ -55,7 +65,7 @@ def main():
             "level_n": r["level_n"], "level_S": [int(x) for x in r["level_S"]], "visits": r["visits"],
             "cluster_rounds": r["cluster_rounds"], "refine_rounds": r["refine_rounds"],
         }
-    with open(os.path.join(HERE, "oracle_digests.json"), "w") as f:
+    with open(path, "w") as f:
         json.dump(out, f, indent=1)
 
 
