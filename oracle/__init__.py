@@ -47,7 +47,7 @@ class Options(ctypes.Structure):
     _fields_ = [("coarsen_rounds", ctypes.c_int32), ("refine_rounds", ctypes.c_int32),
                 ("subrounds", ctypes.c_int32), ("cluster_divisor", ctypes.c_int32),
                 ("coarsest_nodes", ctypes.c_int32), ("max_levels", ctypes.c_int32),
-                ("vcycles", ctypes.c_int32)]
+                ("vcycles", ctypes.c_int32), ("degree_order", ctypes.c_int32)]
 
 
 _MAXL = 64
@@ -82,6 +82,7 @@ def _load():
             "orc_subround_within": (i64, [G, vp, i32, i32, i32, i32, i32, u64, i64, vp, vp, vp, vp, vp]),
             "orc_cluster_within": (i32, [G, vp, i64, i32, i32, u64, i32, vp, vp, vp, vp]),
             "orc_cycle_seed": (u64, [u64, i32]),
+            "orc_degree_colors": (None, [G, vp, i32, vp]),
             "orc_refine": (i32, [G, i32, i64, i32, i32, u64, i32, vp, vp, vp, vp]),
             "orc_contract": (i32, [G, vp, vp, vp, vp, vp, vp, vp, vp]),
             "orc_project": (None, [i32, vp, vp, vp]),
@@ -152,6 +153,16 @@ def validate(g):
 
 def _block(block):
     return None if block is None else np.ascontiguousarray(block, dtype=np.int32)
+
+
+def degree_colors(g, nsub=4, block=None):
+    """Sub-round of every node when clustering visits nodes by increasing
+    degree (Section 3.1, Section 4.1)."""
+    gv = _GraphView(g)
+    blk = _block(block)
+    col = np.empty(gv.n, dtype=np.int32)
+    _load().orc_degree_colors(gv.ref, _ptr(blk), nsub, col.ctypes.data)
+    return col
 
 
 def cycle_seed(seed, cycle):

@@ -335,6 +335,42 @@ int32_t orc_cluster_within(const orc_graph* g, const int32_t* block, int64_t U, 
     return 0;
 }
 
+/* Degree-ordered sub-rounds (Section 3.1: visiting nodes by increasing
+ * degree lets low-degree nodes settle first and improves quality and time;
+ * Section 4.1: used while coarsening only).  The nodes with at least one
+ * neighbour to look at are ranked by (degree, id), both ascending, and cut
+ * into nsub consecutive groups of equal size (group s: ranks r with
+ * floor(r * nsub / count) = s), group s forming sub-round s.  The degree
+ * counts the neighbours the node looks at (same-block ones with a block
+ * array).  Nodes with none never move and are put in sub-round 0. */
+typedef struct { int64_t deg; int32_t v; } deg_node;
+
+static int cmp_deg(const void* x, const void* y) {
+    const deg_node* p = (const deg_node*)x;
+    const deg_node* q = (const deg_node*)y;
+    if (p->deg != q->deg) return p->deg < q->deg ? -1 : 1;
+    return (p->v > q->v) - (p->v < q->v);
+}
+
+void orc_degree_colors(const orc_graph* g, const int32_t* block, int32_t nsub, int32_t* color) {
+    int32_t n = g->n;
+    deg_node* D = (deg_node*)malloc((size_t)(n > 0 ? n : 1) * sizeof(deg_node));
+    int64_t cnt = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        int64_t d = 0;
+        for (int64_t i = g->xadj[v]; i < g->xadj[v + 1]; ++i) d += in_block(block, v, g->adjncy[i]);
+        color[v] = 0;
+        if (d > 0) {
+            D[cnt].deg = d;
+            D[cnt].v = v;
+            ++cnt;
+        }
+    }
+    qsort(D, (size_t)cnt, sizeof(deg_node), cmp_deg);
+    for (int64_t r = 0; r < cnt; ++r) color[D[r].v] = (int32_t)(r * nsub / cnt);
+    free(D);
+}
+
 int32_t orc_cluster(const orc_graph* g, int64_t U, int32_t rounds, int32_t nsub, uint64_t seed,
                     int32_t level, const int32_t* color_override, int32_t* labels, int32_t* rounds_run,
                     int64_t* visits) {
@@ -511,6 +547,7 @@ void orc_default_options(orc_options* o) {
     o->coarsest_nodes = 10000;
     o->max_levels = ORC_MAX_LEVELS;
     o->vcycles = 1;
+    o->degree_order = 0;
 }
 
 typedef struct {
@@ -596,8 +633,14 @@ int32_t orc_partition(const orc_graph* g, int32_t k, double eps, uint64_t seed, 
             int64_t U = cmax > W ? cmax : W;
             int32_t* labels = (int32_t*)malloc((size_t)n * sizeof(int32_t));
             int32_t rr = 0;
-            orc_cluster_within(&G, L[lev].blk, U, opt.coarsen_rounds, opt.subrounds, sd, lev, NULL, labels, &rr,
+            int32_t* dcol = NULL;
+            if (opt.degree_order) {
+                dcol = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+                orc_degree_colors(&G, L[lev].blk, opt.subrounds, dcol);
+            }
+            orc_cluster_within(&G, L[lev].blk, U, opt.coarsen_rounds, opt.subrounds, sd, lev, dcol, labels, &rr,
                                &S->visits);
+            free(dcol);
             S->cluster_rounds[lev] = rr;
             int64_t Sl = G.xadj[n];
             level_t nx;

@@ -112,7 +112,12 @@ typedef struct {
     int32_t coarsest_nodes;  /* 10000 */
     int32_t max_levels;      /* 64 */
     int32_t vcycles;         /* 1: multilevel cycles, each after the first inside the previous blocks */
+    int32_t degree_order;    /* 0; 1: clustering sub-rounds by increasing degree (orc_degree_colors) */
 } orc_options;
+
+/* Sub-round of every node for degree-ordered clustering (Section 3.1,
+ * Section 4.1); block may be NULL. */
+void orc_degree_colors(const orc_graph* g, const int32_t* block, int32_t nsub, int32_t* color);
 
 uint64_t orc_cycle_seed(uint64_t seed, int32_t cycle);
 

@@ -214,3 +214,10 @@ def test_handworked_clustering_inside_blocks(golden_dir):
     coarse_blk = np.zeros(cg["n"], dtype=np.int32)
     coarse_blk[C] = blk
     assert oracle.cut(cg, coarse_blk, 2)[0] == oracle.cut(g, blk, 2)[0] == ex["expected_coarse_cut"]
+
+
+def test_handworked_degree_order(golden_dir):
+    ex = _load(golden_dir, "handworked.json")["H_degree_order"]
+    g = synth.from_edges(ex["n"], [tuple(e) for e in ex["edges"]])
+    assert oracle.degree_colors(g, ex["nsub"]).tolist() == ex["expected_colors"]
+    assert oracle.degree_colors(g, ex["nsub"], block=ex["block"]).tolist() == ex["expected_colors_within_blocks"]

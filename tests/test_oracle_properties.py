@@ -429,6 +429,10 @@ def test_stall_rule_on_mostly_isolated_graph(seed):
 # ------------------------------------------ clustering inside blocks, V-cycles
 # (Section 4.5, Iterated Multilevel Schemes)
 
+def ceil_div(a, b):
+    return -(-a // b)
+
+
 def py_block_conns(r, lab, blk, v):
     c = {}
     for u, w in r:
@@ -538,3 +542,67 @@ def test_vcycles_compose_from_single_operations(make, k):
         assert r["cut"] == py_cut(g, r["part"])
         assert np.array_equal(r["block_weights"], py_weights(g, r["part"], k))
         assert r["status"] == (1 if r["block_weights"].max() > oracle.lmax(int(vw(g).sum()), k, 0.03) else 0)
+
+
+# ------------------------------------------------- degree-ordered sub-rounds
+# (Section 3.1, Section 4.1)
+
+@pytest.mark.parametrize("name,make", GRAPHS + [("rmat_iso", lambda: synth.rmat(10, 2, seed=8))])
+@pytest.mark.parametrize("nsub", [1, 2, 4, 7])
+@pytest.mark.parametrize("blocked", [False, True])
+def test_degree_colors_partition_by_degree(name, make, nsub, blocked):
+    g = make()
+    n = g["n"]
+    blk = np.random.default_rng(2).integers(0, 3, size=n).astype(np.int32) if blocked else None
+    col = oracle.degree_colors(g, nsub, block=blk)
+    deg = np.array([sum(1 for u, _ in r if blk is None or blk[u] == blk[v]) for v, r in enumerate(rows(g))])
+    pos = np.flatnonzero(deg > 0)
+    assert np.all(col[deg == 0] == 0)
+    cnt = len(pos)
+    for s in range(nsub):
+        members = pos[col[pos] == s]
+        # ranks r with floor(r * nsub / cnt) == s: r in [ceil(s cnt / nsub), ceil((s+1) cnt / nsub))
+        assert len(members) == ceil_div((s + 1) * cnt, nsub) - ceil_div(s * cnt, nsub)
+    # every (degree, id) of a sub-round precedes every one of the next
+    for s in range(nsub - 1):
+        a = [(deg[v], v) for v in pos if col[v] == s]
+        b = [(deg[v], v) for v in pos if col[v] == s + 1]
+        if a and b:
+            assert max(a) < min(b)
+
+
+def py_multilevel(g, k, eps, seed, coarsest, degree_order):
+    """The first multilevel cycle composed from the oracle's single operations."""
+    cV = int(vw(g).sum())
+    Lmax = oracle.lmax(cV, k, eps)
+    W = cV // (18 * k)
+    levels, Cs = [g], []
+    while levels[-1]["n"] > coarsest:
+        G = levels[-1]
+        U = max(int(vw(G).max()), W)
+        col = oracle.degree_colors(G, 4) if degree_order else None
+        lab, _, _ = oracle.cluster(G, U, rounds=10, seed=seed, level=len(Cs), color_override=col)
+        C, cg = oracle.contract(G, lab)
+        if cg["n"] >= G["n"]:
+            break
+        Cs.append(C)
+        levels.append(cg)
+        if 20 * cg["n"] > 19 * G["n"]:
+            break
+    part = oracle.initial_partition(levels[-1], k, -(-cV // k))
+    for lev in range(len(levels) - 1, -1, -1):
+        if lev < len(levels) - 1:
+            part = oracle.project(Cs[lev], part)
+        part, _, _ = oracle.refine(levels[lev], k, Lmax, part, rounds=10, seed=seed, level=lev)
+    return part
+
+
+@pytest.mark.parametrize("make,k", [(lambda: synth.ba(3000, 4, seed=2), 4),
+                                    (lambda: synth.rmat(12, 8, seed=3, weighted=True), 8)])
+def test_degree_order_composes_from_single_operations(make, k):
+    g = make()
+    r = oracle.partition(g, k, 0.03, 5, coarsest_nodes=200, degree_order=1)
+    assert np.array_equal(py_multilevel(g, k, 0.03, 5, 200, True), r["part"])
+    plain = oracle.partition(g, k, 0.03, 5, coarsest_nodes=200)
+    assert np.array_equal(py_multilevel(g, k, 0.03, 5, 200, False), plain["part"])
+    assert r["cut"] == py_cut(g, r["part"])
