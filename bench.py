@@ -234,6 +234,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", dest="variants", action="store_false",
+                    help="skip the V-cycle / degree-order runs after the timed steps")
     ap.add_argument("--copy-calib", type=int, default=0, help="bytes for a plain copy kernel (counter scaling)")
     ap.add_argument("--batch-graphs", type=int, default=512, help="graphs in the batched-vs-plain comparison (0: skip)")
     ap.add_argument("--batch-log2", type=int, nargs=2, default=[10, 18], help="log2 range of n in the batch")
@@ -327,6 +329,22 @@ def main():
         "lp_eval_GB_per_step": round(lp_gb, 3),
         "roofline": roofline, "kernels": kernels,
     }
+    if args.variants:
+        # the paper's quality levers on the same workload, one timed run each
+        var = {}
+        for vname, kw in (("vcycles2", dict(vcycles=2)), ("degree_order", dict(degree_order=1)),
+                          ("degree_order_vcycles2", dict(degree_order=1, vcycles=2))):
+            vo = sc.default_options(**w["opts"], **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            q = sc.partition_dev(d, w["k"], w["eps"], w["seed"], part=part, stream=stream, opts=vo)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1000.0
+            var[vname] = {"ms": round(ms, 3), "cut": q["cut"], "cut_vs_default": round(q["cut"] / r["cut"], 5),
+                          "status": q["status"], "edge_visits": q["stats"]["visits"],
+                          "max_block_weight": int(np.max(q["block_weights"]))}
+            log("variant %s: %.1f ms cut=%d (%.4f of the default cut)" % (vname, ms, q["cut"], q["cut"] / r["cut"]))
+        out["variants"] = var
     if args.batch_graphs > 0:
         out["batched"] = batch_comparison(args.batch_graphs, 0, args.batch_log2[0], args.batch_log2[1])
     if args.serve_requests > 0:

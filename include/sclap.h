@@ -105,6 +105,13 @@ typedef struct {
                                  starts refinement from that result on its coarsest graph; cycle c
                                  uses the seed H(seed, 4, c) for c >= 1.  The last result is
                                  returned.  Default 1. */
+    int32_t degree_order;     /* 1: clustering visits nodes by increasing degree (Section 3.1;
+                                 Section 4.1, coarsening only): the nodes with neighbours are ranked
+                                 by (degree, id) and cut into `subrounds` equal consecutive groups,
+                                 group s forming sub-round s (degree-0 nodes: sub-round 0); the
+                                 degree counts the neighbours looked at.  Used by sclap_cluster*
+                                 when color_override is NULL, and by every multilevel entry point.
+                                 0 (default): hash colours. */
 } sclap_options;
 
 #define SCLAP_MAX_LEVELS 64

@@ -66,7 +66,8 @@ class Options(ctypes.Structure):
                 ("lane_max_degree", ctypes.c_int32), ("wave_max_degree", ctypes.c_int32),
                 ("block_max_degree", ctypes.c_int32), ("hub_part_limit", ctypes.c_int32),
                 ("hub_region_cap", ctypes.c_int32), ("select_small_max", ctypes.c_int32),
-                ("skip_quiet", ctypes.c_int32), ("vcycles", ctypes.c_int32)]
+                ("skip_quiet", ctypes.c_int32), ("vcycles", ctypes.c_int32),
+                ("degree_order", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):

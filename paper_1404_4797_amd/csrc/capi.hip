@@ -158,6 +158,12 @@ int cluster_impl(const DevGraph& g, int64_t U, int32_t rounds, uint64_t seed, in
         gc = inside.view();
         gc.vw = g.vw;
     }
+    DBuf<int32_t> dcol;
+    if (o.degree_order && !color_dev && g.n > 0) {
+        dcol.alloc(g.n, s);
+        degree_colors(gc, 1, nullptr, nullptr, nullptr, o.nsub, dcol.get(), s);
+        color_dev = dcol.get();
+    }
     const LPResult r = run_lp(gc, kCluster, level, seed, o.nsub, rounds, U, labels, w.get(), g.n, color_dev, o.tune, s);
     HIPCHK(hipStreamSynchronize(s));
     if (rounds_run) *rounds_run = r.rounds_run;

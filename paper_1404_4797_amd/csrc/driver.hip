@@ -42,6 +42,7 @@ Opts resolve(const sclap_options* o) {
     if (o->select_small_max > 0) r.tune.select_small_max = o->select_small_max;
     r.tune.skip_quiet = o->skip_quiet < 0 ? -1 : (o->skip_quiet > 0 ? 1 : 0);
     r.vcycles = o->vcycles == 0 ? 1 : o->vcycles;
+    r.degree_order = o->degree_order != 0 ? 1 : 0;
     if (r.vcycles < 1 || r.vcycles > 64) fail(SCLAP_ERR_INVALID, "vcycles must be in 1..64");
     if (r.coarsen_rounds < 0 || r.refine_rounds < 0) fail(SCLAP_ERR_INVALID, "round counts must be >= 0");
     if (r.nsub < 1 || r.nsub > 16) fail(SCLAP_ERR_INVALID, "subrounds must be in 1..16");
@@ -499,9 +500,14 @@ void multilevel_cycle(const DevGraph& g0, int32_t k, int64_t cV, int64_t cmax0, 
             Gc = inside.view();
             Gc.vw = G.vw;
         }
+        DBuf<int32_t> dcol;
+        if (o.degree_order) {
+            dcol.alloc(n, s);
+            degree_colors(Gc, 1, nullptr, nullptr, nullptr, o.nsub, dcol.get(), s);
+        }
         auto t_lp = Clock::now();
         const LPResult r = run_lp(Gc, kCluster, lev, seed, o.nsub, o.coarsen_rounds, U, labels.get(), w.get(), n,
-                                  nullptr, o.tune, s);
+                                  dcol.get(), o.tune, s);
         lp_ms += ms_since(t_lp);
         inside = OwnedDevGraph();
         st->visits += r.visits;
@@ -843,9 +849,19 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
                 Gc = inside.view();
                 Gc.vw = B.g.vw;
             }
+            DBuf<int32_t> dcol;
+            if (o.degree_order) {
+                std::vector<int32_t> gcnt(G, 0);
+                for (int32_t m = 0; m < M; ++m) gcnt[B.ids[m]] = B.nb[m + 1] - B.nb[m];
+                DBuf<int32_t> d_gcnt(G, s);
+                upload_vec(d_gcnt, gcnt, s);
+                dcol.alloc(n, s);
+                degree_colors(Gc, G, B.gid.get(), d_nbase.get(), d_gcnt.get(), o.nsub, dcol.get(), s);
+                HIPCHK(hipStreamSynchronize(s));  // gcnt is read by the upload above
+            }
             auto t_lp = Clock::now();
-            const LPResult r =
-                run_lp(Gc, kCluster, lev, 0, o.nsub, o.coarsen_rounds, 0, labels.get(), wl.get(), n, nullptr, o.tune, s, &mg);
+            const LPResult r = run_lp(Gc, kCluster, lev, 0, o.nsub, o.coarsen_rounds, 0, labels.get(), wl.get(), n,
+                                      dcol.get(), o.tune, s, &mg);
             lp_ms += ms_since(t_lp);
             inside = OwnedDevGraph();
             st->visits += r.visits;

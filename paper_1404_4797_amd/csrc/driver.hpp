@@ -20,6 +20,7 @@ struct Opts {
     int32_t validate = 1;
     const int32_t* color_override = nullptr;
     int32_t vcycles = 1;
+    int32_t degree_order = 0;
     LPTuning tune;
 };
 

@@ -685,6 +685,107 @@ void inherit_blocks(int32_t n, const int32_t* C, const int32_t* blk, int32_t* cb
     LAUNCHCHK();
 }
 
+// ------------------------------------------------- degree-ordered rounds
+//
+// Sub-rounds by increasing degree (Section 3.1; Section 4.1, while
+// coarsening): per graph, the nodes with at least one neighbour ranked by
+// (degree, id) and cut into nsub equal consecutive groups; degree-0 nodes
+// never move and go to sub-round 0.  One radix sort of (degree, id) keys;
+// in a batch a second, stable sort by graph groups each graph's nodes in its
+// own node range, in (degree, id) order.
+
+namespace {
+
+__global__ void degree_keys_kernel(int32_t n, const int64_t* __restrict__ xadj, int bn,
+                                   uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= n) return;
+    const uint64_t d = static_cast<uint64_t>(xadj[v + 1] - xadj[v]);
+    keys[v] = (d << bn) | static_cast<uint32_t>(v);
+    vals[v] = static_cast<uint32_t>(v);
+}
+
+__global__ void graph_keys_kernel(int32_t n, const uint32_t* __restrict__ vals, const int32_t* __restrict__ gid,
+                                  uint64_t* __restrict__ keys) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) keys[i] = static_cast<uint32_t>(gid[vals[i]]);
+}
+
+// n0[g] = number of degree-0 nodes of graph g (they lead its segment)
+__global__ void zero_run_kernel(int32_t n, const uint32_t* __restrict__ vals, const int64_t* __restrict__ xadj,
+                                const int32_t* __restrict__ gid, const int32_t* __restrict__ gbase,
+                                const int32_t* __restrict__ gcount, int32_t* __restrict__ n0) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int32_t v = static_cast<int32_t>(vals[i]);
+    if (xadj[v + 1] != xadj[v]) return;
+    const int32_t g = gid ? gid[v] : 0;
+    const int32_t end = gbase[g] + gcount[g];
+    bool last = i + 1 == end;
+    if (!last) {
+        const int32_t u = static_cast<int32_t>(vals[i + 1]);
+        last = xadj[u + 1] != xadj[u];
+    }
+    if (last) n0[g] = i + 1 - gbase[g];
+}
+
+__global__ void degree_color_kernel(int32_t n, const uint32_t* __restrict__ vals, const int64_t* __restrict__ xadj,
+                                    const int32_t* __restrict__ gid, const int32_t* __restrict__ gbase,
+                                    const int32_t* __restrict__ gcount, const int32_t* __restrict__ n0,
+                                    int32_t nsub, int32_t* __restrict__ color) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int32_t v = static_cast<int32_t>(vals[i]);
+    if (xadj[v + 1] == xadj[v]) {
+        color[v] = 0;
+        return;
+    }
+    const int32_t g = gid ? gid[v] : 0;
+    const int64_t r = static_cast<int64_t>(i) - gbase[g] - n0[g];
+    const int64_t cnt = static_cast<int64_t>(gcount[g]) - n0[g];
+    color[v] = static_cast<int32_t>(r * nsub / cnt);
+}
+
+}  // namespace
+
+void degree_colors(const DevGraph& g, int32_t G, const int32_t* gid, const int32_t* gbase, const int32_t* gcount,
+                   int32_t nsub, int32_t* color, hipStream_t s) {
+    const int32_t n = g.n;
+    if (n == 0) return;
+    ProfScope ps("degree_order", 0, s);
+    const int bn = std::max(1, bits_for(static_cast<uint64_t>(n - 1)));
+    const int bd = std::max(1, bits_for(static_cast<uint64_t>(std::max<int64_t>(g.S, 1))));
+    if (bn + bd > 64) fail(-1, "graph too large for degree-ordered sub-rounds");
+    DBuf<uint64_t> keys(n, s), ktmp(n, s);
+    DBuf<uint32_t> vals(n, s), vtmp(n, s);
+    degree_keys_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, g.xadj, bn, keys.get(), vals.get());
+    LAUNCHCHK();
+    RadixScratch rs;
+    radix_sort_pairs(keys.get(), vals.get(), ktmp.get(), vtmp.get(), n, 0, bn + bd, rs, s);
+    DBuf<int32_t> one_base, one_count;
+    if (gid) {
+        graph_keys_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, vals.get(), gid, keys.get());
+        LAUNCHCHK();
+        radix_sort_pairs(keys.get(), vals.get(), ktmp.get(), vtmp.get(), n, 0,
+                         std::max(1, bits_for(static_cast<uint64_t>(std::max(G - 1, 1)))), rs, s);
+    } else {
+        G = 1;
+        one_base.alloc(1, s);
+        one_count.alloc(1, s);
+        fill_i32(one_base.get(), 0, 1, s);
+        fill_i32(one_count.get(), n, 1, s);
+        gbase = one_base.get();
+        gcount = one_count.get();
+    }
+    DBuf<int32_t> n0(std::max(G, 1), s);
+    fill_i32(n0.get(), 0, std::max(G, 1), s);
+    zero_run_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, vals.get(), g.xadj, gid, gbase, gcount, n0.get());
+    LAUNCHCHK();
+    degree_color_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, vals.get(), g.xadj, gid, gbase, gcount, n0.get(), nsub,
+                                                         color);
+    LAUNCHCHK();
+}
+
 void project_kept(int32_t n, const int32_t* C, const int32_t* coarse_part, int32_t* part, hipStream_t s) {
     if (n == 0) return;
     project_kept_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, C, coarse_part, part);

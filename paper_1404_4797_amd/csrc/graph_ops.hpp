@@ -90,6 +90,15 @@ void within_blocks(const DevGraph& g, const int32_t* blk, OwnedDevGraph& out, hi
 // block of its members).
 void inherit_blocks(int32_t n, const int32_t* C, const int32_t* blk, int32_t* cblk, hipStream_t s);
 
+// Sub-round of every node for degree-ordered clustering (Section 3.1;
+// Section 4.1): per graph, nodes with neighbours ranked by (degree, id) and
+// cut into nsub equal groups; degree-0 nodes get 0.  Single graph: gid,
+// gbase and gcount null.  Batch: gid[n] is the graph of each node, and graph
+// gr's nodes are [gbase[gr], gbase[gr] + gcount[gr]) (device arrays of G
+// entries; graph ranges in ascending graph order).
+void degree_colors(const DevGraph& g, int32_t G, const int32_t* gid, const int32_t* gbase, const int32_t* gcount,
+                   int32_t nsub, int32_t* color, hipStream_t s);
+
 void project_kept(int32_t n, const int32_t* C, const int32_t* coarse_part, int32_t* part, hipStream_t s);
 // part[v] += sign * add[gid[v]] (add: device array indexed by graph).
 void shift_by_graph(int32_t n, const int32_t* gid, const int32_t* add, int32_t sign, int32_t* part, hipStream_t s);
