@@ -112,6 +112,8 @@ typedef struct {
                                  degree counts the neighbours looked at.  Used by sclap_cluster*
                                  when color_override is NULL, and by every multilevel entry point.
                                  0 (default): hash colours. */
+    int32_t contract_bucket_mean; /* tuning (never changes results; 0 = 1024): merged entries per
+                                     bucket when contraction merges very long coarse rows by buckets */
 } sclap_options;
 
 #define SCLAP_MAX_LEVELS 64
@@ -135,6 +137,15 @@ int sclap_default_options(sclap_options* opt);
 
 /* Message for the last non-zero status on this thread ("" if none). */
 const char* sclap_last_error(void);
+
+/*
+ * Device memory: the library keeps blocks it freed on a stream for reuse by
+ * later calls on that stream (at most a quarter of the device's memory).
+ * sclap_trim_memory returns every cached block of the current device to the
+ * device's memory pool; call it when the memory is needed elsewhere or before
+ * destroying a stream that was passed to _dev calls.  Returns 0.
+ */
+int sclap_trim_memory(void);
 
 /*
  * Input staging and validation (Section 2.1 problem statement): offsets

@@ -36,7 +36,7 @@ EXPORTS = [
     "sclap_partition", "sclap_partition_dev",
     "sclap_partition_batch", "sclap_partition_batch_dev",
     "sclap_server_create", "sclap_server_submit", "sclap_server_poll", "sclap_server_destroy",
-    "sclap_autotune_dev",
+    "sclap_autotune_dev", "sclap_trim_memory",
     "sclap_profile_begin", "sclap_profile_end",
 ]
 
@@ -67,7 +67,7 @@ class Options(ctypes.Structure):
                 ("block_max_degree", ctypes.c_int32), ("hub_part_limit", ctypes.c_int32),
                 ("hub_region_cap", ctypes.c_int32), ("select_small_max", ctypes.c_int32),
                 ("skip_quiet", ctypes.c_int32), ("vcycles", ctypes.c_int32),
-                ("degree_order", ctypes.c_int32)]
+                ("degree_order", ctypes.c_int32), ("contract_bucket_mean", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):
@@ -149,6 +149,7 @@ def load():
         "sclap_server_poll": (ctypes.c_int, [vp, u64, i32, vp, vp, vp, vp, ctypes.POINTER(RequestInfo)]),
         "sclap_server_destroy": (None, [vp]),
         "sclap_autotune_dev": (ctypes.c_int, [G, i32, O, vp]),
+        "sclap_trim_memory": (ctypes.c_int, []),
         "sclap_partition_batch_dev": (ctypes.c_int, [G, i32, vp, vp, vp, vp, O, vp, vp, vp, BST, vp]),
         "sclap_profile_begin": (ctypes.c_int, []),
         "sclap_profile_end": (ctypes.c_int, [ctypes.POINTER(KernelStat), i32, vp]),

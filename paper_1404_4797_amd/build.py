@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsclap.so")
-SOURCES = ["primitives.hip", "profile.hip", "lp.hip", "graph_ops.hip", "contract.hip", "driver.hip", "server.hip", "capi.hip"]
+SOURCES = ["alloc.hip", "primitives.hip", "profile.hip", "lp.hip", "graph_ops.hip", "contract.hip", "driver.hip", "server.hip", "capi.hip"]
 ARCH = os.environ.get("SCLAP_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
          # no packed-FP32 instructions anywhere in the device code

@@ -33,37 +33,7 @@ void hip_check(hipError_t e, const char* what, const char* file, int line) {
 
 // ------------------------------------------------------------ memory pool
 
-namespace {
-std::mutex g_pool_mu;
-bool g_pool_ready[256] = {};
 
-void ensure_pool() {
-    int dev = 0;
-    HIPCHK(hipGetDevice(&dev));
-    if (dev >= 0 && dev < 256 && g_pool_ready[dev]) return;
-    std::lock_guard<std::mutex> lk(g_pool_mu);
-    if (dev >= 0 && dev < 256 && g_pool_ready[dev]) return;
-    hipMemPool_t pool;
-    HIPCHK(hipDeviceGetDefaultMemPool(&pool, dev));
-    uint64_t keep = ~0ULL;  // keep freed blocks cached in the pool
-    HIPCHK(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
-    if (dev >= 0 && dev < 256) g_pool_ready[dev] = true;
-}
-}  // namespace
-
-void* dev_alloc(size_t bytes, hipStream_t s) {
-    ensure_pool();
-    void* p = nullptr;
-    const hipError_t e = hipMallocAsync(&p, bytes, s);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        fail(e == hipErrorOutOfMemory ? SCLAP_ERR_NO_MEMORY : SCLAP_ERR_HIP,
-             "device allocation of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
-    }
-    return p;
-}
-
-void dev_free(void* p, hipStream_t s) { (void)hipFreeAsync(p, s); }
 
 namespace {
 
@@ -212,6 +182,14 @@ int sclap_default_options(sclap_options* opt) {
 }
 
 const char* sclap_last_error(void) { return t_err.c_str(); }
+
+int sclap_trim_memory(void) {
+    return guarded([&] {
+        release_cached(nullptr, true);
+        HIPCHK(hipDeviceSynchronize());
+        return SCLAP_OK;
+    });
+}
 
 int64_t sclap_lmax(int64_t cV, int32_t k, double eps) {
     if (k < 1) return -1;

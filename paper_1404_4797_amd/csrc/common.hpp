@@ -26,11 +26,13 @@ void hip_check(hipError_t e, const char* what, const char* file, int line);
 
 // ------------------------------------------------------------ device memory
 
-// Stream-ordered allocation from the device's default memory pool, which is
-// configured to keep freed memory cached (no release to the driver between
-// calls), so repeated partitions do not pay for hipMalloc.
+// Stream-ordered device memory through a block cache (alloc.hip): a freed
+// block is reused by later allocations of its size class on the same stream.
 void* dev_alloc(size_t bytes, hipStream_t s);
-void dev_free(void* p, hipStream_t s);
+void dev_free(void* p, size_t bytes, hipStream_t s);
+// Returns the cached blocks of stream s (or of every stream of the current
+// device) to the device's memory pool.
+void release_cached(hipStream_t s, bool all_streams);
 
 template <typename T>
 struct DBuf {
@@ -58,7 +60,7 @@ struct DBuf {
         if (n > count || p == nullptr) alloc(n > 0 ? n : 1, st);
     }
     void release() {
-        if (p) dev_free(p, s);
+        if (p) dev_free(p, count * sizeof(T), s);
         p = nullptr;
         count = 0;
     }

@@ -502,6 +502,188 @@ __global__ void __launch_bounds__(256) block_hash_rows_kernel(const int32_t* __r
     }
 }
 
+
+// Unsorted merge of long rows after the chunk merge, by buckets: the merged
+// chunk entries of long row l are spread over P_l = ceil(m_l / kBucketMean)
+// buckets by a hash of the neighbour id (so equal ids meet in one bucket),
+// scattered bucket by bucket into a staging array, merged per bucket in an
+// LDS table by one workgroup, and copied back into the row.  Every step
+// streams the entries once; nothing probes a table in HBM.  A bucket whose
+// distinct neighbours do not fit its LDS table raises a flag, and the caller
+// then merges the long rows through per-row HBM tables instead.
+constexpr int kBucketMean = 1024;   // merged entries per bucket on average (default)
+constexpr int kBucketTable = 4096;  // LDS table slots of one bucket merge
+constexpr int kBucketLds = 4096;    // rows with up to this many buckets count and reserve in LDS
+
+__device__ __forceinline__ uint32_t bucket_of(int32_t x, uint32_t P) {
+    const uint32_t h = slot_hash(static_cast<uint32_t>(x) ^ 0x5BD1E995u);  // independent of the table slot
+    return static_cast<uint32_t>((static_cast<uint64_t>(h) * P) >> 32);
+}
+
+__global__ void long_bucket_counts_kernel(uint32_t nl, const int64_t* __restrict__ loff, int32_t mean,
+                                          int32_t* __restrict__ nbk) {
+    const uint32_t l = blockIdx.x * 256 + threadIdx.x;
+    if (l >= nl) return;
+    const int64_t m = loff[l + 1] - loff[l];
+    nbk[l] = static_cast<int32_t>(m > mean ? (m + mean - 1) / mean : 1);
+}
+
+// bucket q belongs to long row brow[q]
+__global__ void long_bucket_rows_kernel(uint32_t nl, const int64_t* __restrict__ bfirst, int32_t* __restrict__ brow) {
+    const uint32_t l = blockIdx.x;
+    if (l >= nl) return;
+    for (int64_t q = bfirst[l] + threadIdx.x; q < bfirst[l + 1]; q += 256) brow[q] = static_cast<int32_t>(l);
+}
+
+// Pass 1 (reserve = false): bucket sizes.  Pass 2 (reserve = true): every
+// entry to its bucket's range of the staging arrays; each workgroup reserves
+// its part of a bucket with one atomic per bucket it touches.
+template <bool kReserve>
+__global__ void __launch_bounds__(256) long_bucket_scatter_kernel(
+    const int32_t* __restrict__ list, const int32_t* __restrict__ crow, const int64_t* __restrict__ cfirst,
+    const int32_t* __restrict__ ccnt, const int64_t* __restrict__ rowoff, const int64_t* __restrict__ bfirst,
+    const int32_t* __restrict__ tk, const int32_t* __restrict__ tw, int32_t* __restrict__ bcount,
+    const int64_t* __restrict__ boff, int32_t* __restrict__ bfill, int32_t* __restrict__ sk,
+    int32_t* __restrict__ sw) {
+    __shared__ int32_t lcnt[kBucketLds];
+    __shared__ int32_t lbase[kBucketLds];
+    const int tid = threadIdx.x;
+    const int64_t c = blockIdx.x;
+    const int32_t l = crow[c];
+    const int64_t src = rowoff[list[l]] + (c - cfirst[l]) * kLongChunk;
+    const int32_t cnt = ccnt[c];
+    const int64_t b0 = bfirst[l];
+    const uint32_t P = static_cast<uint32_t>(bfirst[l + 1] - b0);
+    if (P > static_cast<uint32_t>(kBucketLds)) {  // very long row: global atomics per entry
+        for (int32_t j = tid; j < cnt; j += 256) {
+            const int64_t q = b0 + bucket_of(tk[src + j], P);
+            if (kReserve) {
+                const int64_t at = boff[q] + atomicAdd(&bfill[q], 1);
+                sk[at] = tk[src + j];
+                sw[at] = tw[src + j];
+            } else {
+                atomicAdd(&bcount[q], 1);
+            }
+        }
+        return;
+    }
+    for (uint32_t j = tid; j < P; j += 256) lcnt[j] = 0;
+    __syncthreads();
+    for (int32_t j = tid; j < cnt; j += 256) atomicAdd(&lcnt[bucket_of(tk[src + j], P)], 1);
+    __syncthreads();
+    for (uint32_t j = tid; j < P; j += 256) {
+        const int32_t k = lcnt[j];
+        if (k == 0) continue;
+        if (kReserve) {
+            lbase[j] = atomicAdd(&bfill[b0 + j], k);
+            lcnt[j] = 0;
+        } else {
+            atomicAdd(&bcount[b0 + j], k);
+        }
+    }
+    if (!kReserve) return;
+    __syncthreads();
+    for (int32_t j = tid; j < cnt; j += 256) {
+        const int32_t x = tk[src + j];
+        const uint32_t q = bucket_of(x, P);
+        const int64_t at = boff[b0 + q] + lbase[q] + atomicAdd(&lcnt[q], 1);
+        sk[at] = x;
+        sw[at] = tw[src + j];
+    }
+}
+
+// One workgroup per bucket: equal neighbours summed in an LDS table, the
+// distinct entries written back to the bucket's start, their number to qcnt.
+__global__ void __launch_bounds__(256) long_bucket_merge_kernel(const int64_t* __restrict__ boff,
+                                                                int32_t* __restrict__ sk, int32_t* __restrict__ sw,
+                                                                int32_t* __restrict__ qcnt,
+                                                                uint32_t* __restrict__ overflow) {
+    __shared__ int32_t keys[kBucketTable];
+    __shared__ int32_t sums[kBucketTable];
+    __shared__ int32_t s_w[4];
+    __shared__ int32_t s_full;
+    const int tid = threadIdx.x;
+    const int64_t q = blockIdx.x;
+    const int64_t b = boff[q];
+    const int32_t len = static_cast<int32_t>(boff[q + 1] - b);
+    for (int j = tid; j < kBucketTable; j += 256) {
+        keys[j] = -1;
+        sums[j] = 0;
+    }
+    if (tid == 0) s_full = 0;
+    __syncthreads();
+    for (int j = tid; j < len; j += 256) {
+        const int32_t x = sk[b + j];
+        uint32_t h = slot_hash(static_cast<uint32_t>(x)) & (kBucketTable - 1);
+        int probes = 0;
+        while (true) {
+            const int32_t prev = atomicCAS(&keys[h], -1, x);
+            if (prev == -1 || prev == x) break;
+            h = (h + 1) & (kBucketTable - 1);
+            if (++probes == kBucketTable) break;  // table full
+        }
+        if (probes == kBucketTable) {
+            s_full = 1;
+            break;
+        }
+        atomicAdd(&sums[h], sw[b + j]);  // partial sums never exceed the final coarse weight
+    }
+    __syncthreads();
+    if (s_full) {
+        if (tid == 0) atomicOr(overflow, 1u);
+        return;
+    }
+    // exclusive prefix of the occupied slots, kPer consecutive slots per thread
+    constexpr int kPer = kBucketTable / 256;
+    int32_t mine = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) mine += keys[tid * kPer + j] >= 0;
+    int32_t incl = mine;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int32_t t = __shfl_up(incl, o, 64);
+        if (lane_id() >= o) incl += t;
+    }
+    if (lane_id() == kWave - 1) s_w[tid / kWave] = incl;
+    __syncthreads();
+    int32_t pos = incl - mine;
+    for (int w = 0; w < tid / kWave; ++w) pos += s_w[w];
+    if (tid == 255) qcnt[q] = pos + mine;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int e = tid * kPer + j;
+        if (keys[e] < 0) continue;
+        sk[b + pos] = keys[e];
+        sw[b + pos] = sums[e];
+        ++pos;
+    }
+}
+
+__global__ void __launch_bounds__(256) long_bucket_write_kernel(const int32_t* __restrict__ list,
+                                                                const int32_t* __restrict__ brow,
+                                                                const int64_t* __restrict__ bfirst,
+                                                                const int64_t* __restrict__ boff,
+                                                                const int64_t* __restrict__ qoff,
+                                                                const int32_t* __restrict__ qcnt,
+                                                                const int64_t* __restrict__ rowoff,
+                                                                const int32_t* __restrict__ sk,
+                                                                const int32_t* __restrict__ sw,
+                                                                int32_t* __restrict__ tk, int32_t* __restrict__ tw,
+                                                                int32_t* __restrict__ dcnt) {
+    const int64_t q = blockIdx.x;
+    const int32_t l = brow[q];
+    const int32_t row = list[l];
+    const int64_t q0 = bfirst[l];
+    const int64_t dst = rowoff[row] + (qoff[q] - qoff[q0]);
+    const int64_t src = boff[q];
+    const int32_t cnt = qcnt[q];
+    for (int32_t j = threadIdx.x; j < cnt; j += 256) {
+        tk[dst + j] = sk[src + j];
+        tw[dst + j] = sw[src + j];
+    }
+    if (q == q0 && threadIdx.x == 0) dcnt[row] = static_cast<int32_t>(qoff[bfirst[l + 1]] - qoff[q0]);
+}
+
 // Unsorted merge of long rows after the chunk merge: one open-addressing
 // table in HBM per row (at least twice its merged entries, a power of two),
 // filled with atomics, then compacted chunk by chunk.
@@ -636,13 +818,63 @@ __global__ void __launch_bounds__(kTileThreads) row_copy_kernel(const int64_t* _
     }
 }
 
+// Long rows (unsorted) merged by buckets; false if a bucket's distinct
+// neighbours overflowed its LDS table (tk/tw untouched then).
+bool bucket_merge_long_rows(uint32_t nl, const int32_t* llist, int64_t nch, const int32_t* crow,
+                            const int64_t* cfirst, const int32_t* ccnt, const int64_t* loff, int64_t ml,
+                            const int64_t* rowoff, int32_t* tk, int32_t* tw, int32_t* dcnt, int32_t mean,
+                            hipStream_t s) {
+    ProfScope ps("contract_long_buckets", 40.0 * static_cast<double>(ml), s);
+    DBuf<int32_t> nbk(nl, s);
+    DBuf<int64_t> bfirst(static_cast<size_t>(nl) + 1, s), tot(2, s);
+    long_bucket_counts_kernel<<<grid_for(nl, 256), 256, 0, s>>>(nl, loff, mean, nbk.get());
+    LAUNCHCHK();
+    exclusive_scan_i32_to_i64(nbk.get(), bfirst.get(), nl, tot.get(), s);
+    int64_t NB = 0;
+    HIPCHK(hipMemcpyAsync(&NB, tot.get(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    fill_i64(bfirst.get() + nl, NB, 1, s);
+    DBuf<int32_t> brow(NB, s), bcount(NB, s), bfill(NB, s), qcnt(NB, s);
+    DBuf<int64_t> boff(static_cast<size_t>(NB) + 1, s), qoff(static_cast<size_t>(NB) + 1, s);
+    DBuf<int32_t> sk(std::max<int64_t>(ml, 1), s), sw(std::max<int64_t>(ml, 1), s);
+    DBuf<uint32_t> overflow(1, s);
+    long_bucket_rows_kernel<<<nl, 256, 0, s>>>(nl, bfirst.get(), brow.get());
+    LAUNCHCHK();
+    fill_i32(bcount.get(), 0, NB, s);
+    fill_i32(bfill.get(), 0, NB, s);
+    fill_u32(overflow.get(), 0, 1, s);
+    long_bucket_scatter_kernel<false><<<static_cast<unsigned>(nch), 256, 0, s>>>(
+        llist, crow, cfirst, ccnt, rowoff, bfirst.get(), tk, tw, bcount.get(), nullptr, nullptr, nullptr, nullptr);
+    LAUNCHCHK();
+    exclusive_scan_i32_to_i64(bcount.get(), boff.get(), NB, tot.get(), s);
+    HIPCHK(hipMemcpyAsync(boff.get() + NB, tot.get(), sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    long_bucket_scatter_kernel<true><<<static_cast<unsigned>(nch), 256, 0, s>>>(
+        llist, crow, cfirst, ccnt, rowoff, bfirst.get(), tk, tw, nullptr, boff.get(), bfill.get(), sk.get(),
+        sw.get());
+    LAUNCHCHK();
+    long_bucket_merge_kernel<<<static_cast<unsigned>(NB), 256, 0, s>>>(boff.get(), sk.get(), sw.get(), qcnt.get(),
+                                                                      overflow.get());
+    LAUNCHCHK();
+    uint32_t over = 0;
+    HIPCHK(hipMemcpyAsync(&over, overflow.get(), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (over) return false;
+    exclusive_scan_i32_to_i64(qcnt.get(), qoff.get(), NB, tot.get() + 1, s);
+    HIPCHK(hipMemcpyAsync(qoff.get() + NB, tot.get() + 1, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    long_bucket_write_kernel<<<static_cast<unsigned>(NB), 256, 0, s>>>(llist, brow.get(), bfirst.get(), boff.get(),
+                                                                      qoff.get(), qcnt.get(), rowoff, sk.get(),
+                                                                      sw.get(), tk, tw, dcnt);
+    LAUNCHCHK();
+    return true;
+}
+
 }  // namespace
 
 // Merges (and, if `sorted`, orders by neighbour id) every row r of the
 // entries tk/tw[rowoff[r] .. rowoff[r] + rowcnt[r]) in place; dcnt[r]
 // receives the number of distinct neighbours, written at the row's start.
 void merge_rows(int32_t nc, int64_t m, const int64_t* rowoff, const int32_t* rowcnt, int32_t* tk, int32_t* tw,
-                int32_t* dcnt, bool sorted, hipStream_t s) {
+                int32_t* dcnt, bool sorted, hipStream_t s, int32_t bucket_mean = 0) {
     DBuf<int32_t> lists(3 * static_cast<size_t>(nc), s);
     DBuf<uint32_t> counts(3, s);
     uint32_t hc[3] = {0, 0, 0};
@@ -699,7 +931,10 @@ void merge_rows(int32_t nc, int64_t m, const int64_t* rowoff, const int32_t* row
         long_offsets_kernel<<<grid_for(static_cast<int64_t>(nl) + 1, 256), 256, 0, s>>>(nl, cfirst.get(), coff.get(),
                                                                                          loff.get());
         LAUNCHCHK();
-        if (!sorted) {
+        if (!sorted && bucket_merge_long_rows(nl, llist, nch, crow.get(), cfirst.get(), ccnt.get(), loff.get(), ml,
+                                              rowoff, tk, tw, dcnt, bucket_mean > 0 ? bucket_mean : kBucketMean, s))
+            return;
+        if (!sorted) {  // a bucket overflowed: per-row tables in HBM
             DBuf<int64_t> tsz(nl, s), tch(nl, s), toff(static_cast<size_t>(nl) + 1, s),
                 tcfirst(static_cast<size_t>(nl) + 1, s);
             long_table_sizes_kernel<<<grid_for(nl, 256), 256, 0, s>>>(nl, loff.get(), tsz.get(), tch.get());
@@ -773,7 +1008,7 @@ void merge_rows(int32_t nc, int64_t m, const int64_t* rowoff, const int32_t* row
 
 
 void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGraph& coarse, hipStream_t s,
-              const int32_t* probe, int32_t nprobe, int32_t* probe_out, bool sorted) {
+              const int32_t* probe, int32_t nprobe, int32_t* probe_out, bool sorted, int32_t bucket_mean) {
     const int32_t n = g.n;
     if (n == 0) {
         coarse.n = 0;
@@ -849,7 +1084,7 @@ void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGrap
 
     // 3: merge (and order) every row
     DBuf<int32_t> dcnt(nc, s);
-    merge_rows(nc, m, rowoff.get(), rowcnt.get(), tk.get(), tw.get(), dcnt.get(), sorted, s);
+    merge_rows(nc, m, rowoff.get(), rowcnt.get(), tk.get(), tw.get(), dcnt.get(), sorted, s, bucket_mean);
 
     // 4: coarse offsets and the merged rows
     ProfScope ps_copy("contract_copy", 16.0 * static_cast<double>(m), s);

@@ -43,6 +43,8 @@ Opts resolve(const sclap_options* o) {
     r.tune.skip_quiet = o->skip_quiet < 0 ? -1 : (o->skip_quiet > 0 ? 1 : 0);
     r.vcycles = o->vcycles == 0 ? 1 : o->vcycles;
     r.degree_order = o->degree_order != 0 ? 1 : 0;
+    r.bucket_mean = o->contract_bucket_mean;
+    if (r.bucket_mean < 0) fail(SCLAP_ERR_INVALID, "contract_bucket_mean must be >= 0");
     if (r.vcycles < 1 || r.vcycles > 64) fail(SCLAP_ERR_INVALID, "vcycles must be in 1..64");
     if (r.coarsen_rounds < 0 || r.refine_rounds < 0) fail(SCLAP_ERR_INVALID, "round counts must be >= 0");
     if (r.nsub < 1 || r.nsub > 16) fail(SCLAP_ERR_INVALID, "subrounds must be in 1..16");
@@ -515,7 +517,7 @@ void multilevel_cycle(const DevGraph& g0, int32_t k, int64_t cV, int64_t cmax0, 
         w.release();
         DBuf<int32_t> C(n, s);
         Level nx;
-        contract(G, labels.get(), C.get(), nx.own, s, nullptr, 0, nullptr, false);
+        contract(G, labels.get(), C.get(), nx.own, s, nullptr, 0, nullptr, false, o.bucket_mean);
         if (nx.own.n >= n) break;  // no shrink: keep the current level as the coarsest
         DBuf<int32_t> cb;
         if (blk0) {
@@ -870,7 +872,7 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
             DBuf<int32_t> probe(M + 1, s), qb(M + 1, s), C(n, s);
             upload_vec(probe, B.nb, s);
             OwnedDevGraph coarse;
-            contract(B.g, labels.get(), C.get(), coarse, s, probe.get(), M + 1, qb.get(), false);
+            contract(B.g, labels.get(), C.get(), coarse, s, probe.get(), M + 1, qb.get(), false, o.bucket_mean);
             std::vector<int32_t> cb(M + 1);
             HIPCHK(hipMemcpyAsync(cb.data(), qb.get(), (M + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));

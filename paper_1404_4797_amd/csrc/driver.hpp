@@ -21,6 +21,7 @@ struct Opts {
     const int32_t* color_override = nullptr;
     int32_t vcycles = 1;
     int32_t degree_order = 0;
+    int32_t bucket_mean = 0;  // contraction tuning
     LPTuning tune;
 };
 

@@ -35,8 +35,11 @@ struct OwnedDevGraph {
 // base of label positions: probe_out[i] = number of used labels < probe[i].
 // sorted = false leaves each coarse row's distinct neighbours in an unspecified
 // order (label propagation and contraction do not depend on row order).
+// bucket_mean (tuning, 0 = default): merged entries per bucket when long rows
+// are merged unsorted.
 void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGraph& coarse, hipStream_t s,
-              const int32_t* probe = nullptr, int32_t nprobe = 0, int32_t* probe_out = nullptr, bool sorted = true);
+              const int32_t* probe = nullptr, int32_t nprobe = 0, int32_t* probe_out = nullptr, bool sorted = true,
+              int32_t bucket_mean = 0);
 
 // Orders every row of g by neighbour id (rows hold distinct neighbours).
 void sort_rows(OwnedDevGraph& g, hipStream_t s);

@@ -225,7 +225,11 @@ void worker(sclap_server* sv) {
         sv->cv_done.notify_all();
         sv->cv_work.notify_all();
     }
-    if (s) (void)hipStreamDestroy(s);
+    if (s) {
+        release_cached(s, false);  // this worker's cached blocks go back to the pool
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+    }
 }
 
 }  // namespace

@@ -197,6 +197,20 @@ def test_partition_parity(sc, gname, k):
     assert r["status"] == ref["status"]
 
 
+@pytest.mark.parametrize("gname", ["rmat_13", "star_9000", "ba_4k"])
+@pytest.mark.parametrize("mean", [1, 3, 1 << 30])
+def test_partition_contraction_bucket_paths(sc, gname, mean):
+    # long coarse rows merged by buckets: mean 1 gives rows with more buckets
+    # than the LDS counters hold (global atomics), mean 3 the LDS path, one
+    # bucket per row overflows the LDS table and falls back to HBM tables
+    g = GRAPHS[gname]()
+    say("partition", gname, "bucket mean", mean)
+    r = sc.partition_dev(dev(sc, g), 2, 0.03, 4, coarsest_nodes=300, contract_bucket_mean=mean)
+    ref = oracle.partition(g, 2, 0.03, 4, coarsest_nodes=300)
+    assert r["stats"]["level_n"] == ref["level_n"] and r["stats"]["level_S"] == ref["level_S"]
+    assert np.array_equal(r["part"].cpu().numpy(), ref["part"]) and r["cut"] == ref["cut"]
+
+
 def test_partition_host_entry_point(sc):
     g = synth.rmat(12, 16, seed=21, weighted=True)
     r = sc.partition(g, 8, 0.05, 2, coarsest_nodes=500)
