@@ -151,7 +151,10 @@ def batch_comparison(ngraphs, seed, log_lo, log_hi):
             "batched_graphs_per_s": ngraphs / t_batch, "plain_graphs_per_s": ngraphs / t_plain,
             "speedup": t_plain / t_batch, "identical_parts_and_cuts": same,
             "batched_edge_visits": r["stats"]["visits"], "plain_edge_visits": visits_plain,
-            "levels_max": r["stats"]["levels"]}
+            "levels_max": r["stats"]["levels"],
+            "batched_phase_ms": {"coarsen": round(r["stats"]["ms_coarsen"], 3),
+                                 "initial": round(r["stats"]["ms_initial"], 3),
+                                 "refine": round(r["stats"]["ms_refine"], 3)}}
 
 
 def serve_benchmark(nreq, log_lo, log_hi, fracs, plain_sample):
@@ -322,7 +325,8 @@ def main():
                    "subrounds": opts.subrounds, "max_levels": opts.max_levels},
         "partition_ms": ms_per_step, "edge_visits_per_step": visits, "cut": r["cut"],
         "max_block_weight": int(np.max(r["block_weights"])), "status": r["status"],
-        "levels": st["levels"], "level_n": st["level_n"], "cluster_rounds": st["cluster_rounds"],
+        "levels": st["levels"], "level_n": st["level_n"], "level_S": st["level_S"],
+        "cluster_rounds": st["cluster_rounds"],
         "refine_rounds": st["refine_rounds"],
         "phase_ms": {"coarsen": st["ms_coarsen"], "initial": st["ms_initial"], "refine": st["ms_refine"],
                      "lp": st["ms_lp"]},

@@ -229,6 +229,8 @@ int sclap_cut_dev(const sclap_graph* g, const int32_t* part, int32_t k, int64_t*
  * place of the paper's evolutionary algorithm (Section 4.5): greedy
  * breadth-first growing of blocks 0..k-2 up to T = ceil(c(V)/k) each, then
  * the remaining nodes in id order to the lightest block.  Host memory.
+ * Returns SCLAP_ERR_NOT_SYMMETRIC if a neighbour id is out of range or
+ * belongs to a node without neighbours.
  */
 int sclap_initial_partition(const sclap_graph* g, int32_t k, int32_t* part);
 
@@ -329,7 +331,9 @@ void sclap_server_destroy(sclap_server* sv);
  * bound from k as in sclap_partition) of the device graph g under each of a
  * few candidate sets of degree-bucket thresholds, which fix the LDS table
  * size each row gets, and writes the fastest set into opt's tuning fields
- * (lane_max_degree, wave_max_degree, block_max_degree).  g may be a batch
+ * (lane_max_degree, wave_max_degree, block_max_degree); each set is timed
+ * twice, and the library default is kept unless a set is at least 3 %
+ * faster.  g may be a batch
  * union; k is then a representative block count.  Semantic fields of opt are
  * read, not changed; results of later calls do not depend on the choice.
  */

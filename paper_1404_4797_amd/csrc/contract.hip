@@ -446,17 +446,19 @@ __global__ void long_tails_kernel(const int32_t* __restrict__ list, const int64_
 }
 
 // Unsorted merge of rows of 65..4096 entries: one workgroup per row sums
-// equal neighbours in an LDS table and writes the distinct entries (in table
-// order) to the row's start.
+// equal neighbours in an LDS table of kT >= 2 len slots and writes the
+// distinct entries (in table order) to the row's start.  Rows are grouped by
+// length so that short rows get small tables (less to clear, more workgroups
+// per CU).
+template <int kT>
 __global__ void __launch_bounds__(256) block_hash_rows_kernel(const int32_t* __restrict__ list,
                                                               const int64_t* __restrict__ rowoff,
                                                               const int32_t* __restrict__ rowcnt,
                                                               int32_t* __restrict__ tk, int32_t* __restrict__ tw,
                                                               int32_t* __restrict__ dcnt) {
-    constexpr int kT = 2 * kBlockRow;
     __shared__ int32_t keys[kT];
     __shared__ int32_t sums[kT];
-    __shared__ int32_t s_cnt[256];
+    __shared__ int32_t s_w[4];
     const int tid = threadIdx.x;
     const int32_t row = list[blockIdx.x];
     const int64_t b = rowoff[row];
@@ -477,22 +479,23 @@ __global__ void __launch_bounds__(256) block_hash_rows_kernel(const int32_t* __r
         atomicAdd(&sums[h], tw[b + j]);  // partial sums never exceed the final coarse weight
     }
     __syncthreads();
+    // exclusive prefix of the occupied slots, kPer consecutive slots per thread
     constexpr int kPer = kT / 256;
     int32_t mine = 0;
+#pragma unroll
     for (int j = 0; j < kPer; ++j) mine += keys[tid * kPer + j] >= 0;
-    s_cnt[tid] = mine;
-    __syncthreads();
-    if (tid == 0) {
-        int32_t run = 0;
-        for (int t = 0; t < 256; ++t) {
-            const int32_t x = s_cnt[t];
-            s_cnt[t] = run;
-            run += x;
-        }
-        dcnt[row] = run;
+    int32_t incl = mine;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int32_t t = __shfl_up(incl, o, 64);
+        if (lane_id() >= o) incl += t;
     }
+    if (lane_id() == kWave - 1) s_w[tid / kWave] = incl;
     __syncthreads();
-    int32_t pos = s_cnt[tid];
+    int32_t pos = incl - mine;
+    for (int w = 0; w < tid / kWave; ++w) pos += s_w[w];
+    if (tid == 255) dcnt[row] = pos + mine;
+#pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int e = tid * kPer + j;
         if (keys[e] < 0) continue;
@@ -502,6 +505,31 @@ __global__ void __launch_bounds__(256) block_hash_rows_kernel(const int32_t* __r
     }
 }
 
+// Splits the workgroup-row list by length: class c holds rows of at most
+// 256 << c entries (c = 0..4).
+__global__ void block_row_split_kernel(const int32_t* __restrict__ list, uint32_t count,
+                                       const int32_t* __restrict__ rowcnt, int32_t* __restrict__ out, uint32_t cap,
+                                       uint32_t* __restrict__ counts) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    int cls = -1;
+    int32_t r = 0;
+    if (i < count) {
+        r = list[i];
+        const int32_t len = rowcnt[r];
+        cls = 0;
+        while (cls < 4 && len > (256 << cls)) ++cls;
+    }
+    const uint64_t below = lanemask_lt();
+    for (int c = 0; c < 5; ++c) {
+        const uint64_t m = __ballot(cls == c);
+        if (!m) continue;
+        const int leader = __ffsll(static_cast<long long>(m)) - 1;
+        uint32_t base = 0;
+        if (lane_id() == leader) base = atomicAdd(&counts[c], static_cast<uint32_t>(__popcll(m)));
+        base = __shfl(base, leader, 64);
+        if (cls == c) out[static_cast<int64_t>(c) * cap + base + __popcll(m & below)] = r;
+    }
+}
 
 // Unsorted merge of long rows after the chunk merge, by buckets: the merged
 // chunk entries of long row l are spread over P_l = ceil(m_l / kBucketMean)
@@ -818,6 +846,27 @@ __global__ void __launch_bounds__(kTileThreads) row_copy_kernel(const int64_t* _
     }
 }
 
+// Unsorted merge of the workgroup rows, by length class (table of 512 <<
+// class slots).
+void hash_block_rows(const int32_t* list, uint32_t count, const int64_t* rowoff, const int32_t* rowcnt,
+                     int32_t* tk, int32_t* tw, int32_t* dcnt, hipStream_t s) {
+    DBuf<int32_t> sub(5 * static_cast<size_t>(count), s);
+    DBuf<uint32_t> cnt(5, s);
+    fill_u32(cnt.get(), 0, 5, s);
+    block_row_split_kernel<<<grid_for(count, 256), 256, 0, s>>>(list, count, rowcnt, sub.get(), count, cnt.get());
+    LAUNCHCHK();
+    uint32_t hc[5];
+    HIPCHK(hipMemcpyAsync(hc, cnt.get(), sizeof(hc), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const int32_t* l = sub.get();
+    if (hc[0]) block_hash_rows_kernel<512><<<hc[0], 256, 0, s>>>(l, rowoff, rowcnt, tk, tw, dcnt);
+    if (hc[1]) block_hash_rows_kernel<1024><<<hc[1], 256, 0, s>>>(l + count, rowoff, rowcnt, tk, tw, dcnt);
+    if (hc[2]) block_hash_rows_kernel<2048><<<hc[2], 256, 0, s>>>(l + 2 * count, rowoff, rowcnt, tk, tw, dcnt);
+    if (hc[3]) block_hash_rows_kernel<4096><<<hc[3], 256, 0, s>>>(l + 3 * count, rowoff, rowcnt, tk, tw, dcnt);
+    if (hc[4]) block_hash_rows_kernel<8192><<<hc[4], 256, 0, s>>>(l + 4 * count, rowoff, rowcnt, tk, tw, dcnt);
+    LAUNCHCHK();
+}
+
 // Long rows (unsorted) merged by buckets; false if a bucket's distinct
 // neighbours overflowed its LDS table (tk/tw untouched then).
 bool bucket_merge_long_rows(uint32_t nl, const int32_t* llist, int64_t nch, const int32_t* crow,
@@ -895,7 +944,7 @@ void merge_rows(int32_t nc, int64_t m, const int64_t* rowoff, const int32_t* row
             if (sorted)
                 block_rows_kernel<<<hc[1], 256, 0, s>>>(lists.get() + nc, rowoff, rowcnt, tk, tw, dcnt);
             else
-                block_hash_rows_kernel<<<hc[1], 256, 0, s>>>(lists.get() + nc, rowoff, rowcnt, tk, tw, dcnt);
+                hash_block_rows(lists.get() + nc, hc[1], rowoff, rowcnt, tk, tw, dcnt, s);
             LAUNCHCHK();
         }
     }

@@ -191,7 +191,7 @@ struct BlockHeap {
 // lightest block (lowest id on ties).  Weights fit 31 bits (c(V) <= 2^31-1).
 
 void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, const int32_t* vw, int32_t k,
-                            int64_t T, int32_t* part, bool rows_sorted) {
+                            int64_t T, int32_t* part, bool rows_sorted, bool adj_ranked) {
     auto T0 = Clock::now();
     const unsigned hw = std::thread::hardware_concurrency();
     const int32_t nthr = static_cast<int32_t>(std::min(16u, hw ? hw : 1u));
@@ -202,7 +202,6 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
         w0 = words * t / ntask;
         w1 = words * (t + 1) / ntask;
     };
-    std::vector<uint64_t> taken(words, 0);  // 1 bit per node, cache resident
     std::vector<int64_t> wb(static_cast<size_t>(k), 0);
     // seed candidates: nodes of positive degree, in id order; a bitmap with
     // per-word prefix counts gives a node's index among them in O(1)
@@ -248,32 +247,89 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
         const size_t i = static_cast<size_t>(v) >> 6;
         return rank_base[i] + __builtin_popcountll(has_deg[i] & ((1ULL << (v & 63)) - 1));
     };
+    const double t_pre = ms_since(T0);
     MinTree seeds(seed_w);
+    const double t_tree = ms_since(T0);
+    // Growth runs on the positive-degree nodes renumbered by rank (a
+    // monotone renumbering, so seeds and neighbours keep their order and the
+    // result is the same): its random accesses then hit arrays of the
+    // core's size instead of n.  Nodes of degree 0 are never reached.
+    const int32_t ncore = static_cast<int32_t>(seed_node.size());
+    const int64_t S = n > 0 ? xadj[n] : 0;
+    // the renumbered rows live in a per-thread buffer kept between calls:
+    // first-touch page faults of a fresh buffer cost more than the mapping
+    thread_local std::unique_ptr<int32_t[]> cadj_buf;
+    thread_local size_t cadj_cap = 0;
+    if (!adj_ranked && cadj_cap < static_cast<size_t>(std::max<int64_t>(S, 1))) {
+        cadj_buf.reset();
+        cadj_cap = static_cast<size_t>(std::max<int64_t>(S, 1));
+        cadj_buf.reset(new int32_t[cadj_cap]);  // every entry used is written below
+    }
+    const int32_t* const cadj = adj_ranked ? adj : cadj_buf.get();
+    int32_t* const cadj_w = cadj_buf.get();
+    std::vector<int64_t> cx(static_cast<size_t>(ncore) + 1);
+    std::vector<int32_t> cw32(static_cast<size_t>(ncore));
+    std::atomic<int> bad{0};
+    parallel_for(ntask, nthr, [&](int32_t t) {
+        const int32_t i0 = static_cast<int32_t>(static_cast<int64_t>(ncore) * t / ntask);
+        const int32_t i1 = static_cast<int32_t>(static_cast<int64_t>(ncore) * (t + 1) / ntask);
+        for (int32_t i = i0; i < i1; ++i) {
+            const int32_t v = seed_node[i];
+            cx[i] = xadj[v];
+            cw32[i] = static_cast<int32_t>(seed_w[i]);
+            if (adj_ranked) continue;
+            for (int64_t e = xadj[v]; e < xadj[v + 1]; ++e) {
+                const int32_t x = adj[e];
+                // a neighbour without neighbours of its own: the graph is not symmetric
+                if (x < 0 || x >= n || !((has_deg[static_cast<size_t>(x) >> 6] >> (x & 63)) & 1ULL)) {
+                    bad.store(1, std::memory_order_relaxed);
+                    cadj_w[e] = 0;
+                } else {
+                    cadj_w[e] = seed_rank(x);
+                }
+            }
+        }
+    });
+    if (bad.load()) fail(SCLAP_ERR_NOT_SYMMETRIC, "initial partition: a neighbour id is out of range or has no neighbours");
+    cx[ncore] = S;
     const double t_seed = ms_since(T0);
+    std::vector<uint64_t> ctaken((static_cast<size_t>(ncore) + 63) / 64, 0);
     std::vector<int32_t> nb;
-    std::vector<int32_t> fifo(static_cast<size_t>(seed_node.size()) + 1);  // every node is queued at most once
-    auto take = [&](int32_t v, int32_t b) {
-        part[v] = b;
-        taken[static_cast<size_t>(v) >> 6] |= 1ULL << (v & 63);
-        wb[b] += vw ? vw[v] : 1;
-        if ((has_deg[static_cast<size_t>(v) >> 6] >> (v & 63)) & 1ULL) seeds.erase(seed_rank(v));
-    };
+    // core nodes in the order blocks take them; each search's queue is the
+    // tail of this list that it appended (a node is queued at most once)
+    std::vector<int32_t> order(static_cast<size_t>(ncore) + 1);
+    std::vector<size_t> bstart(static_cast<size_t>(k) + 1, 0);
+    size_t ntaken = 0;
+    bool nonsym = false;
     for (int32_t b = 0; b + 1 < k; ++b) {
+        bstart[b] = ntaken;
+        int64_t wcur = wb[b];
+        auto take = [&](int32_t c) {
+            ctaken[static_cast<size_t>(c) >> 6] |= 1ULL << (c & 63);
+            wcur += cw32[c];
+            seeds.erase(c);
+            order[ntaken++] = c;
+        };
         int32_t from = 0;
         while (true) {
-            const int32_t si = seeds.first_le(from, T - wb[b]);
+            const int32_t si = seeds.first_le(from, T - wcur);
             if (si < 0) break;
-            const int32_t sd = seed_node[si];
-            take(sd, b);
-            size_t head = 0, tail = 0;
-            fifo[tail++] = sd;
-            while (head < tail) {
+            size_t head = ntaken;
+            take(si);
+            while (head < ntaken) {
                 // every node a search can reach has positive degree, so once
                 // the lightest such unassigned node does not fit, stop
-                if (seeds.min() > T - wb[b]) break;
-                const int32_t u = fifo[head++];
-                const int32_t* row = adj + xadj[u];
-                const int32_t* row_end = adj + xadj[u + 1];
+                if (seeds.min() > T - wcur) break;
+                const int32_t u = order[head++];
+                // rows are visited in queue order, far apart in memory: fetch
+                // the row a few places ahead in the queue early
+                if (head + 6 < ntaken) {
+                    const int64_t p = cx[order[head + 6]];
+                    __builtin_prefetch(cadj + p);
+                    __builtin_prefetch(cadj + p + 16);
+                }
+                const int32_t* row = cadj + cx[u];
+                const int32_t* row_end = cadj + cx[u + 1];
                 if (!rows_sorted && !std::is_sorted(row, row_end)) {
                     nb.assign(row, row_end);
                     std::sort(nb.begin(), nb.end());
@@ -282,15 +338,25 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
                 }
                 for (const int32_t* it = row; it != row_end; ++it) {
                     const int32_t x = *it;
-                    if ((taken[static_cast<size_t>(x) >> 6] >> (x & 63)) & 1ULL) continue;
-                    if (wb[b] + (vw ? vw[x] : 1) > T) continue;
-                    take(x, b);
-                    fifo[tail++] = x;
+                    if (static_cast<uint32_t>(x) >= static_cast<uint32_t>(ncore)) {  // -1 from core_ranks:
+                        nonsym = true;                                                // not symmetric
+                        continue;
+                    }
+                    if ((ctaken[static_cast<size_t>(x) >> 6] >> (x & 63)) & 1ULL) continue;
+                    if (wcur + cw32[x] > T) continue;
+                    take(x);
                 }
             }
             from = si + 1;
         }
+        wb[b] = wcur;
     }
+    bstart[k > 1 ? k - 1 : 0] = ntaken;
+    if (nonsym || bad.load()) fail(SCLAP_ERR_NOT_SYMMETRIC, "initial partition: a neighbour has no neighbours");
+    parallel_for(std::max(k - 1, 1), ntask == 1 ? 1 : nthr, [&](int32_t b) {  // small graphs: this thread
+        if (b + 1 >= k) return;
+        for (size_t i = bstart[b]; i < bstart[b + 1]; ++i) part[seed_node[order[i]]] = b;
+    });
     const double t_bfs = ms_since(T0);
     // unassigned nodes in id order (compacted per task, then concatenated)
     std::fill(task_cnt.begin(), task_cnt.end(), 0);
@@ -317,13 +383,21 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
     const double t_rest = ms_since(T0);
     auto cw = [&](int32_t v) -> int64_t { return vw ? vw[v] : 1; };
     std::vector<int32_t> ord(static_cast<size_t>(k));
+    BlockHeap heap(wb);  // kept in step with wb by the node-by-node path
+    bool heap_ok = true;
     size_t i = 0;
+    size_t nruns = 0, nheap = 0;
     while (i < nrest) {
         const int64_t c = cw(rest[i]);
         size_t j = i;
         while (j < nrest && cw(rest[j]) == c) ++j;
-        if (c == 0 || k > 4096) {  // node by node
-            BlockHeap heap(wb);
+        ++nruns;
+        if (c == 0 || k > 4096 || j - i < 4 * static_cast<size_t>(k)) {  // node by node
+            nheap += j - i;
+            if (!heap_ok) {
+                heap = BlockHeap(wb);
+                heap_ok = true;
+            }
             for (; i < j; ++i) {
                 const int32_t b = heap.top();
                 part[rest[i]] = b;
@@ -332,6 +406,7 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
             }
             continue;
         }
+        heap_ok = false;
         while (i < j) {
             for (int32_t b = 0; b < k; ++b) ord[b] = b;
             std::sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
@@ -355,7 +430,11 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
             // node t of the run goes to ord[t mod gsz]
             const int32_t* r0 = rest + i;
             auto deal = [&](size_t t0, size_t t1) {
-                for (size_t t = t0; t < t1; ++t) part[r0[t]] = ord[t % gsz];
+                size_t g = t0 % static_cast<size_t>(gsz);
+                for (size_t t = t0; t < t1; ++t) {
+                    part[r0[t]] = ord[g];
+                    if (++g == static_cast<size_t>(gsz)) g = 0;
+                }
             };
             const size_t nt = take < (1u << 20) ? 1 : static_cast<size_t>(nthr);
             if (nt <= 1) {
@@ -372,8 +451,11 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
     }
     static const bool trace = std::getenv("SCLAP_TRACE") != nullptr;
     if (trace)
-        fprintf(stderr, "[sclap] host partition phases: seeds %.1f, growth %.1f, rest %.1f, total %.1f ms\n", t_seed,
-                t_bfs - t_seed, t_rest - t_bfs, ms_since(T0));
+        fprintf(stderr,
+                "[sclap] host partition phases: scan %.1f, tree %.1f, core %.1f (%d nodes), growth %.1f, rest %.1f "
+                "(%zu nodes), dealing %.1f ms (%zu runs, %zu nodes one by one)\n",
+                t_pre, t_tree - t_pre, t_seed - t_tree, ncore, t_bfs - t_seed, t_rest - t_bfs, nrest,
+                ms_since(T0) - t_rest, nruns, nheap);
 }
 
 // ------------------------------------------------------------ multilevel
@@ -563,16 +645,21 @@ void multilevel_cycle(const DevGraph& g0, int32_t k, int64_t cV, int64_t cmax0, 
         int32_t* ha = reinterpret_cast<int32_t*>(stage.data() + bx);
         int32_t* hv = reinterpret_cast<int32_t*>(stage.data() + bx + ba);
         int32_t* hp = reinterpret_cast<int32_t*>(stage.data() + bx + ba + bn);
+        DBuf<int32_t> ranked;  // the adjacency renumbered to the positive-degree core
         if (nc > 0) {
             HIPCHK(hipMemcpyAsync(hx, Gc.xadj, bx, hipMemcpyDeviceToHost, s));
-            if (Gc.S > 0) HIPCHK(hipMemcpyAsync(ha, Gc.adj, Gc.S * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            if (Gc.S > 0) {
+                ranked.alloc(Gc.S, s);
+                core_ranks(Gc, ranked.get(), s);
+                HIPCHK(hipMemcpyAsync(ha, ranked.get(), Gc.S * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            }
             if (Gc.vw) HIPCHK(hipMemcpyAsync(hv, Gc.vw, nc * sizeof(int32_t), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
         }
         const double ms_d2h = ms_since(t_init);
         const int64_t T = (cV + k - 1) / k;
         // rows of contracted levels are sorted by construction
-        host_initial_partition(nc, hx, ha, Gc.vw ? hv : nullptr, k, T, hp, lev > 0);
+        host_initial_partition(nc, hx, ha, Gc.vw ? hv : nullptr, k, T, hp, lev > 0, true);
         const double ms_ip = ms_since(t_init) - ms_d2h;
         if (nc > 0) HIPCHK(hipMemcpyAsync(curp, hp, nc * sizeof(int32_t), hipMemcpyHostToDevice, s));
         HIPCHK(hipStreamSynchronize(s));  // the staging buffer is released below
@@ -659,29 +746,42 @@ LPTuning autotune(const DevGraph& g_in, int32_t k, const Opts& o, hipStream_t s)
     static const int32_t kCand[][3] = {{16, 256, 8192}, {16, 128, 8192}, {8, 256, 8192},
                                        {16, 256, 4096}, {16, 64, 2048},  {4, 128, 8192}};
     LPTuning best = o.tune;
-    double best_ms = 1e300;
+    double best_ms = 1e300, default_ms = 1e300;
     if (g.n == 0) return best;
     DBuf<int32_t> labels(g.n, s), w(g.n, s);
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    for (const auto& c : kCand) {
+    for (size_t ci = 0; ci < sizeof(kCand) / sizeof(kCand[0]); ++ci) {
         LPTuning t = o.tune;
-        t.lane_max = c[0];
-        t.wave_max = c[1];
-        t.block_max = c[2];
-        iota_u32(reinterpret_cast<uint32_t*>(labels.get()), g.n, s);
-        label_weights(g, labels.get(), w.get(), g.n, s);
-        HIPCHK(hipEventRecord(e0, s));
-        run_lp(g, kCluster, 0, 1, o.nsub, 1, U, labels.get(), w.get(), g.n, nullptr, t, s);
-        HIPCHK(hipEventRecord(e1, s));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        t.lane_max = kCand[ci][0];
+        t.wave_max = kCand[ci][1];
+        t.block_max = kCand[ci][2];
+        double ms = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {  // the faster of two timings
+            iota_u32(reinterpret_cast<uint32_t*>(labels.get()), g.n, s);
+            label_weights(g, labels.get(), w.get(), g.n, s);
+            HIPCHK(hipEventRecord(e0, s));
+            run_lp(g, kCluster, 0, 1, o.nsub, 1, U, labels.get(), w.get(), g.n, nullptr, t, s);
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipEventSynchronize(e1));
+            float f = 0;
+            HIPCHK(hipEventElapsedTime(&f, e0, e1));
+            ms = std::min(ms, static_cast<double>(f));
+        }
+        if (ci == 0) default_ms = ms;
         if (ms < best_ms) {
             best_ms = ms;
             best = t;
         }
+    }
+    // one round predicts a whole run only roughly: keep the default unless a
+    // candidate is clearly faster
+    if (best_ms > 0.97 * default_ms) {
+        best = o.tune;
+        best.lane_max = kCand[0][0];
+        best.wave_max = kCand[0][1];
+        best.block_max = kCand[0][2];
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

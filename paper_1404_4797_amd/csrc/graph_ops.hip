@@ -786,6 +786,33 @@ void degree_colors(const DevGraph& g, int32_t G, const int32_t* gid, const int32
     LAUNCHCHK();
 }
 
+// ------------------------------------------------------- core renumbering
+
+namespace {
+
+__global__ void has_degree_kernel(int32_t n, const int64_t* __restrict__ xadj, int32_t* __restrict__ flag) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v < n) flag[v] = xadj[v + 1] > xadj[v] ? 1 : 0;
+}
+
+__global__ void core_map_kernel(int64_t S, const int32_t* __restrict__ adj, const int32_t* __restrict__ flag,
+                                const int32_t* __restrict__ rank, int32_t* __restrict__ out) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (e < S) out[e] = flag[adj[e]] ? rank[adj[e]] : -1;  // -1: a neighbour without neighbours
+}
+
+}  // namespace
+
+void core_ranks(const DevGraph& g, int32_t* out, hipStream_t s) {
+    if (g.n == 0 || g.S == 0) return;
+    DBuf<int32_t> flag(g.n, s), rank(g.n, s), tot(1, s);
+    has_degree_kernel<<<grid_for(g.n, 256), 256, 0, s>>>(g.n, g.xadj, flag.get());
+    LAUNCHCHK();
+    exclusive_scan_i32(flag.get(), rank.get(), g.n, tot.get(), s);
+    core_map_kernel<<<grid_for(g.S, 256), 256, 0, s>>>(g.S, g.adj, flag.get(), rank.get(), out);
+    LAUNCHCHK();
+}
+
 void project_kept(int32_t n, const int32_t* C, const int32_t* coarse_part, int32_t* part, hipStream_t s) {
     if (n == 0) return;
     project_kept_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, C, coarse_part, part);

@@ -102,6 +102,11 @@ void inherit_blocks(int32_t n, const int32_t* C, const int32_t* blk, int32_t* cb
 void degree_colors(const DevGraph& g, int32_t G, const int32_t* gid, const int32_t* gbase, const int32_t* gcount,
                    int32_t nsub, int32_t* color, hipStream_t s);
 
+// out[e] = rank of adj[e] among the nodes of positive degree (ascending ids),
+// -1 if adj[e] has no neighbours (not symmetric): the adjacency of the
+// positive-degree core, renumbered (S entries).
+void core_ranks(const DevGraph& g, int32_t* out, hipStream_t s);
+
 void project_kept(int32_t n, const int32_t* C, const int32_t* coarse_part, int32_t* part, hipStream_t s);
 // part[v] += sign * add[gid[v]] (add: device array indexed by graph).
 void shift_by_graph(int32_t n, const int32_t* gid, const int32_t* add, int32_t sign, int32_t* part, hipStream_t s);
