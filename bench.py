@@ -157,6 +157,38 @@ def batch_comparison(ngraphs, seed, log_lo, log_hi):
                                  "refine": round(r["stats"]["ms_refine"], 3)}}
 
 
+def mesh_runs(log2n, k, eps, seed):
+    """The paper's mesh-type families (delX, rggX with radius 0.55 sqrt(ln n/n))
+    at n = 2^log2n: one warm-up and one timed partition each."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1404_4797_amd as sc
+    out = {}
+    for name, make in (("del%d" % log2n, lambda: synth.delaunay(1 << log2n, seed=seed)),
+                       ("rgg%d_paper" % log2n, lambda: synth.rgg_paper(1 << log2n, seed=seed))):
+        t = time.time()
+        g = make()
+        log("mesh %s: n=%d S=%d generated in %.1fs" % (name, g["n"], int(g["xadj"][-1]), time.time() - t))
+        d = sc.to_device(g, "cuda")
+        part = torch.empty(g["n"], dtype=torch.int32, device="cuda")
+        stream = torch.cuda.current_stream()
+        sc.partition_dev(d, k, eps, seed, part=part, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = sc.partition_dev(d, k, eps, seed, part=part, stream=stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        st = r["stats"]
+        out[name] = {"n": g["n"], "S": int(g["xadj"][-1]), "k": k, "ms": round(ms, 3), "cut": r["cut"],
+                     "status": r["status"], "levels": st["levels"], "level_n": st["level_n"],
+                     "edge_visits": st["visits"], "edge_visits_per_s": st["visits"] / (ms / 1e3),
+                     "max_block_weight": int(np.max(r["block_weights"]))}
+        log("mesh %s: %.1f ms, cut %d, levels %d" % (name, ms, r["cut"], st["levels"]))
+        del d, part
+    return out
+
+
 def serve_benchmark(nreq, log_lo, log_hi, fracs, plain_sample):
     """Poisson arrivals of partition requests (the batch mix's graph
     distribution) at fixed rates, given as multiples of the plain path's
@@ -237,6 +269,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mesh-log2", type=int, default=20,
+                    help="log2 n of the Delaunay and RGG (paper radius) runs (0: skip)")
     ap.add_argument("--no-variants", dest="variants", action="store_false",
                     help="skip the V-cycle / degree-order runs after the timed steps")
     ap.add_argument("--copy-calib", type=int, default=0, help="bytes for a plain copy kernel (counter scaling)")
@@ -349,6 +383,8 @@ def main():
                           "max_block_weight": int(np.max(q["block_weights"]))}
             log("variant %s: %.1f ms cut=%d (%.4f of the default cut)" % (vname, ms, q["cut"], q["cut"] / r["cut"]))
         out["variants"] = var
+    if args.mesh_log2 > 0:
+        out["mesh"] = mesh_runs(args.mesh_log2, w["k"], w["eps"], w["seed"])
     if args.batch_graphs > 0:
         out["batched"] = batch_comparison(args.batch_graphs, 0, args.batch_log2[0], args.batch_log2[1])
     if args.serve_requests > 0:

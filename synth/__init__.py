@@ -116,6 +116,34 @@ def rgg(n, radius=None, seed=1, weighted=False):
     return _finish(n, S, xadj, padj, pw)
 
 
+def rgg_paper(n, seed=1, weighted=False):
+    """rggX of the paper's benchmark set: radius 0.55 sqrt(ln n / n), chosen
+    there so that the graph is almost surely connected."""
+    return rgg(n, radius=0.55 * math.sqrt(math.log(max(n, 2)) / max(n, 1)), seed=seed, weighted=weighted)
+
+
+def delaunay(n, seed=1):
+    """delX of the paper's benchmark set: the Delaunay triangulation of n
+    points drawn uniformly from the unit square (numpy generator seeded with
+    ``seed``; triangulation by scipy's Qhull).  Unit weights, sorted rows."""
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(seed)
+    pts = rng.random((n, 2))
+    tri = Delaunay(pts).simplices.astype(np.int64)
+    e = np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]])
+    e = np.sort(e, axis=1)
+    key = np.unique(e[:, 0] * n + e[:, 1])
+    u, v = key // n, key % n
+    src = np.concatenate([u, v])
+    dst = np.concatenate([v, u])
+    order = np.argsort(src * n + dst, kind="stable")
+    src, dst = src[order], dst[order]
+    xadj = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(xadj, src + 1, 1)
+    xadj = np.cumsum(xadj)
+    return {"n": n, "xadj": xadj, "adjncy": dst.astype(np.int32), "adjwgt": None, "vwgt": None}
+
+
 def draw(key, i):
     """i-th output of the SplitMix64 stream seeded with ``key``."""
     return int(_load().synth_draw(key, i))

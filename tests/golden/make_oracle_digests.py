@@ -28,6 +28,8 @@ WORKLOADS = {
     # R-MAT scale 20, edge factor 16, (0.57, 0.19, 0.19, 0.05); full multilevel; k=16
     "rmat20_ef16_k16": dict(gen=("rmat", dict(scale=20, edge_factor=16, seed=1)), k=16, eps=0.03, seed=1,
                             opts=dict()),
+    # Delaunay triangulation of 2^18 uniform points (the paper's delX family); k=16
+    "del18_k16": dict(gen=("del", dict(n=1 << 18, seed=1)), k=16, eps=0.03, seed=1, opts=dict()),
     # the same with two multilevel cycles (Section 4.5, iterated V-cycles)
     "rmat20_ef16_k16_vcycles2": dict(gen=("rmat", dict(scale=20, edge_factor=16, seed=1)), k=16, eps=0.03,
                                      seed=1, opts=dict(vcycles=2)),
@@ -36,6 +38,8 @@ WORKLOADS = {
 
 def make_graph(spec):
     kind, kw = spec
+    if kind == "del":
+        return synth.delaunay(**kw)
     return synth.ba(**kw) if kind == "ba" else synth.rmat(**kw)
 
 
