@@ -349,6 +349,33 @@ def main():
     lp_gb = sum(v["bytes"] for k, v in kstats.items()
                 if k.startswith("lp_eval") or k.startswith("lp_refine")) / max(args.steps, 1) / 1e9
 
+    # reference ceiling for the evaluation: a plain random gather label[adj[e]]
+    # over every slot of the benchmark graph (torch index_select), the access
+    # that dominates evaluation; one pass per edge visit at that rate bounds
+    # the label-propagation time from below
+    gather = None
+    if S > 0:
+        adj64 = d["adjncy"].long()
+        lab = torch.arange(n, dtype=torch.int32, device="cuda")
+        gout = torch.empty(S, dtype=torch.int32, device="cuda")
+        torch.index_select(lab, 0, adj64, out=gout)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            torch.index_select(lab, 0, adj64, out=gout)
+        e1.record()
+        torch.cuda.synchronize()
+        gms = e0.elapsed_time(e1) / 3
+        rate = S / (gms / 1e3)
+        lp_ms = st["ms_lp"]
+        gather = {"ms_per_pass": round(gms, 3), "G_gathers_per_s": round(rate / 1e9, 1),
+                  "lp_ms_at_ceiling": round(visits / rate * 1e3, 1), "lp_ms": round(lp_ms, 1),
+                  "frac": round(visits / rate * 1e3 / lp_ms, 3)}
+        del adj64, lab, gout
+        log("gather ceiling: %.2f ms per pass over S, %.1f G gathers/s; LP %.1f ms vs %.1f ms at the ceiling"
+            % (gms, rate / 1e9, lp_ms, visits / rate * 1e3))
+
     out = {
         "metric": "SCLaP edge-visits/s & partition time; batched vs plain graphs/s, same cut",
         "value": value, "unit": "edge-visits/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -365,7 +392,7 @@ def main():
         "phase_ms": {"coarsen": st["ms_coarsen"], "initial": st["ms_initial"], "refine": st["ms_refine"],
                      "lp": st["ms_lp"]},
         "lp_eval_GB_per_step": round(lp_gb, 3),
-        "roofline": roofline, "kernels": kernels,
+        "roofline": roofline, "gather_ceiling": gather, "kernels": kernels,
     }
     if args.variants:
         # the paper's quality levers on the same workload, one timed run each

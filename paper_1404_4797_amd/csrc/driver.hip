@@ -1041,49 +1041,68 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
         // ---- initial partition of every graph's coarsest level, on the host
         // (first cycle; later ones inherit it)
         auto t_init = Clock::now();
-        struct Slice {
-            std::vector<int64_t> x;
-            std::vector<int32_t> a, v, part;
-        };
-        std::vector<Slice> ip(G);
+        // whole levels are copied once (pinned staging), each graph reads its
+        // slice; results go to one host array per level, uploaded before the
+        // projection of the graphs that continue
+        std::vector<uint8_t> ends(static_cast<size_t>(top) + 1, 0);
+        for (int32_t l = 0; l <= top; ++l)
+            for (size_t m = 0; m < L[l].ids.size(); ++m) mpos[L[l].ids[m]] = static_cast<int32_t>(m);
+        if (!carry)
+            for (int32_t g = 0; g < G; ++g) ends[last[g]] = 1;
+        auto rnd8 = [](size_t x) { return (x + 7) & ~static_cast<size_t>(7); };
+        std::vector<size_t> lofs(static_cast<size_t>(top) + 2, 0);
         for (int32_t l = 0; l <= top; ++l) {
-            const BatchLevel& B = L[l];
-            for (size_t m = 0; m < B.ids.size(); ++m) {
-                const int32_t g = B.ids[m];
-                mpos[g] = static_cast<int32_t>(m);
-                if (last[g] != l || carry) continue;
-                const int32_t nm = B.nb[m + 1] - B.nb[m];
-                const int64_t Sm = B.sb[m + 1] - B.sb[m];
-                Slice& sl = ip[g];
-                sl.x.resize(static_cast<size_t>(nm) + 1);
-                sl.a.resize(static_cast<size_t>(std::max<int64_t>(Sm, 1)));
-                sl.part.resize(static_cast<size_t>(nm));
-                HIPCHK(hipMemcpyAsync(sl.x.data(), B.g.xadj + B.nb[m], (nm + 1) * sizeof(int64_t), hipMemcpyDeviceToHost,
-                                      s));
-                if (Sm > 0)
-                    HIPCHK(hipMemcpyAsync(sl.a.data(), B.g.adj + B.sb[m], Sm * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-                if (B.g.vw && nm > 0) {
-                    sl.v.resize(nm);
-                    HIPCHK(hipMemcpyAsync(sl.v.data(), B.g.vw + B.nb[m], nm * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-                }
+            size_t bytes = 0;
+            if (ends[l]) {
+                const size_t nl = static_cast<size_t>(L[l].g.n);
+                bytes = rnd8((nl + 1) * sizeof(int64_t)) + rnd8(static_cast<size_t>(L[l].g.S) * sizeof(int32_t)) +
+                        2 * rnd8(nl * sizeof(int32_t));
             }
+            lofs[l + 1] = lofs[l] + bytes;
         }
-        HIPCHK(hipStreamSynchronize(s));
+        std::unique_ptr<HostStage> stage;
+        struct LevelHost {
+            int64_t* x = nullptr;
+            int32_t *a = nullptr, *v = nullptr, *p = nullptr;
+        };
+        std::vector<LevelHost> lh(static_cast<size_t>(top) + 1);
+        if (lofs[top + 1] > 0) {
+            stage.reset(new HostStage(lofs[top + 1]));
+            for (int32_t l = 0; l <= top; ++l) {
+                if (!ends[l]) continue;
+                const BatchLevel& B = L[l];
+                const size_t nl = static_cast<size_t>(B.g.n);
+                char* base = stage->data() + lofs[l];
+                LevelHost& h = lh[l];
+                h.x = reinterpret_cast<int64_t*>(base);
+                h.a = reinterpret_cast<int32_t*>(base + rnd8((nl + 1) * sizeof(int64_t)));
+                h.v = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(h.a) + rnd8(static_cast<size_t>(B.g.S) * sizeof(int32_t)));
+                h.p = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(h.v) + rnd8(nl * sizeof(int32_t)));
+                HIPCHK(hipMemcpyAsync(h.x, B.g.xadj, (nl + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+                if (B.g.S > 0)
+                    HIPCHK(hipMemcpyAsync(h.a, B.g.adj, B.g.S * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                if (B.g.vw && nl > 0) HIPCHK(hipMemcpyAsync(h.v, B.g.vw, nl * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                if (!B.g.vw) h.v = nullptr;
+            }
+            HIPCHK(hipStreamSynchronize(s));
+        }
         const unsigned hw = std::thread::hardware_concurrency();
         if (!carry) parallel_for(G, static_cast<int32_t>(std::min(16u, hw ? hw : 1u)), [&](int32_t g) {
-            Slice& sl = ip[g];
-            const BatchLevel& B = L[last[g]];
+            const int32_t l = last[g];
+            const BatchLevel& B = L[l];
+            const LevelHost& h = lh[l];
             const int32_t m = mpos[g];
-            const int32_t nm = B.nb[m + 1] - B.nb[m];
-            const int64_t x0 = sl.x[0];
-            for (auto& x : sl.x) x -= x0;
-            for (int64_t j = 0; j < sl.x[nm]; ++j) sl.a[j] -= B.nb[m];
-            host_initial_partition(nm, sl.x.data(), sl.a.data(), sl.v.empty() ? nullptr : sl.v.data(), k[g], T[g],
-                                   sl.part.data(), false);  // rows of inner levels are unordered
-            for (auto& b : sl.part) b += kb[g];  // labels of the batch's block space
-            sl.x = {};
-            sl.a = {};
-            sl.v = {};
+            const int32_t nb0 = B.nb[m];
+            const int32_t nm = B.nb[m + 1] - nb0;
+            std::vector<int64_t> x(h.x + nb0, h.x + nb0 + nm + 1);  // row ends are shared with the next graph
+            const int64_t x0 = x[0];
+            for (auto& e : x) e -= x0;
+            int32_t* a = h.a + x0;  // this graph's slots, to graph-local ids in place
+            for (int64_t j = 0; j < x[nm]; ++j) a[j] -= nb0;
+            int32_t* pp = h.p + nb0;
+            host_initial_partition(nm, x.data(), a, h.v ? h.v + nb0 : nullptr, k[g], T[g], pp,
+                                   false);  // rows of inner levels are unordered
+            for (int32_t i = 0; i < nm; ++i) pp[i] += kb[g];  // labels of the batch's block space
         });
         st->ms_initial += ms_since(t_init);
 
@@ -1103,13 +1122,10 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
             }
             if (carry && part != blk_of(l) && n > 0)  // graphs ending here keep their inherited blocks
                 HIPCHK(hipMemcpyAsync(part, blk_of(l), n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+            // graphs ending here: their initial partitions (the other ranges
+            // are overwritten by the projection next)
+            if (ends[l] && n > 0) HIPCHK(hipMemcpyAsync(part, lh[l].p, n * sizeof(int32_t), hipMemcpyHostToDevice, s));
             if (l < top) project_kept(n, B.C.get(), cur.get(), part, s);
-            for (size_t m = 0; m < B.ids.size(); ++m) {
-                const int32_t g = B.ids[m];
-                if (last[g] != l || ip[g].part.empty()) continue;
-                HIPCHK(hipMemcpyAsync(part + B.nb[m], ip[g].part.data(), ip[g].part.size() * sizeof(int32_t),
-                                      hipMemcpyHostToDevice, s));
-            }
             std::vector<int32_t> base(G, 0);
             for (size_t m = 0; m < B.ids.size(); ++m) base[B.ids[m]] = B.nb[m];
             upload_vec(d_nbase, base, s);
@@ -1129,9 +1145,7 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
                 run_lp(B.g, kRefine, l, 0, o.nsub, o.refine_rounds, 0, part, w.get(), K, nullptr, o.tune, s, &mg);
             lp_ms += ms_since(t_lp);
             st->visits += r.visits;
-            HIPCHK(hipStreamSynchronize(s));  // host slices uploaded above must stay alive until here
-            for (size_t m = 0; m < B.ids.size(); ++m)
-                if (last[B.ids[m]] == l) ip[B.ids[m]].part = {};
+            HIPCHK(hipStreamSynchronize(s));  // the staging uploaded above must stay alive until here
             cur = std::move(mine);
             if (l < top) {
                 L[l + 1] = BatchLevel();
