@@ -269,6 +269,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--opt", action="append", default=[], metavar="KEY=INT",
+                    help="extra sclap_options field for the timed partitions (e.g. skip_quiet=1)")
     ap.add_argument("--mesh-log2", type=int, default=20,
                     help="log2 n of the Delaunay and RGG (paper radius) runs (0: skip)")
     ap.add_argument("--no-variants", dest="variants", action="store_false",
@@ -299,7 +301,11 @@ def main():
     d = sc.to_device(g, "cuda")
     part = torch.empty(n, dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
-    opts = sc.default_options(**w["opts"])
+    extra = {}
+    for kv in args.opt:
+        key, val = kv.split("=", 1)
+        extra[key] = int(val)
+    opts = sc.default_options(**w["opts"], **extra)
     torch.cuda.synchronize()
     if args.copy_calib:
         copy_calibration(args.copy_calib)

@@ -382,6 +382,19 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
     });
     const double t_rest = ms_since(T0);
     auto cw = [&](int32_t v) -> int64_t { return vw ? vw[v] : 1; };
+    // runs of equal weight in the leftover order: their starts, found in
+    // parallel (a run is dealt as one unit below)
+    std::vector<std::vector<size_t>> task_starts(static_cast<size_t>(ntask));
+    if (vw) {
+        parallel_for(ntask, nthr, [&](int32_t t) {
+            const size_t a0 = nrest * static_cast<size_t>(t) / ntask, a1 = nrest * static_cast<size_t>(t + 1) / ntask;
+            for (size_t q = std::max<size_t>(a0, 1); q < a1; ++q)
+                if (vw[rest[q]] != vw[rest[q - 1]]) task_starts[t].push_back(q);
+        });
+    }
+    std::vector<size_t> run_end;  // end of each run, in order
+    for (const auto& ts : task_starts) run_end.insert(run_end.end(), ts.begin(), ts.end());
+    run_end.push_back(nrest);
     std::vector<int32_t> ord(static_cast<size_t>(k));
     BlockHeap heap(wb);  // kept in step with wb by the node-by-node path
     bool heap_ok = true;
@@ -389,8 +402,7 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
     size_t nruns = 0, nheap = 0;
     while (i < nrest) {
         const int64_t c = cw(rest[i]);
-        size_t j = i;
-        while (j < nrest && cw(rest[j]) == c) ++j;
+        const size_t j = run_end[nruns];
         ++nruns;
         if (c == 0 || k > 4096 || j - i < 4 * static_cast<size_t>(k)) {  // node by node
             nheap += j - i;

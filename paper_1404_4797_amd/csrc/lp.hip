@@ -2055,47 +2055,9 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
             for (int32_t bk = 0; bk < kNB; ++bk) colour_slots += cslots[c0 + bk];
             const bool side = colour_slots >= (1ULL << 22);  // small colours stay on one stream
             if (side) evs.fork(s);
-            for (int32_t bk = 0; bk < kHubBucket; ++bk) {
-                const hipStream_t bs = side ? evs.bucket(bk) : s;
-                const int64_t count = off[c0 + bk + 1] - off[c0 + bk];
-                if (count == 0) continue;
-                A.nodes = nodes + off[c0 + bk];
-                A.count = static_cast<int32_t>(count);
-                A.ct = ct.get() + (off[c0 + bk] - off[c0]);
-                A.cg = cg.get() + (off[c0 + bk] - off[c0]);
-                static const char* const kNames[2][kHubBucket] = {
-                    {"lp_eval_lane4", "lp_eval_lane16", "lp_eval_group16", "lp_eval_group32", "lp_eval_wave",
-                     "lp_eval_block1k", "lp_eval_block4k", "lp_eval_block8k"},
-                    {"lp_refine_lane4", "lp_refine_lane16", "lp_refine_group16", "lp_refine_group32",
-                     "lp_refine_wave", "lp_refine_block1k", "lp_refine_block4k", "lp_refine_block8k"}};
-                ProfScope ps(kNames[A.refine][bk], eval_bytes(count, cslots[c0 + bk]), bs);
-                const unsigned nb = static_cast<unsigned>(count);
-                if (bk == 0) {
-                    eval_lane_kernel<kLaneSmall><<<grid_for(count, 256), 256, 0, bs>>>(A);
-                } else if (bk == 1) {
-                    eval_lane_kernel<kLaneMax><<<grid_for(count, 256), 256, 0, bs>>>(A);
-                } else if (dense) {  // refinement blocks: dense connection arrays
-                    if (bk == 2) eval_dense_group_kernel<16><<<grid_for(count, 16), 256, 0, bs>>>(A);
-                    else if (bk == 3) eval_dense_group_kernel<32><<<grid_for(count, 8), 256, 0, bs>>>(A);
-                    else if (bk == 4) eval_dense_group_kernel<64><<<grid_for(count, 4), 256, 0, bs>>>(A);
-                    else if (bk == 5) eval_dense_block_kernel<256><<<nb, 256, 0, bs>>>(A);
-                    else if (bk == 6) eval_dense_block_kernel<512><<<nb, 512, 0, bs>>>(A);
-                    else eval_dense_block_kernel<1024><<<nb, 1024, 0, bs>>>(A);
-                } else if (bk == 2) {
-                    eval_group_kernel<16, 2 * kG16Max><<<grid_for(count, 16), 256, 0, bs>>>(A);
-                } else if (bk == 3) {
-                    eval_group_kernel<32, 2 * kG32Max><<<grid_for(count, 8), 256, 0, bs>>>(A);
-                } else if (bk == 4) {
-                    eval_group_kernel<64, kWaveTable><<<grid_for(count, 4), 256, 0, bs>>>(A);
-                } else if (bk == 5) {
-                    eval_block_kernel<256, 2 * kBlock1Max><<<nb, 256, 0, bs>>>(A);
-                } else if (bk == 6) {
-                    eval_block_kernel<512, 2 * kBlock2Max><<<nb, 512, 0, bs>>>(A);
-                } else {
-                    eval_block_kernel<1024, kBlockTable><<<nb, 1024, 0, bs>>>(A);
-                }
-                LAUNCHCHK();
-            }
+            // hubs first: their chain (chunks, partitions, decision) is the
+            // longest, so its workgroups should be dispatched before the
+            // other buckets fill the device
             const HubPlan& P = plans[sc];
             const hipStream_t hs = side ? evs.hub() : s;
             if (P.count > 0) {
@@ -2168,6 +2130,47 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                     LAUNCHCHK();
                 }
                 }
+            }
+            for (int32_t bk = 0; bk < kHubBucket; ++bk) {
+                const hipStream_t bs = side ? evs.bucket(bk) : s;
+                const int64_t count = off[c0 + bk + 1] - off[c0 + bk];
+                if (count == 0) continue;
+                A.nodes = nodes + off[c0 + bk];
+                A.count = static_cast<int32_t>(count);
+                A.ct = ct.get() + (off[c0 + bk] - off[c0]);
+                A.cg = cg.get() + (off[c0 + bk] - off[c0]);
+                static const char* const kNames[2][kHubBucket] = {
+                    {"lp_eval_lane4", "lp_eval_lane16", "lp_eval_group16", "lp_eval_group32", "lp_eval_wave",
+                     "lp_eval_block1k", "lp_eval_block4k", "lp_eval_block8k"},
+                    {"lp_refine_lane4", "lp_refine_lane16", "lp_refine_group16", "lp_refine_group32",
+                     "lp_refine_wave", "lp_refine_block1k", "lp_refine_block4k", "lp_refine_block8k"}};
+                ProfScope ps(kNames[A.refine][bk], eval_bytes(count, cslots[c0 + bk]), bs);
+                const unsigned nb = static_cast<unsigned>(count);
+                if (bk == 0) {
+                    eval_lane_kernel<kLaneSmall><<<grid_for(count, 256), 256, 0, bs>>>(A);
+                } else if (bk == 1) {
+                    eval_lane_kernel<kLaneMax><<<grid_for(count, 256), 256, 0, bs>>>(A);
+                } else if (dense) {  // refinement blocks: dense connection arrays
+                    if (bk == 2) eval_dense_group_kernel<16><<<grid_for(count, 16), 256, 0, bs>>>(A);
+                    else if (bk == 3) eval_dense_group_kernel<32><<<grid_for(count, 8), 256, 0, bs>>>(A);
+                    else if (bk == 4) eval_dense_group_kernel<64><<<grid_for(count, 4), 256, 0, bs>>>(A);
+                    else if (bk == 5) eval_dense_block_kernel<256><<<nb, 256, 0, bs>>>(A);
+                    else if (bk == 6) eval_dense_block_kernel<512><<<nb, 512, 0, bs>>>(A);
+                    else eval_dense_block_kernel<1024><<<nb, 1024, 0, bs>>>(A);
+                } else if (bk == 2) {
+                    eval_group_kernel<16, 2 * kG16Max><<<grid_for(count, 16), 256, 0, bs>>>(A);
+                } else if (bk == 3) {
+                    eval_group_kernel<32, 2 * kG32Max><<<grid_for(count, 8), 256, 0, bs>>>(A);
+                } else if (bk == 4) {
+                    eval_group_kernel<64, kWaveTable><<<grid_for(count, 4), 256, 0, bs>>>(A);
+                } else if (bk == 5) {
+                    eval_block_kernel<256, 2 * kBlock1Max><<<nb, 256, 0, bs>>>(A);
+                } else if (bk == 6) {
+                    eval_block_kernel<512, 2 * kBlock2Max><<<nb, 512, 0, bs>>>(A);
+                } else {
+                    eval_block_kernel<1024, kBlockTable><<<nb, 1024, 0, bs>>>(A);
+                }
+                LAUNCHCHK();
             }
             if (side) evs.join(s);
 
