@@ -47,7 +47,7 @@ class Options(ctypes.Structure):
     _fields_ = [("coarsen_rounds", ctypes.c_int32), ("refine_rounds", ctypes.c_int32),
                 ("subrounds", ctypes.c_int32), ("cluster_divisor", ctypes.c_int32),
                 ("coarsest_nodes", ctypes.c_int32), ("max_levels", ctypes.c_int32),
-                ("vcycles", ctypes.c_int32), ("degree_order", ctypes.c_int32)]
+                ("vcycles", ctypes.c_int32), ("degree_order", ctypes.c_int32), ("initial", ctypes.c_int32)]
 
 
 _MAXL = 64
@@ -83,6 +83,7 @@ def _load():
             "orc_cluster_within": (i32, [G, vp, i64, i32, i32, u64, i32, vp, vp, vp, vp]),
             "orc_cycle_seed": (u64, [u64, i32]),
             "orc_degree_colors": (None, [G, vp, i32, vp]),
+            "orc_initial_partition_lp": (i32, [G, i32, i64, i64, u64, i32, i32, i32, vp, vp, vp]),
             "orc_refine": (i32, [G, i32, i64, i32, i32, u64, i32, vp, vp, vp, vp]),
             "orc_contract": (i32, [G, vp, vp, vp, vp, vp, vp, vp, vp]),
             "orc_project": (None, [i32, vp, vp, vp]),
@@ -275,6 +276,20 @@ def initial_partition(g, k, T):
     part = np.empty(gv.n, dtype=np.int32)
     _load().orc_initial_partition(gv.ref, k, T, part.ctypes.data)
     return part
+
+
+def initial_partition_lp(g, k, T, Lmax, seed=1, level=0, rounds=10, nsub=4):
+    """Initial partition by label propagation from hashed seeds with a pool
+    label.  Returns (part, rounds_run, visits)."""
+    gv = _GraphView(g)
+    part = np.empty(gv.n, dtype=np.int32)
+    rr = np.zeros(1, dtype=np.int32)
+    visits = np.zeros(1, dtype=np.int64)
+    st = _load().orc_initial_partition_lp(gv.ref, k, T, Lmax, seed, level, rounds, nsub, part.ctypes.data,
+                                          rr.ctypes.data, visits.ctypes.data)
+    if st != 0:
+        raise ValueError("orc_initial_partition_lp status %d" % st)
+    return part, int(rr[0]), int(visits[0])
 
 
 def default_options(**kw):

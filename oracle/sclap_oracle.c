@@ -176,7 +176,7 @@ int32_t orc_eval_node_within(const orc_graph* g, const int32_t* block, int32_t p
     int32_t a = label[v];
     int64_t cv = node_w(g, v);
     int64_t b = g->xadj[v], e = g->xadj[v + 1], d = 0;
-    out->over = (phase == ORC_REFINE && w[a] > bound) ? 1 : 0;
+    out->over = (phase != ORC_CLUSTER && w[a] > bound) ? 1 : 0;
     if (e == b) return 0;
     lw_pair* P = (lw_pair*)malloc((size_t)(e - b) * sizeof(lw_pair));
     for (int64_t i = b; i < e; ++i) {
@@ -537,6 +537,77 @@ int32_t orc_initial_partition(const orc_graph* g, int32_t k, int64_t T, int32_t*
     return 0;
 }
 
+/*
+ * Initial partition by label propagation from seeds (a deterministic
+ * stand-in for the evolutionary partitioner of Section 4.5, built from the
+ * size-constrained label propagation of Section 3.1):
+ *   1. seeds: the min(k, #nodes with neighbours) nodes with neighbours of
+ *      smallest (H(seed, 5, level, v), v); seed i starts block i;
+ *   2. every other node starts in a pool, label k, whose weight carries an
+ *      offset BIG = 2^30 > Lmax: the pool is never an eligible target and
+ *      always overloaded, so by the overloaded-block rule each pool node
+ *      joins its best eligible neighbouring block (none: it stays);
+ *   3. `rounds` label-propagation rounds under Lmax with k + 1 labels, with
+ *      the refinement rules and hash phase 2 (ORC_INITIAL);
+ *   4. the nodes still in the pool (isolated ones among them), in id order,
+ *      fill the blocks' remaining room max(0, T - w(b)) in block order: the
+ *      node whose exclusive prefix weight is P goes to the first block whose
+ *      cumulative room exceeds P (block k - 1 if none does).
+ * Requires Lmax < 2^30 and c(V) < 2^30 (returns -1 otherwise).
+ */
+typedef struct { uint64_t h; int32_t v; } seed_key;
+
+static int cmp_seed_key(const void* x, const void* y) {
+    const seed_key* p = (const seed_key*)x;
+    const seed_key* q = (const seed_key*)y;
+    if (p->h != q->h) return p->h < q->h ? -1 : 1;
+    return (p->v > q->v) - (p->v < q->v);
+}
+
+int32_t orc_initial_partition_lp(const orc_graph* g, int32_t k, int64_t T, int64_t Lmax, uint64_t seed,
+                                 int32_t level, int32_t rounds, int32_t nsub, int32_t* part, int32_t* rounds_run,
+                                 int64_t* visits) {
+    const int64_t BIG = (int64_t)1 << 30;
+    int32_t n = g->n;
+    int64_t cV = total_node_weight(g);
+    if (k < 1 || nsub < 1 || rounds < 0 || Lmax >= BIG || cV >= BIG) return -1;
+    seed_key* S = (seed_key*)malloc((size_t)(n > 0 ? n : 1) * sizeof(seed_key));
+    int32_t npos = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        part[v] = k;
+        if (g->xadj[v + 1] == g->xadj[v]) continue;
+        uint64_t words[4] = {seed, 5, (uint64_t)(uint32_t)level, (uint64_t)(uint32_t)v};
+        S[npos].h = orc_hash(words, 4);
+        S[npos].v = v;
+        ++npos;
+    }
+    qsort(S, (size_t)npos, sizeof(seed_key), cmp_seed_key);
+    for (int32_t i = 0; i < k && i < npos; ++i) part[S[i].v] = i;
+    free(S);
+    int64_t* w = (int64_t*)calloc((size_t)k + 1, sizeof(int64_t));
+    for (int32_t v = 0; v < n; ++v) w[part[v]] += node_w(g, v);
+    w[k] += BIG;
+    run_rounds(g, NULL, ORC_INITIAL, level, rounds, nsub, seed, Lmax, NULL, part, w, rounds_run, visits);
+    /* the pool fills the remaining room of the blocks in block order */
+    int64_t* cum = (int64_t*)malloc((size_t)k * sizeof(int64_t));
+    int64_t run = 0;
+    for (int32_t b = 0; b < k; ++b) {
+        run += w[b] < T ? T - w[b] : 0;
+        cum[b] = run;
+    }
+    int64_t P = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        if (part[v] != k) continue;
+        int32_t b = 0;
+        while (b < k && cum[b] <= P) ++b;
+        part[v] = b < k ? b : k - 1;
+        P += node_w(g, v);
+    }
+    free(cum);
+    free(w);
+    return 0;
+}
+
 /* ------------------------------------------------------------ multilevel */
 
 void orc_default_options(orc_options* o) {
@@ -548,6 +619,7 @@ void orc_default_options(orc_options* o) {
     o->max_levels = ORC_MAX_LEVELS;
     o->vcycles = 1;
     o->degree_order = 0;
+    o->initial = 0;
 }
 
 typedef struct {
@@ -590,7 +662,7 @@ int32_t orc_partition(const orc_graph* g, int32_t k, double eps, uint64_t seed, 
     else orc_default_options(&opt);
     if (!g || k < 1 || !(eps >= 0.0) || eps > 1000.0) return -1;
     if (opt.subrounds < 1 || opt.cluster_divisor < 1 || opt.max_levels < 0 || opt.max_levels > ORC_MAX_LEVELS ||
-        opt.coarsen_rounds < 0 || opt.refine_rounds < 0 || opt.vcycles < 1)
+        opt.coarsen_rounds < 0 || opt.refine_rounds < 0 || opt.vcycles < 1 || opt.initial < 0 || opt.initial > 1)
         return -1;
     int32_t st = orc_validate(g);
     if (st != 0) return st;
@@ -676,6 +748,19 @@ int32_t orc_partition(const orc_graph* g, int32_t k, double eps, uint64_t seed, 
         int32_t* cur = (int32_t*)malloc((size_t)(L[lev].n > 0 ? L[lev].n : 1) * sizeof(int32_t));
         if (L[lev].blk) {
             memcpy(cur, L[lev].blk, (size_t)L[lev].n * sizeof(int32_t));
+        } else if (opt.initial == 1) {
+            orc_graph G = {L[lev].n, L[lev].xadj, L[lev].adj, L[lev].vw, L[lev].adjw};
+            int32_t rr = 0;
+            if (orc_initial_partition_lp(&G, k, T, Lmax, sd, lev, opt.refine_rounds, opt.subrounds, cur, &rr,
+                                         &S->visits) != 0) {
+                free(cur);
+                for (int32_t l = 0; l <= lev; ++l) {
+                    if (l > 0) { free(L[l].xadj); free(L[l].adj); free(L[l].blk); }
+                    free(L[l].adjw); free(L[l].vw); free(L[l].C);
+                }
+                free(prev);
+                return -1;
+            }
         } else {
             orc_graph G = {L[lev].n, L[lev].xadj, L[lev].adj, L[lev].vw, L[lev].adjw};
             orc_initial_partition(&G, k, T, cur);

@@ -37,7 +37,7 @@ typedef struct {
     const int32_t* adjwgt; /* [xadj[n]] or NULL (all 1) */
 } orc_graph;
 
-enum { ORC_CLUSTER = 0, ORC_REFINE = 1 };
+enum { ORC_CLUSTER = 0, ORC_REFINE = 1, ORC_INITIAL = 2 };
 
 /* Hash: SplitMix64 output function of z + 0x9E3779B97F4A7C15, chained. */
 uint64_t orc_mix(uint64_t z);
@@ -113,7 +113,15 @@ typedef struct {
     int32_t max_levels;      /* 64 */
     int32_t vcycles;         /* 1: multilevel cycles, each after the first inside the previous blocks */
     int32_t degree_order;    /* 0; 1: clustering sub-rounds by increasing degree (orc_degree_colors) */
+    int32_t initial;         /* 0: orc_initial_partition; 1: orc_initial_partition_lp */
 } orc_options;
+
+/* Initial partition by label propagation from hashed seeds with a pool label
+ * (see the definition in the source); phase 2 hashes.  Returns -1 unless
+ * Lmax < 2^30 and c(V) < 2^30. */
+int32_t orc_initial_partition_lp(const orc_graph* g, int32_t k, int64_t T, int64_t Lmax, uint64_t seed,
+                                 int32_t level, int32_t rounds, int32_t nsub, int32_t* part, int32_t* rounds_run,
+                                 int64_t* visits);
 
 /* Sub-round of every node for degree-ordered clustering (Section 3.1,
  * Section 4.1); block may be NULL. */

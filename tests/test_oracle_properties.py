@@ -606,3 +606,87 @@ def test_degree_order_composes_from_single_operations(make, k):
     plain = oracle.partition(g, k, 0.03, 5, coarsest_nodes=200)
     assert np.array_equal(py_multilevel(g, k, 0.03, 5, 200, False), plain["part"])
     assert r["cut"] == py_cut(g, r["part"])
+
+
+# --------------------------------------- label-propagation initial partition
+
+def test_initial_lp_edgeless_closed_form():
+    # no node has neighbours: no seed, every node stays in the pool and the
+    # pool fills blocks 0, 1, ... up to T in id order
+    n, k = 10, 3
+    g = {"n": n, "xadj": np.zeros(n + 1, dtype=np.int64), "adjncy": np.zeros(0, dtype=np.int32)}
+    T = -(-n // k)
+    part, rr, visits = oracle.initial_partition_lp(g, k, T, oracle.lmax(n, k, 0.03), seed=3)
+    assert part.tolist() == [v // T for v in range(n)] and visits == 0
+
+
+@pytest.mark.parametrize("name,make", GRAPHS)
+@pytest.mark.parametrize("k", [2, 7, 32])
+def test_initial_lp_properties(name, make, k):
+    g = make()
+    c = vw(g)
+    cV = int(c.sum())
+    T = -(-cV // k)
+    Lmax = oracle.lmax(cV, k, 0.03)
+    part, rr, _ = oracle.initial_partition_lp(g, k, T, Lmax, seed=4, level=2, rounds=10)
+    assert part.min() >= 0 and part.max() < k
+    bw = py_weights(g, part, k)
+    assert bw.max() <= max(Lmax, T + int(c.max()) - 1)
+    # with no label-propagation round every node but the seeds is dealt into
+    # the remaining room: each block stays within T plus one node
+    p0, rr0, v0 = oracle.initial_partition_lp(g, k, T, Lmax, seed=4, level=2, rounds=0)
+    assert rr0 == 0 and v0 == 0
+    assert py_weights(g, p0, k).max() <= T + int(c.max())
+    # the same inputs give the same partition
+    again, _, _ = oracle.initial_partition_lp(g, k, T, Lmax, seed=4, level=2, rounds=10)
+    assert np.array_equal(again, part)
+
+
+def test_initial_lp_seeds_are_smallest_hashes():
+    # rounds = 0, unit weights: block i holds seed i, and the other nodes
+    # follow in id order; the seeds are the k nodes with neighbours of
+    # smallest H(seed, 5, level, v), computed here with an independent
+    # SplitMix64 chain
+    M64 = (1 << 64) - 1
+
+    def mix(z):
+        z = (z + 0x9E3779B97F4A7C15) & M64
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+        return z ^ (z >> 31)
+
+    def H(*w):
+        h = mix(w[0])
+        for x in w[1:]:
+            h = mix(h ^ x)
+        return h
+
+    g = synth.ba(60, 2, seed=5)
+    k, seed, level = 4, 9, 1
+    n = g["n"]
+    T = -(-n // k)
+    part, _, _ = oracle.initial_partition_lp(g, k, T, 10 ** 6, seed=seed, level=level, rounds=0)
+    deg = np.diff(g["xadj"])
+    order = sorted((H(seed, 5, level, v), v) for v in range(n) if deg[v] > 0)
+    seeds = [v for _, v in order[:k]]
+    for i, v in enumerate(seeds):
+        assert part[v] == i
+    rest = [v for v in range(n) if v not in seeds]
+    room = [T - 1] * k  # each block holds its seed (weight 1)
+    expect, b = [], 0
+    for v in rest:
+        while room[b] == 0:
+            b += 1
+        expect.append(b)
+        room[b] -= 1
+    assert part[rest].tolist() == expect
+
+
+@pytest.mark.parametrize("make,k", [(lambda: synth.rmat(12, 8, seed=3, weighted=True), 8),
+                                    (lambda: synth.ba(3000, 4, seed=2), 4)])
+def test_initial_lp_in_the_multilevel_run(make, k):
+    g = make()
+    r = oracle.partition(g, k, 0.03, 5, coarsest_nodes=200, initial=1)
+    assert r["cut"] == py_cut(g, r["part"])
+    assert np.array_equal(r["block_weights"], py_weights(g, r["part"], k))
+    assert r["status"] == (1 if r["block_weights"].max() > oracle.lmax(int(vw(g).sum()), k, 0.03) else 0)
