@@ -404,7 +404,8 @@ def main():
         # the paper's quality levers on the same workload, one timed run each
         var = {}
         for vname, kw in (("vcycles2", dict(vcycles=2)), ("degree_order", dict(degree_order=1)),
-                          ("degree_order_vcycles2", dict(degree_order=1, vcycles=2))):
+                          ("degree_order_vcycles2", dict(degree_order=1, vcycles=2)),
+                          ("device_initial", dict(initial_partitioner=1))):
             vo = sc.default_options(**w["opts"], **kw)
             torch.cuda.synchronize()
             t0 = time.perf_counter()

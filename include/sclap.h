@@ -114,6 +114,15 @@ typedef struct {
                                  0 (default): hash colours. */
     int32_t contract_bucket_mean; /* tuning (never changes results; 0 = 1024): merged entries per
                                      bucket when contraction merges very long coarse rows by buckets */
+    int32_t initial_partitioner;  /* 0 (default): host greedy growing (sclap_initial_partition);
+                                     1: on the device, label propagation from seeds: the
+                                     min(k, #nodes with neighbours) nodes with neighbours of smallest
+                                     (H(seed, 5, level, v), v) start blocks 0.., all others start in a
+                                     pool label k that is never eligible and always overloaded; then
+                                     refine_rounds rounds under Lmax with k + 1 labels and hash
+                                     phase 2; nodes left in the pool fill the blocks' remaining room
+                                     max(0, T - w(b)) in id and block order.  Needs Lmax and c(V)
+                                     below 2^30; single-graph entry points only. */
 } sclap_options;
 
 #define SCLAP_MAX_LEVELS 64
@@ -233,6 +242,17 @@ int sclap_cut_dev(const sclap_graph* g, const int32_t* part, int32_t k, int64_t*
  * belongs to a node without neighbours.
  */
 int sclap_initial_partition(const sclap_graph* g, int32_t k, int32_t* part);
+
+/*
+ * The device initial partitioner (see sclap_options.initial_partitioner): label
+ * propagation from the hashed seeds of `level` and `seed` with a pool label,
+ * `rounds` rounds under Lmax (options: subrounds and tuning knobs), then the
+ * pool fills the remaining room up to T.  Device memory; part[n] receives
+ * blocks in [0, k); *visits (may be NULL) the adjacency slots evaluated.
+ */
+int sclap_initial_partition_lp_dev(const sclap_graph* g, int32_t k, int64_t T, int64_t Lmax, uint64_t seed,
+                                   int32_t level, int32_t rounds, const sclap_options* opt, int32_t* part,
+                                   int64_t* visits, void* stream);
 
 /* Lmax = T + floor(T * round(eps * 10^6) / 10^6), T = ceil(cV / k). */
 int64_t sclap_lmax(int64_t cV, int32_t k, double eps);

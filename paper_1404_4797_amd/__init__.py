@@ -36,7 +36,7 @@ EXPORTS = [
     "sclap_partition", "sclap_partition_dev",
     "sclap_partition_batch", "sclap_partition_batch_dev",
     "sclap_server_create", "sclap_server_submit", "sclap_server_poll", "sclap_server_destroy",
-    "sclap_autotune_dev", "sclap_trim_memory",
+    "sclap_autotune_dev", "sclap_trim_memory", "sclap_initial_partition_lp_dev",
     "sclap_profile_begin", "sclap_profile_end",
 ]
 
@@ -67,7 +67,8 @@ class Options(ctypes.Structure):
                 ("block_max_degree", ctypes.c_int32), ("hub_part_limit", ctypes.c_int32),
                 ("hub_region_cap", ctypes.c_int32), ("select_small_max", ctypes.c_int32),
                 ("skip_quiet", ctypes.c_int32), ("vcycles", ctypes.c_int32),
-                ("degree_order", ctypes.c_int32), ("contract_bucket_mean", ctypes.c_int32)]
+                ("degree_order", ctypes.c_int32), ("contract_bucket_mean", ctypes.c_int32),
+                ("initial_partitioner", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):
@@ -150,6 +151,7 @@ def load():
         "sclap_server_destroy": (None, [vp]),
         "sclap_autotune_dev": (ctypes.c_int, [G, i32, O, vp]),
         "sclap_trim_memory": (ctypes.c_int, []),
+        "sclap_initial_partition_lp_dev": (ctypes.c_int, [G, i32, i64, i64, u64, i32, i32, O, vp, vp, vp]),
         "sclap_partition_batch_dev": (ctypes.c_int, [G, i32, vp, vp, vp, vp, O, vp, vp, vp, BST, vp]),
         "sclap_profile_begin": (ctypes.c_int, []),
         "sclap_profile_end": (ctypes.c_int, [ctypes.POINTER(KernelStat), i32, vp]),
@@ -556,6 +558,19 @@ def partition_batch_dev(d, node_base, k, eps, seed, part=None, stream=None, opts
                                                      ctypes.byref(st), _stream(stream)), allow_warn=True)
     return {"part": part, "cut": cut, "block_weights": bw, "levels": levels, "status": status,
             "stats": st.to_dict()}
+
+
+def initial_partition_lp_dev(d, k, T, Lmax, seed=1, level=0, rounds=10, part=None, stream=None, **opts):
+    """Device initial partitioner on a device graph; returns (part tensor, visits)."""
+    import torch
+    dg = _DevGraph(d)
+    if part is None:
+        part = torch.empty(max(dg.n, 1), dtype=torch.int32, device=d["xadj"].device)
+    o = _opts(opts)
+    visits = ctypes.c_int64(0)
+    _check(load().sclap_initial_partition_lp_dev(dg.ref, k, T, Lmax, seed, level, rounds, ctypes.byref(o),
+                                                 _t_ptr(part), ctypes.addressof(visits), _stream(stream)))
+    return part[:dg.n], visits.value
 
 
 def autotune_dev(d, k, stream=None, opts=None, **kw):

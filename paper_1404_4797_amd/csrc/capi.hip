@@ -468,6 +468,24 @@ int sclap_initial_partition(const sclap_graph* g, int32_t k, int32_t* part) {
     });
 }
 
+int sclap_initial_partition_lp_dev(const sclap_graph* g, int32_t k, int64_t T, int64_t Lmax, uint64_t seed,
+                                   int32_t level, int32_t rounds, const sclap_options* opt, int32_t* part,
+                                   int64_t* visits, void* stream) {
+    return guarded([&] {
+        hipStream_t s = as_stream(stream);
+        const Opts o = resolve(opt);
+        const DevGraph d = dev_view(g, s);
+        if (k < 1 || rounds < 0 || T < 0 || Lmax < 0) fail(SCLAP_ERR_INVALID, "bad k, rounds, T or Lmax");
+        if (d.n > 0 && !part) fail(SCLAP_ERR_INVALID, "part is NULL");
+        int64_t cV = 0, cmax = 0;
+        check_graph(d, o.validate != 0, &cV, &cmax, s);
+        const LPResult r = device_initial_partition(d, k, T, Lmax, seed, level, o.nsub, rounds, o.tune, part, s);
+        HIPCHK(hipStreamSynchronize(s));
+        if (visits) *visits = r.visits;
+        return SCLAP_OK;
+    });
+}
+
 int sclap_partition_dev(const sclap_graph* g, int32_t k, double eps, uint64_t seed, const sclap_options* opt,
                         int32_t* part, int64_t* cut, int64_t* block_w, sclap_stats* stats, void* stream) {
     return guarded([&] {

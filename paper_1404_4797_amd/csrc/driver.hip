@@ -44,6 +44,8 @@ Opts resolve(const sclap_options* o) {
     r.vcycles = o->vcycles == 0 ? 1 : o->vcycles;
     r.degree_order = o->degree_order != 0 ? 1 : 0;
     r.bucket_mean = o->contract_bucket_mean;
+    r.initial = o->initial_partitioner;
+    if (r.initial < 0 || r.initial > 1) fail(SCLAP_ERR_INVALID, "initial_partitioner must be 0 or 1");
     if (r.bucket_mean < 0) fail(SCLAP_ERR_INVALID, "contract_bucket_mean must be >= 0");
     if (r.vcycles < 1 || r.vcycles > 64) fail(SCLAP_ERR_INVALID, "vcycles must be in 1..64");
     if (r.coarsen_rounds < 0 || r.refine_rounds < 0) fail(SCLAP_ERR_INVALID, "round counts must be >= 0");
@@ -630,7 +632,7 @@ void multilevel_cycle(const DevGraph& g0, int32_t k, int64_t cV, int64_t cmax0, 
     st->levels = lev;
     // inner levels keep their rows unordered; the initial partition grows
     // blocks along ascending neighbour ids, so order the coarsest graph's rows
-    if (lev > 0 && !blk0) sort_rows(L[lev].own, s);
+    if (lev > 0 && !blk0 && o.initial == 0) sort_rows(L[lev].own, s);
     HIPCHK(hipStreamSynchronize(s));
     st->ms_coarsen += ms_since(t_coarsen);
 
@@ -647,6 +649,11 @@ void multilevel_cycle(const DevGraph& g0, int32_t k, int64_t cV, int64_t cmax0, 
         // the inherited partition of the coarsest graph
         if (nc > 0 && curp != blk_of(lev))
             HIPCHK(hipMemcpyAsync(curp, blk_of(lev), nc * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    } else if (o.initial == 1) {
+        // on the device: label propagation from hashed seeds
+        const int64_t T = (cV + k - 1) / k;
+        const LPResult r = device_initial_partition(Gc, k, T, Lmax, seed, lev, o.nsub, o.refine_rounds, o.tune, curp, s);
+        st->visits += r.visits;
     } else {
         // initial partition of the coarsest graph on the host
         const size_t bx = (static_cast<size_t>(nc) + 1) * sizeof(int64_t);
@@ -838,6 +845,7 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
     // many small graphs converge early: skipping their quiet nodes pays off
     if (o.tune.skip_quiet == 0) o.tune.skip_quiet = 1;
     if (G < 1) fail(SCLAP_ERR_INVALID, "count must be >= 1");
+    if (o.initial != 0) fail(SCLAP_ERR_INVALID, "initial_partitioner 1 is for single graphs only");
     if (!node_base || !k || !eps || !seed) fail(SCLAP_ERR_INVALID, "node_base, k, eps or seed is NULL");
     if (node_base[0] != 0 || node_base[G] != g0.n) fail(SCLAP_ERR_INVALID, "node_base must run from 0 to n");
     std::vector<int32_t> kb(static_cast<size_t>(G) + 1, 0);

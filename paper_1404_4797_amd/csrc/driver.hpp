@@ -22,6 +22,7 @@ struct Opts {
     int32_t vcycles = 1;
     int32_t degree_order = 0;
     int32_t bucket_mean = 0;  // contraction tuning
+    int32_t initial = 0;      // 0: host greedy growing; 1: device label propagation from seeds
     LPTuning tune;
 };
 

@@ -813,6 +813,107 @@ void core_ranks(const DevGraph& g, int32_t* out, hipStream_t s) {
     LAUNCHCHK();
 }
 
+// --------------------------------------------- device initial partition
+
+namespace {
+
+// positive-degree nodes: hash key and id at their rank
+__global__ void seed_keys_kernel(int32_t n, const int64_t* __restrict__ xadj, const int32_t* __restrict__ rank,
+                                 uint64_t prefix, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= n || xadj[v + 1] == xadj[v]) return;
+    keys[rank[v]] = mix64(prefix ^ static_cast<uint64_t>(static_cast<uint32_t>(v)));
+    vals[rank[v]] = static_cast<uint32_t>(v);
+}
+
+__global__ void place_seeds_kernel(int32_t count, const uint32_t* __restrict__ vals, int32_t* __restrict__ part) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < count) part[vals[i]] = i;
+}
+
+__global__ void add_to_kernel(int32_t* __restrict__ w, int32_t add) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) w[0] += add;
+}
+
+__global__ void pool_weight_kernel(int32_t n, const int32_t* __restrict__ part, int32_t pool,
+                                   const int32_t* __restrict__ vw, int32_t* __restrict__ pw) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v < n) pw[v] = part[v] == pool ? (vw ? vw[v] : 1) : 0;
+}
+
+// pool node with exclusive prefix weight P: first block whose cumulative room exceeds P
+__global__ void deal_pool_kernel(int32_t n, int32_t k, const int64_t* __restrict__ P,
+                                 const int64_t* __restrict__ cum, int32_t* __restrict__ part) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= n || part[v] != k) return;
+    const int64_t p = P[v];
+    int32_t lo = 0, hi = k;  // first b in [0, k) with cum[b] > p, k if none
+    while (lo < hi) {
+        const int32_t mid = lo + (hi - lo) / 2;
+        if (cum[mid] > p) hi = mid;
+        else lo = mid + 1;
+    }
+    part[v] = lo < k ? lo : k - 1;
+}
+
+}  // namespace
+
+LPResult device_initial_partition(const DevGraph& g, int32_t k, int64_t T, int64_t Lmax, uint64_t seed, int32_t level,
+                                  int32_t nsub, int32_t rounds, const LPTuning& tune, int32_t* part, hipStream_t s) {
+    constexpr int64_t kBig = int64_t(1) << 30;  // pool weight offset: never eligible, always overloaded
+    const int32_t n = g.n;
+    LPResult res;
+    if (n == 0) return res;
+    int64_t cV = 0, cmax = 0;
+    node_weight_stats(g, &cV, &cmax, s);
+    if (Lmax >= kBig || cV >= kBig) fail(-1, "device initial partition needs Lmax and c(V) below 2^30");
+    ProfScope ps("initial_seeds", 0, s);
+    DBuf<int32_t> flag(n, s), rank(n, s), tot(1, s);
+    has_degree_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, g.xadj, flag.get());
+    LAUNCHCHK();
+    exclusive_scan_i32(flag.get(), rank.get(), n, tot.get(), s);
+    int32_t npos = 0;
+    HIPCHK(hipMemcpyAsync(&npos, tot.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    fill_i32(part, k, n, s);  // everything starts in the pool
+    if (npos > 0) {
+        DBuf<uint64_t> keys(npos, s), ktmp(npos, s);
+        DBuf<uint32_t> vals(npos, s), vtmp(npos, s);
+        const uint64_t prefix = hash_prefix({seed, 5, static_cast<uint64_t>(static_cast<uint32_t>(level))});
+        seed_keys_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, g.xadj, rank.get(), prefix, keys.get(), vals.get());
+        LAUNCHCHK();
+        RadixScratch rs;
+        radix_sort_pairs(keys.get(), vals.get(), ktmp.get(), vtmp.get(), npos, 0, 64, rs, s);
+        const int32_t ns = std::min(k, npos);
+        place_seeds_kernel<<<grid_for(ns, 256), 256, 0, s>>>(ns, vals.get(), part);
+        LAUNCHCHK();
+    }
+    DBuf<int32_t> w(static_cast<size_t>(k) + 1, s);
+    label_weights(g, part, w.get(), k + 1, s);
+    add_to_kernel<<<1, 64, 0, s>>>(w.get() + k, static_cast<int32_t>(kBig));
+    LAUNCHCHK();
+    res = run_lp(g, kInitial, level, seed, nsub, rounds, Lmax, part, w.get(), k + 1, nullptr, tune, s);
+    // the pool fills the blocks' remaining room in block order
+    std::vector<int32_t> hw(static_cast<size_t>(k));
+    HIPCHK(hipMemcpyAsync(hw.data(), w.get(), k * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<int64_t> cum(static_cast<size_t>(k));
+    int64_t run = 0;
+    for (int32_t b = 0; b < k; ++b) {
+        run += hw[b] < T ? T - hw[b] : 0;
+        cum[b] = run;
+    }
+    DBuf<int64_t> dcum(k, s), P(n, s), ptot(1, s);
+    HIPCHK(hipMemcpyAsync(dcum.get(), cum.data(), k * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    pool_weight_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, part, k, g.vw, flag.get());
+    LAUNCHCHK();
+    exclusive_scan_i32_to_i64(flag.get(), P.get(), n, ptot.get(), s);
+    deal_pool_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, k, P.get(), dcum.get(), part);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(s));  // cum is read by the copy above
+    return res;
+}
+
 void project_kept(int32_t n, const int32_t* C, const int32_t* coarse_part, int32_t* part, hipStream_t s) {
     if (n == 0) return;
     project_kept_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, C, coarse_part, part);

@@ -107,6 +107,15 @@ void degree_colors(const DevGraph& g, int32_t G, const int32_t* gid, const int32
 // positive-degree core, renumbered (S entries).
 void core_ranks(const DevGraph& g, int32_t* out, hipStream_t s);
 
+// Initial partition by label propagation from hashed seeds with a pool label
+// k (never eligible, always overloaded): seeds are the min(k, #nodes with
+// neighbours) such nodes of smallest (H(seed, 5, level, v), v); `rounds`
+// rounds under Lmax with k + 1 labels (phase kInitial); the nodes left in the
+// pool fill the blocks' remaining room max(0, T - w(b)) in id and block order.
+// Writes part[n] in [0, k); returns the label-propagation statistics.
+LPResult device_initial_partition(const DevGraph& g, int32_t k, int64_t T, int64_t Lmax, uint64_t seed, int32_t level,
+                                  int32_t nsub, int32_t rounds, const LPTuning& tune, int32_t* part, hipStream_t s);
+
 void project_kept(int32_t n, const int32_t* C, const int32_t* coarse_part, int32_t* part, hipStream_t s);
 // part[v] += sign * add[gid[v]] (add: device array indexed by graph).
 void shift_by_graph(int32_t n, const int32_t* gid, const int32_t* add, int32_t sign, int32_t* part, hipStream_t s);

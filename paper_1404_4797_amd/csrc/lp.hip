@@ -1978,14 +1978,14 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     A.label = label;
     A.w = w;
     A.bound = bound;
-    A.refine = phase == kRefine ? 1 : 0;
+    A.refine = phase != kCluster ? 1 : 0;  // the initial phase follows the refinement rules
     A.gid = mg ? mg->gid : nullptr;
     A.g_tp = g_tp.get();
     A.g_bound = mg ? mg->bound : nullptr;
     A.g_lbase = mg ? mg->lbase : nullptr;
     const Bounds BB{bound, mg ? mg->lgid : nullptr, mg ? mg->bound : nullptr};
     // refinement labels are blocks: dense connection arrays when few enough
-    const int32_t dense_k = phase == kRefine ? (mg ? mg->max_labels : nw) : 0;
+    const int32_t dense_k = phase != kCluster ? (mg ? mg->max_labels : nw) : 0;
     A.dense_k = dense_k > 0 && dense_k <= kDenseMax ? dense_k : 0;
     const bool dense = A.dense_k > 0;
     DBuf<int32_t> hub_sum;
@@ -2023,7 +2023,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     // row offsets, own label and weight (and w(own) when refining) and its
     // result (target, gain); per slot the neighbour id, edge weight and
     // neighbour label (1, 2 or 4 bytes).
-    const double node_bytes = 4.0 + 16.0 + 4.0 + (g.vw ? 4.0 : 0.0) + (phase == kRefine ? 4.0 : 0.0) + 8.0;
+    const double node_bytes = 4.0 + 16.0 + 4.0 + (g.vw ? 4.0 : 0.0) + (phase != kCluster ? 4.0 : 0.0) + 8.0;
     const double slot_bytes = 4.0 + (nw <= 256 ? 1.0 : nw <= 65536 ? 2.0 : 4.0) + (g.ew ? 4.0 : 0.0);
     auto eval_bytes = [&](int64_t nodes_in, unsigned long long slots_in) {
         return node_bytes * static_cast<double>(nodes_in) + slot_bytes * static_cast<double>(slots_in);
@@ -2232,7 +2232,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 HIPCHK(hipMemcpyAsync(hctr, ctr.get(), sizeof(Counters), hipMemcpyDeviceToHost, s));
                 HIPCHK(hipStreamSynchronize(s));
                 fprintf(stderr, "[sclap] %s L%d r%d s%d n=%lld cand=%u slow=%u targets=%u gain=[%d,%d] hubs=%d\n",
-                        phase == kRefine ? "refine" : "cluster", level, r, sc, static_cast<long long>(ccount),
+                        phase != kCluster ? "refine" : "cluster", level, r, sc, static_cast<long long>(ccount),
                         hctr->ncand, hctr->nslow, hctr->nseg, hctr->nslow ? hctr->gmin : 0,
                         hctr->nslow ? hctr->gmax : 0, plans[sc].count);
             }

@@ -6,7 +6,9 @@
 
 namespace sclap {
 
-enum Phase : int32_t { kCluster = 0, kRefine = 1 };
+// kInitial: label propagation of the device initial partitioner; refinement
+// rules, its own hash phase.
+enum Phase : int32_t { kCluster = 0, kRefine = 1, kInitial = 2 };
 
 struct DevGraph {
     int32_t n = 0;
