@@ -88,7 +88,7 @@ def recorded_traffic(kernel, workload):
     return None
 
 
-def batch_comparison(ngraphs, seed, log_lo, log_hi):
+def batch_comparison(ngraphs, seed, log_lo, log_hi, extra=None):
     """Batched vs plain on the same device-resident mix: all graphs in one
     batched call, then each graph by itself through the one-graph entry
     point; per-graph parts and cuts must be identical."""
@@ -108,16 +108,17 @@ def batch_comparison(ngraphs, seed, log_lo, log_hi):
     dgs = [sc.to_device(g, "cuda") for g in gs]
     part = torch.empty(max(u["n"], 1), dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
-    r = sc.partition_batch_dev(du, nb, ks, eps, seeds, part=part, stream=stream)  # warmup
+    extra = extra or {}
+    r = sc.partition_batch_dev(du, nb, ks, eps, seeds, part=part, stream=stream, **extra)  # warmup
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r = sc.partition_batch_dev(du, nb, ks, eps, seeds, part=part, stream=stream)
+    r = sc.partition_batch_dev(du, nb, ks, eps, seeds, part=part, stream=stream, **extra)
     torch.cuda.synchronize()
     t_default = time.perf_counter() - t0
     ref_part = part.clone()
     # degree-bucket thresholds tuned on one clustering round of the union
     t0 = time.perf_counter()
-    o = sc.autotune_dev(du, int(np.median(ks)), stream=stream)
+    o = sc.autotune_dev(du, int(np.median(ks)), stream=stream, **extra)
     torch.cuda.synchronize()
     t_tune = time.perf_counter() - t0
     tuned = [o.lane_max_degree, o.wave_max_degree, o.block_max_degree]
@@ -137,7 +138,7 @@ def batch_comparison(ngraphs, seed, log_lo, log_hi):
         p = torch.empty(max(gs[i]["n"], 1), dtype=torch.int32, device="cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        q = sc.partition_dev(dg, ks[i], eps[i], seeds[i], part=p, stream=stream)
+        q = sc.partition_dev(dg, ks[i], eps[i], seeds[i], part=p, stream=stream, **extra)
         torch.cuda.synchronize()
         t_plain += time.perf_counter() - t0
         visits_plain += q["stats"]["visits"]
@@ -420,7 +421,7 @@ def main():
     if args.mesh_log2 > 0:
         out["mesh"] = mesh_runs(args.mesh_log2, w["k"], w["eps"], w["seed"])
     if args.batch_graphs > 0:
-        out["batched"] = batch_comparison(args.batch_graphs, 0, args.batch_log2[0], args.batch_log2[1])
+        out["batched"] = batch_comparison(args.batch_graphs, 0, args.batch_log2[0], args.batch_log2[1], extra)
     if args.serve_requests > 0:
         out["serving"] = serve_benchmark(args.serve_requests, args.serve_log2[0], args.serve_log2[1],
                                          args.serve_rates, plain_sample=24)

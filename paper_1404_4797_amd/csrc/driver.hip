@@ -834,6 +834,214 @@ void upload_vec(DBuf<T>& d, const std::vector<T>& h, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(d.get(), h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
+__global__ void pool_init_kernel(int32_t n, const int32_t* __restrict__ gid, const int32_t* __restrict__ pool,
+                                 int32_t* __restrict__ part) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v < n) part[v] = pool[gid[v]];
+}
+
+__global__ void seed_flag_kernel(int32_t n, const int64_t* __restrict__ xadj, const int32_t* __restrict__ gid,
+                                 const uint8_t* __restrict__ act, int32_t* __restrict__ flag) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v < n) flag[v] = (act[gid[v]] && xadj[v + 1] > xadj[v]) ? 1 : 0;
+}
+
+__global__ void batch_seed_keys_kernel(int32_t n, const int32_t* __restrict__ flag, const int32_t* __restrict__ rank,
+                                       const int32_t* __restrict__ gid, const int32_t* __restrict__ nbase,
+                                       const uint64_t* __restrict__ prefix, uint64_t* __restrict__ keys,
+                                       uint32_t* __restrict__ vals, int32_t* __restrict__ gcount) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= n || !flag[v]) return;
+    const int32_t g = gid[v];
+    keys[rank[v]] = mix64(prefix[g] ^ static_cast<uint64_t>(static_cast<uint32_t>(v - nbase[g])));
+    vals[rank[v]] = static_cast<uint32_t>(v);
+    atomicAdd(&gcount[g], 1);
+}
+
+__global__ void gid_keys_kernel(int32_t m, const uint32_t* __restrict__ vals, const int32_t* __restrict__ gid,
+                                uint64_t* __restrict__ keys) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < m) keys[i] = static_cast<uint32_t>(gid[vals[i]]);
+}
+
+__global__ void batch_place_seeds_kernel(int32_t m, const uint32_t* __restrict__ vals, const int32_t* __restrict__ gid,
+                                         const int32_t* __restrict__ start, const int32_t* __restrict__ kg,
+                                         const int32_t* __restrict__ kb2, int32_t* __restrict__ part) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    const int32_t v = static_cast<int32_t>(vals[i]);
+    const int32_t g = gid[v];
+    const int32_t r = i - start[g];
+    if (r < kg[g]) part[v] = kb2[g] + r;
+}
+
+__global__ void pool_offset_kernel(int32_t G, const uint8_t* __restrict__ act, const int32_t* __restrict__ pool,
+                                   int32_t* __restrict__ w, int32_t add) {
+    const int32_t g = blockIdx.x * 256 + threadIdx.x;
+    if (g < G && act[g]) w[pool[g]] += add;
+}
+
+__global__ void batch_pool_weight_kernel(int32_t n, const int32_t* __restrict__ gid, const uint8_t* __restrict__ act,
+                                         const int32_t* __restrict__ pool, const int32_t* __restrict__ part,
+                                         const int32_t* __restrict__ vw, int32_t* __restrict__ pw) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= n) return;
+    const int32_t g = gid[v];
+    pw[v] = (act[g] && part[v] == pool[g]) ? (vw ? vw[v] : 1) : 0;
+}
+
+// blocks of the graphs that end here, in the batch's block space: pool nodes
+// fill the remaining room of their graph's blocks by their prefix weight
+__global__ void batch_deal_kernel(int32_t n, const int32_t* __restrict__ gid, const uint8_t* __restrict__ act,
+                                  const int32_t* __restrict__ nbase, const int32_t* __restrict__ kg,
+                                  const int32_t* __restrict__ kb2, const int32_t* __restrict__ kb,
+                                  const int64_t* __restrict__ P, const int64_t* __restrict__ cum,
+                                  int32_t* __restrict__ part) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= n) return;
+    const int32_t g = gid[v];
+    if (!act[g]) return;
+    int32_t local = part[v] - kb2[g];
+    const int32_t k = kg[g];
+    if (local == k) {
+        const int64_t p = P[v] - P[nbase[g]];
+        const int64_t* c = cum + kb2[g];
+        int32_t lo = 0, hi = k;
+        while (lo < hi) {
+            const int32_t mid = lo + (hi - lo) / 2;
+            if (c[mid] > p) hi = mid;
+            else lo = mid + 1;
+        }
+        local = lo < k ? lo : k - 1;
+    }
+    part[v] = kb[g] + local;
+}
+
+// The device initial partitioner for every graph of a batch level whose
+// coarsest level this is (ending[g]), as device_initial_partition does for one
+// graph: each graph gets k_g + 1 labels (its pool last) in a label space of
+// its own, its seeds from its own hash, its own bound and rooms.  Writes the
+// ending graphs' blocks, in the batch's block space, into part; the other
+// nodes of the level are left for the projection.
+LPResult batch_device_initial(const DevGraph& g, const int32_t* gid, const std::vector<int32_t>& ids,
+                              const std::vector<int32_t>& nb, int32_t level, int32_t G, const int32_t* k,
+                              const std::vector<int32_t>& kb, const std::vector<int64_t>& T,
+                              const std::vector<int64_t>& cV, const std::vector<int64_t>& Lmax,
+                              const std::vector<uint8_t>& ending, const std::vector<uint64_t>& cseed,
+                              const uint64_t* d_seed, const int64_t* d_bound, const Opts& o, int32_t* part,
+                              hipStream_t s) {
+    constexpr int64_t kBig = int64_t(1) << 30;
+    const int32_t n = g.n;
+    std::vector<int32_t> kb2(static_cast<size_t>(G) + 1, 0), pool(G), nbase(G, 0), kg(k, k + G);
+    for (int32_t x = 0; x < G; ++x) {
+        kb2[x + 1] = kb2[x] + k[x] + 1;
+        pool[x] = kb2[x] + k[x];
+    }
+    const int32_t K2 = kb2[G];
+    std::vector<int32_t> lg(static_cast<size_t>(K2));
+    for (int32_t x = 0; x < G; ++x)
+        for (int32_t b = kb2[x]; b < kb2[x + 1]; ++b) lg[b] = x;
+    std::vector<uint8_t> act(G, 0);
+    std::vector<uint64_t> prefix(G, 0);
+    int32_t max_labels = 1;
+    for (size_t m = 0; m < ids.size(); ++m) {
+        const int32_t x = ids[m];
+        nbase[x] = nb[m];
+        if (!ending[x]) continue;
+        if (Lmax[x] >= kBig || cV[x] >= kBig) fail(SCLAP_ERR_INVALID, "device initial partition needs Lmax and c(V) below 2^30");
+        act[x] = 1;
+        prefix[x] = hash_prefix({cseed[x], 5, static_cast<uint64_t>(static_cast<uint32_t>(level))});
+        max_labels = std::max(max_labels, k[x] + 1);
+    }
+    DBuf<int32_t> d_kb2(static_cast<size_t>(G) + 1, s), d_pool(G, s), d_nbase(G, s), d_kg(G, s), d_kb(G, s),
+        d_lg(std::max(K2, 1), s), d_gcount(G, s), d_start(G, s);
+    DBuf<uint8_t> d_act(G, s);
+    DBuf<uint64_t> d_prefix(G, s);
+    upload_vec(d_kb2, kb2, s);
+    upload_vec(d_pool, pool, s);
+    upload_vec(d_nbase, nbase, s);
+    upload_vec(d_kg, kg, s);
+    upload_vec(d_kb, std::vector<int32_t>(kb.begin(), kb.begin() + G), s);
+    upload_vec(d_lg, lg, s);
+    upload_vec(d_act, act, s);
+    upload_vec(d_prefix, prefix, s);
+    fill_i32(d_gcount.get(), 0, G, s);
+    pool_init_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, gid, d_pool.get(), part);
+    LAUNCHCHK();
+    // seeds: per graph the k smallest (hash, id) among its nodes with neighbours
+    DBuf<int32_t> flag(n, s), rank(n, s), tot(1, s);
+    seed_flag_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, g.xadj, gid, d_act.get(), flag.get());
+    LAUNCHCHK();
+    exclusive_scan_i32(flag.get(), rank.get(), n, tot.get(), s);
+    int32_t ncand = 0;
+    HIPCHK(hipMemcpyAsync(&ncand, tot.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (ncand > 0) {
+        DBuf<uint64_t> keys(ncand, s), ktmp(ncand, s);
+        DBuf<uint32_t> vals(ncand, s), vtmp(ncand, s);
+        batch_seed_keys_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, flag.get(), rank.get(), gid, d_nbase.get(),
+                                                                d_prefix.get(), keys.get(), vals.get(),
+                                                                d_gcount.get());
+        LAUNCHCHK();
+        RadixScratch rs;
+        radix_sort_pairs(keys.get(), vals.get(), ktmp.get(), vtmp.get(), ncand, 0, 64, rs, s);
+        gid_keys_kernel<<<grid_for(ncand, 256), 256, 0, s>>>(ncand, vals.get(), gid, keys.get());
+        LAUNCHCHK();
+        radix_sort_pairs(keys.get(), vals.get(), ktmp.get(), vtmp.get(), ncand, 0,
+                         std::max(1, bits_for(static_cast<uint64_t>(std::max(G - 1, 1)))), rs, s);
+        std::vector<int32_t> gc(G), start(G, 0);
+        HIPCHK(hipMemcpyAsync(gc.data(), d_gcount.get(), G * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int32_t x = 1; x < G; ++x) start[x] = start[x - 1] + gc[x - 1];
+        upload_vec(d_start, start, s);
+        batch_place_seeds_kernel<<<grid_for(ncand, 256), 256, 0, s>>>(ncand, vals.get(), gid, d_start.get(),
+                                                                      d_kg.get(), d_kb2.get(), part);
+        LAUNCHCHK();
+        HIPCHK(hipStreamSynchronize(s));  // start is read by the upload above
+    }
+    DBuf<int32_t> w(std::max(K2, 1), s);
+    label_weights(g, part, w.get(), K2, s);
+    pool_offset_kernel<<<grid_for(G, 256), 256, 0, s>>>(G, d_act.get(), d_pool.get(), w.get(), static_cast<int32_t>(kBig));
+    LAUNCHCHK();
+    MultiGraph mg;
+    mg.G = G;
+    mg.gid = gid;
+    mg.lgid = d_lg.get();
+    mg.max_labels = max_labels;
+    mg.nbase = d_nbase.get();
+    mg.lbase = d_kb2.get();
+    mg.bound = d_bound;
+    mg.seed = d_seed;
+    mg.active = d_act.get();
+    const LPResult r = run_lp(g, kInitial, level, 0, o.nsub, o.refine_rounds, 0, part, w.get(), K2, nullptr, o.tune, s,
+                              &mg);
+    // pools fill their graph's remaining room
+    std::vector<int32_t> hw(static_cast<size_t>(std::max(K2, 1)));
+    HIPCHK(hipMemcpyAsync(hw.data(), w.get(), std::max(K2, 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<int64_t> cum(static_cast<size_t>(std::max(K2, 1)), 0);
+    for (int32_t x = 0; x < G; ++x) {
+        if (!act[x]) continue;
+        int64_t run = 0;
+        for (int32_t b = 0; b < k[x]; ++b) {
+            const int64_t wb = hw[kb2[x] + b];
+            run += wb < T[x] ? T[x] - wb : 0;
+            cum[kb2[x] + b] = run;
+        }
+    }
+    DBuf<int64_t> d_cum(std::max(K2, 1), s), P(n, s), ptot(1, s);
+    upload_vec(d_cum, cum, s);
+    batch_pool_weight_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, gid, d_act.get(), d_pool.get(), part, g.vw,
+                                                              flag.get());
+    LAUNCHCHK();
+    exclusive_scan_i32_to_i64(flag.get(), P.get(), n, ptot.get(), s);
+    batch_deal_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, gid, d_act.get(), d_nbase.get(), d_kg.get(), d_kb2.get(),
+                                                       d_kb.get(), P.get(), d_cum.get(), part);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(s));  // the host vectors uploaded above stay alive until here
+    return r;
+}
+
 
 }  // namespace
 
@@ -845,7 +1053,6 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
     // many small graphs converge early: skipping their quiet nodes pays off
     if (o.tune.skip_quiet == 0) o.tune.skip_quiet = 1;
     if (G < 1) fail(SCLAP_ERR_INVALID, "count must be >= 1");
-    if (o.initial != 0) fail(SCLAP_ERR_INVALID, "initial_partitioner 1 is for single graphs only");
     if (!node_base || !k || !eps || !seed) fail(SCLAP_ERR_INVALID, "node_base, k, eps or seed is NULL");
     if (node_base[0] != 0 || node_base[G] != g0.n) fail(SCLAP_ERR_INVALID, "node_base must run from 0 to n");
     std::vector<int32_t> kb(static_cast<size_t>(G) + 1, 0);
@@ -1067,8 +1274,10 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
         std::vector<uint8_t> ends(static_cast<size_t>(top) + 1, 0);
         for (int32_t l = 0; l <= top; ++l)
             for (size_t m = 0; m < L[l].ids.size(); ++m) mpos[L[l].ids[m]] = static_cast<int32_t>(m);
-        if (!carry)
-            for (int32_t g = 0; g < G; ++g) ends[last[g]] = 1;
+        // device initial partitions run level by level in the refinement loop
+        const bool dev_ip = o.initial == 1 && !carry;
+        std::vector<uint8_t> ends_dev(static_cast<size_t>(top) + 1, 0);
+        for (int32_t g = 0; g < G; ++g) (dev_ip ? ends_dev : ends)[last[g]] = carry ? 0 : 1;
         auto rnd8 = [](size_t x) { return (x + 7) & ~static_cast<size_t>(7); };
         std::vector<size_t> lofs(static_cast<size_t>(top) + 2, 0);
         for (int32_t l = 0; l <= top; ++l) {
@@ -1107,7 +1316,7 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
             HIPCHK(hipStreamSynchronize(s));
         }
         const unsigned hw = std::thread::hardware_concurrency();
-        if (!carry) parallel_for(G, static_cast<int32_t>(std::min(16u, hw ? hw : 1u)), [&](int32_t g) {
+        if (!carry && !dev_ip) parallel_for(G, static_cast<int32_t>(std::min(16u, hw ? hw : 1u)), [&](int32_t g) {
             const int32_t l = last[g];
             const BatchLevel& B = L[l];
             const LevelHost& h = lh[l];
@@ -1131,6 +1340,7 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
         upload_vec(d_bound, Lmax, s);
         upload_vec(d_active, std::vector<uint8_t>(G, 1), s);
         DBuf<int32_t> cur;
+        double ip_ms = 0;
         for (int32_t l = top; l >= 0; --l) {
             BatchLevel& B = L[l];
             const int32_t n = B.g.n;
@@ -1145,6 +1355,16 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
             // graphs ending here: their initial partitions (the other ranges
             // are overwritten by the projection next)
             if (ends[l] && n > 0) HIPCHK(hipMemcpyAsync(part, lh[l].p, n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            if (ends_dev[l] && n > 0) {
+                std::vector<uint8_t> endg(G, 0);
+                for (size_t m = 0; m < B.ids.size(); ++m)
+                    if (last[B.ids[m]] == l) endg[B.ids[m]] = 1;
+                auto t_ip = Clock::now();
+                const LPResult ri = batch_device_initial(B.g, B.gid.get(), B.ids, B.nb, l, G, k, kb, T, cV, Lmax, endg,
+                                                         cseed, d_seed.get(), d_bound.get(), o, part, s);
+                st->visits += ri.visits;
+                ip_ms += ms_since(t_ip);
+            }
             if (l < top) project_kept(n, B.C.get(), cur.get(), part, s);
             std::vector<int32_t> base(G, 0);
             for (size_t m = 0; m < B.ids.size(); ++m) base[B.ids[m]] = B.nb[m];
@@ -1174,7 +1394,8 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
             B.C.release();
         }
         HIPCHK(hipStreamSynchronize(s));
-        st->ms_refine += ms_since(t_ref);
+        st->ms_refine += ms_since(t_ref) - ip_ms;
+        st->ms_initial += ip_ms;
     }  // cycles
     auto t_fin = Clock::now();
     std::vector<int32_t> hw_(std::max(K, 1));

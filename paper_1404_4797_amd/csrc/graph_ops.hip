@@ -867,7 +867,6 @@ LPResult device_initial_partition(const DevGraph& g, int32_t k, int64_t T, int64
     int64_t cV = 0, cmax = 0;
     node_weight_stats(g, &cV, &cmax, s);
     if (Lmax >= kBig || cV >= kBig) fail(-1, "device initial partition needs Lmax and c(V) below 2^30");
-    ProfScope ps("initial_seeds", 0, s);
     DBuf<int32_t> flag(n, s), rank(n, s), tot(1, s);
     has_degree_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, g.xadj, flag.get());
     LAUNCHCHK();
@@ -877,6 +876,7 @@ LPResult device_initial_partition(const DevGraph& g, int32_t k, int64_t T, int64
     HIPCHK(hipStreamSynchronize(s));
     fill_i32(part, k, n, s);  // everything starts in the pool
     if (npos > 0) {
+        ProfScope ps("initial_seeds", 0, s);
         DBuf<uint64_t> keys(npos, s), ktmp(npos, s);
         DBuf<uint32_t> vals(npos, s), vtmp(npos, s);
         const uint64_t prefix = hash_prefix({seed, 5, static_cast<uint64_t>(static_cast<uint32_t>(level))});

@@ -2,7 +2,7 @@
 a pool label) against the oracle, bit for bit: the partitioner alone
 (several k, round counts, weighted graphs, isolated nodes, more blocks than
 nodes with neighbours) and full partitions with initial_partitioner = 1,
-plus its range checks.
+the batched path, plus its range checks.
 """
 import numpy as np
 import pytest
@@ -86,5 +86,20 @@ def test_device_initial_range_checks(sc):
     g = synth.ba(500, 2, seed=1)
     with pytest.raises(sc.SclapError):
         sc.partition(g, 4, 0.03, 1, initial_partitioner=2)
-    with pytest.raises(sc.SclapError):  # batches keep the host partitioner
-        sc.partition_batch([g, g], [2, 2], [0.03, 0.03], [1, 2], initial_partitioner=1)
+
+
+def test_batch_with_device_initial(sc):
+    # every graph of a batch gets its own seeds, pool, bound and rooms: its
+    # result equals the oracle's for that graph alone
+    gs = synth.batch_mix(12, seed=8, n_lo_log2=8, n_hi_log2=13)
+    ks = [g["k"] for g in gs]
+    eps = [g["eps"] for g in gs]
+    seeds = [g["seed"] for g in gs]
+    for vc in (1, 2):
+        say("batch initial=1 vcycles", vc)
+        r = sc.partition_batch(gs, ks, eps, seeds, coarsest_nodes=400, initial_partitioner=1, vcycles=vc)
+        for i, g in enumerate(gs):
+            ref = oracle.partition(g, ks[i], eps[i], seeds[i], coarsest_nodes=400, initial=1, vcycles=vc)
+            got = r["graphs"][i]
+            assert np.array_equal(got["part"], ref["part"]), (vc, i)
+            assert got["cut"] == ref["cut"], (vc, i)
