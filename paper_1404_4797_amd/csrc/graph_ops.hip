@@ -30,10 +30,13 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v
     return t;
 }
 
-// Grid-stride over tiles; one atomic per workgroup.
+// Grid-stride over tiles; one atomic per workgroup.  P: the block type read
+// for every neighbour (a byte copy when k <= 256: four times the neighbours
+// per cache line of the random gather).
+template <typename P>
 __global__ void __launch_bounds__(kTileThreads) cut_kernel(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj,
                                                            const int32_t* __restrict__ ew, int32_t n, int64_t S,
-                                                           const int32_t* __restrict__ part,
+                                                           const P* __restrict__ part,
                                                            unsigned long long* __restrict__ cut) {
     __shared__ int32_t owner[kTile];
     unsigned long long acc = 0;
@@ -49,6 +52,11 @@ __global__ void __launch_bounds__(kTileThreads) cut_kernel(const int64_t* __rest
     }
     acc = block_sum_u64(acc);
     if (threadIdx.x == 0 && acc) atomicAdd(cut, acc);
+}
+
+__global__ void to_u8_kernel(int32_t n, const int32_t* __restrict__ part, uint8_t* __restrict__ out) {
+    const int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v < n) out[v] = static_cast<uint8_t>(part[v]);
 }
 
 __global__ void __launch_bounds__(256) block_weight_kernel(int32_t n, const int32_t* __restrict__ part,
@@ -180,7 +188,16 @@ void cut_and_weights(const DevGraph& g, const int32_t* part, int32_t k, int64_t*
     DBuf<unsigned long long> acc(1 + static_cast<size_t>(k), s);
     HIPCHK(hipMemsetAsync(acc.get(), 0, (1 + static_cast<size_t>(k)) * sizeof(unsigned long long), s));
     if (g.S > 0) {
-        cut_kernel<<<capped_tiles(g.S), kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, g.n, g.S, part, acc.get());
+        if (k <= 256) {
+            DBuf<uint8_t> p8(g.n, s);
+            to_u8_kernel<<<grid_for(g.n, 256), 256, 0, s>>>(g.n, part, p8.get());
+            LAUNCHCHK();
+            cut_kernel<uint8_t><<<capped_tiles(g.S), kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, g.n, g.S, p8.get(),
+                                                                          acc.get());
+        } else {
+            cut_kernel<int32_t><<<capped_tiles(g.S), kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, g.n, g.S, part,
+                                                                          acc.get());
+        }
         LAUNCHCHK();
     }
     if (g.n > 0) {
