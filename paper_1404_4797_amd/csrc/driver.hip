@@ -128,26 +128,26 @@ void parallel_for(int32_t count, int32_t threads, F f) {
 }
 
 // Smallest index >= from whose value is <= cap, over a segment tree of mins.
-struct MinTree {
+struct MinTree {  // node weights are int32; INT32_MAX marks an erased leaf
     int64_t size = 1;
-    std::vector<int64_t> t;
+    std::vector<int32_t> t;
     explicit MinTree(const std::vector<int64_t>& a) {
         while (size < static_cast<int64_t>(a.size())) size <<= 1;
-        t.assign(2 * static_cast<size_t>(size), INT64_MAX);
-        for (size_t i = 0; i < a.size(); ++i) t[size + i] = a[i];
-        for (int32_t i = size - 1; i > 0; --i) t[i] = std::min(t[2 * i], t[2 * i + 1]);
+        t.assign(2 * static_cast<size_t>(size), INT32_MAX);
+        for (size_t i = 0; i < a.size(); ++i) t[size + i] = static_cast<int32_t>(a[i]);
+        for (int64_t i = size - 1; i > 0; --i) t[i] = std::min(t[2 * i], t[2 * i + 1]);
     }
     void erase(int64_t i) {
         int64_t p = i + size;
-        t[p] = INT64_MAX;
+        t[p] = INT32_MAX;
         for (p >>= 1; p > 0; p >>= 1) {
-            const int64_t m = std::min(t[2 * p], t[2 * p + 1]);
+            const int32_t m = std::min(t[2 * p], t[2 * p + 1]);
             if (m == t[p]) break;  // ancestors keep their minima
             t[p] = m;
         }
     }
     int32_t first_le(int64_t from, int64_t cap) const { return static_cast<int32_t>(descend(1, 0, size, from, cap)); }
-    int64_t min() const { return t[1]; }
+    int64_t min() const { return t[1] == INT32_MAX ? INT64_MAX : t[1]; }
     int64_t descend(int64_t node, int64_t lo, int64_t hi, int64_t from, int64_t cap) const {
         if (hi <= from || t[node] > cap) return -1;
         if (hi - lo == 1) return lo;
@@ -338,16 +338,33 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
                     row = nb.data();
                     row_end = nb.data() + nb.size();
                 }
-                for (const int32_t* it = row; it != row_end; ++it) {
-                    const int32_t x = *it;
+                // eight neighbours at a time: a mask of the untaken ones without
+                // branches, then the set bits in order (each rechecked, since
+                // taking one can affect a later equal neighbour)
+                auto visit = [&](int32_t x) {
                     if (static_cast<uint32_t>(x) >= static_cast<uint32_t>(ncore)) {  // -1 from core_ranks:
                         nonsym = true;                                                // not symmetric
-                        continue;
+                        return;
                     }
-                    if ((ctaken[static_cast<size_t>(x) >> 6] >> (x & 63)) & 1ULL) continue;
-                    if (wcur + cw32[x] > T) continue;
+                    if ((ctaken[static_cast<size_t>(x) >> 6] >> (x & 63)) & 1ULL) return;
+                    if (wcur + cw32[x] > T) return;
                     take(x);
+                };
+                const int32_t* it = row;
+                for (; row_end - it >= 8; it += 8) {
+                    uint32_t m = 0;
+                    for (int q = 0; q < 8; ++q) {
+                        const uint32_t x = static_cast<uint32_t>(it[q]);
+                        const uint64_t word = x < static_cast<uint32_t>(ncore) ? ctaken[x >> 6] : 0ULL;
+                        m |= static_cast<uint32_t>(~(word >> (x & 63)) & 1ULL) << q;
+                    }
+                    while (m) {
+                        const int q = __builtin_ctz(m);
+                        m &= m - 1;
+                        visit(it[q]);
+                    }
                 }
+                for (; it != row_end; ++it) visit(*it);
             }
             from = si + 1;
         }
