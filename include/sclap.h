@@ -367,8 +367,8 @@ int sclap_autotune_dev(const sclap_graph* g, int32_t k, sclap_options* opt, void
  * the algorithmic bytes the launches must move: for node evaluation, per
  * evaluated node its list entry, row offsets, label and weight, and per
  * adjacency slot the neighbour id, edge weight and neighbour label), sets
- * *count and clears the totals.  Timing adds event records but does not
- * change any result.
+ * *count and clears the totals.  Timing adds event records (each one costs
+ * device time between launches) but does not change any result.
  */
 typedef struct {
     char name[48];
@@ -379,6 +379,15 @@ typedef struct {
 
 int sclap_profile_begin(void);
 int sclap_profile_end(sclap_kernel_stat* out, int32_t capacity, int32_t* count);
+
+/*
+ * Same as sclap_profile_begin, but only launches of the kernel named `name`
+ * (a name that sclap_profile_end reports, copied) get events; every other
+ * launch runs as with profiling off.  NULL or "" times every kernel.  For
+ * timing one kernel inside a measured run without the cost of events around
+ * all the others.
+ */
+int sclap_profile_begin_only(const char* name);
 
 #ifdef __cplusplus
 }

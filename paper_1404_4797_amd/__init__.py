@@ -37,7 +37,7 @@ EXPORTS = [
     "sclap_partition_batch", "sclap_partition_batch_dev",
     "sclap_server_create", "sclap_server_submit", "sclap_server_poll", "sclap_server_destroy",
     "sclap_autotune_dev", "sclap_trim_memory", "sclap_initial_partition_lp_dev",
-    "sclap_profile_begin", "sclap_profile_end",
+    "sclap_profile_begin", "sclap_profile_end", "sclap_profile_begin_only",
 ]
 
 
@@ -154,6 +154,7 @@ def load():
         "sclap_initial_partition_lp_dev": (ctypes.c_int, [G, i32, i64, i64, u64, i32, i32, O, vp, vp, vp]),
         "sclap_partition_batch_dev": (ctypes.c_int, [G, i32, vp, vp, vp, vp, O, vp, vp, vp, BST, vp]),
         "sclap_profile_begin": (ctypes.c_int, []),
+        "sclap_profile_begin_only": (ctypes.c_int, [ctypes.c_char_p]),
         "sclap_profile_end": (ctypes.c_int, [ctypes.POINTER(KernelStat), i32, vp]),
     }
     for name, (res, args) in sig.items():
@@ -444,9 +445,13 @@ def partition_dev(d, k, eps=0.03, seed=1, part=None, stream=None, opts=None, **k
     return {"part": part, "cut": c.value, "block_weights": bw, "status": status, "stats": st.to_dict()}
 
 
-def profile_begin():
-    """Starts per-kernel HIP-event timing of the library's launches on this thread."""
-    _check(load().sclap_profile_begin())
+def profile_begin(only=None):
+    """Starts per-kernel HIP-event timing of the library's launches on this
+    thread; with ``only``, of that kernel's launches alone."""
+    if only:
+        _check(load().sclap_profile_begin_only(only.encode()))
+    else:
+        _check(load().sclap_profile_begin())
 
 
 def profile_end():

@@ -582,9 +582,12 @@ int sclap_autotune_dev(const sclap_graph* g, int32_t k, sclap_options* opt, void
     });
 }
 
-int sclap_profile_begin(void) {
+int sclap_profile_begin(void) { return sclap_profile_begin_only(nullptr); }
+
+int sclap_profile_begin_only(const char* name) {
     return guarded([&] {
         profiler().reset();
+        profiler().only = name ? name : "";
         profiler().on = true;
         return SCLAP_OK;
     });

@@ -59,6 +59,7 @@ constexpr int kSmallLabels = 4096;       // LDS-private histograms up to this ma
 constexpr int kMaxBlocks = 1024;         // grid cap of the grid-stride candidate kernels
 constexpr int kSmallSeg = 4096;          // segments up to this length: one selecting workgroup
 constexpr int kSegChunk = 4096;          // entries per workgroup in the multi-workgroup selection
+constexpr int kLargeBlocks = 256;        // grid of the multi-workgroup selection kernels
 
 struct Counters {
     uint32_t ncand;        // candidates of the sub-round
@@ -1170,28 +1171,59 @@ __global__ void __launch_bounds__(256) admit_kernel(const int32_t* __restrict__ 
     }
 }
 
+// Multi-workgroup selection for segments longer than the single-workgroup
+// limit: the same most-significant-digit-first selection, with per-segment
+// histograms in HBM. A segment is registered when its target claims it: it
+// takes the next large index l and a run of kSegChunk-entry chunks.
+struct LargeSel {
+    int32_t* base;      // [nlarge] first entry of each large segment
+    int32_t* len;       // [nlarge] its entries
+    int32_t* chunk0;    // [nlarge] its first chunk
+    int32_t* owner;     // [nlchunks] large segment of each chunk
+    uint32_t* hist;     // [nlarge][256] weight per digit
+    uint64_t* prefix;   // [nlarge] digits fixed so far
+    int64_t* room;      // [nlarge] weight still admissible below the prefix
+    uint32_t* done;     // [nlarge] chunks finished with the current digit
+};
+
+__device__ __forceinline__ int32_t seg_chunks(int32_t len) { return (len + kSegChunk - 1) / kSegChunk; }
+
+__device__ void register_large(const LargeSel& L, int32_t base, int32_t len, int64_t room, Counters* ctr) {
+    const uint32_t l = atomicAdd(&ctr->nlarge, 1u);
+    const int32_t nch = seg_chunks(len);
+    const int32_t c0 = static_cast<int32_t>(atomicAdd(&ctr->nlchunks, static_cast<uint32_t>(nch)));
+    L.base[l] = base;
+    L.len[l] = len;
+    L.chunk0[l] = c0;
+    L.prefix[l] = 0;
+    L.room[l] = room;
+    for (int32_t c = 0; c < nch; ++c) L.owner[c0 + c] = static_cast<int32_t>(l);
+}
+
 // A target that cannot take all its candidates gets a segment of cnt[t]
 // entries (small label spaces: one thread per label).
 __global__ void __launch_bounds__(256) claim_small_kernel(int32_t nw, const int32_t* __restrict__ w,
                                                           const int32_t* __restrict__ tsum,
                                                           const int32_t* __restrict__ cnt, Bounds B,
                                                           int32_t* __restrict__ seg_off, int32_t* __restrict__ seg_list,
-                                                          int32_t* __restrict__ large_list, int32_t small_max,
-                                                          Counters* ctr) {
+                                                          LargeSel L, int32_t small_max, Counters* ctr) {
     const int32_t t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= nw || cnt[t] == 0 || static_cast<int64_t>(w[t]) + tsum[t] <= bound_of(B, t)) return;
-    seg_off[t] = static_cast<int32_t>(atomicAdd(&ctr->slow_total, static_cast<uint32_t>(cnt[t])));
+    if (t >= nw || cnt[t] == 0) return;
+    const int64_t room = bound_of(B, t) - static_cast<int64_t>(w[t]);
+    if (tsum[t] <= room) return;
+    const int32_t base = static_cast<int32_t>(atomicAdd(&ctr->slow_total, static_cast<uint32_t>(cnt[t])));
+    seg_off[t] = base;
     seg_list[atomicAdd(&ctr->nseg, 1u)] = t;
-    if (cnt[t] > small_max) large_list[atomicAdd(&ctr->nlarge, 1u)] = t;
+    if (cnt[t] > small_max) register_large(L, base, cnt[t], room, ctr);
 }
 
 // Same for large label spaces: the first slow candidate of a target claims;
 // each block tries a label once per chunk.
 __global__ void __launch_bounds__(256) claim_big_kernel(const uint32_t* __restrict__ slow_idx,
                                                         const int32_t* __restrict__ ct, const int32_t* __restrict__ cnt,
+                                                        const int32_t* __restrict__ w, Bounds B,
                                                         int32_t* __restrict__ seg_off, int32_t* __restrict__ seg_list,
-                                                        int32_t* __restrict__ large_list, int32_t small_max,
-                                                        Counters* ctr) {
+                                                        LargeSel L, int32_t small_max, Counters* ctr) {
     __shared__ int32_t keys[kAggTable];
     for (int j = threadIdx.x; j < kAggTable; j += 256) keys[j] = -1;
     __syncthreads();
@@ -1210,9 +1242,11 @@ __global__ void __launch_bounds__(256) claim_big_kernel(const uint32_t* __restri
                 h = (h + 1) & (kAggTable - 1);
             }
             if (!fresh || seg_off[t] != -1 || atomicCAS(&seg_off[t], -1, -2) != -1) continue;
-            seg_off[t] = static_cast<int32_t>(atomicAdd(&ctr->slow_total, static_cast<uint32_t>(cnt[t])));
+            const int32_t base = static_cast<int32_t>(atomicAdd(&ctr->slow_total, static_cast<uint32_t>(cnt[t])));
+            seg_off[t] = base;
             seg_list[atomicAdd(&ctr->nseg, 1u)] = t;
-            if (cnt[t] > small_max) large_list[atomicAdd(&ctr->nlarge, 1u)] = t;
+            if (cnt[t] > small_max)
+                register_large(L, base, cnt[t], bound_of(B, t) - static_cast<int64_t>(w[t]), ctr);
         }
         __syncthreads();
         for (int j = threadIdx.x; j < kAggTable; j += 256) keys[j] = -1;
@@ -1301,7 +1335,13 @@ __global__ void __launch_bounds__(256) select_kernel(const int32_t* __restrict__
         const int32_t t = seg_list[sid];
         const int32_t base = seg_off[t];
         const int32_t len = cnt[t];
-        if (len > small_max) continue;  // selected by the multi-workgroup kernels
+        if (len > small_max) {  // selected by the multi-workgroup kernels, which keep their own copy of the range
+            if (threadIdx.x == 0) {
+                seg_off[t] = -1;
+                seg_fill[t] = 0;
+            }
+            continue;
+        }
         if (threadIdx.x == 0) {
             s_prefix = 0;
             s_mask = 0;
@@ -1343,50 +1383,11 @@ __global__ void __launch_bounds__(256) select_kernel(const int32_t* __restrict__
     }
 }
 
-// Multi-workgroup selection for segments longer than kSmallSeg: the same
-// most-significant-digit-first selection, with per-segment histograms in HBM.
-struct LargeSel {
-    int32_t* large_list;    // [nlarge] target of each large segment
-    int32_t* chunk_first;   // [nlarge+1] first chunk of each large segment
-    uint32_t* hist;         // [nlarge][256] weight per digit
-    uint64_t* prefix;       // [nlarge] digits fixed so far
-    int64_t* room;          // [nlarge] weight still admissible below the prefix
-    uint32_t* done;         // [nlarge] chunks finished with the current digit
-};
-
-__global__ void large_setup_kernel(LargeSel L, const int32_t* __restrict__ cnt, const int32_t* __restrict__ w,
-                                   Bounds B, Counters* ctr) {
-    // one thread: chunk prefix over the large segments (their number is small)
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int32_t run = 0;
-    for (uint32_t l = 0; l < ctr->nlarge; ++l) {
-        const int32_t t = L.large_list[l];
-        L.chunk_first[l] = run;
-        run += (cnt[t] + kSegChunk - 1) / kSegChunk;
-        L.prefix[l] = 0;
-        L.room[l] = bound_of(B, t) - static_cast<int64_t>(w[t]);
-    }
-    L.chunk_first[ctr->nlarge] = run;
-    ctr->nlchunks = static_cast<uint32_t>(run);
-}
-
-__device__ __forceinline__ int32_t large_of_chunk(const LargeSel& L, uint32_t nlarge, int32_t c) {
-    int32_t lo = 0, hi = static_cast<int32_t>(nlarge);  // chunk_first[lo] <= c < chunk_first[hi]
-    while (hi - lo > 1) {
-        const int32_t mid = (lo + hi) / 2;
-        if (L.chunk_first[mid] <= c) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
 // One digit of the multi-workgroup selection: every block adds its chunk's
 // weight histogram to the segment's histogram in HBM; the last block to
 // finish a segment picks that segment's boundary digit with a block-wide scan
 // (no block waits for another).
 __global__ void __launch_bounds__(256) large_pass_kernel(LargeSel L, int pass, int bits_v,
-                                                         const int32_t* __restrict__ seg_off,
-                                                         const int32_t* __restrict__ cnt,
                                                          const uint64_t* __restrict__ skey,
                                                          const int32_t* __restrict__ swt, Counters* ctr) {
     __shared__ uint32_t h[256];
@@ -1402,11 +1403,10 @@ __global__ void __launch_bounds__(256) large_pass_kernel(LargeSel L, int pass, i
     const int32_t nch = static_cast<int32_t>(ctr->nlchunks);
     const int j = threadIdx.x;
     for (int32_t c = blockIdx.x; c < nch; c += gridDim.x) {
-        const int32_t l = large_of_chunk(L, nlarge, c);
-        const int32_t t = L.large_list[l];
-        const int32_t base = seg_off[t];
-        const int32_t len = cnt[t];
-        const int32_t i0 = (c - L.chunk_first[l]) * kSegChunk;
+        const int32_t l = L.owner[c];
+        const int32_t base = L.base[l];
+        const int32_t len = L.len[l];
+        const int32_t i0 = (c - L.chunk0[l]) * kSegChunk;
         const int32_t i1 = i0 + kSegChunk < len ? i0 + kSegChunk : len;
         const uint64_t prefix = L.prefix[l];
         uint32_t* hl = L.hist + static_cast<size_t>(l) * 256;
@@ -1422,7 +1422,7 @@ __global__ void __launch_bounds__(256) large_pass_kernel(LargeSel L, int pass, i
         __threadfence();
         __syncthreads();
         if (j == 0) {
-            const uint32_t nchunks = static_cast<uint32_t>(L.chunk_first[l + 1] - L.chunk_first[l]);
+            const uint32_t nchunks = static_cast<uint32_t>(seg_chunks(len));
             s_last = atomicAdd(&L.done[l], 1u) == nchunks - 1;
         }
         __syncthreads();
@@ -1462,44 +1462,53 @@ __global__ void __launch_bounds__(256) large_pass_kernel(LargeSel L, int pass, i
     }
 }
 
-__global__ void __launch_bounds__(256) large_admit_kernel(LargeSel L, int32_t* __restrict__ seg_off,
-                                                          int32_t* __restrict__ seg_fill,
-                                                          const int32_t* __restrict__ cnt,
-                                                          const uint64_t* __restrict__ skey,
+__global__ void __launch_bounds__(256) large_admit_kernel(LargeSel L, const uint64_t* __restrict__ skey,
                                                           const uint32_t* __restrict__ spos,
                                                           uint8_t* __restrict__ ok, const Counters* ctr) {
-    const uint32_t nlarge = ctr->nlarge;
     const int32_t nch = static_cast<int32_t>(ctr->nlchunks);
     for (int32_t c = blockIdx.x; c < nch; c += gridDim.x) {
-        const int32_t l = large_of_chunk(L, nlarge, c);
-        const int32_t t = L.large_list[l];
-        const int32_t base = seg_off[t];
-        const int32_t len = cnt[t];
-        const int32_t i0 = (c - L.chunk_first[l]) * kSegChunk;
+        const int32_t l = L.owner[c];
+        const int32_t base = L.base[l];
+        const int32_t len = L.len[l];
+        const int32_t i0 = (c - L.chunk0[l]) * kSegChunk;
         const int32_t i1 = i0 + kSegChunk < len ? i0 + kSegChunk : len;
         const uint64_t boundary = L.prefix[l];  // smallest key that does not fit
         for (int32_t i = i0 + threadIdx.x; i < i1; i += 256) ok[spos[base + i]] = skey[base + i] < boundary ? 1 : 0;
     }
 }
 
-__global__ void large_reset_kernel(LargeSel L, int32_t* __restrict__ seg_off, int32_t* __restrict__ seg_fill,
-                                   const Counters* ctr) {
-    const uint32_t nlarge = ctr->nlarge;
-    for (uint32_t l = blockIdx.x * 256 + threadIdx.x; l < nlarge; l += gridDim.x * 256) {
-        const int32_t t = L.large_list[l];
-        seg_off[t] = -1;
-        seg_fill[t] = 0;
-    }
+// The per-sub-round counters back to their empty state (the round's
+// candidate count is kept).
+__device__ __forceinline__ void clear_subround(Counters* ctr) {
+    ctr->ncand = 0;
+    ctr->nslow = 0;
+    ctr->gmin = INT_MAX;
+    ctr->gmax = INT_MIN;
+    ctr->nseg = 0;
+    ctr->slow_total = 0;
+    ctr->nlarge = 0;
+    ctr->nlchunks = 0;
 }
 
+// Moves the admitted candidates and updates the label weights; also clears
+// the per-target candidate sums and counts and the sub-round counters for the
+// next sub-round (no kernel of this one reads them any more).
 template <bool kSmall>
 __global__ void __launch_bounds__(256) apply_kernel(const int32_t* __restrict__ ct, const uint8_t* __restrict__ ok,
                                                     const int32_t* __restrict__ nodes, int32_t count,
                                                     const int32_t* __restrict__ vw, int32_t* __restrict__ label,
                                                     uint8_t* __restrict__ label8, uint16_t* __restrict__ label16,
                                                     int32_t* __restrict__ w, int32_t* __restrict__ tsum,
-                                                    int32_t* __restrict__ cnt, int32_t nw) {
+                                                    int32_t* __restrict__ cnt, int32_t nw, Counters* ctr) {
     __shared__ int32_t delta[kSmall ? kSmallLabels : 1];
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) clear_subround(ctr);
+        if (kSmall)
+            for (int j = threadIdx.x; j < nw; j += 256) {
+                tsum[j] = 0;
+                cnt[j] = 0;
+            }
+    }
     if (kSmall) {
         for (int j = threadIdx.x; j < nw; j += 256) delta[j] = 0;
         __syncthreads();
@@ -1562,14 +1571,7 @@ __global__ void __launch_bounds__(256) unquiet_kernel(const int32_t* __restrict_
 }
 
 __global__ void reset_counters_kernel(Counters* ctr, int round_too) {
-    ctr->ncand = 0;
-    ctr->nslow = 0;
-    ctr->gmin = INT_MAX;
-    ctr->gmax = INT_MIN;
-    ctr->nseg = 0;
-    ctr->slow_total = 0;
-    ctr->nlarge = 0;
-    ctr->nlchunks = 0;
+    clear_subround(ctr);
     if (round_too) ctr->round_cands = 0;
 }
 
@@ -1955,14 +1957,16 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     // multi-workgroup selection state: at most cap / kSmallSeg large segments
     const int32_t small_max = std::max(1, std::min(tune.select_small_max, kSmallSeg));
     const int64_t max_large = cap / small_max + 1;
-    DBuf<int32_t> large_list(max_large, s), chunk_first(max_large + 1, s);
+    const int64_t max_lchunks = cap / kSegChunk + max_large;
+    DBuf<int32_t> lbase(max_large, s), llen(max_large, s), lchunk0(max_large, s), lowner(max_lchunks, s);
     DBuf<uint32_t> lhist(max_large * 256, s);
     DBuf<uint64_t> lprefix(max_large, s);
     DBuf<int64_t> lroom(max_large, s);
     DBuf<uint32_t> ldone(max_large, s);
     fill_u32(lhist.get(), 0, max_large * 256, s);
     fill_u32(ldone.get(), 0, max_large, s);
-    LargeSel LS{large_list.get(), chunk_first.get(), lhist.get(), lprefix.get(), lroom.get(), ldone.get()};
+    LargeSel LS{lbase.get(), llen.get(), lchunk0.get(), lowner.get(), lhist.get(), lprefix.get(), lroom.get(),
+                ldone.get()};
     // digits of the selection key: node id bits plus at most 32 bits of gain range
     const int max_sel_passes = (bits_for(static_cast<uint64_t>(n - 1)) + 32 + 7) / 8;
     fill_i32(tsum.get(), 0, nw, s);
@@ -2197,36 +2201,35 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 if (small) {
                     claim_small_kernel<<<grid_for(nw, 256), 256, 0, s>>>(nw, w, tsum.get(), tcnt.get(), BB,
                                                                          seg_off.get(), seg_list.get(),
-                                                                         large_list.get(), small_max, ctr.get());
+                                                                         LS, small_max, ctr.get());
                     LAUNCHCHK();
                     scatter_kernel<true><<<gc, 256, 0, s>>>(slow_idx.get(), cnodes, ct.get(), cg.get(), g.vw, bits_v,
                                                             nw, seg_off.get(), seg_fill.get(), skey.get(), spos.get(),
                                                             swt.get(), ctr.get());
                 } else {
-                    claim_big_kernel<<<gc, 256, 0, s>>>(slow_idx.get(), ct.get(), tcnt.get(), seg_off.get(),
-                                                        seg_list.get(), large_list.get(), small_max, ctr.get());
+                    claim_big_kernel<<<gc, 256, 0, s>>>(slow_idx.get(), ct.get(), tcnt.get(), w, BB, seg_off.get(),
+                                                        seg_list.get(), LS, small_max, ctr.get());
                     LAUNCHCHK();
                     scatter_kernel<false><<<gc, 256, 0, s>>>(slow_idx.get(), cnodes, ct.get(), cg.get(), g.vw, bits_v,
                                                              nw, seg_off.get(), seg_fill.get(), skey.get(), spos.get(),
                                                              swt.get(), ctr.get());
                 }
                 LAUNCHCHK();
-                large_setup_kernel<<<1, 1, 0, s>>>(LS, tcnt.get(), w, BB, ctr.get());
-                LAUNCHCHK();
                 select_kernel<<<kMaxBlocks, 256, 0, s>>>(seg_list.get(), seg_off.get(), seg_fill.get(), tcnt.get(), w,
                                                          BB, bits_v, skey.get(), spos.get(), swt.get(), ok.get(),
                                                          small_max, ctr.get());
                 LAUNCHCHK();
-                for (int pass = max_sel_passes - 1; pass >= 0; --pass) {
-                    large_pass_kernel<<<kMaxBlocks, 256, 0, s>>>(LS, pass, bits_v, seg_off.get(), tcnt.get(),
-                                                                 skey.get(), swt.get(), ctr.get());
+                // a target has at most ccount candidates: no large segment
+                // unless the colour has more than the single-workgroup limit
+                if (ccount > small_max) {
+                    for (int pass = max_sel_passes - 1; pass >= 0; --pass) {
+                        large_pass_kernel<<<kLargeBlocks, 256, 0, s>>>(LS, pass, bits_v, skey.get(), swt.get(),
+                                                                       ctr.get());
+                        LAUNCHCHK();
+                    }
+                    large_admit_kernel<<<kLargeBlocks, 256, 0, s>>>(LS, skey.get(), spos.get(), ok.get(), ctr.get());
                     LAUNCHCHK();
                 }
-                large_admit_kernel<<<kMaxBlocks, 256, 0, s>>>(LS, seg_off.get(), seg_fill.get(), tcnt.get(),
-                                                              skey.get(), spos.get(), ok.get(), ctr.get());
-                LAUNCHCHK();
-                large_reset_kernel<<<1, 256, 0, s>>>(LS, seg_off.get(), seg_fill.get(), ctr.get());
-                LAUNCHCHK();
             }
             if (trace) {
                 HIPCHK(hipMemcpyAsync(hctr, ctr.get(), sizeof(Counters), hipMemcpyDeviceToHost, s));
@@ -2241,14 +2244,12 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 if (small) {
                     apply_kernel<true><<<capped_grid(ccount), 256, 0, s>>>(ct.get(), ok.get(), cnodes, ccount, g.vw,
                                                                            label, lab8.get(), lab16.get(), w,
-                                                                           tsum.get(), tcnt.get(), nw);
+                                                                           tsum.get(), tcnt.get(), nw, ctr.get());
                     LAUNCHCHK();
-                    fill_i32(tsum.get(), 0, nw, s);
-                    fill_i32(tcnt.get(), 0, nw, s);
                 } else {
                     apply_kernel<false><<<grid_for(ccount, 256), 256, 0, s>>>(ct.get(), ok.get(), cnodes, ccount,
                                                                               g.vw, label, lab8.get(), lab16.get(), w,
-                                                                              tsum.get(), tcnt.get(), nw);
+                                                                              tsum.get(), tcnt.get(), nw, ctr.get());
                     LAUNCHCHK();
                 }
             }
@@ -2259,8 +2260,6 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                                                                       A.quiet);
                 LAUNCHCHK();
             }
-            reset_counters_kernel<<<1, 1, 0, s>>>(ctr.get(), 0);
-            LAUNCHCHK();
         }
         // one host synchronisation per round: a round without candidates
         // moved nothing (the first candidate of every target is always admitted)

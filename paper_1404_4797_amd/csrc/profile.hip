@@ -9,6 +9,7 @@ Profiler& profiler() {
 }
 
 int Profiler::begin(const char* name, double bytes, hipStream_t s) {
+    if (!only.empty() && only != name) return -1;
     size_t idx = stats.size();
     for (size_t i = 0; i < stats.size(); ++i)
         if (stats[i].name == name) idx = i;

@@ -19,6 +19,7 @@ struct KernelStat {
 
 struct Profiler {
     bool on = false;
+    std::string only;  // when set, only scopes of this name are timed
     std::vector<KernelStat> stats;
     struct Pending {
         hipEvent_t a, b;
