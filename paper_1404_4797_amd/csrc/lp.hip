@@ -72,7 +72,8 @@ struct Counters {
     uint32_t round_cands;  // candidates of the round so far
     uint32_t nlarge;       // segments longer than kSmallSeg
     uint32_t nlchunks;     // kSegChunk-entry chunks of those segments
-    uint32_t pad[2];
+    int32_t gkey;          // gmax of the sub-round's keys, kept past the counter reset
+    uint32_t pad;
 };
 
 struct EvalArgs {
@@ -1121,14 +1122,76 @@ __global__ void __launch_bounds__(256) cand_accum_kernel(const int32_t* __restri
     }
 }
 
+// ------------------------------------------------------------- admission
+//
+// Outcome of a candidate in ok[p]: 0 not a candidate (or rejected), 1
+// admitted, kOkSlow aimed at a target that cannot take all its candidates.
+// The apply kernel decides those from the target's boundary key bnd[t]: a
+// candidate is admitted when its key [gmax - gain][node] is below it.
+constexpr uint8_t kOkSlow = 2;
+
+// Multi-workgroup selection for segments longer than the single-workgroup
+// limit: the same most-significant-digit-first selection with kLDigit-bit
+// digits and per-segment histograms in HBM. A segment is registered when its
+// target claims it: it takes the next large index l and a run of
+// kSegChunk-entry chunks.
+constexpr int kLDigit = 12;
+constexpr int kLBins = 1 << kLDigit;
+
+struct LargeSel {
+    int32_t* target;    // [nlarge] target of each large segment
+    int32_t* base;      // [nlarge] its first entry
+    int32_t* len;       // [nlarge] its entries
+    int32_t* chunk0;    // [nlarge] its first chunk
+    int32_t* owner;     // [nlchunks] large segment of each chunk
+    uint32_t* hist;     // [nlarge][kLBins] weight per digit
+    uint64_t* prefix;   // [nlarge] digits fixed so far
+    int64_t* room;      // [nlarge] weight still admissible below the prefix
+    uint32_t* done;     // [nlarge] chunks finished with the current digit
+};
+
+__device__ __forceinline__ int32_t seg_chunks(int32_t len) { return (len + kSegChunk - 1) / kSegChunk; }
+
+// Gives target t (room = bound - w(t)) a segment of cnt[t] entries, and a
+// large index when that is longer than small_max.
+__device__ void claim_segment(int32_t t, int32_t len, int64_t room, int32_t* seg_off, int32_t* seg_list,
+                              const LargeSel& L, int32_t small_max, Counters* ctr) {
+    const int32_t base = static_cast<int32_t>(atomicAdd(&ctr->slow_total, static_cast<uint32_t>(len)));
+    seg_off[t] = base;
+    seg_list[atomicAdd(&ctr->nseg, 1u)] = t;
+    if (len <= small_max) return;
+    const uint32_t l = atomicAdd(&ctr->nlarge, 1u);
+    const int32_t nch = seg_chunks(len);
+    const int32_t c0 = static_cast<int32_t>(atomicAdd(&ctr->nlchunks, static_cast<uint32_t>(nch)));
+    L.target[l] = t;
+    L.base[l] = base;
+    L.len[l] = len;
+    L.chunk0[l] = c0;
+    L.prefix[l] = 0;
+    L.room[l] = room;
+    for (int32_t c = 0; c < nch; ++c) L.owner[c0 + c] = static_cast<int32_t>(l);
+}
+
 // Fast path of admission: if everything aimed at t fits, admit it all;
-// otherwise the candidate goes to the slow list.
+// otherwise the candidate goes to the slow list and its target gets a
+// segment (small label spaces: the grid walks the labels; otherwise the first
+// slow candidate of a target claims it).
+template <bool kSmall>
 __global__ void __launch_bounds__(256) admit_kernel(const int32_t* __restrict__ ct, const int32_t* __restrict__ cg,
                                                     int32_t count, const int32_t* __restrict__ w,
-                                                    const int32_t* __restrict__ tsum, Bounds B,
+                                                    const int32_t* __restrict__ tsum,
+                                                    const int32_t* __restrict__ cnt, Bounds B,
                                                     uint8_t* __restrict__ ok, uint32_t* __restrict__ slow_idx,
-                                                    Counters* ctr) {
+                                                    int32_t* __restrict__ seg_off, int32_t* __restrict__ seg_list,
+                                                    LargeSel L, int32_t small_max, int32_t nw, Counters* ctr) {
     __shared__ int32_t s_min[4], s_max[4];
+    if (kSmall) {
+        for (int32_t t = blockIdx.x * 256 + threadIdx.x; t < nw; t += gridDim.x * 256) {
+            if (cnt[t] == 0) continue;
+            const int64_t room = bound_of(B, t) - static_cast<int64_t>(w[t]);
+            if (tsum[t] > room) claim_segment(t, cnt[t], room, seg_off, seg_list, L, small_max, ctr);
+        }
+    }
     const int32_t stride = gridDim.x * 256;
     const int32_t iters = (count + stride - 1) / stride;
     int32_t gmin = INT_MAX, gmax = INT_MIN;
@@ -1139,13 +1202,17 @@ __global__ void __launch_bounds__(256) admit_kernel(const int32_t* __restrict__ 
             const int32_t t = ct[p];
             uint8_t o = 0;
             if (t >= 0) {
-                if (static_cast<int64_t>(w[t]) + tsum[t] <= bound_of(B, t)) {
+                const int64_t room = bound_of(B, t) - static_cast<int64_t>(w[t]);
+                if (tsum[t] <= room) {
                     o = 1;
                 } else {
+                    o = kOkSlow;
                     slow = true;
                     const int32_t gain = cg[p];
                     gmin = gain < gmin ? gain : gmin;
                     gmax = gain > gmax ? gain : gmax;
+                    if (!kSmall && seg_off[t] == -1 && atomicCAS(&seg_off[t], -1, -2) == -1)
+                        claim_segment(t, cnt[t], room, seg_off, seg_list, L, small_max, ctr);
                 }
             }
             ok[p] = o;
@@ -1171,89 +1238,6 @@ __global__ void __launch_bounds__(256) admit_kernel(const int32_t* __restrict__ 
     }
 }
 
-// Multi-workgroup selection for segments longer than the single-workgroup
-// limit: the same most-significant-digit-first selection, with per-segment
-// histograms in HBM. A segment is registered when its target claims it: it
-// takes the next large index l and a run of kSegChunk-entry chunks.
-struct LargeSel {
-    int32_t* base;      // [nlarge] first entry of each large segment
-    int32_t* len;       // [nlarge] its entries
-    int32_t* chunk0;    // [nlarge] its first chunk
-    int32_t* owner;     // [nlchunks] large segment of each chunk
-    uint32_t* hist;     // [nlarge][256] weight per digit
-    uint64_t* prefix;   // [nlarge] digits fixed so far
-    int64_t* room;      // [nlarge] weight still admissible below the prefix
-    uint32_t* done;     // [nlarge] chunks finished with the current digit
-};
-
-__device__ __forceinline__ int32_t seg_chunks(int32_t len) { return (len + kSegChunk - 1) / kSegChunk; }
-
-__device__ void register_large(const LargeSel& L, int32_t base, int32_t len, int64_t room, Counters* ctr) {
-    const uint32_t l = atomicAdd(&ctr->nlarge, 1u);
-    const int32_t nch = seg_chunks(len);
-    const int32_t c0 = static_cast<int32_t>(atomicAdd(&ctr->nlchunks, static_cast<uint32_t>(nch)));
-    L.base[l] = base;
-    L.len[l] = len;
-    L.chunk0[l] = c0;
-    L.prefix[l] = 0;
-    L.room[l] = room;
-    for (int32_t c = 0; c < nch; ++c) L.owner[c0 + c] = static_cast<int32_t>(l);
-}
-
-// A target that cannot take all its candidates gets a segment of cnt[t]
-// entries (small label spaces: one thread per label).
-__global__ void __launch_bounds__(256) claim_small_kernel(int32_t nw, const int32_t* __restrict__ w,
-                                                          const int32_t* __restrict__ tsum,
-                                                          const int32_t* __restrict__ cnt, Bounds B,
-                                                          int32_t* __restrict__ seg_off, int32_t* __restrict__ seg_list,
-                                                          LargeSel L, int32_t small_max, Counters* ctr) {
-    const int32_t t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= nw || cnt[t] == 0) return;
-    const int64_t room = bound_of(B, t) - static_cast<int64_t>(w[t]);
-    if (tsum[t] <= room) return;
-    const int32_t base = static_cast<int32_t>(atomicAdd(&ctr->slow_total, static_cast<uint32_t>(cnt[t])));
-    seg_off[t] = base;
-    seg_list[atomicAdd(&ctr->nseg, 1u)] = t;
-    if (cnt[t] > small_max) register_large(L, base, cnt[t], room, ctr);
-}
-
-// Same for large label spaces: the first slow candidate of a target claims;
-// each block tries a label once per chunk.
-__global__ void __launch_bounds__(256) claim_big_kernel(const uint32_t* __restrict__ slow_idx,
-                                                        const int32_t* __restrict__ ct, const int32_t* __restrict__ cnt,
-                                                        const int32_t* __restrict__ w, Bounds B,
-                                                        int32_t* __restrict__ seg_off, int32_t* __restrict__ seg_list,
-                                                        LargeSel L, int32_t small_max, Counters* ctr) {
-    __shared__ int32_t keys[kAggTable];
-    for (int j = threadIdx.x; j < kAggTable; j += 256) keys[j] = -1;
-    __syncthreads();
-    const uint32_t m = ctr->nslow;
-    for (uint32_t base = blockIdx.x * kAggChunk; base < m; base += gridDim.x * kAggChunk) {
-        for (int r = 0; r < kAggChunk / 256; ++r) {
-            const uint32_t j = base + r * 256 + threadIdx.x;
-            if (j >= m) continue;
-            const int32_t t = ct[slow_idx[j]];
-            uint32_t h = slot_hash(static_cast<uint32_t>(t)) & (kAggTable - 1);
-            bool fresh = false;
-            while (true) {
-                const int32_t k = atomicCAS(&keys[h], -1, t);
-                if (k == -1) fresh = true;
-                if (k == -1 || k == t) break;
-                h = (h + 1) & (kAggTable - 1);
-            }
-            if (!fresh || seg_off[t] != -1 || atomicCAS(&seg_off[t], -1, -2) != -1) continue;
-            const int32_t base = static_cast<int32_t>(atomicAdd(&ctr->slow_total, static_cast<uint32_t>(cnt[t])));
-            seg_off[t] = base;
-            seg_list[atomicAdd(&ctr->nseg, 1u)] = t;
-            if (cnt[t] > small_max)
-                register_large(L, base, cnt[t], bound_of(B, t) - static_cast<int64_t>(w[t]), ctr);
-        }
-        __syncthreads();
-        for (int j = threadIdx.x; j < kAggTable; j += 256) keys[j] = -1;
-        __syncthreads();
-    }
-}
-
 // Writes every slow candidate into its target's segment as the key
 // [gmax - gain][node] (ascending key = gain desc, node asc), with its weight.
 // Space is reserved once per label per block chunk.
@@ -1263,8 +1247,7 @@ __global__ void __launch_bounds__(256) scatter_kernel(const uint32_t* __restrict
                                                       const int32_t* __restrict__ cg, const int32_t* __restrict__ vw,
                                                       int bits_v, int32_t nw, const int32_t* __restrict__ seg_off,
                                                       int32_t* __restrict__ seg_fill, uint64_t* __restrict__ skey,
-                                                      uint32_t* __restrict__ spos, int32_t* __restrict__ swt,
-                                                      const Counters* ctr) {
+                                                      int32_t* __restrict__ swt, const Counters* ctr) {
     constexpr int kSlots = kSmall ? kSmallLabels : kAggTable;
     __shared__ int32_t keys[kSmall ? 1 : kAggTable];
     __shared__ int32_t lcnt[kSlots];
@@ -1299,7 +1282,6 @@ __global__ void __launch_bounds__(256) scatter_kernel(const uint32_t* __restrict
             const int32_t at = seg_off[t] + lbase[i] + atomicAdd(&lcnt[i], 1);
             skey[at] = (static_cast<uint64_t>(static_cast<int64_t>(gmax) - cg[p]) << bits_v) |
                        static_cast<uint64_t>(static_cast<uint32_t>(v));
-            spos[at] = p;
             swt[at] = vw ? vw[v] : 1;
         }
         __syncthreads();
@@ -1313,21 +1295,29 @@ __global__ void __launch_bounds__(256) scatter_kernel(const uint32_t* __restrict
 
 __device__ __forceinline__ int bits_of(uint64_t x) { return x ? 64 - __clzll(static_cast<long long>(x)) : 0; }
 
+__device__ __forceinline__ int64_t shfl_up_i64(int64_t v, int o) {
+    const uint32_t lo = __shfl_up(static_cast<uint32_t>(static_cast<uint64_t>(v)), o, 64);
+    const uint32_t hi = __shfl_up(static_cast<uint32_t>(static_cast<uint64_t>(v) >> 32), o, 64);
+    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 // One workgroup per overflowing target (grid-stride over the segments):
 // finds the smallest key whose inclusive weight prefix, in key order, exceeds
 // the target's room bound - w(t), by a most-significant-digit-first radix
-// selection on weight histograms; every candidate with a smaller key is
-// admitted (node weights are >= 0, so that is exactly the admitted prefix).
+// selection on weight histograms, and stores it as the target's boundary:
+// every candidate with a smaller key is admitted (node weights are >= 0, so
+// that is exactly the admitted prefix).  Block 0 also keeps the sub-round's
+// gmax for the apply kernel.
 __global__ void __launch_bounds__(256) select_kernel(const int32_t* __restrict__ seg_list,
                                                      int32_t* __restrict__ seg_off, int32_t* __restrict__ seg_fill,
                                                      const int32_t* __restrict__ cnt, const int32_t* __restrict__ w,
                                                      Bounds B, int bits_v, const uint64_t* __restrict__ skey,
-                                                     const uint32_t* __restrict__ spos,
-                                                     const int32_t* __restrict__ swt, uint8_t* __restrict__ ok,
-                                                     int32_t small_max, const Counters* ctr) {
+                                                     const int32_t* __restrict__ swt, uint64_t* __restrict__ bnd,
+                                                     int32_t small_max, Counters* ctr) {
     __shared__ unsigned long long hist[256];
     __shared__ uint64_t s_prefix, s_mask;
     __shared__ int64_t s_room;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->gkey = ctr->gmax;
     const uint32_t nseg = ctr->nseg;
     const int total_bits = bits_of(static_cast<uint64_t>(static_cast<int64_t>(ctr->gmax) - ctr->gmin)) + bits_v;
     const int passes = total_bits > 0 ? (total_bits + 7) / 8 : 1;
@@ -1359,24 +1349,51 @@ __global__ void __launch_bounds__(256) select_kernel(const int32_t* __restrict__
                 if ((k & pmask) == prefix && c) atomicAdd(&hist[(k >> shift) & 255], static_cast<unsigned long long>(c));
             }
             __syncthreads();
-            if (threadIdx.x == 0) {
-                // boundary digit: the first whose cumulative weight exceeds the room
-                int64_t run = 0, room = s_room;
-                int d = 0;
-                for (; d < 255; ++d) {
-                    if (run + static_cast<int64_t>(hist[d]) > room) break;
-                    run += static_cast<int64_t>(hist[d]);
+            if (threadIdx.x < 64) {
+                // boundary digit: the first whose cumulative weight exceeds the
+                // room (digit 255 when none of 0..254 does); lane j holds digits
+                // 4j .. 4j+3
+                const int lane = threadIdx.x;
+                const int64_t room = s_room;
+                int64_t h[4], local = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    h[q] = static_cast<int64_t>(hist[4 * lane + q]);
+                    local += h[q];
                 }
-                s_room = room - run;
-                s_prefix = prefix | (static_cast<uint64_t>(d) << shift);
-                s_mask = pmask | (255ULL << shift);
+                int64_t incl = local;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int64_t u = shfl_up_i64(incl, o);
+                    if (lane >= o) incl += u;
+                }
+                int64_t run = incl - local;
+                int d = 256;
+                int64_t rund = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (d != 256) continue;
+                    if (run + h[q] > room) {
+                        d = 4 * lane + q;
+                        rund = run;
+                    } else {
+                        run += h[q];
+                    }
+                }
+                const int dmin = wave_min(d);
+                const bool mine = dmin == 256 ? lane == 63 : d == dmin;
+                if (mine) {
+                    const int dd = dmin == 256 ? 255 : dmin;
+                    const int64_t before = dmin == 256 ? incl - h[3] : rund;
+                    s_room = room - before;
+                    s_prefix = prefix | (static_cast<uint64_t>(dd) << shift);
+                    s_mask = pmask | (255ULL << shift);
+                }
             }
             __syncthreads();
         }
-        const uint64_t boundary = s_prefix;  // smallest key that does not fit
-        for (int32_t i = threadIdx.x; i < len; i += 256) ok[spos[base + i]] = skey[base + i] < boundary ? 1 : 0;
-        __syncthreads();
         if (threadIdx.x == 0) {
+            bnd[t] = s_prefix;  // smallest key that does not fit
             seg_off[t] = -1;
             seg_fill[t] = 0;
         }
@@ -1386,20 +1403,23 @@ __global__ void __launch_bounds__(256) select_kernel(const int32_t* __restrict__
 // One digit of the multi-workgroup selection: every block adds its chunk's
 // weight histogram to the segment's histogram in HBM; the last block to
 // finish a segment picks that segment's boundary digit with a block-wide scan
-// (no block waits for another).
+// (no block waits for another) and, after the last digit, stores the
+// segment's boundary key.
 __global__ void __launch_bounds__(256) large_pass_kernel(LargeSel L, int pass, int bits_v,
                                                          const uint64_t* __restrict__ skey,
-                                                         const int32_t* __restrict__ swt, Counters* ctr) {
-    __shared__ uint32_t h[256];
+                                                         const int32_t* __restrict__ swt,
+                                                         uint64_t* __restrict__ bnd, const Counters* ctr) {
+    constexpr int kPerT = kLBins / 256;
+    __shared__ uint32_t h[kLBins];
     __shared__ int64_t sc[256];
     __shared__ int s_last, s_d;
     __shared__ int64_t s_run;
     const int total_bits = bits_of(static_cast<uint64_t>(static_cast<int64_t>(ctr->gmax) - ctr->gmin)) + bits_v;
-    const int passes = total_bits > 0 ? (total_bits + 7) / 8 : 1;
+    const int passes = total_bits > 0 ? (total_bits + kLDigit - 1) / kLDigit : 1;
     const uint32_t nlarge = ctr->nlarge;
     if (pass >= passes || nlarge == 0) return;  // uniform over the grid
-    const int shift = 8 * pass;
-    const uint64_t above = pass + 1 >= 8 ? 0ULL : ~0ULL << (shift + 8);  // digits already fixed
+    const int shift = kLDigit * pass;
+    const uint64_t above = shift + kLDigit >= 64 ? 0ULL : ~0ULL << (shift + kLDigit);  // digits already fixed
     const int32_t nch = static_cast<int32_t>(ctr->nlchunks);
     const int j = threadIdx.x;
     for (int32_t c = blockIdx.x; c < nch; c += gridDim.x) {
@@ -1409,16 +1429,18 @@ __global__ void __launch_bounds__(256) large_pass_kernel(LargeSel L, int pass, i
         const int32_t i0 = (c - L.chunk0[l]) * kSegChunk;
         const int32_t i1 = i0 + kSegChunk < len ? i0 + kSegChunk : len;
         const uint64_t prefix = L.prefix[l];
-        uint32_t* hl = L.hist + static_cast<size_t>(l) * 256;
-        h[j] = 0;
+        uint32_t* hl = L.hist + static_cast<size_t>(l) * kLBins;
+        for (int q = j; q < kLBins; q += 256) h[q] = 0;
         __syncthreads();
         for (int32_t i = i0 + j; i < i1; i += 256) {
             const uint64_t k = skey[base + i];
             const int32_t wt = swt[base + i];
-            if ((k & above) == prefix && wt) atomicAdd(&h[(k >> shift) & 255], static_cast<uint32_t>(wt));
+            if ((k & above) == prefix && wt)
+                atomicAdd(&h[(k >> shift) & (kLBins - 1)], static_cast<uint32_t>(wt));
         }
         __syncthreads();
-        if (h[j]) atomicAdd(&hl[j], h[j]);
+        for (int q = j; q < kLBins; q += 256)
+            if (h[q]) atomicAdd(&hl[q], h[q]);
         __threadfence();
         __syncthreads();
         if (j == 0) {
@@ -1428,8 +1450,15 @@ __global__ void __launch_bounds__(256) large_pass_kernel(LargeSel L, int pass, i
         __syncthreads();
         if (s_last) {  // block-uniform
             __threadfence();
-            const uint32_t hj = __hip_atomic_load(&hl[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            sc[j] = hj;
+            // thread j holds digits kPerT*j .. kPerT*j + kPerT-1
+            int64_t hv[kPerT];
+            int64_t local = 0;
+#pragma unroll
+            for (int q = 0; q < kPerT; ++q) {
+                hv[q] = __hip_atomic_load(&hl[kPerT * j + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                local += hv[q];
+            }
+            sc[j] = local;
             __syncthreads();
             for (int o = 1; o < 256; o <<= 1) {  // inclusive scan
                 const int64_t add = j >= o ? sc[j - o] : 0;
@@ -1439,46 +1468,43 @@ __global__ void __launch_bounds__(256) large_pass_kernel(LargeSel L, int pass, i
             }
             const int64_t room = L.room[l];
             const int64_t incl = sc[j];
-            const int64_t excl = incl - hj;
-            if (j == 255) {
-                s_d = 255;
-                s_run = excl;
+            const int64_t excl = incl - local;
+            if (j == 255) {  // no digit below the last one exceeds the room
+                s_d = kLBins - 1;
+                s_run = incl - hv[kPerT - 1];
             }
             __syncthreads();
             // the digit where the admissible weight runs out (monotone: one thread)
-            if (incl > room && excl <= room && j < 255) {
-                s_d = j;
-                s_run = excl;
+            if (incl > room && excl <= room) {
+                int64_t run = excl;
+                int d = kPerT * j + kPerT - 1;
+                for (int q = 0; q < kPerT - 1; ++q) {
+                    if (run + hv[q] > room) {
+                        d = kPerT * j + q;
+                        break;
+                    }
+                    run += hv[q];
+                }
+                s_d = d;
+                s_run = run;
             }
-            hl[j] = 0;
+#pragma unroll
+            for (int q = 0; q < kPerT; ++q) hl[kPerT * j + q] = 0;
             __syncthreads();
             if (j == 0) {
+                const uint64_t np = prefix | (static_cast<uint64_t>(s_d) << shift);
                 L.room[l] = room - s_run;
-                L.prefix[l] |= static_cast<uint64_t>(s_d) << shift;
+                L.prefix[l] = np;
                 L.done[l] = 0;
+                if (pass == 0) bnd[L.target[l]] = np;  // smallest key that does not fit
             }
         }
         __syncthreads();
     }
 }
 
-__global__ void __launch_bounds__(256) large_admit_kernel(LargeSel L, const uint64_t* __restrict__ skey,
-                                                          const uint32_t* __restrict__ spos,
-                                                          uint8_t* __restrict__ ok, const Counters* ctr) {
-    const int32_t nch = static_cast<int32_t>(ctr->nlchunks);
-    for (int32_t c = blockIdx.x; c < nch; c += gridDim.x) {
-        const int32_t l = L.owner[c];
-        const int32_t base = L.base[l];
-        const int32_t len = L.len[l];
-        const int32_t i0 = (c - L.chunk0[l]) * kSegChunk;
-        const int32_t i1 = i0 + kSegChunk < len ? i0 + kSegChunk : len;
-        const uint64_t boundary = L.prefix[l];  // smallest key that does not fit
-        for (int32_t i = i0 + threadIdx.x; i < i1; i += 256) ok[spos[base + i]] = skey[base + i] < boundary ? 1 : 0;
-    }
-}
-
 // The per-sub-round counters back to their empty state (the round's
-// candidate count is kept).
+// candidate count and the kept gmax are not touched).
 __device__ __forceinline__ void clear_subround(Counters* ctr) {
     ctr->ncand = 0;
     ctr->nslow = 0;
@@ -1490,17 +1516,21 @@ __device__ __forceinline__ void clear_subround(Counters* ctr) {
     ctr->nlchunks = 0;
 }
 
-// Moves the admitted candidates and updates the label weights; also clears
-// the per-target candidate sums and counts and the sub-round counters for the
+// Decides the slow candidates from their targets' boundary keys, moves the
+// admitted candidates and updates the label weights; also clears the
+// per-target candidate sums and counts and the sub-round counters for the
 // next sub-round (no kernel of this one reads them any more).
 template <bool kSmall>
-__global__ void __launch_bounds__(256) apply_kernel(const int32_t* __restrict__ ct, const uint8_t* __restrict__ ok,
+__global__ void __launch_bounds__(256) apply_kernel(const int32_t* __restrict__ ct, uint8_t* __restrict__ ok,
                                                     const int32_t* __restrict__ nodes, int32_t count,
+                                                    const int32_t* __restrict__ cg, int bits_v,
+                                                    const uint64_t* __restrict__ bnd,
                                                     const int32_t* __restrict__ vw, int32_t* __restrict__ label,
                                                     uint8_t* __restrict__ label8, uint16_t* __restrict__ label16,
                                                     int32_t* __restrict__ w, int32_t* __restrict__ tsum,
                                                     int32_t* __restrict__ cnt, int32_t nw, Counters* ctr) {
     __shared__ int32_t delta[kSmall ? kSmallLabels : 1];
+    const int32_t gkey = ctr->gkey;
     if (blockIdx.x == 0) {
         if (threadIdx.x == 0) clear_subround(ctr);
         if (kSmall)
@@ -1520,8 +1550,15 @@ __global__ void __launch_bounds__(256) apply_kernel(const int32_t* __restrict__ 
             tsum[t] = 0;
             cnt[t] = 0;
         }
-        if (!ok[p]) continue;
+        uint8_t o = ok[p];
         const int32_t v = nodes[p];
+        if (o == kOkSlow) {
+            const uint64_t key = (static_cast<uint64_t>(static_cast<int64_t>(gkey) - cg[p]) << bits_v) |
+                                 static_cast<uint64_t>(static_cast<uint32_t>(v));
+            o = key < bnd[t] ? 1 : 0;
+            ok[p] = o;
+        }
+        if (!o) continue;
         const int32_t a = label[v];
         const int32_t c = vw ? vw[v] : 1;
         label[v] = t;
@@ -1952,23 +1989,27 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     DBuf<int32_t> ct(cap, s), cg(cap, s), tsum(nw, s), tcnt(nw, s), seg_off(nw, s), seg_fill(nw, s);
     DBuf<int32_t> seg_list(std::min<int64_t>(cap, nw), s), swt(cap, s);
     DBuf<uint8_t> ok(cap, s);
-    DBuf<uint32_t> slow_idx(cap, s), spos(cap, s);
+    DBuf<uint32_t> slow_idx(cap, s);
     DBuf<uint64_t> skey(cap, s);
     // multi-workgroup selection state: at most cap / kSmallSeg large segments
     const int32_t small_max = std::max(1, std::min(tune.select_small_max, kSmallSeg));
     const int64_t max_large = cap / small_max + 1;
     const int64_t max_lchunks = cap / kSegChunk + max_large;
-    DBuf<int32_t> lbase(max_large, s), llen(max_large, s), lchunk0(max_large, s), lowner(max_lchunks, s);
-    DBuf<uint32_t> lhist(max_large * 256, s);
+    DBuf<int32_t> ltarget(max_large, s), lbase(max_large, s), llen(max_large, s), lchunk0(max_large, s);
+    DBuf<int32_t> lowner(max_lchunks, s);
+    DBuf<uint32_t> lhist(max_large * kLBins, s);
     DBuf<uint64_t> lprefix(max_large, s);
     DBuf<int64_t> lroom(max_large, s);
     DBuf<uint32_t> ldone(max_large, s);
-    fill_u32(lhist.get(), 0, max_large * 256, s);
+    fill_u32(lhist.get(), 0, max_large * kLBins, s);
     fill_u32(ldone.get(), 0, max_large, s);
-    LargeSel LS{lbase.get(), llen.get(), lchunk0.get(), lowner.get(), lhist.get(), lprefix.get(), lroom.get(),
+    LargeSel LS{ltarget.get(), lbase.get(), llen.get(), lchunk0.get(), lowner.get(), lhist.get(), lprefix.get(),
+                lroom.get(),
                 ldone.get()};
     // digits of the selection key: node id bits plus at most 32 bits of gain range
-    const int max_sel_passes = (bits_for(static_cast<uint64_t>(n - 1)) + 32 + 7) / 8;
+    const int max_sel_passes = (bits_for(static_cast<uint64_t>(n - 1)) + 32 + kLDigit - 1) / kLDigit;
+    // boundary key of every target that cannot take all its candidates
+    DBuf<uint64_t> bnd(nw, s);
     fill_i32(tsum.get(), 0, nw, s);
     fill_i32(tcnt.get(), 0, nw, s);
     fill_i32(seg_off.get(), -1, nw, s);
@@ -2191,44 +2232,40 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                     cand_accum_kernel<false><<<gc, 256, 0, s>>>(ct.get(), cnodes, ccount, g.vw, tsum.get(),
                                                                 tcnt.get(), nw, ctr.get());
                 LAUNCHCHK();
-                admit_kernel<<<gc, 256, 0, s>>>(ct.get(), cg.get(), ccount, w, tsum.get(), BB, ok.get(),
-                                                slow_idx.get(), ctr.get());
+                if (small)
+                    admit_kernel<true><<<gc, 256, 0, s>>>(ct.get(), cg.get(), ccount, w, tsum.get(), tcnt.get(), BB,
+                                                          ok.get(), slow_idx.get(), seg_off.get(), seg_list.get(), LS,
+                                                          small_max, nw, ctr.get());
+                else
+                    admit_kernel<false><<<gc, 256, 0, s>>>(ct.get(), cg.get(), ccount, w, tsum.get(), tcnt.get(), BB,
+                                                           ok.get(), slow_idx.get(), seg_off.get(), seg_list.get(),
+                                                           LS, small_max, nw, ctr.get());
                 LAUNCHCHK();
             }
             {
                 ProfScope ps(A.refine ? "lp_refine_admit_select" : "lp_admit_select", 0, s);
                 const unsigned gc = capped_grid(ccount);
-                if (small) {
-                    claim_small_kernel<<<grid_for(nw, 256), 256, 0, s>>>(nw, w, tsum.get(), tcnt.get(), BB,
-                                                                         seg_off.get(), seg_list.get(),
-                                                                         LS, small_max, ctr.get());
-                    LAUNCHCHK();
+                if (small)
                     scatter_kernel<true><<<gc, 256, 0, s>>>(slow_idx.get(), cnodes, ct.get(), cg.get(), g.vw, bits_v,
-                                                            nw, seg_off.get(), seg_fill.get(), skey.get(), spos.get(),
-                                                            swt.get(), ctr.get());
-                } else {
-                    claim_big_kernel<<<gc, 256, 0, s>>>(slow_idx.get(), ct.get(), tcnt.get(), w, BB, seg_off.get(),
-                                                        seg_list.get(), LS, small_max, ctr.get());
-                    LAUNCHCHK();
+                                                            nw, seg_off.get(), seg_fill.get(), skey.get(), swt.get(),
+                                                            ctr.get());
+                else
                     scatter_kernel<false><<<gc, 256, 0, s>>>(slow_idx.get(), cnodes, ct.get(), cg.get(), g.vw, bits_v,
-                                                             nw, seg_off.get(), seg_fill.get(), skey.get(), spos.get(),
-                                                             swt.get(), ctr.get());
-                }
+                                                             nw, seg_off.get(), seg_fill.get(), skey.get(), swt.get(),
+                                                             ctr.get());
                 LAUNCHCHK();
                 select_kernel<<<kMaxBlocks, 256, 0, s>>>(seg_list.get(), seg_off.get(), seg_fill.get(), tcnt.get(), w,
-                                                         BB, bits_v, skey.get(), spos.get(), swt.get(), ok.get(),
-                                                         small_max, ctr.get());
+                                                         BB, bits_v, skey.get(), swt.get(), bnd.get(), small_max,
+                                                         ctr.get());
                 LAUNCHCHK();
                 // a target has at most ccount candidates: no large segment
                 // unless the colour has more than the single-workgroup limit
                 if (ccount > small_max) {
                     for (int pass = max_sel_passes - 1; pass >= 0; --pass) {
                         large_pass_kernel<<<kLargeBlocks, 256, 0, s>>>(LS, pass, bits_v, skey.get(), swt.get(),
-                                                                       ctr.get());
+                                                                       bnd.get(), ctr.get());
                         LAUNCHCHK();
                     }
-                    large_admit_kernel<<<kLargeBlocks, 256, 0, s>>>(LS, skey.get(), spos.get(), ok.get(), ctr.get());
-                    LAUNCHCHK();
                 }
             }
             if (trace) {
@@ -2242,14 +2279,16 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
             {
                 ProfScope ps("lp_apply", 0, s);
                 if (small) {
-                    apply_kernel<true><<<capped_grid(ccount), 256, 0, s>>>(ct.get(), ok.get(), cnodes, ccount, g.vw,
-                                                                           label, lab8.get(), lab16.get(), w,
-                                                                           tsum.get(), tcnt.get(), nw, ctr.get());
+                    apply_kernel<true><<<capped_grid(ccount), 256, 0, s>>>(ct.get(), ok.get(), cnodes, ccount,
+                                                                           cg.get(), bits_v, bnd.get(), g.vw, label,
+                                                                           lab8.get(), lab16.get(), w, tsum.get(),
+                                                                           tcnt.get(), nw, ctr.get());
                     LAUNCHCHK();
                 } else {
                     apply_kernel<false><<<grid_for(ccount, 256), 256, 0, s>>>(ct.get(), ok.get(), cnodes, ccount,
-                                                                              g.vw, label, lab8.get(), lab16.get(), w,
-                                                                              tsum.get(), tcnt.get(), nw, ctr.get());
+                                                                              cg.get(), bits_v, bnd.get(), g.vw, label,
+                                                                              lab8.get(), lab16.get(), w, tsum.get(),
+                                                                              tcnt.get(), nw, ctr.get());
                     LAUNCHCHK();
                 }
             }
