@@ -58,7 +58,7 @@ constexpr int kHubTChunk = 4096;         // HBM table entries per scan workgroup
 constexpr int kSmallLabels = 4096;       // LDS-private histograms up to this many labels
 constexpr int kMaxBlocks = 1024;         // grid cap of the grid-stride candidate kernels
 constexpr int kSmallSeg = 4096;          // segments up to this length: one selecting workgroup
-constexpr int kSegChunk = 4096;          // entries per workgroup in the multi-workgroup selection
+constexpr int kSegChunk = 16384;         // entries per workgroup in the multi-workgroup selection
 constexpr int kLargeBlocks = 256;        // grid of the multi-workgroup selection kernels
 
 struct Counters {
@@ -1020,6 +1020,36 @@ __device__ __forceinline__ uint32_t block_append(bool flag, uint32_t* counter) {
     return idx;
 }
 
+// Same for c items per thread (256 threads): returns the position of this
+// thread's first item; the thread's items are consecutive.
+__device__ __forceinline__ uint32_t block_append_count(uint32_t c, uint32_t* counter) {
+    __shared__ uint32_t s_cnt[4];
+    __shared__ uint32_t s_base;
+    const int wid = threadIdx.x >> 6;
+    const int lane = lane_id();
+    uint32_t incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) s_cnt[wid] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < 4; ++w) {
+            const uint32_t t = s_cnt[w];
+            s_cnt[w] = run;
+            run += t;
+        }
+        s_base = run ? atomicAdd(counter, run) : 0;
+    }
+    __syncthreads();
+    const uint32_t idx = s_base + s_cnt[wid] + incl - c;
+    __syncthreads();
+    return idx;
+}
+
 __device__ __forceinline__ int32_t block_sum_i32(int32_t v) {
     __shared__ int32_t s[4];
     v = wave_sum(v);
@@ -1192,13 +1222,16 @@ __global__ void __launch_bounds__(256) admit_kernel(const int32_t* __restrict__ 
             if (tsum[t] > room) claim_segment(t, cnt[t], room, seg_off, seg_list, L, small_max, ctr);
         }
     }
-    const int32_t stride = gridDim.x * 256;
-    const int32_t iters = (count + stride - 1) / stride;
+    // each block takes kAdmitIters * 256 consecutive candidates at a time
+    // and appends its slow ones with one atomic
+    constexpr int kAdmitIters = 16;
     int32_t gmin = INT_MAX, gmax = INT_MIN;
-    for (int32_t it = 0; it < iters; ++it) {
-        const int32_t p = it * stride + blockIdx.x * 256 + threadIdx.x;
-        bool slow = false;
-        if (p < count) {
+    for (int32_t base = blockIdx.x * (kAdmitIters * 256); base < count; base += gridDim.x * (kAdmitIters * 256)) {
+        uint32_t mask = 0;
+#pragma unroll 4
+        for (int it = 0; it < kAdmitIters; ++it) {
+            const int32_t p = base + it * 256 + static_cast<int32_t>(threadIdx.x);
+            if (p >= count) break;
             const int32_t t = ct[p];
             uint8_t o = 0;
             if (t >= 0) {
@@ -1207,7 +1240,7 @@ __global__ void __launch_bounds__(256) admit_kernel(const int32_t* __restrict__ 
                     o = 1;
                 } else {
                     o = kOkSlow;
-                    slow = true;
+                    mask |= 1u << it;
                     const int32_t gain = cg[p];
                     gmin = gain < gmin ? gain : gmin;
                     gmax = gain > gmax ? gain : gmax;
@@ -1217,8 +1250,12 @@ __global__ void __launch_bounds__(256) admit_kernel(const int32_t* __restrict__ 
             }
             ok[p] = o;
         }
-        const uint32_t j = block_append(slow, &ctr->nslow);
-        if (slow) slow_idx[j] = static_cast<uint32_t>(p);
+        uint32_t j = block_append_count(static_cast<uint32_t>(__popc(mask)), &ctr->nslow);
+        while (mask) {
+            const int it = __ffs(mask) - 1;
+            mask &= mask - 1;
+            slow_idx[j++] = static_cast<uint32_t>(base + it * 256 + static_cast<int32_t>(threadIdx.x));
+        }
     }
     gmin = wave_min(gmin);
     gmax = wave_max(gmax);
