@@ -59,7 +59,8 @@ constexpr int kSmallLabels = 4096;       // LDS-private histograms up to this ma
 constexpr int kMaxBlocks = 1024;         // grid cap of the grid-stride candidate kernels
 constexpr int kSmallSeg = 4096;          // segments up to this length: one selecting workgroup
 constexpr int kSegChunk = 16384;         // entries per workgroup in the multi-workgroup selection
-constexpr int kLargeBlocks = 256;        // grid of the multi-workgroup selection kernels
+constexpr int kLargeBlocks = 256;        // grid of the multi-workgroup selection kernel
+constexpr int kLargeThreads = 1024;      // and its workgroup size
 
 struct Counters {
     uint32_t ncand;        // candidates of the sub-round
@@ -1442,13 +1443,15 @@ __global__ void __launch_bounds__(256) select_kernel(const int32_t* __restrict__
 // finish a segment picks that segment's boundary digit with a block-wide scan
 // (no block waits for another) and, after the last digit, stores the
 // segment's boundary key.
-__global__ void __launch_bounds__(256) large_pass_kernel(LargeSel L, int pass, int bits_v,
-                                                         const uint64_t* __restrict__ skey,
-                                                         const int32_t* __restrict__ swt,
-                                                         uint64_t* __restrict__ bnd, const Counters* ctr) {
-    constexpr int kPerT = kLBins / 256;
+__global__ void __launch_bounds__(kLargeThreads) large_pass_kernel(LargeSel L, int pass, int bits_v,
+                                                                   const uint64_t* __restrict__ skey,
+                                                                   const int32_t* __restrict__ swt,
+                                                                   uint64_t* __restrict__ bnd, const Counters* ctr) {
+    constexpr int NT = kLargeThreads;
+    constexpr int kPerT = kLBins / NT;
+    constexpr int U = 4;
     __shared__ uint32_t h[kLBins];
-    __shared__ int64_t sc[256];
+    __shared__ int64_t sc[NT];
     __shared__ int s_last, s_d;
     __shared__ int64_t s_run;
     const int total_bits = bits_of(static_cast<uint64_t>(static_cast<int64_t>(ctr->gmax) - ctr->gmin)) + bits_v;
@@ -1467,26 +1470,39 @@ __global__ void __launch_bounds__(256) large_pass_kernel(LargeSel L, int pass, i
         const int32_t i1 = i0 + kSegChunk < len ? i0 + kSegChunk : len;
         const uint64_t prefix = L.prefix[l];
         uint32_t* hl = L.hist + static_cast<size_t>(l) * kLBins;
-        for (int q = j; q < kLBins; q += 256) h[q] = 0;
+        for (int q = j; q < kLBins; q += NT) h[q] = 0;
         __syncthreads();
-        for (int32_t i = i0 + j; i < i1; i += 256) {
-            const uint64_t k = skey[base + i];
-            const int32_t wt = swt[base + i];
-            if ((k & above) == prefix && wt)
-                atomicAdd(&h[(k >> shift) & (kLBins - 1)], static_cast<uint32_t>(wt));
+        for (int32_t i = i0 + j; i < i1; i += NT * U) {
+            uint64_t k[U];
+            int32_t wt[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t x = i + u * NT;
+                k[u] = x < i1 ? skey[base + x] : 0;
+                wt[u] = x < i1 ? swt[base + x] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if ((k[u] & above) == prefix && wt[u])
+                    atomicAdd(&h[(k[u] >> shift) & (kLBins - 1)], static_cast<uint32_t>(wt[u]));
         }
         __syncthreads();
-        for (int q = j; q < kLBins; q += 256)
+        for (int q = j; q < kLBins; q += NT)
             if (h[q]) atomicAdd(&hl[q], h[q]);
-        __threadfence();
+        // the barrier orders every thread's adds before thread 0's release
+        // fence, and thread 0's acquire fence before every thread's reads (a
+        // device-scope fence writes back and invalidates the L2, so one
+        // thread issues it, not every wave)
         __syncthreads();
         if (j == 0) {
             const uint32_t nchunks = static_cast<uint32_t>(seg_chunks(len));
-            s_last = atomicAdd(&L.done[l], 1u) == nchunks - 1;
+            __threadfence();
+            const bool last = atomicAdd(&L.done[l], 1u) == nchunks - 1;
+            if (last) __threadfence();
+            s_last = last;
         }
         __syncthreads();
         if (s_last) {  // block-uniform
-            __threadfence();
             // thread j holds digits kPerT*j .. kPerT*j + kPerT-1
             int64_t hv[kPerT];
             int64_t local = 0;
@@ -1497,7 +1513,7 @@ __global__ void __launch_bounds__(256) large_pass_kernel(LargeSel L, int pass, i
             }
             sc[j] = local;
             __syncthreads();
-            for (int o = 1; o < 256; o <<= 1) {  // inclusive scan
+            for (int o = 1; o < NT; o <<= 1) {  // inclusive scan
                 const int64_t add = j >= o ? sc[j - o] : 0;
                 __syncthreads();
                 sc[j] += add;
@@ -1506,7 +1522,7 @@ __global__ void __launch_bounds__(256) large_pass_kernel(LargeSel L, int pass, i
             const int64_t room = L.room[l];
             const int64_t incl = sc[j];
             const int64_t excl = incl - local;
-            if (j == 255) {  // no digit below the last one exceeds the room
+            if (j == NT - 1) {  // no digit below the last one exceeds the room
                 s_d = kLBins - 1;
                 s_run = incl - hv[kPerT - 1];
             }
@@ -2299,8 +2315,8 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 // unless the colour has more than the single-workgroup limit
                 if (ccount > small_max) {
                     for (int pass = max_sel_passes - 1; pass >= 0; --pass) {
-                        large_pass_kernel<<<kLargeBlocks, 256, 0, s>>>(LS, pass, bits_v, skey.get(), swt.get(),
-                                                                       bnd.get(), ctr.get());
+                        large_pass_kernel<<<kLargeBlocks, kLargeThreads, 0, s>>>(LS, pass, bits_v, skey.get(),
+                                                                                 swt.get(), bnd.get(), ctr.get());
                         LAUNCHCHK();
                     }
                 }
