@@ -162,8 +162,11 @@ struct MinTree {  // node weights are int32; INT32_MAX marks an erased leaf
 struct BlockHeap {
     std::vector<uint64_t> h;
     static uint64_t key(int64_t w, int32_t b) { return (static_cast<uint64_t>(w) << 32) | static_cast<uint32_t>(b); }
-    explicit BlockHeap(const std::vector<int64_t>& wb) {
-        for (size_t b = 0; b < wb.size(); ++b) h.push_back(key(wb[b], static_cast<int32_t>(b)));
+    explicit BlockHeap(const std::vector<int64_t>& wb) { reset(wb); }
+    // rebuilds the heap from the block weights (storage reused)
+    void reset(const std::vector<int64_t>& wb) {
+        h.resize(wb.size());
+        for (size_t b = 0; b < wb.size(); ++b) h[b] = key(wb[b], static_cast<int32_t>(b));
         std::make_heap(h.begin(), h.end(), std::greater<uint64_t>());
     }
     int32_t top() const { return static_cast<int32_t>(h[0] & 0xFFFFFFFFu); }
@@ -414,9 +417,40 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
     std::vector<size_t> run_end;  // end of each run, in order
     for (const auto& ts : task_starts) run_end.insert(run_end.end(), ts.begin(), ts.end());
     run_end.push_back(nrest);
+    // blocks by (weight, id); kept across runs and repaired by insertion
+    // (a run changes the weights of a few blocks only), rebuilt after the
+    // node-by-node path
     std::vector<int32_t> ord(static_cast<size_t>(k));
+    bool ord_ok = false;
+    auto lighter = [&](int32_t x, int32_t y) { return wb[x] != wb[y] ? wb[x] < wb[y] : x < y; };
+    auto order_blocks = [&]() {
+        if (!ord_ok) {
+            for (int32_t b = 0; b < k; ++b) ord[b] = b;
+            std::sort(ord.begin(), ord.end(), lighter);
+            ord_ok = true;
+            return;
+        }
+        for (int32_t a = 1; a < k; ++a) {
+            const int32_t x = ord[a];
+            int32_t q = a - 1;
+            while (q >= 0 && lighter(x, ord[q])) {
+                ord[q + 1] = ord[q];
+                --q;
+            }
+            ord[q + 1] = x;
+        }
+    };
     BlockHeap heap(wb);  // kept in step with wb by the node-by-node path
     bool heap_ok = true;
+    // a dealt run: node t of rest[i, i + take) goes to plan_ord[at + t mod gsz];
+    // the block weights are advanced here and the labels written afterwards,
+    // in parallel
+    struct DealPlan {
+        size_t i, take, at;
+        int32_t gsz;
+    };
+    std::vector<DealPlan> plans;
+    std::vector<int32_t> plan_ord;
     size_t i = 0;
     size_t nruns = 0, nheap = 0;
     while (i < nrest) {
@@ -426,9 +460,10 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
         if (c == 0 || k > 4096 || j - i < 4 * static_cast<size_t>(k)) {  // node by node
             nheap += j - i;
             if (!heap_ok) {
-                heap = BlockHeap(wb);
+                heap.reset(wb);
                 heap_ok = true;
             }
+            ord_ok = false;
             for (; i < j; ++i) {
                 const int32_t b = heap.top();
                 part[rest[i]] = b;
@@ -439,10 +474,7 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
         }
         heap_ok = false;
         while (i < j) {
-            for (int32_t b = 0; b < k; ++b) ord[b] = b;
-            std::sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
-                return wb[x] != wb[y] ? wb[x] < wb[y] : x < y;
-            });
+            order_blocks();
             const int64_t m0 = wb[ord[0]];
             int32_t gsz = 1;
             while (gsz < k && wb[ord[gsz]] < m0 + c) ++gsz;
@@ -453,32 +485,48 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
                 uint64_t before = 0;
                 for (int32_t t = 0; t < gsz; ++t) {
                     const int32_t g = ord[t];
-                    const int64_t d = wx - wb[g];
-                    before += static_cast<uint64_t>((d + c - 1) / c + ((d % c == 0 && g < X) ? 1 : 0));
+                    const int64_t d = wx - wb[g];  // >= 0: g is not heavier than X
+                    if (c == 1) {
+                        before += static_cast<uint64_t>(d + (g < X ? 1 : 0));
+                    } else {
+                        const int64_t q = d / c, r = d - q * c;
+                        before += static_cast<uint64_t>(q + (r != 0 ? 1 : 0) + ((r == 0 && g < X) ? 1 : 0));
+                    }
                 }
                 take = std::min<size_t>(take, static_cast<size_t>(before));
             }
             // node t of the run goes to ord[t mod gsz]
-            const int32_t* r0 = rest + i;
-            auto deal = [&](size_t t0, size_t t1) {
-                size_t g = t0 % static_cast<size_t>(gsz);
-                for (size_t t = t0; t < t1; ++t) {
-                    part[r0[t]] = ord[g];
-                    if (++g == static_cast<size_t>(gsz)) g = 0;
-                }
-            };
-            const size_t nt = take < (1u << 20) ? 1 : static_cast<size_t>(nthr);
-            if (nt <= 1) {
-                deal(0, take);
-            } else {
-                std::vector<std::thread> pool;
-                for (size_t q = 0; q < nt; ++q) pool.emplace_back(deal, take * q / nt, take * (q + 1) / nt);
-                for (auto& th : pool) th.join();
-            }
+            plans.push_back(DealPlan{i, take, plan_ord.size(), gsz});
+            plan_ord.insert(plan_ord.end(), ord.begin(), ord.begin() + gsz);
             for (int32_t g = 0; g < gsz; ++g)
                 wb[ord[g]] += c * static_cast<int64_t>(take / gsz + (static_cast<size_t>(g) < take % gsz ? 1 : 0));
             i += take;
         }
+    }
+    // labels of the dealt runs: nodes split evenly over the threads
+    if (!plans.empty()) {
+        std::vector<size_t> pstart(plans.size() + 1, 0);
+        for (size_t q = 0; q < plans.size(); ++q) pstart[q + 1] = pstart[q] + plans[q].take;
+        const size_t total = pstart.back();
+        const int32_t nt = total < (1u << 16) ? 1 : 4 * nthr;
+        parallel_for(nt, nthr, [&](int32_t t) {
+            const size_t a0 = total * static_cast<size_t>(t) / nt, a1 = total * static_cast<size_t>(t + 1) / nt;
+            size_t q = static_cast<size_t>(std::upper_bound(pstart.begin(), pstart.end(), a0) - pstart.begin()) - 1;
+            for (size_t a = a0; a < a1; ++q) {
+                const DealPlan& P = plans[q];
+                const size_t t0 = a - pstart[q];
+                const size_t t1 = std::min(P.take, a1 - pstart[q]);
+                const int32_t* r0 = rest + P.i;
+                const int32_t* o = plan_ord.data() + P.at;
+                const size_t gsz = static_cast<size_t>(P.gsz);
+                size_t g = t0 % gsz;
+                for (size_t x = t0; x < t1; ++x) {
+                    part[r0[x]] = o[g];
+                    if (++g == gsz) g = 0;
+                }
+                a = pstart[q] + t1;
+            }
+        });
     }
     static const bool trace = std::getenv("SCLAP_TRACE") != nullptr;
     if (trace)
