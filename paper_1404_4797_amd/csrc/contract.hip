@@ -74,11 +74,13 @@ __device__ __forceinline__ void wave_runs(int32_t key, int& lead, int& end) {
 }
 
 // Step 1: inter-cluster slots per fine node, cross[u] (one atomic per wave and
-// row run: rows are contiguous in slot order).
+// row run: rows are contiguous in slot order); keeps C(v) of every slot for
+// step 2, which then reads it in slot order instead of gathering it again.
 __global__ void __launch_bounds__(kTileThreads) cross_count_kernel(const int64_t* __restrict__ xadj,
                                                                    const int32_t* __restrict__ adj, int32_t n,
                                                                    int64_t S, const int32_t* __restrict__ C,
-                                                                   int32_t* __restrict__ cross) {
+                                                                   int32_t* __restrict__ cross,
+                                                                   int32_t* __restrict__ cvs) {
     __shared__ int32_t owner[kTile];
     const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kTile;
     const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
@@ -90,7 +92,9 @@ __global__ void __launch_bounds__(kTileThreads) cross_count_kernel(const int64_t
         bool e = false;
         if (i < i1) {
             u = owner[i - i0];
-            e = C[u] != C[adj[i]];
+            const int32_t cv = C[adj[i]];
+            cvs[i] = cv;
+            e = C[u] != cv;
         }
         int lead, end;
         wave_runs(u, lead, end);
@@ -119,7 +123,7 @@ __global__ void node_base_kernel(int32_t n, const int32_t* __restrict__ C, const
 // Step 2: (C(v), w) of every inter-cluster slot into its node's block of the
 // coarse row; each wave run of a row reserves its part of the block.
 __global__ void __launch_bounds__(kTileThreads) row_scatter_kernel(const int64_t* __restrict__ xadj,
-                                                                   const int32_t* __restrict__ adj,
+                                                                   const int32_t* __restrict__ cvs,
                                                                    const int32_t* __restrict__ ew, int32_t n, int64_t S,
                                                                    const int32_t* __restrict__ C,
                                                                    const int64_t* __restrict__ nbase,
@@ -136,7 +140,7 @@ __global__ void __launch_bounds__(kTileThreads) row_scatter_kernel(const int64_t
         bool e = false;
         if (i < i1) {
             u = owner[i - i0];
-            cv = C[adj[i]];
+            cv = cvs[i];
             e = C[u] != cv;
         }
         int lead, end;
@@ -1096,11 +1100,12 @@ void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGrap
     fill_i32(rowcnt.get(), 0, nc, s);
     int64_t m = 0;
     DBuf<int32_t> cross(n, s);
+    DBuf<int32_t> cvs(g.S > 0 ? g.S : 1, s);  // C(v) of every slot
     fill_i32(cross.get(), 0, n, s);
     if (g.S > 0) {
-        ProfScope ps("contract_count", (8.0 + 4.0) * static_cast<double>(g.S) + 8.0 * n, s);
+        ProfScope ps("contract_count", (8.0 + 8.0) * static_cast<double>(g.S) + 8.0 * n, s);
         cross_count_kernel<<<static_cast<unsigned>(ntiles), kTileThreads, 0, s>>>(g.xadj, g.adj, n, g.S, C,
-                                                                                   cross.get());
+                                                                                   cross.get(), cvs.get());
         LAUNCHCHK();
         row_count_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, C, cross.get(), rowcnt.get());
         LAUNCHCHK();
@@ -1127,9 +1132,10 @@ void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGrap
         node_base_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, C, cross.get(), rowoff.get(), fill.get(), nbase.get());
         LAUNCHCHK();
         row_scatter_kernel<<<static_cast<unsigned>(ntiles), kTileThreads, 0, s>>>(
-            g.xadj, g.adj, g.ew, n, g.S, C, nbase.get(), nfill.get(), tk.get(), tw.get());
+            g.xadj, cvs.get(), g.ew, n, g.S, C, nbase.get(), nfill.get(), tk.get(), tw.get());
         LAUNCHCHK();
     }
+    cvs.release();
 
     // 3: merge (and order) every row
     DBuf<int32_t> dcnt(nc, s);

@@ -92,8 +92,11 @@ struct VStats {
     uint32_t pad[2];
 };
 
+// Hash of a directed slot (u, v, w): sums over all slots and over all
+// reversed slots agree for a symmetric graph.  One mix of the ordered pair,
+// with the weight spread over all 64 bits by an odd multiplier.
 __device__ __forceinline__ unsigned long long edge_hash(uint32_t u, uint32_t v, uint32_t w) {
-    return mix64(mix64((static_cast<uint64_t>(u) << 32) | v) ^ w);
+    return mix64(((static_cast<uint64_t>(u) << 32) | v) ^ (static_cast<uint64_t>(w) * 0xD6E8FEB86659FD93ULL));
 }
 
 __global__ void __launch_bounds__(kTileThreads) validate_nodes_kernel(int32_t n, const int64_t* __restrict__ xadj,
