@@ -80,11 +80,11 @@ __global__ void __launch_bounds__(kTileThreads) cross_count_kernel(const int64_t
                                                                    const int32_t* __restrict__ adj, int32_t n,
                                                                    int64_t S, const int32_t* __restrict__ C,
                                                                    int32_t* __restrict__ cross,
-                                                                   int32_t* __restrict__ cvs) {
+                                                                   int32_t* __restrict__ cvs, const int32_t* __restrict__ trow) {
     __shared__ int32_t owner[kTile];
     const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kTile;
     const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
-    tile_owners(xadj, n, i0, i1, owner);
+    tile_owners(xadj, trow, static_cast<int64_t>(blockIdx.x), i0, i1, owner);
     const int lane = lane_id();
     for (int r = 0; r < kTilePer; ++r) {
         const int64_t i = i0 + r * kTileThreads + threadIdx.x;
@@ -128,11 +128,11 @@ __global__ void __launch_bounds__(kTileThreads) row_scatter_kernel(const int64_t
                                                                    const int32_t* __restrict__ C,
                                                                    const int64_t* __restrict__ nbase,
                                                                    int32_t* __restrict__ nfill,
-                                                                   int32_t* __restrict__ tk, int32_t* __restrict__ tw) {
+                                                                   int32_t* __restrict__ tk, int32_t* __restrict__ tw, const int32_t* __restrict__ trow) {
     __shared__ int32_t owner[kTile];
     const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kTile;
     const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
-    tile_owners(xadj, n, i0, i1, owner);
+    tile_owners(xadj, trow, static_cast<int64_t>(blockIdx.x), i0, i1, owner);
     const int lane = lane_id();
     for (int r = 0; r < kTilePer; ++r) {
         const int64_t i = i0 + r * kTileThreads + threadIdx.x;
@@ -833,11 +833,11 @@ __global__ void __launch_bounds__(kTileThreads) row_copy_kernel(const int64_t* _
                                                                 const int64_t* __restrict__ cxadj,
                                                                 const int32_t* __restrict__ tk,
                                                                 const int32_t* __restrict__ tw,
-                                                                int32_t* __restrict__ cadj, int32_t* __restrict__ cew) {
+                                                                int32_t* __restrict__ cadj, int32_t* __restrict__ cew, const int32_t* __restrict__ trow) {
     __shared__ int32_t owner[kTile];
     const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kTile;
     const int64_t i1 = i0 + kTile < m ? i0 + kTile : m;
-    tile_owners(rowoff, nc, i0, i1, owner);
+    tile_owners(rowoff, trow, static_cast<int64_t>(blockIdx.x), i0, i1, owner);
     for (int r = 0; r < kTilePer; ++r) {
         const int64_t i = i0 + r * kTileThreads + threadIdx.x;
         if (i >= i1) continue;
@@ -1101,11 +1101,13 @@ void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGrap
     int64_t m = 0;
     DBuf<int32_t> cross(n, s);
     DBuf<int32_t> cvs(g.S > 0 ? g.S : 1, s);  // C(v) of every slot
+    TileRows gtiles(g.xadj, n, g.S, s);
     fill_i32(cross.get(), 0, n, s);
     if (g.S > 0) {
         ProfScope ps("contract_count", (8.0 + 8.0) * static_cast<double>(g.S) + 8.0 * n, s);
         cross_count_kernel<<<static_cast<unsigned>(ntiles), kTileThreads, 0, s>>>(g.xadj, g.adj, n, g.S, C,
-                                                                                   cross.get(), cvs.get());
+                                                                                   cross.get(), cvs.get(),
+                                                                                   gtiles.trow.get());
         LAUNCHCHK();
         row_count_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, C, cross.get(), rowcnt.get());
         LAUNCHCHK();
@@ -1132,7 +1134,7 @@ void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGrap
         node_base_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, C, cross.get(), rowoff.get(), fill.get(), nbase.get());
         LAUNCHCHK();
         row_scatter_kernel<<<static_cast<unsigned>(ntiles), kTileThreads, 0, s>>>(
-            g.xadj, cvs.get(), g.ew, n, g.S, C, nbase.get(), nfill.get(), tk.get(), tw.get());
+            g.xadj, cvs.get(), g.ew, n, g.S, C, nbase.get(), nfill.get(), tk.get(), tw.get(), gtiles.trow.get());
         LAUNCHCHK();
     }
     cvs.release();
@@ -1153,9 +1155,11 @@ void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGrap
     coarse.adj.alloc(std::max<int64_t>(Sc, 1), s);
     coarse.ew.alloc(std::max<int64_t>(Sc, 1), s);
     const int64_t mtiles = (m + kTile - 1) / kTile;
+    TileRows ctiles(rowoff.get(), nc, m, s);
     row_copy_kernel<<<static_cast<unsigned>(mtiles), kTileThreads, 0, s>>>(rowoff.get(), nc, m, dcnt.get(),
                                                                            coarse.xadj.get(), tk.get(), tw.get(),
-                                                                           coarse.adj.get(), coarse.ew.get());
+                                                                           coarse.adj.get(), coarse.ew.get(),
+                                                                           ctiles.trow.get());
     LAUNCHCHK();
     HIPCHK(hipStreamSynchronize(s));
 }

@@ -37,13 +37,13 @@ template <typename P>
 __global__ void __launch_bounds__(kTileThreads) cut_kernel(const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj,
                                                            const int32_t* __restrict__ ew, int32_t n, int64_t S,
                                                            const P* __restrict__ part,
-                                                           unsigned long long* __restrict__ cut) {
+                                                           unsigned long long* __restrict__ cut, const int32_t* __restrict__ trow) {
     __shared__ int32_t owner[kTile];
     unsigned long long acc = 0;
     for (int64_t tile = blockIdx.x; tile * kTile < S; tile += gridDim.x) {
         const int64_t i0 = tile * kTile;
         const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
-        tile_owners(xadj, n, i0, i1, owner);
+        tile_owners(xadj, trow, tile, i0, i1, owner);
         for (int r = 0; r < kTilePer; ++r) {
             const int64_t i = i0 + r * kTileThreads + threadIdx.x;
             if (i < i1 && part[owner[i - i0]] != part[adj[i]]) acc += ew ? static_cast<unsigned long long>(ew[i]) : 1ULL;
@@ -130,14 +130,14 @@ __global__ void __launch_bounds__(kTileThreads) validate_nodes_kernel(int32_t n,
 __global__ void __launch_bounds__(kTileThreads) validate_slots_kernel(const int64_t* __restrict__ xadj,
                                                                       const int32_t* __restrict__ adj,
                                                                       const int32_t* __restrict__ ew, int32_t n,
-                                                                      int64_t S, VStats* st) {
+                                                                      int64_t S, VStats* st, const int32_t* __restrict__ trow) {
     __shared__ int32_t owner[kTile];
     unsigned long long ws = 0, hf = 0, hb = 0;
     uint32_t bad = 0;
     for (int64_t tile = blockIdx.x; tile * kTile < S; tile += gridDim.x) {
         const int64_t i0 = tile * kTile;
         const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
-        tile_owners(xadj, n, i0, i1, owner);
+        tile_owners(xadj, trow, tile, i0, i1, owner);
         for (int r = 0; r < kTilePer; ++r) {
             const int64_t i = i0 + r * kTileThreads + threadIdx.x;
             if (i >= i1) continue;
@@ -191,15 +191,16 @@ void cut_and_weights(const DevGraph& g, const int32_t* part, int32_t k, int64_t*
     DBuf<unsigned long long> acc(1 + static_cast<size_t>(k), s);
     HIPCHK(hipMemsetAsync(acc.get(), 0, (1 + static_cast<size_t>(k)) * sizeof(unsigned long long), s));
     if (g.S > 0) {
+        TileRows tr(g.xadj, g.n, g.S, s);
         if (k <= 256) {
             DBuf<uint8_t> p8(g.n, s);
             to_u8_kernel<<<grid_for(g.n, 256), 256, 0, s>>>(g.n, part, p8.get());
             LAUNCHCHK();
             cut_kernel<uint8_t><<<capped_tiles(g.S), kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, g.n, g.S, p8.get(),
-                                                                          acc.get());
+                                                                          acc.get(), tr.trow.get());
         } else {
             cut_kernel<int32_t><<<capped_tiles(g.S), kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, g.n, g.S, part,
-                                                                          acc.get());
+                                                                          acc.get(), tr.trow.get());
         }
         LAUNCHCHK();
     }
@@ -238,7 +239,9 @@ int validate_graph(const DevGraph& g, int64_t* cV, int64_t* cmax, hipStream_t s)
     HIPCHK(hipStreamSynchronize(s));
     if (h.bad) return -1;  // offsets not monotone or negative node weight
     if (g.S > 0) {
-        validate_slots_kernel<<<capped_tiles(g.S), kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, n, g.S, st.get());
+        TileRows tr(g.xadj, n, g.S, s);  // offsets checked monotone above
+        validate_slots_kernel<<<capped_tiles(g.S), kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, n, g.S, st.get(),
+                                                                          tr.trow.get());
         LAUNCHCHK();
         HIPCHK(hipMemcpyAsync(&h, st.get(), sizeof(VStats), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -354,12 +357,12 @@ __global__ void __launch_bounds__(kTileThreads) graph_cut_kernel(const int64_t* 
                                                                  const int32_t* __restrict__ ew, int32_t n, int64_t S,
                                                                  const int32_t* __restrict__ part,
                                                                  const int32_t* __restrict__ gid,
-                                                                 unsigned long long* __restrict__ cut) {
+                                                                 unsigned long long* __restrict__ cut, const int32_t* __restrict__ trow) {
     __shared__ int32_t owner[kTile];
     for (int64_t tile = blockIdx.x; tile * kTile < S; tile += gridDim.x) {
         const int64_t i0 = tile * kTile;
         const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
-        tile_owners(xadj, n, i0, i1, owner);
+        tile_owners(xadj, trow, tile, i0, i1, owner);
         for (int r = 0; r < kTilePer; ++r) {
             const int64_t i = i0 + r * kTileThreads + threadIdx.x;
             const bool valid = i < i1;
@@ -503,7 +506,9 @@ void graph_cuts(const DevGraph& g, const int32_t* part, const int32_t* gid, int3
     if (g.S > 0) {
         const int64_t ntiles = (g.S + kTile - 1) / kTile;
         const unsigned grid = static_cast<unsigned>(ntiles < 2048 ? ntiles : 2048);
-        graph_cut_kernel<<<grid, kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, g.n, g.S, part, gid, d.get());
+        TileRows tr(g.xadj, g.n, g.S, s);
+        graph_cut_kernel<<<grid, kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, g.n, g.S, part, gid, d.get(),
+                                                       tr.trow.get());
         LAUNCHCHK();
     }
     std::vector<unsigned long long> h(std::max(G, 1));
@@ -565,12 +570,12 @@ namespace {
 __global__ void __launch_bounds__(kTileThreads) within_count_kernel(const int64_t* __restrict__ xadj,
                                                                     const int32_t* __restrict__ adj, int32_t n,
                                                                     int64_t S, const int32_t* __restrict__ blk,
-                                                                    int32_t* __restrict__ tcnt) {
+                                                                    int32_t* __restrict__ tcnt, const int32_t* __restrict__ trow) {
     __shared__ int32_t owner[kTile];
     __shared__ int32_t s_w[kTileThreads / kWave];
     const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kTile;
     const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
-    tile_owners(xadj, n, i0, i1, owner);
+    tile_owners(xadj, trow, static_cast<int64_t>(blockIdx.x), i0, i1, owner);
     int32_t c = 0;
     for (int r = 0; r < kTilePer; ++r) {
         const int64_t i = i0 + r * kTileThreads + threadIdx.x;
@@ -600,7 +605,7 @@ __device__ int32_t first_row_from(const int64_t* __restrict__ xadj, int32_t n, i
 __global__ void __launch_bounds__(kTileThreads) within_scatter_kernel(
     const int64_t* __restrict__ xadj, const int32_t* __restrict__ adj, const int32_t* __restrict__ ew, int32_t n,
     int64_t S, const int32_t* __restrict__ blk, const int64_t* __restrict__ tbase, int64_t* __restrict__ oxadj,
-    int32_t* __restrict__ oadj, int32_t* __restrict__ oew) {
+    int32_t* __restrict__ oadj, int32_t* __restrict__ oew, const int32_t* __restrict__ trow) {
     __shared__ int32_t owner[kTile];
     __shared__ int32_t pre[kTile];
     __shared__ int32_t s_w[kTileThreads / kWave];
@@ -609,7 +614,7 @@ __global__ void __launch_bounds__(kTileThreads) within_scatter_kernel(
     const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kTile;
     const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
     if (tid == 0) s_u0 = first_row_from(xadj, n, i0);
-    tile_owners(xadj, n, i0, i1, owner);  // synchronises
+    tile_owners(xadj, trow, static_cast<int64_t>(blockIdx.x), i0, i1, owner);  // synchronises
     // kTilePer consecutive slots per thread
     uint32_t keep = 0;
     int32_t c = 0;
@@ -673,11 +678,14 @@ void within_blocks(const DevGraph& g, const int32_t* blk, OwnedDevGraph& out, hi
     int64_t St = 0;
     const int64_t tiles = (g.S + kTile - 1) / kTile;
     DBuf<int64_t> tbase;
+    DBuf<int32_t> trow;
     if (g.S > 0) {
+        TileRows tr(g.xadj, g.n, g.S, s);
+        trow = std::move(tr.trow);
         DBuf<int32_t> tcnt(tiles, s);
         tbase.alloc(tiles, s);
         within_count_kernel<<<static_cast<unsigned>(tiles), kTileThreads, 0, s>>>(g.xadj, g.adj, g.n, g.S, blk,
-                                                                                  tcnt.get());
+                                                                                  tcnt.get(), trow.get());
         LAUNCHCHK();
         exclusive_scan_i32_to_i64(tcnt.get(), tbase.get(), tiles, total.get(), s);
         HIPCHK(hipMemcpyAsync(&St, total.get(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -691,7 +699,7 @@ void within_blocks(const DevGraph& g, const int32_t* blk, OwnedDevGraph& out, hi
     if (g.S > 0) {
         within_scatter_kernel<<<static_cast<unsigned>(tiles), kTileThreads, 0, s>>>(
             g.xadj, g.adj, g.ew, g.n, g.S, blk, tbase.get(), out.xadj.get(), out.adj.get(),
-            g.ew ? out.ew.get() : nullptr);
+            g.ew ? out.ew.get() : nullptr, trow.get());
         LAUNCHCHK();
     }
     within_tail_kernel<<<grid_for(static_cast<int64_t>(g.n) + 1, 256), 256, 0, s>>>(g.xadj, g.n, g.S, total.get(),
