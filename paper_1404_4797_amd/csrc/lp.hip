@@ -70,7 +70,7 @@ struct Counters {
     uint32_t bad_color;
     uint32_t nseg;         // targets that cannot take all their candidates
     uint32_t slow_total;   // entries reserved in their segments
-    uint32_t round_cands;  // candidates of the round so far
+    uint32_t unused;
     uint32_t nlarge;       // segments longer than kSmallSeg
     uint32_t nlchunks;     // kSegChunk-entry chunks of those segments
     int32_t gkey;          // gmax of the sub-round's keys, kept past the counter reset
@@ -1080,6 +1080,13 @@ __device__ __forceinline__ int64_t bound_of(const Bounds& B, int32_t t) {
 constexpr int kAggChunk = 2048;
 constexpr int kAggTable = 4096;
 
+// A round runs only while the previous one had candidates (gate: that
+// round's candidate count, null for the first round).  The host enqueues
+// round r + 1 before it has read round r's count, so every kernel that
+// changes the state checks the gate: after a round without candidates the
+// following ones change nothing.
+__device__ __forceinline__ bool stopped(const uint32_t* gate) { return gate && *gate == 0; }
+
 template <bool kSmall>
 __device__ __forceinline__ int32_t agg_slot(int32_t* keys, int32_t t, bool insert) {
     if (kSmall) return t;
@@ -1098,7 +1105,10 @@ template <bool kSmall>
 __global__ void __launch_bounds__(256) cand_accum_kernel(const int32_t* __restrict__ ct,
                                                          const int32_t* __restrict__ nodes, int32_t count,
                                                          const int32_t* __restrict__ vw, int32_t* __restrict__ tsum,
-                                                         int32_t* __restrict__ cnt, int32_t nw, Counters* ctr) {
+                                                         int32_t* __restrict__ cnt, int32_t nw, Counters* ctr,
+                                                         const uint32_t* __restrict__ gate,
+                                                         uint32_t* __restrict__ round_cnt) {
+    if (stopped(gate)) return;  // uniform over the grid
     constexpr int kSlots = kSmall ? kSmallLabels : kAggTable;
     __shared__ int32_t keys[kSmall ? 1 : kAggTable];
     __shared__ int32_t lsum[kSlots];
@@ -1149,7 +1159,7 @@ __global__ void __launch_bounds__(256) cand_accum_kernel(const int32_t* __restri
     const int32_t tot = block_sum_i32(found);
     if (threadIdx.x == 0 && tot) {
         atomicAdd(&ctr->ncand, static_cast<uint32_t>(tot));
-        atomicAdd(&ctr->round_cands, static_cast<uint32_t>(tot));
+        atomicAdd(round_cnt, static_cast<uint32_t>(tot));
     }
 }
 
@@ -1214,8 +1224,10 @@ __global__ void __launch_bounds__(256) admit_kernel(const int32_t* __restrict__ 
                                                     const int32_t* __restrict__ cnt, Bounds B,
                                                     uint8_t* __restrict__ ok, uint32_t* __restrict__ slow_idx,
                                                     int32_t* __restrict__ seg_off, int32_t* __restrict__ seg_list,
-                                                    LargeSel L, int32_t small_max, int32_t nw, Counters* ctr) {
+                                                    LargeSel L, int32_t small_max, int32_t nw, Counters* ctr,
+                                                    const uint32_t* __restrict__ gate) {
     __shared__ int32_t s_min[4], s_max[4];
+    if (stopped(gate)) return;  // uniform over the grid
     if (kSmall) {
         for (int32_t t = blockIdx.x * 256 + threadIdx.x; t < nw; t += gridDim.x * 256) {
             if (cnt[t] == 0) continue;
@@ -1581,7 +1593,8 @@ __global__ void __launch_bounds__(256) apply_kernel(const int32_t* __restrict__ 
                                                     const int32_t* __restrict__ vw, int32_t* __restrict__ label,
                                                     uint8_t* __restrict__ label8, uint16_t* __restrict__ label16,
                                                     int32_t* __restrict__ w, int32_t* __restrict__ tsum,
-                                                    int32_t* __restrict__ cnt, int32_t nw, Counters* ctr) {
+                                                    int32_t* __restrict__ cnt, int32_t nw, Counters* ctr,
+                                                    const uint32_t* __restrict__ gate) {
     __shared__ int32_t delta[kSmall ? kSmallLabels : 1];
     const int32_t gkey = ctr->gkey;
     if (blockIdx.x == 0) {
@@ -1592,6 +1605,7 @@ __global__ void __launch_bounds__(256) apply_kernel(const int32_t* __restrict__ 
                 cnt[j] = 0;
             }
     }
+    if (stopped(gate)) return;  // uniform over the grid
     if (kSmall) {
         for (int j = threadIdx.x; j < nw; j += 256) delta[j] = 0;
         __syncthreads();
@@ -1645,7 +1659,9 @@ __global__ void narrow_kernel(const int32_t* __restrict__ label, int32_t n, T* _
 __global__ void __launch_bounds__(256) unquiet_kernel(const int32_t* __restrict__ ct, const uint8_t* __restrict__ ok,
                                                       const int32_t* __restrict__ nodes, int32_t count,
                                                       const int64_t* __restrict__ xadj,
-                                                      const int32_t* __restrict__ adj, uint8_t* __restrict__ quiet) {
+                                                      const int32_t* __restrict__ adj, uint8_t* __restrict__ quiet,
+                                                      const uint32_t* __restrict__ gate) {
+    if (stopped(gate)) return;
     const int64_t base = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) & ~63LL;
     const int lane = lane_id();
     const int64_t p = base + lane;
@@ -1660,10 +1676,7 @@ __global__ void __launch_bounds__(256) unquiet_kernel(const int32_t* __restrict_
     }
 }
 
-__global__ void reset_counters_kernel(Counters* ctr, int round_too) {
-    clear_subround(ctr);
-    if (round_too) ctr->round_cands = 0;
-}
+__global__ void reset_counters_kernel(Counters* ctr) { clear_subround(ctr); }
 
 // --------------------------------------------------------------- schedule
 
@@ -1841,6 +1854,34 @@ thread_local Counters* t_host_ctr = nullptr;
 Counters* host_counters() {
     if (!t_host_ctr) HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&t_host_ctr), sizeof(Counters), hipHostMallocDefault));
     return t_host_ctr;
+}
+
+// Pinned host copies of the per-round candidate counts (grown as needed,
+// kept for the thread's lifetime).
+thread_local uint32_t* t_host_rc = nullptr;
+thread_local int32_t t_host_rc_cap = 0;
+
+uint32_t* host_round_counts(int32_t rounds) {
+    if (rounds > t_host_rc_cap) {
+        if (t_host_rc) HIPCHK(hipHostFree(t_host_rc));
+        t_host_rc_cap = std::max(rounds, 64);
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&t_host_rc), sizeof(uint32_t) * t_host_rc_cap,
+                             hipHostMallocDefault));
+    }
+    return t_host_rc;
+}
+
+// Two events marking the end of consecutive rounds (per thread).
+struct RoundEvents {
+    hipEvent_t ev[2];
+    RoundEvents() {
+        for (hipEvent_t& e : ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+};
+
+RoundEvents& round_events() {
+    thread_local RoundEvents r;
+    return r;
 }
 
 unsigned capped_grid(int64_t items) {
@@ -2126,12 +2167,33 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     auto eval_bytes = [&](int64_t nodes_in, unsigned long long slots_in) {
         return node_bytes * static_cast<double>(nodes_in) + slot_bytes * static_cast<double>(slots_in);
     };
-    reset_counters_kernel<<<1, 1, 0, s>>>(ctr.get(), 1);
+    reset_counters_kernel<<<1, 1, 0, s>>>(ctr.get());
     LAUNCHCHK();
     const int bits_v = bits_for(static_cast<uint64_t>(n - 1));
     EvalStreams& evs = eval_streams();
 
-    for (int32_t r = 0; r < rounds; ++r) {
+    // candidates per round, read back one round late (see stopped())
+    DBuf<uint32_t> rcnt(std::max(rounds, 1), s);
+    fill_u32(rcnt.get(), 0, std::max(rounds, 1), s);
+    uint32_t* hrc = host_round_counts(rounds);
+    RoundEvents& rev = round_events();
+    bool halted = false;
+    // bookkeeping of a finished round q (read back from the device)
+    auto finish_round = [&](int32_t q) {
+        HIPCHK(hipEventSynchronize(rev.ev[q & 1]));
+        const uint32_t round_cands = hrc[q];
+        res.rounds_run = q + 1;
+        res.moves += round_cands;
+        if (round_cands == 0) {
+            halted = true;
+            return;
+        }
+        // round q + 1 is already enqueued: tracking can start at q + 2
+        if (track_quiet && mark_from == INT_MAX && static_cast<int64_t>(round_cands) * 8 <= n) mark_from = q + 2;
+    };
+
+    for (int32_t r = 0; r < rounds && !halted; ++r) {
+        const uint32_t* gate = r > 0 ? rcnt.get() + (r - 1) : nullptr;
         if (mg) {
             graph_prefix_kernel<<<grid_for(mg->G, 256), 256, 0, s>>>(mg->G, mg->seed, 2, lvl64, ph64, r, g_tp.get());
             LAUNCHCHK();
@@ -2280,19 +2342,19 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 const unsigned gc = capped_grid(ccount);
                 if (small)
                     cand_accum_kernel<true><<<gc, 256, 0, s>>>(ct.get(), cnodes, ccount, g.vw, tsum.get(), tcnt.get(),
-                                                               nw, ctr.get());
+                                                               nw, ctr.get(), gate, rcnt.get() + r);
                 else
                     cand_accum_kernel<false><<<gc, 256, 0, s>>>(ct.get(), cnodes, ccount, g.vw, tsum.get(),
-                                                                tcnt.get(), nw, ctr.get());
+                                                                tcnt.get(), nw, ctr.get(), gate, rcnt.get() + r);
                 LAUNCHCHK();
                 if (small)
                     admit_kernel<true><<<gc, 256, 0, s>>>(ct.get(), cg.get(), ccount, w, tsum.get(), tcnt.get(), BB,
                                                           ok.get(), slow_idx.get(), seg_off.get(), seg_list.get(), LS,
-                                                          small_max, nw, ctr.get());
+                                                          small_max, nw, ctr.get(), gate);
                 else
                     admit_kernel<false><<<gc, 256, 0, s>>>(ct.get(), cg.get(), ccount, w, tsum.get(), tcnt.get(), BB,
                                                            ok.get(), slow_idx.get(), seg_off.get(), seg_list.get(),
-                                                           LS, small_max, nw, ctr.get());
+                                                           LS, small_max, nw, ctr.get(), gate);
                 LAUNCHCHK();
             }
             {
@@ -2335,13 +2397,13 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                     apply_kernel<true><<<capped_grid(ccount), 256, 0, s>>>(ct.get(), ok.get(), cnodes, ccount,
                                                                            cg.get(), bits_v, bnd.get(), g.vw, label,
                                                                            lab8.get(), lab16.get(), w, tsum.get(),
-                                                                           tcnt.get(), nw, ctr.get());
+                                                                           tcnt.get(), nw, ctr.get(), gate);
                     LAUNCHCHK();
                 } else {
                     apply_kernel<false><<<grid_for(ccount, 256), 256, 0, s>>>(ct.get(), ok.get(), cnodes, ccount,
                                                                               cg.get(), bits_v, bnd.get(), g.vw, label,
                                                                               lab8.get(), lab16.get(), w, tsum.get(),
-                                                                              tcnt.get(), nw, ctr.get());
+                                                                              tcnt.get(), nw, ctr.get(), gate);
                     LAUNCHCHK();
                 }
             }
@@ -2349,23 +2411,18 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 ProfScope ps("lp_unquiet", 0, s);
                 unquiet_kernel<<<grid_for(ccount, 256), 256, 0, s>>>(ct.get(), ok.get(), cnodes,
                                                                       static_cast<int32_t>(ccount), g.xadj, g.adj,
-                                                                      A.quiet);
+                                                                      A.quiet, gate);
                 LAUNCHCHK();
             }
         }
-        // one host synchronisation per round: a round without candidates
-        // moved nothing (the first candidate of every target is always admitted)
-        HIPCHK(hipMemcpyAsync(hctr, ctr.get(), sizeof(Counters), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (profiler().on) profiler().collect();
-        const uint32_t round_cands = hctr->round_cands;
-        reset_counters_kernel<<<1, 1, 0, s>>>(ctr.get(), 1);
-        LAUNCHCHK();
-        res.rounds_run = r + 1;
-        res.moves += round_cands;
-        if (round_cands == 0) break;
-        if (track_quiet && mark_from == INT_MAX && static_cast<int64_t>(round_cands) * 8 <= n) mark_from = r + 1;
+        // a round without candidates moved nothing (the first candidate of
+        // every target is always admitted) and ends the run; its count is
+        // read while the next round runs
+        HIPCHK(hipMemcpyAsync(hrc + r, rcnt.get() + r, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(rev.ev[r & 1], s));
+        if (r > 0) finish_round(r - 1);
     }
+    if (!halted && rounds > 0) finish_round(rounds - 1);
     res.visits = static_cast<int64_t>(res.rounds_run) * g.S;
     HIPCHK(hipStreamSynchronize(s));
     if (profiler().on) profiler().collect();
