@@ -1126,7 +1126,7 @@ void contract(const DevGraph& g, const int32_t* labels, int32_t* C, OwnedDevGrap
     fill_i64(rowoff.get() + nc, m, 1, s);
     DBuf<int32_t> tk(m, s), tw(m, s);
     {
-        ProfScope ps("contract_emit", (8.0 + (g.ew ? 4.0 : 0.0)) * static_cast<double>(g.S) + 8.0 * n + 8.0 * m, s);
+        ProfScope ps("contract_emit", (4.0 + (g.ew ? 4.0 : 0.0)) * static_cast<double>(g.S) + 8.0 * n + 8.0 * m, s);
         DBuf<int32_t> fill(nc, s), nfill(n, s);
         DBuf<int64_t> nbase(n, s);
         fill_i32(fill.get(), 0, nc, s);
