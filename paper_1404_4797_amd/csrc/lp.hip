@@ -1808,10 +1808,12 @@ struct HubPlan {
 // Side streams for the independent evaluation launches of a sub-round
 // (default priority, created once per thread).  fork() makes them wait for
 // the work already on the caller's stream, join() makes the caller's stream
-// wait for them.
+// wait for them.  The hub chain, usually the longest, stays on the caller's
+// stream, so the join mostly waits on work that has already finished (a
+// cross-stream wait on unfinished work costs the device some 20 us).
 class EvalStreams {
   public:
-    static constexpr int kN = 3;
+    static constexpr int kN = 2;
     EvalStreams() {
         for (int i = 0; i < kN; ++i) {
             HIPCHK(hipStreamCreateWithFlags(&st_[i], hipStreamNonBlocking));
@@ -1831,10 +1833,9 @@ class EvalStreams {
             HIPCHK(hipStreamWaitEvent(s, done_[i], 0));
         }
     }
-    hipStream_t hub() const { return st_[0]; }
     // heavy buckets (large rows) apart from each other and from the hubs
     hipStream_t bucket(int bk) const {
-        static const int kMap[kNB - 1] = {1, 1, 2, 2, 2, 1, 2, 1};
+        static const int kMap[kNB - 1] = {0, 0, 1, 1, 1, 0, 1, 0};
         return st_[kMap[bk]];
     }
 
@@ -2210,7 +2211,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
             const int32_t* cnodes = nodes + off[c0];
             // evaluation: one result per schedule entry of this colour; the
             // buckets are independent and run side by side on the evaluation
-            // streams (hubs on the first), joined before admission
+            // streams (hubs on the caller's stream), joined before admission
             unsigned long long colour_slots = 0;
             for (int32_t bk = 0; bk < kNB; ++bk) colour_slots += cslots[c0 + bk];
             const bool side = colour_slots >= (1ULL << 22);  // small colours stay on one stream
@@ -2219,7 +2220,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
             // longest, so its workgroups should be dispatched before the
             // other buckets fill the device
             const HubPlan& P = plans[sc];
-            const hipStream_t hs = side ? evs.hub() : s;
+            const hipStream_t hs = s;
             if (P.count > 0) {
                 const int32_t Hn = P.count;
                 HubArgs H;
