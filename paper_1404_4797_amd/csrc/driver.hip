@@ -16,6 +16,8 @@
 #include <utility>
 #include <vector>
 
+#include <immintrin.h>
+
 #include "driver.hpp"
 #include "profile.hpp"
 
@@ -146,15 +148,30 @@ struct MinTree {  // node weights are int32; INT32_MAX marks an erased leaf
             t[p] = m;
         }
     }
-    int32_t first_le(int64_t from, int64_t cap) const { return static_cast<int32_t>(descend(1, 0, size, from, cap)); }
-    int64_t min() const { return t[1] == INT32_MAX ? INT64_MAX : t[1]; }
-    int64_t descend(int64_t node, int64_t lo, int64_t hi, int64_t from, int64_t cap) const {
-        if (hi <= from || t[node] > cap) return -1;
-        if (hi - lo == 1) return lo;
-        const int64_t mid = (lo + hi) / 2;
-        const int64_t r = descend(2 * node, lo, mid, from, cap);
-        return r >= 0 ? r : descend(2 * node + 1, mid, hi, from, cap);
+    // smallest index >= from whose weight is <= cap, or -1: from the leaf,
+    // climb while on a right child, step to the right sibling until one holds
+    // a fitting leaf, then descend to its leftmost fitting leaf (the next
+    // seed is usually close, so this climbs only a few levels)
+    int32_t first_le(int64_t from, int64_t cap) const {
+        if (from < 0) from = 0;
+        if (from >= size) return -1;
+        int64_t p = from + size;
+        if (t[p] <= cap) return static_cast<int32_t>(from);
+        while (true) {
+            while (p & 1) {
+                p >>= 1;
+                if (p <= 1) return -1;
+            }
+            ++p;
+            if (t[p] <= cap) break;
+        }
+        while (p < size) {
+            p <<= 1;
+            if (t[p] > cap) ++p;
+        }
+        return static_cast<int32_t>(p - size);
     }
+    int64_t min() const { return t[1] == INT32_MAX ? INT64_MAX : t[1]; }
 };
 
 // Binary min-heap of packed (weight << 32 | block) keys: the lightest block,
@@ -189,6 +206,42 @@ struct BlockHeap {
 };
 
 }  // namespace
+
+// Untaken-neighbour masks of a row, eight slots per byte (bit q of byte j for
+// slot 8j + q of the first 8 * nb slots): set when the neighbour's bit in the
+// taken bitmap is clear or its id is outside [0, ncore).  AVX2 gathers of the
+// bitmap words where the CPU has them, one slot at a time otherwise.  Bits
+// only go from clear to set while a row is walked, so a mask computed before
+// the walk may only over-report, and every reported slot is checked again.
+__attribute__((target("avx2"))) void untaken_masks_avx2(const int32_t* row, size_t nb, const uint32_t* taken32,
+                                                       uint32_t ncore, uint8_t* masks) {
+    const __m256i bias = _mm256_set1_epi32(static_cast<int>(0x80000000u));
+    const __m256i ncb = _mm256_xor_si256(_mm256_set1_epi32(static_cast<int>(ncore)), bias);
+    const __m256i low5 = _mm256_set1_epi32(31);
+    const __m256i one = _mm256_set1_epi32(1);
+    for (size_t j = 0; j < nb; ++j) {
+        const __m256i x = _mm256_loadu_si256(reinterpret_cast<const __m256i*>(row + 8 * j));
+        const __m256i inb = _mm256_cmpgt_epi32(ncb, _mm256_xor_si256(x, bias));  // x < ncore, unsigned
+        const __m256i idx = _mm256_and_si256(_mm256_srli_epi32(x, 5), inb);    // outside: word 0
+        const __m256i w = _mm256_i32gather_epi32(reinterpret_cast<const int*>(taken32), idx, 4);
+        const __m256i bit = _mm256_and_si256(_mm256_srlv_epi32(w, _mm256_and_si256(x, low5)), one);
+        const __m256i want = _mm256_or_si256(_mm256_cmpeq_epi32(bit, _mm256_setzero_si256()),
+                                             _mm256_andnot_si256(inb, _mm256_set1_epi32(-1)));
+        masks[j] = static_cast<uint8_t>(_mm256_movemask_ps(_mm256_castsi256_ps(want)));
+    }
+}
+
+void untaken_masks_scalar(const int32_t* row, size_t nb, const uint64_t* taken, uint32_t ncore, uint8_t* masks) {
+    for (size_t j = 0; j < nb; ++j) {
+        uint32_t m = 0;
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t x = static_cast<uint32_t>(row[8 * j + q]);
+            const uint64_t word = x < ncore ? taken[x >> 6] : 0ULL;
+            m |= static_cast<uint32_t>(~(word >> (x & 63)) & 1ULL) << q;
+        }
+        masks[j] = static_cast<uint8_t>(m);
+    }
+}
 
 // Grows blocks 0..k-2 by breadth-first search up to T each (seeds: smallest
 // unassigned node of positive degree that fits; neighbours in ascending id
@@ -298,7 +351,9 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
     if (bad.load()) fail(SCLAP_ERR_NOT_SYMMETRIC, "initial partition: a neighbour id is out of range or has no neighbours");
     cx[ncore] = S;
     const double t_seed = ms_since(T0);
-    std::vector<uint64_t> ctaken((static_cast<size_t>(ncore) + 63) / 64, 0);
+    std::vector<uint64_t> ctaken((static_cast<size_t>(ncore) + 63) / 64 + 1, 0);
+    static const bool use_avx2 = __builtin_cpu_supports("avx2");
+    std::vector<uint8_t> masks;
     std::vector<int32_t> nb;
     // core nodes in the order blocks take them; each search's queue is the
     // tail of this list that it appended (a node is queued at most once)
@@ -341,8 +396,8 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
                     row = nb.data();
                     row_end = nb.data() + nb.size();
                 }
-                // eight neighbours at a time: a mask of the untaken ones without
-                // branches, then the set bits in order (each rechecked, since
+                // eight neighbours at a time: masks of the untaken ones for the
+                // whole row, then the set bits in order (each rechecked, since
                 // taking one can affect a later equal neighbour)
                 auto visit = [&](int32_t x) {
                     if (static_cast<uint32_t>(x) >= static_cast<uint32_t>(ncore)) {  // -1 from core_ranks:
@@ -353,21 +408,22 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
                     if (wcur + cw32[x] > T) return;
                     take(x);
                 };
-                const int32_t* it = row;
-                for (; row_end - it >= 8; it += 8) {
-                    uint32_t m = 0;
-                    for (int q = 0; q < 8; ++q) {
-                        const uint32_t x = static_cast<uint32_t>(it[q]);
-                        const uint64_t word = x < static_cast<uint32_t>(ncore) ? ctaken[x >> 6] : 0ULL;
-                        m |= static_cast<uint32_t>(~(word >> (x & 63)) & 1ULL) << q;
-                    }
+                const size_t nb = static_cast<size_t>(row_end - row) / 8;
+                if (masks.size() < nb) masks.resize(nb);
+                if (use_avx2)
+                    untaken_masks_avx2(row, nb, reinterpret_cast<const uint32_t*>(ctaken.data()),
+                                       static_cast<uint32_t>(ncore), masks.data());
+                else
+                    untaken_masks_scalar(row, nb, ctaken.data(), static_cast<uint32_t>(ncore), masks.data());
+                for (size_t j = 0; j < nb; ++j) {
+                    uint32_t m = masks[j];
                     while (m) {
                         const int q = __builtin_ctz(m);
                         m &= m - 1;
-                        visit(it[q]);
+                        visit(row[8 * j + q]);
                     }
                 }
-                for (; it != row_end; ++it) visit(*it);
+                for (const int32_t* it = row + 8 * nb; it != row_end; ++it) visit(*it);
             }
             from = si + 1;
         }
