@@ -1123,15 +1123,25 @@ __global__ void __launch_bounds__(256) cand_accum_kernel(const int32_t* __restri
     int32_t found = 0;
     for (int64_t base = static_cast<int64_t>(blockIdx.x) * kAggChunk; base < count;
          base += static_cast<int64_t>(gridDim.x) * kAggChunk) {
-        for (int r = 0; r < kAggChunk / 256; ++r) {
+        // all of the thread's loads of the chunk first, then the LDS updates
+        constexpr int R = kAggChunk / 256;
+        int32_t tr[R], cr[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
             const int64_t p = base + r * 256 + threadIdx.x;
-            if (p >= count) continue;
-            const int32_t t = ct[p];
-            if (t < 0) continue;
+            tr[r] = p < count ? ct[p] : -1;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t p = base + r * 256 + threadIdx.x;
+            cr[r] = tr[r] >= 0 ? (vw ? vw[nodes[p]] : 1) : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (tr[r] < 0) continue;
             ++found;
-            const int32_t c = vw ? vw[nodes[p]] : 1;
-            const int32_t i = agg_slot<kSmall>(keys, t, true);
-            if (c) atomicAdd(&lsum[i], c);
+            const int32_t i = agg_slot<kSmall>(keys, tr[r], true);
+            if (cr[r]) atomicAdd(&lsum[i], cr[r]);
             atomicAdd(&lcnt[i], 1);
         }
         if (!kSmall) {  // flush this chunk's labels
@@ -1241,11 +1251,20 @@ __global__ void __launch_bounds__(256) admit_kernel(const int32_t* __restrict__ 
     int32_t gmin = INT_MAX, gmax = INT_MIN;
     for (int32_t base = blockIdx.x * (kAdmitIters * 256); base < count; base += gridDim.x * (kAdmitIters * 256)) {
         uint32_t mask = 0;
-#pragma unroll 4
+        // the thread's targets and gains first (loads in flight together),
+        // then the decisions
+        int32_t tt[kAdmitIters], gg[kAdmitIters];
+#pragma unroll
         for (int it = 0; it < kAdmitIters; ++it) {
             const int32_t p = base + it * 256 + static_cast<int32_t>(threadIdx.x);
-            if (p >= count) break;
-            const int32_t t = ct[p];
+            tt[it] = p < count ? ct[p] : -2;
+            gg[it] = p < count ? cg[p] : 0;
+        }
+#pragma unroll
+        for (int it = 0; it < kAdmitIters; ++it) {
+            const int32_t p = base + it * 256 + static_cast<int32_t>(threadIdx.x);
+            const int32_t t = tt[it];
+            if (t == -2) continue;  // past the end
             uint8_t o = 0;
             if (t >= 0) {
                 const int64_t room = bound_of(B, t) - static_cast<int64_t>(w[t]);
@@ -1254,7 +1273,7 @@ __global__ void __launch_bounds__(256) admit_kernel(const int32_t* __restrict__ 
                 } else {
                     o = kOkSlow;
                     mask |= 1u << it;
-                    const int32_t gain = cg[p];
+                    const int32_t gain = gg[it];
                     gmin = gain < gmin ? gain : gmin;
                     gmax = gain > gmax ? gain : gmax;
                     if (!kSmall && seg_off[t] == -1 && atomicCAS(&seg_off[t], -1, -2) == -1)
