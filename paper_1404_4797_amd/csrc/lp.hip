@@ -1329,11 +1329,22 @@ __global__ void __launch_bounds__(256) scatter_kernel(const uint32_t* __restrict
         lcnt[j] = 0;
     }
     __syncthreads();
+    constexpr int R = kAggChunk / 256;
     for (uint32_t base = blockIdx.x * kAggChunk; base < m; base += gridDim.x * kAggChunk) {
-        for (int r = 0; r < kAggChunk / 256; ++r) {
+        // the thread's slow candidates, their targets, nodes and gains, all
+        // loaded before the LDS work
+        uint32_t pr[R];
+        int32_t tr[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
             const uint32_t j = base + r * 256 + threadIdx.x;
-            if (j < m) atomicAdd(&lcnt[agg_slot<kSmall>(keys, ct[slow_idx[j]], true)], 1);
+            pr[r] = j < m ? slow_idx[j] : 0xFFFFFFFFu;
         }
+#pragma unroll
+        for (int r = 0; r < R; ++r) tr[r] = pr[r] != 0xFFFFFFFFu ? ct[pr[r]] : -1;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (tr[r] >= 0) atomicAdd(&lcnt[agg_slot<kSmall>(keys, tr[r], true)], 1);
         __syncthreads();
         for (int i = threadIdx.x; i < nslots; i += 256) {
             const int32_t t = kSmall ? i : keys[i];
@@ -1341,17 +1352,23 @@ __global__ void __launch_bounds__(256) scatter_kernel(const uint32_t* __restrict
             lcnt[i] = 0;
         }
         __syncthreads();
-        for (int r = 0; r < kAggChunk / 256; ++r) {
-            const uint32_t j = base + r * 256 + threadIdx.x;
-            if (j >= m) continue;
-            const uint32_t p = slow_idx[j];
-            const int32_t t = ct[p];
-            const int32_t v = nodes[p];
+        int32_t vr[R], gr[R], cr[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            vr[r] = tr[r] >= 0 ? nodes[pr[r]] : 0;
+            gr[r] = tr[r] >= 0 ? cg[pr[r]] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) cr[r] = tr[r] >= 0 ? (vw ? vw[vr[r]] : 1) : 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (tr[r] < 0) continue;
+            const int32_t t = tr[r];
             const int32_t i = agg_slot<kSmall>(keys, t, false);
             const int32_t at = seg_off[t] + lbase[i] + atomicAdd(&lcnt[i], 1);
-            skey[at] = (static_cast<uint64_t>(static_cast<int64_t>(gmax) - cg[p]) << bits_v) |
-                       static_cast<uint64_t>(static_cast<uint32_t>(v));
-            swt[at] = vw ? vw[v] : 1;
+            skey[at] = (static_cast<uint64_t>(static_cast<int64_t>(gmax) - gr[r]) << bits_v) |
+                       static_cast<uint64_t>(static_cast<uint32_t>(vr[r]));
+            swt[at] = cr[r];
         }
         __syncthreads();
         for (int i = threadIdx.x; i < nslots; i += 256) {
@@ -1629,34 +1646,62 @@ __global__ void __launch_bounds__(256) apply_kernel(const int32_t* __restrict__ 
         for (int j = threadIdx.x; j < nw; j += 256) delta[j] = 0;
         __syncthreads();
     }
-    for (int32_t p = blockIdx.x * 256 + threadIdx.x; p < count; p += gridDim.x * 256) {
-        const int32_t t = ct[p];
-        if (t < 0) continue;
-        if (!kSmall) {
-            tsum[t] = 0;
-            cnt[t] = 0;
+    // U grid-stride positions per thread at a time: their loads are issued
+    // together, level by level, before the updates
+    constexpr int U = 4;
+    const int32_t stride = gridDim.x * 256;
+    for (int32_t p0 = blockIdx.x * 256 + threadIdx.x; p0 < count; p0 += stride * U) {
+        int32_t tq[U], vq[U], aq[U], cq[U];
+        uint8_t oq[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t p = p0 + u * stride;
+            tq[u] = p < count ? ct[p] : -1;
         }
-        uint8_t o = ok[p];
-        const int32_t v = nodes[p];
-        if (o == kOkSlow) {
-            const uint64_t key = (static_cast<uint64_t>(static_cast<int64_t>(gkey) - cg[p]) << bits_v) |
-                                 static_cast<uint64_t>(static_cast<uint32_t>(v));
-            o = key < bnd[t] ? 1 : 0;
-            ok[p] = o;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t p = p0 + u * stride;
+            oq[u] = tq[u] >= 0 ? ok[p] : 0;
+            vq[u] = tq[u] >= 0 ? nodes[p] : 0;
         }
-        if (!o) continue;
-        const int32_t a = label[v];
-        const int32_t c = vw ? vw[v] : 1;
-        label[v] = t;
-        if (label8) label8[v] = static_cast<uint8_t>(t);
-        if (label16) label16[v] = static_cast<uint16_t>(t);
-        if (c) {
-            if (kSmall) {
-                atomicAdd(&delta[t], c);
-                atomicSub(&delta[a], c);
-            } else {
-                atomicAdd(&w[t], c);
-                atomicSub(&w[a], c);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t p = p0 + u * stride;
+            if (oq[u] == kOkSlow) {
+                const uint64_t key = (static_cast<uint64_t>(static_cast<int64_t>(gkey) - cg[p]) << bits_v) |
+                                     static_cast<uint64_t>(static_cast<uint32_t>(vq[u]));
+                oq[u] = key < bnd[tq[u]] ? 1 : 0;
+                ok[p] = oq[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            aq[u] = oq[u] ? label[vq[u]] : 0;
+            cq[u] = oq[u] ? (vw ? vw[vq[u]] : 1) : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t t = tq[u];
+            if (t < 0) continue;
+            if (!kSmall) {
+                tsum[t] = 0;
+                cnt[t] = 0;
+            }
+            if (!oq[u]) continue;
+            const int32_t v = vq[u];
+            const int32_t a = aq[u];
+            const int32_t c = cq[u];
+            label[v] = t;
+            if (label8) label8[v] = static_cast<uint8_t>(t);
+            if (label16) label16[v] = static_cast<uint16_t>(t);
+            if (c) {
+                if (kSmall) {
+                    atomicAdd(&delta[t], c);
+                    atomicSub(&delta[a], c);
+                } else {
+                    atomicAdd(&w[t], c);
+                    atomicSub(&w[a], c);
+                }
             }
         }
     }
