@@ -137,3 +137,29 @@ def test_union_builder():
         assert np.array_equal(a, g["adjncy"])
         assert np.array_equal(u["adjwgt"][u["xadj"][lo]:u["xadj"][hi]],
                               g["adjwgt"] if g.get("adjwgt") is not None else np.ones(len(a), np.int32))
+
+
+@pytest.mark.parametrize("k", [3, 64])
+def test_initial_partition_many_edgeless_nodes(k):
+    # a small connected core among 300 000 edgeless nodes whose weights come
+    # in runs (ones broken by single heavier and zero-weight nodes), so the
+    # leftover nodes are dealt in many runs and the labels are written by
+    # several threads; checked against the oracle
+    sc, _ = _lib()
+    rng = np.random.default_rng(k)
+    n = 300_000
+    core = np.sort(rng.choice(n, 2000, replace=False))
+    edges = set()
+    for i in range(len(core)):
+        for j in rng.integers(0, len(core), 3):
+            if j != i:
+                a, b = int(core[i]), int(core[j])
+                edges.add((min(a, b), max(a, b)))
+    g = synth.from_edges(n, sorted(edges))
+    vw = np.ones(n, dtype=np.int32)
+    vw[rng.choice(n, 3000, replace=False)] = rng.integers(2, 6, 3000)
+    vw[rng.choice(n, 500, replace=False)] = 0
+    vw[core] = rng.integers(1, 9, len(core))
+    g["vwgt"] = vw
+    T = -(-int(vw.sum()) // k)
+    assert np.array_equal(sc.initial_partition(g, k), oracle.initial_partition(g, k, T))
