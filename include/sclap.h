@@ -123,6 +123,9 @@ typedef struct {
                                      phase 2; nodes left in the pool fill the blocks' remaining room
                                      max(0, T - w(b)) in id and block order.  Needs Lmax and c(V)
                                      below 2^30; single-graph entry points only. */
+    int32_t select_launches;      /* tuning (never changes results; 0 = library default): launches of
+                                     the multi-workgroup selection per sub-round, one key digit each;
+                                     keys with more digits finish in the last launch */
 } sclap_options;
 
 #define SCLAP_MAX_LEVELS 64

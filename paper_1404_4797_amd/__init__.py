@@ -68,7 +68,7 @@ class Options(ctypes.Structure):
                 ("hub_region_cap", ctypes.c_int32), ("select_small_max", ctypes.c_int32),
                 ("skip_quiet", ctypes.c_int32), ("vcycles", ctypes.c_int32),
                 ("degree_order", ctypes.c_int32), ("contract_bucket_mean", ctypes.c_int32),
-                ("initial_partitioner", ctypes.c_int32)]
+                ("initial_partitioner", ctypes.c_int32), ("select_launches", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):

@@ -42,6 +42,8 @@ Opts resolve(const sclap_options* o) {
     if (o->hub_part_limit > 0) r.tune.hub_part_limit = o->hub_part_limit;
     if (o->hub_region_cap > 0) r.tune.hub_region_cap = o->hub_region_cap;
     if (o->select_small_max > 0) r.tune.select_small_max = o->select_small_max;
+    if (o->select_launches < 0) fail(SCLAP_ERR_INVALID, "select_launches must be >= 0");
+    r.tune.select_launches = o->select_launches;
     r.tune.skip_quiet = o->skip_quiet < 0 ? -1 : (o->skip_quiet > 0 ? 1 : 0);
     r.vcycles = o->vcycles == 0 ? 1 : o->vcycles;
     r.degree_order = o->degree_order != 0 ? 1 : 0;

@@ -1486,12 +1486,55 @@ __global__ void __launch_bounds__(256) select_kernel(const int32_t* __restrict__
     }
 }
 
-// One digit of the multi-workgroup selection: every block adds its chunk's
-// weight histogram to the segment's histogram in HBM; the last block to
-// finish a segment picks that segment's boundary digit with a block-wide scan
-// (no block waits for another) and, after the last digit, stores the
-// segment's boundary key.
-__global__ void __launch_bounds__(kLargeThreads) large_pass_kernel(LargeSel L, int pass, int bits_v,
+// Boundary digit of a histogram held as kPerT consecutive digits per thread
+// (hv, summing to local): the first digit whose cumulative weight exceeds
+// room (the last digit when none below it does); *s_d and *s_run (the weight
+// of the digits before it) are set for the whole block.
+template <int NT, int kPerT>
+__device__ __forceinline__ void block_pick_digit(const int64_t* hv, int64_t local, int64_t room, int64_t* sc,
+                                                 int* s_d, int64_t* s_run) {
+    const int j = threadIdx.x;
+    sc[j] = local;
+    __syncthreads();
+    for (int o = 1; o < NT; o <<= 1) {  // inclusive scan
+        const int64_t add = j >= o ? sc[j - o] : 0;
+        __syncthreads();
+        sc[j] += add;
+        __syncthreads();
+    }
+    const int64_t incl = sc[j];
+    const int64_t excl = incl - local;
+    if (j == NT - 1) {  // no digit below the last one exceeds the room
+        *s_d = NT * kPerT - 1;
+        *s_run = incl - hv[kPerT - 1];
+    }
+    __syncthreads();
+    // the digit where the admissible weight runs out (monotone: one thread)
+    if (incl > room && excl <= room) {
+        int64_t run = excl;
+        int d = kPerT * j + kPerT - 1;
+        for (int q = 0; q < kPerT - 1; ++q) {
+            if (run + hv[q] > room) {
+                d = kPerT * j + q;
+                break;
+            }
+            run += hv[q];
+        }
+        *s_d = d;
+        *s_run = run;
+    }
+    __syncthreads();
+}
+
+// One digit of the multi-workgroup selection per launch, most significant
+// first: launch j of nlaunch handles digit passes - 1 - j.  Every block adds
+// its chunk's weight histogram to the segment's histogram in HBM; the last
+// block to finish a segment picks that segment's boundary digit (no block
+// waits for another).  Keys rarely need more digits than the host launches;
+// when they do, the last block of each segment in the final launch finishes
+// the remaining digits alone, over the whole segment.  After the last digit
+// the segment's boundary key is stored.
+__global__ void __launch_bounds__(kLargeThreads) large_pass_kernel(LargeSel L, int launch, int nlaunch, int bits_v,
                                                                    const uint64_t* __restrict__ skey,
                                                                    const int32_t* __restrict__ swt,
                                                                    uint64_t* __restrict__ bnd, const Counters* ctr) {
@@ -1504,22 +1547,17 @@ __global__ void __launch_bounds__(kLargeThreads) large_pass_kernel(LargeSel L, i
     __shared__ int64_t s_run;
     const int total_bits = bits_of(static_cast<uint64_t>(static_cast<int64_t>(ctr->gmax) - ctr->gmin)) + bits_v;
     const int passes = total_bits > 0 ? (total_bits + kLDigit - 1) / kLDigit : 1;
+    const int pass = passes - 1 - launch;
     const uint32_t nlarge = ctr->nlarge;
-    if (pass >= passes || nlarge == 0) return;  // uniform over the grid
+    if (pass < 0 || nlarge == 0) return;  // uniform over the grid
+    const bool finish = launch == nlaunch - 1;
     const int shift = kLDigit * pass;
     const uint64_t above = shift + kLDigit >= 64 ? 0ULL : ~0ULL << (shift + kLDigit);  // digits already fixed
     const int32_t nch = static_cast<int32_t>(ctr->nlchunks);
     const int j = threadIdx.x;
-    for (int32_t c = blockIdx.x; c < nch; c += gridDim.x) {
-        const int32_t l = L.owner[c];
-        const int32_t base = L.base[l];
-        const int32_t len = L.len[l];
-        const int32_t i0 = (c - L.chunk0[l]) * kSegChunk;
-        const int32_t i1 = i0 + kSegChunk < len ? i0 + kSegChunk : len;
-        const uint64_t prefix = L.prefix[l];
-        uint32_t* hl = L.hist + static_cast<size_t>(l) * kLBins;
-        for (int q = j; q < kLBins; q += NT) h[q] = 0;
-        __syncthreads();
+    // adds the weights of entries [i0, i1) of a segment whose key matches
+    // prefix on the digits above `sh` to the LDS histogram of digit `sh`
+    auto accumulate = [&](int32_t base, int32_t i0, int32_t i1, uint64_t prefix, uint64_t ab, int sh) {
         for (int32_t i = i0 + j; i < i1; i += NT * U) {
             uint64_t k[U];
             int32_t wt[U];
@@ -1531,9 +1569,20 @@ __global__ void __launch_bounds__(kLargeThreads) large_pass_kernel(LargeSel L, i
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if ((k[u] & above) == prefix && wt[u])
-                    atomicAdd(&h[(k[u] >> shift) & (kLBins - 1)], static_cast<uint32_t>(wt[u]));
+                if ((k[u] & ab) == prefix && wt[u]) atomicAdd(&h[(k[u] >> sh) & (kLBins - 1)], static_cast<uint32_t>(wt[u]));
         }
+    };
+    for (int32_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        const int32_t l = L.owner[c];
+        const int32_t base = L.base[l];
+        const int32_t len = L.len[l];
+        const int32_t i0 = (c - L.chunk0[l]) * kSegChunk;
+        const int32_t i1 = i0 + kSegChunk < len ? i0 + kSegChunk : len;
+        const uint64_t prefix = L.prefix[l];
+        uint32_t* hl = L.hist + static_cast<size_t>(l) * kLBins;
+        for (int q = j; q < kLBins; q += NT) h[q] = 0;
+        __syncthreads();
+        accumulate(base, i0, i1, prefix, above, shift);
         __syncthreads();
         for (int q = j; q < kLBins; q += NT)
             if (h[q]) atomicAdd(&hl[q], h[q]);
@@ -1559,45 +1608,36 @@ __global__ void __launch_bounds__(kLargeThreads) large_pass_kernel(LargeSel L, i
                 hv[q] = __hip_atomic_load(&hl[kPerT * j + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 local += hv[q];
             }
-            sc[j] = local;
-            __syncthreads();
-            for (int o = 1; o < NT; o <<= 1) {  // inclusive scan
-                const int64_t add = j >= o ? sc[j - o] : 0;
-                __syncthreads();
-                sc[j] += add;
-                __syncthreads();
-            }
-            const int64_t room = L.room[l];
-            const int64_t incl = sc[j];
-            const int64_t excl = incl - local;
-            if (j == NT - 1) {  // no digit below the last one exceeds the room
-                s_d = kLBins - 1;
-                s_run = incl - hv[kPerT - 1];
-            }
-            __syncthreads();
-            // the digit where the admissible weight runs out (monotone: one thread)
-            if (incl > room && excl <= room) {
-                int64_t run = excl;
-                int d = kPerT * j + kPerT - 1;
-                for (int q = 0; q < kPerT - 1; ++q) {
-                    if (run + hv[q] > room) {
-                        d = kPerT * j + q;
-                        break;
-                    }
-                    run += hv[q];
-                }
-                s_d = d;
-                s_run = run;
-            }
+            int64_t room = L.room[l];
+            block_pick_digit<NT, kPerT>(hv, local, room, sc, &s_d, &s_run);
 #pragma unroll
             for (int q = 0; q < kPerT; ++q) hl[kPerT * j + q] = 0;
-            __syncthreads();
+            uint64_t np = prefix | (static_cast<uint64_t>(s_d) << shift);
+            room -= s_run;
+            if (finish) {
+                for (int q2 = pass - 1; q2 >= 0; --q2) {  // remaining digits, this block alone
+                    const int sh = kLDigit * q2;
+                    __syncthreads();
+                    for (int q = j; q < kLBins; q += NT) h[q] = 0;
+                    __syncthreads();
+                    accumulate(base, 0, len, np, ~0ULL << (sh + kLDigit), sh);
+                    __syncthreads();
+                    local = 0;
+#pragma unroll
+                    for (int q = 0; q < kPerT; ++q) {
+                        hv[q] = h[kPerT * j + q];
+                        local += hv[q];
+                    }
+                    block_pick_digit<NT, kPerT>(hv, local, room, sc, &s_d, &s_run);
+                    np |= static_cast<uint64_t>(s_d) << sh;
+                    room -= s_run;
+                }
+            }
             if (j == 0) {
-                const uint64_t np = prefix | (static_cast<uint64_t>(s_d) << shift);
-                L.room[l] = room - s_run;
+                L.room[l] = room;
                 L.prefix[l] = np;
                 L.done[l] = 0;
-                if (pass == 0) bnd[L.target[l]] = np;  // smallest key that does not fit
+                if (pass == 0 || finish) bnd[L.target[l]] = np;  // smallest key that does not fit
             }
         }
         __syncthreads();
@@ -2166,7 +2206,13 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 lroom.get(),
                 ldone.get()};
     // digits of the selection key: node id bits plus at most 32 bits of gain range
-    const int max_sel_passes = (bits_for(static_cast<uint64_t>(n - 1)) + 32 + kLDigit - 1) / kLDigit;
+    // launches of the multi-workgroup selection: enough digits for node ids
+    // plus a 12-bit gain range; wider keys finish in the last launch
+    const int max_launches = (bits_for(static_cast<uint64_t>(n - 1)) + 32 + kLDigit - 1) / kLDigit;
+    const int sel_launches =
+        tune.select_launches > 0
+            ? std::min(tune.select_launches, max_launches)
+            : std::min(max_launches, (bits_for(static_cast<uint64_t>(n - 1)) + 12 + kLDigit - 1) / kLDigit);
     // boundary key of every target that cannot take all its candidates
     DBuf<uint64_t> bnd(nw, s);
     fill_i32(tsum.get(), 0, nw, s);
@@ -2441,9 +2487,9 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 // a target has at most ccount candidates: no large segment
                 // unless the colour has more than the single-workgroup limit
                 if (ccount > small_max) {
-                    for (int pass = max_sel_passes - 1; pass >= 0; --pass) {
-                        large_pass_kernel<<<kLargeBlocks, kLargeThreads, 0, s>>>(LS, pass, bits_v, skey.get(),
-                                                                                 swt.get(), bnd.get(), ctr.get());
+                    for (int launch = 0; launch < sel_launches; ++launch) {
+                        large_pass_kernel<<<kLargeBlocks, kLargeThreads, 0, s>>>(
+                            LS, launch, sel_launches, bits_v, skey.get(), swt.get(), bnd.get(), ctr.get());
                         LAUNCHCHK();
                     }
                 }

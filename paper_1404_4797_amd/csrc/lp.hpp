@@ -26,6 +26,7 @@ struct LPTuning {
     int32_t hub_part_limit = 4096;  // <= 4096; larger hub partitions use the HBM table
     int32_t hub_region_cap = 0;     // 0: about twice a partition's expected share
     int32_t select_small_max = 4096;  // larger overflow segments: multi-workgroup selection
+    int32_t select_launches = 0;      // multi-workgroup selection launches per sub-round (0: default)
     int32_t skip_quiet = 0;           // 1: skip nodes whose decision cannot have changed; -1: never; 0: caller's choice
 };
 

@@ -67,6 +67,8 @@ KNOBS = [dict(), dict(lane_max_degree=2, wave_max_degree=8, block_max_degree=24)
          dict(lane_max_degree=2, wave_max_degree=8, block_max_degree=24, hub_part_limit=1),
          dict(lane_max_degree=2, wave_max_degree=8, block_max_degree=40, hub_region_cap=3),
          dict(block_max_degree=60, hub_part_limit=5, hub_region_cap=2, select_small_max=1),
+         # one selection launch: the remaining key digits finish inside it
+         dict(select_small_max=1, select_launches=1),
          # quiet nodes skipped once few nodes move
          dict(skip_quiet=1)]
 
@@ -125,7 +127,8 @@ def test_cluster_parity(sc, gname, knobs):
 
 REFINE_KNOBS = [dict(block_max_degree=40), dict(block_max_degree=30, hub_part_limit=1, hub_region_cap=2),
                 # every overflowing target through the multi-workgroup selection
-                dict(select_small_max=1), dict(select_small_max=7), dict(skip_quiet=1)]
+                dict(select_small_max=1), dict(select_small_max=7), dict(skip_quiet=1),
+                dict(select_small_max=1, select_launches=1), dict(select_small_max=3, select_launches=2)]
 
 
 @pytest.mark.parametrize("gname", list(GRAPHS))
