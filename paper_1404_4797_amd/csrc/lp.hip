@@ -549,8 +549,8 @@ struct HubArgs {
 
 constexpr int kHubThreads = 1024;
 constexpr int kPartThreads = 256;
-constexpr int kPartTable = 8192;  // 64 KB LDS table of a partition workgroup
-constexpr int kMaxPartLog = 10;   // at most 1024 partitions per hub
+constexpr int kPartTable = 4096;  // 32 KB LDS table of a partition workgroup (four per CU)
+constexpr int kMaxPartLog = 11;   // at most 2048 partitions per hub
 
 __device__ __forceinline__ uint32_t part_of(int32_t x, int32_t plog) {
     return plog == 0 ? 0u : (slot_hash(static_cast<uint32_t>(x)) >> (32 - plog));
@@ -2108,9 +2108,10 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
         int64_t rtot = 0, otot = 0, ttot = 0;
         int32_t np = 0, ntc = 0;
         for (int32_t h = 0; h < H; ++h) {
-            // about 2048 entries per label partition, at most 1024 partitions
+            // at most 1024 entries per label partition on average (half the
+            // LDS table's limit), at most 2048 partitions
             int32_t lg = 0;
-            while (lg < kMaxPartLog && (static_cast<int64_t>(2048) << lg) < hd[h]) ++lg;
+            while (lg < kMaxPartLog && (static_cast<int64_t>(1024) << lg) < hd[h]) ++lg;
             plog[h] = lg;
             const int64_t per = (hd[h] + (1LL << lg) - 1) >> lg;
             cap[h] = static_cast<int32_t>(std::min<int64_t>(2 * per + 64, hd[h]));
