@@ -53,7 +53,8 @@ constexpr int kBlockTable = 16384;
 constexpr int kBlockMaxDeg = kBlockTable / 2;
 constexpr int kBlock1Max = 1024;  // 256 threads, 16 KB table
 constexpr int kBlock2Max = 4096;  // 512 threads, 64 KB table
-constexpr int kHubChunk = kBlockMaxDeg;  // slots per hub workgroup (table load <= 1/2)
+constexpr int kHubTable = 8192;          // LDS table of a hub chunk workgroup (64 KB: two per CU)
+constexpr int kHubChunk = kHubTable / 2; // slots per hub workgroup (table load <= 1/2)
 constexpr int kHubTChunk = 4096;         // HBM table entries per scan workgroup
 constexpr int kSmallLabels = 4096;       // LDS-private histograms up to this many labels
 constexpr int kMaxBlocks = 1024;         // grid cap of the grid-stride candidate kernels
@@ -559,18 +560,18 @@ __device__ __forceinline__ uint32_t part_of(int32_t x, int32_t plog) {
 // Sums one chunk of a hub row in an LDS table, then scatters the chunk's
 // distinct (label, weight) entries into the hub's label partitions.
 __global__ void __launch_bounds__(kHubThreads) hub_chunk_kernel(EvalArgs A, HubArgs H) {
-    __shared__ int32_t keys[kBlockTable];
-    __shared__ int32_t vals[kBlockTable];
+    __shared__ int32_t keys[kHubTable];
+    __shared__ int32_t vals[kHubTable];
     __shared__ uint32_t pcount[1 << kMaxPartLog];
     __shared__ int32_t pbase[1 << kMaxPartLog];
-    constexpr int kPer = kBlockTable / kHubThreads;
+    constexpr int kPer = kHubTable / kHubThreads;
     const int tid = threadIdx.x;
     const int32_t h = H.chunk_hub[blockIdx.x];
     const int32_t v = H.hub_nodes[h];
     const int64_t begin = H.chunk_begin[blockIdx.x];
     const int64_t row_end = A.xadj[v + 1];
     const int64_t end = begin + kHubChunk < row_end ? begin + kHubChunk : row_end;
-    const uint32_t tsz = table_size_for(static_cast<int32_t>(end - begin), 1024, kBlockTable);
+    const uint32_t tsz = table_size_for(static_cast<int32_t>(end - begin), 1024, kHubTable);
     const uint32_t mask = tsz - 1;
     const int32_t plog = H.hub_plog[h];
     const int32_t P = 1 << plog;
