@@ -55,6 +55,7 @@ constexpr int kBlock1Max = 1024;  // 256 threads, 16 KB table
 constexpr int kBlock2Max = 4096;  // 512 threads, 64 KB table
 constexpr int kHubTable = 8192;          // LDS table of a hub chunk workgroup (64 KB: two per CU)
 constexpr int kHubChunk = kHubTable / 2; // slots per hub workgroup (table load <= 1/2)
+constexpr int kHubDenseChunk = 8192;     // slots per hub workgroup with dense block arrays
 constexpr int kHubTChunk = 4096;         // HBM table entries per scan workgroup
 constexpr int kSmallLabels = 4096;       // LDS-private histograms up to this many labels
 constexpr int kMaxBlocks = 1024;         // grid cap of the grid-stride candidate kernels
@@ -952,7 +953,7 @@ __global__ void __launch_bounds__(kHubThreads) hub_dense_chunk_kernel(EvalArgs A
     const Ctx kx = ctx_of(A, v);
     const int64_t begin = H.chunk_begin[blockIdx.x];
     const int64_t row_end = A.xadj[v + 1];
-    const int64_t end = begin + kHubChunk < row_end ? begin + kHubChunk : row_end;
+    const int64_t end = begin + kHubDenseChunk < row_end ? begin + kHubDenseChunk : row_end;
     for (int32_t j = tid; j < A.dense_k; j += kHubThreads) conn[j] = 0;
     __syncthreads();
     dense_slots<kHubThreads>(A, kx, begin, static_cast<int32_t>(end - begin), conn, tid);
@@ -2083,6 +2084,10 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     // --- hub plans per colour
     std::vector<HubPlan> plans(nsub);
     int64_t max_region = 0, max_over = 0, max_table = 0, max_win = 0, max_hub_ints = 0;
+    // refinement labels fit dense arrays when there are few enough blocks
+    // (the same test sets EvalArgs::dense_k below); hub chunks are then longer
+    const int32_t dense_labels = phase != kCluster ? (mg ? mg->max_labels : nw) : 0;
+    const int64_t hub_chunk = dense_labels > 0 && dense_labels <= kDenseMax ? kHubDenseChunk : kHubChunk;
     for (int32_t sc = 0; sc < nsub; ++sc) {
         const int32_t cat = sc * kNB + kHubBucket;
         const int32_t H = static_cast<int32_t>(cnt[cat]);
@@ -2128,7 +2133,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
             while (tsz < 2 * static_cast<uint64_t>(hd[h])) tsz <<= 1;
             toff[h] = ttot;
             tmask[h] = static_cast<uint32_t>(tsz - 1);
-            for (int64_t sl = 0; sl < hd[h]; sl += kHubChunk) {
+            for (int64_t sl = 0; sl < hd[h]; sl += hub_chunk) {
                 chub.push_back(h);
                 cbeg.push_back(xs[h] + sl);
             }
@@ -2237,7 +2242,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     A.g_lbase = mg ? mg->lbase : nullptr;
     const Bounds BB{bound, mg ? mg->lgid : nullptr, mg ? mg->bound : nullptr};
     // refinement labels are blocks: dense connection arrays when few enough
-    const int32_t dense_k = phase != kCluster ? (mg ? mg->max_labels : nw) : 0;
+    const int32_t dense_k = dense_labels;
     A.dense_k = dense_k > 0 && dense_k <= kDenseMax ? dense_k : 0;
     const bool dense = A.dense_k > 0;
     DBuf<int32_t> hub_sum;
