@@ -176,4 +176,36 @@ inline unsigned grid_for(int64_t items, int per_block) {
     return static_cast<unsigned>(g < 1 ? 1 : g);
 }
 
+// Block-wide append for 256-thread workgroups with one atomic per workgroup:
+// c items per thread; returns the position of this thread's first item in
+// *counter's sequence (the thread's items are consecutive, the order across
+// workgroups unspecified).
+__device__ __forceinline__ uint32_t block_append_count(uint32_t c, uint32_t* counter) {
+    __shared__ uint32_t s_cnt[4];
+    __shared__ uint32_t s_base;
+    const int wid = threadIdx.x >> 6;
+    const int lane = lane_id();
+    uint32_t incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) s_cnt[wid] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < 4; ++w) {
+            const uint32_t t = s_cnt[w];
+            s_cnt[w] = run;
+            run += t;
+        }
+        s_base = run ? atomicAdd(counter, run) : 0;
+    }
+    __syncthreads();
+    const uint32_t idx = s_base + s_cnt[wid] + incl - c;
+    __syncthreads();
+    return idx;
+}
+
 }  // namespace sclap

@@ -161,21 +161,41 @@ __global__ void __launch_bounds__(kTileThreads) row_scatter_kernel(const int64_t
 
 // Rows by length: 0 or 1 entries are final as they are; the others go to the
 // wave, workgroup or long-row lists.
-__global__ void row_classify_kernel(int32_t nc, const int32_t* __restrict__ rowcnt, int32_t* __restrict__ dcnt,
-                                    int32_t* __restrict__ lists, int32_t cap, uint32_t* __restrict__ counts) {
-    const int32_t r = blockIdx.x * 256 + threadIdx.x;
-    const int32_t len = r < nc ? rowcnt[r] : 0;
-    if (r < nc && len <= 1) dcnt[r] = len;
-    const int cls = r >= nc || len <= 1 ? -1 : (len <= kWaveRow ? 0 : (len <= kBlockRow ? 1 : 2));
-    const uint64_t below = lanemask_lt();
-    for (int c = 0; c < 3; ++c) {
-        const uint64_t m = __ballot(cls == c);
-        if (!m) continue;
-        const int leader = __ffsll(static_cast<long long>(m)) - 1;
-        uint32_t base = 0;
-        if (lane_id() == leader) base = atomicAdd(&counts[c], static_cast<uint32_t>(__popcll(m)));
-        base = __shfl(base, leader, 64);
-        if (cls == c) lists[static_cast<int64_t>(c) * cap + base + __popcll(m & below)] = r;
+// (each workgroup takes kClassifyIters * 256 consecutive rows at a time and
+// appends to each list with one atomic: the three counters are few and hot)
+constexpr int kClassifyIters = 16;
+
+__global__ void __launch_bounds__(256) row_classify_kernel(int32_t nc, const int32_t* __restrict__ rowcnt,
+                                                           int32_t* __restrict__ dcnt, int32_t* __restrict__ lists,
+                                                           int32_t cap, uint32_t* __restrict__ counts) {
+    for (int32_t base = blockIdx.x * (kClassifyIters * 256); base < nc; base += gridDim.x * (kClassifyIters * 256)) {
+        uint32_t m[3] = {0, 0, 0};
+        int32_t lens[kClassifyIters];
+#pragma unroll
+        for (int it = 0; it < kClassifyIters; ++it) {
+            const int32_t r = base + it * 256 + static_cast<int32_t>(threadIdx.x);
+            lens[it] = r < nc ? rowcnt[r] : -1;
+        }
+#pragma unroll
+        for (int it = 0; it < kClassifyIters; ++it) {
+            const int32_t r = base + it * 256 + static_cast<int32_t>(threadIdx.x);
+            const int32_t len = lens[it];
+            if (len < 0) continue;
+            if (len <= 1) {
+                dcnt[r] = len;
+                continue;
+            }
+            m[len <= kWaveRow ? 0 : (len <= kBlockRow ? 1 : 2)] |= 1u << it;
+        }
+        for (int c = 0; c < 3; ++c) {
+            uint32_t bits = m[c];
+            uint32_t j = block_append_count(static_cast<uint32_t>(__popc(bits)), &counts[c]);
+            while (bits) {
+                const int it = __ffs(bits) - 1;
+                bits &= bits - 1;
+                lists[static_cast<int64_t>(c) * cap + j++] = base + it * 256 + static_cast<int32_t>(threadIdx.x);
+            }
+        }
     }
 }
 
@@ -934,8 +954,8 @@ void merge_rows(int32_t nc, int64_t m, const int64_t* rowoff, const int32_t* row
     {
         ProfScope ps("contract_rows", 16.0 * static_cast<double>(m), s);
         fill_u32(counts.get(), 0, 3, s);
-        row_classify_kernel<<<grid_for(nc, 256), 256, 0, s>>>(nc, rowcnt, dcnt, lists.get(), nc,
-                                                               counts.get());
+        row_classify_kernel<<<std::min(grid_for(nc, 256 * kClassifyIters), 1024u), 256, 0, s>>>(
+            nc, rowcnt, dcnt, lists.get(), nc, counts.get());
         LAUNCHCHK();
         HIPCHK(hipMemcpyAsync(hc, counts.get(), sizeof(hc), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));

@@ -1023,35 +1023,6 @@ __device__ __forceinline__ uint32_t block_append(bool flag, uint32_t* counter) {
     return idx;
 }
 
-// Same for c items per thread (256 threads): returns the position of this
-// thread's first item; the thread's items are consecutive.
-__device__ __forceinline__ uint32_t block_append_count(uint32_t c, uint32_t* counter) {
-    __shared__ uint32_t s_cnt[4];
-    __shared__ uint32_t s_base;
-    const int wid = threadIdx.x >> 6;
-    const int lane = lane_id();
-    uint32_t incl = c;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t u = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += u;
-    }
-    if (lane == 63) s_cnt[wid] = incl;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int w = 0; w < 4; ++w) {
-            const uint32_t t = s_cnt[w];
-            s_cnt[w] = run;
-            run += t;
-        }
-        s_base = run ? atomicAdd(counter, run) : 0;
-    }
-    __syncthreads();
-    const uint32_t idx = s_base + s_cnt[wid] + incl - c;
-    __syncthreads();
-    return idx;
-}
 
 __device__ __forceinline__ int32_t block_sum_i32(int32_t v) {
     __shared__ int32_t s[4];
@@ -1810,8 +1781,9 @@ __global__ void __launch_bounds__(256) classify_kernel(int32_t n, const int64_t*
         shist[j] = 0;
     }
     __syncthreads();
-    const int32_t v = blockIdx.x * 256 + threadIdx.x;
-    if (v < n) {
+    // grid-stride: few workgroups, so the per-category totals cost few global
+    // atomics on their handful of addresses
+    for (int32_t v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) {
         const int64_t d = xadj[v + 1] - xadj[v];
         uint64_t hcv = hc;
         int32_t lv = v;  // graph-local id
@@ -2056,7 +2028,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     }
     {
         ProfScope ps("lp_schedule", 0, s);
-        classify_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, g.xadj, color_override, hc, mg ? mg->gid : nullptr,
+        classify_kernel<<<capped_grid(n), 256, 0, s>>>(n, g.xadj, color_override, hc, mg ? mg->gid : nullptr,
                                                          g_hc.get(), mg ? mg->nbase : nullptr,
                                                          mg ? mg->active : nullptr, nsub, th,
                                                          ckeys.get(), order.get(), cat_count.get(), cat_slots.get(),
