@@ -58,7 +58,7 @@ constexpr int kHubChunk = kHubTable / 2; // slots per hub workgroup (table load 
 constexpr int kHubDenseChunk = 8192;     // slots per hub workgroup with dense block arrays
 constexpr int kHubTChunk = 4096;         // HBM table entries per scan workgroup
 constexpr int kSmallLabels = 4096;       // LDS-private histograms up to this many labels
-constexpr int kMaxBlocks = 1024;         // grid cap of the grid-stride candidate kernels
+constexpr int kMaxBlocks = 512;          // grid cap of the grid-stride candidate kernels
 constexpr int kSmallSeg = 4096;          // segments up to this length: one selecting workgroup
 constexpr int kSegChunk = 16384;         // entries per workgroup in the multi-workgroup selection
 constexpr int kLargeBlocks = 256;        // grid of the multi-workgroup selection kernel
