@@ -2416,7 +2416,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 } else if (bk == 5) {
                     eval_block_kernel<256, 2 * kBlock1Max><<<nb, 256, 0, bs>>>(A);
                 } else if (bk == 6) {
-                    eval_block_kernel<512, 2 * kBlock2Max><<<nb, 512, 0, bs>>>(A);
+                    eval_block_kernel<1024, 2 * kBlock2Max><<<nb, 1024, 0, bs>>>(A);
                 } else {
                     eval_block_kernel<1024, kBlockTable><<<nb, 1024, 0, bs>>>(A);
                 }
