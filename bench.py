@@ -286,7 +286,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build partitions on one GPU; --gpus %d is not supported "
-              "(multi-GPU sharding is described in DESIGN.md, not built)" % args.gpus, file=sys.stderr)
+              "(sharding over several GPUs is not built)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
