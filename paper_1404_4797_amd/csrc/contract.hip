@@ -530,28 +530,39 @@ __global__ void __launch_bounds__(256) block_hash_rows_kernel(const int32_t* __r
 }
 
 // Splits the workgroup-row list by length: class c holds rows of at most
-// 256 << c entries (c = 0..4).
-__global__ void block_row_split_kernel(const int32_t* __restrict__ list, uint32_t count,
-                                       const int32_t* __restrict__ rowcnt, int32_t* __restrict__ out, uint32_t cap,
-                                       uint32_t* __restrict__ counts) {
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    int cls = -1;
-    int32_t r = 0;
-    if (i < count) {
-        r = list[i];
-        const int32_t len = rowcnt[r];
-        cls = 0;
-        while (cls < 4 && len > (256 << cls)) ++cls;
-    }
-    const uint64_t below = lanemask_lt();
-    for (int c = 0; c < 5; ++c) {
-        const uint64_t m = __ballot(cls == c);
-        if (!m) continue;
-        const int leader = __ffsll(static_cast<long long>(m)) - 1;
-        uint32_t base = 0;
-        if (lane_id() == leader) base = atomicAdd(&counts[c], static_cast<uint32_t>(__popcll(m)));
-        base = __shfl(base, leader, 64);
-        if (cls == c) out[static_cast<int64_t>(c) * cap + base + __popcll(m & below)] = r;
+// 256 << c entries (c = 0..4).  Each workgroup takes kClassifyIters * 256
+// list entries at a time and appends to each class with one atomic.
+__global__ void __launch_bounds__(256) block_row_split_kernel(const int32_t* __restrict__ list, uint32_t count,
+                                                              const int32_t* __restrict__ rowcnt,
+                                                              int32_t* __restrict__ out, uint32_t cap,
+                                                              uint32_t* __restrict__ counts) {
+    for (uint32_t base = blockIdx.x * (kClassifyIters * 256); base < count;
+         base += gridDim.x * (kClassifyIters * 256)) {
+        int32_t rows[kClassifyIters], lens[kClassifyIters];
+#pragma unroll
+        for (int it = 0; it < kClassifyIters; ++it) {
+            const uint32_t i = base + it * 256 + threadIdx.x;
+            rows[it] = i < count ? list[i] : -1;
+        }
+#pragma unroll
+        for (int it = 0; it < kClassifyIters; ++it) lens[it] = rows[it] >= 0 ? rowcnt[rows[it]] : 0;
+        uint32_t m[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+        for (int it = 0; it < kClassifyIters; ++it) {
+            if (rows[it] < 0) continue;
+            int cls = 0;
+            while (cls < 4 && lens[it] > (256 << cls)) ++cls;
+            m[cls] |= 1u << it;
+        }
+        for (int c = 0; c < 5; ++c) {
+            uint32_t bits = m[c];
+            uint32_t j = block_append_count(static_cast<uint32_t>(__popc(bits)), &counts[c]);
+            while (bits) {
+                const int it = __ffs(bits) - 1;
+                bits &= bits - 1;
+                out[static_cast<int64_t>(c) * cap + j++] = rows[it];
+            }
+        }
     }
 }
 
@@ -877,7 +888,8 @@ void hash_block_rows(const int32_t* list, uint32_t count, const int64_t* rowoff,
     DBuf<int32_t> sub(5 * static_cast<size_t>(count), s);
     DBuf<uint32_t> cnt(5, s);
     fill_u32(cnt.get(), 0, 5, s);
-    block_row_split_kernel<<<grid_for(count, 256), 256, 0, s>>>(list, count, rowcnt, sub.get(), count, cnt.get());
+    block_row_split_kernel<<<std::min(grid_for(count, 256 * kClassifyIters), 1024u), 256, 0, s>>>(
+        list, count, rowcnt, sub.get(), count, cnt.get());
     LAUNCHCHK();
     uint32_t hc[5];
     HIPCHK(hipMemcpyAsync(hc, cnt.get(), sizeof(hc), hipMemcpyDeviceToHost, s));
