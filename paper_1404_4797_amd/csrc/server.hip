@@ -48,10 +48,12 @@ struct Request {
 
 using RequestPtr = std::shared_ptr<Request>;
 
-// Device bytes a request may need while its batch runs: the graph (8 B per
-// node for offsets, 4 for weights; 4 + 4 per slot), coarser levels of at most
-// the same size, about 40 B per node of label propagation state and about
-// 44 B per slot of contraction keys, values, sort buffers and run sums.
+// Device bytes a request may need while its batch runs (an upper bound): the
+// graph (8 B per node for offsets, 4 for weights; 4 + 4 per slot), coarser
+// levels of at most the same size, about 48 B per node of label propagation
+// state (labels, weights, results, selection keys, boundary keys) and at most
+// about 28 B per slot of contraction buffers (kept coarse ids, row entries,
+// bucket staging).
 int64_t footprint_of(int64_t n, int64_t S) { return 64 * n + 64 * S + (4LL << 20); }
 
 }  // namespace
