@@ -517,6 +517,26 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
         ++nruns;
         if (c == 0 || k > 4096 || j - i < 4 * static_cast<size_t>(k)) {  // node by node
             nheap += j - i;
+            if (ord_ok && j - i <= 2) {
+                // a node or two (typically one heavier node between runs of
+                // equal weight): with the order repaired (a dealt run leaves
+                // it stale), the lightest block is ord[0]; it moves right
+                // past the blocks that are now lighter, keeping the order
+                order_blocks();
+                for (; i < j; ++i) {
+                    const int32_t b = ord[0];
+                    part[rest[i]] = b;
+                    wb[b] += c;
+                    int32_t q = 0;
+                    while (q + 1 < k && lighter(ord[q + 1], b)) {
+                        ord[q] = ord[q + 1];
+                        ++q;
+                    }
+                    ord[q] = b;
+                }
+                heap_ok = false;
+                continue;
+            }
             if (!heap_ok) {
                 heap.reset(wb);
                 heap_ok = true;
