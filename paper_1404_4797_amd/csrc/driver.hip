@@ -478,7 +478,7 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
     // blocks by (weight, id); kept across runs and repaired by insertion
     // (a run changes the weights of a few blocks only), rebuilt after the
     // node-by-node path
-    std::vector<int32_t> ord(static_cast<size_t>(k));
+    std::vector<int32_t> ord(static_cast<size_t>(k)), ord_next(static_cast<size_t>(k));
     bool ord_ok = false;
     auto lighter = [&](int32_t x, int32_t y) { return wb[x] != wb[y] ? wb[x] < wb[y] : x < y; };
     auto order_blocks = [&]() {
@@ -578,6 +578,33 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
             plan_ord.insert(plan_ord.end(), ord.begin(), ord.begin() + gsz);
             for (int32_t g = 0; g < gsz; ++g)
                 wb[ord[g]] += c * static_cast<int64_t>(take / gsz + (static_cast<size_t>(g) < take % gsz ? 1 : 0));
+            // the order is now three sorted runs (the blocks that took one
+            // node more, the rest of the group, the blocks outside it): one
+            // three-way merge restores it
+            {
+                const int32_t r = static_cast<int32_t>(take % static_cast<size_t>(gsz));
+                int32_t a = 0, b2 = r, c2 = gsz;
+                for (int32_t o = 0; o < k; ++o) {
+                    int32_t w = -1, from = -1;
+                    if (a < r) {
+                        w = ord[a];
+                        from = 0;
+                    }
+                    if (b2 < gsz && (from < 0 || lighter(ord[b2], w))) {
+                        w = ord[b2];
+                        from = 1;
+                    }
+                    if (c2 < k && (from < 0 || lighter(ord[c2], w))) {
+                        w = ord[c2];
+                        from = 2;
+                    }
+                    ord_next[o] = w;
+                    if (from == 0) ++a;
+                    else if (from == 1) ++b2;
+                    else ++c2;
+                }
+                ord.swap(ord_next);
+            }
             i += take;
         }
     }
