@@ -99,7 +99,7 @@ typedef struct {
                                  neighbouring label stronger than their own and saw no neighbour move
                                  since (their decision is unchanged); -1: evaluate every node;
                                  0: on for batches, off for single graphs */
-    int32_t vcycles;          /* multilevel cycles (Section 4.5, iterated V-cycles; 0 counts as 1,
+    int32_t vcycles;          /* multilevel cycles (Section 4.4, iterated V-cycles; 0 counts as 1,
                                  at most 64): every cycle after the first clusters only inside the
                                  blocks of the previous result, so no cut edge is contracted, and
                                  starts refinement from that result on its coarsest graph; cycle c
@@ -187,7 +187,7 @@ int sclap_cluster_dev(const sclap_graph* g, int64_t U, int32_t rounds, uint64_t 
                       const sclap_options* opt, int32_t* labels, int32_t* rounds_run, void* stream);
 
 /*
- * Clustering inside the blocks of a partition (Section 4.5, Iterated
+ * Clustering inside the blocks of a partition (Section 4.4, Iterated
  * Multilevel Schemes): as sclap_cluster, but a node only looks at the
  * neighbours u with block[u] == block[v], so it only joins clusters of its own
  * block and every cluster lies inside one block (contracting it keeps every

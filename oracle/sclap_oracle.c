@@ -162,7 +162,7 @@ static int cmp_lw(const void* x, const void* y) {
  */
 /*
  * With a block array (clustering inside the blocks of an input partition,
- * Section 4.5, Iterated Multilevel Schemes), only neighbours in v's own block
+ * Section 4.4, Miscellanea: Iterated Multilevel Schemes), only neighbours in v's own block
  * are looked at: a cluster then never spans two blocks, so these are exactly
  * the clusters of v's block.
  */
@@ -317,7 +317,7 @@ static int32_t run_rounds(const orc_graph* g, const int32_t* block, int32_t phas
 
 /* Size-constrained clustering: every node starts in its own cluster (label =
  * node id), cluster weights w(x) = c(x) (Section 3.1).  With a block array,
- * a node only joins clusters of its own block (Section 4.5, Iterated
+ * a node only joins clusters of its own block (Section 4.4, Iterated
  * Multilevel Schemes): singletons lie in one block each, and only same-block
  * neighbours are looked at, so every cluster stays inside one block. */
 int32_t orc_cluster_within(const orc_graph* g, const int32_t* block, int64_t U, int32_t rounds, int32_t nsub,
@@ -648,7 +648,7 @@ uint64_t orc_cycle_seed(uint64_t seed, int32_t cycle) {
  * coarsest to the finest project the partition and refine it with SCLaP under
  * Lmax.
  *
- * Iterated V-cycles (Section 4.5, Iterated Multilevel Schemes): every cycle
+ * Iterated V-cycles (Section 4.4, Miscellanea: Iterated Multilevel Schemes): every cycle
  * after the first clusters inside the blocks of the previous cycle's result,
  * so no cut edge is contracted, each coarse node inherits the block of its
  * members, and the inherited partition of the coarsest graph (same cut and

@@ -64,7 +64,7 @@ typedef struct {
 int32_t orc_eval_node(const orc_graph* g, int32_t phase, int32_t level, int32_t round, uint64_t seed,
                       int64_t bound, const int32_t* label, const int64_t* w, int32_t v, orc_eval* out);
 /* The same with block[n] != NULL: only neighbours u with block[u] == block[v]
- * count (clustering inside the blocks of a partition, Section 4.5). */
+ * count (clustering inside the blocks of a partition, Section 4.4). */
 int32_t orc_eval_node_within(const orc_graph* g, const int32_t* block, int32_t phase, int32_t level,
                              int32_t round, uint64_t seed, int64_t bound, const int32_t* label, const int64_t* w,
                              int32_t v, orc_eval* out);
@@ -83,7 +83,7 @@ int32_t orc_cluster(const orc_graph* g, int64_t U, int32_t rounds, int32_t nsub,
                     int32_t level, const int32_t* color_override, int32_t* labels, int32_t* rounds_run,
                     int64_t* visits);
 
-/* Clustering inside the blocks of block[n] (Section 4.5, Iterated Multilevel
+/* Clustering inside the blocks of block[n] (Section 4.4, Iterated Multilevel
  * Schemes); visits counts only the same-block slots looked at. */
 int32_t orc_cluster_within(const orc_graph* g, const int32_t* block, int64_t U, int32_t rounds, int32_t nsub,
                            uint64_t seed, int32_t level, const int32_t* color_override, int32_t* labels,

@@ -1284,7 +1284,7 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
     upload_vec(d_lgid, lgid, s);
     DBuf<int32_t> w(std::max(K, 1), s);
 
-    // Multilevel cycles (Section 4.5): from the second on, part_out holds the
+    // Multilevel cycles (Section 4.4, Iterated Multilevel Schemes): from the second on, part_out holds the
     // previous cycle's partition in the batch's block space; clustering stays
     // inside its blocks and the inherited coarsest partitions replace the
     // initial partitioner, as in multilevel_cycle.

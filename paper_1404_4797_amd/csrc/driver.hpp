@@ -26,7 +26,7 @@ struct Opts {
     LPTuning tune;
 };
 
-// Seed of multilevel cycle c (Section 4.5, iterated V-cycles): the caller's
+// Seed of multilevel cycle c (Section 4.4, Miscellanea: iterated V-cycles): the caller's
 // seed for the first, H(seed, 4, c) for later ones.
 uint64_t cycle_seed(uint64_t seed, int32_t cycle);
 

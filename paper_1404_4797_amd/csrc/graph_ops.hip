@@ -559,7 +559,7 @@ void remap_members(int32_t n, const int32_t* gid, const std::vector<int32_t>& de
 
 // ------------------------------------------------------- inside blocks
 //
-// Clustering inside the blocks of a partition (Section 4.5, iterated
+// Clustering inside the blocks of a partition (Section 4.4, Miscellanea: iterated
 // V-cycles) runs on the subgraph of the slots u->v with blk[u] == blk[v]:
 // every cluster then stays inside one block.  Kept slots keep their order.
 // Pass 1 counts the kept slots of each slot tile, pass 2 scans inside the

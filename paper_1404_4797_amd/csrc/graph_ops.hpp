@@ -85,7 +85,7 @@ void compact_members(const DevGraph& src, const std::vector<int32_t>& onb, const
 void remap_members(int32_t n, const int32_t* gid, const std::vector<int32_t>& delta, int32_t* C, hipStream_t s);
 // part[v] = coarse_part[C[v]] where C[v] >= 0.
 // The subgraph of the slots u->v with blk[u] == blk[v], slot order kept
-// (clustering inside the blocks of a partition, Section 4.5).  out.vw is left
+// (clustering inside the blocks of a partition, Section 4.4, Iterated Multilevel Schemes).  out.vw is left
 // empty: the caller pairs out's view with g.vw.
 void within_blocks(const DevGraph& g, const int32_t* blk, OwnedDevGraph& out, hipStream_t s);
 

@@ -1,5 +1,5 @@
 """GPU parity of clustering inside the blocks of a partition and of iterated
-V-cycles (Section 4.5, Iterated Multilevel Schemes) against the CPU oracle,
+V-cycles (Section 4.4, Iterated Multilevel Schemes) against the CPU oracle,
 bit for bit: labels and round counts of the restricted clustering (every
 degree bucket, rows spanning several slot tiles, empty rows at the ends,
 one block, singleton blocks), full partitions with 2 and 3 cycles (parts,

@@ -221,3 +221,47 @@ def test_handworked_degree_order(golden_dir):
     g = synth.from_edges(ex["n"], [tuple(e) for e in ex["edges"]])
     assert oracle.degree_colors(g, ex["nsub"]).tolist() == ex["expected_colors"]
     assert oracle.degree_colors(g, ex["nsub"], block=ex["block"]).tolist() == ex["expected_colors_within_blocks"]
+
+
+def _rows_graph(n, rows, vwgt):
+    """CSR with rows exactly as given (unsorted rows allowed), unit edge weights."""
+    xadj = np.zeros(n + 1, dtype=np.int64)
+    adj = []
+    for v in range(n):
+        adj += rows[v]
+        xadj[v + 1] = len(adj)
+    return {"n": n, "xadj": xadj, "adjncy": np.array(adj, dtype=np.int32),
+            "adjwgt": np.ones(len(adj), dtype=np.int32), "vwgt": np.array(vwgt, dtype=np.int32)}
+
+
+def test_handworked_initial_partition_growth(golden_dir):
+    ex = _load(golden_dir, "handworked.json")["I_initial_partition_growth"]
+    g = _rows_graph(ex["n"], ex["rows"], ex["vwgt"])
+    assert oracle.validate(g) == 0
+    assert -(-int(g["vwgt"].sum()) // ex["k"]) == ex["T"]
+    assert oracle.initial_partition(g, ex["k"], ex["T"]).tolist() == ex["expected_part"]
+
+
+def test_handworked_initial_lp_pool_rule(golden_dir):
+    ex = _load(golden_dir, "handworked.json")["J_initial_lp_pool_rule"]
+    g = synth.from_edges(ex["n"], [tuple(e) for e in ex["edges"]], ex["weights"], vwgt=ex["vwgt"])
+    for v, hx in ex["seed_hashes_hex"].items():
+        assert _h([ex["seed"], 5, ex["level"], int(v)]) == int(hx, 16)
+    assert oracle.lmax(int(g["vwgt"].sum()), ex["k"], 0.0) == ex["Lmax"]
+    part, rr, visits = oracle.initial_partition_lp(g, ex["k"], ex["T"], ex["Lmax"], seed=ex["seed"],
+                                                   level=ex["level"], rounds=ex["rounds"], nsub=ex["nsub"])
+    assert part.tolist() == ex["expected_part"]
+    assert rr == ex["expected_rounds_run"] and visits == ex["expected_visits"]
+    # with no round at all every pool node is dealt: the partition the rule avoids
+    p0, rr0, _ = oracle.initial_partition_lp(g, ex["k"], ex["T"], ex["Lmax"], seed=ex["seed"], level=ex["level"],
+                                             rounds=0, nsub=ex["nsub"])
+    assert p0.tolist() == ex["expected_part_without_pool_offset"] and rr0 == 0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 7, 12345678901234567, M64])
+def test_cycle_seed_independent_chain(seed):
+    # V-cycle c >= 1 draws fresh colours and ties from the seed H(seed, 4, c);
+    # the first cycle keeps the caller's seed
+    assert oracle.cycle_seed(seed, 0) == seed
+    for c in (1, 2, 3, 63):
+        assert oracle.cycle_seed(seed, c) == _h([seed, 4, c])

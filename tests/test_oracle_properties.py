@@ -22,7 +22,7 @@ the oracle's own arithmetic:
   bound for the multilevel result, which must be balanced;
 * storage-order independence: permuting the neighbours inside rows changes
   nothing;
-* clustering inside the blocks of a partition (Section 4.5, iterated
+* clustering inside the blocks of a partition (Section 4.4, iterated
   V-cycles): every cluster lies in one block, contracting keeps the cut and
   the block weights, one block reduces to plain clustering and singleton
   blocks to the identity; a later V-cycle equals its composition from the
@@ -47,6 +47,25 @@ def rows(g):
         b, e = int(xa[v]), int(xa[v + 1])
         out.append([(int(adj[i]), 1 if ew is None else int(ew[i])) for i in range(b, e)])
     return out
+
+
+M64 = (1 << 64) - 1
+
+
+def sm_mix(z):
+    """SplitMix64's published output function applied to z + golden gamma,
+    written out here independently of the oracle."""
+    z = (z + 0x9E3779B97F4A7C15) & M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+    return z ^ (z >> 31)
+
+
+def sm_hash(*w):
+    h = sm_mix(w[0])
+    for x in w[1:]:
+        h = sm_mix(h ^ x)
+    return h
 
 
 def vw(g):
@@ -427,7 +446,7 @@ def test_stall_rule_on_mostly_isolated_graph(seed):
 
 
 # ------------------------------------------ clustering inside blocks, V-cycles
-# (Section 4.5, Iterated Multilevel Schemes)
+# (Section 4.4, Iterated Multilevel Schemes)
 
 def ceil_div(a, b):
     return -(-a // b)
@@ -499,8 +518,9 @@ def test_one_vcycle_is_the_plain_multilevel_run():
 
 
 def py_vcycle(g, k, eps, seed, prev, cycle, coarsest):
-    """One later V-cycle composed from the oracle's single operations."""
-    sd = oracle.cycle_seed(seed, cycle)
+    """One later V-cycle composed from the oracle's single operations; the
+    cycle's seed H(seed, 4, cycle) comes from the independent hash chain."""
+    sd = sm_hash(seed, 4, cycle)
     cV = int(vw(g).sum())
     Lmax = oracle.lmax(cV, k, eps)
     W = cV // (18 * k)
