@@ -52,7 +52,10 @@ def make_graph(w):
 
 def cpu_baseline(g, w):
     """The oracle, as it stands, on a bounded sample: the first sub-round
-    (colour 0 of 4) of the first clustering round on the full level-0 graph."""
+    (colour 0 of 4) of the first clustering round on the full level-0 graph,
+    single thread; then the whole first clustering round (4 sub-rounds) with
+    the oracle's node evaluation on all host cores (OpenMP; admission and
+    apply sequential, so the labels equal the single-threaded oracle's)."""
     import numpy as np
     import oracle
     n = g["n"]
@@ -62,9 +65,24 @@ def cpu_baseline(g, w):
     t = time.perf_counter()
     moves, visits, ncand = oracle.subround(g, oracle.CLUSTER, 0, 0, 0, 4, w["seed"], U, label, wt)
     dt = time.perf_counter() - t
-    return {"value": visits / dt, "unit": "edge-visits/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle sub-round 0 of 4 of clustering round 0 on the full level-0 graph "
-                      "(%d edge visits, %.1f s, single thread)" % (visits, dt)}
+    one = {"value": visits / dt, "unit": "edge-visits/s", "cores": 1, "kind": "oracle",
+           "sample": "oracle sub-round 0 of 4 of clustering round 0 on the full level-0 graph "
+                     "(%d edge visits, %.1f s, single thread)" % (visits, dt)}
+    threads = oracle.max_threads()
+    plabel = np.arange(n, dtype=np.int32)
+    pwt = g["vwgt"].astype(np.int64)
+    t = time.perf_counter()
+    pvisits = 0
+    for sub in range(4):
+        _, v = oracle.subround_par(g, oracle.CLUSTER, 0, 0, sub, 4, w["seed"], U, plabel, pwt, threads=threads)
+        pvisits += v
+        if sub == 0:
+            assert np.array_equal(plabel, label), "parallel oracle sub-round differs"
+    pdt = time.perf_counter() - t
+    allc = {"value": pvisits / pdt, "unit": "edge-visits/s", "cores": threads, "kind": "oracle",
+            "sample": "oracle clustering round 0 (4 sub-rounds) on the full level-0 graph with the node evaluation "
+                      "on %d OpenMP threads (%d edge visits, %.1f s)" % (threads, pvisits, pdt)}
+    return one, allc
 
 
 def recorded_traffic(kernel, workload):
@@ -116,12 +134,14 @@ def batch_comparison(ngraphs, seed, log_lo, log_hi, extra=None):
     torch.cuda.synchronize()
     t_default = time.perf_counter() - t0
     ref_part = part.clone()
-    # degree-bucket thresholds tuned on one clustering round of the union
+    # tuning options (degree thresholds, so LDS table sizes per degree range,
+    # and graph capture) searched on the union by the library's autotuner
     t0 = time.perf_counter()
     o = sc.autotune_dev(du, int(np.median(ks)), stream=stream, **extra)
     torch.cuda.synchronize()
     t_tune = time.perf_counter() - t0
-    tuned = [o.lane_max_degree, o.wave_max_degree, o.block_max_degree]
+    tuned = {"lane_max_degree": o.lane_max_degree, "wave_max_degree": o.wave_max_degree,
+             "block_max_degree": o.block_max_degree, "graph_capture": o.graph_capture}
     r = sc.partition_batch_dev(du, nb, ks, eps, seeds, part=part, stream=stream, opts=o)  # warmup
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -147,8 +167,9 @@ def batch_comparison(ngraphs, seed, log_lo, log_hi, extra=None):
             same = False
     log("plain: %.1f ms for %d graphs, identical=%s" % (t_plain * 1e3, ngraphs, same))
     return {"graphs": ngraphs, "n_log2_range": [log_lo, log_hi], "n": u["n"], "S": int(u["xadj"][-1]),
-            "batched_ms": round(t_batch * 1e3, 3), "batched_default_thresholds_ms": round(t_default * 1e3, 3),
-            "tuned_thresholds": tuned, "tuning_ms": round(t_tune * 1e3, 3), "plain_ms": round(t_plain * 1e3, 3),
+            "batched_ms": round(t_batch * 1e3, 3), "batched_default_options_ms": round(t_default * 1e3, 3),
+            "tuned_options": tuned, "tuned_vs_default": round(t_default / t_batch, 4),
+            "tuning_ms": round(t_tune * 1e3, 3), "plain_ms": round(t_plain * 1e3, 3),
             "batched_graphs_per_s": ngraphs / t_batch, "plain_graphs_per_s": ngraphs / t_plain,
             "speedup": t_plain / t_batch, "identical_parts_and_cuts": same,
             "batched_edge_visits": r["stats"]["visits"], "plain_edge_visits": visits_plain,
@@ -190,11 +211,15 @@ def mesh_runs(log2n, k, eps, seed):
     return out
 
 
-def serve_benchmark(nreq, log_lo, log_hi, fracs, plain_sample):
+def serve_benchmark(nreq, log_lo, log_hi, fracs, slots=3, max_batch=64):
     """Poisson arrivals of partition requests (the batch mix's graph
-    distribution) at fixed rates, given as multiples of the plain path's
-    throughput on the same distribution; reports p50/p99 latency (arrival to
-    result) and graphs/s of the continuous-batching server."""
+    distribution, n log-uniform in [2^log_lo, 2^log_hi], seed 7) at fixed
+    rates, given as multiples of the plain path's throughput on the same
+    requests; reports p50/p99 latency (arrival to result) with the queueing
+    and service parts of the slowest requests, graphs/s of the
+    continuous-batching server, and the batched path (max_batch graphs per
+    call) on the same requests.  Every served and batched result must equal
+    the plain path's part of that request, node for node."""
     import threading
     import numpy as np
     import torch
@@ -202,24 +227,49 @@ def serve_benchmark(nreq, log_lo, log_hi, fracs, plain_sample):
     import paper_1404_4797_amd as sc
     t = time.time()
     gs = synth.batch_mix(nreq, seed=7, n_lo_log2=log_lo, n_hi_log2=log_hi)
-    log("serve mix: %d requests, n=%d generated in %.1fs" % (nreq, sum(g["n"] for g in gs), time.time() - t))
-    # plain path (one graph per call, graph already on the device) on a sample
-    plain = {}
+    ntot = sum(g["n"] for g in gs)
+    log("serve mix: %d requests, n=%d generated in %.1fs" % (nreq, ntot, time.time() - t))
+    # plain path: one graph per call, the graph already on the device
+    plain_part, plain_cut = [], []
     t_plain = 0.0
-    for i in range(min(plain_sample, nreq)):
-        d = sc.to_device(gs[i], "cuda")
+    stream = torch.cuda.current_stream()
+    for i, g in enumerate(gs):
+        d = sc.to_device(g, "cuda")
+        p = torch.empty(max(g["n"], 1), dtype=torch.int32, device="cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = sc.partition_dev(d, gs[i]["k"], gs[i]["eps"], gs[i]["seed"])
+        r = sc.partition_dev(d, g["k"], g["eps"], g["seed"], part=p, stream=stream)
         torch.cuda.synchronize()
         t_plain += time.perf_counter() - t0
-        plain[i] = r["cut"]
-    plain_gps = len(plain) / t_plain
-    log("plain: %.1f graphs/s on %d requests" % (plain_gps, len(plain)))
+        plain_part.append(p[:g["n"]].cpu().numpy())
+        plain_cut.append(r["cut"])
+        del d, p
+    plain_gps = nreq / t_plain
+    log("plain: %.1f graphs/s on %d requests" % (plain_gps, nreq))
+    # batched path: consecutive groups of max_batch requests, one call each
+    t_batch = 0.0
+    batch_same = True
+    for b0 in range(0, nreq, max_batch):
+        grp = gs[b0:b0 + max_batch]
+        u, nb = sc.union(grp)
+        du = sc.to_device(u, "cuda")
+        part = torch.empty(max(u["n"], 1), dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = sc.partition_batch_dev(du, nb, [g["k"] for g in grp], [g["eps"] for g in grp],
+                                   [g["seed"] for g in grp], part=part, stream=stream)
+        torch.cuda.synchronize()
+        t_batch += time.perf_counter() - t0
+        bp = part.cpu().numpy()
+        for j in range(len(grp)):
+            batch_same &= bool(np.array_equal(bp[nb[j]:nb[j + 1]], plain_part[b0 + j])) and \
+                int(r["cut"][j]) == plain_cut[b0 + j]
+        del du, part
+    log("batched: %.1f graphs/s in groups of %d, identical=%s" % (nreq / t_batch, max_batch, batch_same))
     rng = np.random.default_rng(7)
     runs = []
-    same = True
-    with sc.Server(slots=3, max_batch=64) as sv:
+    serve_same = True
+    with sc.Server(slots=slots, max_batch=max_batch) as sv:
         sv.wait(sv.submit(gs[0], gs[0]["k"], gs[0]["eps"], gs[0]["seed"]))  # warm up the workers
         for f in fracs:
             qps = f * plain_gps
@@ -239,17 +289,30 @@ def serve_benchmark(nreq, log_lo, log_hi, fracs, plain_sample):
             th.start()
             th.join()
             res = [sv.wait(i) for i in ids]
+            same = all(r["cut"] == plain_cut[i] and np.array_equal(r["part"], plain_part[i])
+                       for i, r in enumerate(res))
+            serve_same &= same
             lat = np.array([r["done_ms"] - r["submit_ms"] for r in res])
+            wait = np.array([r["start_ms"] - r["submit_ms"] for r in res])
+            service = np.array([r["done_ms"] - r["start_ms"] for r in res])
             span = (max(r["done_ms"] for r in res) - min(r["submit_ms"] for r in res)) / 1000.0
-            for i, c in plain.items():
-                same &= res[i]["cut"] == c
+            slow = np.argsort(lat)[-max(1, nreq // 100):]  # the requests at or above p99
             runs.append({"rate_vs_plain": f, "offered_qps": round(qps, 2), "graphs_per_s": round(nreq / span, 2),
                          "p50_ms": round(float(np.percentile(lat, 50)), 2),
                          "p99_ms": round(float(np.percentile(lat, 99)), 2),
-                         "mean_batch": round(float(np.mean([r["batch_size"] for r in res])), 2)})
+                         "mean_batch": round(float(np.mean([r["batch_size"] for r in res])), 2),
+                         "identical_parts": bool(same),
+                         "tail": {"requests": int(len(slow)),
+                                  "median_n": int(np.median([gs[i]["n"] for i in slow])),
+                                  "median_n_all": int(np.median([g["n"] for g in gs])),
+                                  "mean_wait_ms": round(float(wait[slow].mean()), 2),
+                                  "mean_service_ms": round(float(service[slow].mean()), 2),
+                                  "mean_batch": round(float(np.mean([res[i]["batch_size"] for i in slow])), 2)}})
             log("serve at %.1fx plain (%.1f qps): %s" % (f, qps, runs[-1]))
-    return {"requests": nreq, "n_log2_range": [log_lo, log_hi], "plain_graphs_per_s": round(plain_gps, 2),
-            "plain_sample": len(plain), "identical_cuts_on_sample": bool(same), "runs": runs}
+    return {"requests": nreq, "n_log2_range": [log_lo, log_hi], "nodes": int(ntot),
+            "plain_graphs_per_s": round(plain_gps, 2), "batched_graphs_per_s": round(nreq / t_batch, 2),
+            "batch_size": max_batch, "identical_parts_batched": bool(batch_same),
+            "identical_parts_served": bool(serve_same), "runs": runs}
 
 
 def copy_calibration(nbytes):
@@ -277,11 +340,14 @@ def main():
     ap.add_argument("--no-variants", dest="variants", action="store_false",
                     help="skip the V-cycle / degree-order runs after the timed steps")
     ap.add_argument("--copy-calib", type=int, default=0, help="bytes for a plain copy kernel (counter scaling)")
+    ap.add_argument("--no-kernel-timing", dest="kernel_timing", action="store_false",
+                    help="no HIP events around the dominant kernel in the timed steps (no roofline)")
     ap.add_argument("--batch-graphs", type=int, default=512, help="graphs in the batched-vs-plain comparison (0: skip)")
     ap.add_argument("--batch-log2", type=int, nargs=2, default=[10, 18], help="log2 range of n in the batch")
-    ap.add_argument("--serve-requests", type=int, default=120, help="requests per serving run (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests per serving run (0: skip); the Poisson serving workload has 2000")
     ap.add_argument("--serve-log2", type=int, nargs=2, default=[10, 20], help="log2 range of n of the requests")
-    ap.add_argument("--serve-rates", type=float, nargs="+", default=[0.5, 0.8, 4.0],
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[0.5, 0.8],
                     help="arrival rates as multiples of the plain path's graphs/s")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -326,7 +392,8 @@ def main():
     dom = max(modeled, key=lambda k: modeled[k]["ms"]) if modeled else None
     log("profiled step: cut=%d, dominant kernel %s" % (r_prof["cut"], dom))
 
-    sc.profile_begin(only=dom)
+    if args.kernel_timing:
+        sc.profile_begin(only=dom)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
@@ -336,7 +403,7 @@ def main():
         log("step %d: cut=%d" % (i, r["cut"]))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kdom = sc.profile_end()
+    kdom = sc.profile_end() if args.kernel_timing else {}
     ms_per_step = (t1 - t0) * 1000.0 / max(args.steps, 1)
     r = results[-1]
     st = r["stats"]
@@ -366,33 +433,37 @@ def main():
                for k, v in sorted(kstats.items(), key=lambda kv: -kv[1]["ms"])}
     lp_gb = sum(v["bytes"] for k, v in kstats.items()
                 if k.startswith("lp_eval") or k.startswith("lp_refine")) / 1e9
+    # the whole label-propagation phase against the HBM roofline: per round
+    # executed at level l, 24 B per node and 12 B per slot scanned (a round's
+    # minimal traffic), over the wall time of all rounds
+    lp_nodes = sum(st["level_n"][l] * st["cluster_rounds"][l] for l in range(len(st["cluster_rounds"])))
+    lp_nodes += sum(st["level_n"][l] * st["refine_rounds"][l] for l in range(len(st["refine_rounds"])))
+    lp_bytes = 24.0 * lp_nodes + 12.0 * visits
+    lp_phase = {"bytes_per_step": lp_bytes, "ms": round(st["ms_lp"], 3),
+                "achieved_GBps": round(lp_bytes / (st["ms_lp"] / 1e3) / 1e9, 1),
+                "frac": round(lp_bytes / (st["ms_lp"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                "edge_visits_per_s": visits / (st["ms_lp"] / 1e3)}
 
-    # reference ceiling for the evaluation: a plain random gather label[adj[e]]
-    # over every slot of the benchmark graph (torch index_select), the access
-    # that dominates evaluation; one pass per edge visit at that rate bounds
-    # the label-propagation time from below
+    # the access that bounds evaluation: one neighbour-label gather per slot,
+    # measured by the library's probe kernel on this graph (4-byte labels as
+    # in clustering, 1-byte labels as in refinement); the label-propagation
+    # rounds' visits at those rates bound their time from below
     gather = None
     if S > 0:
-        adj64 = d["adjncy"].long()
-        lab = torch.arange(n, dtype=torch.int32, device="cuda")
-        gout = torch.empty(S, dtype=torch.int32, device="cuda")
-        torch.index_select(lab, 0, adj64, out=gout)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(3):
-            torch.index_select(lab, 0, adj64, out=gout)
-        e1.record()
-        torch.cuda.synchronize()
-        gms = e0.elapsed_time(e1) / 3
-        rate = S / (gms / 1e3)
+        g4 = sc.gather_probe_dev(d, 4, reps=3, stream=stream)
+        g1 = sc.gather_probe_dev(d, 1, reps=3, stream=stream)
+        r4, r1 = S / (g4 / 1e3), S / (g1 / 1e3)
+        cvis = sum(st["level_S"][l] * st["cluster_rounds"][l] for l in range(len(st["cluster_rounds"])))
+        rvis = visits - cvis
+        floor_ms = (cvis / r4 + rvis / r1) * 1e3
         lp_ms = st["ms_lp"]
-        gather = {"ms_per_pass": round(gms, 3), "G_gathers_per_s": round(rate / 1e9, 1),
-                  "lp_ms_at_ceiling": round(visits / rate * 1e3, 1), "lp_ms": round(lp_ms, 1),
-                  "frac": round(visits / rate * 1e3 / lp_ms, 3)}
-        del adj64, lab, gout
-        log("gather ceiling: %.2f ms per pass over S, %.1f G gathers/s; LP %.1f ms vs %.1f ms at the ceiling"
-            % (gms, rate / 1e9, lp_ms, visits / rate * 1e3))
+        gather = {"ms_per_pass_i32": round(g4, 3), "ms_per_pass_u8": round(g1, 3),
+                  "G_gathers_per_s_i32": round(r4 / 1e9, 1), "G_gathers_per_s_u8": round(r1 / 1e9, 1),
+                  "lp_ms_at_ceiling": round(floor_ms, 1), "lp_ms": round(lp_ms, 1),
+                  "frac": round(floor_ms / lp_ms, 3),
+                  "lp_bytes_frac_at_ceiling": round(lp_bytes / (floor_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        log("gather ceiling: %.1f G/s (int32 labels), %.1f G/s (byte labels); LP %.1f ms vs %.1f ms at the ceiling"
+            % (r4 / 1e9, r1 / 1e9, lp_ms, floor_ms))
 
     out = {
         "metric": "SCLaP edge-visits/s & partition time; batched vs plain graphs/s, same cut",
@@ -410,7 +481,7 @@ def main():
         "phase_ms": {"coarsen": st["ms_coarsen"], "initial": st["ms_initial"], "refine": st["ms_refine"],
                      "lp": st["ms_lp"]},
         "lp_eval_GB_per_step": round(lp_gb, 3),
-        "roofline": roofline, "gather_ceiling": gather, "kernels": kernels,
+        "roofline": roofline, "lp_phase_roofline": lp_phase, "gather_ceiling": gather, "kernels": kernels,
         "kernels_from": "one step with events around every launch, outside the timed steps",
     }
     if args.variants:
@@ -436,10 +507,10 @@ def main():
         out["batched"] = batch_comparison(args.batch_graphs, 0, args.batch_log2[0], args.batch_log2[1], extra)
     if args.serve_requests > 0:
         out["serving"] = serve_benchmark(args.serve_requests, args.serve_log2[0], args.serve_log2[1],
-                                         args.serve_rates, plain_sample=24)
+                                         args.serve_rates)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample) ...")
-        out["cpu_baseline"] = cpu_baseline(g, w)
+        out["cpu_baseline"], out["cpu_baseline_all_cores"] = cpu_baseline(g, w)
     print(json.dumps(out), flush=True)
 
 

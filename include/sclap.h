@@ -126,6 +126,10 @@ typedef struct {
     int32_t select_launches;      /* tuning (never changes results; 0 = library default): launches of
                                      the multi-workgroup selection per sub-round, one key digit each;
                                      keys with more digits finish in the last launch */
+    int32_t graph_capture;        /* tuning (never changes results): 1: every label-propagation call
+                                     records all its rounds into one HIP graph and launches it once,
+                                     with no host work between rounds; 0 (default) or -1: kernels are
+                                     launched one by one, the host one round ahead of the device */
 } sclap_options;
 
 #define SCLAP_MAX_LEVELS 64
@@ -350,15 +354,19 @@ int sclap_server_poll(sclap_server* sv, uint64_t req, int32_t timeout_ms, int32_
 void sclap_server_destroy(sclap_server* sv);
 
 /*
- * Tuning (result-free): times one clustering round (level 0, seed 1, cluster
- * bound from k as in sclap_partition) of the device graph g under each of a
- * few candidate sets of degree-bucket thresholds, which fix the LDS table
- * size each row gets, and writes the fastest set into opt's tuning fields
- * (lane_max_degree, wave_max_degree, block_max_degree); each set is timed
- * twice, and the library default is kept unless a set is at least 3 %
- * faster.  g may be a batch
- * union; k is then a representative block count.  Semantic fields of opt are
- * read, not changed; results of later calls do not depend on the choice.
+ * Tuning (result-free): searches the tuning options for the device graph g
+ * (normally a batch union, with k a representative block count) and writes
+ * the choice into opt's tuning fields (lane_max_degree, wave_max_degree,
+ * block_max_degree, graph_capture).  The objective is the measured time of one
+ * clustering round from singletons (cluster bound from k as in
+ * sclap_partition) plus one refinement round of a k-way partition, the faster
+ * of two timings.  The degree thresholds decide which kernel and LDS table a
+ * row gets (registers of one lane; 64-, 128- or 512-entry tables for 16, 32
+ * or 64 lanes; 2048-, 8192- or 16384-entry tables for a workgroup; hub chunks
+ * above), so the search sizes the tables by degree range.  Coordinate search
+ * from the library defaults: capture, then block, wave and lane thresholds;
+ * a value is kept only if it is at least 3 % faster.  Semantic fields of opt
+ * are read, not changed; results of later calls do not depend on the choice.
  */
 int sclap_autotune_dev(const sclap_graph* g, int32_t k, sclap_options* opt, void* stream);
 
@@ -367,9 +375,9 @@ int sclap_autotune_dev(const sclap_graph* g, int32_t k, sclap_options* opt, void
  * that later calls on this thread issue, with HIP events recorded on the
  * launching stream around each launch; sclap_profile_end() stops, writes up to
  * `capacity` per-kernel totals to out (launch count, summed event time, and
- * the algorithmic bytes the launches must move: for node evaluation, per
- * evaluated node its list entry, row offsets, label and weight, and per
- * adjacency slot the neighbour id, edge weight and neighbour label), sets
+ * the algorithmic bytes the launches must move: for node evaluation 24 per
+ * evaluated node (row offsets, label, node weight, one label weight) and 12
+ * per adjacency slot (neighbour id, edge weight, neighbour label)), sets
  * *count and clears the totals.  Timing adds event records (each one costs
  * device time between launches) but does not change any result.
  */
@@ -382,6 +390,17 @@ typedef struct {
 
 int sclap_profile_begin(void);
 int sclap_profile_end(sclap_kernel_stat* out, int32_t capacity, int32_t* count);
+
+/*
+ * Measurement helper: the rate at which the neighbour labels of the device
+ * graph g can be gathered, the access that bounds node evaluation (Section
+ * 3.1: a node scans the labels of all its neighbours).  Runs reps passes of a
+ * kernel that sums label[adj[e]] over every slot (label_bytes 4: int32 labels,
+ * as in clustering; 1: byte labels, as in refinement with at most 256 blocks)
+ * with several loads in flight per thread, after one warm-up pass, and writes
+ * the average pass time in milliseconds to *ms.  Allocates n label entries.
+ */
+int sclap_gather_probe_dev(const sclap_graph* g, int32_t label_bytes, int32_t reps, double* ms, void* stream);
 
 /*
  * Same as sclap_profile_begin, but only launches of the kernel named `name`

@@ -29,7 +29,7 @@ def build(force=False):
     newest = max(os.path.getmtime(_SRC), os.path.getmtime(_HDR))
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=c99", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
 
 
@@ -80,6 +80,8 @@ def _load():
             "orc_cluster": (i32, [G, i64, i32, i32, u64, i32, vp, vp, vp, vp]),
             "orc_eval_node_within": (i32, [G, vp, i32, i32, i32, u64, i64, vp, vp, i32, ctypes.POINTER(_Eval)]),
             "orc_subround_within": (i64, [G, vp, i32, i32, i32, i32, i32, u64, i64, vp, vp, vp, vp, vp]),
+            "orc_subround_par": (i64, [G, i32, i32, i32, i32, i32, u64, i64, vp, vp, vp, i32]),
+            "orc_max_threads": (i32, []),
             "orc_cluster_within": (i32, [G, vp, i64, i32, i32, u64, i32, vp, vp, vp, vp]),
             "orc_cycle_seed": (u64, [u64, i32]),
             "orc_degree_colors": (None, [G, vp, i32, vp]),
@@ -197,6 +199,22 @@ def subround(g, phase, level, rnd, sub, nsub, seed, bound, label, w, color_overr
                                         label.ctypes.data, w.ctypes.data, visits.ctypes.data,
                                         ncand.ctypes.data)
     return int(moves), int(visits[0]), int(ncand[0])
+
+
+def subround_par(g, phase, level, rnd, sub, nsub, seed, bound, label, w, threads=0):
+    """orc_subround with the node evaluation on ``threads`` OpenMP threads
+    (0: all); in place on ``label`` and ``w``.  Returns (moves, visits)."""
+    gv = _GraphView(g)
+    assert label.dtype == np.int32 and w.dtype == np.int64 and label.flags.c_contiguous and w.flags.c_contiguous
+    visits = np.zeros(1, dtype=np.int64)
+    t = threads if threads > 0 else max_threads()
+    moves = _load().orc_subround_par(gv.ref, phase, level, rnd, sub, nsub, seed, bound, label.ctypes.data,
+                                     w.ctypes.data, visits.ctypes.data, t)
+    return int(moves), int(visits[0])
+
+
+def max_threads():
+    return int(_load().orc_max_threads())
 
 
 def cluster(g, U, rounds=10, seed=1, level=0, nsub=4, color_override=None, block=None):

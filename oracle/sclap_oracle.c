@@ -19,6 +19,9 @@
 #include "sclap_oracle.h"
 
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -239,29 +242,24 @@ static int cmp_cand(const void* x, const void* y) {
  * sub-round are not credited).  Every block that started within the bound
  * therefore stays within it, which is the size constraint of Section 3.1.
  */
-int64_t orc_subround_within(const orc_graph* g, const int32_t* block, int32_t phase, int32_t level,
-                            int32_t round, int32_t sub, int32_t nsub, uint64_t seed, int64_t bound,
-                            const int32_t* color_override, int32_t* label, int64_t* w, int64_t* visits,
-                            int64_t* ncand) {
-    int32_t n = g->n;
-    cand* C = (cand*)malloc((size_t)(n > 0 ? n : 1) * sizeof(cand));
-    int64_t nc = 0;
-    for (int32_t v = 0; v < n; ++v) {
-        int32_t col = color_override ? color_override[v] : orc_color(seed, level, phase, v, nsub);
-        if (col != sub) continue;
-        if (visits)
-            for (int64_t i = g->xadj[v]; i < g->xadj[v + 1]; ++i) *visits += in_block(block, v, g->adjncy[i]);
-        orc_eval ev;
-        orc_eval_node_within(g, block, phase, level, round, seed, bound, label, w, v, &ev);
-        if (!ev.emit) continue;
-        C[nc].t = ev.target;
-        C[nc].gain = ev.gain;
-        C[nc].v = v;
-        C[nc].from = label[v];
-        C[nc].c = node_w(g, v);
-        ++nc;
-    }
-    if (ncand) *ncand += nc;
+/* Candidate of node v in this sub-round (Section 3.1 rule, orc_eval_node). */
+static int eval_candidate(const orc_graph* g, const int32_t* block, int32_t phase, int32_t level, int32_t round,
+                          uint64_t seed, int64_t bound, const int32_t* label, const int64_t* w, int32_t v, cand* out) {
+    orc_eval ev;
+    orc_eval_node_within(g, block, phase, level, round, seed, bound, label, w, v, &ev);
+    if (!ev.emit) return 0;
+    out->t = ev.target;
+    out->gain = ev.gain;
+    out->v = v;
+    out->from = label[v];
+    out->c = node_w(g, v);
+    return 1;
+}
+
+/* For each target, admit the longest prefix of its candidates in
+ * (gain desc, node asc) order that keeps w(target) <= bound, counted from the
+ * target's weight at the start of the sub-round; then apply the moves. */
+static int64_t admit_and_apply(cand* C, int64_t nc, int64_t bound, int32_t* label, int64_t* w) {
     qsort(C, (size_t)nc, sizeof(cand), cmp_cand);
     char* admit = (char*)calloc((size_t)(nc > 0 ? nc : 1), 1);
     for (int64_t i = 0; i < nc;) {
@@ -286,8 +284,76 @@ int64_t orc_subround_within(const orc_graph* g, const int32_t* block, int32_t ph
         ++moves;
     }
     free(admit);
+    return moves;
+}
+
+static int32_t color_of(const int32_t* color_override, uint64_t seed, int32_t level, int32_t phase, int32_t v,
+                        int32_t nsub) {
+    return color_override ? color_override[v] : orc_color(seed, level, phase, v, nsub);
+}
+
+/*
+ * One sub-round.  Evaluate all nodes of colour `sub` against the frozen state,
+ * then for each target admit the longest prefix of its candidates, in
+ * (gain desc, node asc) order, that keeps w(target) <= bound, counting from
+ * the target's weight at the start of the sub-round (departures in the same
+ * sub-round are not credited).  Every block that started within the bound
+ * therefore stays within it, which is the size constraint of Section 3.1.
+ */
+int64_t orc_subround_within(const orc_graph* g, const int32_t* block, int32_t phase, int32_t level,
+                            int32_t round, int32_t sub, int32_t nsub, uint64_t seed, int64_t bound,
+                            const int32_t* color_override, int32_t* label, int64_t* w, int64_t* visits,
+                            int64_t* ncand) {
+    int32_t n = g->n;
+    cand* C = (cand*)malloc((size_t)(n > 0 ? n : 1) * sizeof(cand));
+    int64_t nc = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        if (color_of(color_override, seed, level, phase, v, nsub) != sub) continue;
+        if (visits)
+            for (int64_t i = g->xadj[v]; i < g->xadj[v + 1]; ++i) *visits += in_block(block, v, g->adjncy[i]);
+        nc += eval_candidate(g, block, phase, level, round, seed, bound, label, w, v, &C[nc]);
+    }
+    if (ncand) *ncand += nc;
+    int64_t moves = admit_and_apply(C, nc, bound, label, w);
     free(C);
     return moves;
+}
+
+/*
+ * The same sub-round with the evaluation spread over `threads` OpenMP
+ * threads (the CPU baseline on all host cores).  Evaluation reads only the
+ * frozen state, so the candidates are those of the sequential loop; they are
+ * kept per node and gathered in node order, and admission and apply run
+ * sequentially as above: the result is identical.
+ */
+int64_t orc_subround_par(const orc_graph* g, int32_t phase, int32_t level, int32_t round, int32_t sub, int32_t nsub,
+                         uint64_t seed, int64_t bound, int32_t* label, int64_t* w, int64_t* visits, int32_t threads) {
+    int32_t n = g->n;
+    cand* P = (cand*)malloc((size_t)(n > 0 ? n : 1) * sizeof(cand));
+    char* has = (char*)calloc((size_t)(n > 0 ? n : 1), 1);
+    int64_t vis = 0;
+#pragma omp parallel for schedule(dynamic, 256) num_threads(threads) reduction(+ : vis)
+    for (int32_t v = 0; v < n; ++v) {
+        if (orc_color(seed, level, phase, v, nsub) != sub) continue;
+        vis += g->xadj[v + 1] - g->xadj[v];
+        has[v] = (char)eval_candidate(g, NULL, phase, level, round, seed, bound, label, w, v, &P[v]);
+    }
+    if (visits) *visits += vis;
+    int64_t nc = 0;
+    for (int32_t v = 0; v < n; ++v)
+        if (has[v]) P[nc++] = P[v];
+    int64_t moves = admit_and_apply(P, nc, bound, label, w);
+    free(has);
+    free(P);
+    return moves;
+}
+
+int32_t orc_max_threads(void) {
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 int64_t orc_subround(const orc_graph* g, int32_t phase, int32_t level, int32_t round, int32_t sub,

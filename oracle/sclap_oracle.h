@@ -78,6 +78,13 @@ int64_t orc_subround_within(const orc_graph* g, const int32_t* block, int32_t ph
                             int32_t round, int32_t sub, int32_t nsub, uint64_t seed, int64_t bound,
                             const int32_t* color_override, int32_t* label, int64_t* w, int64_t* visits,
                             int64_t* ncand);
+/* orc_subround (hash colours, no block array) with the node evaluation on
+ * `threads` OpenMP threads; admission and apply stay sequential, so the result
+ * is identical.  For the CPU baseline on all cores. */
+int64_t orc_subround_par(const orc_graph* g, int32_t phase, int32_t level, int32_t round, int32_t sub, int32_t nsub,
+                         uint64_t seed, int64_t bound, int32_t* label, int64_t* w, int64_t* visits, int32_t threads);
+/* Threads OpenMP would use by default (1 without OpenMP). */
+int32_t orc_max_threads(void);
 
 int32_t orc_cluster(const orc_graph* g, int64_t U, int32_t rounds, int32_t nsub, uint64_t seed,
                     int32_t level, const int32_t* color_override, int32_t* labels, int32_t* rounds_run,

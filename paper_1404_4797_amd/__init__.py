@@ -37,7 +37,7 @@ EXPORTS = [
     "sclap_partition_batch", "sclap_partition_batch_dev",
     "sclap_server_create", "sclap_server_submit", "sclap_server_poll", "sclap_server_destroy",
     "sclap_autotune_dev", "sclap_trim_memory", "sclap_initial_partition_lp_dev",
-    "sclap_profile_begin", "sclap_profile_end", "sclap_profile_begin_only",
+    "sclap_profile_begin", "sclap_profile_end", "sclap_profile_begin_only", "sclap_gather_probe_dev",
 ]
 
 
@@ -68,7 +68,8 @@ class Options(ctypes.Structure):
                 ("hub_region_cap", ctypes.c_int32), ("select_small_max", ctypes.c_int32),
                 ("skip_quiet", ctypes.c_int32), ("vcycles", ctypes.c_int32),
                 ("degree_order", ctypes.c_int32), ("contract_bucket_mean", ctypes.c_int32),
-                ("initial_partitioner", ctypes.c_int32), ("select_launches", ctypes.c_int32)]
+                ("initial_partitioner", ctypes.c_int32), ("select_launches", ctypes.c_int32),
+                ("graph_capture", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):
@@ -156,6 +157,7 @@ def load():
         "sclap_profile_begin": (ctypes.c_int, []),
         "sclap_profile_begin_only": (ctypes.c_int, [ctypes.c_char_p]),
         "sclap_profile_end": (ctypes.c_int, [ctypes.POINTER(KernelStat), i32, vp]),
+        "sclap_gather_probe_dev": (ctypes.c_int, [G, i32, i32, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -462,6 +464,15 @@ def profile_end():
     _check(load().sclap_profile_end(arr, cap, ctypes.addressof(cnt)))
     return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].ms, "bytes": arr[i].bytes}
             for i in range(min(cnt.value, cap))}
+
+
+def gather_probe_dev(d, label_bytes=4, reps=3, stream=None):
+    """Average ms of one pass gathering label[adj[e]] over every slot of the
+    device graph ``d`` (1- or 4-byte labels)."""
+    dg = _DevGraph(d)
+    ms = ctypes.c_double(0)
+    _check(load().sclap_gather_probe_dev(dg.ref, label_bytes, reps, ctypes.addressof(ms), _stream(stream)))
+    return ms.value
 
 
 # ------------------------------------------------------------------ batches

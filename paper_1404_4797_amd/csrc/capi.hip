@@ -578,6 +578,17 @@ int sclap_autotune_dev(const sclap_graph* g, int32_t k, sclap_options* opt, void
         opt->lane_max_degree = t.lane_max;
         opt->wave_max_degree = t.wave_max;
         opt->block_max_degree = t.block_max;
+        opt->graph_capture = t.capture;
+        return SCLAP_OK;
+    });
+}
+
+int sclap_gather_probe_dev(const sclap_graph* g, int32_t label_bytes, int32_t reps, double* ms, void* stream) {
+    return guarded([&] {
+        if (!ms || reps < 1) fail(SCLAP_ERR_INVALID, "ms is NULL or reps < 1");
+        hipStream_t s = as_stream(stream);
+        const DevGraph d = dev_view(g, s);
+        *ms = gather_probe(d, label_bytes, reps, s);
         return SCLAP_OK;
     });
 }

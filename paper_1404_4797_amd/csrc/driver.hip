@@ -44,6 +44,8 @@ Opts resolve(const sclap_options* o) {
     if (o->select_small_max > 0) r.tune.select_small_max = o->select_small_max;
     if (o->select_launches < 0) fail(SCLAP_ERR_INVALID, "select_launches must be >= 0");
     r.tune.select_launches = o->select_launches;
+    if (o->graph_capture < -1 || o->graph_capture > 1) fail(SCLAP_ERR_INVALID, "graph_capture must be -1, 0 or 1");
+    r.tune.capture = o->graph_capture;
     r.tune.skip_quiet = o->skip_quiet < 0 ? -1 : (o->skip_quiet > 0 ? 1 : 0);
     r.vcycles = o->vcycles == 0 ? 1 : o->vcycles;
     r.degree_order = o->degree_order != 0 ? 1 : 0;
@@ -930,48 +932,67 @@ LPTuning autotune(const DevGraph& g_in, int32_t k, const Opts& o, hipStream_t s)
     int64_t cV = 0, cmax = 0;
     check_graph(g, false, &cV, &cmax, s);
     drop_unit_weights(g, s);
-    const int64_t U = std::max(cmax, cV / (static_cast<int64_t>(o.divisor) * k));
-    // (lane, wave, block) upper degrees; the first is the library default
-    static const int32_t kCand[][3] = {{16, 256, 8192}, {16, 128, 8192}, {8, 256, 8192},
-                                       {16, 256, 4096}, {16, 64, 2048},  {4, 128, 8192}};
     LPTuning best = o.tune;
-    double best_ms = 1e300, default_ms = 1e300;
     if (g.n == 0) return best;
-    DBuf<int32_t> labels(g.n, s), w(g.n, s);
+    const int64_t U = std::max(cmax, cV / (static_cast<int64_t>(o.divisor) * k));
+    const int64_t Lmax = lmax_of(cV, k, 0.03);
+    DBuf<int32_t> labels(g.n, s), w(std::max<int64_t>(g.n, k), s);
+    std::vector<int32_t> hpart(g.n);
+    for (int32_t v = 0; v < g.n; ++v) hpart[v] = static_cast<int32_t>(static_cast<int64_t>(v) * k / g.n);
+    DBuf<int32_t> part0(g.n, s), part(g.n, s);
+    HIPCHK(hipMemcpyAsync(part0.get(), hpart.data(), g.n * sizeof(int32_t), hipMemcpyHostToDevice, s));
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    for (size_t ci = 0; ci < sizeof(kCand) / sizeof(kCand[0]); ++ci) {
-        LPTuning t = o.tune;
-        t.lane_max = kCand[ci][0];
-        t.wave_max = kCand[ci][1];
-        t.block_max = kCand[ci][2];
+    // The objective: one clustering round from singletons plus one refinement
+    // round of a k-way partition (contiguous id ranges), the faster of two
+    // timings.  Neither depends on the knobs' values, only their time does.
+    auto measure = [&](const LPTuning& t) {
         double ms = 1e300;
-        for (int rep = 0; rep < 2; ++rep) {  // the faster of two timings
+        for (int rep = 0; rep < 2; ++rep) {
             iota_u32(reinterpret_cast<uint32_t*>(labels.get()), g.n, s);
             label_weights(g, labels.get(), w.get(), g.n, s);
+            HIPCHK(hipMemcpyAsync(part.get(), part0.get(), g.n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
             HIPCHK(hipEventRecord(e0, s));
             run_lp(g, kCluster, 0, 1, o.nsub, 1, U, labels.get(), w.get(), g.n, nullptr, t, s);
+            label_weights(g, part.get(), w.get(), k, s);
+            run_lp(g, kRefine, 0, 1, o.nsub, 1, Lmax, part.get(), w.get(), k, nullptr, t, s);
             HIPCHK(hipEventRecord(e1, s));
             HIPCHK(hipEventSynchronize(e1));
             float f = 0;
             HIPCHK(hipEventElapsedTime(&f, e0, e1));
             ms = std::min(ms, static_cast<double>(f));
         }
-        if (ci == 0) default_ms = ms;
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = t;
+        return ms;
+    };
+    // Coordinate search from the library defaults.  The degree thresholds
+    // decide which kernel, and so which LDS table, a row gets: one lane and
+    // registers (degree <= lane_max), 16, 32 or 64 lanes with 64-, 128- and
+    // 512-entry tables (<= wave_max), one workgroup with 2048-, 8192- or
+    // 16384-entry tables (<= block_max), above that the hub chunks; the
+    // capture choice decides whether the rounds run as one HIP graph.  A
+    // value is taken only if it is at least 3 % faster than the current best.
+    best.lane_max = 16;
+    best.wave_max = 256;
+    best.block_max = 8192;
+    double best_ms = measure(best);
+    auto try_values = [&](int32_t LPTuning::*field, std::initializer_list<int32_t> values) {
+        const int32_t keep = best.*field;
+        for (int32_t val : values) {
+            if (val == keep) continue;
+            LPTuning t = best;
+            t.*field = val;
+            const double ms = measure(t);
+            if (ms < 0.97 * best_ms) {
+                best_ms = ms;
+                best = t;
+            }
         }
-    }
-    // one round predicts a whole run only roughly: keep the default unless a
-    // candidate is clearly faster
-    if (best_ms > 0.97 * default_ms) {
-        best = o.tune;
-        best.lane_max = kCand[0][0];
-        best.wave_max = kCand[0][1];
-        best.block_max = kCand[0][2];
-    }
+    };
+    try_values(&LPTuning::capture, {1, -1});
+    try_values(&LPTuning::block_max, {1024, 2048, 4096});
+    try_values(&LPTuning::wave_max, {32, 64, 128});
+    try_values(&LPTuning::lane_max, {4, 8});
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return best;

@@ -4,6 +4,7 @@
 #include <climits>
 
 #include "graph_ops.hpp"
+#include "sclap.h"
 #include "profile.hpp"
 #include "tiles.hpp"
 
@@ -213,6 +214,68 @@ void cut_and_weights(const DevGraph& g, const int32_t* part, int32_t k, int64_t*
     HIPCHK(hipStreamSynchronize(s));
     *cut = static_cast<int64_t>(h[0] / 2);
     for (int32_t b = 0; b < k; ++b) bw[b] = static_cast<int64_t>(h[1 + b]);
+}
+
+// ------------------------------------------------------ gather-rate probe
+//
+// The access that bounds node evaluation: for every adjacency slot, the
+// label of the neighbour (a random 1- or 4-byte read).  The probe sums
+// label[adj[e]] over all slots with several loads in flight per thread and
+// writes one number, so its time is the rate at which this graph's neighbour
+// labels can be gathered at all.
+
+namespace {
+
+template <typename T>
+__global__ void __launch_bounds__(256) gather_probe_kernel(const int32_t* __restrict__ adj, const T* __restrict__ lab,
+                                                           int64_t S, unsigned long long* __restrict__ out) {
+    constexpr int U = 8;
+    unsigned long long acc = 0;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * 256 * U;
+    for (int64_t b = static_cast<int64_t>(blockIdx.x) * 256 * U + threadIdx.x; b < S; b += stride) {
+        int32_t x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = b + u * 256;
+            x[u] = e < S ? adj[e] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += x[u] >= 0 ? static_cast<unsigned long long>(lab[x[u]]) : 0ULL;
+    }
+    acc = wave_sum(acc);
+    if (lane_id() == 0) atomicAdd(out, acc);
+}
+
+}  // namespace
+
+float gather_probe(const DevGraph& g, int32_t label_bytes, int32_t reps, hipStream_t s) {
+    if (g.S == 0 || g.n == 0) return 0.0f;
+    if (label_bytes != 1 && label_bytes != 4) fail(SCLAP_ERR_INVALID, "label_bytes must be 1 or 4");
+    DBuf<int32_t> lab(g.n, s);
+    iota_u32(reinterpret_cast<uint32_t*>(lab.get()), g.n, s);  // any values: only the addresses matter
+    DBuf<unsigned long long> out(1, s);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const unsigned grid = 4096;
+    auto launch = [&] {
+        if (label_bytes == 1)
+            gather_probe_kernel<uint8_t><<<grid, 256, 0, s>>>(g.adj, reinterpret_cast<const uint8_t*>(lab.get()),
+                                                              g.S, out.get());
+        else
+            gather_probe_kernel<int32_t><<<grid, 256, 0, s>>>(g.adj, lab.get(), g.S, out.get());
+        LAUNCHCHK();
+    };
+    launch();  // warm-up
+    HIPCHK(hipEventRecord(e0, s));
+    for (int32_t r = 0; r < reps; ++r) launch();
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms / static_cast<float>(reps > 0 ? reps : 1);
 }
 
 int validate_graph(const DevGraph& g, int64_t* cV, int64_t* cmax, hipStream_t s) {

@@ -49,7 +49,6 @@ void project(int32_t n, const int32_t* C, const int32_t* coarse_part, int32_t* p
 
 // cut (host out) and block weights bw[k] (host out).
 void cut_and_weights(const DevGraph& g, const int32_t* part, int32_t k, int64_t* cut, int64_t* bw, hipStream_t s);
-
 // Checks CSR structure, ranges, weights, totals and symmetry (hash test).
 // Returns 0 or a negative status.  Also reports c(V) and max c(v).
 int validate_graph(const DevGraph& g, int64_t* cV, int64_t* cmax, hipStream_t s);
@@ -59,6 +58,9 @@ void node_weight_stats(const DevGraph& g, int64_t* cV, int64_t* cmax, hipStream_
 
 // True iff every value of a[0..count) lies in [lo, hi).
 bool all_in_range(const int32_t* a, int64_t count, int32_t lo, int32_t hi, hipStream_t s);
+// Average time (ms) of a pass that gathers one 1- or 4-byte label per slot
+// of g (label[adj[e]]), over reps passes after one warm-up.
+float gather_probe(const DevGraph& g, int32_t label_bytes, int32_t reps, hipStream_t s);
 
 // Several disjoint graphs in one CSR.  Member m owns nodes [nb[m], nb[m+1])
 // and slots [sb[m], sb[m+1]); ids[m] is its index in the caller's batch.

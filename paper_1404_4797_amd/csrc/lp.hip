@@ -103,14 +103,40 @@ struct EvalArgs {
     // than their own, not overloaded, and no neighbour has moved since.  Such a
     // node emits nothing while it stays quiet and its block is not overloaded
     // (its connections are unchanged), so it need not be evaluated again.
-    uint8_t* quiet;     // [n] flags, written by every evaluation (null: not tracked)
+    uint8_t* quiet;     // [n] flags (null: not tracked); see quiet_mode()
+    const uint32_t* rcnt;  // candidates of each round so far (device)
+    int32_t round;         // this round
+    int32_t quiet_n;       // nodes of the graph (the tracking threshold is 1/8 of them)
     int32_t dense_k;    // > 0: every node's labels are lbase + [0, dense_k) (refinement blocks)
-    int32_t use_quiet;  // 1: skip quiet nodes
+    // the previous round's candidate count (null in the first round): after a
+    // round without candidates the state is a fixed point and the evaluation
+    // of the later rounds is skipped
+    const uint32_t* gate;
     const int32_t* nodes;  // schedule entries of this launch
     int32_t count;
     int32_t* ct;  // per entry: target label or -1
     int32_t* cg;  // per entry: gain
 };
+
+// A round runs only while the previous one had candidates (gate: that
+// round's candidate count, null for the first round).  Rounds are enqueued
+// before the previous round's count is known (ahead of the host, or all of
+// a level's rounds at once in a captured graph), so every kernel checks the
+// gate: after a round without candidates the following ones do nothing.
+__device__ __forceinline__ bool stopped(const uint32_t* gate) { return gate && *gate == 0; }
+
+// Quiet-node tracking: marks are written from two rounds after the first
+// round with at most n/8 candidates on, and used to skip nodes one round
+// later (1: mark, 2: mark and skip, 0: off).  Derived from the per-round
+// candidate counts on the device, so it needs no host decision per round.
+__device__ __forceinline__ int quiet_mode(const uint8_t* quiet, const uint32_t* rcnt, int32_t round, int32_t n) {
+    if (!quiet) return 0;
+    for (int32_t q = 0; q + 2 <= round; ++q)
+        if (static_cast<int64_t>(rcnt[q]) * 8 <= n) return q + 2 < round ? 2 : 1;
+    return 0;
+}
+
+__device__ __forceinline__ int quiet_mode(const EvalArgs& A) { return quiet_mode(A.quiet, A.rcnt, A.round, A.quiet_n); }
 
 // ------------------------------------------------------- selection helpers
 
@@ -284,8 +310,8 @@ __device__ __forceinline__ void store_result(const EvalArgs& A, int32_t i, int32
 }
 
 // True if v is quiet and may skip evaluation (its block is not overloaded).
-__device__ __forceinline__ bool skip_quiet(const EvalArgs& A, int32_t v, const Ctx& kx) {
-    if (!A.use_quiet || !A.quiet[v]) return false;
+__device__ __forceinline__ bool skip_quiet(const EvalArgs& A, int qm, int32_t v, const Ctx& kx) {
+    if (qm < 2 || !A.quiet[v]) return false;
     return !A.refine || A.w[A.label[v]] <= kx.bound;
 }
 
@@ -338,10 +364,11 @@ __device__ __forceinline__ void insert_slots(const EvalArgs& A, int64_t b, int32
 template <int MAXD>
 __global__ void __launch_bounds__(256) eval_lane_kernel(EvalArgs A) {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= A.count) return;
+    if (i >= A.count || stopped(A.gate)) return;
+    const int qm = quiet_mode(A);
     const int32_t v = A.nodes[i];
     const Ctx kx = ctx_of(A, v);
-    if (skip_quiet(A, v, kx)) {
+    if (skip_quiet(A, qm, v, kx)) {
         store_result(A, i, -1, 0, 0, false);
         return;
     }
@@ -384,7 +411,7 @@ __global__ void __launch_bounds__(256) eval_lane_kernel(EvalArgs A) {
         best_consider(best, x, conn, kx);
     }
     store_result(A, i, best.x, best.conn, own, over);
-    if (A.quiet) A.quiet[v] = (!over && !blocked) ? 1 : 0;
+    if (qm) A.quiet[v] = (!over && !blocked) ? 1 : 0;
 }
 
 // --------------------------------------------------- group and wave buckets
@@ -399,12 +426,13 @@ __global__ void __launch_bounds__(256) eval_group_kernel(EvalArgs A) {
     const int grp = threadIdx.x / G;
     const int gl = threadIdx.x % G;
     const int node_i = blockIdx.x * NG + grp;
-    if (node_i >= A.count) return;  // uniform per group
+    if (node_i >= A.count || stopped(A.gate)) return;  // uniform per group
+    const int qm = quiet_mode(A);
     int32_t* keys = tkeys[grp];
     int32_t* vals = tvals[grp];
     const int32_t v = A.nodes[node_i];
     const Ctx kx = ctx_of(A, v);
-    if (skip_quiet(A, v, kx)) {
+    if (skip_quiet(A, qm, v, kx)) {
         if (gl == 0) store_result(A, node_i, -1, 0, 0, false);
         return;
     }
@@ -444,7 +472,7 @@ __global__ void __launch_bounds__(256) eval_group_kernel(EvalArgs A) {
     const bool any_blocked = group_any<G>(blocked);
     if (gl == 0) {
         store_result(A, node_i, bx, bconn, own, over);
-        if (A.quiet) A.quiet[v] = (!over && !any_blocked) ? 1 : 0;
+        if (qm) A.quiet[v] = (!over && !any_blocked) ? 1 : 0;
     }
 }
 
@@ -461,9 +489,11 @@ __global__ void __launch_bounds__(NT) eval_block_kernel(EvalArgs A) {
     const int tid = threadIdx.x;
     const int wid = tid >> 6;
     const int lane = lane_id();
+    if (stopped(A.gate)) return;  // uniform over the grid
+    const int qm = quiet_mode(A);
     const int32_t v = A.nodes[blockIdx.x];
     const Ctx kx = ctx_of(A, v);
-    if (skip_quiet(A, v, kx)) {  // uniform over the workgroup
+    if (skip_quiet(A, qm, v, kx)) {  // uniform over the workgroup
         if (tid == 0) store_result(A, blockIdx.x, -1, 0, 0, false);
         return;
     }
@@ -512,7 +542,7 @@ __global__ void __launch_bounds__(NT) eval_block_kernel(EvalArgs A) {
         uint64_t ft = ~0ULL;
         for (int w = 0; w < NT / 64; ++w) combine_into(fc, ft, fx, s_conn[w], s_tie[w], s_x[w]);
         store_result(A, blockIdx.x, fx, fc, own, over);
-        if (A.quiet) A.quiet[v] = (!over && !any_blocked) ? 1 : 0;
+        if (qm) A.quiet[v] = (!over && !any_blocked) ? 1 : 0;
     }
 }
 
@@ -566,6 +596,7 @@ __global__ void __launch_bounds__(kHubThreads) hub_chunk_kernel(EvalArgs A, HubA
     __shared__ uint32_t pcount[1 << kMaxPartLog];
     __shared__ int32_t pbase[1 << kMaxPartLog];
     constexpr int kPer = kHubTable / kHubThreads;
+    if (stopped(A.gate)) return;  // uniform over the grid
     const int tid = threadIdx.x;
     const int32_t h = H.chunk_hub[blockIdx.x];
     const int32_t v = H.hub_nodes[h];
@@ -634,6 +665,7 @@ __global__ void __launch_bounds__(kPartThreads) hub_part_kernel(EvalArgs A, HubA
     __shared__ int32_t s_conn[kPartThreads / 64];
     __shared__ int32_t s_x[kPartThreads / 64];
     __shared__ uint64_t s_tie[kPartThreads / 64];
+    if (stopped(A.gate)) return;  // uniform over the grid
     const int tid = threadIdx.x;
     const int32_t gp = blockIdx.x;
     const int32_t h = H.part_hub[gp];
@@ -722,7 +754,7 @@ __device__ __forceinline__ void hub_decide(const EvalArgs& A, const HubArgs& H, 
 }
 
 __global__ void __launch_bounds__(64) hub_finish_kernel(EvalArgs A, HubArgs H) {
-    if (H.big[blockIdx.x]) return;
+    if (stopped(A.gate) || H.big[blockIdx.x]) return;
     hub_decide(A, H, blockIdx.x, H.hub_pbase);
 }
 
@@ -764,7 +796,7 @@ __global__ void __launch_bounds__(256) hub_scan_kernel(EvalArgs A, HubArgs H, in
     __shared__ int32_t s_x[4];
     __shared__ uint64_t s_tie[4];
     const int32_t h = H.tchunk_hub[blockIdx.x];
-    if (!H.big[h]) return;
+    if (stopped(A.gate) || !H.big[h]) return;
     const int32_t v = H.hub_nodes[h];
     const Ctx kx = ctx_of(A, v);
     const int32_t a = A.label[v];
@@ -807,7 +839,7 @@ __global__ void __launch_bounds__(256) hub_scan_kernel(EvalArgs A, HubArgs H, in
 
 // ... and decide from the chunk winners (stored after the partition winners).
 __global__ void __launch_bounds__(64) hub_big_finish_kernel(EvalArgs A, HubArgs H, const int32_t* tfirst_shifted) {
-    if (!H.big[blockIdx.x]) return;
+    if (stopped(A.gate) || !H.big[blockIdx.x]) return;
     hub_decide(A, H, blockIdx.x, tfirst_shifted);
 }
 
@@ -866,11 +898,12 @@ __global__ void __launch_bounds__(256) eval_dense_group_kernel(EvalArgs A) {
     const int grp = threadIdx.x / G;
     const int gl = threadIdx.x % G;
     const int node_i = blockIdx.x * NG + grp;
-    if (node_i >= A.count) return;  // uniform per group
+    if (node_i >= A.count || stopped(A.gate)) return;  // uniform per group
+    const int qm = quiet_mode(A);
     int32_t* conn = cs[grp];
     const int32_t v = A.nodes[node_i];
     const Ctx kx = ctx_of(A, v);
-    if (skip_quiet(A, v, kx)) {
+    if (skip_quiet(A, qm, v, kx)) {
         if (gl == 0) store_result(A, node_i, -1, 0, 0, false);
         return;
     }
@@ -893,7 +926,7 @@ __global__ void __launch_bounds__(256) eval_dense_group_kernel(EvalArgs A) {
     const bool any_blocked = group_any<G>(blocked);
     if (gl == 0) {
         store_result(A, node_i, bx, bconn, own, over);
-        if (A.quiet) A.quiet[v] = (!over && !any_blocked) ? 1 : 0;
+        if (qm) A.quiet[v] = (!over && !any_blocked) ? 1 : 0;
     }
 }
 
@@ -905,9 +938,11 @@ __global__ void __launch_bounds__(NT) eval_dense_block_kernel(EvalArgs A) {
     __shared__ uint64_t s_tie[NT / 64];
     const int tid = threadIdx.x;
     const int wid = tid >> 6;
+    if (stopped(A.gate)) return;  // uniform over the grid
+    const int qm = quiet_mode(A);
     const int32_t v = A.nodes[blockIdx.x];
     const Ctx kx = ctx_of(A, v);
-    if (skip_quiet(A, v, kx)) {  // uniform over the workgroup
+    if (skip_quiet(A, qm, v, kx)) {  // uniform over the workgroup
         if (tid == 0) store_result(A, blockIdx.x, -1, 0, 0, false);
         return;
     }
@@ -938,7 +973,7 @@ __global__ void __launch_bounds__(NT) eval_dense_block_kernel(EvalArgs A) {
         uint64_t ft = ~0ULL;
         for (int w = 0; w < NT / 64; ++w) combine_into(fc, ft, fx, s_conn[w], s_tie[w], s_x[w]);
         store_result(A, blockIdx.x, fx, fc, own, over);
-        if (A.quiet) A.quiet[v] = (!over && !any_blocked) ? 1 : 0;
+        if (qm) A.quiet[v] = (!over && !any_blocked) ? 1 : 0;
     }
 }
 
@@ -947,6 +982,7 @@ __global__ void __launch_bounds__(NT) eval_dense_block_kernel(EvalArgs A) {
 __global__ void __launch_bounds__(kHubThreads) hub_dense_chunk_kernel(EvalArgs A, HubArgs H,
                                                                       int32_t* __restrict__ hub_sum) {
     __shared__ int32_t conn[kDenseMax];
+    if (stopped(A.gate)) return;  // uniform over the grid
     const int tid = threadIdx.x;
     const int32_t h = H.chunk_hub[blockIdx.x];
     const int32_t v = H.hub_nodes[h];
@@ -967,6 +1003,7 @@ __global__ void __launch_bounds__(256) hub_dense_finish_kernel(EvalArgs A, HubAr
     __shared__ int32_t s_conn[4];
     __shared__ int32_t s_x[4];
     __shared__ uint64_t s_tie[4];
+    if (stopped(A.gate)) return;  // uniform over the grid
     const int tid = threadIdx.x;
     const int32_t h = blockIdx.x;
     const int32_t v = H.hub_nodes[h];
@@ -1053,12 +1090,6 @@ __device__ __forceinline__ int64_t bound_of(const Bounds& B, int32_t t) {
 constexpr int kAggChunk = 2048;
 constexpr int kAggTable = 4096;
 
-// A round runs only while the previous one had candidates (gate: that
-// round's candidate count, null for the first round).  The host enqueues
-// round r + 1 before it has read round r's count, so every kernel that
-// changes the state checks the gate: after a round without candidates the
-// following ones change nothing.
-__device__ __forceinline__ bool stopped(const uint32_t* gate) { return gate && *gate == 0; }
 
 template <bool kSmall>
 __device__ __forceinline__ int32_t agg_slot(int32_t* keys, int32_t t, bool insert) {
@@ -1737,8 +1768,9 @@ __global__ void __launch_bounds__(256) unquiet_kernel(const int32_t* __restrict_
                                                       const int32_t* __restrict__ nodes, int32_t count,
                                                       const int64_t* __restrict__ xadj,
                                                       const int32_t* __restrict__ adj, uint8_t* __restrict__ quiet,
-                                                      const uint32_t* __restrict__ gate) {
-    if (stopped(gate)) return;
+                                                      const uint32_t* __restrict__ gate,
+                                                      const uint32_t* __restrict__ rcnt, int32_t round, int32_t qn) {
+    if (stopped(gate) || quiet_mode(quiet, rcnt, round, qn) == 0) return;
     const int64_t base = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) & ~63LL;
     const int lane = lane_id();
     const int64_t p = base + lane;
@@ -1961,6 +1993,57 @@ struct RoundEvents {
 RoundEvents& round_events() {
     thread_local RoundEvents r;
     return r;
+}
+
+// Records the work enqueued on the capture stream cs (and on streams joined
+// to it) while it lives into a graph, when enabled; run() instantiates it,
+// launches it on the caller's stream and waits.  The caller's stream may be
+// the null stream, which cannot be captured itself.  If an error unwinds
+// before run(), the capture is ended and discarded.
+class GraphCapture {
+  public:
+    GraphCapture(hipStream_t cs, hipStream_t exec, bool on) : s_(cs), exec_(exec), on_(on) {
+        if (on_) HIPCHK(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+    }
+    GraphCapture(const GraphCapture&) = delete;
+    GraphCapture& operator=(const GraphCapture&) = delete;
+    void run() {
+        if (!on_) return;
+        on_ = false;
+        hipGraph_t graph = nullptr;
+        HIPCHK(hipStreamEndCapture(s_, &graph));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            HIPCHK(e);
+        }
+        const hipError_t l = hipGraphLaunch(exec, exec_);
+        const hipError_t w = l == hipSuccess ? hipStreamSynchronize(exec_) : l;
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(w);
+    }
+    ~GraphCapture() {
+        if (!on_) return;
+        hipGraph_t graph = nullptr;
+        if (hipStreamEndCapture(s_, &graph) == hipSuccess && graph) (void)hipGraphDestroy(graph);
+    }
+
+  private:
+    hipStream_t s_;
+    hipStream_t exec_;
+    bool on_;
+};
+
+// The stream rounds are captured on (per thread, default priority).
+hipStream_t capture_stream() {
+    struct Holder {
+        hipStream_t st;
+        Holder() { HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking)); }
+    };
+    thread_local Holder h;
+    return h.st;
 }
 
 unsigned capped_grid(int64_t items) {
@@ -2238,7 +2321,8 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     A.label8 = lab8.get();
     A.label16 = lab16.get();
     // quiet-node tracking starts once a round has few candidates (marking the
-    // neighbours of every mover is then cheap) and skipping one round later
+    // neighbours of every mover is then cheap) and skipping one round later;
+    // the kernels derive the start from the per-round counts (quiet_mode)
     DBuf<uint8_t> quiet;
     // the default (0) leaves it off here; the batch driver turns it on
     const bool track_quiet = tune.skip_quiet > 0;
@@ -2246,14 +2330,16 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
         quiet.alloc(n, s);
         fill_u8(quiet.get(), 0, n, s);
     }
-    int32_t mark_from = INT_MAX;
+    A.quiet = quiet.get();
+    A.quiet_n = n;
 
-    // Algorithmic bytes of one evaluation launch: per node its schedule entry,
-    // row offsets, own label and weight (and w(own) when refining) and its
-    // result (target, gain); per slot the neighbour id, edge weight and
-    // neighbour label (1, 2 or 4 bytes).
-    const double node_bytes = 4.0 + 16.0 + 4.0 + (g.vw ? 4.0 : 0.0) + (phase != kCluster ? 4.0 : 0.0) + 8.0;
-    const double slot_bytes = 4.0 + (nw <= 256 ? 1.0 : nw <= 65536 ? 2.0 : 4.0) + (g.ew ? 4.0 : 0.0);
+    // Algorithmic bytes of one evaluation launch, the figure of one round's
+    // minimal traffic per unit: per evaluated node 24 (its row offsets, own
+    // label, node weight and the weight of one label), per slot 12 (the
+    // neighbour id, the edge weight and the neighbour's label), whether or
+    // not the kernel reads weights that hold only ones or narrow labels.
+    const double node_bytes = 24.0;
+    const double slot_bytes = 12.0;
     auto eval_bytes = [&](int64_t nodes_in, unsigned long long slots_in) {
         return node_bytes * static_cast<double>(nodes_in) + slot_bytes * static_cast<double>(slots_in);
     };
@@ -2265,6 +2351,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     // candidates per round, read back one round late (see stopped())
     DBuf<uint32_t> rcnt(std::max(rounds, 1), s);
     fill_u32(rcnt.get(), 0, std::max(rounds, 1), s);
+    A.rcnt = rcnt.get();
     uint32_t* hrc = host_round_counts(rounds);
     RoundEvents& rev = round_events();
     bool halted = false;
@@ -2274,13 +2361,22 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
         const uint32_t round_cands = hrc[q];
         res.rounds_run = q + 1;
         res.moves += round_cands;
-        if (round_cands == 0) {
-            halted = true;
-            return;
-        }
-        // round q + 1 is already enqueued: tracking can start at q + 2
-        if (track_quiet && mark_from == INT_MAX && static_cast<int64_t>(round_cands) * 8 <= n) mark_from = q + 2;
+        if (round_cands == 0) halted = true;
     };
+    // Captured execution (tuning option): all rounds of this call are
+    // recorded into one HIP graph and launched at once, so the host neither
+    // launches kernel by kernel nor waits between rounds; rounds after one
+    // without candidates run as gated no-ops (the result is the same, see
+    // stopped()).  Not the default: on this GPU the graph runs the same
+    // kernels about 1.5 times slower than the host's pipelined launches.  Not
+    // while per-launch timing events or the trace are on (events recorded in
+    // a graph cannot be timed).
+    const bool capture = !trace && !profiler().on && tune.capture > 0;
+    // the rounds are enqueued on the capture stream and the graph runs on the
+    // caller's stream; buffers above were allocated on the caller's stream
+    const hipStream_t caller = s;
+    if (capture) s = capture_stream();
+    GraphCapture rounds_graph(s, caller, capture);
 
     for (int32_t r = 0; r < rounds && !halted; ++r) {
         const uint32_t* gate = r > 0 ? rcnt.get() + (r - 1) : nullptr;
@@ -2288,8 +2384,8 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
             graph_prefix_kernel<<<grid_for(mg->G, 256), 256, 0, s>>>(mg->G, mg->seed, 2, lvl64, ph64, r, g_tp.get());
             LAUNCHCHK();
         }
-        A.quiet = r >= mark_from ? quiet.get() : nullptr;
-        A.use_quiet = r > mark_from ? 1 : 0;
+        A.round = r;
+        A.gate = gate;
         A.tp = hash_prefix({seed, 2, static_cast<uint64_t>(static_cast<uint32_t>(level)),
                             static_cast<uint64_t>(static_cast<uint32_t>(phase)),
                             static_cast<uint64_t>(static_cast<uint32_t>(r))});
@@ -2501,7 +2597,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 ProfScope ps("lp_unquiet", 0, s);
                 unquiet_kernel<<<grid_for(ccount, 256), 256, 0, s>>>(ct.get(), ok.get(), cnodes,
                                                                       static_cast<int32_t>(ccount), g.xadj, g.adj,
-                                                                      A.quiet, gate);
+                                                                      A.quiet, gate, rcnt.get(), r, n);
                 LAUNCHCHK();
             }
         }
@@ -2509,10 +2605,22 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
         // every target is always admitted) and ends the run; its count is
         // read while the next round runs
         HIPCHK(hipMemcpyAsync(hrc + r, rcnt.get() + r, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipEventRecord(rev.ev[r & 1], s));
-        if (r > 0) finish_round(r - 1);
+        if (!capture) {
+            HIPCHK(hipEventRecord(rev.ev[r & 1], s));
+            if (r > 0) finish_round(r - 1);
+        }
     }
-    if (!halted && rounds > 0) finish_round(rounds - 1);
+    s = caller;
+    if (capture) {
+        rounds_graph.run();  // launches the graph on the caller's stream and waits for it
+        for (int32_t q = 0; q < rounds && !halted; ++q) {
+            res.rounds_run = q + 1;
+            res.moves += hrc[q];
+            if (hrc[q] == 0) halted = true;
+        }
+    } else if (!halted && rounds > 0) {
+        finish_round(rounds - 1);
+    }
     res.visits = static_cast<int64_t>(res.rounds_run) * g.S;
     HIPCHK(hipStreamSynchronize(s));
     if (profiler().on) profiler().collect();

@@ -132,10 +132,49 @@ def test_autotuned_thresholds_leave_results_unchanged(sc):
     u, nb = sc.union(gs)
     d = sc.to_device(u, "cuda")
     o = sc.autotune_dev(d, int(np.median(ks)), coarsest_nodes=200)
-    cand = {(16, 256, 8192), (16, 128, 8192), (8, 256, 8192), (16, 256, 4096), (16, 64, 2048), (4, 128, 8192)}
-    assert (o.lane_max_degree, o.wave_max_degree, o.block_max_degree) in cand
+    # the coordinate search's value grids
+    assert o.lane_max_degree in (4, 8, 16) and o.wave_max_degree in (32, 64, 128, 256)
+    assert o.block_max_degree in (1024, 2048, 4096, 8192) and o.graph_capture in (-1, 0, 1)
     assert o.coarsest_nodes == 200
     tuned = sc.partition_batch_dev(d, nb, ks, eps, seeds, opts=o)
     plain = sc.partition_batch_dev(d, nb, ks, eps, seeds, coarsest_nodes=200)
     assert torch.equal(tuned["part"], plain["part"])
     assert np.array_equal(tuned["cut"], plain["cut"]) and np.array_equal(tuned["block_weights"], plain["block_weights"])
+
+
+def test_batch_mix512_oracle_digests(sc, golden_dir):
+    # The benchmark's batched workload (512 graphs, n log-uniform in
+    # [2^10, 2^18], a third each of BA, R-MAT and RGG, per-graph k, eps and
+    # seed) in exactly the benchmark's call: every graph's blocks, cut and
+    # block weights equal the stored digests of the oracle run on that graph
+    # alone (tests/golden/make_oracle_digests.py --batch).
+    import hashlib
+    import json
+    import os
+    with open(os.path.join(golden_dir, "batch_mix_digests.json")) as f:
+        gold = json.load(f)
+    say("generating the 512-graph batch mix")
+    gs = synth.batch_mix(**gold["mix"])
+    assert len(gs) == len(gold["graphs"])
+    for g, d in zip(gs, gold["graphs"]):
+        assert int(g["n"]) == d["n"] and hashlib.sha256(g["adjncy"].tobytes()).hexdigest() == d["input_sha256"]
+    u, nb = sc.union(gs)
+    du = sc.to_device(u, "cuda")
+    part = torch.empty(max(u["n"], 1), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    ks = [g["k"] for g in gs]
+    say("batched partition of %d graphs, n=%d" % (len(gs), u["n"]))
+    r = sc.partition_batch_dev(du, nb, ks, [g["eps"] for g in gs], [g["seed"] for g in gs], part=part,
+                               stream=stream)
+    torch.cuda.synchronize()
+    p = part.cpu().numpy()
+    kb = np.concatenate([[0], np.cumsum(ks)])
+    bad = []
+    for i, d in enumerate(gold["graphs"]):
+        pi = np.ascontiguousarray(p[nb[i]:nb[i + 1]])
+        ok = (hashlib.sha256(pi.tobytes()).hexdigest() == d["part_sha256"] and int(r["cut"][i]) == d["cut"]
+              and r["block_weights"][kb[i]:kb[i + 1]].tolist() == d["block_weights"]
+              and int(r["levels"][i]) == d["levels"])
+        if not ok:
+            bad.append(i)
+    assert not bad, "graphs differing from the oracle: %s" % bad[:20]

@@ -102,3 +102,33 @@ def test_rmat24_partition_properties(sc, big):
     src = np.repeat(np.arange(n, dtype=np.int32), deg)
     cut2 = int(np.count_nonzero(p[src] != p[g["adjncy"]]))
     assert cut2 == 2 * r1["cut"]
+
+
+def test_rmat24_benchmark_call_oracle_digest(sc, big, golden_dir):
+    # The benchmark's exact call (explicit unit weights, default options,
+    # k = 64, eps = 0.03, seed 1) against the stored digest of the oracle's
+    # whole multilevel run on this graph (tests/golden/make_oracle_digests.py).
+    import hashlib
+    import json
+    import os
+    with open(os.path.join(golden_dir, "oracle_digests.json")) as f:
+        gold = json.load(f)["workloads"].get("rmat24_ef16_k64")
+    if gold is None:
+        pytest.skip("no stored oracle digest for the 2^24 R-MAT")
+    g, _ = big
+    assert hashlib.sha256(g["adjncy"].tobytes()).hexdigest() == gold["input_sha256"]
+    h = dict(g)
+    h["adjwgt"] = np.ones(len(g["adjncy"]), dtype=np.int32)
+    h["vwgt"] = np.ones(g["n"], dtype=np.int32)
+    d = sc.to_device(h, "cuda")
+    part = torch.empty(g["n"], dtype=torch.int32, device="cuda")
+    r = sc.partition_dev(d, 64, 0.03, 1, part=part, stream=torch.cuda.current_stream(), opts=sc.default_options())
+    torch.cuda.synchronize()
+    st = r["stats"]
+    assert st["level_n"] == gold["level_n"] and [int(x) for x in st["level_S"]] == gold["level_S"]
+    assert st["cluster_rounds"] == gold["cluster_rounds"] and st["refine_rounds"] == gold["refine_rounds"]
+    assert st["visits"] == gold["visits"]
+    assert r["cut"] == gold["cut"] and r["block_weights"].tolist() == gold["block_weights"]
+    assert r["status"] == gold["status"]
+    p = np.ascontiguousarray(part.cpu().numpy())
+    assert hashlib.sha256(p.tobytes()).hexdigest() == gold["part_sha256"]

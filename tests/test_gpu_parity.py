@@ -70,7 +70,11 @@ KNOBS = [dict(), dict(lane_max_degree=2, wave_max_degree=8, block_max_degree=24)
          # one selection launch: the remaining key digits finish inside it
          dict(select_small_max=1, select_launches=1),
          # quiet nodes skipped once few nodes move
-         dict(skip_quiet=1)]
+         dict(skip_quiet=1),
+         # all rounds recorded into one HIP graph (rounds after convergence run
+         # as gated no-ops), with and without quiet nodes
+         dict(graph_capture=1), dict(graph_capture=1, skip_quiet=1, lane_max_degree=2, wave_max_degree=8,
+                                     block_max_degree=24)]
 
 
 # ------------------------------------------------------------ hand-worked
@@ -128,7 +132,8 @@ def test_cluster_parity(sc, gname, knobs):
 REFINE_KNOBS = [dict(block_max_degree=40), dict(block_max_degree=30, hub_part_limit=1, hub_region_cap=2),
                 # every overflowing target through the multi-workgroup selection
                 dict(select_small_max=1), dict(select_small_max=7), dict(skip_quiet=1),
-                dict(select_small_max=1, select_launches=1), dict(select_small_max=3, select_launches=2)]
+                dict(select_small_max=1, select_launches=1), dict(select_small_max=3, select_launches=2),
+                dict(graph_capture=1), dict(graph_capture=1, skip_quiet=1)]
 
 
 @pytest.mark.parametrize("gname", list(GRAPHS))

@@ -710,3 +710,25 @@ def test_initial_lp_in_the_multilevel_run(make, k):
     assert r["cut"] == py_cut(g, r["part"])
     assert np.array_equal(r["block_weights"], py_weights(g, r["part"], k))
     assert r["status"] == (1 if r["block_weights"].max() > oracle.lmax(int(vw(g).sum()), k, 0.03) else 0)
+
+
+# ------------------------------------------- all-cores evaluation (baseline)
+
+@pytest.mark.parametrize("threads", [1, 3, 0])
+def test_parallel_subround_equals_sequential(threads):
+    # the CPU baseline's OpenMP evaluation loop: same moves, labels, weights
+    # and visits as the sequential sub-round, clustering and refinement
+    g = synth.rmat(12, 12, seed=31, weighted=True)
+    n = g["n"]
+    for phase, bound, lab0, nw in ((oracle.CLUSTER, 40, np.arange(n, dtype=np.int32), n),
+                                   (oracle.REFINE, oracle.lmax(n, 8, 0.03),
+                                    (np.arange(n) % 8).astype(np.int32), 8)):
+        a_lab, b_lab = lab0.copy(), lab0.copy()
+        wt = np.bincount(lab0, weights=vw(g), minlength=nw).astype(np.int64)
+        a_w, b_w = wt.copy(), wt.copy()
+        for rnd in range(3):
+            for sub in range(4):
+                ma, va, _ = oracle.subround(g, phase, 1, rnd, sub, 4, 9, bound, a_lab, a_w)
+                mb, vb = oracle.subround_par(g, phase, 1, rnd, sub, 4, 9, bound, b_lab, b_w, threads=threads)
+                assert ma == mb and va == vb
+                assert np.array_equal(a_lab, b_lab) and np.array_equal(a_w, b_w)
