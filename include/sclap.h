@@ -241,6 +241,20 @@ int sclap_cut_dev(const sclap_graph* g, const int32_t* part, int32_t k, int64_t*
                   void* stream);
 
 /*
+ * sclap_cut_dev without device allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc): same arguments, results and errors as
+ * sclap_cut_dev, but every temporary lives in a fixed 16 MiB workspace that
+ * the library image holds on each device it runs on (until the process
+ * ends).  Limits: k <= 65536 and at most 3,932,159 tiles of 2048 adjacency
+ * slots (about 8 * 10^9 slots); larger inputs return SCLAP_ERR_INVALID
+ * before any work.  The call allocates nothing; calls that overlap on one
+ * device share the workspace and race (serialise them, e.g. on one stream).
+ */
+int sclap_cut_dev_noalloc(const sclap_graph* g, const int32_t* part, int32_t k, int64_t* cut, int64_t* block_w,
+                          void* stream);
+
+/*
  * Host initial partition of a (coarsest) graph, the plain routine used in
  * place of the paper's evolutionary algorithm (Section 4.5): greedy
  * breadth-first growing of blocks 0..k-2 up to T = ceil(c(V)/k) each, then

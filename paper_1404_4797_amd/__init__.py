@@ -31,7 +31,7 @@ EXPORTS = [
     "sclap_contract", "sclap_contract_dev", "sclap_graph_free",
     "sclap_project", "sclap_project_dev",
     "sclap_refine", "sclap_refine_dev",
-    "sclap_cut", "sclap_cut_dev",
+    "sclap_cut", "sclap_cut_dev", "sclap_cut_dev_noalloc",
     "sclap_initial_partition",
     "sclap_partition", "sclap_partition_dev",
     "sclap_partition_batch", "sclap_partition_batch_dev",
@@ -142,6 +142,7 @@ def load():
         "sclap_refine_dev": (ctypes.c_int, [G, i32, i64, i32, u64, i32, O, vp, vp, vp]),
         "sclap_cut": (ctypes.c_int, [G, vp, i32, vp, vp]),
         "sclap_cut_dev": (ctypes.c_int, [G, vp, i32, vp, vp, vp]),
+        "sclap_cut_dev_noalloc": (ctypes.c_int, [G, vp, i32, vp, vp, vp]),
         "sclap_initial_partition": (ctypes.c_int, [G, i32, vp]),
         "sclap_partition": (ctypes.c_int, [G, i32, dbl, u64, O, vp, vp, vp, ST]),
         "sclap_partition_dev": (ctypes.c_int, [G, i32, dbl, u64, O, vp, vp, vp, ST, vp]),
@@ -427,6 +428,16 @@ def cut_dev(d, part, k, stream=None):
     c = ctypes.c_int64(0)
     bw = np.zeros(k, dtype=np.int64)
     _check(load().sclap_cut_dev(dg.ref, _t_ptr(part), k, ctypes.addressof(c), bw.ctypes.data, _stream(stream)))
+    return c.value, bw
+
+
+def cut_dev_noalloc(d, part, k, stream=None):
+    """As cut_dev, through the entry point that allocates no device memory."""
+    dg = _DevGraph(d)
+    c = ctypes.c_int64(0)
+    bw = np.zeros(k, dtype=np.int64)
+    _check(load().sclap_cut_dev_noalloc(dg.ref, _t_ptr(part), k, ctypes.addressof(c), bw.ctypes.data,
+                                        _stream(stream)))
     return c.value, bw
 
 

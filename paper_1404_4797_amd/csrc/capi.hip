@@ -443,6 +443,18 @@ int sclap_cut_dev(const sclap_graph* g, const int32_t* part, int32_t k, int64_t*
     });
 }
 
+int sclap_cut_dev_noalloc(const sclap_graph* g, const int32_t* part, int32_t k, int64_t* cut, int64_t* block_w,
+                          void* stream) {
+    return guarded([&] {
+        hipStream_t s = as_stream(stream);
+        if (k < 1 || !cut || !block_w) fail(SCLAP_ERR_INVALID, "bad k or NULL output");
+        const DevGraph d = dev_view(g, s);
+        if (d.n > 0 && !part) fail(SCLAP_ERR_INVALID, "part is NULL");
+        cut_and_weights_noalloc(d, part, k, cut, block_w, s);
+        return SCLAP_OK;
+    });
+}
+
 int sclap_cut(const sclap_graph* g, const int32_t* part, int32_t k, int64_t* cut, int64_t* block_w) {
     return guarded([&] {
         hipStream_t s = nullptr;

@@ -2,6 +2,8 @@
 // gfx950 (contraction is in contract.hip).  Slot-parallel kernels use the
 // slot tiles of tiles.hpp.
 #include <climits>
+#include <mutex>
+#include <string>
 
 #include "graph_ops.hpp"
 #include "sclap.h"
@@ -214,6 +216,85 @@ void cut_and_weights(const DevGraph& g, const int32_t* part, int32_t k, int64_t*
     HIPCHK(hipStreamSynchronize(s));
     *cut = static_cast<int64_t>(h[0] / 2);
     for (int32_t b = 0; b < k; ++b) bw[b] = static_cast<int64_t>(h[1 + b]);
+}
+
+// ------------------------------------------- cut without device allocation
+//
+// Workspace of cut_and_weights_noalloc: a fixed array in the library's
+// device image (every device the library runs on holds its own copy until
+// the process ends).  Layout: the cut and up to kNoAllocMaxK block weight
+// accumulators (u64), the range flag, then from kNoAllocAccBytes the first
+// row of every slot tile (int32).  Calls that overlap on one device share
+// it and race; each call clears the accumulators and the flag itself.
+
+namespace {
+
+constexpr size_t kNoAllocBytes = size_t(16) << 20;
+constexpr int32_t kNoAllocMaxK = 65536;
+constexpr size_t kNoAllocAccBytes = size_t(1) << 20;  // 8 * (1 + kNoAllocMaxK) + 4 fits
+constexpr int64_t kNoAllocMaxTiles = static_cast<int64_t>((kNoAllocBytes - kNoAllocAccBytes) / sizeof(int32_t)) - 1;
+constexpr int kNoAllocDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoAllocDevices] = {};
+
+// Device address of this device's copy of `scratch`, looked up once per
+// device (the array's name is only a host-side handle).
+unsigned char* noalloc_scratch() {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocDevices) fail(SCLAP_ERR_INVALID, "device index beyond the workspace table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) fail(SCLAP_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    return static_cast<unsigned char*>(g_scratch_ptr[dev]);
+}
+
+}  // namespace
+
+void cut_and_weights_noalloc(const DevGraph& g, const int32_t* part, int32_t k, int64_t* cut, int64_t* bw,
+                             hipStream_t s) {
+    const int64_t ntiles = g.S > 0 ? (g.S + kTile - 1) / kTile : 0;
+    if (k > kNoAllocMaxK) fail(SCLAP_ERR_INVALID, "k exceeds the no-allocation workspace (at most 65536 blocks)");
+    if (ntiles > kNoAllocMaxTiles)
+        fail(SCLAP_ERR_INVALID, "graph exceeds the no-allocation workspace (at most 3,932,159 tiles of 2048 slots)");
+    unsigned char* ws = noalloc_scratch();
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(ws);
+    uint32_t* flag = reinterpret_cast<uint32_t*>(ws + sizeof(unsigned long long) * (1 + static_cast<size_t>(kNoAllocMaxK)));
+    int32_t* trow = reinterpret_cast<int32_t*>(ws + kNoAllocAccBytes);
+    // cleared by kernels (no memset node if a caller captures the call)
+    fill_u32(reinterpret_cast<uint32_t*>(acc), 0, 2 * (1 + static_cast<int64_t>(k)), s);
+    fill_u32(flag, 0, 1, s);
+    if (g.n > 0) {
+        range_kernel<<<grid_for(g.n, 256), 256, 0, s>>>(part, g.n, 0, k, flag);
+        LAUNCHCHK();
+        uint32_t bad = 0;
+        HIPCHK(hipMemcpyAsync(&bad, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (bad) fail(SCLAP_ERR_INVALID, "part value outside [0, k)");
+    }
+    if (ntiles > 0) {
+        tile_rows_kernel<<<grid_for(ntiles + 1, 256), 256, 0, s>>>(g.xadj, g.n, g.S, ntiles, trow);
+        LAUNCHCHK();
+        cut_kernel<int32_t><<<capped_tiles(g.S), kTileThreads, 0, s>>>(g.xadj, g.adj, g.ew, g.n, g.S, part, acc, trow);
+        LAUNCHCHK();
+    }
+    if (g.n > 0) {
+        block_weight_kernel<<<capped_nodes(g.n), 256, 0, s>>>(g.n, part, g.vw, k, acc + 1);
+        LAUNCHCHK();
+    }
+    unsigned long long c2 = 0;
+    HIPCHK(hipMemcpyAsync(&c2, acc, sizeof(c2), hipMemcpyDeviceToHost, s));
+    // block weights are non-negative and below 2^63: the u64 sums are the int64 values
+    HIPCHK(hipMemcpyAsync(bw, acc + 1, sizeof(int64_t) * static_cast<size_t>(k), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *cut = static_cast<int64_t>(c2 / 2);
 }
 
 // ------------------------------------------------------ gather-rate probe

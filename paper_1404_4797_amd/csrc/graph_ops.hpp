@@ -49,6 +49,12 @@ void project(int32_t n, const int32_t* C, const int32_t* coarse_part, int32_t* p
 
 // cut (host out) and block weights bw[k] (host out).
 void cut_and_weights(const DevGraph& g, const int32_t* part, int32_t k, int64_t* cut, int64_t* bw, hipStream_t s);
+// The same without allocating device memory: a fixed per-device workspace in
+// the library image (k <= 65536, at most 3,932,159 slot tiles of 2048); checks
+// part values itself.  Overlapping calls on one device race.
+void cut_and_weights_noalloc(const DevGraph& g, const int32_t* part, int32_t k, int64_t* cut, int64_t* bw,
+                             hipStream_t s);
+
 // Checks CSR structure, ranges, weights, totals and symmetry (hash test).
 // Returns 0 or a negative status.  Also reports c(V) and max c(v).
 int validate_graph(const DevGraph& g, int64_t* cV, int64_t* cmax, hipStream_t s);
