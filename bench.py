@@ -226,7 +226,8 @@ def serve_benchmark(nreq, log_lo, log_hi, fracs, slots=3, max_batch=64):
     import synth
     import paper_1404_4797_amd as sc
     t = time.time()
-    gs = synth.batch_mix(nreq, seed=7, n_lo_log2=log_lo, n_hi_log2=log_hi)
+    gs = synth.batch_mix(nreq, seed=7, n_lo_log2=log_lo, n_hi_log2=log_hi,
+                         progress=lambda i: log("serve mix: %d graphs generated" % i))
     ntot = sum(g["n"] for g in gs)
     log("serve mix: %d requests, n=%d generated in %.1fs" % (nreq, ntot, time.time() - t))
     # plain path: one graph per call, the graph already on the device
@@ -244,6 +245,8 @@ def serve_benchmark(nreq, log_lo, log_hi, fracs, slots=3, max_batch=64):
         plain_part.append(p[:g["n"]].cpu().numpy())
         plain_cut.append(r["cut"])
         del d, p
+        if (i + 1) % 200 == 0:
+            log("plain: %d of %d requests" % (i + 1, nreq))
     plain_gps = nreq / t_plain
     log("plain: %.1f graphs/s on %d requests" % (plain_gps, nreq))
     # batched path: consecutive groups of max_batch requests, one call each

@@ -175,7 +175,7 @@ def from_edges(n, edges, weights=None, vwgt=None):
             "vwgt": (np.ones(n, dtype=np.int32) if vwgt is None else np.asarray(vwgt, dtype=np.int32))}
 
 
-def batch_mix(count=512, seed=0, n_lo_log2=10, n_hi_log2=18):
+def batch_mix(count=512, seed=0, n_lo_log2=10, n_hi_log2=18, progress=None):
     """Mixed batch of graphs: a third each of BA, R-MAT and 2D RGG.
 
     Graph i: n = round(2**(lo + (hi-lo)*u)) with u uniform in [0,1);
@@ -184,6 +184,7 @@ def batch_mix(count=512, seed=0, n_lo_log2=10, n_hi_log2=18):
     near 8.  Edge weights uniform in [1, 4].  k is a power of two in [2, 64],
     eps in {0.01, 0.03, 0.05}, seed 1000 + i.
     Returns a list of dicts (graph arrays plus "k", "eps", "seed", "kind").
+    ``progress(i)``, if given, is called after every 100th graph.
     """
     key = (seed * 0x9E3779B97F4A7C15 + 0x632BE59BD9B4E019) & 0xFFFFFFFFFFFFFFFF
     out = []
@@ -211,4 +212,6 @@ def batch_mix(count=512, seed=0, n_lo_log2=10, n_hi_log2=18):
         g["eps"] = (0.01, 0.03, 0.05)[(r2 >> 8) % 3]
         g["seed"] = gseed
         out.append(g)
+        if progress is not None and (i + 1) % 100 == 0:
+            progress(i + 1)
     return out
