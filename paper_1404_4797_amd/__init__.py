@@ -36,6 +36,7 @@ EXPORTS = [
     "sclap_partition", "sclap_partition_dev",
     "sclap_partition_batch", "sclap_partition_batch_dev",
     "sclap_server_create", "sclap_server_submit", "sclap_server_poll", "sclap_server_destroy",
+    "sclap_server_plan_batch",
     "sclap_autotune_dev", "sclap_trim_memory", "sclap_initial_partition_lp_dev",
     "sclap_profile_begin", "sclap_profile_end", "sclap_profile_begin_only", "sclap_gather_probe_dev",
 ]
@@ -159,6 +160,7 @@ def load():
         "sclap_profile_begin_only": (ctypes.c_int, [ctypes.c_char_p]),
         "sclap_profile_end": (ctypes.c_int, [ctypes.POINTER(KernelStat), i32, vp]),
         "sclap_gather_probe_dev": (ctypes.c_int, [G, i32, i32, vp, vp]),
+        "sclap_server_plan_batch": (ctypes.c_int32, [vp, vp, vp, i32, i64, i32, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -610,6 +612,19 @@ def autotune_dev(d, k, stream=None, opts=None, **kw):
 
 
 # ------------------------------------------------------------------ serving
+
+def server_plan_batch(nodes, slots, footprint, free_budget, max_batch, idle=True):
+    """The server's batch-packing rule: how many of the queued requests
+    (node counts, slot counts, footprints in queue order) one batch takes."""
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+    slots = np.ascontiguousarray(slots, dtype=np.int64)
+    footprint = np.ascontiguousarray(footprint, dtype=np.int64)
+    r = load().sclap_server_plan_batch(nodes.ctypes.data, slots.ctypes.data, footprint.ctypes.data, len(nodes),
+                                       free_budget, max_batch, int(bool(idle)))
+    if r < 0:
+        raise SclapError(r, "invalid arguments")
+    return int(r)
+
 
 class Server:
     """Continuous-batching partition server on one GPU (see sclap.h).

@@ -573,6 +573,12 @@ int sclap_server_poll(sclap_server* sv, uint64_t req, int32_t timeout_ms, int32_
     return guarded([&] { return server_poll(sv, req, timeout_ms, done, part, cut, block_w, info); });
 }
 
+int32_t sclap_server_plan_batch(const int64_t* nodes, const int64_t* slots, const int64_t* footprint, int32_t count,
+                                int64_t free_budget, int32_t max_batch, int32_t idle) {
+    if (count < 0 || max_batch < 1 || (count > 0 && (!nodes || !slots || !footprint))) return SCLAP_ERR_INVALID;
+    return plan_batch(nodes, slots, footprint, count, free_budget, max_batch, idle != 0);
+}
+
 void sclap_server_destroy(sclap_server* sv) {
     guarded([&] {
         server_destroy(sv);

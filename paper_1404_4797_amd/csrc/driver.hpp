@@ -73,5 +73,9 @@ uint64_t server_submit(sclap_server* sv, const sclap_graph* g, int32_t k, double
 int server_poll(sclap_server* sv, uint64_t id, int32_t timeout_ms, int32_t* done, int32_t* part, int64_t* cut,
                 int64_t* block_w, sclap_request_info* info);
 void server_destroy(sclap_server* sv);
+// The server's batch-packing rule (see server.hip): how many of `count`
+// queued requests one batch takes.
+int32_t plan_batch(const int64_t* nodes, const int64_t* slots, const int64_t* footprint, int32_t count,
+                   int64_t free_budget, int32_t max_batch, bool idle);
 
 }  // namespace sclap

@@ -2,9 +2,10 @@
 //
 // submit() copies a request's graph into server memory and queues it.  Each
 // of `slots` worker threads owns a HIP stream; an idle worker takes the
-// longest prefix of the queue whose device-memory footprint fits the free
-// budget (at most max_batch graphs), partitions it as one batch and stores
-// each request's result.  Requests that arrive while batches run are taken
+// longest prefix of the queue that the packing rule allows (plan_batch: the
+// footprint fits the free budget, at most max_batch graphs, sizes within a
+// factor of each other, the union's node count within int32), partitions it
+// as one batch and stores each request's result.  Requests that arrive while batches run are taken
 // by the next idle worker, so their work overlaps on the device with the
 // batches already running.  A batch uses graph-local ids in every hash and
 // order, so a request's result does not depend on the requests it shares a
@@ -55,6 +56,43 @@ using RequestPtr = std::shared_ptr<Request>;
 // about 28 B per slot of contraction buffers (kept coarse ids, row entries,
 // bucket staging).
 int64_t footprint_of(int64_t n, int64_t S) { return 64 * n + 64 * S + (4LL << 20); }
+
+// Work of a request for the packing rule: nodes plus slots.
+constexpr int64_t kBatchSpread = 8;  // largest / smallest work in one batch
+
+}  // namespace
+
+// How many of the queued requests (in queue order) one batch takes: the
+// longest prefix, at most max_batch, whose summed footprint fits the free
+// budget (the first request alone is always taken when nothing else runs),
+// whose summed node count stays within int32 (batch ids are int32), and
+// whose works (nodes + slots) lie within a factor kBatchSpread of each other:
+// a batch finishes with its largest member, so small requests are not held
+// behind a much larger one, which the next idle worker takes instead.
+int32_t plan_batch(const int64_t* nodes, const int64_t* slots, const int64_t* footprint, int32_t count,
+                   int64_t free_budget, int32_t max_batch, bool idle) {
+    int32_t taken = 0;
+    int64_t bytes = 0, ntot = 0, wmin = 0, wmax = 0;
+    for (int32_t i = 0; i < count && taken < max_batch; ++i) {
+        const int64_t w = nodes[i] + slots[i];
+        if (taken == 0) {
+            if (!idle && footprint[i] > free_budget) break;
+        } else {
+            if (bytes + footprint[i] > free_budget) break;
+            if (ntot + nodes[i] > INT32_MAX) break;
+            const int64_t lo = std::min(wmin, w), hi = std::max(wmax, w);
+            if (hi > kBatchSpread * std::max<int64_t>(lo, 1)) break;
+        }
+        bytes += footprint[i];
+        ntot += nodes[i];
+        wmin = taken == 0 ? w : std::min(wmin, w);
+        wmax = taken == 0 ? w : std::max(wmax, w);
+        ++taken;
+    }
+    return taken;
+}
+
+namespace {
 
 }  // namespace
 }  // namespace sclap
@@ -174,12 +212,19 @@ void worker(sclap_server* sv) {
                 return sv->in_flight == 0 || sv->in_flight + sv->queue.front()->footprint <= sv->budget;
             });
             if (sv->stop) break;
-            while (!sv->queue.empty() && static_cast<int32_t>(batch.size()) < sv->max_batch) {
-                const RequestPtr& r = sv->queue.front();
-                const bool alone = batch.empty() && sv->in_flight == 0;
-                if (!alone && sv->in_flight + bytes + r->footprint > sv->budget) break;
-                bytes += r->footprint;
-                batch.push_back(r);
+            const int32_t look = static_cast<int32_t>(std::min<size_t>(sv->queue.size(), sv->max_batch));
+            std::vector<int64_t> qn(look), qs(look), qf(look);
+            for (int32_t i = 0; i < look; ++i) {
+                const Request& r = *sv->queue[i];
+                qn[i] = r.n;
+                qs[i] = r.n > 0 ? r.xadj[r.n] : 0;
+                qf[i] = r.footprint;
+            }
+            const int32_t take = plan_batch(qn.data(), qs.data(), qf.data(), look, sv->budget - sv->in_flight,
+                                            sv->max_batch, sv->in_flight == 0);
+            for (int32_t i = 0; i < take; ++i) {
+                bytes += sv->queue.front()->footprint;
+                batch.push_back(sv->queue.front());
                 sv->queue.pop_front();
             }
             sv->in_flight += bytes;
@@ -190,7 +235,13 @@ void worker(sclap_server* sv) {
             for (auto& r : batch) finish_error(r, SCLAP_ERR_HIP, "server stream creation failed");
         } else {
             try {
-                run_batch(sv, batch, s);
+                try {
+                    run_batch(sv, batch, s);
+                } catch (const std::exception& e) {
+                    // host failures (staging allocation, sizes) are retried alone too
+                    if (dynamic_cast<const Error*>(&e)) throw;
+                    throw Error(SCLAP_ERR_HIP, e.what());
+                }
             } catch (const Error& e) {
                 // attribute the failure: run every request of the batch alone
                 if (batch.size() == 1) {
@@ -207,8 +258,6 @@ void worker(sclap_server* sv) {
                         }
                     }
                 }
-            } catch (const std::exception& e) {
-                for (auto& r : batch) finish_error(r, SCLAP_ERR_HIP, e.what());
             }
         }
         {

@@ -163,3 +163,35 @@ def test_initial_partition_many_edgeless_nodes(k):
     g["vwgt"] = vw
     T = -(-int(vw.sum()) // k)
     assert np.array_equal(sc.initial_partition(g, k), oracle.initial_partition(g, k, T))
+
+
+# ------------------------------------------------- serving: batch packing
+
+def _plan(sc, reqs, free, max_batch=64, idle=True):
+    n = [r[0] for r in reqs]
+    S = [r[1] for r in reqs]
+    fp = [64 * a + 64 * b + (4 << 20) for a, b in reqs]
+    return sc.server_plan_batch(n, S, fp, free, max_batch, idle)
+
+
+def test_server_packing_rule():
+    sc, _ = _lib()
+    small = (1000, 8000)
+    # same-size requests: the prefix that fits max_batch and the budget
+    assert _plan(sc, [small] * 10, 1 << 40, max_batch=4) == 4
+    assert _plan(sc, [small] * 10, 1 << 40) == 10
+    fp = 64 * 1000 + 64 * 8000 + (4 << 20)
+    assert _plan(sc, [small] * 10, 3 * fp) == 3
+    # a request much larger than the batch so far ends the batch (it goes to
+    # the next batch), and so does a much smaller one after a large head
+    big = (1 << 20, 16 << 20)
+    assert _plan(sc, [small, small, big, small], 1 << 40) == 2
+    assert _plan(sc, [big, small, small], 1 << 40) == 1
+    assert _plan(sc, [(4000, 30000), small, (2000, 20000)], 1 << 40) == 3  # within a factor 8
+    # the first request is taken when nothing else runs, whatever its footprint
+    assert _plan(sc, [big], 1 << 20, idle=True) == 1
+    assert _plan(sc, [big], 1 << 20, idle=False) == 0
+    # the union's node count stays within int32
+    huge = (1 << 30, 1 << 30)
+    assert _plan(sc, [huge, huge, huge], 1 << 62) == 1
+    assert _plan(sc, [], 1 << 40) == 0
