@@ -373,10 +373,9 @@ void sclap_server_destroy(sclap_server* sv);
  * adjacency slot counts and footprints (host arrays, in queue order), one
  * batch takes the longest prefix, at most max_batch, whose summed footprint
  * fits free_budget (idle != 0: nothing else runs, so the first request is
- * taken whatever its footprint), whose summed node count stays within
- * 2^31-1, and whose works (nodes + slots) lie within a factor 8 of each
- * other, so that small requests do not wait for a much larger one in their
- * batch.  Returns the number taken, or SCLAP_ERR_INVALID.
+ * taken whatever its footprint) and whose summed node count stays within
+ * 2^31-1 (the batch's node ids are int32).  slots is read by no rule yet.
+ * Returns the number taken, or SCLAP_ERR_INVALID.
  */
 int32_t sclap_server_plan_batch(const int64_t* nodes, const int64_t* slots, const int64_t* footprint, int32_t count,
                                 int64_t free_budget, int32_t max_batch, int32_t idle);

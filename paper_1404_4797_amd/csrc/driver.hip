@@ -1459,9 +1459,11 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
         // ---- initial partition of every graph's coarsest level, on the host
         // (first cycle; later ones inherit it)
         auto t_init = Clock::now();
-        // whole levels are copied once (pinned staging), each graph reads its
-        // slice; results go to one host array per level, uploaded before the
-        // projection of the graphs that continue
+        // the slices of the graphs that end at a level are copied into one
+        // pinned staging area laid out like the whole level (runs of
+        // consecutive ending graphs in one copy each; the graphs that go on
+        // coarsening are not copied); results go to one host array per
+        // level, uploaded before the projection of the graphs that continue
         std::vector<uint8_t> ends(static_cast<size_t>(top) + 1, 0);
         for (int32_t l = 0; l <= top; ++l)
             for (size_t m = 0; m < L[l].ids.size(); ++m) mpos[L[l].ids[m]] = static_cast<int32_t>(m);
@@ -1498,10 +1500,26 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
                 h.a = reinterpret_cast<int32_t*>(base + rnd8((nl + 1) * sizeof(int64_t)));
                 h.v = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(h.a) + rnd8(static_cast<size_t>(B.g.S) * sizeof(int32_t)));
                 h.p = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(h.v) + rnd8(nl * sizeof(int32_t)));
-                HIPCHK(hipMemcpyAsync(h.x, B.g.xadj, (nl + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-                if (B.g.S > 0)
-                    HIPCHK(hipMemcpyAsync(h.a, B.g.adj, B.g.S * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-                if (B.g.vw && nl > 0) HIPCHK(hipMemcpyAsync(h.v, B.g.vw, nl * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                const size_t M = B.ids.size();
+                for (size_t m0 = 0; m0 < M;) {
+                    if (last[B.ids[m0]] != l) {
+                        ++m0;
+                        continue;
+                    }
+                    size_t m1 = m0 + 1;
+                    while (m1 < M && last[B.ids[m1]] == l) ++m1;
+                    const int64_t v0 = B.nb[m0], v1 = B.nb[m1];
+                    const int64_t e0 = B.sb[m0], e1 = B.sb[m1];
+                    HIPCHK(hipMemcpyAsync(h.x + v0, B.g.xadj + v0, (v1 - v0 + 1) * sizeof(int64_t),
+                                          hipMemcpyDeviceToHost, s));
+                    if (e1 > e0)
+                        HIPCHK(hipMemcpyAsync(h.a + e0, B.g.adj + e0, (e1 - e0) * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                              s));
+                    if (B.g.vw && v1 > v0)
+                        HIPCHK(hipMemcpyAsync(h.v + v0, B.g.vw + v0, (v1 - v0) * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                              s));
+                    m0 = m1;
+                }
                 if (!B.g.vw) h.v = nullptr;
             }
             HIPCHK(hipStreamSynchronize(s));
@@ -1545,7 +1563,19 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
                 HIPCHK(hipMemcpyAsync(part, blk_of(l), n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
             // graphs ending here: their initial partitions (the other ranges
             // are overwritten by the projection next)
-            if (ends[l] && n > 0) HIPCHK(hipMemcpyAsync(part, lh[l].p, n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            if (ends[l] && n > 0)
+                for (size_t m0 = 0; m0 < B.ids.size();) {  // runs of consecutive graphs ending here
+                    if (last[B.ids[m0]] != l) {
+                        ++m0;
+                        continue;
+                    }
+                    size_t m1 = m0 + 1;
+                    while (m1 < B.ids.size() && last[B.ids[m1]] == l) ++m1;
+                    if (B.nb[m1] > B.nb[m0])
+                        HIPCHK(hipMemcpyAsync(part + B.nb[m0], lh[l].p + B.nb[m0], (B.nb[m1] - B.nb[m0]) * sizeof(int32_t),
+                                              hipMemcpyHostToDevice, s));
+                    m0 = m1;
+                }
             if (ends_dev[l] && n > 0) {
                 std::vector<uint8_t> endg(G, 0);
                 for (size_t m = 0; m < B.ids.size(); ++m)

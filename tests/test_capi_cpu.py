@@ -182,12 +182,11 @@ def test_server_packing_rule():
     assert _plan(sc, [small] * 10, 1 << 40) == 10
     fp = 64 * 1000 + 64 * 8000 + (4 << 20)
     assert _plan(sc, [small] * 10, 3 * fp) == 3
-    # a request much larger than the batch so far ends the batch (it goes to
-    # the next batch), and so does a much smaller one after a large head
+    # sizes are mixed; the footprint decides
     big = (1 << 20, 16 << 20)
-    assert _plan(sc, [small, small, big, small], 1 << 40) == 2
-    assert _plan(sc, [big, small, small], 1 << 40) == 1
-    assert _plan(sc, [(4000, 30000), small, (2000, 20000)], 1 << 40) == 3  # within a factor 8
+    assert _plan(sc, [small, small, big, small], 1 << 40) == 4
+    bfp = 64 * (1 << 20) + 64 * (16 << 20) + (4 << 20)
+    assert _plan(sc, [small, small, big, small], 2 * fp + bfp - 1) == 2
     # the first request is taken when nothing else runs, whatever its footprint
     assert _plan(sc, [big], 1 << 20, idle=True) == 1
     assert _plan(sc, [big], 1 << 20, idle=False) == 0
