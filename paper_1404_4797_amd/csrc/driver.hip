@@ -9,6 +9,7 @@
 #include <cstring>
 #include <deque>
 #include <exception>
+#include <future>
 #include <memory>
 #include <mutex>
 #include <queue>
@@ -1524,23 +1525,49 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
             }
             HIPCHK(hipStreamSynchronize(s));
         }
+        // The host partitions run level by level, top first, on a helper
+        // thread: the device refines the top levels while the host still
+        // partitions the graphs that end lower down (most small graphs end at
+        // level 0), and the refinement of level l waits only for level l's.
         const unsigned hw = std::thread::hardware_concurrency();
-        if (!carry && !dev_ip) parallel_for(G, static_cast<int32_t>(std::min(16u, hw ? hw : 1u)), [&](int32_t g) {
-            const int32_t l = last[g];
+        const int32_t host_threads = static_cast<int32_t>(std::min(16u, hw ? hw : 1u));
+        std::vector<std::vector<int32_t>> ending(static_cast<size_t>(top) + 1);
+        if (!carry && !dev_ip)
+            for (int32_t g = 0; g < G; ++g) ending[last[g]].push_back(g);
+        std::vector<std::promise<void>> level_done(static_cast<size_t>(top) + 1);
+        std::vector<std::shared_future<void>> level_ready;
+        for (auto& pr : level_done) level_ready.push_back(pr.get_future().share());
+        auto partition_level = [&](int32_t l) {
             const BatchLevel& B = L[l];
             const LevelHost& h = lh[l];
-            const int32_t m = mpos[g];
-            const int32_t nb0 = B.nb[m];
-            const int32_t nm = B.nb[m + 1] - nb0;
-            std::vector<int64_t> x(h.x + nb0, h.x + nb0 + nm + 1);  // row ends are shared with the next graph
-            const int64_t x0 = x[0];
-            for (auto& e : x) e -= x0;
-            int32_t* a = h.a + x0;  // this graph's slots, to graph-local ids in place
-            for (int64_t j = 0; j < x[nm]; ++j) a[j] -= nb0;
-            int32_t* pp = h.p + nb0;
-            host_initial_partition(nm, x.data(), a, h.v ? h.v + nb0 : nullptr, k[g], T[g], pp,
-                                   false);  // rows of inner levels are unordered
-            for (int32_t i = 0; i < nm; ++i) pp[i] += kb[g];  // labels of the batch's block space
+            parallel_for(static_cast<int32_t>(ending[l].size()), host_threads, [&](int32_t i) {
+                const int32_t g = ending[l][i];
+                const int32_t m = mpos[g];
+                const int32_t nb0 = B.nb[m];
+                const int32_t nm = B.nb[m + 1] - nb0;
+                std::vector<int64_t> x(h.x + nb0, h.x + nb0 + nm + 1);  // row ends are shared with the next graph
+                const int64_t x0 = x[0];
+                for (auto& e : x) e -= x0;
+                int32_t* a = h.a + x0;  // this graph's slots, to graph-local ids in place
+                for (int64_t j = 0; j < x[nm]; ++j) a[j] -= nb0;
+                int32_t* pp = h.p + nb0;
+                host_initial_partition(nm, x.data(), a, h.v ? h.v + nb0 : nullptr, k[g], T[g], pp,
+                                       false);  // rows of inner levels are unordered
+                for (int32_t q = 0; q < nm; ++q) pp[q] += kb[g];  // labels of the batch's block space
+            });
+        };
+        // declared after everything the helper reads, so that an error on this
+        // thread waits for the helper before those are destroyed
+        std::future<void> host_parts = std::async(std::launch::async, [&] {
+            for (int32_t l = top; l >= 0; --l) {
+                try {
+                    if (!ending[l].empty()) partition_level(l);
+                    level_done[l].set_value();
+                } catch (...) {
+                    for (int32_t q = l; q >= 0; --q) level_done[q].set_exception(std::current_exception());
+                    return;
+                }
+            }
         });
         st->ms_initial += ms_since(t_init);
 
@@ -1563,6 +1590,11 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
                 HIPCHK(hipMemcpyAsync(part, blk_of(l), n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
             // graphs ending here: their initial partitions (the other ranges
             // are overwritten by the projection next)
+            {
+                auto t_wait = Clock::now();
+                level_ready[l].get();  // rethrows the helper's error
+                ip_ms += ms_since(t_wait);
+            }
             if (ends[l] && n > 0)
                 for (size_t m0 = 0; m0 < B.ids.size();) {  // runs of consecutive graphs ending here
                     if (last[B.ids[m0]] != l) {
