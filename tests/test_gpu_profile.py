@@ -52,3 +52,18 @@ def test_profiling_all_and_one_kernel(sc):
     sc.partition_dev(d, 8, 0.03, 2, coarsest_nodes=500)
     torch.cuda.synchronize()
     assert sc.profile_end() == {}
+
+
+def test_gather_probe(sc):
+    # the measurement helper: positive pass times for 4- and 1-byte labels,
+    # an error for other label widths, and an edgeless graph takes no time
+    g = synth.rmat(16, 16, seed=4)
+    d = sc.to_device(g, "cuda")
+    t4 = sc.gather_probe_dev(d, 4, reps=2)
+    t1 = sc.gather_probe_dev(d, 1, reps=2)
+    assert t4 > 0 and t1 > 0
+    with pytest.raises(sc.SclapError):
+        sc.gather_probe_dev(d, 2)
+    n = 100
+    e = {"n": n, "xadj": np.zeros(n + 1, dtype=np.int64), "adjncy": np.zeros(0, dtype=np.int32)}
+    assert sc.gather_probe_dev(sc.to_device(e, "cuda"), 4) == 0.0
