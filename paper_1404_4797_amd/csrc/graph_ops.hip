@@ -166,10 +166,18 @@ __global__ void __launch_bounds__(kTileThreads) validate_slots_kernel(const int6
     if (bad) atomicOr(&st->bad, bad);
 }
 
+// Flags any value outside [lo, hi) with at most one atomic per wave (a
+// per-element atomic on the one flag serialises when most values are out,
+// as in the unit-weight test of a weighted graph).
 __global__ void range_kernel(const int32_t* __restrict__ a, int64_t count, int32_t lo, int32_t hi,
                              uint32_t* __restrict__ bad) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (i < count && (a[i] < lo || a[i] >= hi)) atomicOr(bad, 1u);
+    bool b = false;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < count;
+         i += static_cast<int64_t>(gridDim.x) * 256) {
+        const int32_t x = a[i];
+        b |= x < lo || x >= hi;
+    }
+    if (__any(b) && lane_id() == 0) atomicOr(bad, 1u);
 }
 
 unsigned capped_tiles(int64_t S) {
@@ -419,7 +427,8 @@ bool all_in_range(const int32_t* a, int64_t count, int32_t lo, int32_t hi, hipSt
     if (count <= 0) return true;
     DBuf<uint32_t> bad(1, s);
     fill_u32(bad.get(), 0, 1, s);
-    range_kernel<<<grid_for(count, 256), 256, 0, s>>>(a, count, lo, hi, bad.get());
+    range_kernel<<<static_cast<unsigned>(std::min<int64_t>((count + 255) / 256, 8192)), 256, 0, s>>>(a, count, lo, hi,
+                                                                                                    bad.get());
     LAUNCHCHK();
     uint32_t h = 0;
     HIPCHK(hipMemcpyAsync(&h, bad.get(), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -507,18 +516,24 @@ __global__ void __launch_bounds__(kTileThreads) graph_cut_kernel(const int64_t* 
         const int64_t i0 = tile * kTile;
         const int64_t i1 = i0 + kTile < S ? i0 + kTile : S;
         tile_owners(xadj, trow, tile, i0, i1, owner);
+        // each lane sums its slots of the tile per graph (its graph changes
+        // at most at a graph boundary), then one atomic per wave when the
+        // wave's lanes ended in one graph
+        int32_t gc = -1;
+        unsigned long long acc = 0;
         for (int r = 0; r < kTilePer; ++r) {
             const int64_t i = i0 + r * kTileThreads + threadIdx.x;
-            const bool valid = i < i1;
-            int32_t g = 0;
-            unsigned long long val = 0;
-            if (valid) {
-                const int32_t u = owner[i - i0];
-                g = gid[u];
-                if (part[u] != part[adj[i]]) val = ew ? static_cast<unsigned long long>(ew[i]) : 1ULL;
+            if (i >= i1) break;
+            const int32_t u = owner[i - i0];
+            const int32_t g = gid[u];
+            if (g != gc) {
+                if (acc) atomicAdd(&cut[gc], acc);
+                gc = g;
+                acc = 0;
             }
-            add_by_graph(valid, g, val, cut);
+            if (part[u] != part[adj[i]]) acc += ew ? static_cast<unsigned long long>(ew[i]) : 1ULL;
         }
+        add_by_graph(gc >= 0, gc, acc, cut);
         __syncthreads();
     }
 }

@@ -1877,25 +1877,71 @@ __global__ void graph_prefix_kernel(int32_t G, const uint64_t* __restrict__ seed
     out[g] = h;
 }
 
+constexpr int kLWChunk = 2048;  // nodes per block and step of label_weights_kernel<false>
+
 template <bool kSmall>
 __global__ void __launch_bounds__(256) label_weights_kernel(int32_t n, const int32_t* __restrict__ label,
                                                             const int32_t* __restrict__ vw, int32_t* __restrict__ w,
                                                             int32_t nw) {
-    __shared__ int32_t loc[kSmall ? kSmallLabels : 1];
+    __shared__ int32_t loc[kSmallLabels];
     if (kSmall) {
         for (int j = threadIdx.x; j < nw; j += 256) loc[j] = 0;
         __syncthreads();
-    }
-    for (int32_t v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) {
-        const int32_t c = vw ? vw[v] : 1;
-        if (!c) continue;
-        if (kSmall) atomicAdd(&loc[label[v]], c);
-        else atomicAdd(&w[label[v]], c);
-    }
-    if (kSmall) {
+        for (int32_t v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) {
+            const int32_t c = vw ? vw[v] : 1;
+            if (c) atomicAdd(&loc[label[v]], c);
+        }
         __syncthreads();
         for (int j = threadIdx.x; j < nw; j += 256)
             if (loc[j]) atomicAdd(&w[j], loc[j]);
+        return;
+    }
+    // Large label spaces, kLWChunk consecutive nodes per block at a time: when
+    // their labels span fewer than kSmallLabels ids (the blocks of the few
+    // graphs a chunk of a batch covers, or a run of singleton clusters), they
+    // are summed in LDS first, so a label many nodes share costs one global
+    // atomic per chunk; otherwise every node adds to HBM directly.
+    constexpr int R = kLWChunk / 256;
+    __shared__ int32_t s_lo[4], s_hi[4];
+    for (int64_t base = static_cast<int64_t>(blockIdx.x) * kLWChunk; base < n;
+         base += static_cast<int64_t>(gridDim.x) * kLWChunk) {
+        int32_t lab[R], cw[R];
+        int32_t lo = INT_MAX, hi = INT_MIN;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t v = base + r * 256 + threadIdx.x;
+            lab[r] = v < n ? label[v] : -1;
+            cw[r] = v < n ? (vw ? vw[v] : 1) : 0;
+            if (lab[r] >= 0) {
+                lo = lab[r] < lo ? lab[r] : lo;
+                hi = lab[r] > hi ? lab[r] : hi;
+            }
+        }
+        lo = wave_min(lo);
+        hi = wave_max(hi);
+        if (lane_id() == 0) {
+            s_lo[threadIdx.x >> 6] = lo;
+            s_hi[threadIdx.x >> 6] = hi;
+        }
+        __syncthreads();
+        lo = min(min(s_lo[0], s_lo[1]), min(s_lo[2], s_lo[3]));
+        hi = max(max(s_hi[0], s_hi[1]), max(s_hi[2], s_hi[3]));
+        const int64_t span = static_cast<int64_t>(hi) - lo + 1;
+        if (span > 0 && span <= kSmallLabels) {
+            for (int j = threadIdx.x; j < span; j += 256) loc[j] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (cw[r]) atomicAdd(&loc[lab[r] - lo], cw[r]);
+            __syncthreads();
+            for (int j = threadIdx.x; j < span; j += 256)
+                if (loc[j]) atomicAdd(&w[lo + j], loc[j]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (cw[r]) atomicAdd(&w[lab[r]], cw[r]);
+        }
+        __syncthreads();  // s_lo, s_hi and loc are reused by the next chunk
     }
 }
 
@@ -2059,7 +2105,9 @@ void label_weights(const DevGraph& g, const int32_t* label, int32_t* w, int32_t 
         if (nw <= kSmallLabels)
             label_weights_kernel<true><<<capped_grid(g.n), 256, 0, s>>>(g.n, label, g.vw, w, nw);
         else
-            label_weights_kernel<false><<<grid_for(g.n, 256), 256, 0, s>>>(g.n, label, g.vw, w, nw);
+            label_weights_kernel<false><<<static_cast<unsigned>(std::min<int64_t>((g.n + kLWChunk - 1) / kLWChunk,
+                                                                                  kMaxBlocks)),
+                                          256, 0, s>>>(g.n, label, g.vw, w, nw);
         LAUNCHCHK();
     }
 }
