@@ -7,12 +7,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <deque>
 #include <exception>
 #include <future>
 #include <memory>
 #include <mutex>
-#include <queue>
 #include <thread>
 #include <utility>
 #include <vector>
@@ -254,10 +252,10 @@ void untaken_masks_scalar(const int32_t* row, size_t nb, const uint64_t* taken, 
 // lightest block (lowest id on ties).  Weights fit 31 bits (c(V) <= 2^31-1).
 
 void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, const int32_t* vw, int32_t k,
-                            int64_t T, int32_t* part, bool rows_sorted, bool adj_ranked) {
+                            int64_t T, int32_t* part, bool rows_sorted, bool adj_ranked, int32_t threads) {
     auto T0 = Clock::now();
     const unsigned hw = std::thread::hardware_concurrency();
-    const int32_t nthr = static_cast<int32_t>(std::min(16u, hw ? hw : 1u));
+    const int32_t nthr = threads > 0 ? threads : static_cast<int32_t>(std::min(16u, hw ? hw : 1u));
     // id ranges of whole 64-node words, one task each
     const size_t words = (static_cast<size_t>(n) + 63) / 64;
     const int32_t ntask = n < (1 << 20) ? 1 : 4 * nthr;
@@ -360,6 +358,7 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
     static const bool use_avx2 = __builtin_cpu_supports("avx2");
     std::vector<uint8_t> masks;
     std::vector<int32_t> nb;
+    std::vector<uint64_t> rowbits;  // scratch bitmap of the core for ordering unsorted rows
     // core nodes in the order blocks take them; each search's queue is the
     // tail of this list that it appended (a node is queued at most once)
     std::vector<int32_t> order(static_cast<size_t>(ncore) + 1);
@@ -396,8 +395,28 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
                 const int32_t* row = cadj + cx[u];
                 const int32_t* row_end = cadj + cx[u + 1];
                 if (!rows_sorted && !std::is_sorted(row, row_end)) {
-                    nb.assign(row, row_end);
-                    std::sort(nb.begin(), nb.end());
+                    // ascending copy of the row: through a bitmap of the core
+                    // when the row is dense in its id range (equal ids
+                    // collapse, which the walk below would skip anyway),
+                    // else by sorting
+                    const auto mm = std::minmax_element(row, row_end);
+                    const int32_t lo = *mm.first, hi = *mm.second;
+                    const size_t d = static_cast<size_t>(row_end - row);
+                    nb.clear();
+                    if (lo >= 0 && hi < ncore &&
+                        static_cast<size_t>((hi >> 6) - (lo >> 6) + 1) <= 4 * d) {
+                        if (rowbits.empty()) rowbits.assign((static_cast<size_t>(ncore) + 63) / 64, 0);
+                        for (const int32_t* it = row; it != row_end; ++it)
+                            rowbits[static_cast<size_t>(*it) >> 6] |= 1ULL << (*it & 63);
+                        for (int32_t wd = lo >> 6; wd <= (hi >> 6); ++wd) {
+                            for (uint64_t bits = rowbits[wd]; bits; bits &= bits - 1)
+                                nb.push_back(wd * 64 + __builtin_ctzll(bits));
+                            rowbits[wd] = 0;
+                        }
+                    } else {
+                        nb.assign(row, row_end);
+                        std::sort(nb.begin(), nb.end());
+                    }
                     row = nb.data();
                     row_end = nb.data() + nb.size();
                 }
@@ -616,7 +635,7 @@ void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, 
         std::vector<size_t> pstart(plans.size() + 1, 0);
         for (size_t q = 0; q < plans.size(); ++q) pstart[q + 1] = pstart[q] + plans[q].take;
         const size_t total = pstart.back();
-        const int32_t nt = total < (1u << 16) ? 1 : 4 * nthr;
+        const int32_t nt = total < (1u << 20) ? 1 : 4 * nthr;  // starting threads costs more below
         parallel_for(nt, nthr, [&](int32_t t) {
             const size_t a0 = total * static_cast<size_t>(t) / nt, a1 = total * static_cast<size_t>(t + 1) / nt;
             size_t q = static_cast<size_t>(std::upper_bound(pstart.begin(), pstart.end(), a0) - pstart.begin()) - 1;
@@ -1026,6 +1045,180 @@ void upload_vec(DBuf<T>& d, const std::vector<T>& h, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(d.get(), h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
+// Host initial partitions of a batch, overlapped with coarsening.  As soon
+// as coarsening decides which graphs end at a level, their slices are packed
+// on the device (neighbours as core ranks) and copied to pinned host memory,
+// one copy per array, and a task of its own partitions them (one graph per
+// host thread, largest first) while the device coarsens the levels below;
+// the levels decided last (usually two at the end of coarsening) run side by
+// side.  Refinement of a level waits only for that level's partitions, which
+// go back in one copy and are scattered into the level's layout on the
+// device.
+class HostIpPipeline {
+  public:
+    // stage_bytes bounds the packed levels together (every graph ends at one
+    // level, no larger there than at level 0)
+    HostIpPipeline(size_t stage_bytes, const int32_t* k, const std::vector<int64_t>& T, const std::vector<int32_t>& kb,
+                   hipStream_t s)
+        : stage_(stage_bytes), cap_(stage_bytes), k_(k), T_(T), kb_(kb), s_(s) {
+        const unsigned hw = std::thread::hardware_concurrency();
+        threads_ = static_cast<int32_t>(std::min(16u, hw ? hw : 1u));
+        lv_.resize(static_cast<size_t>(SCLAP_MAX_LEVELS) + 1);
+        HIPCHK(hipStreamCreateWithFlags(&cs_, hipStreamNonBlocking));
+    }
+    HostIpPipeline(const HostIpPipeline&) = delete;
+    HostIpPipeline& operator=(const HostIpPipeline&) = delete;
+    ~HostIpPipeline() {
+        closed_.store(true);
+        for (auto& L : lv_)
+            if (L && L->task.valid()) L->task.wait();
+        (void)hipStreamSynchronize(cs_);  // copies still reading the packed levels
+        for (auto& L : lv_)
+            if (L && L->ev) (void)hipEventDestroy(L->ev);
+        (void)hipStreamDestroy(cs_);
+    }
+
+    // The members `members` (indices into B) end at level l.
+    void stage(int32_t l, const BatchLevel& B, const std::vector<int32_t>& members) {
+        std::unique_ptr<Level> lv(new Level);
+        Level& L = *lv;
+        L.ready = L.done.get_future().share();
+        const int32_t Mk = static_cast<int32_t>(members.size());
+        L.nnb.push_back(0);
+        L.nsb.push_back(0);
+        std::vector<int64_t> osb;
+        for (int32_t m : members) {
+            L.gids.push_back(B.ids[m]);
+            L.onb.push_back(B.nb[m]);
+            osb.push_back(B.sb[m]);
+            L.nnb.push_back(L.nnb.back() + (B.nb[m + 1] - B.nb[m]));
+            L.nsb.push_back(L.nsb.back() + (B.sb[m + 1] - B.sb[m]));
+        }
+        L.n = L.nnb[Mk];
+        const int64_t S = L.nsb[Mk];
+        if (L.n > 0) {
+            L.dx.alloc(static_cast<size_t>(L.n) + Mk, s_);
+            L.da.alloc(static_cast<size_t>(std::max<int64_t>(S, 1)), s_);
+            if (B.g.vw) L.dv.alloc(L.n, s_);
+            pack_members_for_host(B.g, L.onb, osb, L.nnb, L.nsb, L.dx.get(), L.da.get(), L.dv.get(), s_);  // syncs
+            L.x = take<int64_t>(static_cast<size_t>(L.n) + Mk);
+            L.a = take<int32_t>(static_cast<size_t>(S));
+            L.v = B.g.vw ? take<int32_t>(L.n) : nullptr;
+            L.p = take<int32_t>(L.n);
+            // on a stream of their own, beside the coarsening of the next level
+            HIPCHK(hipMemcpyAsync(L.x, L.dx.get(), (static_cast<size_t>(L.n) + Mk) * sizeof(int64_t),
+                                  hipMemcpyDeviceToHost, cs_));
+            if (S > 0)
+                HIPCHK(hipMemcpyAsync(L.a, L.da.get(), static_cast<size_t>(S) * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                      cs_));
+            if (L.v) HIPCHK(hipMemcpyAsync(L.v, L.dv.get(), L.n * sizeof(int32_t), hipMemcpyDeviceToHost, cs_));
+            HIPCHK(hipEventCreateWithFlags(&L.ev, hipEventDisableTiming));
+            HIPCHK(hipEventRecord(L.ev, cs_));
+            // where the partitions go back: nnb | onb on the device
+            L.dnb.alloc(2 * static_cast<size_t>(Mk) + 1, s_);
+            HIPCHK(hipMemcpyAsync(L.dnb.get(), L.nnb.data(), (Mk + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s_));
+            HIPCHK(hipMemcpyAsync(L.dnb.get() + Mk + 1, L.onb.data(), Mk * sizeof(int32_t), hipMemcpyHostToDevice,
+                                  s_));
+        }
+        L.t_staged = ms_since(t0_);
+        Level* lp = lv.get();
+        lv_[l] = std::move(lv);
+        lp->task = std::async(std::launch::async, [this, lp, l] { work(*lp, l); });
+    }
+
+    // Waits for level l's partitions and writes them into part (the level's
+    // layout, labels in the batch's block space).  Returns the ms waited.
+    double finish(int32_t l, int32_t* part) {
+        Level* L = lv_[l].get();  // staged by this thread
+        if (!L) fail(SCLAP_ERR_INVALID, "batch level without initial partitions");
+        const auto t = Clock::now();
+        L->ready.get();  // rethrows the helper's error
+        const double waited = ms_since(t);
+        if (L->n > 0) {
+            L->dp.alloc(L->n, s_);
+            HIPCHK(hipMemcpyAsync(L->dp.get(), L->p, L->n * sizeof(int32_t), hipMemcpyHostToDevice, s_));
+            unpack_members(L->dp.get(), L->n, static_cast<int32_t>(L->onb.size()), L->dnb.get(), part, s_);
+        }
+        return waited;
+    }
+
+  private:
+    struct Level {
+        int32_t n = 0;
+        std::vector<int32_t> gids, onb, nnb;  // batch index, old and packed node base of each member
+        std::vector<int64_t> nsb;             // packed slot base
+        DBuf<int64_t> dx;                     // packed on the device
+        DBuf<int32_t> da, dv, dnb, dp;
+        int64_t* x = nullptr;  // pinned host copies
+        int32_t *a = nullptr, *v = nullptr, *p = nullptr;
+        hipEvent_t ev = nullptr;  // the copies to the host have landed
+        double t_staged = 0, t_start = 0, t_copied = 0, t_done = 0;  // ms since the pipeline started
+        std::promise<void> done;
+        std::shared_future<void> ready;
+        std::future<void> task;  // the host partitioning of this level
+    };
+
+    template <typename T>
+    T* take(size_t count) {
+        const size_t bytes = (count * sizeof(T) + 7) & ~static_cast<size_t>(7);
+        if (used_ + bytes > cap_) fail(SCLAP_ERR_INVALID, "batch staging area too small");
+        T* p = reinterpret_cast<T*>(stage_.data() + used_);
+        used_ += bytes;
+        return p;
+    }
+
+    void work(Level& L, int32_t l) {
+        try {
+            L.t_start = ms_since(t0_);
+            if (L.n > 0 && !closed_.load()) {
+                HIPCHK(hipEventSynchronize(L.ev));
+                L.t_copied = ms_since(t0_);
+                partition(L);
+            }
+            L.t_done = ms_since(t0_);
+            if (trace_on())
+                fprintf(stderr, "[sclap] batch host partitions L%d: %zu graphs, %d nodes; staged %.1f, started %.1f, "
+                        "copied %.1f, done %.1f ms\n", l, L.gids.size(), L.n, L.t_staged, L.t_start, L.t_copied,
+                        L.t_done);
+            L.done.set_value();
+        } catch (...) {
+            L.done.set_exception(std::current_exception());
+        }
+    }
+
+    void partition(Level& L) {
+        const int32_t Mk = static_cast<int32_t>(L.gids.size());
+        std::vector<int32_t> order(Mk);
+        for (int32_t m = 0; m < Mk; ++m) order[m] = m;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+            return L.nnb[x + 1] - L.nnb[x] > L.nnb[y + 1] - L.nnb[y];
+        });
+        parallel_for(Mk, threads_, [&](int32_t i) {
+            const int32_t m = order[i];
+            const int32_t nm = L.nnb[m + 1] - L.nnb[m];
+            if (nm == 0) return;
+            const int32_t g = L.gids[m];
+            int32_t* pp = L.p + L.nnb[m];
+            // rows of inner levels are unordered; neighbours come as core ranks
+            host_initial_partition(nm, L.x + L.nnb[m] + m, L.a + L.nsb[m], L.v ? L.v + L.nnb[m] : nullptr, k_[g], T_[g],
+                                   pp, false, true, 1);
+            for (int32_t q = 0; q < nm; ++q) pp[q] += kb_[g];  // labels of the batch's block space
+        });
+    }
+
+    HostStage stage_;
+    Clock::time_point t0_ = Clock::now();
+    size_t cap_, used_ = 0;
+    const int32_t* k_;
+    const std::vector<int64_t>& T_;
+    const std::vector<int32_t>& kb_;
+    hipStream_t s_;
+    hipStream_t cs_ = nullptr;  // copies to the host (default priority)
+    int32_t threads_ = 1;
+    std::vector<std::unique_ptr<Level>> lv_;
+    std::atomic<bool> closed_{false};  // being destroyed: levels not yet started are skipped
+};
+
 __global__ void pool_init_kernel(int32_t n, const int32_t* __restrict__ gid, const int32_t* __restrict__ pool,
                                  int32_t* __restrict__ part) {
     const int32_t v = blockIdx.x * 256 + threadIdx.x;
@@ -1319,6 +1512,16 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
         std::vector<DBuf<int32_t>> bblk(1);  // inherited blocks of levels >= 1
         auto blk_of = [&](int32_t l) -> const int32_t* { return l == 0 ? carry : bblk[l].get(); };
         t_coarsen = Clock::now();
+        // host initial partitions (first cycle; later ones inherit theirs),
+        // computed while coarsening goes on
+        std::unique_ptr<HostIpPipeline> pipe;
+        if (!carry && o.initial != 1) {
+            auto r8 = [](size_t x) { return (x + 7) & ~static_cast<size_t>(7); };
+            const size_t n0 = static_cast<size_t>(g0.n), S0 = static_cast<size_t>(g0.S);
+            const size_t bytes = r8((n0 + G) * sizeof(int64_t)) + r8(S0 * sizeof(int32_t)) +
+                                 2 * r8(n0 * sizeof(int32_t)) + 4 * 8 * (static_cast<size_t>(SCLAP_MAX_LEVELS) + 1);
+            pipe.reset(new HostIpPipeline(bytes, k, T, kb, s));
+        }
 
         // ---- coarsening
         std::vector<uint8_t> cont(G, 1);
@@ -1335,7 +1538,14 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
                     any = true;
                 }
             }
-            if (!any) break;
+            if (!any) {  // every graph of this level ends here
+                if (pipe) {
+                    std::vector<int32_t> all(M);
+                    for (int32_t m = 0; m < M; ++m) all[m] = m;
+                    pipe->stage(lev, L[lev], all);
+                }
+                break;
+            }
             BatchLevel& B = L[lev];
             const int32_t n = B.g.n;
             std::vector<int64_t> cvl(G), cm = cmax0;
@@ -1411,6 +1621,18 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
                 keep.push_back(m);
                 if (20 * nc > 19 * nm) cont[g] = 0;  // stalled
             }
+            if (pipe) {  // the graphs not kept end at this level
+                std::vector<int32_t> ending;
+                size_t q = 0;
+                for (int32_t m = 0; m < M; ++m) {
+                    if (q < keep.size() && keep[q] == m) {
+                        ++q;
+                        continue;
+                    }
+                    ending.push_back(m);
+                }
+                pipe->stage(lev, B, ending);
+            }
             if (keep.empty()) break;
             BatchLevel N;
             const std::vector<int64_t> csb = member_slot_bases(coarse.xadj.get(), cb, s);
@@ -1448,7 +1670,7 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
             ++lev;
         }
         const int32_t top = lev;
-        std::vector<int32_t> last(G, 0), mpos(G, 0);
+        std::vector<int32_t> last(G, 0);
         for (int32_t l = 0; l <= top; ++l)
             for (size_t m = 0; m < L[l].ids.size(); ++m) last[L[l].ids[m]] = l;
         st->levels = top;
@@ -1456,120 +1678,15 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
             for (int32_t g = 0; g < G; ++g) st->graph_levels[g] = last[g];
         HIPCHK(hipStreamSynchronize(s));
         st->ms_coarsen += ms_since(t_coarsen);
+        if (trace_on() && pipe) fprintf(stderr, "[sclap] batch coarsening done at %.1f ms\n", ms_since(t_coarsen));
 
-        // ---- initial partition of every graph's coarsest level, on the host
-        // (first cycle; later ones inherit it)
-        auto t_init = Clock::now();
-        // the slices of the graphs that end at a level are copied into one
-        // pinned staging area laid out like the whole level (runs of
-        // consecutive ending graphs in one copy each; the graphs that go on
-        // coarsening are not copied); results go to one host array per
-        // level, uploaded before the projection of the graphs that continue
-        std::vector<uint8_t> ends(static_cast<size_t>(top) + 1, 0);
-        for (int32_t l = 0; l <= top; ++l)
-            for (size_t m = 0; m < L[l].ids.size(); ++m) mpos[L[l].ids[m]] = static_cast<int32_t>(m);
-        // device initial partitions run level by level in the refinement loop
+        // ---- initial partitions: on the host (staged during coarsening
+        // above), or on the device level by level in the refinement loop
         const bool dev_ip = o.initial == 1 && !carry;
         std::vector<uint8_t> ends_dev(static_cast<size_t>(top) + 1, 0);
-        for (int32_t g = 0; g < G; ++g) (dev_ip ? ends_dev : ends)[last[g]] = carry ? 0 : 1;
-        auto rnd8 = [](size_t x) { return (x + 7) & ~static_cast<size_t>(7); };
-        std::vector<size_t> lofs(static_cast<size_t>(top) + 2, 0);
-        for (int32_t l = 0; l <= top; ++l) {
-            size_t bytes = 0;
-            if (ends[l]) {
-                const size_t nl = static_cast<size_t>(L[l].g.n);
-                bytes = rnd8((nl + 1) * sizeof(int64_t)) + rnd8(static_cast<size_t>(L[l].g.S) * sizeof(int32_t)) +
-                        2 * rnd8(nl * sizeof(int32_t));
-            }
-            lofs[l + 1] = lofs[l] + bytes;
-        }
-        std::unique_ptr<HostStage> stage;
-        struct LevelHost {
-            int64_t* x = nullptr;
-            int32_t *a = nullptr, *v = nullptr, *p = nullptr;
-        };
-        std::vector<LevelHost> lh(static_cast<size_t>(top) + 1);
-        if (lofs[top + 1] > 0) {
-            stage.reset(new HostStage(lofs[top + 1]));
-            for (int32_t l = 0; l <= top; ++l) {
-                if (!ends[l]) continue;
-                const BatchLevel& B = L[l];
-                const size_t nl = static_cast<size_t>(B.g.n);
-                char* base = stage->data() + lofs[l];
-                LevelHost& h = lh[l];
-                h.x = reinterpret_cast<int64_t*>(base);
-                h.a = reinterpret_cast<int32_t*>(base + rnd8((nl + 1) * sizeof(int64_t)));
-                h.v = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(h.a) + rnd8(static_cast<size_t>(B.g.S) * sizeof(int32_t)));
-                h.p = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(h.v) + rnd8(nl * sizeof(int32_t)));
-                const size_t M = B.ids.size();
-                for (size_t m0 = 0; m0 < M;) {
-                    if (last[B.ids[m0]] != l) {
-                        ++m0;
-                        continue;
-                    }
-                    size_t m1 = m0 + 1;
-                    while (m1 < M && last[B.ids[m1]] == l) ++m1;
-                    const int64_t v0 = B.nb[m0], v1 = B.nb[m1];
-                    const int64_t e0 = B.sb[m0], e1 = B.sb[m1];
-                    HIPCHK(hipMemcpyAsync(h.x + v0, B.g.xadj + v0, (v1 - v0 + 1) * sizeof(int64_t),
-                                          hipMemcpyDeviceToHost, s));
-                    if (e1 > e0)
-                        HIPCHK(hipMemcpyAsync(h.a + e0, B.g.adj + e0, (e1 - e0) * sizeof(int32_t), hipMemcpyDeviceToHost,
-                                              s));
-                    if (B.g.vw && v1 > v0)
-                        HIPCHK(hipMemcpyAsync(h.v + v0, B.g.vw + v0, (v1 - v0) * sizeof(int32_t), hipMemcpyDeviceToHost,
-                                              s));
-                    m0 = m1;
-                }
-                if (!B.g.vw) h.v = nullptr;
-            }
-            HIPCHK(hipStreamSynchronize(s));
-        }
-        // The host partitions run level by level, top first, on a helper
-        // thread: the device refines the top levels while the host still
-        // partitions the graphs that end lower down (most small graphs end at
-        // level 0), and the refinement of level l waits only for level l's.
-        const unsigned hw = std::thread::hardware_concurrency();
-        const int32_t host_threads = static_cast<int32_t>(std::min(16u, hw ? hw : 1u));
-        std::vector<std::vector<int32_t>> ending(static_cast<size_t>(top) + 1);
-        if (!carry && !dev_ip)
-            for (int32_t g = 0; g < G; ++g) ending[last[g]].push_back(g);
-        std::vector<std::promise<void>> level_done(static_cast<size_t>(top) + 1);
-        std::vector<std::shared_future<void>> level_ready;
-        for (auto& pr : level_done) level_ready.push_back(pr.get_future().share());
-        auto partition_level = [&](int32_t l) {
-            const BatchLevel& B = L[l];
-            const LevelHost& h = lh[l];
-            parallel_for(static_cast<int32_t>(ending[l].size()), host_threads, [&](int32_t i) {
-                const int32_t g = ending[l][i];
-                const int32_t m = mpos[g];
-                const int32_t nb0 = B.nb[m];
-                const int32_t nm = B.nb[m + 1] - nb0;
-                std::vector<int64_t> x(h.x + nb0, h.x + nb0 + nm + 1);  // row ends are shared with the next graph
-                const int64_t x0 = x[0];
-                for (auto& e : x) e -= x0;
-                int32_t* a = h.a + x0;  // this graph's slots, to graph-local ids in place
-                for (int64_t j = 0; j < x[nm]; ++j) a[j] -= nb0;
-                int32_t* pp = h.p + nb0;
-                host_initial_partition(nm, x.data(), a, h.v ? h.v + nb0 : nullptr, k[g], T[g], pp,
-                                       false);  // rows of inner levels are unordered
-                for (int32_t q = 0; q < nm; ++q) pp[q] += kb[g];  // labels of the batch's block space
-            });
-        };
-        // declared after everything the helper reads, so that an error on this
-        // thread waits for the helper before those are destroyed
-        std::future<void> host_parts = std::async(std::launch::async, [&] {
-            for (int32_t l = top; l >= 0; --l) {
-                try {
-                    if (!ending[l].empty()) partition_level(l);
-                    level_done[l].set_value();
-                } catch (...) {
-                    for (int32_t q = l; q >= 0; --q) level_done[q].set_exception(std::current_exception());
-                    return;
-                }
-            }
-        });
-        st->ms_initial += ms_since(t_init);
+        if (dev_ip)
+            for (int32_t g = 0; g < G; ++g) ends_dev[last[g]] = 1;
+        std::vector<double> ms_wait(static_cast<size_t>(top) + 1, 0.0);
 
         // ---- refinement from the top level down
         auto t_ref = Clock::now();
@@ -1590,24 +1707,10 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
                 HIPCHK(hipMemcpyAsync(part, blk_of(l), n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
             // graphs ending here: their initial partitions (the other ranges
             // are overwritten by the projection next)
-            {
-                auto t_wait = Clock::now();
-                level_ready[l].get();  // rethrows the helper's error
-                ip_ms += ms_since(t_wait);
+            if (pipe) {
+                ms_wait[l] = pipe->finish(l, part);
+                ip_ms += ms_wait[l];
             }
-            if (ends[l] && n > 0)
-                for (size_t m0 = 0; m0 < B.ids.size();) {  // runs of consecutive graphs ending here
-                    if (last[B.ids[m0]] != l) {
-                        ++m0;
-                        continue;
-                    }
-                    size_t m1 = m0 + 1;
-                    while (m1 < B.ids.size() && last[B.ids[m1]] == l) ++m1;
-                    if (B.nb[m1] > B.nb[m0])
-                        HIPCHK(hipMemcpyAsync(part + B.nb[m0], lh[l].p + B.nb[m0], (B.nb[m1] - B.nb[m0]) * sizeof(int32_t),
-                                              hipMemcpyHostToDevice, s));
-                    m0 = m1;
-                }
             if (ends_dev[l] && n > 0) {
                 std::vector<uint8_t> endg(G, 0);
                 for (size_t m = 0; m < B.ids.size(); ++m)
@@ -1649,6 +1752,11 @@ int partition_batch_impl(const DevGraph& g0_in, int32_t G, const int32_t* node_b
         HIPCHK(hipStreamSynchronize(s));
         st->ms_refine += ms_since(t_ref) - ip_ms;
         st->ms_initial += ip_ms;
+        if (trace_on()) {
+            fprintf(stderr, "[sclap] batch initial partitions: ms waited per level:");
+            for (int32_t l = top; l >= 0; --l) fprintf(stderr, " L%d %.1f", l, ms_wait[l]);
+            fprintf(stderr, "\n");
+        }
     }  // cycles
     auto t_fin = Clock::now();
     std::vector<int32_t> hw_(std::max(K, 1));

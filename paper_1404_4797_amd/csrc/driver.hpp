@@ -46,9 +46,11 @@ void check_k_eps(int32_t k, double eps);
 // Greedy BFS growing of blocks 0..k-2 up to T, the rest in id order to the
 // lightest block (host memory).  rows_sorted: rows ascend (skips a sort).
 // adj_ranked: adj holds each neighbour's rank among the positive-degree nodes
-// (core_ranks) instead of its id.
+// (core_ranks) instead of its id.  threads: host threads it may use (0: up
+// to 16; callers that already run one graph per thread pass 1).
 void host_initial_partition(int32_t n, const int64_t* xadj, const int32_t* adj, const int32_t* vw, int32_t k,
-                            int64_t T, int32_t* part, bool rows_sorted = false, bool adj_ranked = false);
+                            int64_t T, int32_t* part, bool rows_sorted = false, bool adj_ranked = false,
+                            int32_t threads = 0);
 
 // One graph: outputs part (device, n), cut and bw[k] (host); o.vcycles
 // multilevel cycles.

@@ -566,6 +566,43 @@ __global__ void compact_slots_kernel(int64_t S_new, int32_t Mk, const int64_t* _
     }
 }
 
+__global__ void pack_nodes_kernel(int32_t n_new, int32_t Mk, const int32_t* __restrict__ nnb,
+                                  const int32_t* __restrict__ onb, const int64_t* __restrict__ osb,
+                                  const int64_t* __restrict__ oxadj, const int32_t* __restrict__ ovw,
+                                  int64_t* __restrict__ nx, int32_t* __restrict__ nvw, int32_t* __restrict__ has_deg) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n_new) return;
+    const int32_t m = member_of(nnb, Mk, i);
+    const int32_t o = onb[m] + (i - nnb[m]);
+    nx[i + m] = oxadj[o] - osb[m];
+    if (i + 1 == nnb[m + 1]) nx[i + m + 1] = oxadj[o + 1] - osb[m];
+    if (nvw) nvw[i] = ovw[o];
+    has_deg[i] = oxadj[o + 1] > oxadj[o] ? 1 : 0;
+}
+
+// rank: exclusive prefix count of has_deg over the packed nodes
+__global__ void pack_slots_kernel(int64_t S_new, int32_t Mk, const int64_t* __restrict__ nsb,
+                                  const int64_t* __restrict__ osb, const int32_t* __restrict__ onb,
+                                  const int32_t* __restrict__ nnb, const int32_t* __restrict__ has_deg,
+                                  const int32_t* __restrict__ rank, const int32_t* __restrict__ oadj,
+                                  int32_t* __restrict__ nadj) {
+    for (int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; j < S_new;
+         j += static_cast<int64_t>(gridDim.x) * 256) {
+        const int32_t m = member_of(nsb, Mk, j);
+        const int32_t xp = nnb[m] + (oadj[osb[m] + (j - nsb[m])] - onb[m]);
+        nadj[j] = has_deg[xp] ? rank[xp] - rank[nnb[m]] : -1;
+    }
+}
+
+__global__ void unpack_members_kernel(int32_t n_new, int32_t Mk, const int32_t* __restrict__ nnb,
+                                      const int32_t* __restrict__ onb, const int32_t* __restrict__ src,
+                                      int32_t* __restrict__ dst) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n_new) return;
+    const int32_t m = member_of(nnb, Mk, i);
+    dst[onb[m] + (i - nnb[m])] = src[i];
+}
+
 __global__ void remap_members_kernel(int32_t n, const int32_t* __restrict__ gid, const int32_t* __restrict__ delta,
                                      int32_t* __restrict__ C) {
     const int32_t v = blockIdx.x * 256 + threadIdx.x;
@@ -705,6 +742,40 @@ void compact_members(const DevGraph& src, const std::vector<int32_t>& onb, const
         LAUNCHCHK();
     }
     HIPCHK(hipStreamSynchronize(s));
+}
+
+void pack_members_for_host(const DevGraph& src, const std::vector<int32_t>& onb, const std::vector<int64_t>& osb,
+                           const std::vector<int32_t>& nnb, const std::vector<int64_t>& nsb, int64_t* x,
+                           int32_t* adj, int32_t* vw, hipStream_t s) {
+    const int32_t Mk = static_cast<int32_t>(onb.size());
+    const int32_t n_new = nnb[Mk];
+    const int64_t S_new = nsb[Mk];
+    if (Mk == 0 || n_new == 0) return;
+    DBuf<int32_t> i32(2 * static_cast<size_t>(Mk) + 1, s);  // nnb[Mk+1] | onb[Mk]
+    DBuf<int64_t> i64(2 * static_cast<size_t>(Mk) + 1, s);  // nsb[Mk+1] | osb[Mk]
+    HIPCHK(hipMemcpyAsync(i32.get(), nnb.data(), (Mk + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(i32.get() + Mk + 1, onb.data(), Mk * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(i64.get(), nsb.data(), (Mk + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(i64.get() + Mk + 1, osb.data(), Mk * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    DBuf<int32_t> flag(n_new, s), rank(n_new, s), tot(1, s);
+    pack_nodes_kernel<<<grid_for(n_new, 256), 256, 0, s>>>(n_new, Mk, i32.get(), i32.get() + Mk + 1,
+                                                           i64.get() + Mk + 1, src.xadj, src.vw, x,
+                                                           src.vw ? vw : nullptr, flag.get());
+    LAUNCHCHK();
+    if (S_new > 0) {
+        exclusive_scan_i32(flag.get(), rank.get(), n_new, tot.get(), s);
+        pack_slots_kernel<<<capped_grid_s(S_new), 256, 0, s>>>(S_new, Mk, i64.get(), i64.get() + Mk + 1,
+                                                               i32.get() + Mk + 1, i32.get(), flag.get(), rank.get(),
+                                                               src.adj, adj);
+        LAUNCHCHK();
+    }
+    HIPCHK(hipStreamSynchronize(s));  // the host index vectors are read by the copies above
+}
+
+void unpack_members(const int32_t* src, int32_t n_new, int32_t Mk, const int32_t* dnb, int32_t* dst, hipStream_t s) {
+    if (n_new == 0 || Mk == 0) return;
+    unpack_members_kernel<<<grid_for(n_new, 256), 256, 0, s>>>(n_new, Mk, dnb, dnb + Mk + 1, src, dst);
+    LAUNCHCHK();
 }
 
 void remap_members(int32_t n, const int32_t* gid, const std::vector<int32_t>& delta, int32_t* C, hipStream_t s) {

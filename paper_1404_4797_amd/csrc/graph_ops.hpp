@@ -89,6 +89,19 @@ void graph_cuts(const DevGraph& g, const int32_t* part, const int32_t* gid, int3
 void compact_members(const DevGraph& src, const std::vector<int32_t>& onb, const std::vector<int64_t>& osb,
                      const std::vector<int32_t>& nnb, const std::vector<int64_t>& nsb, OwnedDevGraph& dst,
                      hipStream_t s);
+// The members of src with old bases (onb, osb) packed for a host copy:
+// member m's nnb[m+1] - nnb[m] nodes at [nnb[m], ...) of vw (if src.vw),
+// its row offsets (starting at 0) at [nnb[m] + m, ... + nm] of x, and its
+// slots at [nsb[m], nsb[m+1]) of adj, each neighbour given as its rank among
+// the member's nodes of positive degree (-1 for a neighbour without
+// neighbours, which only an asymmetric graph has).  x holds n_new + Mk
+// entries.  Synchronises.
+void pack_members_for_host(const DevGraph& src, const std::vector<int32_t>& onb, const std::vector<int64_t>& osb,
+                           const std::vector<int32_t>& nnb, const std::vector<int64_t>& nsb, int64_t* x,
+                           int32_t* adj, int32_t* vw, hipStream_t s);
+// dst[onb[m] + i - nnb[m]] = src[i] for every packed node i (device arrays;
+// dnb holds nnb[0..Mk] then onb[0..Mk-1]).
+void unpack_members(const int32_t* src, int32_t n_new, int32_t Mk, const int32_t* dnb, int32_t* dst, hipStream_t s);
 // C[v] += delta[gid[v]], or -1 where delta is INT_MIN (graph dropped).
 void remap_members(int32_t n, const int32_t* gid, const std::vector<int32_t>& delta, int32_t* C, hipStream_t s);
 // part[v] = coarse_part[C[v]] where C[v] >= 0.

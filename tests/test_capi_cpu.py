@@ -111,15 +111,34 @@ def test_initial_partition_cross_coded(make, k):
     assert np.array_equal(a, b)
 
 
-def test_initial_partition_unsorted_rows():
+@pytest.mark.parametrize("make,k", [
+    (lambda: synth.rmat(10, 8, seed=9), 4),
+    # dense rows: ordered through the core bitmap
+    (lambda: synth.rmat(11, 48, seed=10, weighted=True), 16),
+    # rows spread thinly over a wide id range: ordered by sorting
+    (lambda: synth.rgg(60000, seed=11), 8),
+])
+def test_initial_partition_unsorted_rows(make, k):
     sc, _ = _lib()
-    g = synth.rmat(10, 8, seed=9)
-    rng = np.random.default_rng(0)
+    g = make()
+    rng = np.random.default_rng(k)
+    perm = rng.permutation(g["n"]).astype(np.int32)  # relabel, so rows span the id range
+    if k == 8:
+        x, a = g["xadj"], g["adjncy"]
+        inv = np.argsort(perm)
+        deg = np.diff(x)[inv]
+        nx = np.concatenate([[0], np.cumsum(deg)]).astype(np.int64)
+        na = np.empty_like(a)
+        for v in range(g["n"]):
+            o = inv[v]
+            na[nx[v]:nx[v + 1]] = perm[a[x[o]:x[o + 1]]]
+        g = {"n": g["n"], "xadj": nx, "adjncy": na, "adjwgt": None, "vwgt": None}
     for v in range(g["n"]):
         b, e = int(g["xadj"][v]), int(g["xadj"][v + 1])
         g["adjncy"][b:e] = g["adjncy"][b:e][rng.permutation(e - b)]
-    T = -(-g["n"] // 4)
-    assert np.array_equal(sc.initial_partition(g, 4), oracle.initial_partition(g, 4, T))
+    cV = g["n"] if g.get("vwgt") is None else int(np.sum(g["vwgt"]))
+    T = -(-cV // k)
+    assert np.array_equal(sc.initial_partition(g, k), oracle.initial_partition(g, k, T))
 
 
 def test_union_builder():
