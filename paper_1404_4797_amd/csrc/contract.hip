@@ -321,7 +321,8 @@ __global__ void long_lens_kernel(const int32_t* __restrict__ list, uint32_t nl, 
     if (l < nl) nchunks[l] = (rowcnt[list[l]] + chunk - 1) / chunk;
 }
 
-constexpr int kLongChunk = 2048;  // entries merged in LDS per workgroup before the sort
+constexpr int kLongChunk = 8192;  // entries merged in LDS per workgroup before the sort
+constexpr int kDedupThreads = 1024;
 
 // Long-row chunks: chunk c of all long rows belongs to row list[crow[c]] and
 // is that row's chunk number c - cfirst[crow[c]].
@@ -332,17 +333,23 @@ __global__ void long_chunks_kernel(uint32_t nl, const int64_t* __restrict__ cfir
 }
 
 // Merges equal neighbours inside one chunk in an LDS table and writes the
-// chunk's distinct (C(v), summed w) back to the chunk's start.
-__global__ void __launch_bounds__(256) long_dedup_kernel(const int32_t* __restrict__ list,
-                                                         const int32_t* __restrict__ crow,
-                                                         const int64_t* __restrict__ cfirst,
-                                                         const int64_t* __restrict__ rowoff,
-                                                         const int32_t* __restrict__ rowcnt, int32_t* __restrict__ tk,
-                                                         int32_t* __restrict__ tw, int32_t* __restrict__ ccnt) {
+// chunk's distinct (C(v), summed w) back to the chunk's start.  Sums fit 32
+// bits: a partial sum never exceeds the coarse edge's weight, and the edge
+// weight total is checked to fit 31 bits.  Long rows of contracted hubs
+// repeat their neighbours many times, so large chunks shrink what the
+// bucket passes after this one move.
+__global__ void __launch_bounds__(kDedupThreads) long_dedup_kernel(const int32_t* __restrict__ list,
+                                                                   const int32_t* __restrict__ crow,
+                                                                   const int64_t* __restrict__ cfirst,
+                                                                   const int64_t* __restrict__ rowoff,
+                                                                   const int32_t* __restrict__ rowcnt,
+                                                                   int32_t* __restrict__ tk, int32_t* __restrict__ tw,
+                                                                   int32_t* __restrict__ ccnt) {
     constexpr int kT = 2 * kLongChunk;
+    constexpr int kW = kDedupThreads / kWave;
     __shared__ int32_t keys[kT];
-    __shared__ unsigned long long sums[kT];
-    __shared__ int32_t s_cnt[256];
+    __shared__ uint32_t sums[kT];
+    __shared__ int32_t s_w[kW];
     const int tid = threadIdx.x;
     const int64_t c = blockIdx.x;
     const int32_t l = crow[c];
@@ -351,12 +358,12 @@ __global__ void __launch_bounds__(256) long_dedup_kernel(const int32_t* __restri
     const int64_t len = rowcnt[row];
     const int32_t cnt = static_cast<int32_t>(j0 + kLongChunk < len ? kLongChunk : len - j0);
     const int64_t b = rowoff[row] + j0;
-    for (int j = tid; j < kT; j += 256) {
+    for (int j = tid; j < kT; j += kDedupThreads) {
         keys[j] = -1;
         sums[j] = 0;
     }
     __syncthreads();
-    for (int j = tid; j < cnt; j += 256) {
+    for (int j = tid; j < cnt; j += kDedupThreads) {
         const int32_t x = tk[b + j];
         uint32_t h = slot_hash(static_cast<uint32_t>(x)) & (kT - 1);
         while (true) {
@@ -364,25 +371,26 @@ __global__ void __launch_bounds__(256) long_dedup_kernel(const int32_t* __restri
             if (prev == -1 || prev == x) break;
             h = (h + 1) & (kT - 1);
         }
-        atomicAdd(&sums[h], static_cast<unsigned long long>(static_cast<uint32_t>(tw[b + j])));
+        atomicAdd(&sums[h], static_cast<uint32_t>(tw[b + j]));
     }
     __syncthreads();
-    constexpr int kPer = kT / 256;
+    // exclusive prefix of the occupied slots, kPer consecutive slots per thread
+    constexpr int kPer = kT / kDedupThreads;
     int32_t mine = 0;
+#pragma unroll
     for (int j = 0; j < kPer; ++j) mine += keys[tid * kPer + j] >= 0;
-    s_cnt[tid] = mine;
-    __syncthreads();
-    if (tid == 0) {
-        int32_t run = 0;
-        for (int t = 0; t < 256; ++t) {
-            const int32_t x = s_cnt[t];
-            s_cnt[t] = run;
-            run += x;
-        }
-        ccnt[c] = run;
+    int32_t incl = mine;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int32_t t = __shfl_up(incl, o, 64);
+        if (lane_id() >= o) incl += t;
     }
+    if (lane_id() == kWave - 1) s_w[tid / kWave] = incl;
     __syncthreads();
-    int32_t pos = s_cnt[tid];
+    int32_t pos = incl - mine;
+    for (int w = 0; w < tid / kWave; ++w) pos += s_w[w];
+    if (tid == kDedupThreads - 1) ccnt[c] = pos + mine;
+#pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int e = tid * kPer + j;
         if (keys[e] < 0) continue;
@@ -584,11 +592,21 @@ __device__ __forceinline__ uint32_t bucket_of(int32_t x, uint32_t P) {
 }
 
 __global__ void long_bucket_counts_kernel(uint32_t nl, const int64_t* __restrict__ loff, int32_t mean,
-                                          int32_t* __restrict__ nbk) {
+                                          const int32_t* __restrict__ list, const int64_t* __restrict__ cfirst,
+                                          int32_t* __restrict__ dcnt, int32_t* __restrict__ nbk) {
     const uint32_t l = blockIdx.x * 256 + threadIdx.x;
     if (l >= nl) return;
     const int64_t m = loff[l + 1] - loff[l];
-    nbk[l] = static_cast<int32_t>(m > mean ? (m + mean - 1) / mean : 1);
+    if (cfirst[l + 1] - cfirst[l] == 1) {  // one chunk: its merge is the row's
+        nbk[l] = 0;
+        dcnt[list[l]] = static_cast<int32_t>(m);
+        return;
+    }
+    // at most kBucketLds buckets: a row's buckets then count and reserve in
+    // LDS; a bucket whose distinct neighbours overflow its table sends the
+    // long rows to the HBM-table merge
+    const int64_t q = m > mean ? (m + mean - 1) / mean : 1;
+    nbk[l] = static_cast<int32_t>(q < kBucketLds ? q : kBucketLds);
 }
 
 // bucket q belongs to long row brow[q]
@@ -617,19 +635,7 @@ __global__ void __launch_bounds__(256) long_bucket_scatter_kernel(
     const int32_t cnt = ccnt[c];
     const int64_t b0 = bfirst[l];
     const uint32_t P = static_cast<uint32_t>(bfirst[l + 1] - b0);
-    if (P > static_cast<uint32_t>(kBucketLds)) {  // very long row: global atomics per entry
-        for (int32_t j = tid; j < cnt; j += 256) {
-            const int64_t q = b0 + bucket_of(tk[src + j], P);
-            if (kReserve) {
-                const int64_t at = boff[q] + atomicAdd(&bfill[q], 1);
-                sk[at] = tk[src + j];
-                sw[at] = tw[src + j];
-            } else {
-                atomicAdd(&bcount[q], 1);
-            }
-        }
-        return;
-    }
+    if (P == 0) return;  // a one-chunk row, merged already
     for (uint32_t j = tid; j < P; j += 256) lcnt[j] = 0;
     __syncthreads();
     for (int32_t j = tid; j < cnt; j += 256) atomicAdd(&lcnt[bucket_of(tk[src + j], P)], 1);
@@ -912,12 +918,13 @@ bool bucket_merge_long_rows(uint32_t nl, const int32_t* llist, int64_t nch, cons
     ProfScope ps("contract_long_buckets", 40.0 * static_cast<double>(ml), s);
     DBuf<int32_t> nbk(nl, s);
     DBuf<int64_t> bfirst(static_cast<size_t>(nl) + 1, s), tot(2, s);
-    long_bucket_counts_kernel<<<grid_for(nl, 256), 256, 0, s>>>(nl, loff, mean, nbk.get());
+    long_bucket_counts_kernel<<<grid_for(nl, 256), 256, 0, s>>>(nl, loff, mean, llist, cfirst, dcnt, nbk.get());
     LAUNCHCHK();
     exclusive_scan_i32_to_i64(nbk.get(), bfirst.get(), nl, tot.get(), s);
     int64_t NB = 0;
     HIPCHK(hipMemcpyAsync(&NB, tot.get(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (NB == 0) return true;  // every long row was one chunk
     fill_i64(bfirst.get() + nl, NB, 1, s);
     DBuf<int32_t> brow(NB, s), bcount(NB, s), bfill(NB, s), qcnt(NB, s);
     DBuf<int64_t> boff(static_cast<size_t>(NB) + 1, s), qoff(static_cast<size_t>(NB) + 1, s);
@@ -1004,8 +1011,8 @@ void merge_rows(int32_t nc, int64_t m, const int64_t* rowoff, const int32_t* row
             ProfScope ps_m("contract_long_merge", 0, s);
             long_chunks_kernel<<<nl, 256, 0, s>>>(nl, cfirst.get(), crow.get());
             LAUNCHCHK();
-            long_dedup_kernel<<<static_cast<unsigned>(nch), 256, 0, s>>>(llist, crow.get(), cfirst.get(), rowoff,
-                                                                         rowcnt, tk, tw, ccnt.get());
+            long_dedup_kernel<<<static_cast<unsigned>(nch), kDedupThreads, 0, s>>>(llist, crow.get(), cfirst.get(),
+                                                                                   rowoff, rowcnt, tk, tw, ccnt.get());
             LAUNCHCHK();
         }
         exclusive_scan_i32_to_i64(ccnt.get(), coff.get(), nch, mtot2.get(), s);

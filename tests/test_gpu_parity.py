@@ -205,13 +205,21 @@ def test_partition_parity(sc, gname, k):
     assert r["status"] == ref["status"]
 
 
-@pytest.mark.parametrize("gname", ["rmat_13", "star_9000", "ba_4k"])
+def two_stars():
+    # hubs of 6 000 and 20 000 leaves: contracted, their clusters' rows hold
+    # one and three 8 192-entry merge chunks
+    edges = [(0, i) for i in range(1, 6001)] + [(6001, 6002 + i) for i in range(20000)]
+    return synth.from_edges(26002, edges)
+
+
+@pytest.mark.parametrize("gname", ["rmat_13", "star_9000", "ba_4k", "star_6000", "two_stars"])
 @pytest.mark.parametrize("mean", [1, 3, 1 << 30])
 def test_partition_contraction_bucket_paths(sc, gname, mean):
-    # long coarse rows merged by buckets: mean 1 gives rows with more buckets
-    # than the LDS counters hold (global atomics), mean 3 the LDS path, one
-    # bucket per row overflows the LDS table and falls back to HBM tables
-    g = GRAPHS[gname]()
+    # long coarse rows merged by buckets: mean 1 gives many small buckets
+    # (capped at the 4 096 counters a row keeps in LDS), mean 3 fewer, one
+    # bucket per row overflows the LDS table and falls back to HBM tables;
+    # rows of one merge chunk skip the buckets (all of them for star_6000)
+    g = two_stars() if gname == "two_stars" else (star(6000) if gname == "star_6000" else GRAPHS[gname]())
     say("partition", gname, "bucket mean", mean)
     r = sc.partition_dev(dev(sc, g), 2, 0.03, 4, coarsest_nodes=300, contract_bucket_mean=mean)
     ref = oracle.partition(g, 2, 0.03, 4, coarsest_nodes=300)
