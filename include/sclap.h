@@ -130,6 +130,9 @@ typedef struct {
                                      records all its rounds into one HIP graph and launches it once,
                                      with no host work between rounds; 0 (default) or -1: kernels are
                                      launched one by one, the host one round ahead of the device */
+    int32_t fused_eval;           /* tuning (never changes results): 0 (default) or 1: a colour with
+                                     fewer than 2^22 adjacency slots evaluates its buckets of up to
+                                     1 024 slots per node in one launch; -1: one launch per bucket */
 } sclap_options;
 
 #define SCLAP_MAX_LEVELS 64

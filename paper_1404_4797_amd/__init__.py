@@ -70,7 +70,7 @@ class Options(ctypes.Structure):
                 ("skip_quiet", ctypes.c_int32), ("vcycles", ctypes.c_int32),
                 ("degree_order", ctypes.c_int32), ("contract_bucket_mean", ctypes.c_int32),
                 ("initial_partitioner", ctypes.c_int32), ("select_launches", ctypes.c_int32),
-                ("graph_capture", ctypes.c_int32)]
+                ("graph_capture", ctypes.c_int32), ("fused_eval", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):

@@ -45,6 +45,8 @@ Opts resolve(const sclap_options* o) {
     r.tune.select_launches = o->select_launches;
     if (o->graph_capture < -1 || o->graph_capture > 1) fail(SCLAP_ERR_INVALID, "graph_capture must be -1, 0 or 1");
     r.tune.capture = o->graph_capture;
+    if (o->fused_eval < -1 || o->fused_eval > 1) fail(SCLAP_ERR_INVALID, "fused_eval must be -1, 0 or 1");
+    r.tune.fuse = o->fused_eval;
     r.tune.skip_quiet = o->skip_quiet < 0 ? -1 : (o->skip_quiet > 0 ? 1 : 0);
     r.vcycles = o->vcycles == 0 ? 1 : o->vcycles;
     r.degree_order = o->degree_order != 0 ? 1 : 0;

@@ -362,8 +362,8 @@ __device__ __forceinline__ void insert_slots(const EvalArgs& A, int64_t b, int32
 // ------------------------------------------------------------ lane bucket
 
 template <int MAXD>
-__global__ void __launch_bounds__(256) eval_lane_kernel(EvalArgs A) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void eval_lane_body(const EvalArgs& A, int32_t bid) {
+    const int i = bid * 256 + threadIdx.x;
     if (i >= A.count || stopped(A.gate)) return;
     const int qm = quiet_mode(A);
     const int32_t v = A.nodes[i];
@@ -414,22 +414,26 @@ __global__ void __launch_bounds__(256) eval_lane_kernel(EvalArgs A) {
     if (qm) A.quiet[v] = (!over && !blocked) ? 1 : 0;
 }
 
+template <int MAXD>
+__global__ void __launch_bounds__(256) eval_lane_kernel(EvalArgs A) {
+    eval_lane_body<MAXD>(A, blockIdx.x);
+}
+
 // --------------------------------------------------- group and wave buckets
 
 // G lanes per node (G = 16, 32 or 64: 256 / G nodes per workgroup), each
 // group with an open-addressing table of T entries in LDS.
+// LDS: 2 * (256 / G) * T int32 (the groups' key tables, then their sums).
 template <int G, int T>
-__global__ void __launch_bounds__(256) eval_group_kernel(EvalArgs A) {
+__device__ __forceinline__ void eval_group_body(const EvalArgs& A, int32_t bid, int32_t* lds) {
     constexpr int NG = 256 / G;
-    __shared__ int32_t tkeys[NG][T];
-    __shared__ int32_t tvals[NG][T];
     const int grp = threadIdx.x / G;
     const int gl = threadIdx.x % G;
-    const int node_i = blockIdx.x * NG + grp;
+    const int node_i = bid * NG + grp;
     if (node_i >= A.count || stopped(A.gate)) return;  // uniform per group
     const int qm = quiet_mode(A);
-    int32_t* keys = tkeys[grp];
-    int32_t* vals = tvals[grp];
+    int32_t* keys = lds + grp * T;
+    int32_t* vals = lds + (NG + grp) * T;
     const int32_t v = A.nodes[node_i];
     const Ctx kx = ctx_of(A, v);
     if (skip_quiet(A, qm, v, kx)) {
@@ -476,25 +480,44 @@ __global__ void __launch_bounds__(256) eval_group_kernel(EvalArgs A) {
     }
 }
 
+template <int G, int T>
+__global__ void __launch_bounds__(256) eval_group_kernel(EvalArgs A) {
+    __shared__ int32_t lds[2 * (256 / G) * T];
+    eval_group_body<G, T>(A, blockIdx.x, lds);
+}
+
 // ----------------------------------------------------------- block bucket
 
+// LDS of the block bodies: per-wave winners (tie keys, labels, sums) then
+// the body's table.
+template <int NT>
+struct BlockScratch {
+    uint64_t tie[NT / 64];
+    int32_t conn[NT / 64];
+    int32_t x[NT / 64];
+    int32_t own;
+    int32_t pad;
+};
+
+// LDS: BlockScratch<NT> then 2 * TABLE int32 (keys, then sums).
 template <int NT, int TABLE>
-__global__ void __launch_bounds__(NT) eval_block_kernel(EvalArgs A) {
-    __shared__ int32_t keys[TABLE];
-    __shared__ int32_t vals[TABLE];
-    __shared__ int32_t s_own;
-    __shared__ int32_t s_conn[NT / 64];
-    __shared__ int32_t s_x[NT / 64];
-    __shared__ uint64_t s_tie[NT / 64];
+__device__ __forceinline__ void eval_block_body(const EvalArgs& A, int32_t bid, unsigned char* lds) {
+    BlockScratch<NT>& S = *reinterpret_cast<BlockScratch<NT>*>(lds);
+    int32_t* keys = reinterpret_cast<int32_t*>(lds + sizeof(BlockScratch<NT>));
+    int32_t* vals = keys + TABLE;
+    int32_t& s_own = S.own;
+    int32_t* s_conn = S.conn;
+    int32_t* s_x = S.x;
+    uint64_t* s_tie = S.tie;
     const int tid = threadIdx.x;
     const int wid = tid >> 6;
     const int lane = lane_id();
     if (stopped(A.gate)) return;  // uniform over the grid
     const int qm = quiet_mode(A);
-    const int32_t v = A.nodes[blockIdx.x];
+    const int32_t v = A.nodes[bid];
     const Ctx kx = ctx_of(A, v);
     if (skip_quiet(A, qm, v, kx)) {  // uniform over the workgroup
-        if (tid == 0) store_result(A, blockIdx.x, -1, 0, 0, false);
+        if (tid == 0) store_result(A, bid, -1, 0, 0, false);
         return;
     }
     const int64_t b = A.xadj[v];
@@ -541,9 +564,15 @@ __global__ void __launch_bounds__(NT) eval_block_kernel(EvalArgs A) {
         int32_t fc = -1, fx = -1;
         uint64_t ft = ~0ULL;
         for (int w = 0; w < NT / 64; ++w) combine_into(fc, ft, fx, s_conn[w], s_tie[w], s_x[w]);
-        store_result(A, blockIdx.x, fx, fc, own, over);
+        store_result(A, bid, fx, fc, own, over);
         if (qm) A.quiet[v] = (!over && !any_blocked) ? 1 : 0;
     }
+}
+
+template <int NT, int TABLE>
+__global__ void __launch_bounds__(NT) eval_block_kernel(EvalArgs A) {
+    __shared__ __align__(16) unsigned char lds[sizeof(BlockScratch<NT>) + 2 * TABLE * sizeof(int32_t)];
+    eval_block_body<NT, TABLE>(A, blockIdx.x, lds);
 }
 
 // ------------------------------------------------------------- hub bucket
@@ -891,16 +920,16 @@ __device__ __forceinline__ void dense_best(const EvalArgs& A, const Ctx& kx, con
     }
 }
 
+// LDS: (256 / G) * kDenseMax int32 (each group's block sums).
 template <int G>
-__global__ void __launch_bounds__(256) eval_dense_group_kernel(EvalArgs A) {
+__device__ __forceinline__ void eval_dense_group_body(const EvalArgs& A, int32_t bid, int32_t* lds) {
     constexpr int NG = 256 / G;
-    __shared__ int32_t cs[NG][kDenseMax];
     const int grp = threadIdx.x / G;
     const int gl = threadIdx.x % G;
-    const int node_i = blockIdx.x * NG + grp;
+    const int node_i = bid * NG + grp;
     if (node_i >= A.count || stopped(A.gate)) return;  // uniform per group
     const int qm = quiet_mode(A);
-    int32_t* conn = cs[grp];
+    int32_t* conn = lds + grp * kDenseMax;
     const int32_t v = A.nodes[node_i];
     const Ctx kx = ctx_of(A, v);
     if (skip_quiet(A, qm, v, kx)) {
@@ -930,20 +959,28 @@ __global__ void __launch_bounds__(256) eval_dense_group_kernel(EvalArgs A) {
     }
 }
 
+template <int G>
+__global__ void __launch_bounds__(256) eval_dense_group_kernel(EvalArgs A) {
+    __shared__ int32_t lds[(256 / G) * kDenseMax];
+    eval_dense_group_body<G>(A, blockIdx.x, lds);
+}
+
+// LDS: BlockScratch<NT> then kDenseMax int32 (the node's block sums).
 template <int NT>
-__global__ void __launch_bounds__(NT) eval_dense_block_kernel(EvalArgs A) {
-    __shared__ int32_t conn[kDenseMax];
-    __shared__ int32_t s_conn[NT / 64];
-    __shared__ int32_t s_x[NT / 64];
-    __shared__ uint64_t s_tie[NT / 64];
+__device__ __forceinline__ void eval_dense_block_body(const EvalArgs& A, int32_t bid, unsigned char* lds) {
+    BlockScratch<NT>& S = *reinterpret_cast<BlockScratch<NT>*>(lds);
+    int32_t* conn = reinterpret_cast<int32_t*>(lds + sizeof(BlockScratch<NT>));
+    int32_t* s_conn = S.conn;
+    int32_t* s_x = S.x;
+    uint64_t* s_tie = S.tie;
     const int tid = threadIdx.x;
     const int wid = tid >> 6;
     if (stopped(A.gate)) return;  // uniform over the grid
     const int qm = quiet_mode(A);
-    const int32_t v = A.nodes[blockIdx.x];
+    const int32_t v = A.nodes[bid];
     const Ctx kx = ctx_of(A, v);
     if (skip_quiet(A, qm, v, kx)) {  // uniform over the workgroup
-        if (tid == 0) store_result(A, blockIdx.x, -1, 0, 0, false);
+        if (tid == 0) store_result(A, bid, -1, 0, 0, false);
         return;
     }
     const int64_t b = A.xadj[v];
@@ -972,8 +1009,74 @@ __global__ void __launch_bounds__(NT) eval_dense_block_kernel(EvalArgs A) {
         int32_t fc = -1, fx = -1;
         uint64_t ft = ~0ULL;
         for (int w = 0; w < NT / 64; ++w) combine_into(fc, ft, fx, s_conn[w], s_tie[w], s_x[w]);
-        store_result(A, blockIdx.x, fx, fc, own, over);
+        store_result(A, bid, fx, fc, own, over);
         if (qm) A.quiet[v] = (!over && !any_blocked) ? 1 : 0;
+    }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT) eval_dense_block_kernel(EvalArgs A) {
+    __shared__ __align__(16) unsigned char lds[sizeof(BlockScratch<NT>) + kDenseMax * sizeof(int32_t)];
+    eval_dense_block_body<NT>(A, blockIdx.x, lds);
+}
+
+// ------------------------------------------------- small buckets, fused
+
+// The buckets of up to 1 024 slots (one lane, 16, 32 or 64 lanes, or one
+// 256-thread workgroup per node) of a small colour in one launch: consecutive
+// workgroup ranges belong to the buckets in order, and each workgroup runs its
+// bucket's body on an LDS buffer sized for the largest.  A small colour
+// otherwise pays one launch per bucket on one stream.
+constexpr int kFusedBuckets = 6;
+
+struct FusedBuckets {
+    const int32_t* nodes[kFusedBuckets];
+    int32_t* ct[kFusedBuckets];
+    int32_t* cg[kFusedBuckets];
+    int32_t count[kFusedBuckets];
+    int32_t first[kFusedBuckets + 1];  // first workgroup of each bucket, then the total
+};
+
+constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
+constexpr size_t kFusedLds =
+    cmax(cmax(2 * 16 * (2 * kG16Max) * sizeof(int32_t), 2 * 8 * (2 * kG32Max) * sizeof(int32_t)),
+         cmax(cmax(2 * 4 * kWaveTable * sizeof(int32_t), sizeof(BlockScratch<256>) + 2 * (2 * kBlock1Max) * sizeof(int32_t)),
+              cmax(16 * kDenseMax * sizeof(int32_t), sizeof(BlockScratch<256>) + kDenseMax * sizeof(int32_t))));
+
+template <bool kDense>
+__global__ void __launch_bounds__(256) eval_fused_kernel(EvalArgs A, FusedBuckets F) {
+    __shared__ __align__(16) unsigned char lds[kFusedLds];
+    int b = 0;
+    while (b + 1 < kFusedBuckets && static_cast<int32_t>(blockIdx.x) >= F.first[b + 1]) ++b;
+    const int32_t bid = static_cast<int32_t>(blockIdx.x) - F.first[b];
+    A.nodes = F.nodes[b];
+    A.count = F.count[b];
+    A.ct = F.ct[b];
+    A.cg = F.cg[b];
+    int32_t* l32 = reinterpret_cast<int32_t*>(lds);
+    switch (b) {  // uniform over the workgroup
+        case 0:
+            eval_lane_body<kLaneSmall>(A, bid);
+            break;
+        case 1:
+            eval_lane_body<kLaneMax>(A, bid);
+            break;
+        case 2:
+            if (kDense) eval_dense_group_body<16>(A, bid, l32);
+            else eval_group_body<16, 2 * kG16Max>(A, bid, l32);
+            break;
+        case 3:
+            if (kDense) eval_dense_group_body<32>(A, bid, l32);
+            else eval_group_body<32, 2 * kG32Max>(A, bid, l32);
+            break;
+        case 4:
+            if (kDense) eval_dense_group_body<64>(A, bid, l32);
+            else eval_group_body<64, kWaveTable>(A, bid, l32);
+            break;
+        default:
+            if (kDense) eval_dense_block_body<256>(A, bid, lds);
+            else eval_block_body<256, 2 * kBlock1Max>(A, bid, lds);
+            break;
     }
 }
 
@@ -2525,7 +2628,33 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 }
                 }
             }
-            for (int32_t bk = 0; bk < kHubBucket; ++bk) {
+            int32_t bk_from = 0;
+            if (!side && tune.fuse >= 0) {  // buckets 0..5 of a small colour in one launch
+                FusedBuckets F;
+                static const int32_t kPerBlock[kFusedBuckets] = {256, 256, 16, 8, 4, 1};  // nodes per workgroup
+                int32_t blocks = 0, fnodes = 0;
+                unsigned long long fslots = 0;
+                for (int32_t bk = 0; bk < kFusedBuckets; ++bk) {
+                    const int64_t count = off[c0 + bk + 1] - off[c0 + bk];
+                    F.nodes[bk] = nodes + off[c0 + bk];
+                    F.ct[bk] = ct.get() + (off[c0 + bk] - off[c0]);
+                    F.cg[bk] = cg.get() + (off[c0 + bk] - off[c0]);
+                    F.count[bk] = static_cast<int32_t>(count);
+                    F.first[bk] = blocks;
+                    blocks += static_cast<int32_t>((count + kPerBlock[bk] - 1) / kPerBlock[bk]);
+                    fnodes += static_cast<int32_t>(count);
+                    fslots += cslots[c0 + bk];
+                }
+                F.first[kFusedBuckets] = blocks;
+                if (blocks > 0) {
+                    ProfScope ps(A.refine ? "lp_refine_fused" : "lp_eval_fused", eval_bytes(fnodes, fslots), s);
+                    if (dense) eval_fused_kernel<true><<<blocks, 256, 0, s>>>(A, F);
+                    else eval_fused_kernel<false><<<blocks, 256, 0, s>>>(A, F);
+                    LAUNCHCHK();
+                }
+                bk_from = kFusedBuckets;
+            }
+            for (int32_t bk = bk_from; bk < kHubBucket; ++bk) {
                 const hipStream_t bs = side ? evs.bucket(bk) : s;
                 const int64_t count = off[c0 + bk + 1] - off[c0 + bk];
                 if (count == 0) continue;

@@ -29,6 +29,7 @@ struct LPTuning {
     int32_t select_launches = 0;      // multi-workgroup selection launches per sub-round (0: default)
     int32_t skip_quiet = 0;           // 1: skip nodes whose decision cannot have changed; -1: never; 0: caller's choice
     int32_t capture = 0;              // 1: record each call's rounds in a HIP graph; else launch directly
+    int32_t fuse = 0;                 // >= 0: the small buckets of a small colour in one launch; -1: one launch each
 };
 
 // Several disjoint graphs in one CSR (node ranges per graph, no edge between

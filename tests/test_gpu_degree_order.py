@@ -50,7 +50,8 @@ GRAPHS = {
     "star_pad": lambda: star_with_isolated(9000, 700),
 }
 
-KNOBS = [dict(), dict(lane_max_degree=2, wave_max_degree=8, block_max_degree=24), dict(skip_quiet=1)]
+KNOBS = [dict(), dict(lane_max_degree=2, wave_max_degree=8, block_max_degree=24), dict(skip_quiet=1),
+         dict(fused_eval=-1)]
 
 
 def test_handworked_degree_order_on_gpu(sc, golden_dir):

@@ -74,7 +74,9 @@ KNOBS = [dict(), dict(lane_max_degree=2, wave_max_degree=8, block_max_degree=24)
          # all rounds recorded into one HIP graph (rounds after convergence run
          # as gated no-ops), with and without quiet nodes
          dict(graph_capture=1), dict(graph_capture=1, skip_quiet=1, lane_max_degree=2, wave_max_degree=8,
-                                     block_max_degree=24)]
+                                     block_max_degree=24),
+         # small colours with one launch per degree bucket instead of the fused one
+         dict(fused_eval=-1), dict(fused_eval=-1, lane_max_degree=2, wave_max_degree=8, block_max_degree=24)]
 
 
 # ------------------------------------------------------------ hand-worked
@@ -133,7 +135,8 @@ REFINE_KNOBS = [dict(block_max_degree=40), dict(block_max_degree=30, hub_part_li
                 # every overflowing target through the multi-workgroup selection
                 dict(select_small_max=1), dict(select_small_max=7), dict(skip_quiet=1),
                 dict(select_small_max=1, select_launches=1), dict(select_small_max=3, select_launches=2),
-                dict(graph_capture=1), dict(graph_capture=1, skip_quiet=1)]
+                dict(graph_capture=1), dict(graph_capture=1, skip_quiet=1), dict(fused_eval=-1),
+                dict(fused_eval=-1, block_max_degree=30, select_small_max=7)]
 
 
 @pytest.mark.parametrize("gname", list(GRAPHS))
