@@ -1208,7 +1208,7 @@ __device__ __forceinline__ int32_t agg_slot(int32_t* keys, int32_t t, bool inser
 // tsum[t] += c(v) and cnt[t] += 1 over the candidates of the sub-round, summed
 // per block in LDS first so that a label many nodes aim at (a hub's cluster)
 // costs one global atomic per block and chunk, not one per candidate.
-template <bool kSmall>
+template <bool kSmall, int R>
 __global__ void __launch_bounds__(256) cand_accum_kernel(const int32_t* __restrict__ ct,
                                                          const int32_t* __restrict__ nodes, int32_t count,
                                                          const int32_t* __restrict__ vw, int32_t* __restrict__ tsum,
@@ -1228,10 +1228,9 @@ __global__ void __launch_bounds__(256) cand_accum_kernel(const int32_t* __restri
     }
     __syncthreads();
     int32_t found = 0;
-    for (int64_t base = static_cast<int64_t>(blockIdx.x) * kAggChunk; base < count;
-         base += static_cast<int64_t>(gridDim.x) * kAggChunk) {
+    for (int64_t base = static_cast<int64_t>(blockIdx.x) * (R * 256); base < count;
+         base += static_cast<int64_t>(gridDim.x) * (R * 256)) {
         // all of the thread's loads of the chunk first, then the LDS updates
-        constexpr int R = kAggChunk / 256;
         int32_t tr[R], cr[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -1334,7 +1333,7 @@ __device__ void claim_segment(int32_t t, int32_t len, int64_t room, int32_t* seg
 // otherwise the candidate goes to the slow list and its target gets a
 // segment (small label spaces: the grid walks the labels; otherwise the first
 // slow candidate of a target claims it).
-template <bool kSmall>
+template <bool kSmall, int kAdmitIters>
 __global__ void __launch_bounds__(256) admit_kernel(const int32_t* __restrict__ ct, const int32_t* __restrict__ cg,
                                                     int32_t count, const int32_t* __restrict__ w,
                                                     const int32_t* __restrict__ tsum,
@@ -1354,7 +1353,6 @@ __global__ void __launch_bounds__(256) admit_kernel(const int32_t* __restrict__ 
     }
     // each block takes kAdmitIters * 256 consecutive candidates at a time
     // and appends its slow ones with one atomic
-    constexpr int kAdmitIters = 16;
     int32_t gmin = INT_MAX, gmax = INT_MIN;
     for (int32_t base = blockIdx.x * (kAdmitIters * 256); base < count; base += gridDim.x * (kAdmitIters * 256)) {
         uint32_t mask = 0;
@@ -1417,7 +1415,7 @@ __global__ void __launch_bounds__(256) admit_kernel(const int32_t* __restrict__ 
 // Writes every slow candidate into its target's segment as the key
 // [gmax - gain][node] (ascending key = gain desc, node asc), with its weight.
 // Space is reserved once per label per block chunk.
-template <bool kSmall>
+template <bool kSmall, int R>
 __global__ void __launch_bounds__(256) scatter_kernel(const uint32_t* __restrict__ slow_idx,
                                                       const int32_t* __restrict__ nodes, const int32_t* __restrict__ ct,
                                                       const int32_t* __restrict__ cg, const int32_t* __restrict__ vw,
@@ -1436,8 +1434,7 @@ __global__ void __launch_bounds__(256) scatter_kernel(const uint32_t* __restrict
         lcnt[j] = 0;
     }
     __syncthreads();
-    constexpr int R = kAggChunk / 256;
-    for (uint32_t base = blockIdx.x * kAggChunk; base < m; base += gridDim.x * kAggChunk) {
+    for (uint32_t base = blockIdx.x * (R * 256); base < m; base += gridDim.x * (R * 256)) {
         // the thread's slow candidates, their targets, nodes and gains, all
         // loaded before the LDS work
         uint32_t pr[R];
@@ -2697,40 +2694,35 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
             }
             if (side) evs.join(s);
 
+            // colours below 2^16 entries: one entry per thread and pass, so
+            // that every workgroup of the grid has work; larger ones keep
+            // several loads in flight per thread
+            const bool fine = ccount < (1 << 16);
             // per-target candidate weight and count, then admission: targets
             // that can take all their candidates admit them; the others
             // select the admitted prefix on the device
             {
                 ProfScope ps(A.refine ? "lp_refine_admit" : "lp_admit", 0, s);
                 const unsigned gc = capped_grid(ccount);
-                if (small)
-                    cand_accum_kernel<true><<<gc, 256, 0, s>>>(ct.get(), cnodes, ccount, g.vw, tsum.get(), tcnt.get(),
-                                                               nw, ctr.get(), gate, rcnt.get() + r);
-                else
-                    cand_accum_kernel<false><<<gc, 256, 0, s>>>(ct.get(), cnodes, ccount, g.vw, tsum.get(),
-                                                                tcnt.get(), nw, ctr.get(), gate, rcnt.get() + r);
+                auto accum = small ? (fine ? cand_accum_kernel<true, 1> : cand_accum_kernel<true, kAggChunk / 256>)
+                                   : (fine ? cand_accum_kernel<false, 1> : cand_accum_kernel<false, kAggChunk / 256>);
+                accum<<<gc, 256, 0, s>>>(ct.get(), cnodes, ccount, g.vw, tsum.get(), tcnt.get(), nw, ctr.get(), gate,
+                                         rcnt.get() + r);
                 LAUNCHCHK();
-                if (small)
-                    admit_kernel<true><<<gc, 256, 0, s>>>(ct.get(), cg.get(), ccount, w, tsum.get(), tcnt.get(), BB,
-                                                          ok.get(), slow_idx.get(), seg_off.get(), seg_list.get(), LS,
-                                                          small_max, nw, ctr.get(), gate);
-                else
-                    admit_kernel<false><<<gc, 256, 0, s>>>(ct.get(), cg.get(), ccount, w, tsum.get(), tcnt.get(), BB,
-                                                           ok.get(), slow_idx.get(), seg_off.get(), seg_list.get(),
-                                                           LS, small_max, nw, ctr.get(), gate);
+                auto admit = small ? (fine ? admit_kernel<true, 1> : admit_kernel<true, 16>)
+                                   : (fine ? admit_kernel<false, 1> : admit_kernel<false, 16>);
+                admit<<<gc, 256, 0, s>>>(ct.get(), cg.get(), ccount, w, tsum.get(), tcnt.get(), BB, ok.get(),
+                                         slow_idx.get(), seg_off.get(), seg_list.get(), LS, small_max, nw, ctr.get(),
+                                         gate);
                 LAUNCHCHK();
             }
             {
                 ProfScope ps(A.refine ? "lp_refine_admit_select" : "lp_admit_select", 0, s);
                 const unsigned gc = capped_grid(ccount);
-                if (small)
-                    scatter_kernel<true><<<gc, 256, 0, s>>>(slow_idx.get(), cnodes, ct.get(), cg.get(), g.vw, bits_v,
-                                                            nw, seg_off.get(), seg_fill.get(), skey.get(), swt.get(),
-                                                            ctr.get());
-                else
-                    scatter_kernel<false><<<gc, 256, 0, s>>>(slow_idx.get(), cnodes, ct.get(), cg.get(), g.vw, bits_v,
-                                                             nw, seg_off.get(), seg_fill.get(), skey.get(), swt.get(),
-                                                             ctr.get());
+                auto scatter = small ? (fine ? scatter_kernel<true, 1> : scatter_kernel<true, kAggChunk / 256>)
+                                     : (fine ? scatter_kernel<false, 1> : scatter_kernel<false, kAggChunk / 256>);
+                scatter<<<gc, 256, 0, s>>>(slow_idx.get(), cnodes, ct.get(), cg.get(), g.vw, bits_v, nw, seg_off.get(),
+                                           seg_fill.get(), skey.get(), swt.get(), ctr.get());
                 LAUNCHCHK();
                 select_kernel<<<kMaxBlocks, 256, 0, s>>>(seg_list.get(), seg_off.get(), seg_fill.get(), tcnt.get(), w,
                                                          BB, bits_v, skey.get(), swt.get(), bnd.get(), small_max,
