@@ -1139,31 +1139,6 @@ __global__ void __launch_bounds__(256) hub_dense_finish_kernel(EvalArgs A, HubAr
 
 // ------------------------------------------------------- block utilities
 
-// One atomic per block: returns the position of this thread's item among all
-// flagged items of the grid (order within the grid unspecified).
-__device__ __forceinline__ uint32_t block_append(bool flag, uint32_t* counter) {
-    __shared__ uint32_t s_cnt[4];
-    __shared__ uint32_t s_base;
-    const int wid = threadIdx.x >> 6;
-    const uint64_t m = __ballot(flag);
-    if (lane_id() == 0) s_cnt[wid] = static_cast<uint32_t>(__popcll(m));
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int w = 0; w < 4; ++w) {
-            const uint32_t c = s_cnt[w];
-            s_cnt[w] = run;
-            run += c;
-        }
-        s_base = run ? atomicAdd(counter, run) : 0;
-    }
-    __syncthreads();
-    const uint32_t idx = s_base + s_cnt[wid] + static_cast<uint32_t>(__popcll(m & lanemask_lt()));
-    __syncthreads();
-    return idx;
-}
-
-
 __device__ __forceinline__ int32_t block_sum_i32(int32_t v) {
     __shared__ int32_t s[4];
     v = wave_sum(v);
