@@ -354,7 +354,7 @@ def main():
                     help="arrival rates as multiples of the plain path's graphs/s")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build partitions on one GPU; --gpus %d is not supported "
+        print("bench.py: the partitioner runs on one GPU; --gpus %d is not supported "
               "(sharding over several GPUs is not built)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
