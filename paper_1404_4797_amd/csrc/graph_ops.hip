@@ -590,7 +590,10 @@ __global__ void pack_slots_kernel(int64_t S_new, int32_t Mk, const int64_t* __re
          j += static_cast<int64_t>(gridDim.x) * 256) {
         const int32_t m = member_of(nsb, Mk, j);
         const int32_t xp = nnb[m] + (oadj[osb[m] + (j - nsb[m])] - onb[m]);
-        nadj[j] = has_deg[xp] ? rank[xp] - rank[nnb[m]] : -1;
+        // a neighbour outside the member (an unchecked input with an edge
+        // between graphs) reads as -1, which the host partitioner reports
+        const bool inside = xp >= nnb[m] && xp < nnb[m + 1];
+        nadj[j] = inside && has_deg[xp] ? rank[xp] - rank[nnb[m]] : -1;
     }
 }
 
