@@ -323,6 +323,11 @@ def test_validation_codes_on_device(sc):
         sc.refine_dev(d, 2, 300, torch.full((400,), 2, dtype=torch.int32, device="cuda"))
     with pytest.raises(sc.SclapError):
         sc.contract_dev(d, torch.full((400,), 400, dtype=torch.int32, device="cuda"))
+    # tuning options outside their ranges are rejected before any launch
+    for bad in (dict(graph_capture=2), dict(fused_eval=2), dict(fused_eval=-2), dict(select_launches=-1)):
+        with pytest.raises(sc.SclapError) as ei:
+            sc.partition_dev(d, 2, **bad)
+        assert ei.value.status == -1, bad
 
 
 # ------------------------------------------------------------ metamorphic
