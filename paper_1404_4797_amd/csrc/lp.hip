@@ -82,6 +82,7 @@ struct Counters {
 struct EvalArgs {
     const int64_t* xadj;
     const int32_t* adj;
+    int64_t S;  // slots of the graph (bound of the vector loads of short rows)
     const int32_t* ew;
     const int32_t* vw;
     const int32_t* label;
@@ -361,6 +362,69 @@ __device__ __forceinline__ void insert_slots(const EvalArgs& A, int64_t b, int32
 
 // ------------------------------------------------------------ lane bucket
 
+// A short row's neighbour ids and weights, then the neighbours' labels.
+// The row is read with 16-byte loads from the aligned address at or below
+// its start when the aligned window lies inside the arrays (one lane per
+// row: a wave's scalar loads each touch 64 rows, so fewer, wider loads
+// spend less of the load unit's time); -1 and 0 past the row's end.
+template <int MAXD>
+__device__ __forceinline__ void lane_words(const int32_t* base, int64_t b, int d, int64_t S, int32_t* out, bool& vec) {
+    constexpr int NQ = MAXD / 4 + 1;
+    const int off = static_cast<int>((reinterpret_cast<uintptr_t>(base + b) & 15u) >> 2);
+    const int64_t b0 = b - off;
+    const int nq = (off + d + 3) >> 2;
+    vec = b0 >= 0 && b0 + 4 * static_cast<int64_t>(nq) <= S;
+    if (!vec) return;
+    int32_t r[4 * NQ];
+    const int4* q = reinterpret_cast<const int4*>(base + b0);
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        int4 w = make_int4(0, 0, 0, 0);
+        if (k < nq) w = q[k];
+        r[4 * k] = w.x;
+        r[4 * k + 1] = w.y;
+        r[4 * k + 2] = w.z;
+        r[4 * k + 3] = w.w;
+    }
+#pragma unroll
+    for (int j = 0; j < MAXD; ++j) {
+        const int32_t x0 = r[j], x1 = r[j + 1], x2 = r[j + 2], x3 = r[j + 3];
+        out[j] = off == 0 ? x0 : off == 1 ? x1 : off == 2 ? x2 : x3;
+    }
+}
+
+template <int MAXD>
+__device__ __forceinline__ void lane_row(const EvalArgs& A, int64_t b, int d, int32_t* lab, int32_t* wt) {
+    bool vec;
+    lane_words<MAXD>(A.adj, b, d, A.S, lab, vec);
+    if (vec) {
+        if (A.ew) {
+            bool vec_w;
+            lane_words<MAXD>(A.ew, b, d, A.S, wt, vec_w);
+            if (!vec_w)
+#pragma unroll
+                for (int j = 0; j < MAXD; ++j) wt[j] = j < d ? A.ew[b + j] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < MAXD; ++j) {
+            lab[j] = j < d ? nbr_label(A, lab[j]) : -1;
+            if (!A.ew) wt[j] = j < d ? 1 : 0;
+            else if (j >= d) wt[j] = 0;
+        }
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < MAXD; ++j) {
+        if (j < d) {
+            lab[j] = nbr_label(A, A.adj[b + j]);
+            wt[j] = A.ew ? A.ew[b + j] : 1;
+        } else {
+            lab[j] = -1;
+            wt[j] = 0;
+        }
+    }
+}
+
 template <int MAXD>
 __device__ __forceinline__ void eval_lane_body(const EvalArgs& A, int32_t bid) {
     const int i = bid * 256 + threadIdx.x;
@@ -377,16 +441,7 @@ __device__ __forceinline__ void eval_lane_body(const EvalArgs& A, int32_t bid) {
     const int32_t a = A.label[v];
     const int32_t c = A.vw ? A.vw[v] : 1;
     int32_t lab[MAXD], wt[MAXD];
-#pragma unroll
-    for (int j = 0; j < MAXD; ++j) {
-        if (j < d) {
-            lab[j] = nbr_label(A, A.adj[b + j]);
-            wt[j] = A.ew ? A.ew[b + j] : 1;
-        } else {
-            lab[j] = -1;
-            wt[j] = 0;
-        }
-    }
+    lane_row<MAXD>(A, b, d, lab, wt);
     int32_t own = 0;
 #pragma unroll
     for (int j = 0; j < MAXD; ++j) own += (lab[j] == a) ? wt[j] : 0;
@@ -2408,6 +2463,7 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     EvalArgs A;
     A.xadj = g.xadj;
     A.adj = g.adj;
+    A.S = g.S;
     A.ew = g.ew;
     A.vw = g.vw;
     A.label = label;
