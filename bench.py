@@ -141,7 +141,8 @@ def batch_comparison(ngraphs, seed, log_lo, log_hi, extra=None):
     torch.cuda.synchronize()
     t_tune = time.perf_counter() - t0
     tuned = {"lane_max_degree": o.lane_max_degree, "wave_max_degree": o.wave_max_degree,
-             "block_max_degree": o.block_max_degree, "graph_capture": o.graph_capture}
+             "block_max_degree": o.block_max_degree, "graph_capture": o.graph_capture,
+             "block_table": o.block_table}
     r = sc.partition_batch_dev(du, nb, ks, eps, seeds, part=part, stream=stream, opts=o)  # warmup
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -133,6 +133,9 @@ typedef struct {
     int32_t fused_eval;           /* tuning (never changes results): 0 (default) or 1: a colour with
                                      fewer than 2^22 adjacency slots evaluates its buckets of up to
                                      1 024 slots per node in one launch; -1: one launch per bucket */
+    int32_t block_table;          /* tuning (never changes results): entries of the LDS table of the
+                                     workgroup-per-node bucket with the longest rows, 10240 (80 KB,
+                                     probed modulo its size) or 16384 (128 KB; 0 = 16384) */
 } sclap_options;
 
 #define SCLAP_MAX_LEVELS 64
@@ -387,15 +390,17 @@ int32_t sclap_server_plan_batch(const int64_t* nodes, const int64_t* slots, cons
  * Tuning (result-free): searches the tuning options for the device graph g
  * (normally a batch union, with k a representative block count) and writes
  * the choice into opt's tuning fields (lane_max_degree, wave_max_degree,
- * block_max_degree, graph_capture).  The objective is the measured time of one
+ * block_max_degree, graph_capture, block_table).  The objective is the measured time of one
  * clustering round from singletons (cluster bound from k as in
  * sclap_partition) plus one refinement round of a k-way partition, the faster
  * of two timings.  The degree thresholds decide which kernel and LDS table a
  * row gets (registers of one lane; 64-, 128- or 512-entry tables for 16, 32
  * or 64 lanes; 2048-, 8192- or 16384-entry tables for a workgroup; hub chunks
- * above), so the search sizes the tables by degree range.  Coordinate search
- * from the library defaults: capture, then block, wave and lane thresholds;
- * a value is kept only if it is at least 3 % faster.  Semantic fields of opt
+ * above), so the search sizes the tables by degree range; it also tries the
+ * smaller table of the longest-row workgroup bucket (block_table).
+ * Coordinate search from the library defaults: capture, then block, wave and
+ * lane thresholds, then the table size; a value is kept only if it is at
+ * least 3 % faster.  Semantic fields of opt
  * are read, not changed; results of later calls do not depend on the choice.
  */
 int sclap_autotune_dev(const sclap_graph* g, int32_t k, sclap_options* opt, void* stream);

@@ -70,7 +70,8 @@ class Options(ctypes.Structure):
                 ("skip_quiet", ctypes.c_int32), ("vcycles", ctypes.c_int32),
                 ("degree_order", ctypes.c_int32), ("contract_bucket_mean", ctypes.c_int32),
                 ("initial_partitioner", ctypes.c_int32), ("select_launches", ctypes.c_int32),
-                ("graph_capture", ctypes.c_int32), ("fused_eval", ctypes.c_int32)]
+                ("graph_capture", ctypes.c_int32), ("fused_eval", ctypes.c_int32),
+                ("block_table", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):
@@ -603,8 +604,10 @@ def initial_partition_lp_dev(d, k, T, Lmax, seed=1, level=0, rounds=10, part=Non
 
 
 def autotune_dev(d, k, stream=None, opts=None, **kw):
-    """Returns Options whose degree-bucket thresholds ran one clustering round
-    of the device graph ``d`` fastest (results never depend on them)."""
+    """Returns Options whose tuning fields (degree-bucket thresholds, the
+    longest-row workgroup bucket's table size, graph capture) ran one
+    clustering and one refinement round of the device graph ``d`` fastest
+    (results never depend on them)."""
     dg = _DevGraph(d)
     o = opts if isinstance(opts, Options) else default_options(**kw)
     _check(load().sclap_autotune_dev(dg.ref, k, ctypes.byref(o), _stream(stream)))

@@ -597,6 +597,7 @@ int sclap_autotune_dev(const sclap_graph* g, int32_t k, sclap_options* opt, void
         opt->wave_max_degree = t.wave_max;
         opt->block_max_degree = t.block_max;
         opt->graph_capture = t.capture;
+        opt->block_table = t.block_table;
         return SCLAP_OK;
     });
 }

@@ -47,6 +47,9 @@ Opts resolve(const sclap_options* o) {
     r.tune.capture = o->graph_capture;
     if (o->fused_eval < -1 || o->fused_eval > 1) fail(SCLAP_ERR_INVALID, "fused_eval must be -1, 0 or 1");
     r.tune.fuse = o->fused_eval;
+    if (o->block_table != 0 && o->block_table != 10240 && o->block_table != 16384)
+        fail(SCLAP_ERR_INVALID, "block_table must be 0, 10240 or 16384");
+    if (o->block_table != 0) r.tune.block_table = o->block_table;
     r.tune.skip_quiet = o->skip_quiet < 0 ? -1 : (o->skip_quiet > 0 ? 1 : 0);
     r.vcycles = o->vcycles == 0 ? 1 : o->vcycles;
     r.degree_order = o->degree_order != 0 ? 1 : 0;
@@ -991,12 +994,15 @@ LPTuning autotune(const DevGraph& g_in, int32_t k, const Opts& o, hipStream_t s)
     // decide which kernel, and so which LDS table, a row gets: one lane and
     // registers (degree <= lane_max), 16, 32 or 64 lanes with 64-, 128- and
     // 512-entry tables (<= wave_max), one workgroup with 2048-, 8192- or
-    // 16384-entry tables (<= block_max), above that the hub chunks; the
-    // capture choice decides whether the rounds run as one HIP graph.  A
-    // value is taken only if it is at least 3 % faster than the current best.
+    // 16384-entry tables (<= block_max), above that the hub chunks; the table
+    // size of the longest-row workgroup bucket (16384 or 10240 entries) is
+    // searched as well; the capture choice decides whether the rounds run as
+    // one HIP graph.  A value is taken only if it is at least 3 % faster than
+    // the current best.
     best.lane_max = 16;
     best.wave_max = 256;
     best.block_max = 8192;
+    best.block_table = 16384;
     double best_ms = measure(best);
     auto try_values = [&](int32_t LPTuning::*field, std::initializer_list<int32_t> values) {
         const int32_t keep = best.*field;
@@ -1015,6 +1021,7 @@ LPTuning autotune(const DevGraph& g_in, int32_t k, const Opts& o, hipStream_t s)
     try_values(&LPTuning::block_max, {1024, 2048, 4096});
     try_values(&LPTuning::wave_max, {32, 64, 128});
     try_values(&LPTuning::lane_max, {4, 8});
+    try_values(&LPTuning::block_table, {10240});
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return best;

@@ -55,6 +55,9 @@ constexpr int kBlock1Max = 1024;  // 256 threads, 16 KB table
 constexpr int kBlock2Max = 4096;  // 512 threads, 64 KB table
 constexpr int kHubTable = 8192;          // LDS table of a hub chunk workgroup (64 KB: two per CU)
 constexpr int kHubChunk = kHubTable / 2; // slots per hub workgroup (table load <= 1/2)
+// the workgroup bucket with the longest rows: a 16384-entry table by
+// default, 10240 entries (80 KB, probed modulo its size) as a tuning choice
+constexpr int kBlockTableSmall = 10240;
 constexpr int kHubDenseChunk = 8192;     // slots per hub workgroup with dense block arrays
 constexpr int kHubTChunk = 4096;         // HBM table entries per scan workgroup
 constexpr int kSmallLabels = 4096;       // LDS-private histograms up to this many labels
@@ -336,11 +339,26 @@ __device__ __forceinline__ void table_add(int32_t* keys, int32_t* vals, uint32_t
     }
 }
 
-// Adds the slots [b, b+d) of a row to a table; each thread keeps U gathers
-// in flight before inserting.
-template <int NT, int U>
+// The same for a table of any size tsz: the first probe is the hash scaled
+// to [0, tsz), and probing wraps at tsz.
+__device__ __forceinline__ void table_add_sized(int32_t* keys, int32_t* vals, uint32_t tsz, int32_t x, int32_t wt) {
+    uint32_t h = static_cast<uint32_t>((static_cast<uint64_t>(slot_hash(static_cast<uint32_t>(x))) * tsz) >> 32);
+    while (true) {
+        const int32_t prev = atomicCAS(&keys[h], -1, x);
+        if (prev == -1 || prev == x) {
+            atomicAdd(&vals[h], wt);
+            return;
+        }
+        h = h + 1 == tsz ? 0u : h + 1;
+    }
+}
+
+// Adds the slots [b, b+d) of a row to a table of tsz entries; each thread
+// keeps U gathers in flight before inserting.  kPow2: tsz is a power of two
+// (masked probes), else any size (table_add_sized).
+template <int NT, int U, bool kPow2 = true>
 __device__ __forceinline__ void insert_slots(const EvalArgs& A, int64_t b, int32_t d, int32_t* keys, int32_t* vals,
-                                             uint32_t mask, int tid) {
+                                             uint32_t tsz, int tid) {
     for (int32_t j0 = tid; j0 < d; j0 += NT * U) {
         int32_t x[U], wt[U];
 #pragma unroll
@@ -355,8 +373,11 @@ __device__ __forceinline__ void insert_slots(const EvalArgs& A, int64_t b, int32
             x[u] = j < d ? nbr_label(A, x[u]) : -1;
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (x[u] >= 0) table_add(keys, vals, mask, x[u], wt[u]);
+        for (int u = 0; u < U; ++u) {
+            if (x[u] < 0) continue;
+            if (kPow2) table_add(keys, vals, tsz - 1, x[u], wt[u]);
+            else table_add_sized(keys, vals, tsz, x[u], wt[u]);
+        }
     }
 }
 
@@ -500,13 +521,12 @@ __device__ __forceinline__ void eval_group_body(const EvalArgs& A, int32_t bid, 
     const int32_t a = A.label[v];
     const int32_t c = A.vw ? A.vw[v] : 1;
     const uint32_t tsz = table_size_for(d, T < 64 ? T : 64, T);
-    const uint32_t mask = tsz - 1;
     for (uint32_t j = gl; j < tsz; j += G) {
         keys[j] = -1;
         vals[j] = 0;
     }
     wave_sync();
-    insert_slots<G, 4>(A, b, d, keys, vals, mask, gl);
+    insert_slots<G, 4>(A, b, d, keys, vals, tsz, gl);
     wave_sync();
     int32_t ownp = 0;
     for (uint32_t j = gl; j < tsz; j += G)
@@ -579,15 +599,15 @@ __device__ __forceinline__ void eval_block_body(const EvalArgs& A, int32_t bid, 
     const int32_t d = static_cast<int32_t>(A.xadj[v + 1] - b);
     const int32_t a = A.label[v];
     const int32_t c = A.vw ? A.vw[v] : 1;
-    const uint32_t tsz = table_size_for(d, 512, TABLE);
-    const uint32_t mask = tsz - 1;
+    constexpr bool kPow2 = (TABLE & (TABLE - 1)) == 0;
+    const uint32_t tsz = kPow2 ? table_size_for(d, 512, TABLE) : static_cast<uint32_t>(TABLE);
     for (uint32_t j = tid; j < tsz; j += NT) {
         keys[j] = -1;
         vals[j] = 0;
     }
     if (tid == 0) s_own = 0;
     __syncthreads();
-    insert_slots<NT, 4>(A, b, d, keys, vals, mask, tid);
+    insert_slots<NT, 4, kPow2>(A, b, d, keys, vals, tsz, tid);
     __syncthreads();
     for (uint32_t j = tid; j < tsz; j += NT)
         if (keys[j] == a) s_own = vals[j];
@@ -688,7 +708,6 @@ __global__ void __launch_bounds__(kHubThreads) hub_chunk_kernel(EvalArgs A, HubA
     const int64_t row_end = A.xadj[v + 1];
     const int64_t end = begin + kHubChunk < row_end ? begin + kHubChunk : row_end;
     const uint32_t tsz = table_size_for(static_cast<int32_t>(end - begin), 1024, kHubTable);
-    const uint32_t mask = tsz - 1;
     const int32_t plog = H.hub_plog[h];
     const int32_t P = 1 << plog;
     for (uint32_t j = tid; j < tsz; j += kHubThreads) {
@@ -697,7 +716,7 @@ __global__ void __launch_bounds__(kHubThreads) hub_chunk_kernel(EvalArgs A, HubA
     }
     for (int32_t j = tid; j < P; j += kHubThreads) pcount[j] = 0;
     __syncthreads();
-    insert_slots<kHubThreads, 4>(A, begin, static_cast<int32_t>(end - begin), keys, vals, mask, tid);
+    insert_slots<kHubThreads, 4>(A, begin, static_cast<int32_t>(end - begin), keys, vals, tsz, tid);
     __syncthreads();
     for (int j = 0; j < kPer; ++j) {
         const uint32_t e = static_cast<uint32_t>(tid) * kPer + j;
@@ -2222,6 +2241,11 @@ hipStream_t capture_stream() {
     return h.st;
 }
 
+// Launch of the longest-row workgroup bucket with the smaller LDS table (a
+// tuning choice), defined at the end of this file so that its kernel's code
+// follows every other kernel's in the library image.
+void launch_small_block_table(unsigned nb, hipStream_t s, const EvalArgs& A);
+
 unsigned capped_grid(int64_t items) {
     const int64_t g = (items + 255) / 256;
     return static_cast<unsigned>(g < 1 ? 1 : (g > kMaxBlocks ? kMaxBlocks : g));
@@ -2719,7 +2743,10 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 } else if (bk == 6) {
                     eval_block_kernel<1024, 2 * kBlock2Max><<<nb, 1024, 0, bs>>>(A);
                 } else {
-                    eval_block_kernel<1024, kBlockTable><<<nb, 1024, 0, bs>>>(A);
+                    if (tune.block_table == kBlockTableSmall)
+                        launch_small_block_table(nb, bs, A);
+                    else
+                        eval_block_kernel<1024, kBlockTable><<<nb, 1024, 0, bs>>>(A);
                 }
                 LAUNCHCHK();
             }
@@ -2826,5 +2853,13 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     if (profiler().on) profiler().collect();
     return res;
 }
+
+namespace {
+
+void launch_small_block_table(unsigned nb, hipStream_t s, const EvalArgs& A) {
+    eval_block_kernel<1024, kBlockTableSmall><<<nb, 1024, 0, s>>>(A);
+}
+
+}  // namespace
 
 }  // namespace sclap

@@ -135,6 +135,7 @@ def test_autotuned_thresholds_leave_results_unchanged(sc):
     # the coordinate search's value grids
     assert o.lane_max_degree in (4, 8, 16) and o.wave_max_degree in (32, 64, 128, 256)
     assert o.block_max_degree in (1024, 2048, 4096, 8192) and o.graph_capture in (-1, 0, 1)
+    assert o.block_table in (10240, 16384)
     assert o.coarsest_nodes == 200
     tuned = sc.partition_batch_dev(d, nb, ks, eps, seeds, opts=o)
     plain = sc.partition_batch_dev(d, nb, ks, eps, seeds, coarsest_nodes=200)

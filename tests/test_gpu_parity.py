@@ -76,7 +76,9 @@ KNOBS = [dict(), dict(lane_max_degree=2, wave_max_degree=8, block_max_degree=24)
          dict(graph_capture=1), dict(graph_capture=1, skip_quiet=1, lane_max_degree=2, wave_max_degree=8,
                                      block_max_degree=24),
          # small colours with one launch per degree bucket instead of the fused one
-         dict(fused_eval=-1), dict(fused_eval=-1, lane_max_degree=2, wave_max_degree=8, block_max_degree=24)]
+         dict(fused_eval=-1), dict(fused_eval=-1, lane_max_degree=2, wave_max_degree=8, block_max_degree=24),
+         # the sized (not power of two) longest-row workgroup table beside small thresholds
+         dict(lane_max_degree=2, wave_max_degree=4, block_max_degree=40, block_table=10240, hub_region_cap=3)]
 
 
 # ------------------------------------------------------------ hand-worked
@@ -136,7 +138,8 @@ REFINE_KNOBS = [dict(block_max_degree=40), dict(block_max_degree=30, hub_part_li
                 dict(select_small_max=1), dict(select_small_max=7), dict(skip_quiet=1),
                 dict(select_small_max=1, select_launches=1), dict(select_small_max=3, select_launches=2),
                 dict(graph_capture=1), dict(graph_capture=1, skip_quiet=1), dict(fused_eval=-1),
-                dict(fused_eval=-1, block_max_degree=30, select_small_max=7)]
+                dict(fused_eval=-1, block_max_degree=30, select_small_max=7),
+                dict(block_max_degree=30, block_table=10240)]
 
 
 @pytest.mark.parametrize("gname", list(GRAPHS))
@@ -156,6 +159,54 @@ def test_refine_parity(sc, gname, k, knobs):
         part = torch.tensor(p0, device="cuda")
         _, rr = sc.refine_dev(d, k, Lmax, part, rounds=8, seed=3, level=1, **REFINE_KNOBS[knobs])
         ref, rr_ref, _ = oracle.refine(g, k, Lmax, p0, rounds=8, seed=3, level=1)
+        assert rr == rr_ref
+        assert np.array_equal(part.cpu().numpy(), ref)
+
+
+def rmat_with_hub(deg, seed):
+    """A weighted R-MAT graph (scale 13) plus one node joined to ``deg`` random
+    nodes: a row of the longest-row workgroup bucket (4 097 to 8 192 slots)
+    or, above that, a hub row."""
+    g = synth.rmat(13, 8, seed=seed, weighted=True)
+    n = g["n"]
+    src = np.repeat(np.arange(n), np.diff(g["xadj"]))
+    keep = src < g["adjncy"]
+    edges = list(zip(src[keep].tolist(), g["adjncy"][keep].tolist()))
+    weights = g["adjwgt"][keep].tolist()
+    rng = np.random.default_rng(seed)
+    edges += [(n, int(u)) for u in rng.choice(n, size=deg, replace=False)]
+    weights += rng.integers(1, 5, size=deg).tolist()
+    return synth.from_edges(n + 1, edges, weights)
+
+
+TABLE_GRAPHS = {"star_6000": lambda: star(6000), "rmat_13_hub5000": lambda: rmat_with_hub(5000, 21),
+                "rmat_13_hub8000": lambda: rmat_with_hub(8000, 22), "rmat_13_hub8192": lambda: rmat_with_hub(8192, 23)}
+
+
+@pytest.mark.parametrize("gname", list(TABLE_GRAPHS))
+@pytest.mark.parametrize("tables", [dict(), dict(block_table=10240), dict(block_table=10240, block_max_degree=6000)])
+def test_table_size_parity(sc, gname, tables):
+    """Both LDS table sizes of the longest-row workgroup bucket (16 384 entries,
+    or 10 240 probed modulo their size) give the oracle's clustering and
+    refinement exactly, with the longest rows in that bucket or, above 6 000
+    slots, on the hub path beside it."""
+    g = TABLE_GRAPHS[gname]()
+    d = dev(sc, g)
+    cV = int(g["vwgt"].sum())
+    for U, seed in ((max(3, cV // 300), 1), (max(10, cV // 20), 4)):
+        say("cluster", gname, tables, "U=%d seed=%d" % (U, seed))
+        lab, rr = sc.cluster_dev(d, U, rounds=6, seed=seed, level=1, **tables)
+        ref, rr_ref, _ = oracle.cluster(g, U, rounds=6, seed=seed, level=1)
+        assert rr == rr_ref
+        assert np.array_equal(lab.cpu().numpy(), ref)
+    rng = np.random.default_rng(7)
+    for k in (5, 300):
+        Lmax = oracle.lmax(cV, k, 0.03)
+        p0 = rng.integers(0, k, size=g["n"]).astype(np.int32)
+        say("refine", gname, tables, "k=%d" % k)
+        part = torch.tensor(p0, device="cuda")
+        _, rr = sc.refine_dev(d, k, Lmax, part, rounds=6, seed=2, level=0, **tables)
+        ref, rr_ref, _ = oracle.refine(g, k, Lmax, p0, rounds=6, seed=2, level=0)
         assert rr == rr_ref
         assert np.array_equal(part.cpu().numpy(), ref)
 
@@ -324,7 +375,8 @@ def test_validation_codes_on_device(sc):
     with pytest.raises(sc.SclapError):
         sc.contract_dev(d, torch.full((400,), 400, dtype=torch.int32, device="cuda"))
     # tuning options outside their ranges are rejected before any launch
-    for bad in (dict(graph_capture=2), dict(fused_eval=2), dict(fused_eval=-2), dict(select_launches=-1)):
+    for bad in (dict(graph_capture=2), dict(fused_eval=2), dict(fused_eval=-2), dict(select_launches=-1),
+                dict(block_table=8192), dict(block_table=12288), dict(block_table=-1)):
         with pytest.raises(sc.SclapError) as ei:
             sc.partition_dev(d, 2, **bad)
         assert ei.value.status == -1, bad
