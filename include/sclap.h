@@ -135,7 +135,7 @@ typedef struct {
                                      1 024 slots per node in one launch; -1: one launch per bucket */
     int32_t block_table;          /* tuning (never changes results): entries of the LDS table of the
                                      workgroup-per-node bucket with the longest rows, 10240 (80 KB,
-                                     probed modulo its size) or 16384 (128 KB; 0 = 16384) */
+                                     probed modulo its size; 0 = 10240) or 16384 (128 KB) */
 } sclap_options;
 
 #define SCLAP_MAX_LEVELS 64
@@ -395,9 +395,9 @@ int32_t sclap_server_plan_batch(const int64_t* nodes, const int64_t* slots, cons
  * sclap_partition) plus one refinement round of a k-way partition, the faster
  * of two timings.  The degree thresholds decide which kernel and LDS table a
  * row gets (registers of one lane; 64-, 128- or 512-entry tables for 16, 32
- * or 64 lanes; 2048-, 8192- or 16384-entry tables for a workgroup; hub chunks
+ * or 64 lanes; 2048-, 8192- or 10240-entry tables for a workgroup; hub chunks
  * above), so the search sizes the tables by degree range; it also tries the
- * smaller table of the longest-row workgroup bucket (block_table).
+ * other table size of the longest-row workgroup bucket (block_table).
  * Coordinate search from the library defaults: capture, then block, wave and
  * lane thresholds, then the table size; a value is kept only if it is at
  * least 3 % faster.  Semantic fields of opt

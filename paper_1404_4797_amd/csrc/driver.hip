@@ -994,15 +994,15 @@ LPTuning autotune(const DevGraph& g_in, int32_t k, const Opts& o, hipStream_t s)
     // decide which kernel, and so which LDS table, a row gets: one lane and
     // registers (degree <= lane_max), 16, 32 or 64 lanes with 64-, 128- and
     // 512-entry tables (<= wave_max), one workgroup with 2048-, 8192- or
-    // 16384-entry tables (<= block_max), above that the hub chunks; the table
-    // size of the longest-row workgroup bucket (16384 or 10240 entries) is
+    // 10240-entry tables (<= block_max), above that the hub chunks; the table
+    // size of the longest-row workgroup bucket (10240 or 16384 entries) is
     // searched as well; the capture choice decides whether the rounds run as
     // one HIP graph.  A value is taken only if it is at least 3 % faster than
     // the current best.
     best.lane_max = 16;
     best.wave_max = 256;
     best.block_max = 8192;
-    best.block_table = 16384;
+    best.block_table = 10240;
     double best_ms = measure(best);
     auto try_values = [&](int32_t LPTuning::*field, std::initializer_list<int32_t> values) {
         const int32_t keep = best.*field;
@@ -1021,7 +1021,7 @@ LPTuning autotune(const DevGraph& g_in, int32_t k, const Opts& o, hipStream_t s)
     try_values(&LPTuning::block_max, {1024, 2048, 4096});
     try_values(&LPTuning::wave_max, {32, 64, 128});
     try_values(&LPTuning::lane_max, {4, 8});
-    try_values(&LPTuning::block_table, {10240});
+    try_values(&LPTuning::block_table, {16384});
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return best;

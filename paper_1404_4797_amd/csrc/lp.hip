@@ -55,8 +55,9 @@ constexpr int kBlock1Max = 1024;  // 256 threads, 16 KB table
 constexpr int kBlock2Max = 4096;  // 512 threads, 64 KB table
 constexpr int kHubTable = 8192;          // LDS table of a hub chunk workgroup (64 KB: two per CU)
 constexpr int kHubChunk = kHubTable / 2; // slots per hub workgroup (table load <= 1/2)
-// the workgroup bucket with the longest rows: a 16384-entry table by
-// default, 10240 entries (80 KB, probed modulo its size) as a tuning choice
+// the workgroup bucket with the longest rows: a 10240-entry table (80 KB,
+// probed modulo its size) by default, which leaves room on the compute unit
+// for a workgroup with a 64 KB table; 16384 entries as a tuning choice
 constexpr int kBlockTableSmall = 10240;
 constexpr int kHubDenseChunk = 8192;     // slots per hub workgroup with dense block arrays
 constexpr int kHubTChunk = 4096;         // HBM table entries per scan workgroup
@@ -2241,9 +2242,9 @@ hipStream_t capture_stream() {
     return h.st;
 }
 
-// Launch of the longest-row workgroup bucket with the smaller LDS table (a
-// tuning choice), defined at the end of this file so that its kernel's code
-// follows every other kernel's in the library image.
+// Launch of the longest-row workgroup bucket with the smaller LDS table,
+// defined at the end of this file so that its kernel's code follows every
+// other kernel's in the library image.
 void launch_small_block_table(unsigned nb, hipStream_t s, const EvalArgs& A);
 
 unsigned capped_grid(int64_t items) {

@@ -30,7 +30,7 @@ struct LPTuning {
     int32_t skip_quiet = 0;           // 1: skip nodes whose decision cannot have changed; -1: never; 0: caller's choice
     int32_t capture = 0;              // 1: record each call's rounds in a HIP graph; else launch directly
     int32_t fuse = 0;                 // >= 0: the small buckets of a small colour in one launch; -1: one launch each
-    int32_t block_table = 16384;      // LDS table entries of the longest-row workgroup bucket: 10240 or 16384
+    int32_t block_table = 10240;      // LDS table entries of the longest-row workgroup bucket: 10240 or 16384
 };
 
 // Several disjoint graphs in one CSR (node ranges per graph, no edge between

@@ -78,7 +78,7 @@ KNOBS = [dict(), dict(lane_max_degree=2, wave_max_degree=8, block_max_degree=24)
          # small colours with one launch per degree bucket instead of the fused one
          dict(fused_eval=-1), dict(fused_eval=-1, lane_max_degree=2, wave_max_degree=8, block_max_degree=24),
          # the sized (not power of two) longest-row workgroup table beside small thresholds
-         dict(lane_max_degree=2, wave_max_degree=4, block_max_degree=40, block_table=10240, hub_region_cap=3)]
+         dict(lane_max_degree=2, wave_max_degree=4, block_max_degree=40, block_table=16384, hub_region_cap=3)]
 
 
 # ------------------------------------------------------------ hand-worked
@@ -139,7 +139,7 @@ REFINE_KNOBS = [dict(block_max_degree=40), dict(block_max_degree=30, hub_part_li
                 dict(select_small_max=1, select_launches=1), dict(select_small_max=3, select_launches=2),
                 dict(graph_capture=1), dict(graph_capture=1, skip_quiet=1), dict(fused_eval=-1),
                 dict(fused_eval=-1, block_max_degree=30, select_small_max=7),
-                dict(block_max_degree=30, block_table=10240)]
+                dict(block_max_degree=30, block_table=16384)]
 
 
 @pytest.mark.parametrize("gname", list(GRAPHS))
@@ -184,7 +184,8 @@ TABLE_GRAPHS = {"star_6000": lambda: star(6000), "rmat_13_hub5000": lambda: rmat
 
 
 @pytest.mark.parametrize("gname", list(TABLE_GRAPHS))
-@pytest.mark.parametrize("tables", [dict(), dict(block_table=10240), dict(block_table=10240, block_max_degree=6000)])
+@pytest.mark.parametrize("tables", [dict(), dict(block_table=16384), dict(block_table=10240, block_max_degree=6000),
+                                    dict(block_table=16384, block_max_degree=6000)])
 def test_table_size_parity(sc, gname, tables):
     """Both LDS table sizes of the longest-row workgroup bucket (16 384 entries,
     or 10 240 probed modulo their size) give the oracle's clustering and
