@@ -49,16 +49,17 @@ constexpr int kG16Max = 32;  // 16 lanes and a 64-entry table per node
 constexpr int kG32Max = 64;  // 32 lanes and a 128-entry table per node
 constexpr int kWaveTable = 512;
 constexpr int kWaveMaxDeg = kWaveTable / 2;
-constexpr int kBlockTable = 16384;
-constexpr int kBlockMaxDeg = kBlockTable / 2;
+// the workgroup bucket with the longest rows (up to kBlockMaxDeg slots): a
+// 10240-entry table (80 KB, probed modulo its size) by default, which leaves
+// room on the compute unit for a workgroup with a 64 KB table; the 16384-entry
+// power-of-two table (128 KB) as a tuning choice
+constexpr int kBlockTable = 10240;
+constexpr int kBlockTablePow2 = 16384;
+constexpr int kBlockMaxDeg = kBlockTablePow2 / 2;
 constexpr int kBlock1Max = 1024;  // 256 threads, 16 KB table
 constexpr int kBlock2Max = 4096;  // 512 threads, 64 KB table
 constexpr int kHubTable = 8192;          // LDS table of a hub chunk workgroup (64 KB: two per CU)
 constexpr int kHubChunk = kHubTable / 2; // slots per hub workgroup (table load <= 1/2)
-// the workgroup bucket with the longest rows: a 10240-entry table (80 KB,
-// probed modulo its size) by default, which leaves room on the compute unit
-// for a workgroup with a 64 KB table; 16384 entries as a tuning choice
-constexpr int kBlockTableSmall = 10240;
 constexpr int kHubDenseChunk = 8192;     // slots per hub workgroup with dense block arrays
 constexpr int kHubTChunk = 4096;         // HBM table entries per scan workgroup
 constexpr int kSmallLabels = 4096;       // LDS-private histograms up to this many labels
@@ -2242,11 +2243,6 @@ hipStream_t capture_stream() {
     return h.st;
 }
 
-// Launch of the longest-row workgroup bucket with the smaller LDS table,
-// defined at the end of this file so that its kernel's code follows every
-// other kernel's in the library image.
-void launch_small_block_table(unsigned nb, hipStream_t s, const EvalArgs& A);
-
 unsigned capped_grid(int64_t items) {
     const int64_t g = (items + 255) / 256;
     return static_cast<unsigned>(g < 1 ? 1 : (g > kMaxBlocks ? kMaxBlocks : g));
@@ -2744,8 +2740,8 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
                 } else if (bk == 6) {
                     eval_block_kernel<1024, 2 * kBlock2Max><<<nb, 1024, 0, bs>>>(A);
                 } else {
-                    if (tune.block_table == kBlockTableSmall)
-                        launch_small_block_table(nb, bs, A);
+                    if (tune.block_table == kBlockTablePow2)
+                        eval_block_kernel<1024, kBlockTablePow2><<<nb, 1024, 0, bs>>>(A);
                     else
                         eval_block_kernel<1024, kBlockTable><<<nb, 1024, 0, bs>>>(A);
                 }
@@ -2854,13 +2850,5 @@ LPResult run_lp(const DevGraph& g, int32_t phase, int32_t level, uint64_t seed, 
     if (profiler().on) profiler().collect();
     return res;
 }
-
-namespace {
-
-void launch_small_block_table(unsigned nb, hipStream_t s, const EvalArgs& A) {
-    eval_block_kernel<1024, kBlockTableSmall><<<nb, 1024, 0, s>>>(A);
-}
-
-}  // namespace
 
 }  // namespace sclap
